@@ -1,0 +1,250 @@
+"""Sparse direct solve of the frequency-domain system that the leapfrog plus
+on-the-fly DFT reaches exactly; a pin for the time-stepping oracle that
+shares no code with it (grid operators, CPML stretching, averaging and
+interpolation are written again here).
+
+Identity used (derived from the leapfrog by summing each update against
+z^n, z = exp(i w' dt), with zero initial state): the transforms
+E^ = sum_n E^n z^n, H^ = sum_n H^{n+1/2} z^{n+1/2}, J^ = sum J^{n+1/2}
+z^{n+1/2} satisfy
+    curl_h H^ + i Omega eps E^ = J^,     curl_h E^ - i Omega mu H^ = 0,
+    Omega = (2/dt) sin(w' dt / 2),
+which is eq. mittet with w' replaced by Omega.  A CPML memory variable
+psi <- b psi + a D transforms to psi^ = a D^ / (1 - b z), so every
+stretched derivative becomes D^ (1/kappa + a/(1 - b z)) at its node.
+Eliminating H^:  (curl_h curl_h / (i Omega mu) + i Omega eps) E^ = J^.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+MU0 = 4.0e-7 * np.pi
+
+
+def _profile(nodes, pos, npml, dt, vref, order, R, kmax, amax, z):
+    """1/s at positions ``pos`` for the CPML of one axis."""
+    n = len(nodes) - 1
+    xl, xr = nodes[npml], nodes[n - npml]
+    out = np.ones(len(pos), dtype=np.complex128)
+    for m, p in enumerate(pos):
+        if p < xl:
+            L, r = xl - nodes[0], (xl - p) / (xl - nodes[0])
+        elif p > xr:
+            L, r = nodes[n] - xr, (p - xr) / (nodes[n] - xr)
+        else:
+            continue
+        d = -(order + 1.0) * vref * np.log(R) / (2.0 * L) * r ** order
+        kap = 1.0 + (kmax - 1.0) * r ** order
+        alp = amax * (1.0 - r)
+        b = np.exp(-(d / kap + alp) * dt)
+        a = d * (b - 1.0) / (kap * (d + kap * alp)) if d > 0 else 0.0
+        out[m] = 1.0 / kap + a / (1.0 - b * z)
+    return out
+
+
+class Grid:
+    """Index bookkeeping for the six staggered components."""
+
+    def __init__(self, x, y, z):
+        self.x, self.y, self.z = x, y, z
+        self.nx, self.ny, self.nz = len(x) - 1, len(y) - 1, len(z) - 1
+        nx, ny, nz = self.nx, self.ny, self.nz
+        self.eshape = [(nz + 1, ny + 1, nx), (nz + 1, ny, nx + 1), (nz, ny + 1, nx + 1)]
+        self.hshape = [(nz, ny, nx + 1), (nz, ny + 1, nx), (nz + 1, ny, nx)]
+        self.eoff = np.cumsum([0] + [int(np.prod(s)) for s in self.eshape])
+        self.hoff = np.cumsum([0] + [int(np.prod(s)) for s in self.hshape])
+
+    def e(self, c, k, j, i):
+        s = self.eshape[c]
+        return self.eoff[c] + (k * s[1] + j) * s[2] + i
+
+    def h(self, c, k, j, i):
+        s = self.hshape[c]
+        return self.hoff[c] + (k * s[1] + j) * s[2] + i
+
+
+def _dual(nodes):
+    h = np.diff(nodes)
+    d = np.empty(len(nodes))
+    d[0], d[-1] = h[0] / 2, h[-1] / 2
+    d[1:-1] = (h[1:] + h[:-1]) / 2
+    return d
+
+
+def solve(x, y, z, rho, npml, f0, freq, dt, sources, receivers, rec_comp,
+          vref, cpml_order=2.0, cpml_R=1e-6, kappa_max=1.0, alpha_max=0.0,
+          rho_cap=1e8):
+    """Frequency-domain E at ``receivers`` for each dipole in ``sources``
+    (list of (pos, moment)); returns complex [ns][nr][ncomp].  The field is
+    that of J (not J'): the right-hand side is sqrt(-i w/2w0) p w_l / V_l."""
+    g = Grid(x, y, z)
+    nx, ny, nz = g.nx, g.ny, g.nz
+    hx, hy, hz = np.diff(x), np.diff(y), np.diff(z)
+    dx, dy, dz = _dual(x), _dual(y), _dual(z)
+    w0 = 2 * np.pi * f0
+    om = 2 * np.pi * freq
+    wp = (1 + 1j) * np.sqrt(om * w0)
+    zz = np.exp(1j * wp * dt)
+    Om = 2.0 / dt * np.sin(wp * dt / 2)
+    prof = {}
+    for nm, nodes in (("x", x), ("y", y), ("z", z)):
+        mid = 0.5 * (nodes[:-1] + nodes[1:])
+        args = (npml, dt, vref, cpml_order, cpml_R, kappa_max, alpha_max, zz)
+        prof[nm] = (_profile(nodes, nodes, *args), _profile(nodes, mid, *args))
+    isx_n, isx_h = prof["x"]
+    isy_n, isy_h = prof["y"]
+    isz_n, isz_h = prof["z"]
+
+    # curl E -> faces
+    rows, cols, vals = [], [], []
+
+    def add(r, c, v):
+        rows.append(r)
+        cols.append(c)
+        vals.append(v)
+
+    for k in range(nz):
+        for j in range(ny):
+            for i in range(nx + 1):          # H_x = dEz/dy - dEy/dz
+                r = g.h(0, k, j, i)
+                fy = isy_h[j] / hy[j]
+                fz = isz_h[k] / hz[k]
+                add(r, g.e(2, k, j + 1, i), fy)
+                add(r, g.e(2, k, j, i), -fy)
+                add(r, g.e(1, k + 1, j, i), -fz)
+                add(r, g.e(1, k, j, i), fz)
+    for k in range(nz):
+        for j in range(ny + 1):
+            for i in range(nx):              # H_y = dEx/dz - dEz/dx
+                r = g.h(1, k, j, i)
+                fz = isz_h[k] / hz[k]
+                fx = isx_h[i] / hx[i]
+                add(r, g.e(0, k + 1, j, i), fz)
+                add(r, g.e(0, k, j, i), -fz)
+                add(r, g.e(2, k, j, i + 1), -fx)
+                add(r, g.e(2, k, j, i), fx)
+    for k in range(nz + 1):
+        for j in range(ny):
+            for i in range(nx):              # H_z = dEy/dx - dEx/dy
+                r = g.h(2, k, j, i)
+                fx = isx_h[i] / hx[i]
+                fy = isy_h[j] / hy[j]
+                add(r, g.e(1, k, j, i + 1), fx)
+                add(r, g.e(1, k, j, i), -fx)
+                add(r, g.e(0, k, j + 1, i), -fy)
+                add(r, g.e(0, k, j, i), fy)
+    CE = sp.csr_matrix((vals, (rows, cols)), shape=(g.hoff[-1], g.eoff[-1]))
+
+    # curl H -> interior edges
+    rows, cols, vals = [], [], []
+    interior = []
+    for k in range(1, nz):
+        for j in range(1, ny):
+            for i in range(nx):              # E_x: dHz/dy - dHy/dz
+                r = g.e(0, k, j, i)
+                interior.append(r)
+                fy = isy_n[j] / dy[j]
+                fz = isz_n[k] / dz[k]
+                add(r, g.h(2, k, j, i), fy)
+                add(r, g.h(2, k, j - 1, i), -fy)
+                add(r, g.h(1, k, j, i), -fz)
+                add(r, g.h(1, k - 1, j, i), fz)
+    for k in range(1, nz):
+        for j in range(ny):
+            for i in range(1, nx):           # E_y: dHx/dz - dHz/dx
+                r = g.e(1, k, j, i)
+                interior.append(r)
+                fz = isz_n[k] / dz[k]
+                fx = isx_n[i] / dx[i]
+                add(r, g.h(0, k, j, i), fz)
+                add(r, g.h(0, k - 1, j, i), -fz)
+                add(r, g.h(2, k, j, i), -fx)
+                add(r, g.h(2, k, j, i - 1), fx)
+    for k in range(nz):
+        for j in range(1, ny):
+            for i in range(1, nx):           # E_z: dHy/dx - dHx/dy
+                r = g.e(2, k, j, i)
+                interior.append(r)
+                fx = isx_n[i] / dx[i]
+                fy = isy_n[j] / dy[j]
+                add(r, g.h(1, k, j, i), fx)
+                add(r, g.h(1, k, j, i - 1), -fx)
+                add(r, g.h(0, k, j, i), -fy)
+                add(r, g.h(0, k, j - 1, i), fy)
+    CH = sp.csr_matrix((vals, (rows, cols)), shape=(g.eoff[-1], g.hoff[-1]))
+
+    # edge permittivity: volume-weighted cell average, eps = sigma / (2 w0)
+    sig = 1.0 / np.minimum(rho, rho_cap)
+    eps = np.zeros(g.eoff[-1])
+    vol = np.zeros(g.eoff[-1])
+    for k in range(nz):
+        for j in range(ny):
+            for i in range(nx):
+                s = sig[k, j, i]
+                for (kk, jj) in ((k, j), (k + 1, j), (k, j + 1), (k + 1, j + 1)):
+                    w = hz[k] * hy[j]
+                    eps[g.e(0, kk, jj, i)] += s * w
+                    vol[g.e(0, kk, jj, i)] += w
+                for (kk, ii) in ((k, i), (k + 1, i), (k, i + 1), (k + 1, i + 1)):
+                    w = hz[k] * hx[i]
+                    eps[g.e(1, kk, j, ii)] += s * w
+                    vol[g.e(1, kk, j, ii)] += w
+                for (jj, ii) in ((j, i), (j + 1, i), (j, i + 1), (j + 1, i + 1)):
+                    w = hy[j] * hx[i]
+                    eps[g.e(2, k, jj, ii)] += s * w
+                    vol[g.e(2, k, jj, ii)] += w
+    eps = eps / vol / (2.0 * w0)
+
+    A = CH @ CE / (1j * Om * MU0) + sp.diags(1j * Om * eps)
+    idx = np.array(interior)
+    Ai = A[idx][:, idx].tocsc()
+    lu = spla.splu(Ai)
+    pos_of = {int(r): m for m, r in enumerate(idx)}
+
+    # lattices of the three E components and dual volumes
+    xh, yh, zh = 0.5 * (x[1:] + x[:-1]), 0.5 * (y[1:] + y[:-1]), 0.5 * (z[1:] + z[:-1])
+    lat = [(xh, y, z), (x, yh, z), (x, y, zh)]
+    edge_len = [(hx, None), (hy, None), (hz, None)]
+
+    def dualvol(c, k, j, i):
+        if c == 0:
+            return hx[i] * dy[j] * dz[k]
+        if c == 1:
+            return dx[i] * hy[j] * dz[k]
+        return dx[i] * dy[j] * hz[k]
+
+    def weights(c, p):
+        out = []
+        sel = []
+        for q, l in zip(p, lat[c]):
+            m = int(np.clip(np.searchsorted(l, q) - 1, 0, len(l) - 2))
+            t = (q - l[m]) / (l[m + 1] - l[m])
+            sel.append([(m, 1 - t), (m + 1, t)])
+        for i, wi in sel[0]:
+            for j, wj in sel[1]:
+                for k, wk in sel[2]:
+                    if wi * wj * wk != 0:
+                        out.append((k, j, i, wi * wj * wk))
+        return out
+
+    src_fac = np.sqrt(-1j * om / (2 * w0))
+    out = np.zeros((len(sources), len(receivers), len(rec_comp)), dtype=np.complex128)
+    for si, (pos, mom) in enumerate(sources):
+        rhs = np.zeros(len(idx), dtype=np.complex128)
+        for c in range(3):
+            if mom[c] == 0:
+                continue
+            for (k, j, i, w) in weights(c, pos):
+                rhs[pos_of[int(g.e(c, k, j, i))]] += src_fac * mom[c] * w / dualvol(c, k, j, i)
+        sol = lu.solve(rhs)
+        for ri, rp in enumerate(receivers):
+            for ci, c in enumerate(rec_comp):
+                val = 0j
+                for (k, j, i, w) in weights(c, rp):
+                    m = pos_of.get(int(g.e(c, k, j, i)))
+                    if m is not None:
+                        val += w * sol[m]
+                out[si, ri, ci] = val
+    return out
