@@ -1,0 +1,180 @@
+"""Benchmark: one gradient of the marine 1D workload per step on one MI355X.
+
+A step is one pass of the whole hot path for the 101x101x61 stretched-grid
+marine model (3 frequencies, 1 x-dipole, 50 seabed receivers, FP32 fields
+with FP64 transform accumulators): set the model, build the basis functions,
+forward run with the on-the-fly receiver and volume transforms, residual
+against data of the true model, adjoint run driven by the basis-function
+adjoint sources with the on-the-fly gradient product, gradient on cells.
+
+Printed: one JSON line.  value = cell updates per second over the two
+simulations of the step (forward + adjoint), in Mcell-updates/s; a cell
+update advances all six field components of one cell by one step.
+roofline: the forward E-update kernel (fused with the volume transform),
+its algorithmic bytes per launch over its average device time measured with
+HIP events on sampled steps inside the timed region.  cpu_baseline: the CPU
+oracle stepping the same grid for a bounded window of steps.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def algorithmic_bytes_e_forward(nx, ny, nz, npml, nf, tsize=4, accsize=16):
+    """Algorithmic HBM bytes of one launch of the forward E update fused with
+    the volume transform: per updated edge E read + write and dt/eps read
+    (3 tsize), one H value per updated edge (tsize), the accumulator
+    read-modify-write of nf complex values (2 nf accsize), and a CPML memory
+    variable read + write (2 tsize) per derivative taken inside a layer."""
+    n_ex = nx * (ny - 1) * (nz - 1)
+    n_ey = (nx - 1) * ny * (nz - 1)
+    n_ez = (nx - 1) * (ny - 1) * nz
+    edges = n_ex + n_ey + n_ez
+
+    def in_pml_int(n):      # interior integer nodes 1..n-1 inside a layer
+        return sum(1 for i in range(1, n) if i < npml or i > n - npml)
+
+    px, py, pz = in_pml_int(nx), in_pml_int(ny), in_pml_int(nz)
+    # derivatives along y and z for E_x, x and z for E_y, x and y for E_z
+    psi = (nx * py * (nz - 1) + nx * (ny - 1) * pz + px * ny * (nz - 1) + (nx - 1) * ny * pz
+           + px * (ny - 1) * nz + (nx - 1) * py * nz)
+    return edges * (4 * tsize + 2 * nf * accsize) + psi * 2 * tsize, edges
+
+
+def cpu_baseline(w, steps=100):
+    """Oracle (NumPy FP64, single process) stepping the full grid of the
+    workload with the volume transform for a bounded window of steps."""
+    import oracle
+    from oracle.discretization import make_setup
+    from oracle.stepping import receiver_nodes, run_stepping, source_injection
+    s = make_setup(w, nt=steps)
+    inj = source_injection(s, w.src_pos[0], w.src_mom[0])
+    nodes, _ = receiver_nodes(s, w.rec_pos, w.rec_comp)
+    t0 = time.perf_counter()
+    run_stepping(s, inj, s.wavelet[None, :], nodes, True, steps)
+    dt = time.perf_counter() - t0
+    ncells = s.nx * s.ny * s.nz
+    return {"value": ncells * steps / dt / 1e6, "unit": "Mcell-updates/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{w.name}: full {s.nx}x{s.ny}x{s.nz} grid, {steps} forward steps with "
+                      f"the volume transform of {len(s.freqs)} frequencies, FP64 NumPy, "
+                      f"one process ({dt:.1f} s); host {os.cpu_count()} logical CPUs"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--field-dtype", default="f32")
+    ap.add_argument("--acc", default="f64")
+    ap.add_argument("--sample-every", type=int, default=2048)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU: the path has no multi-GPU mode "
+              f"(--gpus {args.gpus} requested)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2211_16665_amd import fwdem as fw
+    from workloads import c2_marine1d
+
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    torch.cuda.set_device(0)
+    w_true = c2_marine1d()
+    # background model of the step: the same column without the reservoir
+    rho0 = w_true.rho.copy()
+    rho0[rho0 == 100.0] = 1.0
+    plan = fw.Plan.from_workload(w_true, field_dtype=args.field_dtype, acc_mode=args.acc)
+    plan.set_model(w_true.rho)
+    d_obs = plan.forward()                               # data of the true model (untimed)
+    plan.set_option(fw.FWD_OPT_SAMPLE_EVERY, args.sample_every)
+    vol = plan.volume_buffer()
+    grad = torch.zeros(plan.shape, dtype=torch.float64, device="cuda")
+    stats = {"fwd": [], "adj": []}
+
+    def step():
+        plan.set_model(rho0)
+        plan.basis_build(gamma_rel=1e-12)
+        E, _ = plan.forward(vol=vol, want_volume=True)
+        stats["fwd"].append(plan.kernel_stats())
+        resid = d_obs - E
+        plan.adjoint(vol, resid, grad=grad)
+        stats["adj"].append(plan.kernel_stats())
+
+    for _ in range(args.warmup):
+        step()
+    stats = {"fwd": [], "adj": []}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+
+    info = plan.info
+    nz, ny, nx = plan.shape
+    ncells = nx * ny * nz
+    nt = info.nt
+    updates = 2.0 * plan.ns * ncells * nt * args.steps
+    value = updates / elapsed / 1e6
+
+    # roofline of the forward E update (dominant kernel)
+    def avg(key, k):
+        v = [s[0][k] for s in stats[key] if s[1] > 0]
+        n = sum(s[1] for s in stats[key])
+        return (float(np.mean(v)) if v else float("nan")), n
+    tsize = 4 if args.field_dtype == "f32" else 8
+    accsize = 8 if args.acc == "f32" else 16
+    bytes_e, edges = algorithmic_bytes_e_forward(nx, ny, nz, w_true.npml, len(w_true.freqs),
+                                                 tsize, accsize)
+    e_ms, n_samp = avg("fwd", 2)
+    achieved = bytes_e / (e_ms * 1e-3) / 1e9
+    kern = {name: {"fwd_ms": avg("fwd", k)[0], "adj_ms": avg("adj", k)[0]}
+            for k, name in enumerate(("update_h", "inject", "update_e", "rec_dft"))}
+    out = {
+        "metric": "Mcell-updates/s",
+        "value": value,
+        "unit": "Mcell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.field_dtype,
+        "data": "synthetic",
+        "config": {"workload": "c2_marine1d gradient: 101x101x61 stretched grid (100 m core, "
+                               "ratio 1.05), air/0.3 ohm-m water/1 ohm-m sediment/100 ohm-m "
+                               "reservoir, 3 freqs 0.25-1.25 Hz, 1 x-dipole, 50 seabed receivers; "
+                               "forward + adjoint + gradient",
+                   "cells": ncells, "nt": nt, "dt": info.dt, "sources": plan.ns,
+                   "field_dtype": args.field_dtype, "accumulators": args.acc,
+                   "basis_fit": info.basis_fit},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_update_e (forward, volume transform fused)",
+                     "bytes_per_launch": bytes_e, "avg_launch_ms": e_ms, "samples": n_samp},
+        "kernels_ms": kern,
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(w_true)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

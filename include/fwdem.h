@@ -1,0 +1,252 @@
+/*
+ * fwdem.h -- C ABI of the MI355X library for fictitious-wave-domain CSEM
+ * modelling and its adjoint gradient (Yang, "3D fictitious wave domain
+ * CSEM inversion by adjoint source estimation", arXiv 2211.16665).
+ *
+ * What the library computes
+ *   forward  The diffusive frequency-domain Maxwell system (Section 2,
+ *            eq. freq) is solved by stepping its fictitious wave-domain
+ *            counterpart (eq. fictitiouswave, sigma = 2 omega0 eps, eq.
+ *            mittet) with a staggered-grid E/H leapfrog on a stretched
+ *            tensor grid with CPML layers, and extracting every frequency
+ *            in one pass by the damped on-the-fly transform (eq. dft).
+ *   adjoint  The adjoint field (eq. adj1, adj2) is stepped with the same
+ *            engine, driven by time series built from the regularised
+ *            basis functions B+ (Section 3.3, eqs. B, mpinv, basis), and the
+ *            gradient of the misfit (eq. phid) with respect to ln(rho) is
+ *            assembled from forward and adjoint fields (eq. gradsigmaij and
+ *            the ln rho chain rule of Section 3.5).
+ *
+ * Conventions
+ *   * Every call returns fwd_status; FWD_OK is 0.  On error a message is
+ *     available from fwd_last_error() (thread-local, valid until the next
+ *     call on the same thread).  No C++ exception crosses this boundary.
+ *   * Grid: nx, ny, nz cells; node coordinates x[nx+1], y[ny+1], z[nz+1]
+ *     strictly increasing (metres, z positive down).  Cell arrays are
+ *     [nz][ny][nx], x fastest.
+ *   * Complex numbers are interleaved (re, im) doubles.
+ *   * Pointers named *_host are host memory read during the call; pointers
+ *     named *_dev are device memory on the current HIP device.  Device
+ *     buffers passed in (workspace, volume, outputs) are owned by the
+ *     caller and must stay alive until the work enqueued on `stream` ends.
+ *     The plan owns only tables proportional to one copy of the model.
+ *   * Work is enqueued on the caller's stream (a hipStream_t passed as
+ *     void*, 0 for the null stream).  fwd_forward / fwd_adjoint wait for
+ *     their own work before returning, so that a non-finite result can be
+ *     reported as FWD_ERR_NONFINITE.
+ *   * fwd_plan_create, fwd_set_model, fwd_get_info, fwd_get_table and
+ *     fwd_basis_build are host-only and make no HIP call.
+ */
+#ifndef FWDEM_H
+#define FWDEM_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fwd_plan fwd_plan;
+
+typedef enum {
+  FWD_OK = 0,
+  FWD_ERR_INVALID_ARG = 1,  /* argument outside its documented range */
+  FWD_ERR_OOM = 2,          /* host or device allocation failed */
+  FWD_ERR_HIP = 3,          /* a HIP runtime call failed */
+  FWD_ERR_NONFINITE = 4,    /* the run produced Inf/NaN (e.g. dt above the CFL bound) */
+  FWD_ERR_CFL = 5,          /* fixed dt above the CFL bound (FWD_OPT_STRICT_CFL on) */
+  FWD_ERR_BASIS = 6,        /* basis functions missing or the iteration failed */
+  FWD_ERR_UNSUPPORTED = 7,  /* combination of options not implemented */
+  FWD_ERR_STATE = 8         /* call order violated (e.g. forward before set_model) */
+} fwd_status;
+
+enum { FWD_F32 = 0, FWD_F64 = 1 };                    /* field precision */
+enum { FWD_ACC_F64 = 0, FWD_ACC_KAHAN = 1, FWD_ACC_F32 = 2 };  /* volume transform accumulators */
+enum { FWD_MODE_FORWARD = 0, FWD_MODE_ADJOINT = 1 };
+
+/* Problem description, copied by fwd_plan_create (the pointers are not kept). */
+typedef struct {
+  int nx, ny, nz;                 /* cells per axis, each >= 2*npml + 4 */
+  const double *x, *y, *z;        /* host node coordinates (m) */
+  int npml;                       /* CPML cells inside each end of each axis (>= 0) */
+  /* CPML of Komatitsch & Martin (cited in Section 2); <= 0 selects the default
+     order 2, R 1e-6, kappa_max 1, alpha_max 0.5 sqrt(omega_min omega0), vref =
+     largest fictitious velocity of the model. */
+  double cpml_order, cpml_R, cpml_kappa_max, cpml_alpha_max, cpml_vref;
+  double f0;                      /* reference frequency omega0 / 2 pi (Hz), > 0 */
+  int nfreq; const double *freqs; /* modelled frequencies (Hz), > 0, distinct */
+  int nsrc;                       /* sources advanced together in one batch */
+  const double *src_pos;          /* host [nsrc][3] dipole positions (m) */
+  const double *src_mom;          /* host [nsrc][3] dipole moments (A m) */
+  int nrec; const double *rec_pos;/* host [nrec][3] receiver positions (m) */
+  int ncomp; const int *rec_comp; /* recorded E components, each 0 (x), 1 (y) or 2 (z) */
+  int field_dtype;                /* FWD_F32 or FWD_F64 */
+  int acc_mode;                   /* FWD_ACC_* for the volume transform */
+  double rho_air_cap;             /* resistivities above the cap are stepped at the cap (<= 0: 1e4) */
+  double cfl;                     /* fraction of the CFL bound used for dt (<= 0: 0.95) */
+  double dt;                      /* > 0 fixes dt (s) instead of deriving it from the model */
+  int nt;                         /* > 0 fixes the number of steps */
+} fwd_plan_desc;
+
+typedef struct {
+  double dt, dt_cfl;              /* time step used and the CFL bound of the model */
+  int nt;                         /* steps per run */
+  double vmax, vref;              /* largest fictitious velocity, CPML reference velocity */
+  double tau, t0;                 /* wavelet width and delay (s) */
+  double src_scale;               /* internal source scaling undone in every output */
+  int nx, ny, nz, px;             /* grid and padded x pitch of device arrays */
+  int n_rec_nodes, n_src_entries, n_adj_targets;
+  int have_basis, basis_iters;
+  double basis_gamma, basis_fit;  /* gamma used and max |B B+ - I| */
+  size_t workspace_bytes_forward, workspace_bytes_adjoint, volume_bytes, state_bytes;
+} fwd_info;
+
+/* Tables readable by fwd_get_table (host copies; for tests and tools). */
+enum {
+  FWD_TAB_WAVELET = 0,   /* [nt] w((n+1/2) dt) */
+  FWD_TAB_NORM = 1,      /* complex [nfreq]: sqrt(-i w / 2 w0) / W_k */
+  FWD_TAB_OMEGA = 2,     /* complex [nfreq]: Omega_k = (2/dt) sin(w'_k dt/2) */
+  FWD_TAB_CPML_X = 3,    /* [6][nx+1]: kappa, b, a at integer nodes, then at half nodes (last unused) */
+  FWD_TAB_CPML_Y = 4,
+  FWD_TAB_CPML_Z = 5,
+  FWD_TAB_BASIS = 6,     /* [2 nfreq][nt] basis functions b_k (rows) */
+  FWD_TAB_EDGE_SIGMA = 7 /* [3][nz+1][ny+1][nx+1] edge conductivity (x, y, z edges; unused slots 0) */
+};
+
+/* Validate `desc` and create a plan.  Host only.  Errors: INVALID_ARG. */
+fwd_status fwd_plan_create(const fwd_plan_desc *desc, fwd_plan **plan_out);
+
+/* Free the plan and its device tables (device work using it must be done). */
+void fwd_plan_destroy(fwd_plan *plan);
+
+/* Set the cell resistivity rho_host [nz][ny][nx] (ohm m, > 0).  Derives dt
+ * (CFL, unless fixed), nt (damping of the lowest frequency to 1e-11, unless
+ * fixed), CPML profiles, wavelet, twiddles and edge coefficients
+ * (Section 2).  A change of dt or nt drops the basis functions.  Host only;
+ * device tables are refreshed by the next device call. */
+fwd_status fwd_set_model(fwd_plan *plan, const double *rho_host);
+
+fwd_status fwd_get_info(const fwd_plan *plan, fwd_info *info);
+
+/* Copy table `which` (FWD_TAB_*) into out_host (capacity n doubles). */
+fwd_status fwd_get_table(const fwd_plan *plan, int which, double *out_host, size_t n);
+
+/* Device bytes the caller provides as workspace for `mode` (FWD_MODE_*). */
+fwd_status fwd_workspace_size(const fwd_plan *plan, int mode, size_t *bytes);
+
+/* Device bytes of the forward volume transform (all sources, frequencies and
+ * E components), the forward "wavefield checkpoint" the gradient needs. */
+fwd_status fwd_volume_size(const fwd_plan *plan, size_t *bytes);
+
+/* Full forward run: zero state, nt leapfrog steps, receiver output.
+ *   ws_dev      workspace of fwd_workspace_size(FORWARD) bytes
+ *   vol_dev     NULL, or fwd_volume_size bytes: receives the raw volume
+ *               transform (layout private; read it with fwd_volume_export)
+ *   E_rec_dev   complex [nsrc][nrec][ncomp][nfreq]: E(omega_k) of J = p delta
+ *               (eq. freq) at the receivers, trilinear interpolation
+ * Errors: STATE (no model), INVALID_ARG (sizes), HIP, NONFINITE. */
+fwd_status fwd_forward(fwd_plan *plan, void *ws_dev, size_t ws_bytes,
+                       void *vol_dev, size_t vol_bytes, double *E_rec_dev,
+                       void *stream);
+
+/* Partial runs for checkpointing.  fwd_run_begin zeroes the state in ws
+ * (and vol, if given); fwd_run_steps advances it by nsteps (the step index
+ * lives in the workspace, so runs may be split anywhere); fwd_run_receivers
+ * writes the receiver output of the steps done so far, normalised as in
+ * fwd_forward.  Only FWD_MODE_FORWARD runs can be split. */
+fwd_status fwd_run_begin(fwd_plan *plan, void *ws_dev, size_t ws_bytes,
+                         void *vol_dev, size_t vol_bytes, void *stream);
+fwd_status fwd_run_steps(fwd_plan *plan, void *ws_dev, void *vol_dev,
+                         int nsteps, void *stream);
+fwd_status fwd_run_receivers(fwd_plan *plan, void *ws_dev, double *E_rec_dev,
+                             void *stream);
+
+/* Snapshot of the forward state (fields, CPML memory, receiver sums, step
+ * index; the volume transform when vol_dev is given): fwd_checkpoint_size
+ * bytes of caller memory (device) per snapshot. */
+fwd_status fwd_checkpoint_size(const fwd_plan *plan, int with_volume, size_t *bytes);
+fwd_status fwd_checkpoint_save(fwd_plan *plan, const void *ws_dev, const void *vol_dev,
+                               void *snap_dev, void *stream);
+fwd_status fwd_checkpoint_restore(fwd_plan *plan, void *ws_dev, void *vol_dev,
+                                  const void *snap_dev, void *stream);
+
+/* Normalised volume field E(omega_k) from a forward volume transform:
+ * out_dev complex [nsrc][nfreq][3][nz+1][ny+1][nx+1]; component c sits at
+ * its staggered position (E_x at (x_{i+1/2}, y_j, z_k), ...), slots outside
+ * a component's lattice are 0. */
+fwd_status fwd_volume_export(fwd_plan *plan, const void *vol_dev, double *out_dev,
+                             void *stream);
+
+/* Basis functions of the adjoint-source estimate (Section 3.3): the 2 nfreq
+ * columns of B+ = (B^T B + gamma I)^-1 B^T, each obtained by a conjugate
+ * gradient iteration on the damped normal equations (CGNR, as in the paper)
+ * with B applied matrix-free.  Rows of B are sampled at the injection times
+ * (n+1/2) dt.  gamma = gamma_abs if > 0, else gamma_rel * ||B||_F^2.
+ * Iterates until the normal-equation residual falls below tol (relative) or
+ * max_iter.  Host only.  Outputs (may be NULL): max |B B+ - I|, iterations
+ * of the slowest column.  Errors: STATE (no model), BASIS (no convergence
+ * and fit_err above 1e-2). */
+fwd_status fwd_basis_build(fwd_plan *plan, double gamma_rel, double gamma_abs,
+                           int max_iter, double tol, double *fit_err, int *iters);
+
+/* Adjoint run and gradient.
+ *   vol_fwd_dev   forward volume transform of the same model and sources
+ *   resid_dev     complex [nsrc][nrec][ncomp][nfreq] weighted residual
+ *                 W^2 (d - E) (eq. phid); for a general loss L(E) pass
+ *                 -dL/dE (real and imaginary partial derivatives as re, im)
+ *   grad_dev      double [nz][ny][nx]: d phi / d ln rho (Section 3.5) of the
+ *                 misfit phi = 1/2 ||W (d - E)||^2, summed over sources;
+ *                 added to the current content if accumulate != 0
+ *   E_adj_dev     NULL or complex [nsrc][nrec][ncomp][nfreq]: transform of
+ *                 the adjoint field at the receivers (raw, for checks)
+ * The adjoint source at receiver r, component c is the time series
+ * sum_k Re s_k b_k + Im s_k b_{k+nfreq} (eq. basis) of the spectrum
+ * s_k = sqrt(-i omega_k / 2 omega0) conj(resid) (eq. adj2, electric
+ * residual in the J' slot).  Errors: STATE (no model / no basis), HIP,
+ * NONFINITE. */
+fwd_status fwd_adjoint(fwd_plan *plan, void *ws_dev, size_t ws_bytes,
+                       const void *vol_fwd_dev, const double *resid_dev,
+                       double *grad_dev, int accumulate, double *E_adj_dev,
+                       void *stream);
+
+/* Tuning knobs (FWD_OPT_*); value semantics per key.  Host only. */
+enum {
+  FWD_OPT_GRAPH_STEPS = 0,   /* steps per captured HIP graph (0 or 1: launch eagerly); default 32 */
+  FWD_OPT_BLOCK_X = 1,       /* threads per block along x: 64, 128 or 256 (x * y <= 256) */
+  FWD_OPT_BLOCK_Y = 2,       /* block rows along y: 1, 2 or 4 */
+  FWD_OPT_XCD_REMAP = 3,     /* 1: group neighbouring tiles on one XCD (default) */
+  FWD_OPT_SAMPLE_EVERY = 4,  /* > 0: time the kernels of one step in every this many with
+                                HIP events (those chunks launch eagerly); see fwd_kernel_stats */
+  FWD_OPT_STRICT_CFL = 5     /* 1 (default): fwd_set_model rejects a fixed dt above the CFL
+                                bound with FWD_ERR_CFL; 0 lets it run (and typically end in
+                                FWD_ERR_NONFINITE) */
+};
+fwd_status fwd_set_option(fwd_plan *plan, int key, double value);
+fwd_status fwd_get_option(const fwd_plan *plan, int key, double *value);
+
+/* Self-written tile/schedule autotuner: times every candidate (block shape,
+ * XCD remap) for a few steps of the given mode on the given buffers, keeps
+ * the fastest and returns its time per step (ms).  The state in ws/vol is
+ * clobbered.  */
+fwd_status fwd_autotune(fwd_plan *plan, void *ws_dev, size_t ws_bytes,
+                        void *vol_dev, size_t vol_bytes, int mode, int steps,
+                        double *best_ms, void *stream);
+
+/* Kernel timing of the last fwd_forward / fwd_adjoint, measured with HIP
+ * events on the caller's stream around the time-stepping region: total
+ * milliseconds and number of steps. */
+fwd_status fwd_last_timing(const fwd_plan *plan, double *ms, int *steps);
+
+/* Average device time (ms) of the four kernels of one step -- H update,
+ * injection, E update (+ volume transform or gradient product), receiver
+ * transform -- over the steps sampled in the last fwd_forward / fwd_adjoint
+ * (FWD_OPT_SAMPLE_EVERY > 0), measured with HIP events on the caller's
+ * stream.  avg_ms has room for 4 values. */
+fwd_status fwd_kernel_stats(const fwd_plan *plan, double *avg_ms, int *samples);
+
+const char *fwd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FWDEM_H */

@@ -67,11 +67,11 @@ def edge_sigma(sig: np.ndarray, hx, hy, hz):
     Returns (sx, sy, sz) with shapes (nz+1, ny+1, nx), (nz+1, ny, nx+1),
     (nz, ny+1, nx+1)."""
     Mx, My, Mz = avg_matrix(hx), avg_matrix(hy), avg_matrix(hz)
-    sx = np.einsum("Kk,Jj,kji->KJi", Mz, My, sig)
+    sx = np.einsum("Kk,Jj,kji->KJi", Mz, My, sig, optimize=True)
     sx /= (Mz.sum(1)[:, None, None] * My.sum(1)[None, :, None])
-    sy = np.einsum("Kk,Ii,kji->KjI", Mz, Mx, sig)
+    sy = np.einsum("Kk,Ii,kji->KjI", Mz, Mx, sig, optimize=True)
     sy /= (Mz.sum(1)[:, None, None] * Mx.sum(1)[None, None, :])
-    sz = np.einsum("Jj,Ii,kji->kJI", My, Mx, sig)
+    sz = np.einsum("Jj,Ii,kji->kJI", My, Mx, sig, optimize=True)
     sz /= (My.sum(1)[None, :, None] * Mx.sum(1)[None, None, :])
     return sx, sy, sz
 
@@ -83,9 +83,9 @@ def edge_sigma_transpose(gx, gy, gz, hx, hy, hz):
     dx = Mz.sum(1)[:, None, None] * My.sum(1)[None, :, None]
     dy = Mz.sum(1)[:, None, None] * Mx.sum(1)[None, None, :]
     dz = My.sum(1)[None, :, None] * Mx.sum(1)[None, None, :]
-    out = np.einsum("Kk,Jj,KJi->kji", Mz, My, gx / dx)
-    out += np.einsum("Kk,Ii,KjI->kji", Mz, Mx, gy / dy)
-    out += np.einsum("Jj,Ii,kJI->kji", My, Mx, gz / dz)
+    out = np.einsum("Kk,Jj,KJi->kji", Mz, My, gx / dx, optimize=True)
+    out += np.einsum("Kk,Ii,KjI->kji", Mz, Mx, gy / dy, optimize=True)
+    out += np.einsum("Jj,Ii,kJI->kji", My, Mx, gz / dz, optimize=True)
     return out
 
 

@@ -1,0 +1,67 @@
+"""torch.autograd wrapper: forward modelling with the adjoint gradient.
+
+``FictitiousForward.apply(log_rho, plan)`` returns E at the receivers
+(complex128 [ns][nr][ncomp][nf]) for the resistivity exp(log_rho); its
+backward runs one adjoint simulation driven by the basis-function adjoint
+sources (Section 3.3) and returns d loss / d log_rho (Section 3.5 chain
+rule).  The forward keeps the volume transform of E as the frequency-domain
+checkpoint the gradient needs; with ``snapshot_every`` > 0 it also keeps
+device snapshots of the full time-domain state every that many steps.
+
+PyTorch hands the backward the conjugate Wirtinger gradient
+gE = dL/dRe E + i dL/dIm E; for the data misfit L = 1/2 ||W (d - E)||^2
+this is -W^2 (d - E), so the library's weighted residual is -gE.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from .fwdem import Plan
+
+
+class FictitiousForward(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, log_rho: torch.Tensor, plan: Plan, snapshot_every: int = 0,
+                gamma_rel: float = 1e-12):
+        rho = torch.exp(log_rho.detach().to(torch.float64)).cpu().numpy()
+        plan.set_model(rho)
+        if not plan.info.have_basis:
+            plan.basis_build(gamma_rel=gamma_rel)
+        vol = plan.volume_buffer()
+        snaps = []
+        if snapshot_every and snapshot_every > 0:
+            nt = plan.info.nt
+            plan.run_begin(vol)
+            done = 0
+            while done < nt:
+                m = min(snapshot_every, nt - done)
+                plan.run_steps(m, vol)
+                done += m
+                if done < nt:
+                    snap = torch.empty(plan.checkpoint_size(False), dtype=torch.uint8,
+                                       device="cuda")
+                    plan.checkpoint_save(snap)
+                    snaps.append((done, snap))
+            E = plan.run_receivers()
+        else:
+            E, vol = plan.forward(vol=vol, want_volume=True)
+        ctx.plan = plan
+        ctx.vol = vol
+        ctx.snapshots = snaps
+        ctx.in_dtype = log_rho.dtype
+        ctx.in_device = log_rho.device
+        return E
+
+    @staticmethod
+    def backward(ctx, gE):
+        plan: Plan = ctx.plan
+        resid = (-gE).to(torch.complex128).contiguous()
+        grad = plan.adjoint(ctx.vol, resid)
+        return grad.to(dtype=ctx.in_dtype, device=ctx.in_device), None, None, None
+
+
+def misfit(E: torch.Tensor, d: torch.Tensor, W=1.0) -> torch.Tensor:
+    """phi_d = 1/2 sum |W (d - E)|^2 (eq. phid, electric data)."""
+    r = (d - E) * W
+    return 0.5 * (r.real ** 2 + r.imag ** 2).sum()

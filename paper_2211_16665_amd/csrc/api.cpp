@@ -1,0 +1,303 @@
+// C ABI of the library: argument checks, error translation (no exception
+// crosses the boundary) and the thread-local last-error message.
+#include <cstring>
+#include <exception>
+#include <new>
+#include <string>
+
+#include "fwdem_internal.hpp"
+
+using namespace fwdem;
+
+static thread_local std::string g_err;
+
+template <typename F>
+static fwd_status guard(F &&f) {
+  try {
+    g_err.clear();
+    f();
+    return FWD_OK;
+  } catch (const Error &e) {
+    g_err = e.msg;
+    return e.code;
+  } catch (const std::bad_alloc &) {
+    g_err = "host allocation failed";
+    return FWD_ERR_OOM;
+  } catch (const std::exception &e) {
+    g_err = e.what();
+    return FWD_ERR_INVALID_ARG;
+  } catch (...) {
+    g_err = "unknown error";
+    return FWD_ERR_INVALID_ARG;
+  }
+}
+
+static Plan &P(fwd_plan *h) {
+  if (!h || !h->p) fail(FWD_ERR_INVALID_ARG, "plan is NULL");
+  return *h->p;
+}
+static const Plan &P(const fwd_plan *h) {
+  if (!h || !h->p) fail(FWD_ERR_INVALID_ARG, "plan is NULL");
+  return *h->p;
+}
+
+extern "C" {
+
+const char *fwd_last_error(void) { return g_err.c_str(); }
+
+fwd_status fwd_plan_create(const fwd_plan_desc *desc, fwd_plan **out) {
+  return guard([&] {
+    if (!out) fail(FWD_ERR_INVALID_ARG, "plan_out is NULL");
+    *out = nullptr;
+    Plan *p = plan_create(desc);
+    *out = new fwd_plan{p};
+  });
+}
+
+void fwd_plan_destroy(fwd_plan *h) {
+  if (!h) return;
+  if (h->p) {
+    try {
+      dev_release(*h->p);
+    } catch (...) {
+    }
+    delete h->p;
+  }
+  delete h;
+}
+
+fwd_status fwd_set_model(fwd_plan *h, const double *rho) {
+  return guard([&] { set_model(P(h), rho); });
+}
+
+fwd_status fwd_get_info(const fwd_plan *h, fwd_info *info) {
+  return guard([&] {
+    const Plan &p = P(h);
+    if (!info) fail(FWD_ERR_INVALID_ARG, "info is NULL");
+    std::memset(info, 0, sizeof *info);
+    info->nx = p.nx;
+    info->ny = p.ny;
+    info->nz = p.nz;
+    info->px = p.PX;
+    info->have_basis = p.have_basis;
+    info->basis_iters = p.basis_iters;
+    info->basis_gamma = p.gamma;
+    info->basis_fit = p.fit;
+    if (!p.have_model) return;
+    info->dt = p.dt;
+    info->dt_cfl = p.dt_cfl;
+    info->nt = p.nt;
+    info->vmax = p.vmax;
+    info->vref = p.vref;
+    info->tau = p.tau;
+    info->t0 = p.t0;
+    info->src_scale = p.src_scale;
+    info->n_rec_nodes = (int)p.rn_c.size();
+    info->n_src_entries = (int)p.src_tg.size();
+    info->n_adj_targets = (int)p.rn_c.size() * p.ns;
+    info->workspace_bytes_forward = p.workspace_bytes(FWD_MODE_FORWARD);
+    info->workspace_bytes_adjoint = p.workspace_bytes(FWD_MODE_ADJOINT);
+    info->volume_bytes = p.volume_bytes();
+    info->state_bytes = p.state_bytes();
+  });
+}
+
+fwd_status fwd_get_table(const fwd_plan *h, int which, double *out, size_t n) {
+  return guard([&] {
+    if (!out) fail(FWD_ERR_INVALID_ARG, "out is NULL");
+    get_table(P(h), which, out, n);
+  });
+}
+
+fwd_status fwd_workspace_size(const fwd_plan *h, int mode, size_t *bytes) {
+  return guard([&] {
+    const Plan &p = P(h);
+    if (!bytes) fail(FWD_ERR_INVALID_ARG, "bytes is NULL");
+    if (mode != FWD_MODE_FORWARD && mode != FWD_MODE_ADJOINT) fail(FWD_ERR_INVALID_ARG, "mode");
+    if (!p.have_model) fail(FWD_ERR_STATE, "no model set");
+    *bytes = p.workspace_bytes(mode);
+  });
+}
+
+fwd_status fwd_volume_size(const fwd_plan *h, size_t *bytes) {
+  return guard([&] {
+    const Plan &p = P(h);
+    if (!bytes) fail(FWD_ERR_INVALID_ARG, "bytes is NULL");
+    *bytes = p.volume_bytes();
+  });
+}
+
+fwd_status fwd_forward(fwd_plan *h, void *ws, size_t ws_bytes, void *vol, size_t vol_bytes,
+                       double *E_rec, void *stream) {
+  return guard([&] {
+    Plan &p = P(h);
+    if (!p.have_model) fail(FWD_ERR_STATE, "no model set");
+    if (!ws || !E_rec) fail(FWD_ERR_INVALID_ARG, "workspace and E_rec are required");
+    dev_forward(p, ws, ws_bytes, vol, vol_bytes, E_rec, stream);
+  });
+}
+
+fwd_status fwd_run_begin(fwd_plan *h, void *ws, size_t ws_bytes, void *vol, size_t vol_bytes,
+                         void *stream) {
+  return guard([&] {
+    Plan &p = P(h);
+    if (!p.have_model) fail(FWD_ERR_STATE, "no model set");
+    if (!ws) fail(FWD_ERR_INVALID_ARG, "workspace is required");
+    dev_run_begin(p, ws, ws_bytes, vol, vol_bytes, stream);
+  });
+}
+
+fwd_status fwd_run_steps(fwd_plan *h, void *ws, void *vol, int nsteps, void *stream) {
+  return guard([&] {
+    Plan &p = P(h);
+    if (!p.have_model) fail(FWD_ERR_STATE, "no model set");
+    if (!ws) fail(FWD_ERR_INVALID_ARG, "workspace is required");
+    dev_run_steps(p, ws, vol, nsteps, stream);
+  });
+}
+
+fwd_status fwd_run_receivers(fwd_plan *h, void *ws, double *E_rec, void *stream) {
+  return guard([&] {
+    Plan &p = P(h);
+    if (!p.have_model) fail(FWD_ERR_STATE, "no model set");
+    if (!ws || !E_rec) fail(FWD_ERR_INVALID_ARG, "workspace and E_rec are required");
+    dev_run_receivers(p, ws, E_rec, stream);
+  });
+}
+
+fwd_status fwd_checkpoint_size(const fwd_plan *h, int with_volume, size_t *bytes) {
+  return guard([&] {
+    const Plan &p = P(h);
+    if (!bytes) fail(FWD_ERR_INVALID_ARG, "bytes is NULL");
+    if (!p.have_model) fail(FWD_ERR_STATE, "no model set");
+    *bytes = p.state_bytes() + (with_volume ? p.volume_bytes() : 0);
+  });
+}
+
+fwd_status fwd_checkpoint_save(fwd_plan *h, const void *ws, const void *vol, void *snap,
+                               void *stream) {
+  return guard([&] {
+    Plan &p = P(h);
+    if (!p.have_model) fail(FWD_ERR_STATE, "no model set");
+    if (!ws || !snap) fail(FWD_ERR_INVALID_ARG, "workspace and snapshot are required");
+    dev_checkpoint(p, ws, vol, snap, 1, stream);
+  });
+}
+
+fwd_status fwd_checkpoint_restore(fwd_plan *h, void *ws, void *vol, const void *snap,
+                                  void *stream) {
+  return guard([&] {
+    Plan &p = P(h);
+    if (!p.have_model) fail(FWD_ERR_STATE, "no model set");
+    if (!ws || !snap) fail(FWD_ERR_INVALID_ARG, "workspace and snapshot are required");
+    dev_checkpoint(p, ws, vol, const_cast<void *>(snap), 0, stream);
+  });
+}
+
+fwd_status fwd_volume_export(fwd_plan *h, const void *vol, double *out, void *stream) {
+  return guard([&] {
+    Plan &p = P(h);
+    if (!p.have_model) fail(FWD_ERR_STATE, "no model set");
+    if (!vol || !out) fail(FWD_ERR_INVALID_ARG, "volume and output are required");
+    dev_volume_export(p, vol, out, stream);
+  });
+}
+
+fwd_status fwd_basis_build(fwd_plan *h, double gamma_rel, double gamma_abs, int max_iter,
+                           double tol, double *fit_err, int *iters) {
+  return guard([&] { basis_build(P(h), gamma_rel, gamma_abs, max_iter, tol, fit_err, iters); });
+}
+
+fwd_status fwd_adjoint(fwd_plan *h, void *ws, size_t ws_bytes, const void *vol,
+                       const double *resid, double *grad, int accumulate, double *E_adj,
+                       void *stream) {
+  return guard([&] {
+    Plan &p = P(h);
+    if (!p.have_model) fail(FWD_ERR_STATE, "no model set");
+    if (!ws || !resid || !grad) fail(FWD_ERR_INVALID_ARG, "workspace, residual and gradient are required");
+    dev_adjoint(p, ws, ws_bytes, vol, resid, grad, accumulate, E_adj, stream);
+  });
+}
+
+fwd_status fwd_set_option(fwd_plan *h, int key, double value) {
+  return guard([&] {
+    Plan &p = P(h);
+    const int v = (int)value;
+    switch (key) {
+      case FWD_OPT_GRAPH_STEPS:
+        if (v < 0 || v > 4096) fail(FWD_ERR_INVALID_ARG, "graph steps in [0, 4096]");
+        p.graph_steps = v;
+        break;
+      case FWD_OPT_BLOCK_X:
+        if (v != 64 && v != 128 && v != 256) fail(FWD_ERR_INVALID_ARG, "block x in {64,128,256}");
+        if (v * p.by > 256) fail(FWD_ERR_INVALID_ARG, "block x * y must be <= 256");
+        p.bx = v;
+        break;
+      case FWD_OPT_BLOCK_Y:
+        if (v != 1 && v != 2 && v != 4) fail(FWD_ERR_INVALID_ARG, "block y in {1,2,4}");
+        if (v * p.bx > 256) fail(FWD_ERR_INVALID_ARG, "block x * y must be <= 256");
+        p.by = v;
+        break;
+      case FWD_OPT_XCD_REMAP:
+        p.xcd = v ? 1 : 0;
+        break;
+      case FWD_OPT_SAMPLE_EVERY:
+        if (v < 0) fail(FWD_ERR_INVALID_ARG, "sample interval >= 0");
+        dev_set_sampling(p, v);
+        break;
+      case FWD_OPT_STRICT_CFL:
+        p.strict_cfl = v ? 1 : 0;
+        break;
+      default:
+        fail(FWD_ERR_INVALID_ARG, "unknown option");
+    }
+  });
+}
+
+fwd_status fwd_get_option(const fwd_plan *h, int key, double *value) {
+  return guard([&] {
+    Plan &p = const_cast<Plan &>(P(h));
+    if (!value) fail(FWD_ERR_INVALID_ARG, "value is NULL");
+    switch (key) {
+      case FWD_OPT_GRAPH_STEPS: *value = p.graph_steps; break;
+      case FWD_OPT_BLOCK_X: *value = p.bx; break;
+      case FWD_OPT_BLOCK_Y: *value = p.by; break;
+      case FWD_OPT_XCD_REMAP: *value = p.xcd; break;
+      case FWD_OPT_SAMPLE_EVERY: *value = dev_get_sampling(p); break;
+      case FWD_OPT_STRICT_CFL: *value = p.strict_cfl; break;
+      default: fail(FWD_ERR_INVALID_ARG, "unknown option");
+    }
+  });
+}
+
+fwd_status fwd_autotune(fwd_plan *h, void *ws, size_t ws_bytes, void *vol, size_t vol_bytes,
+                        int mode, int steps, double *best_ms, void *stream) {
+  return guard([&] {
+    Plan &p = P(h);
+    if (!p.have_model) fail(FWD_ERR_STATE, "no model set");
+    if (!ws) fail(FWD_ERR_INVALID_ARG, "workspace is required");
+    if (steps < 1) fail(FWD_ERR_INVALID_ARG, "steps >= 1");
+    const double ms = dev_autotune(p, ws, ws_bytes, vol, vol_bytes, mode, steps, stream);
+    if (best_ms) *best_ms = ms;
+  });
+}
+
+fwd_status fwd_last_timing(const fwd_plan *h, double *ms, int *steps) {
+  return guard([&] {
+    const Plan &p = P(h);
+    if (ms) *ms = p.last_ms;
+    if (steps) *steps = p.last_steps;
+  });
+}
+
+fwd_status fwd_kernel_stats(const fwd_plan *h, double *avg_ms, int *samples) {
+  return guard([&] {
+    Plan &p = const_cast<Plan &>(P(h));
+    if (!avg_ms) fail(FWD_ERR_INVALID_ARG, "avg_ms is NULL");
+    int n = 0;
+    dev_kernel_stats(p, avg_ms, &n);
+    if (samples) *samples = n;
+  });
+}
+
+}  // extern "C"

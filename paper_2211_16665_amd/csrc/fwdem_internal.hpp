@@ -1,0 +1,155 @@
+// Internal declarations shared by the host setup (setup.cpp), the device
+// driver (device.hip) and the C ABI (api.cpp).
+#pragma once
+
+#include <complex>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "fwdem.h"
+
+namespace fwdem {
+
+using cplx = std::complex<double>;
+
+struct Error {
+  fwd_status code;
+  std::string msg;
+};
+[[noreturn]] void fail(fwd_status code, const std::string &msg);
+
+constexpr double kMu0 = 4.0e-7 * 3.14159265358979323846;
+constexpr double kPi = 3.14159265358979323846;
+
+// Defaults of the CPML and of the step count (mirrored by no other code:
+// the oracle states the same definitions independently).
+constexpr double kCpmlOrder = 2.0;
+constexpr double kCpmlR = 1.0e-6;
+constexpr double kCpmlKappaMax = 1.0;
+constexpr double kCpmlAlphaFactor = 0.5;  // alpha_max = factor * sqrt(omega_min omega0)
+constexpr double kNtTol = 1.0e-11;        // exp(-a_min nt dt)
+constexpr double kDefaultCap = 1.0e4;
+constexpr double kDefaultCfl = 0.95;
+
+struct Axis {
+  int n = 0;                     // cells
+  std::vector<double> nodes;     // n+1
+  std::vector<double> h;         // n   cell widths
+  std::vector<double> hd;        // n+1 dual widths (half a cell at the ends)
+  // CPML: 1/kappa, b, a at integer nodes (n+1) and half nodes (n)
+  std::vector<double> kinv_n, b_n, a_n;
+  std::vector<double> kinv_h, b_h, a_h;
+};
+
+// One injection target: E component c of source s at linear index idx of
+// the padded device layout; the per-step value is
+// sum_r coef[toff + r] * F[r][n] with nrow rows of time functions F.
+struct Target {
+  int s;
+  int c;
+  int64_t idx;
+  int toff;
+};
+
+struct Plan {
+  // ---- description ----
+  int nx = 0, ny = 0, nz = 0, npml = 0;
+  int NX = 0, NY = 0, NZ = 0, PX = 0;   // node counts and padded x pitch
+  Axis ax[3];
+  double cpml_order = 0, cpml_R = 0, cpml_kmax = 0, cpml_amax_in = 0, cpml_vref_in = 0;
+  double f0 = 0, omega0 = 0;
+  std::vector<double> freqs, omega, a;   // a = sqrt(omega omega0)
+  std::vector<cplx> wprime;              // (1+i) a
+  int ns = 0, nr = 0, ncomp = 0;
+  std::vector<double> src_pos, src_mom, rec_pos;
+  std::vector<int> comp;
+  int dtype = FWD_F32, acc = FWD_ACC_F64;
+  double cap = 0, cfl = 0, dt_user = 0;
+  int nt_user = 0;
+
+  // ---- derived from the model ----
+  bool have_model = false;
+  std::vector<double> rho, sigma;
+  std::vector<uint8_t> capped;
+  std::vector<double> sig_e[3];          // edge conductivity, padded layout
+  std::vector<double> ce[3];             // dt/eps on updated edges, 0 elsewhere
+  double dt = 0, dt_cfl = 0, vmax = 0, vref = 0, amax = 0;
+  int nt = 0;
+  std::vector<double> wavelet;           // [nt]
+  double tau = 0, t0 = 0;
+  std::vector<cplx> What, norm, Omega;   // [nf]
+  std::vector<cplx> zE;                  // [nt][nf] z^{n+1}
+  // forward injection (per source, merged duplicates)
+  std::vector<Target> src_tg;
+  std::vector<double> src_coef;          // one coefficient per target
+  double src_scale = 1.0;
+  // receiver nodes (shared by all sources)
+  std::vector<int> rn_c;
+  std::vector<int64_t> rn_idx;
+  std::vector<int> ri_ptr, ri_node;      // CSR over (r, ci) -> nodes
+  std::vector<double> ri_w;
+  // adjoint targets = receiver nodes; CSR node -> (row r*ncomp+ci, w / dual volume)
+  std::vector<int> at_ptr, at_row;
+  std::vector<double> at_w;
+
+  // ---- basis functions ----
+  bool have_basis = false;
+  std::vector<double> basis;             // [2nf][nt]
+  double gamma = 0, fit = 0;
+  int basis_iters = 0;
+
+  // ---- options ----
+  int graph_steps = 32, bx = 64, by = 4, xcd = 1, strict_cfl = 1;
+
+  // ---- device side (managed in device.hip) ----
+  void *dev = nullptr;
+  uint64_t model_version = 0, basis_version = 0;
+  double last_ms = 0;
+  int last_steps = 0;
+
+  int64_t plane() const { return (int64_t)NY * PX; }
+  int64_t field_elems() const { return (int64_t)NZ * NY * PX; }
+  int64_t lin(int k, int j, int i) const { return ((int64_t)k * NY + j) * PX + i; }
+  int nf() const { return (int)freqs.size(); }
+  size_t tsize() const { return dtype == FWD_F64 ? 8 : 4; }
+  size_t acc_bytes() const { return acc == FWD_ACC_F32 ? 8 : 16; }
+  int64_t psi_elems_per_source() const;
+  size_t state_bytes() const;       // fields + psi + receiver sums + step index
+  size_t workspace_bytes(int mode) const;
+  size_t volume_bytes() const;
+};
+
+// host setup (setup.cpp)
+Plan *plan_create(const fwd_plan_desc *d);
+void set_model(Plan &p, const double *rho);
+void basis_build(Plan &p, double gamma_rel, double gamma_abs, int max_iter, double tol,
+                 double *fit_err, int *iters);
+void adjoint_coefficients(const Plan &p, const double *resid_host, std::vector<double> &T,
+                          double &scale);
+void get_table(const Plan &p, int which, double *out, size_t n);
+
+// device driver (device.hip)
+void dev_release(Plan &p);
+void dev_forward(Plan &p, void *ws, size_t ws_bytes, void *vol, size_t vol_bytes,
+                 double *E_rec, void *stream);
+void dev_run_begin(Plan &p, void *ws, size_t ws_bytes, void *vol, size_t vol_bytes,
+                   void *stream);
+void dev_run_steps(Plan &p, void *ws, void *vol, int nsteps, void *stream);
+void dev_run_receivers(Plan &p, void *ws, double *E_rec, void *stream);
+void dev_checkpoint(Plan &p, const void *ws, const void *vol, void *snap, int save,
+                    void *stream);
+void dev_volume_export(Plan &p, const void *vol, double *out, void *stream);
+void dev_adjoint(Plan &p, void *ws, size_t ws_bytes, const void *vol, const double *resid,
+                 double *grad, int accumulate, double *E_adj, void *stream);
+double dev_autotune(Plan &p, void *ws, size_t ws_bytes, void *vol, size_t vol_bytes,
+                    int mode, int steps, void *stream);
+void dev_set_sampling(Plan &p, int every);
+int dev_get_sampling(Plan &p);
+void dev_kernel_stats(Plan &p, double *ms4, int *count);
+
+}  // namespace fwdem
+
+struct fwd_plan {
+  fwdem::Plan *p;
+};

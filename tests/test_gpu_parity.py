@@ -1,0 +1,253 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Tolerances: FP64 fields agree with the FP64 oracle to rounding (1e-10 to
+1e-11 relative to the largest value); FP32 fields with FP64 or compensated
+accumulators to 1e-4 (the stated FP32 field tolerance), the gradient to 1e-3
+in relative L2 norm.  Integer-like properties (batching, checkpoint/resume,
+graph replay, repeated runs) are compared bit for bit.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle.discretization import make_setup
+from oracle.stepping import point_entries
+from workloads import c1_wholespace, c2_marine1d, tiny, with_window
+
+pytestmark = pytest.mark.gpu
+
+fw = pytest.importorskip("paper_2211_16665_amd.fwdem")
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def gpu_forward(w, dtype="f64", acc="f64", volume=False, **opt):
+    p = fw.Plan.from_workload(w, field_dtype=dtype, acc_mode=acc)
+    for k, v in opt.items():
+        p.set_option(getattr(fw, "FWD_OPT_" + k.upper()), v)
+    p.set_model(w.rho)
+    if volume:
+        E, vol = p.forward(want_volume=True)
+        return p, E.cpu().numpy(), vol
+    return p, p.forward().cpu().numpy(), None
+
+
+def rel(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+# --------------------------------------------------------------------------
+# forward
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("seed,npml,ns", [(0, 3, 1), (1, 0, 1), (2, 3, 3)])
+def test_tiny_forward_fp64(seed, npml, ns):
+    w = tiny(seed=seed, npml=npml, ns=ns, moment_dirs=True, contrast=1.5)
+    say(f"tiny forward fp64 seed={seed} npml={npml} ns={ns} shape={w.shape}")
+    ref = oracle.forward(w, want_volume=True)
+    p, E, vol = gpu_forward(w, "f64", "f64", volume=True)
+    assert rel(E, ref["E_rec"]) < 1e-11
+    V = p.volume_export(vol).cpu().numpy()          # [ns][nf][3][nz+1][ny+1][nx+1]
+    nz, ny, nx = w.shape
+    for s in range(ns):
+        ox, oy, oz = ref["vol"][s]
+        assert rel(V[s, :, 0, :, :, :nx], ox) < 1e-11
+        assert rel(V[s, :, 1, :, :ny, :], oy) < 1e-11
+        assert rel(V[s, :, 2, :nz, :, :], oz) < 1e-11
+
+
+@pytest.mark.parametrize("acc,tol", [("f64", 1e-4), ("kahan", 1e-4), ("f32", 1e-3)])
+def test_tiny_forward_fp32(acc, tol):
+    w = tiny(seed=4, npml=3, ns=2, contrast=1.0, nfreq=3)
+    say(f"tiny forward fp32 acc={acc}")
+    ref = oracle.forward(w, want_volume=True)
+    p, E, vol = gpu_forward(w, "f32", acc, volume=True)
+    for s in range(w.ns):
+        for k in range(len(w.freqs)):
+            # per source and frequency, relative to that slice's largest value
+            assert rel(E[s, ..., k], ref["E_rec"][s, ..., k]) < tol
+    V = p.volume_export(vol).cpu().numpy()
+    nz, ny, nx = w.shape
+    assert rel(V[0, :, 0, :, :, :nx], ref["vol"][0][0]) < tol
+
+
+def test_wholespace_fp64_matches_oracle():
+    """Config c1 in full (32^3, 2000 steps, FP64)."""
+    w = c1_wholespace()
+    say("c1 wholespace fp64 full")
+    ref = oracle.forward(w)["E_rec"]
+    _, E, _ = gpu_forward(w, "f64", "f64")
+    err = np.abs(E - ref).max(axis=(0, 2, 3)) / np.abs(ref).max(axis=(0, 2, 3))
+    assert err.max() < 1e-10
+
+
+def test_marine_window_fp32():
+    """Config c2 at full spatial size, first 200 steps (partial sums), FP32
+    fields with FP64 accumulators against the FP64 oracle."""
+    w = with_window(c2_marine1d(), 200)
+    say("c2 marine window 200 steps fp32/f64")
+    ref = oracle.forward(w)["E_rec"]
+    _, E, _ = gpu_forward(w, "f32", "f64")
+    for k in range(len(w.freqs)):
+        assert rel(E[..., k], ref[..., k]) < 1e-4
+
+
+# --------------------------------------------------------------------------
+# properties bit for bit
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_batched_equals_single_sources(dtype):
+    w = tiny(seed=5, npml=3, ns=4, moment_dirs=True, contrast=1.0)
+    say(f"batched vs single dtype={dtype}")
+    _, Eb, _ = gpu_forward(w, dtype, "f64")
+    for s in range(w.ns):
+        ws = w.replace(src_pos=w.src_pos[s:s + 1], src_mom=w.src_mom[s:s + 1])
+        _, E1, _ = gpu_forward(ws, dtype, "f64")
+        assert np.array_equal(Eb[s], E1[0])
+
+
+def test_graph_replay_equals_eager_and_repeatable():
+    w = tiny(seed=6, npml=3, ns=2)
+    say("graph vs eager")
+    _, E1, _ = gpu_forward(w, "f32", "f64", graph_steps=16)
+    _, E2, _ = gpu_forward(w, "f32", "f64", graph_steps=0)
+    _, E3, _ = gpu_forward(w, "f32", "f64", graph_steps=16)
+    _, E4, _ = gpu_forward(w, "f32", "f64", graph_steps=16, xcd_remap=0, block_y=2, block_x=128)
+    assert np.array_equal(E1, E2) and np.array_equal(E1, E3) and np.array_equal(E1, E4)
+
+
+def test_checkpoint_resume_bitwise():
+    w = tiny(seed=7, npml=3, ns=2)
+    say("checkpoint resume")
+    p = fw.Plan.from_workload(w, field_dtype="f32", acc_mode="kahan")
+    p.set_model(w.rho)
+    nt = p.info.nt
+    E_full, vol_full = p.forward(want_volume=True)
+    E_full = E_full.cpu().numpy()
+    vfull = p.volume_export(vol_full).cpu().numpy()
+    vol = p.volume_buffer()
+    p.run_begin(vol)
+    k = nt // 3
+    p.run_steps(k, vol)
+    snap = torch.empty(p.checkpoint_size(True), dtype=torch.uint8, device="cuda")
+    p.checkpoint_save(snap, vol)
+    p.run_steps(nt // 2, vol)                  # diverge
+    p.checkpoint_restore(snap, vol)
+    p.run_steps(nt - k, vol)
+    E = p.run_receivers().cpu().numpy()
+    assert np.array_equal(E, E_full)
+    assert np.array_equal(p.volume_export(vol).cpu().numpy(), vfull)
+
+
+def test_unstable_dt_reports_nonfinite():
+    w = tiny(seed=8, npml=2, n=(10, 10, 10))
+    s = make_setup(w)
+    w2 = w.replace(dt=2.0 * s.dt / 0.95, nt=3000)
+    say("nonfinite")
+    p = fw.Plan.from_workload(w2, field_dtype="f32")
+    p.set_option(fw.FWD_OPT_STRICT_CFL, 0)
+    p.set_model(w2.rho)
+    with pytest.raises(fw.FwdError) as e:
+        p.forward()
+    assert e.value.status == 4
+
+
+def test_reciprocity_gpu_fp64():
+    w = tiny(seed=9, npml=3, contrast=1.5, nr=1)
+    A, B = w.src_pos[0], w.rec_pos[0]
+    say("reciprocity")
+    out = {}
+    for (src, rec) in ((A, B), (B, A)):
+        for a in range(3):
+            mom = np.zeros(3)
+            mom[a] = 1.0
+            ww = w.replace(src_pos=np.array([src]), src_mom=np.array([mom]),
+                           rec_pos=np.array([rec]), rec_comp=(0, 1, 2))
+            out[(tuple(src), a)] = gpu_forward(ww, "f64")[1][0, 0]
+    for a in range(3):
+        for b in range(3):
+            gab, gba = out[(tuple(A), a)][b], out[(tuple(B), b)][a]
+            assert np.allclose(gab, gba, rtol=1e-9, atol=1e-12 * np.abs(gab).max())
+
+
+# --------------------------------------------------------------------------
+# adjoint and gradient
+# --------------------------------------------------------------------------
+def _inverse_problem(seed=3, ns=1):
+    w_true = tiny(seed=seed, n=(14, 12, 10), npml=3, contrast=1.0, nr=8, nfreq=2, ns=ns)
+    rng = np.random.default_rng(seed + 100)
+    w0 = w_true.replace(rho=w_true.rho * np.exp(0.3 * rng.standard_normal(w_true.rho.shape)))
+    d = oracle.forward(w_true)["E_rec"]
+    s0 = make_setup(w0)
+    w0 = w0.replace(dt=s0.dt, nt=s0.nt)
+    w0.cpml_vref = s0.vref
+    return w0, d
+
+
+@pytest.mark.parametrize("dtype,acc,tol", [("f64", "f64", 1e-7), ("f32", "f64", 1e-3),
+                                           ("f32", "kahan", 1e-3)])
+def test_gradient_matches_oracle(dtype, acc, tol):
+    w0, d = _inverse_problem(ns=2)
+    say(f"gradient dtype={dtype} acc={acc}")
+    fwd = oracle.forward(w0, want_volume=True)
+    resid = d - fwd["E_rec"]
+    go = oracle.adjoint_gradient(w0, fwd, resid)["grad"]
+    p = fw.Plan.from_workload(w0, field_dtype=dtype, acc_mode=acc)
+    p.set_model(w0.rho)
+    p.basis_build(gamma_rel=1e-12)
+    E, vol = p.forward(want_volume=True)
+    r = torch.from_numpy(d).cuda() - E
+    g = p.adjoint(vol, r).cpu().numpy()
+    err = np.linalg.norm(g - go) / np.linalg.norm(go)
+    assert err < tol, err
+
+
+def test_adjoint_field_at_receivers_matches_oracle():
+    w0, d = _inverse_problem()
+    say("adjoint field at receivers")
+    fwd = oracle.forward(w0, want_volume=True)
+    s = fwd["setup"]
+    resid = d - fwd["E_rec"]
+    # oracle adjoint transform at the receivers: probe every lattice node the
+    # receivers touch and interpolate
+    nodes, weights = [], []
+    for r, pos in enumerate(w0.rec_pos):
+        for c in w0.rec_comp:
+            ent = point_entries(s, c, pos)
+            weights.append([(len(nodes) + m, e[3]) for m, e in enumerate(ent)])
+            nodes.extend([(c, e[0], e[1], e[2]) for e in ent])
+    go = oracle.adjoint_gradient(w0, fwd, resid, probe_nodes=nodes)
+    pr = go["probe"][0]
+    ref = np.array([[sum(wt * pr[m, k] for m, wt in lst) for k in range(len(w0.freqs))]
+                    for lst in weights]).reshape(len(w0.rec_pos), len(w0.rec_comp), -1)
+    p = fw.Plan.from_workload(w0, field_dtype="f64")
+    p.set_model(w0.rho)
+    p.basis_build(gamma_rel=1e-12)
+    E, vol = p.forward(want_volume=True)
+    _, Ea = p.adjoint(vol, torch.from_numpy(resid).cuda(), want_adjoint_rec=True)
+    assert rel(Ea.cpu().numpy()[0], ref) < 1e-7
+
+
+def test_autograd_gradient_matches_finite_differences():
+    from paper_2211_16665_amd.autograd import FictitiousForward, misfit
+    w0, d = _inverse_problem(seed=4)
+    say("autograd vs finite differences (fp64)")
+    p = fw.Plan.from_workload(w0, field_dtype="f64")
+    dd = torch.from_numpy(d).cuda()
+    m = torch.tensor(np.log(w0.rho), dtype=torch.float64, device="cuda", requires_grad=True)
+    L = misfit(FictitiousForward.apply(m, p), dd)
+    L.backward()
+    g = m.grad.cpu().numpy()
+    h = 1e-3
+    for c in [(4, 5, 6), (5, 5, 5), (6, 4, 8)]:
+        vals = []
+        for sgn in (1, -1):
+            mm = np.log(w0.rho).copy()
+            mm[c] += sgn * h
+            with torch.no_grad():
+                E = FictitiousForward.apply(torch.from_numpy(mm).cuda(), p)
+            vals.append(float(misfit(E, dd)))
+        fd = (vals[0] - vals[1]) / (2 * h)
+        assert abs(fd - g[c]) < 1e-4 * abs(fd), (c, fd, g[c])

@@ -1,0 +1,171 @@
+"""CPU tests of the C ABI: the library loads and exports what include/fwdem.h
+declares, validates its inputs, and its host-side setup (time step, step
+count, CPML profiles, wavelet and its transform, edge conductivity, basis
+functions by CGNR) agrees with the oracle.  No call here touches a GPU."""
+import json
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle.basis import basis_matrix, basis_pinv, gamma_from_rel
+from oracle.discretization import make_setup
+from workloads import c1_wholespace, c2_marine1d, c3_blocks, tiny
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+fw = pytest.importorskip("paper_2211_16665_amd.fwdem")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(fw.LIB_PATH):
+        pytest.skip("libfwdem.so not built")
+    return fw.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    hdr = open(os.path.join(ROOT, "include", "fwdem.h")).read()
+    names = set(re.findall(r"\b(fwd_[a-z_]+)\s*\(", hdr))
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(fw.SIGNATURES) == names
+
+
+def _plan(w, **kw):
+    return fw.Plan.from_workload(w, **kw)
+
+
+def test_rejects_bad_descriptions(lib):
+    w = tiny(seed=0)
+    with pytest.raises(fw.FwdError) as e:
+        fw.Plan(w.x[::-1], w.y, w.z, w.freqs, w.src_pos, w.src_mom, w.rec_pos, npml=3)
+    assert e.value.status == 1
+    with pytest.raises(fw.FwdError):
+        fw.Plan(w.x, w.y, w.z, [0.5, 0.5], w.src_pos, w.src_mom, w.rec_pos, npml=3)
+    with pytest.raises(fw.FwdError):
+        fw.Plan(w.x, w.y, w.z, w.freqs, w.src_pos, w.src_mom, w.rec_pos, npml=8)   # grid too small
+    with pytest.raises(fw.FwdError):
+        fw.Plan(w.x, w.y, w.z, w.freqs, w.src_pos, w.src_mom, w.rec_pos, rec_comp=(3,), npml=3)
+    p = _plan(w)
+    with pytest.raises(fw.FwdError) as e:
+        p.set_model(-w.rho)
+    assert e.value.status == 1
+    with pytest.raises(fw.FwdError) as e:        # no model yet
+        p.basis_build()
+    assert e.value.status == 8
+    # a source outside the grid
+    bad = w.replace(src_pos=np.array([[1e6, 0.0, 0.0]]))
+    pb = _plan(bad)
+    with pytest.raises(fw.FwdError):
+        pb.set_model(bad.rho)
+
+
+def test_strict_cfl(lib):
+    w = tiny(seed=1)
+    s = make_setup(w)
+    p = _plan(w.replace(dt=1.5 * s.dt / 0.95))
+    with pytest.raises(fw.FwdError) as e:
+        p.set_model(w.rho)
+    assert e.value.status == 5
+    p.set_option(fw.FWD_OPT_STRICT_CFL, 0)
+    p.set_model(w.rho)
+    assert np.isclose(p.info.dt, 1.5 * s.dt / 0.95)
+
+
+def test_errors_before_any_device_call(lib):
+    w = tiny(seed=2)
+    p = _plan(w)
+    # forward before set_model: STATE, raised before any HIP call
+    st = p.lib.fwd_forward(p.handle, None, 0, None, 0, None, None)
+    assert st == 8
+    p.set_model(w.rho)
+    st = p.lib.fwd_forward(p.handle, None, 0, None, 0, None, None)
+    assert st == 1
+    assert b"required" in p.lib.fwd_last_error()
+
+
+@pytest.mark.parametrize("make", [c1_wholespace, c2_marine1d, c3_blocks,
+                                  lambda: tiny(seed=3, stretch=1.3, contrast=2.0)])
+def test_setup_matches_oracle(lib, make):
+    w = make()
+    p = _plan(w)
+    p.set_model(w.rho)
+    s = make_setup(w)
+    i = p.info
+    assert np.isclose(i.dt, s.dt, rtol=1e-13)
+    assert i.nt == s.nt
+    assert np.isclose(i.vmax, s.vmax, rtol=1e-13)
+    assert np.isclose(i.tau, s.tau, rtol=1e-13) and np.isclose(i.t0, s.t0, rtol=1e-13)
+    wav = p.table(fw.FWD_TAB_WAVELET, s.nt)
+    assert np.allclose(wav, s.wavelet, rtol=0, atol=1e-14)
+    nf = len(s.freqs)
+    norm = p.table(fw.FWD_TAB_NORM, 2 * nf).view(np.complex128)
+    assert np.allclose(norm, s.norm, rtol=1e-10)
+    om = p.table(fw.FWD_TAB_OMEGA, 2 * nf).view(np.complex128)
+    assert np.allclose(om, s.Omega, rtol=1e-13)
+    for ax, name, n in ((fw.FWD_TAB_CPML_X, "x", s.nx), (fw.FWD_TAB_CPML_Y, "y", s.ny),
+                        (fw.FWD_TAB_CPML_Z, "z", s.nz)):
+        t = p.table(ax, 6 * (n + 1)).reshape(6, n + 1)
+        (kn, bn, an), (kh, bh, ah) = s.cpml[name]
+        assert np.allclose(t[0], kn, rtol=1e-13) and np.allclose(t[3, :n], kh, rtol=1e-13)
+        assert np.allclose(t[1], bn, rtol=1e-12, atol=1e-300)
+        assert np.allclose(t[4, :n], bh, rtol=1e-12, atol=1e-300)
+        assert np.allclose(t[2], an, rtol=1e-12, atol=1e-300)
+        assert np.allclose(t[5, :n], ah, rtol=1e-12, atol=1e-300)
+    if s.nx * s.ny * s.nz < 2e6:
+        es = p.table(fw.FWD_TAB_EDGE_SIGMA, 3 * (s.nx + 1) * (s.ny + 1) * (s.nz + 1))
+        es = es.reshape(3, s.nz + 1, s.ny + 1, s.nx + 1)
+        sx, sy, sz = s.sig_e
+        assert np.allclose(es[0][:, :, :s.nx], sx, rtol=1e-13)
+        assert np.allclose(es[1][:, :s.ny, :], sy, rtol=1e-13)
+        assert np.allclose(es[2][:s.nz, :, :], sz, rtol=1e-13)
+
+
+@pytest.mark.parametrize("freqs,dt,nt,grel", [
+    ([0.25, 0.75, 1.25], 1.73e-3, 4660, 1e-12),
+    ([0.25], 1.734e-2, 2000, 1e-12),
+    ([0.1, 0.25, 0.5, 0.75, 1.25], 1.76e-4, 20000, 1e-12),
+])
+def test_cgnr_basis_matches_definition(lib, freqs, dt, nt, grel):
+    """The library's CGNR (Section 3.3) reaches the basis functions of the
+    definition B+ = (B^T B + gamma I)^-1 B^T computed by the oracle."""
+    w = tiny(seed=0, nfreq=len(freqs)).replace(freqs=np.array(freqs), dt=dt, nt=nt)
+    p = _plan(w)
+    p.set_option(fw.FWD_OPT_STRICT_CFL, 0)
+    p.set_model(w.rho)
+    fit, it = p.basis_build(gamma_rel=grel)
+    b = p.table(fw.FWD_TAB_BASIS, 2 * len(freqs) * nt).reshape(2 * len(freqs), nt)
+    s = make_setup(w, dt=dt, nt=nt)
+    B = basis_matrix(s.a, dt, nt)
+    bo = basis_pinv(B, gamma_from_rel(B, grel))
+    fit_o = np.abs(B @ bo.T - np.eye(B.shape[0])).max()
+    # both satisfy the damped normal equations; the fit of the iteration is
+    # as good as the definition's (to the CG tolerance)
+    assert fit < max(10 * fit_o, 1e-7)
+    rel = np.abs(b - bo).max() / np.abs(bo).max()
+    assert rel < 1e-3, rel
+
+
+def test_paper_basis_demo_cg_iterations(lib):
+    """Paper's demo (golden fixture): gamma = 1e-3, Nt = 1000, f0 = 1 Hz,
+    three frequencies -- the conjugate gradients reach 1e-8 within 15
+    iterations, for either printed dt."""
+    g = json.load(open(os.path.join(ROOT, "tests", "golden", "basis_demo.json")))
+    pr = g["printed"]
+    for dt in (pr["dt_text"], pr["dt_caption"]):
+        w = tiny(seed=0, nfreq=3).replace(freqs=np.array(g["freqs_used"]), dt=dt, nt=pr["nt"],
+                                          f0=pr["f0"])
+        p = _plan(w)
+        p.set_option(fw.FWD_OPT_STRICT_CFL, 0)
+        p.set_model(w.rho)
+        fit, it = p.basis_build(gamma_abs=pr["gamma"], max_iter=pr["cg_iterations"],
+                                tol=pr["cg_error"])
+        assert it <= pr["cg_iterations"]
+        s = make_setup(w, dt=dt, nt=pr["nt"])
+        B = basis_matrix(s.a, dt, pr["nt"])
+        bo = basis_pinv(B, pr["gamma"])
+        b = p.table(fw.FWD_TAB_BASIS, 6 * pr["nt"]).reshape(6, pr["nt"])
+        assert np.abs(b - bo).max() < 1e-6 * np.abs(bo).max()
