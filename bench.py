@@ -32,11 +32,13 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 
 
-def algorithmic_bytes_e_forward(nx, ny, nz, npml, nf, tsize=4, accsize=16):
+def algorithmic_bytes_e_forward(nx, ny, nz, npml, nf, tsize=4, accsize=16, kb=8):
     """Algorithmic HBM bytes of one launch of the forward E update fused with
-    the volume transform: per updated edge E read + write and dt/eps read
-    (3 tsize), one H value per updated edge (tsize), the accumulator
-    read-modify-write of nf complex values (2 nf accsize), and a CPML memory
+    the volume transform, averaged over the kb-step cycle of the transform
+    block: per updated edge E read + write and dt/eps read (3 tsize), one H
+    value (tsize), the accumulator read-modify-write of nf complex values
+    once per cycle (2 nf accsize / kb), the history of the cycle (kb-2
+    samples written once and read once: 2 (kb-2) tsize / kb); a CPML memory
     variable read + write (2 tsize) per derivative taken inside a layer."""
     n_ex = nx * (ny - 1) * (nz - 1)
     n_ey = (nx - 1) * ny * (nz - 1)
@@ -50,10 +52,12 @@ def algorithmic_bytes_e_forward(nx, ny, nz, npml, nf, tsize=4, accsize=16):
     # derivatives along y and z for E_x, x and z for E_y, x and y for E_z
     psi = (nx * py * (nz - 1) + nx * (ny - 1) * pz + px * ny * (nz - 1) + (nx - 1) * ny * pz
            + px * (ny - 1) * nz + (nx - 1) * py * nz)
-    return edges * (4 * tsize + 2 * nf * accsize) + psi * 2 * tsize, edges
+    hist = 2 * max(kb - 2, 0) * tsize / kb
+    per_edge = 4 * tsize + 2 * nf * accsize / kb + hist
+    return int(edges * per_edge + psi * 2 * tsize), edges
 
 
-def cpu_baseline(w, steps=100):
+def cpu_baseline(w, steps=400):
     """Oracle (NumPy FP64, single process) stepping the full grid of the
     workload with the volume transform for a bounded window of steps."""
     import oracle
@@ -73,6 +77,31 @@ def cpu_baseline(w, steps=100):
                       f"one process ({dt:.1f} s); host {os.cpu_count()} logical CPUs"}
 
 
+def profile_mode(args, w_true):
+    """A short run for hardware-counter collection: one elementwise kernel of
+    a known size (256 MiB read + 256 MiB written, the calibration of the byte
+    counters), then a forward and an adjoint run of
+    ``profile_steps`` steps on the full grid of the workload."""
+    import torch
+    from paper_2211_16665_amd import fwdem as fw
+    n = 256 * 1024 * 1024 // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    torch.mul(a, 2.0, out=b)          # one elementwise kernel: 256 MiB read, 256 MiB written
+    torch.cuda.synchronize()
+    w = w_true.replace(nt=args.profile_steps)
+    plan = fw.Plan.from_workload(w, field_dtype=args.field_dtype, acc_mode=args.acc)
+    plan.set_option(fw.FWD_OPT_GRAPH_STEPS, 0)
+    plan.set_model(w.rho)
+    plan.basis_build(gamma_rel=1e-12)
+    E, vol = plan.forward(want_volume=True)
+    plan.adjoint(vol, -E)
+    torch.cuda.synchronize()
+    print(json.dumps({"profile_steps": args.profile_steps, "copy_bytes": 4 * n,
+                      "workload": w.name}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -82,6 +111,10 @@ def main():
     ap.add_argument("--field-dtype", default="f32")
     ap.add_argument("--acc", default="f64")
     ap.add_argument("--sample-every", type=int, default=2048)
+    ap.add_argument("--profile-steps", type=int, default=0,
+                    help="counter-collection mode: a 256 MiB device copy (calibration of the "
+                         "byte counters) then this many forward and adjoint steps of the "
+                         "workload; prints a short JSON line, no metric")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU: the path has no multi-GPU mode "
@@ -95,6 +128,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
     torch.cuda.set_device(0)
     w_true = c2_marine1d()
+    if args.profile_steps > 0:
+        profile_mode(args, w_true)
+        return
     # background model of the step: the same column without the reservoir
     rho0 = w_true.rho.copy()
     rho0[rho0 == 100.0] = 1.0
@@ -139,8 +175,9 @@ def main():
         return (float(np.mean(v)) if v else float("nan")), n
     tsize = 4 if args.field_dtype == "f32" else 8
     accsize = 8 if args.acc == "f32" else 16
+    kb = int(plan.get_option(fw.FWD_OPT_DFT_BLOCK))
     bytes_e, edges = algorithmic_bytes_e_forward(nx, ny, nz, w_true.npml, len(w_true.freqs),
-                                                 tsize, accsize)
+                                                 tsize, accsize, kb)
     e_ms, n_samp = avg("fwd", 2)
     achieved = bytes_e / (e_ms * 1e-3) / 1e9
     kern = {name: {"fwd_ms": avg("fwd", k)[0], "adj_ms": avg("adj", k)[0]}
@@ -167,7 +204,7 @@ def main():
                    "basis_fit": info.basis_fit},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_update_e (forward, volume transform fused)",
+                     "kernel": f"k_update_e (forward, volume transform fused, block {kb})",
                      "bytes_per_launch": bytes_e, "avg_launch_ms": e_ms, "samples": n_samp},
         "kernels_ms": kern,
     }

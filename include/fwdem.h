@@ -161,8 +161,14 @@ fwd_status fwd_run_steps(fwd_plan *plan, void *ws_dev, void *vol_dev,
 fwd_status fwd_run_receivers(fwd_plan *plan, void *ws_dev, double *E_rec_dev,
                              void *stream);
 
+/* Add the samples of an incomplete transform block (nsteps not a multiple of
+ * FWD_OPT_DFT_BLOCK) to the volume transform, so that vol_dev holds the sum
+ * over every step run so far.  Stepping may continue afterwards: samples
+ * already added are not added again.  fwd_forward does this itself. */
+fwd_status fwd_run_flush(fwd_plan *plan, void *ws_dev, void *vol_dev, void *stream);
+
 /* Snapshot of the forward state (fields, CPML memory, receiver sums, step
- * index; the volume transform when vol_dev is given): fwd_checkpoint_size
+ * index, transform-block history; the volume transform when vol_dev is given): fwd_checkpoint_size
  * bytes of caller memory (device) per snapshot. */
 fwd_status fwd_checkpoint_size(const fwd_plan *plan, int with_volume, size_t *bytes);
 fwd_status fwd_checkpoint_save(fwd_plan *plan, const void *ws_dev, const void *vol_dev,
@@ -217,9 +223,14 @@ enum {
   FWD_OPT_XCD_REMAP = 3,     /* 1: group neighbouring tiles on one XCD (default) */
   FWD_OPT_SAMPLE_EVERY = 4,  /* > 0: time the kernels of one step in every this many with
                                 HIP events (those chunks launch eagerly); see fwd_kernel_stats */
-  FWD_OPT_STRICT_CFL = 5     /* 1 (default): fwd_set_model rejects a fixed dt above the CFL
+  FWD_OPT_STRICT_CFL = 5,    /* 1 (default): fwd_set_model rejects a fixed dt above the CFL
                                 bound with FWD_ERR_CFL; 0 lets it run (and typically end in
                                 FWD_ERR_NONFINITE) */
+  FWD_OPT_DFT_BLOCK = 6      /* 1, 2, 4 or 8 (default): samples per read-modify-write of the
+                                volume transform (and of the gradient product).  The E update
+                                holds the last two samples; the others wait in a history buffer
+                                of the workspace.  Changes only the order of the sums.  Set it
+                                before fwd_workspace_size. */
 };
 fwd_status fwd_set_option(fwd_plan *plan, int key, double value);
 fwd_status fwd_get_option(const fwd_plan *plan, int key, double *value);

@@ -165,6 +165,15 @@ fwd_status fwd_run_receivers(fwd_plan *h, void *ws, double *E_rec, void *stream)
   });
 }
 
+fwd_status fwd_run_flush(fwd_plan *h, void *ws, void *vol, void *stream) {
+  return guard([&] {
+    Plan &p = P(h);
+    if (!p.have_model) fail(FWD_ERR_STATE, "no model set");
+    if (!ws) fail(FWD_ERR_INVALID_ARG, "workspace is required");
+    if (vol) dev_run_flush(p, ws, vol, stream);
+  });
+}
+
 fwd_status fwd_checkpoint_size(const fwd_plan *h, int with_volume, size_t *bytes) {
   return guard([&] {
     const Plan &p = P(h);
@@ -248,6 +257,10 @@ fwd_status fwd_set_option(fwd_plan *h, int key, double value) {
       case FWD_OPT_STRICT_CFL:
         p.strict_cfl = v ? 1 : 0;
         break;
+      case FWD_OPT_DFT_BLOCK:
+        if (v != 1 && v != 2 && v != 4 && v != 8) fail(FWD_ERR_INVALID_ARG, "block in {1,2,4,8}");
+        p.kb = v;
+        break;
       default:
         fail(FWD_ERR_INVALID_ARG, "unknown option");
     }
@@ -265,6 +278,7 @@ fwd_status fwd_get_option(const fwd_plan *h, int key, double *value) {
       case FWD_OPT_XCD_REMAP: *value = p.xcd; break;
       case FWD_OPT_SAMPLE_EVERY: *value = dev_get_sampling(p); break;
       case FWD_OPT_STRICT_CFL: *value = p.strict_cfl; break;
+      case FWD_OPT_DFT_BLOCK: *value = p.kb; break;
       default: fail(FWD_ERR_INVALID_ARG, "unknown option");
     }
   });

@@ -68,6 +68,9 @@ struct StepArgs {
   void *vol;          // [ns][nf][3][F] accumulators (forward) or forward transform (adjoint)
   const double2 *Q;   // [nt][nf] gradient weights (adjoint)
   double *gedge;      // [3][F] gradient accumulators (adjoint)
+  T *hist;            // [ns][kb-2][3][F] samples of the current transform block
+  int64_t hist_src;   // history elements per source
+  const int *flushed; // last sample already in the volume transform / gradient
 };
 
 __device__ __forceinline__ void tile_of(int nblocks, int xcd, int nbx, int nby, int &bx, int &by,
@@ -166,19 +169,19 @@ __global__ void __launch_bounds__(256) k_update_h(StepArgs<T> A) {
 enum { ACC_NONE = 0, ACC_F64 = 1, ACC_KAHAN = 2, ACC_F32 = 3 };
 
 template <int ACC>
-__device__ __forceinline__ void acc_add(void *base, int64_t idx, double e, double2 z) {
+__device__ __forceinline__ void acc_add(void *base, int64_t idx, double2 x) {
   if constexpr (ACC == ACC_F64) {
     double2 *p = reinterpret_cast<double2 *>(base) + idx;
     double2 v = *p;
-    v.x = fma(e, z.x, v.x);
-    v.y = fma(e, z.y, v.y);
+    v.x += x.x;
+    v.y += x.y;
     *p = v;
   } else if constexpr (ACC == ACC_KAHAN) {
     // compensated single precision: (hi, lo) per real component, the sum is
     // hi - lo (Kahan's running compensation)
     float4 *p = reinterpret_cast<float4 *>(base) + idx;
     float4 v = *p;
-    const float xr = (float)e * (float)z.x, xi = (float)e * (float)z.y;
+    const float xr = (float)x.x, xi = (float)x.y;
     float yr = xr - v.z, tr = v.x + yr;
     v.z = (tr - v.x) - yr;
     v.x = tr;
@@ -189,8 +192,8 @@ __device__ __forceinline__ void acc_add(void *base, int64_t idx, double e, doubl
   } else if constexpr (ACC == ACC_F32) {
     float2 *p = reinterpret_cast<float2 *>(base) + idx;
     float2 v = *p;
-    v.x = fmaf((float)e, (float)z.x, v.x);
-    v.y = fmaf((float)e, (float)z.y, v.y);
+    v.x += (float)x.x;
+    v.y += (float)x.y;
     *p = v;
   }
 }
@@ -208,26 +211,63 @@ __device__ __forceinline__ double2 acc_read(const void *base, int64_t idx) {
   }
 }
 
-// after the E update of component c at q: forward -> accumulate the volume
-// transform; adjoint -> g_c += u^{n+1} Re(sum_k Q_k^n V_k)  (the gradient
-// product of eq. gradsigmaij summed over time, see the host for Q)
-template <typename T, int ACC, bool ADJ>
-__device__ __forceinline__ void post_e(const StepArgs<T> &A, int s, int c, int64_t q, double e,
+// After the E update of component c at q (old value e0 = sample m-1, new
+// value e1 = sample m, m = n+1): the transform over a block of KB samples
+// is added in one read-modify-write when the block closes (m % KB == 0);
+// samples with m % KB in 1..KB-2 wait in the history buffer, the sample
+// with m % KB == KB-1 is the old value of the closing step.  KB = 1 adds
+// every sample as it comes.  Forward: volume transform acc_k += sum E z_k^m
+// (eq. dft).  Adjoint: g += sum_m u^m Re(sum_k Q_k^m V_k), the gradient
+// product of eq. gradsigmaij accumulated over time (Q on the host).
+// Samples at or before *flushed were already added by a flush.
+template <typename T, int ACC, bool ADJ, int KB>
+__device__ __forceinline__ void post_e(const StepArgs<T> &A, int s, int c, int64_t q, T e0, T e1,
                                        int n, double &g) {
   if constexpr (ACC != ACC_NONE) {
     const int nf = A.nf;
+    const int m = n + 1;
+    const int r = m & (KB - 1);
+    T *h = A.hist + (int64_t)s * A.hist_src + (int64_t)c * A.F + q;
+    if constexpr (KB > 1) {
+      if (r != 0) {
+        if (r <= KB - 2) h[(int64_t)(r - 1) * 3 * A.F] = e1;
+        return;
+      }
+    }
+    // the KB samples of the block: m-KB+1 .. m; zE / Q index = sample - 1
+    double val[KB];
+#pragma unroll
+    for (int t = 0; t < KB - 2; ++t) val[t] = (double)h[(int64_t)t * 3 * A.F];
+    if constexpr (KB >= 2) val[KB - 2] = (double)e0;
+    val[KB - 1] = (double)e1;
+    const int fl = A.flushed[0];
+    const int first = m - KB + 1;
+#pragma unroll
+    for (int t = 0; t < KB; ++t)
+      if (first + t <= fl) val[t] = 0.0;
     const int64_t base = ((int64_t)s * nf * 3 + c) * A.F + q;
     if constexpr (!ADJ) {
-      const double2 *z = A.zE + (int64_t)n * nf;
-      for (int kf = 0; kf < nf; ++kf) acc_add<ACC>(A.vol, base + (int64_t)kf * 3 * A.F, e, z[kf]);
+      for (int kf = 0; kf < nf; ++kf) {
+        double2 sum = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int t = 0; t < KB; ++t) {
+          const double2 z = A.zE[(int64_t)(first - 1 + t) * nf + kf];
+          sum.x = fma(val[t], z.x, sum.x);
+          sum.y = fma(val[t], z.y, sum.y);
+        }
+        acc_add<ACC>(A.vol, base + (int64_t)kf * 3 * A.F, sum);
+      }
     } else {
-      const double2 *Qn = A.Q + (int64_t)n * nf;
       double re = 0.0;
       for (int kf = 0; kf < nf; ++kf) {
         const double2 v = acc_read<ACC>(A.vol, base + (int64_t)kf * 3 * A.F);
-        re += Qn[kf].x * v.x - Qn[kf].y * v.y;
+#pragma unroll
+        for (int t = 0; t < KB; ++t) {
+          const double2 Qt = A.Q[(int64_t)(first - 1 + t) * nf + kf];
+          re = fma(val[t], Qt.x * v.x - Qt.y * v.y, re);
+        }
       }
-      g += e * re;
+      g += re;
     }
   }
 }
@@ -237,7 +277,7 @@ __device__ __forceinline__ void post_e(const StepArgs<T> &A, int s, int c, int64
 //   E_x += ce (dHz/dy - dHy/dz), E_y += ce (dHx/dz - dHz/dx),
 //   E_z += ce (dHy/dx - dHx/dy); backward differences over a dual width
 // ---------------------------------------------------------------------------
-template <typename T, int ACC, bool ADJ>
+template <typename T, int ACC, bool ADJ, int KB>
 __global__ void __launch_bounds__(256) k_update_e(StepArgs<T> A) {
   int bx, by, bz;
   if ((int)blockIdx.x >= A.nblocks) return;
@@ -276,56 +316,177 @@ __global__ void __launch_bounds__(256) k_update_e(StepArgs<T> A) {
       T d2 = (hy[q] - hy[q - plane]) * Z.ihd[k];  // dHy/dz at z_k
       if (py) { T &p = psY[2 * sY + iY]; p = Y.bn[j] * p + Y.an[j] * d1; d1 = d1 * Y.kn[j] + p; }
       if (pz) { T &p = psZ[2 * sZ + iZ]; p = Z.bn[k] * p + Z.an[k] * d2; d2 = d2 * Z.kn[k] + p; }
-      const T e = ex[q] + cex * (d1 - d2);
+      const T e0 = ex[q];
+      const T e = e0 + cex * (d1 - d2);
       ex[q] = e;
-      post_e<T, ACC, ADJ>(A, s, 0, q, (double)e, n, gx);
+      post_e<T, ACC, ADJ, KB>(A, s, 0, q, e0, e, n, gx);
     }
     if (ey_ok) {
       T d1 = (hx[q] - hx[q - plane]) * Z.ihd[k];  // dHx/dz
       T d2 = (hz[q] - hz[q - 1]) * X.ihd[i];      // dHz/dx
       if (pz) { T &p = psZ[3 * sZ + iZ]; p = Z.bn[k] * p + Z.an[k] * d1; d1 = d1 * Z.kn[k] + p; }
       if (px) { T &p = psX[2 * sX + iX]; p = X.bn[i] * p + X.an[i] * d2; d2 = d2 * X.kn[i] + p; }
-      const T e = ey[q] + cey * (d1 - d2);
+      const T e0 = ey[q];
+      const T e = e0 + cey * (d1 - d2);
       ey[q] = e;
-      post_e<T, ACC, ADJ>(A, s, 1, q, (double)e, n, gy);
+      post_e<T, ACC, ADJ, KB>(A, s, 1, q, e0, e, n, gy);
     }
     if (ez_ok) {
       T d1 = (hy[q] - hy[q - 1]) * X.ihd[i];      // dHy/dx
       T d2 = (hx[q] - hx[q - PX]) * Y.ihd[j];     // dHx/dy
       if (px) { T &p = psX[3 * sX + iX]; p = X.bn[i] * p + X.an[i] * d1; d1 = d1 * X.kn[i] + p; }
       if (py) { T &p = psY[3 * sY + iY]; p = Y.bn[j] * p + Y.an[j] * d2; d2 = d2 * Y.kn[j] + p; }
-      const T e = ez[q] + cez * (d1 - d2);
+      const T e0 = ez[q];
+      const T e = e0 + cez * (d1 - d2);
       ez[q] = e;
-      post_e<T, ACC, ADJ>(A, s, 2, q, (double)e, n, gz);
+      post_e<T, ACC, ADJ, KB>(A, s, 2, q, e0, e, n, gz);
     }
   }
   if constexpr (ADJ) {
-    if (ex_ok) A.gedge[q] += gx;
-    if (ey_ok) A.gedge[A.F + q] += gy;
-    if (ez_ok) A.gedge[2 * A.F + q] += gz;
+    if (((n + 1) & (KB - 1)) == 0) {
+      if (ex_ok) A.gedge[q] += gx;
+      if (ey_ok) A.gedge[A.F + q] += gy;
+      if (ez_ok) A.gedge[2 * A.F + q] += gz;
+    }
   }
+}
+
+// Flush: add the samples of the incomplete last block (m_last % KB != 0)
+// that are newer than *flushed; the caller then moves *flushed to m_last
+// with k_set_flushed.  Same thread mapping as the E update.
+template <typename T, int ACC, bool ADJ, int KB>
+__global__ void __launch_bounds__(256) k_flush(StepArgs<T> A) {
+  int bx, by, bz;
+  if ((int)blockIdx.x >= A.nblocks) return;
+  tile_of(A.nblocks, A.xcd, A.nbx, A.nby, bx, by, bz);
+  const int i = bx * blockDim.x + threadIdx.x;
+  const int j = by * blockDim.y + threadIdx.y;
+  const int k = bz;
+  if (i > A.nx || j > A.ny || k > A.nz) return;
+  const int m_last = A.step[0] + 1;
+  const int r_end = m_last & (KB - 1);
+  if (KB == 1 || r_end == 0) return;
+  const int fl = A.flushed[0];
+  const int64_t q = ((int64_t)k * A.NY + j) * A.PX + i;
+  const bool ok[3] = {i < A.nx && j >= 1 && j < A.ny && k >= 1 && k < A.nz,
+                      i >= 1 && i < A.nx && j < A.ny && k >= 1 && k < A.nz,
+                      i >= 1 && i < A.nx && j >= 1 && j < A.ny && k < A.nz};
+  const int nf = A.nf;
+  double g[3] = {0.0, 0.0, 0.0};
+  for (int s = 0; s < A.ns; ++s) {
+    const T *f = A.fields + (int64_t)s * 6 * A.F;
+    for (int c = 0; c < 3; ++c) {
+      if (!ok[c]) continue;
+      const T *h = A.hist + (int64_t)s * A.hist_src + (int64_t)c * A.F + q;
+      const int64_t base = ((int64_t)s * nf * 3 + c) * A.F + q;
+      for (int rr = 1; rr <= r_end; ++rr) {
+        const int mm = m_last - r_end + rr;
+        if (mm <= fl) continue;
+        const double v = rr <= KB - 2 ? (double)h[(int64_t)(rr - 1) * 3 * A.F]
+                                      : (double)f[(int64_t)c * A.F + q];
+        for (int kf = 0; kf < nf; ++kf) {
+          if constexpr (!ADJ) {
+            const double2 z = A.zE[(int64_t)(mm - 1) * nf + kf];
+            acc_add<ACC>(A.vol, base + (int64_t)kf * 3 * A.F, make_double2(v * z.x, v * z.y));
+          } else {
+            const double2 Vk = acc_read<ACC>(A.vol, base + (int64_t)kf * 3 * A.F);
+            const double2 Qt = A.Q[(int64_t)(mm - 1) * nf + kf];
+            g[c] += v * (Qt.x * Vk.x - Qt.y * Vk.y);
+          }
+        }
+      }
+    }
+  }
+  if constexpr (ADJ) {
+    for (int c = 0; c < 3; ++c)
+      if (ok[c]) A.gedge[(int64_t)c * A.F + q] += g[c];
+  }
+}
+
+__global__ void k_set_flushed(int *flushed, const int *step) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) flushed[0] = step[0] + 1;
 }
 
 // ---------------------------------------------------------------------------
 // injection of J'^{n+1/2}: E -= ce * sum_r coef[toff+r] F[r][n]
-// one thread per (source, component, edge) target: no atomics, fixed order
+// Forward: one thread per (source, component, edge) target; adjoint: one
+// thread per (component, edge) node looping over the sources.  No atomics.
+// The E update that follows reads the injected value as its "old" sample
+// E^n; when a transform block closes at this step (KB > 1) the exact
+// difference E^n - (E^n - ce J) is added here to the volume transform
+// (forward) or to the gradient product (adjoint) at the target edge.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ void k_inject(int ntg, const int *tg_s, const int *tg_c, const int64_t *tg_idx,
-                         const int *tg_toff, int nrow, const double *coef, const double *Ftab,
-                         int nt, T *fields, int64_t F, const T *ce0, const T *ce1, const T *ce2,
-                         const int *step) {
+struct InjArgs {
+  int ntg, nrow, nt, ns, nn, nf;
+  const int *tg_s, *tg_c, *tg_toff;
+  const int64_t *tg_idx;
+  const double *coef, *Ftab;
+  T *fields;
+  int64_t F;
+  const T *ce0, *ce1, *ce2;
+  const int *step, *flushed;
+  void *vol;
+  const double2 *zE, *Q;
+  double *gedge;
+};
+
+template <typename T, int ACC, bool ADJ, int KB>
+__global__ void k_inject(InjArgs<T> I) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= ntg) return;
-  const int n = step[0];
-  double v = 0.0;
-  const double *cf = coef + tg_toff[t];
-  for (int r = 0; r < nrow; ++r) v += cf[r] * Ftab[(int64_t)r * nt + n];
-  const int c = tg_c[t];
-  const int64_t idx = tg_idx[t];
-  const T *ce = c == 0 ? ce0 : (c == 1 ? ce1 : ce2);
-  T *E = fields + ((int64_t)tg_s[t] * 6 + c) * F;
-  E[idx] -= (T)((double)ce[idx] * v);
+  if (t >= I.ntg) return;
+  const int n = I.step[0];
+  const bool closing = ACC != ACC_NONE && KB > 1 && ((n + 1) & (KB - 1)) == 0 && n > I.flushed[0];
+  const int c = I.tg_c[t];
+  const int64_t idx = I.tg_idx[t];
+  const T *ce = c == 0 ? I.ce0 : (c == 1 ? I.ce1 : I.ce2);
+  const double cev = (double)ce[idx];
+  const int nf = I.nf;
+  if constexpr (!ADJ) {
+    const int s = I.tg_s[t];
+    double v = 0.0;
+    const double *cf = I.coef + I.tg_toff[t];
+    for (int r = 0; r < I.nrow; ++r) v += cf[r] * I.Ftab[(int64_t)r * I.nt + n];
+    T *E = I.fields + ((int64_t)s * 6 + c) * I.F;
+    const T old = E[idx];
+    const T now = old - (T)(cev * v);
+    E[idx] = now;
+    if constexpr (ACC != ACC_NONE) {
+      if (closing) {
+        const double dlt = (double)old - (double)now;
+        const int64_t base = (((int64_t)s * nf) * 3 + c) * I.F + idx;
+        for (int kf = 0; kf < nf; ++kf) {
+          const double2 z = I.zE[(int64_t)(n - 1) * nf + kf];
+          acc_add<ACC>(I.vol, base + (int64_t)kf * 3 * I.F, make_double2(dlt * z.x, dlt * z.y));
+        }
+      }
+    }
+  } else {
+    double g = 0.0;
+    for (int s = 0; s < I.ns; ++s) {
+      double v = 0.0;
+      const double *cf = I.coef + ((int64_t)s * I.nn + t) * I.nrow;
+      for (int r = 0; r < I.nrow; ++r) v += cf[r] * I.Ftab[(int64_t)r * I.nt + n];
+      T *E = I.fields + ((int64_t)s * 6 + c) * I.F;
+      const T old = E[idx];
+      const T now = old - (T)(cev * v);
+      E[idx] = now;
+      if constexpr (ACC != ACC_NONE) {
+        if (closing) {
+          const double dlt = (double)old - (double)now;
+          const int64_t base = (((int64_t)s * nf) * 3 + c) * I.F + idx;
+          double re = 0.0;
+          for (int kf = 0; kf < nf; ++kf) {
+            const double2 Vk = acc_read<ACC>(I.vol, base + (int64_t)kf * 3 * I.F);
+            const double2 Qt = I.Q[(int64_t)(n - 1) * nf + kf];
+            re += Qt.x * Vk.x - Qt.y * Vk.y;
+          }
+          g += dlt * re;
+        }
+      }
+    }
+    if (closing) I.gedge[(int64_t)c * I.F + idx] += g;
+  }
 }
 
 // transform of E at the receiver lattice nodes: one thread per (source, node)
@@ -437,9 +598,7 @@ struct Dev {
   int *ri_ptr = nullptr, *ri_node = nullptr;
   double *ri_w = nullptr;
   double2 *fwd_scale = nullptr, *adj_scale_v = nullptr, *vol_scale = nullptr;
-  // adjoint targets (s, node) and their coefficients (rebuilt per call)
-  int *at_s = nullptr, *at_c = nullptr, *at_toff = nullptr;
-  int64_t *at_idx = nullptr;
+  // adjoint injection coefficients (rebuilt per call)
   double *at_coef = nullptr;
   double *cellfac = nullptr;
   double2 *eadj = nullptr;      // adjoint receiver transform when the caller passes none
@@ -571,22 +730,9 @@ static void ensure_tables(Plan &p, hipStream_t stream) {
   d.fwd_scale = upload(d, sc);
   d.vol_scale = d.fwd_scale;
   d.adj_scale_v = static_cast<double2 *>(dalloc(d, nf * sizeof(double2)));
-  // adjoint targets: every (source, receiver node)
+  // adjoint injection coefficients [ns][node][2nf] (filled per adjoint call)
   {
     const int nn = (int)p.rn_c.size();
-    std::vector<int> s, c, toff;
-    std::vector<int64_t> idx;
-    for (int si = 0; si < p.ns; ++si)
-      for (int node = 0; node < nn; ++node) {
-        s.push_back(si);
-        c.push_back(p.rn_c[node]);
-        idx.push_back(p.rn_idx[node]);
-        toff.push_back((si * nn + node) * 2 * nf);
-      }
-    d.at_s = upload(d, s);
-    d.at_c = upload(d, c);
-    d.at_idx = upload(d, idx);
-    d.at_toff = upload(d, toff);
     d.at_coef = static_cast<double *>(dalloc(d, (size_t)p.ns * nn * 2 * nf * sizeof(double)));
     d.eadj = static_cast<double2 *>(dalloc(d, (size_t)p.ns * p.nr * p.ncomp * nf * sizeof(double2)));
   }
@@ -626,7 +772,9 @@ static void ensure_tables(Plan &p, hipStream_t stream) {
 struct WS {
   void *fields, *psi;
   double2 *racc;
-  int *step;
+  int *step;      // current step index
+  int *flushed;   // last sample already added by a flush
+  void *hist;
   double *gedge;
 };
 
@@ -642,7 +790,10 @@ static WS carve(const Plan &p, void *ws) {
   w.racc = reinterpret_cast<double2 *>(b);
   b += a256((size_t)p.ns * p.rn_c.size() * p.nf() * 16);
   w.step = reinterpret_cast<int *>(b);
+  w.flushed = w.step + 1;
   b += 256;
+  w.hist = b;
+  b += a256((size_t)p.ns * p.hist_elems_per_source() * p.tsize());
   w.gedge = reinterpret_cast<double *>(b);
   return w;
 }
@@ -695,27 +846,73 @@ static StepArgs<T> make_args(Plan &p, Dev &d, const WS &w, void *vol, bool adj) 
   A.vol = vol;
   A.Q = d.Q;
   A.gedge = adj ? w.gedge : nullptr;
+  A.hist = static_cast<T *>(w.hist);
+  A.hist_src = p.hist_elems_per_source();
+  A.flushed = w.flushed;
   return A;
 }
 
-template <typename T>
-static void launch_e(const StepArgs<T> &A, int acc, bool adj, dim3 grid, dim3 block, hipStream_t st) {
+template <typename T, int KB>
+static void launch_e_kb(const StepArgs<T> &A, int acc, bool adj, bool flush, dim3 grid, dim3 block,
+                        hipStream_t st) {
+#define FWD_LAUNCH(ACCV, ADJV)                                                                 \
+  do {                                                                                         \
+    if (flush) hipLaunchKernelGGL((k_flush<T, ACCV, ADJV, KB>), grid, block, 0, st, A);        \
+    else hipLaunchKernelGGL((k_update_e<T, ACCV, ADJV, KB>), grid, block, 0, st, A);           \
+  } while (0)
   if (!A.vol) {
-    hipLaunchKernelGGL((k_update_e<T, ACC_NONE, false>), grid, block, 0, st, A);
+    if (!flush) hipLaunchKernelGGL((k_update_e<T, ACC_NONE, false, 1>), grid, block, 0, st, A);
     return;
   }
   switch (acc) {
     case FWD_ACC_F64:
-      if (adj) hipLaunchKernelGGL((k_update_e<T, ACC_F64, true>), grid, block, 0, st, A);
-      else hipLaunchKernelGGL((k_update_e<T, ACC_F64, false>), grid, block, 0, st, A);
+      if (adj) FWD_LAUNCH(ACC_F64, true); else FWD_LAUNCH(ACC_F64, false);
       break;
     case FWD_ACC_KAHAN:
-      if (adj) hipLaunchKernelGGL((k_update_e<T, ACC_KAHAN, true>), grid, block, 0, st, A);
-      else hipLaunchKernelGGL((k_update_e<T, ACC_KAHAN, false>), grid, block, 0, st, A);
+      if (adj) FWD_LAUNCH(ACC_KAHAN, true); else FWD_LAUNCH(ACC_KAHAN, false);
       break;
     default:
-      if (adj) hipLaunchKernelGGL((k_update_e<T, ACC_F32, true>), grid, block, 0, st, A);
-      else hipLaunchKernelGGL((k_update_e<T, ACC_F32, false>), grid, block, 0, st, A);
+      if (adj) FWD_LAUNCH(ACC_F32, true); else FWD_LAUNCH(ACC_F32, false);
+  }
+#undef FWD_LAUNCH
+}
+
+// E update (flush = false) or the flush of an incomplete transform block
+template <typename T>
+static void launch_e(const StepArgs<T> &A, int kb, int acc, bool adj, bool flush, dim3 grid,
+                     dim3 block, hipStream_t st) {
+  switch (kb) {
+    case 1: launch_e_kb<T, 1>(A, acc, adj, flush, grid, block, st); break;
+    case 2: launch_e_kb<T, 2>(A, acc, adj, flush, grid, block, st); break;
+    case 4: launch_e_kb<T, 4>(A, acc, adj, flush, grid, block, st); break;
+    default: launch_e_kb<T, 8>(A, acc, adj, flush, grid, block, st);
+  }
+}
+
+template <typename T, int KB>
+static void launch_inject_kb(const InjArgs<T> &I, int acc, bool adj, hipStream_t st) {
+  const dim3 grid((I.ntg + 63) / 64), block(64);
+#define FWD_INJ(ACCV)                                                                         \
+  do {                                                                                        \
+    if (adj) hipLaunchKernelGGL((k_inject<T, ACCV, true, KB>), grid, block, 0, st, I);        \
+    else hipLaunchKernelGGL((k_inject<T, ACCV, false, KB>), grid, block, 0, st, I);           \
+  } while (0)
+  switch (acc) {
+    case FWD_ACC_F64: FWD_INJ(ACC_F64); break;
+    case FWD_ACC_KAHAN: FWD_INJ(ACC_KAHAN); break;
+    case FWD_ACC_F32: FWD_INJ(ACC_F32); break;
+    default: hipLaunchKernelGGL((k_inject<T, ACC_NONE, false, 1>), grid, block, 0, st, I);
+  }
+#undef FWD_INJ
+}
+
+template <typename T>
+static void launch_inject(const InjArgs<T> &I, int kb, int acc, bool adj, hipStream_t st) {
+  switch (kb) {
+    case 1: launch_inject_kb<T, 1>(I, acc, adj, st); break;
+    case 2: launch_inject_kb<T, 2>(I, acc, adj, st); break;
+    case 4: launch_inject_kb<T, 4>(I, acc, adj, st); break;
+    default: launch_inject_kb<T, 8>(I, acc, adj, st);
   }
 }
 
@@ -731,21 +928,44 @@ static void enqueue_step(Plan &p, Dev &d, const WS &w, void *vol, bool adj, hipS
   if (ev) (void)hipEventRecord(ev[0], st);
   hipLaunchKernelGGL((k_update_h<T>), grid, block, 0, st, A);
   if (ev) (void)hipEventRecord(ev[1], st);
-  if (!adj) {
-    const int ntg = (int)p.src_tg.size();
-    hipLaunchKernelGGL((k_inject<T>), dim3((ntg + 63) / 64), dim3(64), 0, st, ntg, d.src_s, d.src_c,
-                       d.src_idx, d.src_toff, 1, d.src_coef, d.wavelet, p.nt, fields, F,
-                       static_cast<const T *>(d.ce[0]), static_cast<const T *>(d.ce[1]),
-                       static_cast<const T *>(d.ce[2]), (const int *)w.step);
-  } else {
-    const int ntg = p.ns * nn;
-    hipLaunchKernelGGL((k_inject<T>), dim3((ntg + 63) / 64), dim3(64), 0, st, ntg, d.at_s, d.at_c,
-                       d.at_idx, d.at_toff, 2 * p.nf(), d.at_coef, d.basis, p.nt, fields, F,
-                       static_cast<const T *>(d.ce[0]), static_cast<const T *>(d.ce[1]),
-                       static_cast<const T *>(d.ce[2]), (const int *)w.step);
+  {
+    InjArgs<T> I{};
+    I.nt = p.nt;
+    I.ns = p.ns;
+    I.nn = nn;
+    I.nf = p.nf();
+    I.fields = fields;
+    I.F = F;
+    I.ce0 = static_cast<const T *>(d.ce[0]);
+    I.ce1 = static_cast<const T *>(d.ce[1]);
+    I.ce2 = static_cast<const T *>(d.ce[2]);
+    I.step = w.step;
+    I.flushed = w.flushed;
+    I.vol = vol;
+    I.zE = d.zE;
+    I.Q = d.Q;
+    I.gedge = adj ? w.gedge : nullptr;
+    if (!adj) {
+      I.ntg = (int)p.src_tg.size();
+      I.nrow = 1;
+      I.tg_s = d.src_s;
+      I.tg_c = d.src_c;
+      I.tg_toff = d.src_toff;
+      I.tg_idx = d.src_idx;
+      I.coef = d.src_coef;
+      I.Ftab = d.wavelet;
+    } else {
+      I.ntg = nn;
+      I.nrow = 2 * p.nf();
+      I.tg_c = d.rn_c;
+      I.tg_idx = d.rn_idx;
+      I.coef = d.at_coef;
+      I.Ftab = d.basis;
+    }
+    launch_inject<T>(I, p.kb, vol ? p.acc : -1, adj, st);
   }
   if (ev) (void)hipEventRecord(ev[2], st);
-  launch_e<T>(A, p.acc, adj, grid, block, st);
+  launch_e<T>(A, p.kb, p.acc, adj, false, grid, block, st);
   if (ev) (void)hipEventRecord(ev[3], st);
   const int nrt = p.ns * nn;
   hipLaunchKernelGGL((k_rec_dft<T>), dim3((nrt + 63) / 64), dim3(64), 0, st, p.ns, nn, d.rn_c,
@@ -754,15 +974,31 @@ static void enqueue_step(Plan &p, Dev &d, const WS &w, void *vol, bool adj, hipS
 }
 
 template <typename T>
+static void flush_t(Plan &p, Dev &d, const WS &w, void *vol, bool adj, hipStream_t st) {
+  if (p.kb == 1 || !vol) return;
+  StepArgs<T> A = make_args<T>(p, d, w, vol, adj);
+  launch_e<T>(A, p.kb, p.acc, adj, true, dim3(A.nblocks), dim3(p.bx, p.by), st);
+  hipLaunchKernelGGL(k_set_flushed, dim3(1), dim3(64), 0, st, w.flushed, (const int *)w.step);
+  HIP_CHECK(hipGetLastError());
+}
+
+static void flush_any(Plan &p, Dev &d, const WS &w, void *vol, bool adj, hipStream_t st) {
+  if (p.dtype == FWD_F64)
+    flush_t<double>(p, d, w, vol, adj, st);
+  else
+    flush_t<float>(p, d, w, vol, adj, st);
+}
+
+template <typename T>
 static void run_steps_t(Plan &p, Dev &d, const WS &w, void *vol, bool adj, int nsteps,
                         hipStream_t st) {
   const int K = p.graph_steps;
   const int sample = d.sample_every;
-  // eager launches of m steps; the first one is bracketed by events if asked
-  auto eager = [&](int m, bool time_first) {
+  // eager launches of m steps, each bracketed by events if asked
+  auto eager = [&](int m, bool timed) {
     for (int t = 0; t < m; ++t) {
       hipEvent_t *ev = nullptr;
-      if (time_first && t == 0) {
+      if (timed) {
         const size_t need = (size_t)(d.kstat_n + 1) * 5;
         while (d.ev.size() < need) {
           hipEvent_t e;
@@ -782,8 +1018,8 @@ static void run_steps_t(Plan &p, Dev &d, const WS &w, void *vol, bool adj, int n
   }
   // graph of K steps, captured on a private stream and replayed on st
   char key[256];
-  snprintf(key, sizeof key, "%p/%p/%d/%d/%d/%d/%d/%llu/%llu", w.fields, vol, (int)adj, K, p.bx,
-           p.by, p.xcd, (unsigned long long)p.model_version,
+  snprintf(key, sizeof key, "%p/%p/%d/%d/%d/%d/%d/%d/%llu/%llu", w.fields, vol, (int)adj, K, p.bx,
+           p.by, p.xcd, p.kb, (unsigned long long)p.model_version,
            (unsigned long long)p.basis_version);
   if (!d.exec || d.exec_key != key) {
     if (d.exec) {
@@ -799,7 +1035,8 @@ static void run_steps_t(Plan &p, Dev &d, const WS &w, void *vol, bool adj, int n
     d.exec_key = key;
   }
   // with sampling on, one chunk in every max(1, sample/K) runs eagerly and
-  // times its first step; all others replay the graph
+  // times each of its steps (all phases of the transform block); all others
+  // replay the graph
   const int every = sample > 0 ? std::max(1, sample / K) : 0;
   int done = 0, chunk = 0;
   while (nsteps - done >= K) {
@@ -886,6 +1123,12 @@ void dev_run_receivers(Plan &p, void *ws, double *E_rec, void *stream) {
   HIP_CHECK(hipGetLastError());
 }
 
+void dev_run_flush(Plan &p, void *ws, void *vol, void *stream) {
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  ensure_tables(p, st);
+  flush_any(p, D(p), carve(p, ws), vol, false, st);
+}
+
 void dev_forward(Plan &p, void *ws, size_t ws_bytes, void *vol, size_t vol_bytes, double *E_rec,
                  void *stream) {
   hipStream_t st = static_cast<hipStream_t>(stream);
@@ -897,6 +1140,7 @@ void dev_forward(Plan &p, void *ws, size_t ws_bytes, void *vol, size_t vol_bytes
   HIP_CHECK(hipEventCreate(&e1));
   HIP_CHECK(hipEventRecord(e0, st));
   run_steps_any(p, d, carve(p, ws), vol, false, p.nt, st);
+  flush_any(p, d, carve(p, ws), vol, false, st);
   HIP_CHECK(hipEventRecord(e1, st));
   dev_run_receivers(p, ws, E_rec, stream);
   HIP_CHECK(hipEventSynchronize(e1));
@@ -976,6 +1220,7 @@ void dev_adjoint(Plan &p, void *ws, size_t ws_bytes, const void *vol, const doub
   HIP_CHECK(hipEventCreate(&e1));
   HIP_CHECK(hipEventRecord(e0, st));
   run_steps_any(p, d, w, const_cast<void *>(vol), true, p.nt, st);
+  flush_any(p, d, w, const_cast<void *>(vol), true, st);
   HIP_CHECK(hipEventRecord(e1, st));
   // gradient on cells
   const double gscale = 1.0 / (p.src_scale * adj_scale);

@@ -101,6 +101,7 @@ struct Plan {
 
   // ---- options ----
   int graph_steps = 32, bx = 64, by = 4, xcd = 1, strict_cfl = 1;
+  int kb = 8;                            // samples per volume-transform block (1, 2, 4, 8)
 
   // ---- device side (managed in device.hip) ----
   void *dev = nullptr;
@@ -115,6 +116,7 @@ struct Plan {
   size_t tsize() const { return dtype == FWD_F64 ? 8 : 4; }
   size_t acc_bytes() const { return acc == FWD_ACC_F32 ? 8 : 16; }
   int64_t psi_elems_per_source() const;
+  int64_t hist_elems_per_source() const { return kb > 2 ? (int64_t)(kb - 2) * 3 * field_elems() : 0; }
   size_t state_bytes() const;       // fields + psi + receiver sums + step index
   size_t workspace_bytes(int mode) const;
   size_t volume_bytes() const;
@@ -137,6 +139,7 @@ void dev_run_begin(Plan &p, void *ws, size_t ws_bytes, void *vol, size_t vol_byt
                    void *stream);
 void dev_run_steps(Plan &p, void *ws, void *vol, int nsteps, void *stream);
 void dev_run_receivers(Plan &p, void *ws, double *E_rec, void *stream);
+void dev_run_flush(Plan &p, void *ws, void *vol, void *stream);
 void dev_checkpoint(Plan &p, const void *ws, const void *vol, void *snap, int save,
                     void *stream);
 void dev_volume_export(Plan &p, const void *vol, double *out, void *stream);

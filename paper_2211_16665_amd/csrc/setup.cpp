@@ -31,7 +31,8 @@ size_t Plan::state_bytes() const {
   size_t b = align256((size_t)ns * 6 * field_elems() * tsize());
   b += align256((size_t)ns * psi_elems_per_source() * tsize());
   b += align256((size_t)ns * rn_c.size() * nf() * 16);
-  b += 256;  // step index
+  b += 256;  // step index and flush marker
+  b += align256((size_t)ns * hist_elems_per_source() * tsize());
   return b;
 }
 

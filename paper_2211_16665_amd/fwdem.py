@@ -27,7 +27,7 @@ FWD_MODE_FORWARD, FWD_MODE_ADJOINT = 0, 1
 (FWD_TAB_WAVELET, FWD_TAB_NORM, FWD_TAB_OMEGA, FWD_TAB_CPML_X, FWD_TAB_CPML_Y,
  FWD_TAB_CPML_Z, FWD_TAB_BASIS, FWD_TAB_EDGE_SIGMA) = range(8)
 (FWD_OPT_GRAPH_STEPS, FWD_OPT_BLOCK_X, FWD_OPT_BLOCK_Y, FWD_OPT_XCD_REMAP,
- FWD_OPT_SAMPLE_EVERY, FWD_OPT_STRICT_CFL) = range(6)
+ FWD_OPT_SAMPLE_EVERY, FWD_OPT_STRICT_CFL, FWD_OPT_DFT_BLOCK) = range(7)
 
 ACC_MODES = {"f64": FWD_ACC_F64, "kahan": FWD_ACC_KAHAN, "f32": FWD_ACC_F32}
 DTYPES = {"f32": FWD_F32, "f64": FWD_F64}
@@ -83,6 +83,7 @@ SIGNATURES = {
     "fwd_run_begin": (c_int, [c_void_p, c_void_p, c_size_t, c_void_p, c_size_t, c_void_p]),
     "fwd_run_steps": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_void_p]),
     "fwd_run_receivers": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
+    "fwd_run_flush": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "fwd_checkpoint_size": (c_int, [c_void_p, c_int, POINTER(c_size_t)]),
     "fwd_checkpoint_save": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "fwd_checkpoint_restore": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
@@ -282,6 +283,10 @@ class Plan:
         E = self.rec_buffer()
         check(self.lib.fwd_run_receivers(self.handle, _ptr(ws), _ptr(E), _stream(stream)))
         return E
+
+    def run_flush(self, vol, stream=None):
+        ws = self.workspace(FWD_MODE_FORWARD)
+        check(self.lib.fwd_run_flush(self.handle, _ptr(ws), _ptr(vol), _stream(stream)))
 
     def checkpoint_size(self, with_volume=False) -> int:
         n = c_size_t()
