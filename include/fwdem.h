@@ -218,25 +218,28 @@ fwd_status fwd_adjoint(fwd_plan *plan, void *ws_dev, size_t ws_bytes,
 /* Tuning knobs (FWD_OPT_*); value semantics per key.  Host only. */
 enum {
   FWD_OPT_GRAPH_STEPS = 0,   /* steps per captured HIP graph (0 or 1: launch eagerly); default 32 */
-  FWD_OPT_BLOCK_X = 1,       /* threads per block along x: 64, 128 or 256 (x * y <= 256) */
-  FWD_OPT_BLOCK_Y = 2,       /* block rows along y: 1, 2 or 4 */
+  FWD_OPT_BLOCK_X = 1,       /* threads per block along x: 16, 32, 64, 128 or 256.  x * y must
+                                not exceed 256 when a run starts (else FWD_ERR_INVALID_ARG) */
+  FWD_OPT_BLOCK_Y = 2,       /* block rows along y: 1, 2, 4, 8 or 16 */
   FWD_OPT_XCD_REMAP = 3,     /* 1: group neighbouring tiles on one XCD (default) */
   FWD_OPT_SAMPLE_EVERY = 4,  /* > 0: time the kernels of one step in every this many with
                                 HIP events (those chunks launch eagerly); see fwd_kernel_stats */
   FWD_OPT_STRICT_CFL = 5,    /* 1 (default): fwd_set_model rejects a fixed dt above the CFL
                                 bound with FWD_ERR_CFL; 0 lets it run (and typically end in
                                 FWD_ERR_NONFINITE) */
-  FWD_OPT_DFT_BLOCK = 6      /* 1, 2, 4 or 8 (default): samples per read-modify-write of the
+  FWD_OPT_DFT_BLOCK = 6,     /* 1, 2, 4 or 8 (default): samples per read-modify-write of the
                                 volume transform (and of the gradient product).  The E update
                                 holds the last two samples; the others wait in a history buffer
                                 of the workspace.  Changes only the order of the sums.  Set it
                                 before fwd_workspace_size. */
+  FWD_OPT_VECTOR = 7         /* 1 (default): each stencil thread updates one x node; 4: a
+                                16-byte vector of consecutive x nodes (4 in FP32, 2 in FP64) */
 };
 fwd_status fwd_set_option(fwd_plan *plan, int key, double value);
 fwd_status fwd_get_option(const fwd_plan *plan, int key, double *value);
 
 /* Self-written tile/schedule autotuner: times every candidate (block shape,
- * XCD remap) for a few steps of the given mode on the given buffers, keeps
+ * vector width, XCD remap) for a few steps of the given mode on the given buffers, keeps
  * the fastest and returns its time per step (ms).  The state in ws/vol is
  * clobbered.  */
 fwd_status fwd_autotune(fwd_plan *plan, void *ws_dev, size_t ws_bytes,
@@ -248,11 +251,11 @@ fwd_status fwd_autotune(fwd_plan *plan, void *ws_dev, size_t ws_bytes,
  * milliseconds and number of steps. */
 fwd_status fwd_last_timing(const fwd_plan *plan, double *ms, int *steps);
 
-/* Average device time (ms) of the four kernels of one step -- H update,
- * injection, E update (+ volume transform or gradient product), receiver
- * transform -- over the steps sampled in the last fwd_forward / fwd_adjoint
- * (FWD_OPT_SAMPLE_EVERY > 0), measured with HIP events on the caller's
- * stream.  avg_ms has room for 4 values. */
+/* Average device time (ms) of the two kernels of one step -- H update, and
+ * E update fused with injection, receiver transform and volume transform or
+ * gradient product -- over the steps sampled in the last fwd_forward /
+ * fwd_adjoint (FWD_OPT_SAMPLE_EVERY > 0), measured with HIP events on the
+ * caller's stream.  avg_ms has room for 2 values. */
 fwd_status fwd_kernel_stats(const fwd_plan *plan, double *avg_ms, int *samples);
 
 const char *fwd_last_error(void);

@@ -238,13 +238,13 @@ fwd_status fwd_set_option(fwd_plan *h, int key, double value) {
         p.graph_steps = v;
         break;
       case FWD_OPT_BLOCK_X:
-        if (v != 64 && v != 128 && v != 256) fail(FWD_ERR_INVALID_ARG, "block x in {64,128,256}");
-        if (v * p.by > 256) fail(FWD_ERR_INVALID_ARG, "block x * y must be <= 256");
+        if (v != 16 && v != 32 && v != 64 && v != 128 && v != 256)
+          fail(FWD_ERR_INVALID_ARG, "block x in {16,32,64,128,256}");
         p.bx = v;
         break;
       case FWD_OPT_BLOCK_Y:
-        if (v != 1 && v != 2 && v != 4) fail(FWD_ERR_INVALID_ARG, "block y in {1,2,4}");
-        if (v * p.bx > 256) fail(FWD_ERR_INVALID_ARG, "block x * y must be <= 256");
+        if (v != 1 && v != 2 && v != 4 && v != 8 && v != 16)
+          fail(FWD_ERR_INVALID_ARG, "block y in {1,2,4,8,16}");
         p.by = v;
         break;
       case FWD_OPT_XCD_REMAP:
@@ -260,6 +260,11 @@ fwd_status fwd_set_option(fwd_plan *h, int key, double value) {
       case FWD_OPT_DFT_BLOCK:
         if (v != 1 && v != 2 && v != 4 && v != 8) fail(FWD_ERR_INVALID_ARG, "block in {1,2,4,8}");
         p.kb = v;
+        break;
+
+      case FWD_OPT_VECTOR:
+        if (v != 1 && v != 4) fail(FWD_ERR_INVALID_ARG, "vector option in {1, 4}");
+        p.vx = v;
         break;
       default:
         fail(FWD_ERR_INVALID_ARG, "unknown option");
@@ -279,6 +284,7 @@ fwd_status fwd_get_option(const fwd_plan *h, int key, double *value) {
       case FWD_OPT_SAMPLE_EVERY: *value = dev_get_sampling(p); break;
       case FWD_OPT_STRICT_CFL: *value = p.strict_cfl; break;
       case FWD_OPT_DFT_BLOCK: *value = p.kb; break;
+      case FWD_OPT_VECTOR: *value = p.vx; break;
       default: fail(FWD_ERR_INVALID_ARG, "unknown option");
     }
   });

@@ -1,22 +1,21 @@
 // Device side of the fictitious-wave-domain engine for gfx950 (MI355X).
 //
-// One leapfrog step (Section 2, eq. fictitiouswave) is four launches on the
+// One leapfrog step (Section 2, eq. fictitiouswave) is two launches on the
 // caller's stream:
-//   k_update_h   H^{n+1/2} = H^{n-1/2} - dt/mu curl E^n            + CPML
-//   k_inject     E^n -= dt/eps J'^{n+1/2} at the source (or adjoint-source)
-//                edges, deterministic: one thread per target edge
-//   k_update_e   E^{n+1} = E^n + dt/eps curl H^{n+1/2}               + CPML
-//                fused with the volume transform acc_k += E^{n+1} z_k^{n+1}
-//                (eq. dft) in the forward run, or with the on-the-fly gradient
-//                product in the adjoint run
-//   k_rec_dft    transform of E at the receiver lattice nodes
+//   k_update_h   H^{n+1/2} = H^{n-1/2} - dt/mu curl E^n                + CPML
+//   k_update_e   E^{n+1} = E^n + dt/eps (curl H^{n+1/2} - J'^{n+1/2})  + CPML
+//                fused with the injection of J' at the source (or
+//                adjoint-source) edges, the receiver transform, and the
+//                volume transform acc_k += E z_k (eq. dft) in the forward
+//                run or the on-the-fly gradient product in the adjoint run
 // The step index lives in device memory (incremented by k_update_h), so a
 // captured HIP graph of K steps replays for any position in the run.
 //
-// The kernels are bound by HBM traffic (a 3D stencil plus an accumulator
-// sweep, ~0.1-0.8 flop/byte): no matrix cores.  Threads own one (i, j, k)
-// node of the padded layout [k][j][PX] (x fastest, PX a multiple of 64) and
-// loop over the batched sources, so the per-edge coefficient is shared by
+// The kernels are bound by memory traffic and latency (a 3D stencil plus an
+// accumulator sweep, ~0.1-0.8 flop/byte): no matrix cores.  Threads own an
+// (i, j) column of the padded layout [k][j][PX] (x fastest, PX a multiple
+// of 64) and handle 16 bytes of consecutive x nodes per field (4 in FP32,
+// 2 in FP64) with vector loads and stores; they loop over the batched sources, so per-edge coefficients are shared by
 // all sources.  A 1D grid is remapped so that consecutive tiles of one XCD
 // are spatial neighbours (their halos hit the same L2).
 #include <hip/hip_runtime.h>
@@ -60,7 +59,7 @@ struct StepArgs {
   T dtmu;             // dt / mu0
   const int *step;    // current step index (device)
   int *step_w;        // same, written by k_update_h
-  // tiling
+  // tiling: (bx x by) threads over x-y, each thread a vector of x nodes
   int nbx, nby, nbz, nblocks, xcd;
   // volume transform / gradient
   int nf;
@@ -71,10 +70,19 @@ struct StepArgs {
   T *hist;            // [ns][kb-2][3][F] samples of the current transform block
   int64_t hist_src;   // history elements per source
   const int *flushed; // last sample already in the volume transform / gradient
+  // per-thread lists of injection targets and receiver nodes (see TileLists)
+  const int *tile_tab;  // [nblocks]: offset of the tile's table in tl_off, or -1
+  const int *tl_off;    // per listed tile: bx*by + 1 entry offsets
+  const int2 *tl_ent;   // entries: x = c | kind << 2 | s << 3, y = ref
+  int nrow, nt;         // rows of the time-function table, steps
+  const double *coef;   // injection coefficients (entry ref = first row)
+  const double *Ftab;   // [nrow][nt] time functions (wavelet or basis functions)
+  double2 *racc;        // [ns][nn][nf] receiver-node transforms
+  int nn;               // receiver nodes
 };
 
-__device__ __forceinline__ void tile_of(int nblocks, int xcd, int nbx, int nby, int &bx, int &by,
-                                        int &bz) {
+__device__ __forceinline__ int tile_of(int nblocks, int xcd, int nbx, int nby, int &bx, int &by,
+                                       int &bz) {
   int b = blockIdx.x;
   if (xcd) {
     // blocks are dealt round-robin to the 8 XCDs: give XCD x the tiles
@@ -87,6 +95,7 @@ __device__ __forceinline__ void tile_of(int nblocks, int xcd, int nbx, int nby, 
   const int t = b / nbx;
   by = t % nby;
   bz = t / nby;
+  return b;
 }
 
 // slab index of a CPML node: half nodes i+1/2 with i < npml or i >= n-npml;
@@ -102,64 +111,153 @@ __device__ __forceinline__ bool pml_int(int i, int n, int npml, int &l) {
   return false;
 }
 
+// Vector of N consecutive x values of a field: N = 1 (one element per
+// thread) or N = 16 / sizeof(T) (one 16-byte access per field)
+template <typename T, int N_>
+struct Vec {
+  static constexpr int N = N_;
+  T v[N];
+};
+
+template <int N, typename T>
+__device__ __forceinline__ Vec<T, N> vload(const T *p) {
+  Vec<T, N> r;
+  if constexpr (N == 1) {
+    r.v[0] = *p;
+  } else if constexpr (sizeof(T) == 4) {
+    static_assert(N == 4, "16-byte vectors");
+    const float4 x = *reinterpret_cast<const float4 *>(p);
+    r.v[0] = x.x; r.v[1] = x.y; r.v[2] = x.z; r.v[3] = x.w;
+  } else {
+    static_assert(N == 2, "16-byte vectors");
+    const double2 x = *reinterpret_cast<const double2 *>(p);
+    r.v[0] = x.x; r.v[1] = x.y;
+  }
+  return r;
+}
+
+template <typename T, int N>
+__device__ __forceinline__ void vstore(T *p, const Vec<T, N> &r) {
+  if constexpr (N == 1) {
+    *p = r.v[0];
+  } else if constexpr (sizeof(T) == 4) {
+    *reinterpret_cast<float4 *>(p) = make_float4(r.v[0], r.v[1], r.v[2], r.v[3]);
+  } else {
+    *reinterpret_cast<double2 *>(p) = make_double2(r.v[0], r.v[1]);
+  }
+}
+
+template <typename T, int N>
+__device__ __forceinline__ Vec<T, N> vzero() {
+  Vec<T, N> r;
+#pragma unroll
+  for (int e = 0; e < N; ++e) r.v[e] = T(0);
+  return r;
+}
+
 // ---------------------------------------------------------------------------
 // H update: H^{n+1/2} = H^{n-1/2} - dt/mu (curl E^n)
 //   H_x -= dt/mu (dEz/dy - dEy/dz), H_y -= dt/mu (dEx/dz - dEz/dx),
-//   H_z -= dt/mu (dEy/dx - dEx/dy); forward differences over a cell width
+//   H_z -= dt/mu (dEy/dx - dEx/dy); forward differences over a cell width.
+// Each thread owns VX consecutive x nodes (one 16-byte vector per field);
+// the x neighbour beyond the vector is one extra element load.  All loads
+// are issued before any store (loads and stores share one in-order
+// completion counter on this GPU).
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, int VX>
+__device__ __forceinline__ void h_vec(const StepArgs<T> &A, const T *__restrict__ ex,
+                                      const T *__restrict__ ey, const T *__restrict__ ez,
+                                      T *__restrict__ hx, T *__restrict__ hy, T *__restrict__ hz,
+                                      T *__restrict__ psX, T *__restrict__ psY,
+                                      T *__restrict__ psZ, int i0, int j, int k) {
+  using V = Vec<T, VX>;
+  const int PX = A.PX, NY = A.NY, NZ = A.NZ, npml = A.npml, W = 2 * npml;
+  const int64_t plane = (int64_t)NY * PX;
+  const int64_t sX = (int64_t)NZ * NY * W, sY = (int64_t)NZ * W * PX, sZ = (int64_t)W * NY * PX;
+  const AxisDev<T> &X = A.ax[0], &Y = A.ax[1], &Z = A.ax[2];
+  const bool j_in = j < A.ny, k_in = k < A.nz;
+  int ly = 0, lz = 0;
+  const bool py = npml > 0 && pml_half(j, A.ny, npml, ly);
+  const bool pz = npml > 0 && pml_half(k, A.nz, npml, lz);
+  const bool pyv = py && j_in, pzv = pz && k_in;
+  const int64_t q = (int64_t)k * plane + (int64_t)j * PX + i0;
+  const bool nbr = i0 + VX <= A.nx;       // the x neighbour of the last element is used
+  // ---- loads ----
+  const V ex0 = vload<VX>(ex + q), ey0 = vload<VX>(ey + q), ez0 = vload<VX>(ez + q);
+  const V exk = k_in ? vload<VX>(ex + q + plane) : vzero<T, VX>();
+  const V eyk = k_in ? vload<VX>(ey + q + plane) : vzero<T, VX>();
+  const V ezj = j_in ? vload<VX>(ez + q + PX) : vzero<T, VX>();
+  const V exj = j_in ? vload<VX>(ex + q + PX) : vzero<T, VX>();
+  const T eyn = nbr ? ey[q + VX] : T(0), ezn = nbr ? ez[q + VX] : T(0);
+  V hxv = vload<VX>(hx + q), hyv = vload<VX>(hy + q), hzv = vload<VX>(hz + q);
+  const int64_t iY = ((int64_t)k * W + ly) * PX + i0;
+  const int64_t iZ = ((int64_t)lz * NY + j) * PX + i0;
+  V ps_hx_y = pyv && k_in ? vload<VX>(psY + 0 * sY + iY) : vzero<T, VX>();
+  V ps_hz_y = pyv ? vload<VX>(psY + 1 * sY + iY) : vzero<T, VX>();
+  V ps_hx_z = pzv && j_in ? vload<VX>(psZ + 0 * sZ + iZ) : vzero<T, VX>();
+  V ps_hy_z = pzv ? vload<VX>(psZ + 1 * sZ + iZ) : vzero<T, VX>();
+  const T ihy = j_in ? Y.ih[j] : T(0), ihz = k_in ? Z.ih[k] : T(0);
+  // ---- compute ----
+  const T dtmu = A.dtmu;
+#pragma unroll
+  for (int e = 0; e < VX; ++e) {
+    const int i = i0 + e;
+    const bool i_in = i < A.nx;
+    const T ihx = i_in ? X.ih[i] : T(0);
+    const T ey_ip = e + 1 < VX ? ey0.v[(e + 1) % VX] : eyn;
+    const T ez_ip = e + 1 < VX ? ez0.v[(e + 1) % VX] : ezn;
+    int lx = 0;
+    const bool px = npml > 0 && i_in && pml_half(i, A.nx, npml, lx);
+    const int64_t iX = ((int64_t)k * NY + j) * W + lx;
+    if (i <= A.nx && j_in && k_in) {
+      T d1 = (ezj.v[e] - ez0.v[e]) * ihy;       // dEz/dy at y_{j+1/2}
+      T d2 = (eyk.v[e] - ey0.v[e]) * ihz;       // dEy/dz at z_{k+1/2}
+      if (py) { T &p = ps_hx_y.v[e]; p = Y.bh[j] * p + Y.ah[j] * d1; d1 = d1 * Y.kh[j] + p; }
+      if (pz) { T &p = ps_hx_z.v[e]; p = Z.bh[k] * p + Z.ah[k] * d2; d2 = d2 * Z.kh[k] + p; }
+      hxv.v[e] -= dtmu * (d1 - d2);
+    }
+    if (i_in && k_in) {
+      T d1 = (exk.v[e] - ex0.v[e]) * ihz;       // dEx/dz
+      T d2 = (ez_ip - ez0.v[e]) * ihx;          // dEz/dx
+      if (pz) { T &p = ps_hy_z.v[e]; p = Z.bh[k] * p + Z.ah[k] * d1; d1 = d1 * Z.kh[k] + p; }
+      if (px) { T &p = psX[0 * sX + iX]; p = X.bh[i] * p + X.ah[i] * d2; d2 = d2 * X.kh[i] + p; }
+      hyv.v[e] -= dtmu * (d1 - d2);
+    }
+    if (i_in && j_in) {
+      T d1 = (ey_ip - ey0.v[e]) * ihx;          // dEy/dx
+      T d2 = (exj.v[e] - ex0.v[e]) * ihy;       // dEx/dy
+      if (px) { T &p = psX[1 * sX + iX]; p = X.bh[i] * p + X.ah[i] * d1; d1 = d1 * X.kh[i] + p; }
+      if (py) { T &p = ps_hz_y.v[e]; p = Y.bh[j] * p + Y.ah[j] * d2; d2 = d2 * Y.kh[j] + p; }
+      hzv.v[e] -= dtmu * (d1 - d2);
+    }
+  }
+  // ---- stores (slots outside a component's lattice keep their zero) ----
+  vstore(hx + q, hxv);
+  vstore(hy + q, hyv);
+  vstore(hz + q, hzv);
+  if (pyv && k_in) vstore(psY + 0 * sY + iY, ps_hx_y);
+  if (pyv) vstore(psY + 1 * sY + iY, ps_hz_y);
+  if (pzv && j_in) vstore(psZ + 0 * sZ + iZ, ps_hx_z);
+  if (pzv) vstore(psZ + 1 * sZ + iZ, ps_hy_z);
+}
+
+template <typename T, int VX>
 __global__ void __launch_bounds__(256) k_update_h(StepArgs<T> A) {
   int bx, by, bz;
   if ((int)blockIdx.x >= A.nblocks) return;
   tile_of(A.nblocks, A.xcd, A.nbx, A.nby, bx, by, bz);
-  const int i = bx * blockDim.x + threadIdx.x;
+  if (blockIdx.x == 0 && threadIdx.x == 0 && threadIdx.y == 0) A.step_w[0] = A.step_w[0] + 1;
+  const int i0 = (bx * blockDim.x + threadIdx.x) * VX;
   const int j = by * blockDim.y + threadIdx.y;
   const int k = bz;
-  if (blockIdx.x == 0 && threadIdx.x == 0 && threadIdx.y == 0) A.step_w[0] = A.step_w[0] + 1;
-  if (i > A.nx || j > A.ny || k > A.nz) return;
-  const int PX = A.PX, NY = A.NY, NZ = A.NZ, npml = A.npml, W = 2 * npml;
-  const int64_t plane = (int64_t)NY * PX;
-  const int64_t q = (int64_t)k * plane + (int64_t)j * PX + i;
-  const T dtmu = A.dtmu;
-  const AxisDev<T> &X = A.ax[0], &Y = A.ax[1], &Z = A.ax[2];
-  const bool hx_ok = j < A.ny && k < A.nz;
-  const bool hy_ok = i < A.nx && k < A.nz;
-  const bool hz_ok = i < A.nx && j < A.ny;
-  int lx = 0, ly = 0, lz = 0;
-  const bool px = npml > 0 && pml_half(i, A.nx, npml, lx);
-  const bool py = npml > 0 && pml_half(j, A.ny, npml, ly);
-  const bool pz = npml > 0 && pml_half(k, A.nz, npml, lz);
-  const int64_t sX = (int64_t)NZ * NY * W, sY = (int64_t)NZ * W * PX, sZ = (int64_t)W * NY * PX;
+  if (i0 > A.nx || j > A.ny || k > A.nz) return;
+  const int W = 2 * A.npml;
+  const int64_t sX = (int64_t)A.NZ * A.NY * W, sY = (int64_t)A.NZ * W * A.PX;
   for (int s = 0; s < A.ns; ++s) {
     T *f = A.fields + (int64_t)s * 6 * A.F;
-    const T *ex = f, *ey = f + A.F, *ez = f + 2 * A.F;
-    T *hx = f + 3 * A.F, *hy = f + 4 * A.F, *hz = f + 5 * A.F;
     T *ps = A.psi + (int64_t)s * A.psi_src;
-    T *psX = ps, *psY = ps + 4 * sX, *psZ = psY + 4 * sY;
-    const int64_t iX = ((int64_t)k * NY + j) * W + lx;
-    const int64_t iY = ((int64_t)k * W + ly) * PX + i;
-    const int64_t iZ = ((int64_t)lz * NY + j) * PX + i;
-    if (hx_ok) {
-      T d1 = (ez[q + PX] - ez[q]) * Y.ih[j];     // dEz/dy at y_{j+1/2}
-      T d2 = (ey[q + plane] - ey[q]) * Z.ih[k];  // dEy/dz at z_{k+1/2}
-      if (py) { T &p = psY[0 * sY + iY]; p = Y.bh[j] * p + Y.ah[j] * d1; d1 = d1 * Y.kh[j] + p; }
-      if (pz) { T &p = psZ[0 * sZ + iZ]; p = Z.bh[k] * p + Z.ah[k] * d2; d2 = d2 * Z.kh[k] + p; }
-      hx[q] -= dtmu * (d1 - d2);
-    }
-    if (hy_ok) {
-      T d1 = (ex[q + plane] - ex[q]) * Z.ih[k];  // dEx/dz
-      T d2 = (ez[q + 1] - ez[q]) * X.ih[i];      // dEz/dx
-      if (pz) { T &p = psZ[1 * sZ + iZ]; p = Z.bh[k] * p + Z.ah[k] * d1; d1 = d1 * Z.kh[k] + p; }
-      if (px) { T &p = psX[0 * sX + iX]; p = X.bh[i] * p + X.ah[i] * d2; d2 = d2 * X.kh[i] + p; }
-      hy[q] -= dtmu * (d1 - d2);
-    }
-    if (hz_ok) {
-      T d1 = (ey[q + 1] - ey[q]) * X.ih[i];      // dEy/dx
-      T d2 = (ex[q + PX] - ex[q]) * Y.ih[j];     // dEx/dy
-      if (px) { T &p = psX[1 * sX + iX]; p = X.bh[i] * p + X.ah[i] * d1; d1 = d1 * X.kh[i] + p; }
-      if (py) { T &p = psY[1 * sY + iY]; p = Y.bh[j] * p + Y.ah[j] * d2; d2 = d2 * Y.kh[j] + p; }
-      hz[q] -= dtmu * (d1 - d2);
-    }
+    h_vec<T, VX>(A, f, f + A.F, f + 2 * A.F, f + 3 * A.F, f + 4 * A.F, f + 5 * A.F, ps, ps + 4 * sX,
+             ps + 4 * sX + 4 * sY, i0, j, k);
   }
 }
 
@@ -211,158 +309,267 @@ __device__ __forceinline__ double2 acc_read(const void *base, int64_t idx) {
   }
 }
 
-// After the E update of component c at q (old value e0 = sample m-1, new
-// value e1 = sample m, m = n+1): the transform over a block of KB samples
-// is added in one read-modify-write when the block closes (m % KB == 0);
-// samples with m % KB in 1..KB-2 wait in the history buffer, the sample
-// with m % KB == KB-1 is the old value of the closing step.  KB = 1 adds
-// every sample as it comes.  Forward: volume transform acc_k += sum E z_k^m
-// (eq. dft).  Adjoint: g += sum_m u^m Re(sum_k Q_k^m V_k), the gradient
-// product of eq. gradsigmaij accumulated over time (Q on the host).
-// Samples at or before *flushed were already added by a flush.
-template <typename T, int ACC, bool ADJ, int KB>
-__device__ __forceinline__ void post_e(const StepArgs<T> &A, int s, int c, int64_t q, T e0, T e1,
-                                       int n, double &g) {
+// After the E update of component c at q .. q+VX-1 (old values e0 = sample
+// m-1, new values e1 = sample m, m = n+1): the transform over a block of KB
+// samples is added in one read-modify-write when the block closes
+// (m % KB == 0); samples with m % KB in 1..KB-2 wait in the history buffer,
+// the sample with m % KB == KB-1 is the old value of the closing step.
+// KB = 1 adds every sample as it comes.  Forward: volume transform
+// acc_k += sum E z_k^m (eq. dft).  Adjoint: gedge += sum_m u^m Re(sum_k
+// Q_k^m V_k), the gradient product of eq. gradsigmaij accumulated over time
+// (Q on the host).  Samples at or before *flushed were already added by a
+// flush.  Elements outside the component's lattice (ok bit clear) are
+// skipped.
+template <typename T, int ACC, bool ADJ, int KB, int VX>
+__device__ __forceinline__ void post_e(const StepArgs<T> &A, int s, int c, int64_t q,
+                                       const Vec<T, VX> &e0, const Vec<T, VX> &e1, unsigned ok,
+                                       int n, int fl) {
   if constexpr (ACC != ACC_NONE) {
+    if (!ok) return;
     const int nf = A.nf;
     const int m = n + 1;
     const int r = m & (KB - 1);
     T *h = A.hist + (int64_t)s * A.hist_src + (int64_t)c * A.F + q;
     if constexpr (KB > 1) {
       if (r != 0) {
-        if (r <= KB - 2) h[(int64_t)(r - 1) * 3 * A.F] = e1;
+        if (r <= KB - 2) vstore(h + (int64_t)(r - 1) * 3 * A.F, e1);
         return;
       }
     }
     // the KB samples of the block: m-KB+1 .. m; zE / Q index = sample - 1
-    double val[KB];
+    Vec<T, VX> hv[KB > 2 ? KB - 2 : 1];
 #pragma unroll
-    for (int t = 0; t < KB - 2; ++t) val[t] = (double)h[(int64_t)t * 3 * A.F];
-    if constexpr (KB >= 2) val[KB - 2] = (double)e0;
-    val[KB - 1] = (double)e1;
-    const int fl = A.flushed[0];
+    for (int t = 0; t < KB - 2; ++t) hv[t] = vload<VX>(h + (int64_t)t * 3 * A.F);
     const int first = m - KB + 1;
-#pragma unroll
-    for (int t = 0; t < KB; ++t)
-      if (first + t <= fl) val[t] = 0.0;
     const int64_t base = ((int64_t)s * nf * 3 + c) * A.F + q;
-    if constexpr (!ADJ) {
-      for (int kf = 0; kf < nf; ++kf) {
-        double2 sum = make_double2(0.0, 0.0);
 #pragma unroll
-        for (int t = 0; t < KB; ++t) {
-          const double2 z = A.zE[(int64_t)(first - 1 + t) * nf + kf];
-          sum.x = fma(val[t], z.x, sum.x);
-          sum.y = fma(val[t], z.y, sum.y);
-        }
-        acc_add<ACC>(A.vol, base + (int64_t)kf * 3 * A.F, sum);
-      }
-    } else {
-      double re = 0.0;
-      for (int kf = 0; kf < nf; ++kf) {
-        const double2 v = acc_read<ACC>(A.vol, base + (int64_t)kf * 3 * A.F);
+    for (int e = 0; e < VX; ++e) {
+      if (!((ok >> e) & 1u)) continue;
+      double val[KB];
 #pragma unroll
-        for (int t = 0; t < KB; ++t) {
-          const double2 Qt = A.Q[(int64_t)(first - 1 + t) * nf + kf];
-          re = fma(val[t], Qt.x * v.x - Qt.y * v.y, re);
+      for (int t = 0; t < KB - 2; ++t) val[t] = (double)hv[t].v[e];
+      if constexpr (KB >= 2) val[KB - 2] = (double)e0.v[e];
+      val[KB - 1] = (double)e1.v[e];
+#pragma unroll
+      for (int t = 0; t < KB; ++t)
+        if (first + t <= fl) val[t] = 0.0;
+      if constexpr (!ADJ) {
+        for (int kf = 0; kf < nf; ++kf) {
+          double2 sum = make_double2(0.0, 0.0);
+#pragma unroll
+          for (int t = 0; t < KB; ++t) {
+            const double2 z = A.zE[(int64_t)(first - 1 + t) * nf + kf];
+            sum.x = fma(val[t], z.x, sum.x);
+            sum.y = fma(val[t], z.y, sum.y);
+          }
+          acc_add<ACC>(A.vol, base + (int64_t)kf * 3 * A.F + e, sum);
         }
+      } else {
+        double re = 0.0;
+        for (int kf = 0; kf < nf; ++kf) {
+          const double2 v = acc_read<ACC>(A.vol, base + (int64_t)kf * 3 * A.F + e);
+#pragma unroll
+          for (int t = 0; t < KB; ++t) {
+            const double2 Qt = A.Q[(int64_t)(first - 1 + t) * nf + kf];
+            re = fma(val[t], Qt.x * v.x - Qt.y * v.y, re);
+          }
+        }
+        A.gedge[(int64_t)c * A.F + q + e] += re;
       }
-      g += re;
+    }
+  }
+}
+
+// per-thread list walk.  Entry x = c | kind << 2 | elem << 3 | s << 5:
+// kind 0 = injection J'^{n+1/2} into component c of source s at vector
+// element elem, value sum_r coef[ref + r] F[r][n]; kind 1 = receiver node
+// (racc[s][node = ref] += E^{n+1} z^{n+1}, every source).
+template <typename T>
+__device__ __forceinline__ double inject_value(const StepArgs<T> &A, int lo, int hi, int s, int c,
+                                               int elem, int n) {
+  double v = 0.0;
+  for (int e = lo; e < hi; ++e) {
+    const int2 en = A.tl_ent[e];
+    if ((en.x & 31) == (c | (elem << 3)) && (en.x >> 5) == s) {
+      const double *cf = A.coef + en.y;
+      for (int r = 0; r < A.nrow; ++r) v += cf[r] * A.Ftab[(int64_t)r * A.nt + n];
+    }
+  }
+  return v;
+}
+
+template <typename T>
+__device__ __forceinline__ void record(const StepArgs<T> &A, int lo, int hi, int s, int c,
+                                       int elem, int n, double e) {
+  for (int e2 = lo; e2 < hi; ++e2) {
+    const int2 en = A.tl_ent[e2];
+    if ((en.x & 31) == (c | 4 | (elem << 3))) {
+      double2 *a = A.racc + ((int64_t)s * A.nn + en.y) * A.nf;
+      const double2 *z = A.zE + (int64_t)n * A.nf;
+      for (int kf = 0; kf < A.nf; ++kf) {
+        double2 v = a[kf];
+        v.x = fma(e, z[kf].x, v.x);
+        v.y = fma(e, z[kf].y, v.y);
+        a[kf] = v;
+      }
     }
   }
 }
 
 // ---------------------------------------------------------------------------
-// E update: E^{n+1} = E^n + dt/eps curl H^{n+1/2} on interior edges
-//   E_x += ce (dHz/dy - dHy/dz), E_y += ce (dHx/dz - dHz/dx),
-//   E_z += ce (dHy/dx - dHx/dy); backward differences over a dual width
+// E update: E^{n+1} = E^n + dt/eps (curl H^{n+1/2} - J'^{n+1/2}) on interior
+// edges:  E_x += ce (dHz/dy - dHy/dz - J_x), E_y += ce (dHx/dz - dHz/dx - J_y),
+// E_z += ce (dHy/dx - dHx/dy - J_z); backward differences over a dual width.
+// Fused: injection at the source (or adjoint-source) edges, the receiver
+// transform, and the volume transform / gradient product.  Each thread owns
+// VX consecutive x nodes; the x neighbour before the vector is one extra
+// element load; all stencil loads precede the stores.
 // ---------------------------------------------------------------------------
-template <typename T, int ACC, bool ADJ, int KB>
+template <typename T, int ACC, bool ADJ, int KB, int VX>
+__device__ __forceinline__ void e_vec(const StepArgs<T> &A, int s, T *__restrict__ ex,
+                                      T *__restrict__ ey, T *__restrict__ ez,
+                                      const T *__restrict__ hx, const T *__restrict__ hy,
+                                      const T *__restrict__ hz, T *__restrict__ psX,
+                                      T *__restrict__ psY, T *__restrict__ psZ, int i0, int j,
+                                      int k, int n, int fl, int lo, int hi) {
+  using V = Vec<T, VX>;
+  const int PX = A.PX, NY = A.NY, NZ = A.NZ, npml = A.npml, W = 2 * npml;
+  const int64_t plane = (int64_t)NY * PX;
+  const int64_t sX = (int64_t)NZ * NY * W, sY = (int64_t)NZ * W * PX, sZ = (int64_t)W * NY * PX;
+  const AxisDev<T> &X = A.ax[0], &Y = A.ax[1], &Z = A.ax[2];
+  const bool j_int = j >= 1 && j < A.ny, k_int = k >= 1 && k < A.nz;
+  const bool j_in = j < A.ny, k_in = k < A.nz;
+  int ly = 0, lz = 0;
+  const bool py = npml > 0 && pml_int(j, A.ny, npml, ly);
+  const bool pz = npml > 0 && pml_int(k, A.nz, npml, lz);
+  const int64_t q = (int64_t)k * plane + (int64_t)j * PX + i0;
+  // lattice masks per element
+  unsigned okx = 0, oky = 0, okz = 0;
+#pragma unroll
+  for (int e = 0; e < VX; ++e) {
+    const int i = i0 + e;
+    if (i < A.nx && j_int && k_int) okx |= 1u << e;
+    if (i >= 1 && i < A.nx && j_in && k_int) oky |= 1u << e;
+    if (i >= 1 && i < A.nx && j_int && k_in) okz |= 1u << e;
+  }
+  // ---- loads ----
+  const V hx0 = vload<VX>(hx + q), hy0 = vload<VX>(hy + q), hz0 = vload<VX>(hz + q);
+  const V hzj = j >= 1 ? vload<VX>(hz + q - PX) : vzero<T, VX>();
+  const V hxj = j >= 1 ? vload<VX>(hx + q - PX) : vzero<T, VX>();
+  const V hyk = k >= 1 ? vload<VX>(hy + q - plane) : vzero<T, VX>();
+  const V hxk = k >= 1 ? vload<VX>(hx + q - plane) : vzero<T, VX>();
+  const T hzp = i0 >= 1 ? hz[q - 1] : T(0), hyp = i0 >= 1 ? hy[q - 1] : T(0);
+  V e0x = vload<VX>(ex + q), e0y = vload<VX>(ey + q), e0z = vload<VX>(ez + q);
+  const V cx = okx ? vload<VX>(A.ce[0] + q) : vzero<T, VX>();
+  const V cy = oky ? vload<VX>(A.ce[1] + q) : vzero<T, VX>();
+  const V cz = okz ? vload<VX>(A.ce[2] + q) : vzero<T, VX>();
+  const int64_t iY = ((int64_t)k * W + ly) * PX + i0;
+  const int64_t iZ = ((int64_t)lz * NY + j) * PX + i0;
+  V ps_ex_y = py && okx ? vload<VX>(psY + 2 * sY + iY) : vzero<T, VX>();
+  V ps_ez_y = py && okz ? vload<VX>(psY + 3 * sY + iY) : vzero<T, VX>();
+  V ps_ex_z = pz && okx ? vload<VX>(psZ + 2 * sZ + iZ) : vzero<T, VX>();
+  V ps_ey_z = pz && oky ? vload<VX>(psZ + 3 * sZ + iZ) : vzero<T, VX>();
+  const T ihdy = j_int ? Y.ihd[j] : T(0), ihdz = k_int ? Z.ihd[k] : T(0);
+  // ---- compute ----
+  V e1x = e0x, e1y = e0y, e1z = e0z;
+#pragma unroll
+  for (int e = 0; e < VX; ++e) {
+    const int i = i0 + e;
+    const bool i_int = i >= 1 && i < A.nx;
+    const T ihdx = i_int ? X.ihd[i] : T(0);
+    const T hz_im = e > 0 ? hz0.v[(e + VX - 1) % VX] : hzp;
+    const T hy_im = e > 0 ? hy0.v[(e + VX - 1) % VX] : hyp;
+    int lx = 0;
+    const bool px = npml > 0 && i_int && pml_int(i, A.nx, npml, lx);
+    const int64_t iX = ((int64_t)k * NY + j) * W + lx;
+    if ((okx >> e) & 1u) {
+      T d1 = (hz0.v[e] - hzj.v[e]) * ihdy;       // dHz/dy at y_j
+      T d2 = (hy0.v[e] - hyk.v[e]) * ihdz;       // dHy/dz at z_k
+      if (py) { T &p = ps_ex_y.v[e]; p = Y.bn[j] * p + Y.an[j] * d1; d1 = d1 * Y.kn[j] + p; }
+      if (pz) { T &p = ps_ex_z.v[e]; p = Z.bn[k] * p + Z.an[k] * d2; d2 = d2 * Z.kn[k] + p; }
+      T v = e0x.v[e] + cx.v[e] * (d1 - d2);
+      if (lo < hi) v -= (T)((double)cx.v[e] * inject_value(A, lo, hi, s, 0, e, n));
+      e1x.v[e] = v;
+    }
+    if ((oky >> e) & 1u) {
+      T d1 = (hx0.v[e] - hxk.v[e]) * ihdz;       // dHx/dz
+      T d2 = (hz0.v[e] - hz_im) * ihdx;          // dHz/dx
+      if (pz) { T &p = ps_ey_z.v[e]; p = Z.bn[k] * p + Z.an[k] * d1; d1 = d1 * Z.kn[k] + p; }
+      if (px) { T &p = psX[2 * sX + iX]; p = X.bn[i] * p + X.an[i] * d2; d2 = d2 * X.kn[i] + p; }
+      T v = e0y.v[e] + cy.v[e] * (d1 - d2);
+      if (lo < hi) v -= (T)((double)cy.v[e] * inject_value(A, lo, hi, s, 1, e, n));
+      e1y.v[e] = v;
+    }
+    if ((okz >> e) & 1u) {
+      T d1 = (hy0.v[e] - hy_im) * ihdx;          // dHy/dx
+      T d2 = (hx0.v[e] - hxj.v[e]) * ihdy;       // dHx/dy
+      if (px) { T &p = psX[3 * sX + iX]; p = X.bn[i] * p + X.an[i] * d1; d1 = d1 * X.kn[i] + p; }
+      if (py) { T &p = ps_ez_y.v[e]; p = Y.bn[j] * p + Y.an[j] * d2; d2 = d2 * Y.kn[j] + p; }
+      T v = e0z.v[e] + cz.v[e] * (d1 - d2);
+      if (lo < hi) v -= (T)((double)cz.v[e] * inject_value(A, lo, hi, s, 2, e, n));
+      e1z.v[e] = v;
+    }
+  }
+  // ---- stores ----
+  if (okx) vstore(ex + q, e1x);
+  if (oky) vstore(ey + q, e1y);
+  if (okz) vstore(ez + q, e1z);
+  if (py && okx) vstore(psY + 2 * sY + iY, ps_ex_y);
+  if (py && okz) vstore(psY + 3 * sY + iY, ps_ez_y);
+  if (pz && okx) vstore(psZ + 2 * sZ + iZ, ps_ex_z);
+  if (pz && oky) vstore(psZ + 3 * sZ + iZ, ps_ey_z);
+  if (lo < hi) {
+#pragma unroll
+    for (int e = 0; e < VX; ++e) {
+      if ((okx >> e) & 1u) record(A, lo, hi, s, 0, e, n, (double)e1x.v[e]);
+      if ((oky >> e) & 1u) record(A, lo, hi, s, 1, e, n, (double)e1y.v[e]);
+      if ((okz >> e) & 1u) record(A, lo, hi, s, 2, e, n, (double)e1z.v[e]);
+    }
+  }
+  // ---- volume transform / gradient product ----
+  post_e<T, ACC, ADJ, KB, VX>(A, s, 0, q, e0x, e1x, okx, n, fl);
+  post_e<T, ACC, ADJ, KB, VX>(A, s, 1, q, e0y, e1y, oky, n, fl);
+  post_e<T, ACC, ADJ, KB, VX>(A, s, 2, q, e0z, e1z, okz, n, fl);
+}
+
+template <typename T, int ACC, bool ADJ, int KB, int VX>
 __global__ void __launch_bounds__(256) k_update_e(StepArgs<T> A) {
   int bx, by, bz;
   if ((int)blockIdx.x >= A.nblocks) return;
-  tile_of(A.nblocks, A.xcd, A.nbx, A.nby, bx, by, bz);
-  const int i = bx * blockDim.x + threadIdx.x;
+  const int b = tile_of(A.nblocks, A.xcd, A.nbx, A.nby, bx, by, bz);
+  const int i0 = (bx * blockDim.x + threadIdx.x) * VX;
   const int j = by * blockDim.y + threadIdx.y;
   const int k = bz;
-  if (i > A.nx || j > A.ny || k > A.nz) return;
-  const int PX = A.PX, NY = A.NY, NZ = A.NZ, npml = A.npml, W = 2 * npml;
-  const int64_t plane = (int64_t)NY * PX;
-  const int64_t q = (int64_t)k * plane + (int64_t)j * PX + i;
+  if (i0 > A.nx || j > A.ny || k > A.nz) return;
   const int n = A.step[0];
-  const AxisDev<T> &X = A.ax[0], &Y = A.ax[1], &Z = A.ax[2];
-  const bool ex_ok = i < A.nx && j >= 1 && j < A.ny && k >= 1 && k < A.nz;
-  const bool ey_ok = i >= 1 && i < A.nx && j < A.ny && k >= 1 && k < A.nz;
-  const bool ez_ok = i >= 1 && i < A.nx && j >= 1 && j < A.ny && k < A.nz;
-  int lx = 0, ly = 0, lz = 0;
-  const bool px = npml > 0 && pml_int(i, A.nx, npml, lx);
-  const bool py = npml > 0 && pml_int(j, A.ny, npml, ly);
-  const bool pz = npml > 0 && pml_int(k, A.nz, npml, lz);
-  const int64_t sX = (int64_t)NZ * NY * W, sY = (int64_t)NZ * W * PX, sZ = (int64_t)W * NY * PX;
-  const T cex = ex_ok ? A.ce[0][q] : T(0), cey = ey_ok ? A.ce[1][q] : T(0),
-          cez = ez_ok ? A.ce[2][q] : T(0);
-  double gx = 0.0, gy = 0.0, gz = 0.0;
+  const int fl = A.flushed[0];
+  const int W = 2 * A.npml;
+  const int64_t sX = (int64_t)A.NZ * A.NY * W, sY = (int64_t)A.NZ * W * A.PX;
+  // this thread's slice of the tile's entry table (if the tile has one)
+  const int tt = A.tile_tab[b];
+  int lo = 0, hi = 0;
+  if (tt >= 0) {
+    const int slot = threadIdx.y * blockDim.x + threadIdx.x;
+    lo = A.tl_off[tt + slot];
+    hi = A.tl_off[tt + slot + 1];
+  }
   for (int s = 0; s < A.ns; ++s) {
     T *f = A.fields + (int64_t)s * 6 * A.F;
-    T *ex = f, *ey = f + A.F, *ez = f + 2 * A.F;
-    const T *hx = f + 3 * A.F, *hy = f + 4 * A.F, *hz = f + 5 * A.F;
     T *ps = A.psi + (int64_t)s * A.psi_src;
-    T *psX = ps, *psY = ps + 4 * sX, *psZ = psY + 4 * sY;
-    const int64_t iX = ((int64_t)k * NY + j) * W + lx;
-    const int64_t iY = ((int64_t)k * W + ly) * PX + i;
-    const int64_t iZ = ((int64_t)lz * NY + j) * PX + i;
-    if (ex_ok) {
-      T d1 = (hz[q] - hz[q - PX]) * Y.ihd[j];     // dHz/dy at y_j
-      T d2 = (hy[q] - hy[q - plane]) * Z.ihd[k];  // dHy/dz at z_k
-      if (py) { T &p = psY[2 * sY + iY]; p = Y.bn[j] * p + Y.an[j] * d1; d1 = d1 * Y.kn[j] + p; }
-      if (pz) { T &p = psZ[2 * sZ + iZ]; p = Z.bn[k] * p + Z.an[k] * d2; d2 = d2 * Z.kn[k] + p; }
-      const T e0 = ex[q];
-      const T e = e0 + cex * (d1 - d2);
-      ex[q] = e;
-      post_e<T, ACC, ADJ, KB>(A, s, 0, q, e0, e, n, gx);
-    }
-    if (ey_ok) {
-      T d1 = (hx[q] - hx[q - plane]) * Z.ihd[k];  // dHx/dz
-      T d2 = (hz[q] - hz[q - 1]) * X.ihd[i];      // dHz/dx
-      if (pz) { T &p = psZ[3 * sZ + iZ]; p = Z.bn[k] * p + Z.an[k] * d1; d1 = d1 * Z.kn[k] + p; }
-      if (px) { T &p = psX[2 * sX + iX]; p = X.bn[i] * p + X.an[i] * d2; d2 = d2 * X.kn[i] + p; }
-      const T e0 = ey[q];
-      const T e = e0 + cey * (d1 - d2);
-      ey[q] = e;
-      post_e<T, ACC, ADJ, KB>(A, s, 1, q, e0, e, n, gy);
-    }
-    if (ez_ok) {
-      T d1 = (hy[q] - hy[q - 1]) * X.ihd[i];      // dHy/dx
-      T d2 = (hx[q] - hx[q - PX]) * Y.ihd[j];     // dHx/dy
-      if (px) { T &p = psX[3 * sX + iX]; p = X.bn[i] * p + X.an[i] * d1; d1 = d1 * X.kn[i] + p; }
-      if (py) { T &p = psY[3 * sY + iY]; p = Y.bn[j] * p + Y.an[j] * d2; d2 = d2 * Y.kn[j] + p; }
-      const T e0 = ez[q];
-      const T e = e0 + cez * (d1 - d2);
-      ez[q] = e;
-      post_e<T, ACC, ADJ, KB>(A, s, 2, q, e0, e, n, gz);
-    }
-  }
-  if constexpr (ADJ) {
-    if (((n + 1) & (KB - 1)) == 0) {
-      if (ex_ok) A.gedge[q] += gx;
-      if (ey_ok) A.gedge[A.F + q] += gy;
-      if (ez_ok) A.gedge[2 * A.F + q] += gz;
-    }
+    e_vec<T, ACC, ADJ, KB, VX>(A, s, f, f + A.F, f + 2 * A.F, f + 3 * A.F, f + 4 * A.F, f + 5 * A.F,
+                           ps, ps + 4 * sX, ps + 4 * sX + 4 * sY, i0, j, k, n, fl, lo, hi);
   }
 }
 
 // Flush: add the samples of the incomplete last block (m_last % KB != 0)
 // that are newer than *flushed; the caller then moves *flushed to m_last
-// with k_set_flushed.  Same thread mapping as the E update.
+// with k_set_flushed.  One thread per node of the padded layout.
 template <typename T, int ACC, bool ADJ, int KB>
 __global__ void __launch_bounds__(256) k_flush(StepArgs<T> A) {
-  int bx, by, bz;
-  if ((int)blockIdx.x >= A.nblocks) return;
-  tile_of(A.nblocks, A.xcd, A.nbx, A.nby, bx, by, bz);
-  const int i = bx * blockDim.x + threadIdx.x;
-  const int j = by * blockDim.y + threadIdx.y;
-  const int k = bz;
-  if (i > A.nx || j > A.ny || k > A.nz) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  const int k = blockIdx.z;
+  if (i > A.nx) return;
   const int m_last = A.step[0] + 1;
   const int r_end = m_last & (KB - 1);
   if (KB == 1 || r_end == 0) return;
@@ -405,107 +612,6 @@ __global__ void __launch_bounds__(256) k_flush(StepArgs<T> A) {
 
 __global__ void k_set_flushed(int *flushed, const int *step) {
   if (threadIdx.x == 0 && blockIdx.x == 0) flushed[0] = step[0] + 1;
-}
-
-// ---------------------------------------------------------------------------
-// injection of J'^{n+1/2}: E -= ce * sum_r coef[toff+r] F[r][n]
-// Forward: one thread per (source, component, edge) target; adjoint: one
-// thread per (component, edge) node looping over the sources.  No atomics.
-// The E update that follows reads the injected value as its "old" sample
-// E^n; when a transform block closes at this step (KB > 1) the exact
-// difference E^n - (E^n - ce J) is added here to the volume transform
-// (forward) or to the gradient product (adjoint) at the target edge.
-// ---------------------------------------------------------------------------
-template <typename T>
-struct InjArgs {
-  int ntg, nrow, nt, ns, nn, nf;
-  const int *tg_s, *tg_c, *tg_toff;
-  const int64_t *tg_idx;
-  const double *coef, *Ftab;
-  T *fields;
-  int64_t F;
-  const T *ce0, *ce1, *ce2;
-  const int *step, *flushed;
-  void *vol;
-  const double2 *zE, *Q;
-  double *gedge;
-};
-
-template <typename T, int ACC, bool ADJ, int KB>
-__global__ void k_inject(InjArgs<T> I) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= I.ntg) return;
-  const int n = I.step[0];
-  const bool closing = ACC != ACC_NONE && KB > 1 && ((n + 1) & (KB - 1)) == 0 && n > I.flushed[0];
-  const int c = I.tg_c[t];
-  const int64_t idx = I.tg_idx[t];
-  const T *ce = c == 0 ? I.ce0 : (c == 1 ? I.ce1 : I.ce2);
-  const double cev = (double)ce[idx];
-  const int nf = I.nf;
-  if constexpr (!ADJ) {
-    const int s = I.tg_s[t];
-    double v = 0.0;
-    const double *cf = I.coef + I.tg_toff[t];
-    for (int r = 0; r < I.nrow; ++r) v += cf[r] * I.Ftab[(int64_t)r * I.nt + n];
-    T *E = I.fields + ((int64_t)s * 6 + c) * I.F;
-    const T old = E[idx];
-    const T now = old - (T)(cev * v);
-    E[idx] = now;
-    if constexpr (ACC != ACC_NONE) {
-      if (closing) {
-        const double dlt = (double)old - (double)now;
-        const int64_t base = (((int64_t)s * nf) * 3 + c) * I.F + idx;
-        for (int kf = 0; kf < nf; ++kf) {
-          const double2 z = I.zE[(int64_t)(n - 1) * nf + kf];
-          acc_add<ACC>(I.vol, base + (int64_t)kf * 3 * I.F, make_double2(dlt * z.x, dlt * z.y));
-        }
-      }
-    }
-  } else {
-    double g = 0.0;
-    for (int s = 0; s < I.ns; ++s) {
-      double v = 0.0;
-      const double *cf = I.coef + ((int64_t)s * I.nn + t) * I.nrow;
-      for (int r = 0; r < I.nrow; ++r) v += cf[r] * I.Ftab[(int64_t)r * I.nt + n];
-      T *E = I.fields + ((int64_t)s * 6 + c) * I.F;
-      const T old = E[idx];
-      const T now = old - (T)(cev * v);
-      E[idx] = now;
-      if constexpr (ACC != ACC_NONE) {
-        if (closing) {
-          const double dlt = (double)old - (double)now;
-          const int64_t base = (((int64_t)s * nf) * 3 + c) * I.F + idx;
-          double re = 0.0;
-          for (int kf = 0; kf < nf; ++kf) {
-            const double2 Vk = acc_read<ACC>(I.vol, base + (int64_t)kf * 3 * I.F);
-            const double2 Qt = I.Q[(int64_t)(n - 1) * nf + kf];
-            re += Qt.x * Vk.x - Qt.y * Vk.y;
-          }
-          g += dlt * re;
-        }
-      }
-    }
-    if (closing) I.gedge[(int64_t)c * I.F + idx] += g;
-  }
-}
-
-// transform of E at the receiver lattice nodes: one thread per (source, node)
-template <typename T>
-__global__ void k_rec_dft(int ns, int nn, const int *rn_c, const int64_t *rn_idx, const T *fields,
-                          int64_t F, int nf, const double2 *zE, double2 *racc, const int *step) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= ns * nn) return;
-  const int s = t / nn, node = t % nn;
-  const int n = step[0];
-  const double e = (double)fields[((int64_t)s * 6 + rn_c[node]) * F + rn_idx[node]];
-  const double2 *z = zE + (int64_t)n * nf;
-  double2 *a = racc + (int64_t)t * nf;
-  for (int kf = 0; kf < nf; ++kf) {
-    double2 v = a[kf];
-    v.x = fma(e, z[kf].x, v.x);
-    v.y = fma(e, z[kf].y, v.y);
-    a[kf] = v;
-  }
 }
 
 // receiver output: interpolate node transforms and scale per frequency
@@ -600,6 +706,12 @@ struct Dev {
   double2 *fwd_scale = nullptr, *adj_scale_v = nullptr, *vol_scale = nullptr;
   // adjoint injection coefficients (rebuilt per call)
   double *at_coef = nullptr;
+  // per-thread entry tables of the E update for the current tiling, forward
+  // (index 0) and adjoint (index 1); see build_lists
+  int *tile_tab[2] = {nullptr, nullptr}, *tl_off[2] = {nullptr, nullptr};
+  int2 *tl_ent[2] = {nullptr, nullptr};
+  std::string list_key;
+  std::vector<DevBuf> list_bufs;
   double *cellfac = nullptr;
   double2 *eadj = nullptr;      // adjoint receiver transform when the caller passes none
   // graphs
@@ -608,7 +720,7 @@ struct Dev {
   std::string exec_key;
   // sampled per-kernel timing
   std::vector<hipEvent_t> ev;
-  double kstat_ms[4] = {0, 0, 0, 0};
+  double kstat_ms[2] = {0, 0};
   int kstat_n = 0;
   int sample_every = 0;
 };
@@ -640,7 +752,18 @@ static T *upload_as(Dev &d, const std::vector<double> &h) {
   return upload(d, t);
 }
 
+static void free_lists(Dev &d) {
+  for (auto &b : d.list_bufs) (void)hipFree(b.p);
+  d.list_bufs.clear();
+  d.list_key.clear();
+  for (int m = 0; m < 2; ++m) {
+    d.tile_tab[m] = d.tl_off[m] = nullptr;
+    d.tl_ent[m] = nullptr;
+  }
+}
+
 static void free_tables(Dev &d) {
+  free_lists(d);
   for (auto &b : d.bufs) (void)hipFree(b.p);
   d.bufs.clear();
   if (d.exec) {
@@ -801,11 +924,100 @@ static WS carve(const Plan &p, void *ws) {
 // ---------------------------------------------------------------------------
 // one step = four launches
 // ---------------------------------------------------------------------------
-struct Launch {
-  int mode;       // FWD_MODE_*
-  bool volume;    // forward: accumulate the volume transform
-  int block_x, block_y;
+// Tiling of the stencil kernels: (bx x by) threads over x-y, each thread a
+// 16-byte vector of VX x nodes, one plane per block row of tiles;
+// tile b = (bz * nby + by) * nbx + bx.
+struct Tiling {
+  int nbx, nby, nbz, nblocks, vx;
 };
+
+static Tiling tiling(const Plan &p) {
+  if (p.bx * p.by > 256) fail(FWD_ERR_INVALID_ARG, "block x * block y must be <= 256");
+  Tiling t;
+  t.vx = p.vx == 1 ? 1 : (int)(16 / p.tsize());
+  t.nbx = (p.NX + p.bx * t.vx - 1) / (p.bx * t.vx);
+  t.nby = (p.NY + p.by - 1) / p.by;
+  t.nbz = p.NZ;
+  t.nblocks = t.nbx * t.nby * t.nbz;
+  return t;
+}
+
+// Per-thread entry tables of the E update.  An entry is an injection target
+// (kind 0: component c of source s; ref = first coefficient row) or a
+// receiver node (kind 1: component c; ref = node index), attached to the
+// thread of the tiling that owns its edge (with the element of that
+// thread's vector), so that the E update finds its own entries with two
+// loads and no search.
+static void build_lists(Plan &p, Dev &d) {
+  const Tiling t = tiling(p);
+  char key[128];
+  snprintf(key, sizeof key, "%d/%d/%d/%llu", p.bx, p.by, p.vx, (unsigned long long)p.model_version);
+  if (d.list_key == key) return;
+  free_lists(d);
+  const int nn = (int)p.rn_c.size(), nf = p.nf();
+  const int slots = p.bx * p.by;
+  for (int mode = 0; mode < 2; ++mode) {
+    struct E {
+      int b, slot;
+      int2 v;
+    };
+    std::vector<E> ents;
+    auto place = [&](int c, int kind, int s, int64_t idx, int ref) {
+      const int64_t plane = (int64_t)p.NY * p.PX;
+      const int k = (int)(idx / plane), j = (int)((idx % plane) / p.PX), i = (int)(idx % p.PX);
+      const int tx = i / t.vx, elem = i % t.vx;
+      const int bxi = tx / p.bx, byi = j / p.by, bzi = k;
+      const int b = (bzi * t.nby + byi) * t.nbx + bxi;
+      const int slot = (j % p.by) * p.bx + (tx % p.bx);
+      ents.push_back({b, slot, make_int2(c | (kind << 2) | (elem << 3) | (s << 5), ref)});
+    };
+    if (mode == 0) {
+      for (size_t q = 0; q < p.src_tg.size(); ++q)
+        place(p.src_tg[q].c, 0, p.src_tg[q].s, p.src_tg[q].idx, (int)q);
+    } else {
+      for (int s = 0; s < p.ns; ++s)
+        for (int node = 0; node < nn; ++node)
+          place(p.rn_c[node], 0, s, p.rn_idx[node], (s * nn + node) * 2 * nf);
+    }
+    for (int node = 0; node < nn; ++node) place(p.rn_c[node], 1, 0, p.rn_idx[node], node);
+    std::stable_sort(ents.begin(), ents.end(), [](const E &a, const E &b) {
+      return a.b != b.b ? a.b < b.b : a.slot < b.slot;
+    });
+    std::vector<int> tab(t.nblocks, -1), off;
+    std::vector<int2> ev;
+    size_t e = 0;
+    while (e < ents.size()) {
+      const int b = ents[e].b;
+      tab[b] = (int)off.size();
+      const size_t base = off.size();
+      off.resize(base + slots + 1, 0);
+      size_t f = e;
+      while (f < ents.size() && ents[f].b == b) ++f;
+      // counts per slot, then prefix offsets into the global entry array
+      std::vector<int> cnt(slots, 0);
+      for (size_t g = e; g < f; ++g) cnt[ents[g].slot]++;
+      int acc = (int)ev.size();
+      for (int sl = 0; sl < slots; ++sl) {
+        off[base + sl] = acc;
+        acc += cnt[sl];
+      }
+      off[base + slots] = acc;
+      for (size_t g = e; g < f; ++g) ev.push_back(ents[g].v);
+      e = f;
+    }
+    auto up = [&](const void *h, size_t bytes) {
+      void *ptr = nullptr;
+      HIP_CHECK(hipMalloc(&ptr, bytes ? bytes : 16));
+      d.list_bufs.push_back({ptr, bytes});
+      if (bytes) HIP_CHECK(hipMemcpy(ptr, h, bytes, hipMemcpyHostToDevice));
+      return ptr;
+    };
+    d.tile_tab[mode] = static_cast<int *>(up(tab.data(), tab.size() * sizeof(int)));
+    d.tl_off[mode] = static_cast<int *>(up(off.data(), off.size() * sizeof(int)));
+    d.tl_ent[mode] = static_cast<int2 *>(up(ev.data(), ev.size() * sizeof(int2)));
+  }
+  d.list_key = key;
+}
 
 template <typename T>
 static StepArgs<T> make_args(Plan &p, Dev &d, const WS &w, void *vol, bool adj) {
@@ -836,10 +1048,11 @@ static StepArgs<T> make_args(Plan &p, Dev &d, const WS &w, void *vol, bool adj) 
   A.dtmu = (T)(p.dt / kMu0);
   A.step = w.step;
   A.step_w = w.step;
-  A.nbx = (p.NX + p.bx - 1) / p.bx;
-  A.nby = (p.NY + p.by - 1) / p.by;
-  A.nbz = p.NZ;
-  A.nblocks = A.nbx * A.nby * A.nbz;
+  const Tiling t = tiling(p);
+  A.nbx = t.nbx;
+  A.nby = t.nby;
+  A.nbz = t.nbz;
+  A.nblocks = t.nblocks;
   A.xcd = p.xcd;
   A.nf = p.nf();
   A.zE = d.zE;
@@ -849,19 +1062,35 @@ static StepArgs<T> make_args(Plan &p, Dev &d, const WS &w, void *vol, bool adj) 
   A.hist = static_cast<T *>(w.hist);
   A.hist_src = p.hist_elems_per_source();
   A.flushed = w.flushed;
+  const int m = adj ? 1 : 0;   // tables built by build_lists before any launch or capture
+  A.tile_tab = d.tile_tab[m];
+  A.tl_off = d.tl_off[m];
+  A.tl_ent = d.tl_ent[m];
+  A.nt = p.nt;
+  if (adj) {
+    A.nrow = 2 * p.nf();
+    A.coef = d.at_coef;
+    A.Ftab = d.basis;
+  } else {
+    A.nrow = 1;
+    A.coef = d.src_coef;
+    A.Ftab = d.wavelet;
+  }
+  A.racc = w.racc;
+  A.nn = (int)p.rn_c.size();
   return A;
 }
 
-template <typename T, int KB>
-static void launch_e_kb(const StepArgs<T> &A, int acc, bool adj, bool flush, dim3 grid, dim3 block,
+template <typename T, int KB, int VX>
+static void launch_e_vx(const StepArgs<T> &A, int acc, bool adj, bool flush, dim3 grid, dim3 block,
                         hipStream_t st) {
 #define FWD_LAUNCH(ACCV, ADJV)                                                                 \
   do {                                                                                         \
     if (flush) hipLaunchKernelGGL((k_flush<T, ACCV, ADJV, KB>), grid, block, 0, st, A);        \
-    else hipLaunchKernelGGL((k_update_e<T, ACCV, ADJV, KB>), grid, block, 0, st, A);           \
+    else hipLaunchKernelGGL((k_update_e<T, ACCV, ADJV, KB, VX>), grid, block, 0, st, A);       \
   } while (0)
   if (!A.vol) {
-    if (!flush) hipLaunchKernelGGL((k_update_e<T, ACC_NONE, false, 1>), grid, block, 0, st, A);
+    if (!flush) hipLaunchKernelGGL((k_update_e<T, ACC_NONE, false, 1, VX>), grid, block, 0, st, A);
     return;
   }
   switch (acc) {
@@ -877,107 +1106,53 @@ static void launch_e_kb(const StepArgs<T> &A, int acc, bool adj, bool flush, dim
 #undef FWD_LAUNCH
 }
 
+template <typename T, int KB>
+static void launch_e_kb(const StepArgs<T> &A, int vx, int acc, bool adj, bool flush, dim3 grid,
+                        dim3 block, hipStream_t st) {
+  constexpr int VV = (int)(16 / sizeof(T));
+  if (vx == 1) launch_e_vx<T, KB, 1>(A, acc, adj, flush, grid, block, st);
+  else launch_e_vx<T, KB, VV>(A, acc, adj, flush, grid, block, st);
+}
+
 // E update (flush = false) or the flush of an incomplete transform block
 template <typename T>
-static void launch_e(const StepArgs<T> &A, int kb, int acc, bool adj, bool flush, dim3 grid,
-                     dim3 block, hipStream_t st) {
+static void launch_e(const StepArgs<T> &A, int kb, int vx, int acc, bool adj, bool flush,
+                     dim3 grid, dim3 block, hipStream_t st) {
   switch (kb) {
-    case 1: launch_e_kb<T, 1>(A, acc, adj, flush, grid, block, st); break;
-    case 2: launch_e_kb<T, 2>(A, acc, adj, flush, grid, block, st); break;
-    case 4: launch_e_kb<T, 4>(A, acc, adj, flush, grid, block, st); break;
-    default: launch_e_kb<T, 8>(A, acc, adj, flush, grid, block, st);
+    case 1: launch_e_kb<T, 1>(A, vx, acc, adj, flush, grid, block, st); break;
+    case 2: launch_e_kb<T, 2>(A, vx, acc, adj, flush, grid, block, st); break;
+    case 4: launch_e_kb<T, 4>(A, vx, acc, adj, flush, grid, block, st); break;
+    default: launch_e_kb<T, 8>(A, vx, acc, adj, flush, grid, block, st);
   }
-}
-
-template <typename T, int KB>
-static void launch_inject_kb(const InjArgs<T> &I, int acc, bool adj, hipStream_t st) {
-  const dim3 grid((I.ntg + 63) / 64), block(64);
-#define FWD_INJ(ACCV)                                                                         \
-  do {                                                                                        \
-    if (adj) hipLaunchKernelGGL((k_inject<T, ACCV, true, KB>), grid, block, 0, st, I);        \
-    else hipLaunchKernelGGL((k_inject<T, ACCV, false, KB>), grid, block, 0, st, I);           \
-  } while (0)
-  switch (acc) {
-    case FWD_ACC_F64: FWD_INJ(ACC_F64); break;
-    case FWD_ACC_KAHAN: FWD_INJ(ACC_KAHAN); break;
-    case FWD_ACC_F32: FWD_INJ(ACC_F32); break;
-    default: hipLaunchKernelGGL((k_inject<T, ACC_NONE, false, 1>), grid, block, 0, st, I);
-  }
-#undef FWD_INJ
 }
 
 template <typename T>
-static void launch_inject(const InjArgs<T> &I, int kb, int acc, bool adj, hipStream_t st) {
-  switch (kb) {
-    case 1: launch_inject_kb<T, 1>(I, acc, adj, st); break;
-    case 2: launch_inject_kb<T, 2>(I, acc, adj, st); break;
-    case 4: launch_inject_kb<T, 4>(I, acc, adj, st); break;
-    default: launch_inject_kb<T, 8>(I, acc, adj, st);
-  }
+static void launch_h(const StepArgs<T> &A, int vx, dim3 grid, dim3 block, hipStream_t st) {
+  constexpr int VV = (int)(16 / sizeof(T));
+  if (vx == 1) hipLaunchKernelGGL((k_update_h<T, 1>), grid, block, 0, st, A);
+  else hipLaunchKernelGGL((k_update_h<T, VV>), grid, block, 0, st, A);
 }
 
-// enqueue one step; if ev != nullptr, record ev[0..4] around the 4 kernels
+// enqueue one step (H update, E update); if ev != nullptr, record ev[0..2]
+// around the two kernels
 template <typename T>
 static void enqueue_step(Plan &p, Dev &d, const WS &w, void *vol, bool adj, hipStream_t st,
                          hipEvent_t *ev) {
   StepArgs<T> A = make_args<T>(p, d, w, vol, adj);
   const dim3 block(p.bx, p.by), grid(A.nblocks);
-  const int64_t F = A.F;
-  T *fields = static_cast<T *>(w.fields);
-  const int nn = (int)p.rn_c.size();
   if (ev) (void)hipEventRecord(ev[0], st);
-  hipLaunchKernelGGL((k_update_h<T>), grid, block, 0, st, A);
+  launch_h<T>(A, p.vx, grid, block, st);
   if (ev) (void)hipEventRecord(ev[1], st);
-  {
-    InjArgs<T> I{};
-    I.nt = p.nt;
-    I.ns = p.ns;
-    I.nn = nn;
-    I.nf = p.nf();
-    I.fields = fields;
-    I.F = F;
-    I.ce0 = static_cast<const T *>(d.ce[0]);
-    I.ce1 = static_cast<const T *>(d.ce[1]);
-    I.ce2 = static_cast<const T *>(d.ce[2]);
-    I.step = w.step;
-    I.flushed = w.flushed;
-    I.vol = vol;
-    I.zE = d.zE;
-    I.Q = d.Q;
-    I.gedge = adj ? w.gedge : nullptr;
-    if (!adj) {
-      I.ntg = (int)p.src_tg.size();
-      I.nrow = 1;
-      I.tg_s = d.src_s;
-      I.tg_c = d.src_c;
-      I.tg_toff = d.src_toff;
-      I.tg_idx = d.src_idx;
-      I.coef = d.src_coef;
-      I.Ftab = d.wavelet;
-    } else {
-      I.ntg = nn;
-      I.nrow = 2 * p.nf();
-      I.tg_c = d.rn_c;
-      I.tg_idx = d.rn_idx;
-      I.coef = d.at_coef;
-      I.Ftab = d.basis;
-    }
-    launch_inject<T>(I, p.kb, vol ? p.acc : -1, adj, st);
-  }
+  launch_e<T>(A, p.kb, p.vx, p.acc, adj, false, grid, block, st);
   if (ev) (void)hipEventRecord(ev[2], st);
-  launch_e<T>(A, p.kb, p.acc, adj, false, grid, block, st);
-  if (ev) (void)hipEventRecord(ev[3], st);
-  const int nrt = p.ns * nn;
-  hipLaunchKernelGGL((k_rec_dft<T>), dim3((nrt + 63) / 64), dim3(64), 0, st, p.ns, nn, d.rn_c,
-                     d.rn_idx, (const T *)fields, F, p.nf(), d.zE, w.racc, (const int *)w.step);
-  if (ev) (void)hipEventRecord(ev[4], st);
 }
 
 template <typename T>
 static void flush_t(Plan &p, Dev &d, const WS &w, void *vol, bool adj, hipStream_t st) {
   if (p.kb == 1 || !vol) return;
+  build_lists(p, d);
   StepArgs<T> A = make_args<T>(p, d, w, vol, adj);
-  launch_e<T>(A, p.kb, p.acc, adj, true, dim3(A.nblocks), dim3(p.bx, p.by), st);
+  launch_e<T>(A, p.kb, 1, p.acc, adj, true, dim3((p.NX + 63) / 64, p.NY, p.NZ), dim3(64), st);
   hipLaunchKernelGGL(k_set_flushed, dim3(1), dim3(64), 0, st, w.flushed, (const int *)w.step);
   HIP_CHECK(hipGetLastError());
 }
@@ -992,6 +1167,7 @@ static void flush_any(Plan &p, Dev &d, const WS &w, void *vol, bool adj, hipStre
 template <typename T>
 static void run_steps_t(Plan &p, Dev &d, const WS &w, void *vol, bool adj, int nsteps,
                         hipStream_t st) {
+  build_lists(p, d);
   const int K = p.graph_steps;
   const int sample = d.sample_every;
   // eager launches of m steps, each bracketed by events if asked
@@ -999,13 +1175,13 @@ static void run_steps_t(Plan &p, Dev &d, const WS &w, void *vol, bool adj, int n
     for (int t = 0; t < m; ++t) {
       hipEvent_t *ev = nullptr;
       if (timed) {
-        const size_t need = (size_t)(d.kstat_n + 1) * 5;
+        const size_t need = (size_t)(d.kstat_n + 1) * 3;
         while (d.ev.size() < need) {
           hipEvent_t e;
           HIP_CHECK(hipEventCreate(&e));
           d.ev.push_back(e);
         }
-        ev = &d.ev[(size_t)d.kstat_n * 5];
+        ev = &d.ev[(size_t)d.kstat_n * 3];
         d.kstat_n++;
       }
       enqueue_step<T>(p, d, w, vol, adj, st, ev);
@@ -1018,18 +1194,24 @@ static void run_steps_t(Plan &p, Dev &d, const WS &w, void *vol, bool adj, int n
   }
   // graph of K steps, captured on a private stream and replayed on st
   char key[256];
-  snprintf(key, sizeof key, "%p/%p/%d/%d/%d/%d/%d/%d/%llu/%llu", w.fields, vol, (int)adj, K, p.bx,
-           p.by, p.xcd, p.kb, (unsigned long long)p.model_version,
+  snprintf(key, sizeof key, "%p/%p/%d/%d/%d/%d/%d/%d/%d/%llu/%llu", w.fields, vol, (int)adj, K,
+           p.bx, p.by, p.xcd, p.kb, p.vx, (unsigned long long)p.model_version,
            (unsigned long long)p.basis_version);
   if (!d.exec || d.exec_key != key) {
     if (d.exec) {
       HIP_CHECK(hipGraphExecDestroy(d.exec));
       d.exec = nullptr;
     }
-    hipGraph_t g;
+    hipGraph_t g = nullptr;
     HIP_CHECK(hipStreamBeginCapture(d.cap, hipStreamCaptureModeRelaxed));
     for (int t = 0; t < K; ++t) enqueue_step<T>(p, d, w, vol, adj, d.cap, nullptr);
-    HIP_CHECK(hipStreamEndCapture(d.cap, &g));
+    const hipError_t le = hipGetLastError();
+    const hipError_t ce = hipStreamEndCapture(d.cap, &g);   // always end the capture
+    if (le != hipSuccess || ce != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      fail(FWD_ERR_HIP, std::string("graph capture failed: ") +
+                            hipGetErrorString(le != hipSuccess ? le : ce));
+    }
     HIP_CHECK(hipGraphInstantiate(&d.exec, g, nullptr, nullptr, 0));
     HIP_CHECK(hipGraphDestroy(g));
     d.exec_key = key;
@@ -1060,16 +1242,16 @@ static void run_steps_any(Plan &p, Dev &d, const WS &w, void *vol, bool adj, int
 }
 
 static void collect_kernel_stats(Dev &d) {
-  double tot[4] = {0, 0, 0, 0};
+  double tot[2] = {0, 0};
   for (int s = 0; s < d.kstat_n; ++s) {
-    hipEvent_t *ev = &d.ev[(size_t)s * 5];
-    for (int k = 0; k < 4; ++k) {
+    hipEvent_t *ev = &d.ev[(size_t)s * 3];
+    for (int k = 0; k < 2; ++k) {
       float ms = 0;
       HIP_CHECK(hipEventElapsedTime(&ms, ev[k], ev[k + 1]));
       tot[k] += ms;
     }
   }
-  for (int k = 0; k < 4; ++k) d.kstat_ms[k] = d.kstat_n ? tot[k] / d.kstat_n : 0.0;
+  for (int k = 0; k < 2; ++k) d.kstat_ms[k] = d.kstat_n ? tot[k] / d.kstat_n : 0.0;
 }
 
 static void zero_state(Plan &p, const WS &w, void *ws, void *vol, int mode, hipStream_t st) {
@@ -1256,19 +1438,23 @@ double dev_autotune(Plan &p, void *ws, size_t ws_bytes, void *vol, size_t vol_by
   ensure_tables(p, st);
   Dev &d = D(p);
   WS w = carve(p, ws);
-  const int cand[][2] = {{64, 4}, {64, 2}, {128, 2}, {128, 1}, {256, 1}, {64, 1}};
-  const int save_bx = p.bx, save_by = p.by, save_xcd = p.xcd, save_sample = d.sample_every;
+  const int cand[][2] = {{64, 4}, {64, 2}, {64, 1}, {32, 8}, {32, 4}, {32, 2}, {16, 16},
+                         {16, 4}, {128, 2}, {128, 1}, {256, 1}};
+  const int save_bx = p.bx, save_by = p.by, save_xcd = p.xcd, save_vx = p.vx,
+            save_sample = d.sample_every;
   d.sample_every = 0;
   double best = 1e300;
-  int bbx = save_bx, bby = save_by, bxcd = save_xcd;
+  int bbx = save_bx, bby = save_by, bxcd = save_xcd, bvx = save_vx;
   hipEvent_t e0, e1;
   HIP_CHECK(hipEventCreate(&e0));
   HIP_CHECK(hipEventCreate(&e1));
-  for (auto &c : cand) {
+  for (auto &c : cand)
+  for (int vx = 0; vx <= 1; ++vx) {
     for (int xc = 0; xc <= 1; ++xc) {
       p.bx = c[0];
       p.by = c[1];
       p.xcd = xc;
+      p.vx = vx ? 4 : 1;
       zero_state(p, w, ws, adj ? nullptr : vol, mode, st);
       run_steps_any(p, d, w, vol, adj, 4, st);   // warm-up (graph capture)
       HIP_CHECK(hipEventRecord(e0, st));
@@ -1283,6 +1469,7 @@ double dev_autotune(Plan &p, void *ws, size_t ws_bytes, void *vol, size_t vol_by
         bbx = c[0];
         bby = c[1];
         bxcd = xc;
+        bvx = p.vx;
       }
     }
   }
@@ -1291,6 +1478,7 @@ double dev_autotune(Plan &p, void *ws, size_t ws_bytes, void *vol, size_t vol_by
   p.bx = bbx;
   p.by = bby;
   p.xcd = bxcd;
+  p.vx = bvx;
   d.sample_every = save_sample;
   return best;
 }
@@ -1298,14 +1486,14 @@ double dev_autotune(Plan &p, void *ws, size_t ws_bytes, void *vol, size_t vol_by
 // option plumbing for the sampled timing lives with the device state
 void dev_set_sampling(Plan &p, int every) { D(p).sample_every = every; }
 int dev_get_sampling(Plan &p) { return p.dev ? D(p).sample_every : 0; }
-void dev_kernel_stats(Plan &p, double *ms4, int *count) {
+void dev_kernel_stats(Plan &p, double *ms2, int *count) {
   if (!p.dev) {
-    for (int k = 0; k < 4; ++k) ms4[k] = 0;
+    for (int k = 0; k < 2; ++k) ms2[k] = 0;
     *count = 0;
     return;
   }
   Dev &d = D(p);
-  for (int k = 0; k < 4; ++k) ms4[k] = d.kstat_ms[k];
+  for (int k = 0; k < 2; ++k) ms2[k] = d.kstat_ms[k];
   *count = d.kstat_n;
 }
 

@@ -100,8 +100,9 @@ struct Plan {
   int basis_iters = 0;
 
   // ---- options ----
-  int graph_steps = 32, bx = 64, by = 4, xcd = 1, strict_cfl = 1;
+  int graph_steps = 32, bx = 64, by = 4, xcd = 1, strict_cfl = 1;   // bx: threads along x
   int kb = 8;                            // samples per volume-transform block (1, 2, 4, 8)
+  int vx = 1;                            // 1: one x node per thread; 4: a 16-byte vector
 
   // ---- device side (managed in device.hip) ----
   void *dev = nullptr;
@@ -149,7 +150,7 @@ double dev_autotune(Plan &p, void *ws, size_t ws_bytes, void *vol, size_t vol_by
                     int mode, int steps, void *stream);
 void dev_set_sampling(Plan &p, int every);
 int dev_get_sampling(Plan &p);
-void dev_kernel_stats(Plan &p, double *ms4, int *count);
+void dev_kernel_stats(Plan &p, double *ms2, int *count);
 
 }  // namespace fwdem
 

@@ -113,7 +113,7 @@ def test_batched_equals_single_sources(dtype):
         assert same(Eb[s], E1[0])
 
 
-def test_graph_replay_equals_eager_and_repeatable():
+def test_graph_replay_equals_eager_and_repeatable():  # noqa: D103
     w = tiny(seed=6, npml=3, ns=2)
     say("graph vs eager")
     _, E1, _ = gpu_forward(w, "f32", "f64", graph_steps=16)
@@ -300,3 +300,44 @@ def test_flush_midway_then_continue():
     V = p.volume_export(vol).cpu().numpy()
     assert rel(V, ref) < 1e-13
     assert same(p.run_receivers().cpu().numpy(), E_full.cpu().numpy())
+
+
+# --------------------------------------------------------------------------
+# tiling and autotuning: the arithmetic of a cell does not depend on them
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("adjoint", [False, True])
+def test_tilings_are_bitwise_identical(adjoint):
+    w0, d = _inverse_problem(seed=6, ns=2)
+    say(f"tilings adjoint={adjoint}")
+    results = []
+    for (by, bx, xcd, vx) in [(4, 64, 1, 1), (1, 64, 0, 4), (2, 128, 1, 4), (1, 256, 0, 1),
+                              (16, 16, 1, 4), (8, 32, 0, 1)]:
+        p = fw.Plan.from_workload(w0, field_dtype="f32", acc_mode="kahan")
+        for key, v in (("BLOCK_Y", by), ("BLOCK_X", bx), ("XCD_REMAP", xcd), ("VECTOR", vx)):
+            p.set_option(getattr(fw, "FWD_OPT_" + key), v)
+        p.set_model(w0.rho)
+        E, vol = p.forward(want_volume=True)
+        out = [E.cpu().numpy(), p.volume_export(vol).cpu().numpy()]
+        if adjoint:
+            p.basis_build(gamma_rel=1e-12)
+            g, Ea = p.adjoint(vol, torch.from_numpy(d).cuda() - E, want_adjoint_rec=True)
+            out += [g.cpu().numpy(), Ea.cpu().numpy()]
+        results.append(out)
+    for r in results[1:]:
+        for a, b in zip(results[0], r):
+            assert same(a, b)
+
+
+def test_autotune_keeps_results():
+    w = with_window(c2_marine1d(), 64)
+    say("autotune on the marine grid (64-step window)")
+    p = fw.Plan.from_workload(w, field_dtype="f32")
+    p.set_model(w.rho)
+    E0, vol = p.forward(want_volume=True)
+    E0 = E0.cpu().numpy()
+    ms = p.autotune(fw.FWD_MODE_FORWARD, vol=vol, steps=8)
+    assert ms > 0
+    cfg = [p.get_option(getattr(fw, "FWD_OPT_" + k)) for k in ("BLOCK_X", "BLOCK_Y", "XCD_REMAP", "VECTOR")]
+    say(f"autotuned: block {cfg[0]:.0f}x{cfg[1]:.0f}, xcd {cfg[2]:.0f}, vector {cfg[3]:.0f}: {ms:.4f} ms/step")
+    E1 = p.forward(vol=vol, want_volume=True)[0].cpu().numpy()
+    assert same(E0, E1)
