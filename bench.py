@@ -77,6 +77,35 @@ def cpu_baseline(w, steps=400):
                       f"one process ({dt:.1f} s); host {os.cpu_count()} logical CPUs"}
 
 
+TILING_KEYS = ("BLOCK_X", "BLOCK_Y", "XCD_REMAP", "VECTOR")
+
+
+def set_tiling(plan, spec):
+    from paper_2211_16665_amd import fwdem as fw
+    if spec:
+        for key, v in zip(TILING_KEYS, spec.split(",")):
+            plan.set_option(getattr(fw, "FWD_OPT_" + key), int(v))
+
+
+def measured_traffic(kernel_tag):
+    """HBM bytes per launch of a kernel from the committed counter summary
+    (profiles/), or None if the device source changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "pmc_marine1d_e_update.md")
+    src = os.path.join(ROOT, "paper_2211_16665_amd", "csrc", "device.hip")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and line.startswith("- "):
+            k, v = line[2:].split(":", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if vals.get("device_source_sha256") != sha or vals.get("kernel") != kernel_tag:
+        return None
+    return float(vals["traffic_bytes_per_launch"]), vals.get("tiling", "")
+
+
 def profile_mode(args, w_true):
     """A short run for hardware-counter collection: one elementwise kernel of
     a known size (256 MiB read + 256 MiB written, the calibration of the byte
@@ -93,6 +122,7 @@ def profile_mode(args, w_true):
     w = w_true.replace(nt=args.profile_steps)
     plan = fw.Plan.from_workload(w, field_dtype=args.field_dtype, acc_mode=args.acc)
     plan.set_option(fw.FWD_OPT_GRAPH_STEPS, 0)
+    set_tiling(plan, args.tiling)
     plan.set_model(w.rho)
     plan.basis_build(gamma_rel=1e-12)
     E, vol = plan.forward(want_volume=True)
@@ -111,6 +141,8 @@ def main():
     ap.add_argument("--field-dtype", default="f32")
     ap.add_argument("--acc", default="f64")
     ap.add_argument("--sample-every", type=int, default=2048)
+    ap.add_argument("--tiling", default="",
+                    help="fixed tiling instead of autotuning: block_x,block_y,xcd_remap,vector")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="counter-collection mode: a 256 MiB device copy (calibration of the "
                          "byte counters) then this many forward and adjoint steps of the "
@@ -139,7 +171,11 @@ def main():
     d_obs = plan.forward()                               # data of the true model (untimed)
     vol = plan.volume_buffer()
     # tile/schedule autotuning on this workload (untimed setup)
-    tune_ms = plan.autotune(fw.FWD_MODE_FORWARD, vol=vol, steps=32)
+    if args.tiling:
+        set_tiling(plan, args.tiling)
+        tune_ms = float("nan")
+    else:
+        tune_ms = plan.autotune(fw.FWD_MODE_FORWARD, vol=vol, steps=32)
     tuned = {k.lower(): int(plan.get_option(getattr(fw, "FWD_OPT_" + k)))
              for k in ("BLOCK_X", "BLOCK_Y", "XCD_REMAP", "DFT_BLOCK", "VECTOR")}
     tuned["ms_per_forward_step"] = tune_ms
@@ -185,6 +221,10 @@ def main():
                                                  tsize, accsize, kb)
     e_ms, n_samp = avg("fwd", 1)
     achieved = bytes_e / (e_ms * 1e-3) / 1e9
+    tiling = ",".join(str(tuned[k.lower()]) for k in TILING_KEYS)
+    kernel_tag = f"k_update_e<float,F64,fwd,{kb}>"
+    mt = measured_traffic(kernel_tag) if args.field_dtype == "f32" and args.acc == "f64" else None
+    traffic, traffic_tiling = mt if mt else (None, None)
     kern = {name: {"fwd_ms": avg("fwd", k)[0], "adj_ms": avg("adj", k)[0]}
             for k, name in enumerate(("update_h", "update_e"))}
     out = {
@@ -208,8 +248,8 @@ def main():
                    "field_dtype": args.field_dtype, "accumulators": args.acc,
                    "basis_fit": info.basis_fit, "tuning": tuned},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": f"k_update_e (forward, volume transform fused, block {kb})",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": kernel_tag, "tiling": tiling, "traffic_tiling": traffic_tiling,
                      "bytes_per_launch": bytes_e, "avg_launch_ms": e_ms, "samples": n_samp},
         "kernels_ms": kern,
     }
