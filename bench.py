@@ -14,6 +14,8 @@ roofline: the forward E-update kernel (fused with the volume transform),
 its algorithmic bytes per launch over its average device time measured with
 HIP events on sampled steps inside the timed region.  cpu_baseline: the CPU
 oracle stepping the same grid for a bounded window of steps.
+batched_vs_plain: gradient time of the 16-source batched workload on a
+window, one batched plan against one single-source plan per source.
 """
 from __future__ import annotations
 
@@ -106,6 +108,60 @@ def measured_traffic(kernel_tag):
     return float(vals["traffic_bytes_per_launch"]), vals.get("tiling", "")
 
 
+def batched_vs_plain(window=200):
+    """Gradient time (forward with volume transform + adjoint) of the 16-source
+    batched workload over a window of steps: all sources in one plan with
+    graph replay, against the plain path of one single-source plan per source
+    run one after the other with eager launches; FP32 fields, FP64
+    accumulators, default tiling.  Also the largest relative gradient
+    difference between the two (the same arithmetic per source: 0)."""
+    import torch
+    from paper_2211_16665_amd import fwdem as fw
+    from workloads import c4_batched, with_window
+    w = with_window(c4_batched(), window)
+
+    def gradient(plan, vol, grad):
+        E, _ = plan.forward(vol=vol, want_volume=True)
+        plan.adjoint(vol, -E, grad=grad, accumulate=True)
+
+    p = fw.Plan.from_workload(w, field_dtype="f32", acc_mode="f64")
+    p.set_model(w.rho)
+    p.basis_build(gamma_rel=1e-12)
+    vol = p.volume_buffer()
+    g_b = torch.zeros(p.shape, dtype=torch.float64, device="cuda")
+    gradient(p, vol, g_b)                        # warm-up (tables, graph capture)
+    g_b.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gradient(p, vol, g_b)
+    torch.cuda.synchronize()
+    t_batched = time.perf_counter() - t0
+    del vol
+    plans = []
+    for s in range(w.ns):
+        ws = w.replace(src_pos=w.src_pos[s:s + 1], src_mom=w.src_mom[s:s + 1])
+        q = fw.Plan.from_workload(ws, field_dtype="f32", acc_mode="f64")
+        q.set_option(fw.FWD_OPT_GRAPH_STEPS, 0)
+        q.set_model(ws.rho)
+        q.basis_build(gamma_rel=1e-12)
+        plans.append((q, q.volume_buffer()))
+    g_p = torch.zeros_like(g_b)
+    gradient(*plans[0], torch.zeros_like(g_b))   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for q, v in plans:
+        gradient(q, v, g_p)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    diff = float((g_b - g_p).abs().max() / g_p.abs().max())
+    nz, ny, nx = p.shape
+    return {"workload": f"c4_batched window: {nx}x{ny}x{nz}, {w.ns} sources, {len(w.freqs)} freqs, "
+                        f"{window} forward + {window} adjoint steps",
+            "batched_s": t_batched, "plain_s": t_plain, "speedup": t_plain / t_batched,
+            "batched_mcell_per_s": 2 * w.ns * nx * ny * nz * window / t_batched / 1e6,
+            "max_rel_grad_diff": diff}
+
+
 def profile_mode(args, w_true):
     """A short run for hardware-counter collection: one elementwise kernel of
     a known size (256 MiB read + 256 MiB written, the calibration of the byte
@@ -141,6 +197,8 @@ def main():
     ap.add_argument("--field-dtype", default="f32")
     ap.add_argument("--acc", default="f64")
     ap.add_argument("--sample-every", type=int, default=2048)
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched-vs-plain gradient-time comparison")
     ap.add_argument("--tiling", default="",
                     help="fixed tiling instead of autotuning: block_x,block_y,xcd_remap,vector")
     ap.add_argument("--profile-steps", type=int, default=0,
@@ -253,6 +311,10 @@ def main():
                      "bytes_per_launch": bytes_e, "avg_launch_ms": e_ms, "samples": n_samp},
         "kernels_ms": kern,
     }
+    if not args.no_batched:
+        del vol, grad
+        torch.cuda.empty_cache()
+        out["batched_vs_plain"] = batched_vs_plain()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w_true)
     print(json.dumps(out), flush=True)

@@ -1,17 +1,22 @@
 """Full-size GPU checks of the five workloads, by properties that hold at any
 size (the CPU oracle cannot run them to completion; it is matched on windows
-and small grids in test_gpu_parity.py):
+and small grids in test_gpu_parity.py).  Receiver transforms always
+accumulate in FP64; the accumulator mode selects the type of the volume
+transform, so accumulator checks compare exported volumes.
 
-  * marine 1D (101x101x61, 45,758 steps): FP32 fields against FP64 fields,
-    per receiver and frequency, for each accumulator mode;
+  * marine 1D (101x101x61, 45,758 steps): FP32 fields against FP64 fields at
+    every receiver and frequency; over the whole run, the volume transform
+    with compensated-FP32 and FP32 accumulators against FP64 accumulators
+    (same FP32 fields);
   * three blocks (128x128x96): the FP64 gradient from FictitiousForward
     (with forward snapshots every 200 steps) against central finite
     differences on 10 random interior cells, and the FP32 gradient against
     the FP64 one;
   * batched (200x200x100, 16 sources): FP32 against FP64 per frequency on a
     window, batch against a single-source run;
-  * large (400x400x200, ~32M cells, 8 frequencies): compensated-FP32 and FP32
-    accumulators against FP64 accumulators on a window, 8 of the 32 sources.
+  * large (400x400x200, ~32M cells, 8 frequencies): the volume transform with
+    compensated-FP32 and FP32 accumulators against FP64 accumulators on a
+    2000-step window of one source.
 """
 import numpy as np
 import pytest
@@ -45,16 +50,47 @@ def receiver_errors(E, ref):
     return np.abs(E - ref) / scale
 
 
-@pytest.mark.parametrize("acc,tol", [("f64", 1e-4), ("kahan", 1e-4), ("f32", 1e-3)])
-def test_marine_full_run_fp32_fields(acc, tol):
+def volume_errors(v, ref):
+    """Largest |v - ref| relative to the largest |ref| of the same source,
+    frequency and component, and largest pointwise relative error over the
+    nodes where |ref| is above 1e-3 of that maximum."""
+    scale = ref.abs().amax(dim=(3, 4, 5), keepdim=True)
+    d = (v - ref).abs()
+    glob = float((d / scale).max())
+    mask = ref.abs() > 1e-3 * scale
+    point = float((d[mask] / ref.abs()[mask]).max())
+    return glob, point
+
+
+def test_marine_full_run_fp32_fields():
     w = c2_marine1d()
-    say(f"marine full run: fp32 fields, {acc} accumulators, against fp64")
+    say("marine full run: fp32 fields against fp64 at the receivers")
     _, E64, _ = forward(w, "f64", "f64")
-    _, E32, _ = forward(w, "f32", acc)
+    _, E32, _ = forward(w, "f32", "f64")
     err = receiver_errors(E32, E64)
     for k, f in enumerate(w.freqs):
         say(f"  {f:.2f} Hz: max {err[..., k].max():.2e}, median {np.median(err[..., k]):.2e}")
-    assert err.max() < tol
+    assert err.max() < 1e-4
+
+
+def accumulator_study(w, tol_kahan, tol_f32):
+    vols = {}
+    for acc in ("f64", "kahan", "f32"):
+        p, _, vol = forward(w, "f32", acc, volume=True)
+        vols[acc] = p.volume_export(vol)
+        del p, vol
+        torch.cuda.empty_cache()
+    ref = vols.pop("f64")
+    for acc, tol in (("kahan", tol_kahan), ("f32", tol_f32)):
+        glob, point = volume_errors(vols[acc], ref)
+        say(f"  {acc} against f64 accumulators: max {glob:.2e} of the maximum, "
+            f"pointwise {point:.2e} above 1e-3 of it")
+        assert glob < tol and point < 100 * tol
+
+
+def test_marine_full_run_accumulators():
+    say("marine full run: volume transform per accumulator mode, fp32 fields")
+    accumulator_study(c2_marine1d(), 1e-7, 1e-5)
 
 
 def _blocks_problem():
@@ -138,20 +174,6 @@ def test_batched_window_fp32_and_single_source():
 
 def test_large_window_accumulators():
     w = c5_large()
-    w = with_window(w.replace(src_pos=w.src_pos[:8], src_mom=w.src_mom[:8]), 40)
-    say("large grid (~32M cells), 8 sources, 40-step window: accumulator modes")
-    out = {}
-    for acc in ("f64", "kahan", "f32"):
-        p, E, vol = forward(w, "f32", acc, volume=True)
-        out[acc] = E
-        del p, vol
-        torch.cuda.empty_cache()
-    ref = out["f64"]
-    # after 40 steps the far receivers still see exactly zero: compare per
-    # source and frequency against the largest value of the window
-    scale = np.abs(ref).max(axis=(1, 2), keepdims=True)
-    assert np.all(scale > 0)
-    for acc in ("kahan", "f32"):
-        err = np.abs(out[acc] - ref) / scale
-        say(f"  {acc} against f64 accumulators: max {err.max():.2e}")
-        assert err.max() < (1e-5 if acc == "kahan" else 1e-3)
+    w = with_window(w.replace(src_pos=w.src_pos[:1], src_mom=w.src_mom[:1]), 2000)
+    say("large grid (~32M cells), 1 source, 2000-step window: volume per accumulator mode")
+    accumulator_study(w, 1e-7, 1e-5)
