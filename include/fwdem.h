@@ -167,9 +167,10 @@ fwd_status fwd_run_receivers(fwd_plan *plan, void *ws_dev, double *E_rec_dev,
  * already added are not added again.  fwd_forward does this itself. */
 fwd_status fwd_run_flush(fwd_plan *plan, void *ws_dev, void *vol_dev, void *stream);
 
-/* Snapshot of the forward state (fields, CPML memory, receiver sums, step
- * index, transform-block history; the volume transform when vol_dev is given): fwd_checkpoint_size
- * bytes of caller memory (device) per snapshot. */
+/* Snapshot of the forward state (both halves of the double-buffered fields
+ * and CPML memory, receiver sums, step index, transform-block history; the
+ * volume transform when vol_dev is given): fwd_checkpoint_size bytes of
+ * caller memory (device) per snapshot. */
 fwd_status fwd_checkpoint_size(const fwd_plan *plan, int with_volume, size_t *bytes);
 fwd_status fwd_checkpoint_save(fwd_plan *plan, const void *ws_dev, const void *vol_dev,
                                void *snap_dev, void *stream);
@@ -232,16 +233,24 @@ enum {
                                 holds the last two samples; the others wait in a history buffer
                                 of the workspace.  Changes only the order of the sums.  Set it
                                 before fwd_workspace_size. */
-  FWD_OPT_VECTOR = 7         /* 1 (default): each stencil thread updates one x node; 4: a
-                                16-byte vector of consecutive x nodes (4 in FP32, 2 in FP64) */
+  FWD_OPT_VECTOR = 7,        /* 1 (default): each stencil thread updates one x node; 4: a
+                                16-byte vector of consecutive x nodes (4 in FP32, 2 in FP64);
+                                two-kernel schedule only */
+  FWD_OPT_SCHEDULE = 8,      /* 0 (default): two launches per step (H update, then E update);
+                                1: one fused launch per step -- each block owns a block_x x
+                                block_y column tile and a chunk of FWD_OPT_ZCHUNK planes, stages
+                                E and H planes with their halo in LDS and marches up in z,
+                                recomputing the H halo of its tile.  Same arithmetic per edge:
+                                results equal those of schedule 0 bit for bit */
+  FWD_OPT_ZCHUNK = 9         /* planes per block of the fused schedule: 1 .. 64 (default 8) */
 };
 fwd_status fwd_set_option(fwd_plan *plan, int key, double value);
 fwd_status fwd_get_option(const fwd_plan *plan, int key, double *value);
 
-/* Self-written tile/schedule autotuner: times every candidate (block shape,
- * vector width, XCD remap) for a few steps of the given mode on the given buffers, keeps
- * the fastest and returns its time per step (ms).  The state in ws/vol is
- * clobbered.  */
+/* Self-written tile/schedule autotuner: times every candidate (schedule,
+ * block shape, vector width or planes per block, XCD remap) for a few steps
+ * of the given mode on the given buffers, keeps the fastest and returns its
+ * time per step (ms).  The state in ws/vol is clobbered.  */
 fwd_status fwd_autotune(fwd_plan *plan, void *ws_dev, size_t ws_bytes,
                         void *vol_dev, size_t vol_bytes, int mode, int steps,
                         double *best_ms, void *stream);
@@ -255,7 +264,8 @@ fwd_status fwd_last_timing(const fwd_plan *plan, double *ms, int *steps);
  * E update fused with injection, receiver transform and volume transform or
  * gradient product -- over the steps sampled in the last fwd_forward /
  * fwd_adjoint (FWD_OPT_SAMPLE_EVERY > 0), measured with HIP events on the
- * caller's stream.  avg_ms has room for 2 values. */
+ * caller's stream.  With the fused schedule the first value is 0 and the
+ * second is the one launch of the step.  avg_ms has room for 2 values. */
 fwd_status fwd_kernel_stats(const fwd_plan *plan, double *avg_ms, int *samples);
 
 const char *fwd_last_error(void);

@@ -266,6 +266,14 @@ fwd_status fwd_set_option(fwd_plan *h, int key, double value) {
         if (v != 1 && v != 4) fail(FWD_ERR_INVALID_ARG, "vector option in {1, 4}");
         p.vx = v;
         break;
+      case FWD_OPT_SCHEDULE:
+        if (v != 0 && v != 1) fail(FWD_ERR_INVALID_ARG, "schedule option in {0, 1}");
+        p.sched = v;
+        break;
+      case FWD_OPT_ZCHUNK:
+        if (v < 1 || v > 64) fail(FWD_ERR_INVALID_ARG, "planes per block in [1, 64]");
+        p.kz = v;
+        break;
       default:
         fail(FWD_ERR_INVALID_ARG, "unknown option");
     }
@@ -285,6 +293,8 @@ fwd_status fwd_get_option(const fwd_plan *h, int key, double *value) {
       case FWD_OPT_STRICT_CFL: *value = p.strict_cfl; break;
       case FWD_OPT_DFT_BLOCK: *value = p.kb; break;
       case FWD_OPT_VECTOR: *value = p.vx; break;
+      case FWD_OPT_SCHEDULE: *value = p.sched; break;
+      case FWD_OPT_ZCHUNK: *value = p.kz; break;
       default: fail(FWD_ERR_INVALID_ARG, "unknown option");
     }
   });

@@ -1,23 +1,31 @@
 // Device side of the fictitious-wave-domain engine for gfx950 (MI355X).
 //
-// One leapfrog step (Section 2, eq. fictitiouswave) is two launches on the
-// caller's stream:
-//   k_update_h   H^{n+1/2} = H^{n-1/2} - dt/mu curl E^n                + CPML
-//   k_update_e   E^{n+1} = E^n + dt/eps (curl H^{n+1/2} - J'^{n+1/2})  + CPML
-//                fused with the injection of J' at the source (or
-//                adjoint-source) edges, the receiver transform, and the
-//                volume transform acc_k += E z_k (eq. dft) in the forward
-//                run or the on-the-fly gradient product in the adjoint run
-// The step index lives in device memory (incremented by k_update_h), so a
-// captured HIP graph of K steps replays for any position in the run.
+// One leapfrog step (Section 2, eq. fictitiouswave) computes
+//   H^{n+1/2} = H^{n-1/2} - dt/mu curl E^n                + CPML
+//   E^{n+1}   = E^n + dt/eps (curl H^{n+1/2} - J'^{n+1/2}) + CPML
+// fused with the injection of J' at the source (or adjoint-source) edges,
+// the receiver transform, and the volume transform acc_k += E z_k (eq. dft)
+// in the forward run or the on-the-fly gradient product in the adjoint run.
+// Two schedules carry out the same arithmetic per edge:
+//   two kernels  k_update_h then k_update_e, one thread per (i, j, k) node
+//                (or per 16-byte vector of x nodes);
+//   fused        k_step, one launch per step: a block owns a column tile and
+//                a chunk of z planes, stages each E plane (with a one-node
+//                halo) and the new H plane (with its low-side halo) in LDS,
+//                recomputes the H halo of its tile and marches up in z with
+//                the plane below carried in registers.
+// Fields and CPML memory are double-buffered: step n reads half n % 2 and
+// writes the other half, so no block of a launch reads a value that another
+// block has already overwritten.  The step index lives in device memory and
+// the last block of a step's final launch advances it, so a captured HIP
+// graph of K steps replays for any position in the run.
 //
 // The kernels are bound by memory traffic and latency (a 3D stencil plus an
-// accumulator sweep, ~0.1-0.8 flop/byte): no matrix cores.  Threads own an
-// (i, j) column of the padded layout [k][j][PX] (x fastest, PX a multiple
-// of 64) and handle 16 bytes of consecutive x nodes per field (4 in FP32,
-// 2 in FP64) with vector loads and stores; they loop over the batched sources, so per-edge coefficients are shared by
-// all sources.  A 1D grid is remapped so that consecutive tiles of one XCD
-// are spatial neighbours (their halos hit the same L2).
+// accumulator sweep, ~0.1-0.8 flop/byte): no matrix cores.  Field layout
+// [k][j][PX] (x fastest, PX a multiple of 64).  Threads loop over the batched
+// sources, so per-edge coefficients are shared by all sources.  A 1D grid is
+// remapped so that consecutive tiles of one XCD are spatial neighbours (their
+// halos hit the same L2).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -52,15 +60,18 @@ struct StepArgs {
   int nx, ny, nz, npml, PX, NY, NZ, ns;
   int64_t F;          // elements per field
   int64_t psi_src;    // psi elements per source
-  T *fields;          // [ns][6][F]: Ex Ey Ez Hx Hy Hz
-  T *psi;             // [ns][psi_src]
+  T *fields;          // [2][ns][6][F]: Ex Ey Ez Hx Hy Hz per source, two halves
+  T *psi;             // [2][ns][psi_src]
+  int64_t fbuf, pbuf; // elements per half of fields and of psi
   const T *ce[3];     // dt/eps per edge component
   AxisDev<T> ax[3];
   T dtmu;             // dt / mu0
-  const int *step;    // current step index (device)
-  int *step_w;        // same, written by k_update_h
-  // tiling: (bx x by) threads over x-y, each thread a vector of x nodes
-  int nbx, nby, nbz, nblocks, xcd;
+  const int *step;    // index of the last completed step (device)
+  int *step_w;        // same, advanced by the last block of the step
+  unsigned *done;     // blocks of the current launch that have finished
+  // tiling: (bx x by) threads over x-y; two kernels: one plane per block,
+  // each thread a vector of x nodes; fused: kz planes per block
+  int nbx, nby, nbz, nblocks, xcd, kz;
   // volume transform / gradient
   int nf;
   const double2 *zE;  // [nt][nf] z^{n+1}
@@ -70,10 +81,10 @@ struct StepArgs {
   T *hist;            // [ns][kb-2][3][F] samples of the current transform block
   int64_t hist_src;   // history elements per source
   const int *flushed; // last sample already in the volume transform / gradient
-  // per-thread lists of injection targets and receiver nodes (see TileLists)
+  // per-thread lists of injection targets and receiver nodes (see build_lists)
   const int *tile_tab;  // [nblocks]: offset of the tile's table in tl_off, or -1
   const int *tl_off;    // per listed tile: bx*by + 1 entry offsets
-  const int2 *tl_ent;   // entries: x = c | kind << 2 | s << 3, y = ref
+  const int2 *tl_ent;   // entries: x = c | kind << 2 | sub << 3 | s << 9, y = ref
   int nrow, nt;         // rows of the time-function table, steps
   const double *coef;   // injection coefficients (entry ref = first row)
   const double *Ftab;   // [nrow][nt] time functions (wavelet or basis functions)
@@ -109,6 +120,49 @@ __device__ __forceinline__ bool pml_int(int i, int n, int npml, int &l) {
   if (i < npml) { l = i; return true; }
   if (i > n - npml) { l = i - n + 2 * npml - 1; return true; }
   return false;
+}
+
+// One source's fields and CPML memory slabs in one half of the double
+// buffer.  Slabs: X [4][NZ][NY][W], Y [4][NZ][W][PX], Z [4][W][NY][PX] with
+// W = 2 npml; memory variables 0 and 1 belong to H, 2 and 3 to E (the E
+// ones are updated in place in half 0).
+template <typename T>
+struct Half {
+  T *ex, *ey, *ez, *hx, *hy, *hz;
+  T *psX, *psY, *psZ;
+};
+
+template <typename T>
+__device__ __forceinline__ Half<T> half_of(const StepArgs<T> &A, int par, int s) {
+  Half<T> h;
+  T *f = A.fields + par * A.fbuf + (int64_t)s * 6 * A.F;
+  h.ex = f;
+  h.ey = f + A.F;
+  h.ez = f + 2 * A.F;
+  h.hx = f + 3 * A.F;
+  h.hy = f + 4 * A.F;
+  h.hz = f + 5 * A.F;
+  const int W = 2 * A.npml;
+  const int64_t sX = (int64_t)A.NZ * A.NY * W, sY = (int64_t)A.NZ * W * A.PX;
+  T *ps = A.psi + par * A.pbuf + (int64_t)s * A.psi_src;
+  h.psX = ps;
+  h.psY = ps + 4 * sX;
+  h.psZ = ps + 4 * sX + 4 * sY;
+  return h;
+}
+
+// The last block to finish a step's final launch advances the step index
+// (every block read it at its start, before its own count) and re-arms the
+// block counter for the next launch.
+template <typename T>
+__device__ __forceinline__ void finish_step(const StepArgs<T> &A, int n) {
+  if (threadIdx.x == 0 && threadIdx.y == 0) {
+    const unsigned prev = atomicAdd(A.done, 1u);
+    if (prev + 1u == (unsigned)A.nblocks) {
+      atomicExch(A.done, 0u);
+      atomicExch(A.step_w, n);
+    }
+  }
 }
 
 // Vector of N consecutive x values of a field: N = 1 (one element per
@@ -155,26 +209,106 @@ __device__ __forceinline__ Vec<T, N> vzero() {
   return r;
 }
 
+template <typename T>
+__device__ __forceinline__ Vec<T, 1> vec1(T x) {
+  Vec<T, 1> r;
+  r.v[0] = x;
+  return r;
+}
+
 // ---------------------------------------------------------------------------
-// H update: H^{n+1/2} = H^{n-1/2} - dt/mu (curl E^n)
-//   H_x -= dt/mu (dEz/dy - dEy/dz), H_y -= dt/mu (dEx/dz - dEz/dx),
-//   H_z -= dt/mu (dEy/dx - dEx/dy); forward differences over a cell width.
-// Each thread owns VX consecutive x nodes (one 16-byte vector per field);
-// the x neighbour beyond the vector is one extra element load.  All loads
-// are issued before any store (loads and stores share one in-order
-// completion counter on this GPU).
+// Per-node arithmetic shared by both schedules.  Explicit fused multiply-adds
+// fix the rounding, so both schedules give the same bits whatever the
+// compiler would contract.
+// ---------------------------------------------------------------------------
+// CPML-stretched derivative: psi <- b psi + a d; returns d / kappa + psi
+template <typename T>
+__device__ __forceinline__ T stretch(T d, T &psi, T b, T a, T kinv) {
+  psi = fma(b, psi, a * d);
+  return fma(d, kinv, psi);
+}
+
+// H^{n+1/2} = H^{n-1/2} - dt/mu (d1 - d2), forward differences over a cell
+//   H_x: d1 = dEz/dy, d2 = dEy/dz   H_y: d1 = dEx/dz, d2 = dEz/dx
+//   H_z: d1 = dEy/dx, d2 = dEx/dy
+template <typename T>
+__device__ __forceinline__ T hx_node(const StepArgs<T> &A, int j, int k, T h, T ez, T ez_jp, T ey,
+                                     T ey_kp, bool py, T &psy, bool pz, T &psz) {
+  const AxisDev<T> &Y = A.ax[1], &Z = A.ax[2];
+  T d1 = (ez_jp - ez) * Y.ih[j];
+  T d2 = (ey_kp - ey) * Z.ih[k];
+  if (py) d1 = stretch(d1, psy, Y.bh[j], Y.ah[j], Y.kh[j]);
+  if (pz) d2 = stretch(d2, psz, Z.bh[k], Z.ah[k], Z.kh[k]);
+  return fma(-A.dtmu, d1 - d2, h);
+}
+template <typename T>
+__device__ __forceinline__ T hy_node(const StepArgs<T> &A, int i, int k, T h, T ex, T ex_kp, T ez,
+                                     T ez_ip, bool pz, T &psz, bool px, T &psx) {
+  const AxisDev<T> &X = A.ax[0], &Z = A.ax[2];
+  T d1 = (ex_kp - ex) * Z.ih[k];
+  T d2 = (ez_ip - ez) * X.ih[i];
+  if (pz) d1 = stretch(d1, psz, Z.bh[k], Z.ah[k], Z.kh[k]);
+  if (px) d2 = stretch(d2, psx, X.bh[i], X.ah[i], X.kh[i]);
+  return fma(-A.dtmu, d1 - d2, h);
+}
+template <typename T>
+__device__ __forceinline__ T hz_node(const StepArgs<T> &A, int i, int j, T h, T ey, T ey_ip, T ex,
+                                     T ex_jp, bool px, T &psx, bool py, T &psy) {
+  const AxisDev<T> &X = A.ax[0], &Y = A.ax[1];
+  T d1 = (ey_ip - ey) * X.ih[i];
+  T d2 = (ex_jp - ex) * Y.ih[j];
+  if (px) d1 = stretch(d1, psx, X.bh[i], X.ah[i], X.kh[i]);
+  if (py) d2 = stretch(d2, psy, Y.bh[j], Y.ah[j], Y.kh[j]);
+  return fma(-A.dtmu, d1 - d2, h);
+}
+
+// E^{n+1} = E^n + dt/eps (d1 - d2), backward differences over a dual width
+//   E_x: d1 = dHz/dy, d2 = dHy/dz   E_y: d1 = dHx/dz, d2 = dHz/dx
+//   E_z: d1 = dHy/dx, d2 = dHx/dy
+template <typename T>
+__device__ __forceinline__ T ex_node(const StepArgs<T> &A, int j, int k, T e, T c, T hz, T hz_jm,
+                                     T hy, T hy_km, bool py, T &psy, bool pz, T &psz) {
+  const AxisDev<T> &Y = A.ax[1], &Z = A.ax[2];
+  T d1 = (hz - hz_jm) * Y.ihd[j];
+  T d2 = (hy - hy_km) * Z.ihd[k];
+  if (py) d1 = stretch(d1, psy, Y.bn[j], Y.an[j], Y.kn[j]);
+  if (pz) d2 = stretch(d2, psz, Z.bn[k], Z.an[k], Z.kn[k]);
+  return fma(c, d1 - d2, e);
+}
+template <typename T>
+__device__ __forceinline__ T ey_node(const StepArgs<T> &A, int i, int k, T e, T c, T hx, T hx_km,
+                                     T hz, T hz_im, bool pz, T &psz, bool px, T &psx) {
+  const AxisDev<T> &X = A.ax[0], &Z = A.ax[2];
+  T d1 = (hx - hx_km) * Z.ihd[k];
+  T d2 = (hz - hz_im) * X.ihd[i];
+  if (pz) d1 = stretch(d1, psz, Z.bn[k], Z.an[k], Z.kn[k]);
+  if (px) d2 = stretch(d2, psx, X.bn[i], X.an[i], X.kn[i]);
+  return fma(c, d1 - d2, e);
+}
+template <typename T>
+__device__ __forceinline__ T ez_node(const StepArgs<T> &A, int i, int j, T e, T c, T hy, T hy_im,
+                                     T hx, T hx_jm, bool px, T &psx, bool py, T &psy) {
+  const AxisDev<T> &X = A.ax[0], &Y = A.ax[1];
+  T d1 = (hy - hy_im) * X.ihd[i];
+  T d2 = (hx - hx_jm) * Y.ihd[j];
+  if (px) d1 = stretch(d1, psx, X.bn[i], X.an[i], X.kn[i]);
+  if (py) d2 = stretch(d2, psy, Y.bn[j], Y.an[j], Y.kn[j]);
+  return fma(c, d1 - d2, e);
+}
+
+// ---------------------------------------------------------------------------
+// H update (two-kernel schedule): each thread owns VX consecutive x nodes
+// (one 16-byte vector per field); the x neighbour beyond the vector is one
+// extra element load.  All loads are issued before any store (loads and
+// stores share one in-order completion counter on this GPU).
 // ---------------------------------------------------------------------------
 template <typename T, int VX>
-__device__ __forceinline__ void h_vec(const StepArgs<T> &A, const T *__restrict__ ex,
-                                      const T *__restrict__ ey, const T *__restrict__ ez,
-                                      T *__restrict__ hx, T *__restrict__ hy, T *__restrict__ hz,
-                                      T *__restrict__ psX, T *__restrict__ psY,
-                                      T *__restrict__ psZ, int i0, int j, int k) {
+__device__ __forceinline__ void h_vec(const StepArgs<T> &A, const Half<T> &I, const Half<T> &O,
+                                      int i0, int j, int k) {
   using V = Vec<T, VX>;
   const int PX = A.PX, NY = A.NY, NZ = A.NZ, npml = A.npml, W = 2 * npml;
   const int64_t plane = (int64_t)NY * PX;
   const int64_t sX = (int64_t)NZ * NY * W, sY = (int64_t)NZ * W * PX, sZ = (int64_t)W * NY * PX;
-  const AxisDev<T> &X = A.ax[0], &Y = A.ax[1], &Z = A.ax[2];
   const bool j_in = j < A.ny, k_in = k < A.nz;
   int ly = 0, lz = 0;
   const bool py = npml > 0 && pml_half(j, A.ny, npml, ly);
@@ -183,82 +317,66 @@ __device__ __forceinline__ void h_vec(const StepArgs<T> &A, const T *__restrict_
   const int64_t q = (int64_t)k * plane + (int64_t)j * PX + i0;
   const bool nbr = i0 + VX <= A.nx;       // the x neighbour of the last element is used
   // ---- loads ----
-  const V ex0 = vload<VX>(ex + q), ey0 = vload<VX>(ey + q), ez0 = vload<VX>(ez + q);
-  const V exk = k_in ? vload<VX>(ex + q + plane) : vzero<T, VX>();
-  const V eyk = k_in ? vload<VX>(ey + q + plane) : vzero<T, VX>();
-  const V ezj = j_in ? vload<VX>(ez + q + PX) : vzero<T, VX>();
-  const V exj = j_in ? vload<VX>(ex + q + PX) : vzero<T, VX>();
-  const T eyn = nbr ? ey[q + VX] : T(0), ezn = nbr ? ez[q + VX] : T(0);
-  V hxv = vload<VX>(hx + q), hyv = vload<VX>(hy + q), hzv = vload<VX>(hz + q);
+  const V ex0 = vload<VX>(I.ex + q), ey0 = vload<VX>(I.ey + q), ez0 = vload<VX>(I.ez + q);
+  const V exk = k_in ? vload<VX>(I.ex + q + plane) : vzero<T, VX>();
+  const V eyk = k_in ? vload<VX>(I.ey + q + plane) : vzero<T, VX>();
+  const V ezj = j_in ? vload<VX>(I.ez + q + PX) : vzero<T, VX>();
+  const V exj = j_in ? vload<VX>(I.ex + q + PX) : vzero<T, VX>();
+  const T eyn = nbr ? I.ey[q + VX] : T(0), ezn = nbr ? I.ez[q + VX] : T(0);
+  V hxv = vload<VX>(I.hx + q), hyv = vload<VX>(I.hy + q), hzv = vload<VX>(I.hz + q);
   const int64_t iY = ((int64_t)k * W + ly) * PX + i0;
   const int64_t iZ = ((int64_t)lz * NY + j) * PX + i0;
-  V ps_hx_y = pyv && k_in ? vload<VX>(psY + 0 * sY + iY) : vzero<T, VX>();
-  V ps_hz_y = pyv ? vload<VX>(psY + 1 * sY + iY) : vzero<T, VX>();
-  V ps_hx_z = pzv && j_in ? vload<VX>(psZ + 0 * sZ + iZ) : vzero<T, VX>();
-  V ps_hy_z = pzv ? vload<VX>(psZ + 1 * sZ + iZ) : vzero<T, VX>();
-  const T ihy = j_in ? Y.ih[j] : T(0), ihz = k_in ? Z.ih[k] : T(0);
+  V ps_hx_y = pyv && k_in ? vload<VX>(I.psY + 0 * sY + iY) : vzero<T, VX>();
+  V ps_hz_y = pyv ? vload<VX>(I.psY + 1 * sY + iY) : vzero<T, VX>();
+  V ps_hx_z = pzv && j_in ? vload<VX>(I.psZ + 0 * sZ + iZ) : vzero<T, VX>();
+  V ps_hy_z = pzv ? vload<VX>(I.psZ + 1 * sZ + iZ) : vzero<T, VX>();
   // ---- compute ----
-  const T dtmu = A.dtmu;
 #pragma unroll
   for (int e = 0; e < VX; ++e) {
     const int i = i0 + e;
     const bool i_in = i < A.nx;
-    const T ihx = i_in ? X.ih[i] : T(0);
     const T ey_ip = e + 1 < VX ? ey0.v[(e + 1) % VX] : eyn;
     const T ez_ip = e + 1 < VX ? ez0.v[(e + 1) % VX] : ezn;
     int lx = 0;
     const bool px = npml > 0 && i_in && pml_half(i, A.nx, npml, lx);
     const int64_t iX = ((int64_t)k * NY + j) * W + lx;
-    if (i <= A.nx && j_in && k_in) {
-      T d1 = (ezj.v[e] - ez0.v[e]) * ihy;       // dEz/dy at y_{j+1/2}
-      T d2 = (eyk.v[e] - ey0.v[e]) * ihz;       // dEy/dz at z_{k+1/2}
-      if (py) { T &p = ps_hx_y.v[e]; p = Y.bh[j] * p + Y.ah[j] * d1; d1 = d1 * Y.kh[j] + p; }
-      if (pz) { T &p = ps_hx_z.v[e]; p = Z.bh[k] * p + Z.ah[k] * d2; d2 = d2 * Z.kh[k] + p; }
-      hxv.v[e] -= dtmu * (d1 - d2);
-    }
+    if (i <= A.nx && j_in && k_in)
+      hxv.v[e] = hx_node(A, j, k, hxv.v[e], ez0.v[e], ezj.v[e], ey0.v[e], eyk.v[e], py,
+                         ps_hx_y.v[e], pz, ps_hx_z.v[e]);
     if (i_in && k_in) {
-      T d1 = (exk.v[e] - ex0.v[e]) * ihz;       // dEx/dz
-      T d2 = (ez_ip - ez0.v[e]) * ihx;          // dEz/dx
-      if (pz) { T &p = ps_hy_z.v[e]; p = Z.bh[k] * p + Z.ah[k] * d1; d1 = d1 * Z.kh[k] + p; }
-      if (px) { T &p = psX[0 * sX + iX]; p = X.bh[i] * p + X.ah[i] * d2; d2 = d2 * X.kh[i] + p; }
-      hyv.v[e] -= dtmu * (d1 - d2);
+      T ps = px ? I.psX[0 * sX + iX] : T(0);
+      hyv.v[e] = hy_node(A, i, k, hyv.v[e], ex0.v[e], exk.v[e], ez0.v[e], ez_ip, pz, ps_hy_z.v[e],
+                         px, ps);
+      if (px) O.psX[0 * sX + iX] = ps;
     }
     if (i_in && j_in) {
-      T d1 = (ey_ip - ey0.v[e]) * ihx;          // dEy/dx
-      T d2 = (exj.v[e] - ex0.v[e]) * ihy;       // dEx/dy
-      if (px) { T &p = psX[1 * sX + iX]; p = X.bh[i] * p + X.ah[i] * d1; d1 = d1 * X.kh[i] + p; }
-      if (py) { T &p = ps_hz_y.v[e]; p = Y.bh[j] * p + Y.ah[j] * d2; d2 = d2 * Y.kh[j] + p; }
-      hzv.v[e] -= dtmu * (d1 - d2);
+      T ps = px ? I.psX[1 * sX + iX] : T(0);
+      hzv.v[e] = hz_node(A, i, j, hzv.v[e], ey0.v[e], ey_ip, ex0.v[e], exj.v[e], px, ps, py,
+                         ps_hz_y.v[e]);
+      if (px) O.psX[1 * sX + iX] = ps;
     }
   }
   // ---- stores (slots outside a component's lattice keep their zero) ----
-  vstore(hx + q, hxv);
-  vstore(hy + q, hyv);
-  vstore(hz + q, hzv);
-  if (pyv && k_in) vstore(psY + 0 * sY + iY, ps_hx_y);
-  if (pyv) vstore(psY + 1 * sY + iY, ps_hz_y);
-  if (pzv && j_in) vstore(psZ + 0 * sZ + iZ, ps_hx_z);
-  if (pzv) vstore(psZ + 1 * sZ + iZ, ps_hy_z);
+  vstore(O.hx + q, hxv);
+  vstore(O.hy + q, hyv);
+  vstore(O.hz + q, hzv);
+  if (pyv && k_in) vstore(O.psY + 0 * sY + iY, ps_hx_y);
+  if (pyv) vstore(O.psY + 1 * sY + iY, ps_hz_y);
+  if (pzv && j_in) vstore(O.psZ + 0 * sZ + iZ, ps_hx_z);
+  if (pzv) vstore(O.psZ + 1 * sZ + iZ, ps_hy_z);
 }
 
 template <typename T, int VX>
 __global__ void __launch_bounds__(256) k_update_h(StepArgs<T> A) {
   int bx, by, bz;
-  if ((int)blockIdx.x >= A.nblocks) return;
   tile_of(A.nblocks, A.xcd, A.nbx, A.nby, bx, by, bz);
-  if (blockIdx.x == 0 && threadIdx.x == 0 && threadIdx.y == 0) A.step_w[0] = A.step_w[0] + 1;
+  const int par = (A.step[0] + 1) & 1;   // this step reads half par
   const int i0 = (bx * blockDim.x + threadIdx.x) * VX;
   const int j = by * blockDim.y + threadIdx.y;
   const int k = bz;
   if (i0 > A.nx || j > A.ny || k > A.nz) return;
-  const int W = 2 * A.npml;
-  const int64_t sX = (int64_t)A.NZ * A.NY * W, sY = (int64_t)A.NZ * W * A.PX;
-  for (int s = 0; s < A.ns; ++s) {
-    T *f = A.fields + (int64_t)s * 6 * A.F;
-    T *ps = A.psi + (int64_t)s * A.psi_src;
-    h_vec<T, VX>(A, f, f + A.F, f + 2 * A.F, f + 3 * A.F, f + 4 * A.F, f + 5 * A.F, ps, ps + 4 * sX,
-             ps + 4 * sX + 4 * sY, i0, j, k);
-  }
+  for (int s = 0; s < A.ns; ++s)
+    h_vec<T, VX>(A, half_of(A, par, s), half_of(A, par ^ 1, s), i0, j, k);
 }
 
 // ---------------------------------------------------------------------------
@@ -325,7 +443,7 @@ __device__ __forceinline__ void post_e(const StepArgs<T> &A, int s, int c, int64
                                        const Vec<T, VX> &e0, const Vec<T, VX> &e1, unsigned ok,
                                        int n, int fl) {
   if constexpr (ACC != ACC_NONE) {
-    if (!ok) return;
+    if (!ok || n >= A.nt) return;   // steps past the run add nothing
     const int nf = A.nf;
     const int m = n + 1;
     const int r = m & (KB - 1);
@@ -380,17 +498,18 @@ __device__ __forceinline__ void post_e(const StepArgs<T> &A, int s, int c, int64
   }
 }
 
-// per-thread list walk.  Entry x = c | kind << 2 | elem << 3 | s << 5:
-// kind 0 = injection J'^{n+1/2} into component c of source s at vector
-// element elem, value sum_r coef[ref + r] F[r][n]; kind 1 = receiver node
-// (racc[s][node = ref] += E^{n+1} z^{n+1}, every source).
+// per-thread list walk.  Entry x = c | kind << 2 | sub << 3 | s << 9, where
+// sub is the vector element (two-kernel schedule) or the plane within the
+// block's chunk (fused schedule): kind 0 = injection J'^{n+1/2} into
+// component c of source s, value sum_r coef[ref + r] F[r][n]; kind 1 =
+// receiver node (racc[s][node = ref] += E^{n+1} z^{n+1}, every source).
 template <typename T>
 __device__ __forceinline__ double inject_value(const StepArgs<T> &A, int lo, int hi, int s, int c,
-                                               int elem, int n) {
+                                               int sub, int n) {
   double v = 0.0;
   for (int e = lo; e < hi; ++e) {
     const int2 en = A.tl_ent[e];
-    if ((en.x & 31) == (c | (elem << 3)) && (en.x >> 5) == s) {
+    if ((en.x & 511) == (c | (sub << 3)) && (en.x >> 9) == s) {
       const double *cf = A.coef + en.y;
       for (int r = 0; r < A.nrow; ++r) v += cf[r] * A.Ftab[(int64_t)r * A.nt + n];
     }
@@ -400,10 +519,10 @@ __device__ __forceinline__ double inject_value(const StepArgs<T> &A, int lo, int
 
 template <typename T>
 __device__ __forceinline__ void record(const StepArgs<T> &A, int lo, int hi, int s, int c,
-                                       int elem, int n, double e) {
+                                       int sub, int n, double e) {
   for (int e2 = lo; e2 < hi; ++e2) {
     const int2 en = A.tl_ent[e2];
-    if ((en.x & 31) == (c | 4 | (elem << 3))) {
+    if ((en.x & 511) == (c | 4 | (sub << 3))) {
       double2 *a = A.racc + ((int64_t)s * A.nn + en.y) * A.nf;
       const double2 *z = A.zE + (int64_t)n * A.nf;
       for (int kf = 0; kf < A.nf; ++kf) {
@@ -417,26 +536,21 @@ __device__ __forceinline__ void record(const StepArgs<T> &A, int lo, int hi, int
 }
 
 // ---------------------------------------------------------------------------
-// E update: E^{n+1} = E^n + dt/eps (curl H^{n+1/2} - J'^{n+1/2}) on interior
-// edges:  E_x += ce (dHz/dy - dHy/dz - J_x), E_y += ce (dHx/dz - dHz/dx - J_y),
-// E_z += ce (dHy/dx - dHx/dy - J_z); backward differences over a dual width.
-// Fused: injection at the source (or adjoint-source) edges, the receiver
+// E update (two-kernel schedule): E^{n+1} from E^n (half par) and H^{n+1/2}
+// (half par ^ 1) on interior edges, written to half par ^ 1.  Fused:
+// injection at the source (or adjoint-source) edges, the receiver
 // transform, and the volume transform / gradient product.  Each thread owns
 // VX consecutive x nodes; the x neighbour before the vector is one extra
 // element load; all stencil loads precede the stores.
 // ---------------------------------------------------------------------------
 template <typename T, int ACC, bool ADJ, int KB, int VX>
-__device__ __forceinline__ void e_vec(const StepArgs<T> &A, int s, T *__restrict__ ex,
-                                      T *__restrict__ ey, T *__restrict__ ez,
-                                      const T *__restrict__ hx, const T *__restrict__ hy,
-                                      const T *__restrict__ hz, T *__restrict__ psX,
-                                      T *__restrict__ psY, T *__restrict__ psZ, int i0, int j,
-                                      int k, int n, int fl, int lo, int hi) {
+__device__ __forceinline__ void e_vec(const StepArgs<T> &A, int s, const Half<T> &I,
+                                      const Half<T> &O, const Half<T> &P, int i0, int j, int k,
+                                      int n, int fl, int lo, int hi) {
   using V = Vec<T, VX>;
   const int PX = A.PX, NY = A.NY, NZ = A.NZ, npml = A.npml, W = 2 * npml;
   const int64_t plane = (int64_t)NY * PX;
   const int64_t sX = (int64_t)NZ * NY * W, sY = (int64_t)NZ * W * PX, sZ = (int64_t)W * NY * PX;
-  const AxisDev<T> &X = A.ax[0], &Y = A.ax[1], &Z = A.ax[2];
   const bool j_int = j >= 1 && j < A.ny, k_int = k >= 1 && k < A.nz;
   const bool j_in = j < A.ny, k_in = k < A.nz;
   int ly = 0, lz = 0;
@@ -453,71 +567,64 @@ __device__ __forceinline__ void e_vec(const StepArgs<T> &A, int s, T *__restrict
     if (i >= 1 && i < A.nx && j_int && k_in) okz |= 1u << e;
   }
   // ---- loads ----
-  const V hx0 = vload<VX>(hx + q), hy0 = vload<VX>(hy + q), hz0 = vload<VX>(hz + q);
-  const V hzj = j >= 1 ? vload<VX>(hz + q - PX) : vzero<T, VX>();
-  const V hxj = j >= 1 ? vload<VX>(hx + q - PX) : vzero<T, VX>();
-  const V hyk = k >= 1 ? vload<VX>(hy + q - plane) : vzero<T, VX>();
-  const V hxk = k >= 1 ? vload<VX>(hx + q - plane) : vzero<T, VX>();
-  const T hzp = i0 >= 1 ? hz[q - 1] : T(0), hyp = i0 >= 1 ? hy[q - 1] : T(0);
-  V e0x = vload<VX>(ex + q), e0y = vload<VX>(ey + q), e0z = vload<VX>(ez + q);
+  const V hx0 = vload<VX>(O.hx + q), hy0 = vload<VX>(O.hy + q), hz0 = vload<VX>(O.hz + q);
+  const V hzj = j >= 1 ? vload<VX>(O.hz + q - PX) : vzero<T, VX>();
+  const V hxj = j >= 1 ? vload<VX>(O.hx + q - PX) : vzero<T, VX>();
+  const V hyk = k >= 1 ? vload<VX>(O.hy + q - plane) : vzero<T, VX>();
+  const V hxk = k >= 1 ? vload<VX>(O.hx + q - plane) : vzero<T, VX>();
+  const T hzp = i0 >= 1 ? O.hz[q - 1] : T(0), hyp = i0 >= 1 ? O.hy[q - 1] : T(0);
+  const V e0x = vload<VX>(I.ex + q), e0y = vload<VX>(I.ey + q), e0z = vload<VX>(I.ez + q);
   const V cx = okx ? vload<VX>(A.ce[0] + q) : vzero<T, VX>();
   const V cy = oky ? vload<VX>(A.ce[1] + q) : vzero<T, VX>();
   const V cz = okz ? vload<VX>(A.ce[2] + q) : vzero<T, VX>();
   const int64_t iY = ((int64_t)k * W + ly) * PX + i0;
   const int64_t iZ = ((int64_t)lz * NY + j) * PX + i0;
-  V ps_ex_y = py && okx ? vload<VX>(psY + 2 * sY + iY) : vzero<T, VX>();
-  V ps_ez_y = py && okz ? vload<VX>(psY + 3 * sY + iY) : vzero<T, VX>();
-  V ps_ex_z = pz && okx ? vload<VX>(psZ + 2 * sZ + iZ) : vzero<T, VX>();
-  V ps_ey_z = pz && oky ? vload<VX>(psZ + 3 * sZ + iZ) : vzero<T, VX>();
-  const T ihdy = j_int ? Y.ihd[j] : T(0), ihdz = k_int ? Z.ihd[k] : T(0);
+  V ps_ex_y = py && okx ? vload<VX>(P.psY + 2 * sY + iY) : vzero<T, VX>();
+  V ps_ez_y = py && okz ? vload<VX>(P.psY + 3 * sY + iY) : vzero<T, VX>();
+  V ps_ex_z = pz && okx ? vload<VX>(P.psZ + 2 * sZ + iZ) : vzero<T, VX>();
+  V ps_ey_z = pz && oky ? vload<VX>(P.psZ + 3 * sZ + iZ) : vzero<T, VX>();
   // ---- compute ----
   V e1x = e0x, e1y = e0y, e1z = e0z;
 #pragma unroll
   for (int e = 0; e < VX; ++e) {
     const int i = i0 + e;
     const bool i_int = i >= 1 && i < A.nx;
-    const T ihdx = i_int ? X.ihd[i] : T(0);
     const T hz_im = e > 0 ? hz0.v[(e + VX - 1) % VX] : hzp;
     const T hy_im = e > 0 ? hy0.v[(e + VX - 1) % VX] : hyp;
     int lx = 0;
     const bool px = npml > 0 && i_int && pml_int(i, A.nx, npml, lx);
     const int64_t iX = ((int64_t)k * NY + j) * W + lx;
     if ((okx >> e) & 1u) {
-      T d1 = (hz0.v[e] - hzj.v[e]) * ihdy;       // dHz/dy at y_j
-      T d2 = (hy0.v[e] - hyk.v[e]) * ihdz;       // dHy/dz at z_k
-      if (py) { T &p = ps_ex_y.v[e]; p = Y.bn[j] * p + Y.an[j] * d1; d1 = d1 * Y.kn[j] + p; }
-      if (pz) { T &p = ps_ex_z.v[e]; p = Z.bn[k] * p + Z.an[k] * d2; d2 = d2 * Z.kn[k] + p; }
-      T v = e0x.v[e] + cx.v[e] * (d1 - d2);
+      T v = ex_node(A, j, k, e0x.v[e], cx.v[e], hz0.v[e], hzj.v[e], hy0.v[e], hyk.v[e], py,
+                    ps_ex_y.v[e], pz, ps_ex_z.v[e]);
       if (lo < hi) v -= (T)((double)cx.v[e] * inject_value(A, lo, hi, s, 0, e, n));
       e1x.v[e] = v;
     }
     if ((oky >> e) & 1u) {
-      T d1 = (hx0.v[e] - hxk.v[e]) * ihdz;       // dHx/dz
-      T d2 = (hz0.v[e] - hz_im) * ihdx;          // dHz/dx
-      if (pz) { T &p = ps_ey_z.v[e]; p = Z.bn[k] * p + Z.an[k] * d1; d1 = d1 * Z.kn[k] + p; }
-      if (px) { T &p = psX[2 * sX + iX]; p = X.bn[i] * p + X.an[i] * d2; d2 = d2 * X.kn[i] + p; }
-      T v = e0y.v[e] + cy.v[e] * (d1 - d2);
+      T dummy = T(0);
+      T &psx = px ? P.psX[2 * sX + iX] : dummy;
+      T v = ey_node(A, i, k, e0y.v[e], cy.v[e], hx0.v[e], hxk.v[e], hz0.v[e], hz_im, pz,
+                    ps_ey_z.v[e], px, psx);
       if (lo < hi) v -= (T)((double)cy.v[e] * inject_value(A, lo, hi, s, 1, e, n));
       e1y.v[e] = v;
     }
     if ((okz >> e) & 1u) {
-      T d1 = (hy0.v[e] - hy_im) * ihdx;          // dHy/dx
-      T d2 = (hx0.v[e] - hxj.v[e]) * ihdy;       // dHx/dy
-      if (px) { T &p = psX[3 * sX + iX]; p = X.bn[i] * p + X.an[i] * d1; d1 = d1 * X.kn[i] + p; }
-      if (py) { T &p = ps_ez_y.v[e]; p = Y.bn[j] * p + Y.an[j] * d2; d2 = d2 * Y.kn[j] + p; }
-      T v = e0z.v[e] + cz.v[e] * (d1 - d2);
+      T dummy = T(0);
+      T &psx = px ? P.psX[3 * sX + iX] : dummy;
+      T v = ez_node(A, i, j, e0z.v[e], cz.v[e], hy0.v[e], hy_im, hx0.v[e], hxj.v[e], px, psx, py,
+                    ps_ez_y.v[e]);
       if (lo < hi) v -= (T)((double)cz.v[e] * inject_value(A, lo, hi, s, 2, e, n));
       e1z.v[e] = v;
     }
   }
   // ---- stores ----
-  if (okx) vstore(ex + q, e1x);
-  if (oky) vstore(ey + q, e1y);
-  if (okz) vstore(ez + q, e1z);
-  if (py && okx) vstore(psY + 2 * sY + iY, ps_ex_y);
-  if (py && okz) vstore(psY + 3 * sY + iY, ps_ez_y);
-  if (pz && okx) vstore(psZ + 2 * sZ + iZ, ps_ex_z);
-  if (pz && oky) vstore(psZ + 3 * sZ + iZ, ps_ey_z);
+  if (okx) vstore(O.ex + q, e1x);
+  if (oky) vstore(O.ey + q, e1y);
+  if (okz) vstore(O.ez + q, e1z);
+  if (py && okx) vstore(P.psY + 2 * sY + iY, ps_ex_y);
+  if (py && okz) vstore(P.psY + 3 * sY + iY, ps_ez_y);
+  if (pz && okx) vstore(P.psZ + 2 * sZ + iZ, ps_ex_z);
+  if (pz && oky) vstore(P.psZ + 3 * sZ + iZ, ps_ey_z);
   if (lo < hi) {
 #pragma unroll
     for (int e = 0; e < VX; ++e) {
@@ -534,36 +641,320 @@ __device__ __forceinline__ void e_vec(const StepArgs<T> &A, int s, T *__restrict
 
 template <typename T, int ACC, bool ADJ, int KB, int VX>
 __global__ void __launch_bounds__(256) k_update_e(StepArgs<T> A) {
+  __shared__ int s_n;
   int bx, by, bz;
-  if ((int)blockIdx.x >= A.nblocks) return;
   const int b = tile_of(A.nblocks, A.xcd, A.nbx, A.nby, bx, by, bz);
+  if (threadIdx.x == 0 && threadIdx.y == 0) s_n = A.step[0] + 1;
+  __syncthreads();
+  const int n = s_n;
   const int i0 = (bx * blockDim.x + threadIdx.x) * VX;
   const int j = by * blockDim.y + threadIdx.y;
   const int k = bz;
-  if (i0 > A.nx || j > A.ny || k > A.nz) return;
-  const int n = A.step[0];
+  if (i0 <= A.nx && j <= A.ny && k <= A.nz) {
+    const int fl = A.flushed[0];
+    // this thread's slice of the tile's entry table (if the tile has one)
+    const int tt = A.tile_tab[b];
+    int lo = 0, hi = 0;
+    if (tt >= 0 && n < A.nt) {   // no injection or recording past the run
+      const int slot = threadIdx.y * blockDim.x + threadIdx.x;
+      lo = A.tl_off[tt + slot];
+      hi = A.tl_off[tt + slot + 1];
+    }
+    const int par = n & 1;
+    for (int s = 0; s < A.ns; ++s)
+      e_vec<T, ACC, ADJ, KB, VX>(A, s, half_of(A, par, s), half_of(A, par ^ 1, s),
+                                 half_of(A, 0, s), i0, j, k, n, fl, lo, hi);
+  }
+  finish_step(A, n);
+}
+
+// ---------------------------------------------------------------------------
+// Fused step (one launch per leapfrog step).  A block of bx x by threads
+// owns the columns (i, j) = (x0 + tx, y0 + ty) of a tile and the planes
+// k in [z0, z1) of a chunk.  For each plane:
+//   1. E^n of plane k goes to LDS on the tile plus a one-node halo: the
+//      high-side column and row feed the forward differences of H on the
+//      tile, the low-side column and row those of H at x0 - 1 and y0 - 1;
+//   2. H^{n+1/2} of plane k is computed on the tile and recomputed on the
+//      low-side halo column and row (the operands and operations of the
+//      owning block, so the same bits), and staged in LDS for the backward
+//      differences of the E update;
+//   3. E^{n+1} of plane k, with the z differences taken against H of the
+//      plane below (carried in registers) and E of the plane above (loaded
+//      ahead, carried into the next plane).
+// A chunk with z0 > 0 first recomputes H at plane z0 - 1 of its tile.
+// Threads on the tile edges load the halo; threads outside the grid take
+// part in the barriers with zeros.  Two barriers per plane: after the E
+// staging (H reads E) and after the H staging (E reads H); the next plane's
+// E staging follows the second barrier, its H staging the next first one.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T ld(const StepArgs<T> &A, const T *f, int i, int j, int k) {
+  return (i >= 0 && i <= A.nx && j >= 0 && j <= A.ny && k >= 0 && k <= A.nz)
+             ? f[((int64_t)k * A.NY + j) * A.PX + i]
+             : T(0);
+}
+
+template <typename T, int ACC, bool ADJ, int KB>
+__global__ void __launch_bounds__(256) k_step(StepArgs<T> A) {
+  extern __shared__ double lds_raw[];
+  __shared__ int s_n;
+  const int BX = blockDim.x, BY = blockDim.y;
+  const int WE = BX + 2, WH = BX + 1;
+  const int SE = WE * (BY + 2), SH = WH * (BY + 1);
+  T *sEx = reinterpret_cast<T *>(lds_raw), *sEy = sEx + SE, *sEz = sEy + SE;
+  T *sHx = sEz + SE, *sHy = sHx + SH, *sHz = sHy + SH;
+  int tbx, tby, tbz;
+  const int b = tile_of(A.nblocks, A.xcd, A.nbx, A.nby, tbx, tby, tbz);
+  const int tx = threadIdx.x, ty = threadIdx.y;
+  const int x0 = tbx * BX, y0 = tby * BY;
+  const int i = x0 + tx, j = y0 + ty;
+  const int z0 = tbz * A.kz, z1 = min(z0 + A.kz, A.nz);
+  if (tx == 0 && ty == 0) s_n = A.step[0] + 1;
+  __syncthreads();
+  const int n = s_n, par = n & 1;
   const int fl = A.flushed[0];
-  const int W = 2 * A.npml;
-  const int64_t sX = (int64_t)A.NZ * A.NY * W, sY = (int64_t)A.NZ * W * A.PX;
-  // this thread's slice of the tile's entry table (if the tile has one)
   const int tt = A.tile_tab[b];
   int lo = 0, hi = 0;
-  if (tt >= 0) {
-    const int slot = threadIdx.y * blockDim.x + threadIdx.x;
+  if (tt >= 0 && n < A.nt) {   // no injection or recording past the run
+    const int slot = ty * BX + tx;
     lo = A.tl_off[tt + slot];
     hi = A.tl_off[tt + slot + 1];
   }
+  const int npml = A.npml, W = 2 * npml, PX = A.PX, NY = A.NY, NZ = A.NZ;
+  const int64_t sX = (int64_t)NZ * NY * W, sY = (int64_t)NZ * W * PX, sZ = (int64_t)W * NY * PX;
+  // column geometry of the own node and of the low-side halo nodes
+  const bool act = i <= A.nx && j <= A.ny;
+  const bool i_in = i < A.nx, j_in = j < A.ny;
+  const bool i_int = i >= 1 && i < A.nx, j_int = j >= 1 && j < A.ny;
+  int lxh = 0, lyh = 0, lxn = 0, lyn = 0;
+  const bool pxh = npml > 0 && i_in && pml_half(i, A.nx, npml, lxh);
+  const bool pyh = npml > 0 && j_in && pml_half(j, A.ny, npml, lyh);
+  const bool pxn = npml > 0 && i_int && pml_int(i, A.nx, npml, lxn);
+  const bool pyn = npml > 0 && j_int && pml_int(j, A.ny, npml, lyn);
+  const int ia = x0 - 1, jb = y0 - 1;                     // halo column / row
+  const bool haloA = tx == 0 && ia >= 0 && j <= A.ny;      // node (ia, j): H_y, H_z
+  const bool haloB = ty == 0 && jb >= 0 && i <= A.nx;      // node (i, jb): H_z, H_x
+  int lxa = 0, lyb = 0;
+  const bool pxa = npml > 0 && haloA && pml_half(ia, A.nx, npml, lxa);
+  const bool pyb = npml > 0 && haloB && pml_half(jb, A.ny, npml, lyb);
+  const int own = (ty + 1) * WE + tx + 1, ownH = (ty + 1) * WH + tx + 1;
+
   for (int s = 0; s < A.ns; ++s) {
-    T *f = A.fields + (int64_t)s * 6 * A.F;
-    T *ps = A.psi + (int64_t)s * A.psi_src;
-    e_vec<T, ACC, ADJ, KB, VX>(A, s, f, f + A.F, f + 2 * A.F, f + 3 * A.F, f + 4 * A.F, f + 5 * A.F,
-                           ps, ps + 4 * sX, ps + 4 * sX + 4 * sY, i0, j, k, n, fl, lo, hi);
+    const Half<T> I = half_of(A, par, s), O = half_of(A, par ^ 1, s), P = half_of(A, 0, s);
+    const int kbeg = z0 > 0 ? z0 - 1 : 0;
+    T ex = ld(A, I.ex, i, j, kbeg), ey = ld(A, I.ey, i, j, kbeg), ez = ld(A, I.ez, i, j, kbeg);
+    T exa = tx == 0 ? ld(A, I.ex, ia, j, kbeg) : T(0);   // E_x at (ia, j, k)
+    T eyb = ty == 0 ? ld(A, I.ey, i, jb, kbeg) : T(0);   // E_y at (i, jb, k)
+    T hxm = T(0), hym = T(0);                             // H^{n+1/2} at (i, j, k-1)
+    for (int k = kbeg; k < z1; ++k) {
+      const bool pre = k < z0;
+      const int sub = k - z0;
+      const int64_t q = ((int64_t)k * NY + j) * PX + i;   // dereferenced only when act
+      int lzh = 0, lzn = 0;
+      const bool pzh = npml > 0 && pml_half(k, A.nz, npml, lzh);
+      const bool pzn = npml > 0 && k >= 1 && pml_int(k, A.nz, npml, lzn);
+      // ---- loads: E^n of plane k+1 (own), H^{n-1/2} of plane k, E halo ----
+      const T ex1 = ld(A, I.ex, i, j, k + 1), ey1 = ld(A, I.ey, i, j, k + 1);
+      const T ez1 = ld(A, I.ez, i, j, k + 1);
+      const T hx = ld(A, I.hx, i, j, k), hy = ld(A, I.hy, i, j, k);
+      const T hz = pre ? T(0) : ld(A, I.hz, i, j, k);
+      T gEyR = 0, gEzR = 0, gExT = 0, gEzT = 0, gEyA = 0, gEzA = 0, gExAT = 0;
+      T gExB = 0, gEzB = 0, gEyBR = 0, exa1 = 0, eyb1 = 0;
+      if (tx == BX - 1) {                                  // high-side column x0 + BX
+        gEyR = ld(A, I.ey, x0 + BX, j, k);
+        gEzR = ld(A, I.ez, x0 + BX, j, k);
+      }
+      if (ty == BY - 1) {                                  // high-side row y0 + BY
+        gExT = ld(A, I.ex, i, y0 + BY, k);
+        gEzT = ld(A, I.ez, i, y0 + BY, k);
+      }
+      if (tx == 0) {                                       // low-side column ia
+        gEyA = ld(A, I.ey, ia, j, k);
+        gEzA = ld(A, I.ez, ia, j, k);
+        exa1 = ld(A, I.ex, ia, j, k + 1);
+        if (ty == BY - 1) gExAT = ld(A, I.ex, ia, y0 + BY, k);
+      }
+      if (ty == 0) {                                       // low-side row jb
+        gExB = ld(A, I.ex, i, jb, k);
+        gEzB = ld(A, I.ez, i, jb, k);
+        eyb1 = ld(A, I.ey, i, jb, k + 1);
+        if (tx == BX - 1) gEyBR = ld(A, I.ey, x0 + BX, jb, k);
+      }
+      // CPML memory of H at the own node (read half par)
+      const int64_t iYh = ((int64_t)k * W + lyh) * PX + i, iZh = ((int64_t)lzh * NY + j) * PX + i;
+      const int64_t iXh = ((int64_t)k * NY + j) * W + lxh;
+      T ps_hx_y = act && pyh ? I.psY[0 * sY + iYh] : T(0);
+      T ps_hz_y = act && pyh && !pre ? I.psY[1 * sY + iYh] : T(0);
+      T ps_hx_z = act && pzh && j_in ? I.psZ[0 * sZ + iZh] : T(0);
+      T ps_hy_z = act && pzh ? I.psZ[1 * sZ + iZh] : T(0);
+      T ps_hy_x = act && pxh ? I.psX[0 * sX + iXh] : T(0);
+      T ps_hz_x = act && pxh && j_in && !pre ? I.psX[1 * sX + iXh] : T(0);
+      // halo H^{n-1/2} and its CPML memory
+      T hyA = 0, hzA = 0, pa_hy_z = 0, pa_hy_x = 0, pa_hz_x = 0, pa_hz_y = 0;
+      if (!pre && haloA) {
+        hyA = ld(A, I.hy, ia, j, k);
+        if (pzh) pa_hy_z = I.psZ[1 * sZ + ((int64_t)lzh * NY + j) * PX + ia];
+        if (pxa) pa_hy_x = I.psX[0 * sX + ((int64_t)k * NY + j) * W + lxa];
+        if (j_in) {
+          hzA = ld(A, I.hz, ia, j, k);
+          if (pxa) pa_hz_x = I.psX[1 * sX + ((int64_t)k * NY + j) * W + lxa];
+          if (pyh) pa_hz_y = I.psY[1 * sY + ((int64_t)k * W + lyh) * PX + ia];
+        }
+      }
+      T hxB = 0, hzB = 0, pb_hx_y = 0, pb_hx_z = 0, pb_hz_x = 0, pb_hz_y = 0;
+      if (!pre && haloB) {
+        hxB = ld(A, I.hx, i, jb, k);
+        if (pyb) pb_hx_y = I.psY[0 * sY + ((int64_t)k * W + lyb) * PX + i];
+        if (pzh) pb_hx_z = I.psZ[0 * sZ + ((int64_t)lzh * NY + jb) * PX + i];
+        if (i_in) {
+          hzB = ld(A, I.hz, i, jb, k);
+          if (pxh) pb_hz_x = I.psX[1 * sX + ((int64_t)k * NY + jb) * W + lxh];
+          if (pyb) pb_hz_y = I.psY[1 * sY + ((int64_t)k * W + lyb) * PX + i];
+        }
+      }
+      // ---- stage E^n of plane k ----
+      sEx[own] = ex;
+      sEy[own] = ey;
+      sEz[own] = ez;
+      if (tx == BX - 1) {
+        sEy[(ty + 1) * WE + BX + 1] = gEyR;
+        sEz[(ty + 1) * WE + BX + 1] = gEzR;
+      }
+      if (ty == BY - 1) {
+        sEx[(BY + 1) * WE + tx + 1] = gExT;
+        sEz[(BY + 1) * WE + tx + 1] = gEzT;
+      }
+      if (tx == 0) {
+        sEx[(ty + 1) * WE] = exa;
+        sEy[(ty + 1) * WE] = gEyA;
+        sEz[(ty + 1) * WE] = gEzA;
+        if (ty == BY - 1) sEx[(BY + 1) * WE] = gExAT;
+      }
+      if (ty == 0) {
+        sEx[tx + 1] = gExB;
+        sEy[tx + 1] = eyb;
+        sEz[tx + 1] = gEzB;
+        if (tx == BX - 1) sEy[BX + 1] = gEyBR;
+      }
+      __syncthreads();
+      // ---- H^{n+1/2} of plane k ----
+      T hxn = hx, hyn = hy, hzn = hz;
+      if (act) {
+        if (j_in)
+          hxn = hx_node(A, j, k, hx, ez, sEz[own + WE], ey, ey1, pyh, ps_hx_y, pzh, ps_hx_z);
+        if (i_in)
+          hyn = hy_node(A, i, k, hy, ex, ex1, ez, sEz[own + 1], pzh, ps_hy_z, pxh, ps_hy_x);
+        if (i_in && j_in && !pre)
+          hzn = hz_node(A, i, j, hz, ey, sEy[own + 1], ex, sEx[own + WE], pxh, ps_hz_x, pyh,
+                        ps_hz_y);
+      }
+      if (!pre) {
+        T hyAn = 0, hzAn = 0, hxBn = 0, hzBn = 0;
+        if (haloA) {
+          const int a0 = (ty + 1) * WE;
+          hyAn = hy_node(A, ia, k, hyA, exa, exa1, sEz[a0], sEz[a0 + 1], pzh, pa_hy_z, pxa, pa_hy_x);
+          if (j_in)
+            hzAn = hz_node(A, ia, j, hzA, sEy[a0], sEy[a0 + 1], exa, sEx[a0 + WE], pxa, pa_hz_x, pyh,
+                           pa_hz_y);
+        }
+        if (haloB) {
+          if (i_in)
+            hzBn = hz_node(A, i, jb, hzB, sEy[tx + 1], sEy[tx + 2], sEx[tx + 1], sEx[WE + tx + 1],
+                           pxh, pb_hz_x, pyb, pb_hz_y);
+          hxBn = hx_node(A, jb, k, hxB, sEz[tx + 1], sEz[WE + tx + 1], eyb, eyb1, pyb, pb_hx_y,
+                         pzh, pb_hx_z);
+        }
+        sHx[ownH] = hxn;
+        sHy[ownH] = hyn;
+        sHz[ownH] = hzn;
+        if (tx == 0) {
+          sHy[(ty + 1) * WH] = hyAn;
+          sHz[(ty + 1) * WH] = hzAn;
+        }
+        if (ty == 0) {
+          sHx[tx + 1] = hxBn;
+          sHz[tx + 1] = hzBn;
+        }
+        if (act) {
+          O.hx[q] = hxn;
+          O.hy[q] = hyn;
+          O.hz[q] = hzn;
+          if (pyh) {
+            O.psY[0 * sY + iYh] = ps_hx_y;
+            O.psY[1 * sY + iYh] = ps_hz_y;
+          }
+          if (pzh) {
+            if (j_in) O.psZ[0 * sZ + iZh] = ps_hx_z;
+            O.psZ[1 * sZ + iZh] = ps_hy_z;
+          }
+          if (pxh) {
+            O.psX[0 * sX + iXh] = ps_hy_x;
+            if (j_in) O.psX[1 * sX + iXh] = ps_hz_x;
+          }
+        }
+      }
+      __syncthreads();
+      // ---- E^{n+1} of plane k ----
+      if (!pre && act) {
+        const bool k_int = k >= 1;
+        const bool okx = i_in && j_int && k_int;
+        const bool oky = i_int && j_in && k_int;
+        const bool okz = i_int && j_int;
+        const T cx = okx ? A.ce[0][q] : T(0), cy = oky ? A.ce[1][q] : T(0);
+        const T cz = okz ? A.ce[2][q] : T(0);
+        const int64_t iYn = ((int64_t)k * W + lyn) * PX + i, iZn = ((int64_t)lzn * NY + j) * PX + i;
+        const int64_t iXn = ((int64_t)k * NY + j) * W + lxn;
+        T dummy = T(0);
+        T exn = ex, eyn = ey, ezn = ez;
+        if (okx) {
+          T &psy = pyn ? P.psY[2 * sY + iYn] : dummy;
+          T &psz = pzn ? P.psZ[2 * sZ + iZn] : dummy;
+          exn = ex_node(A, j, k, ex, cx, hzn, sHz[ownH - WH], hyn, hym, pyn, psy, pzn, psz);
+          if (lo < hi) exn -= (T)((double)cx * inject_value(A, lo, hi, s, 0, sub, n));
+          O.ex[q] = exn;
+        }
+        if (oky) {
+          T &psz = pzn ? P.psZ[3 * sZ + iZn] : dummy;
+          T &psx = pxn ? P.psX[2 * sX + iXn] : dummy;
+          eyn = ey_node(A, i, k, ey, cy, hxn, hxm, hzn, sHz[ownH - 1], pzn, psz, pxn, psx);
+          if (lo < hi) eyn -= (T)((double)cy * inject_value(A, lo, hi, s, 1, sub, n));
+          O.ey[q] = eyn;
+        }
+        if (okz) {
+          T &psx = pxn ? P.psX[3 * sX + iXn] : dummy;
+          T &psy = pyn ? P.psY[3 * sY + iYn] : dummy;
+          ezn = ez_node(A, i, j, ez, cz, hyn, sHy[ownH - 1], hxn, sHx[ownH - WH], pxn, psx, pyn,
+                        psy);
+          if (lo < hi) ezn -= (T)((double)cz * inject_value(A, lo, hi, s, 2, sub, n));
+          O.ez[q] = ezn;
+        }
+        if (lo < hi) {
+          if (okx) record(A, lo, hi, s, 0, sub, n, (double)exn);
+          if (oky) record(A, lo, hi, s, 1, sub, n, (double)eyn);
+          if (okz) record(A, lo, hi, s, 2, sub, n, (double)ezn);
+        }
+        post_e<T, ACC, ADJ, KB, 1>(A, s, 0, q, vec1(ex), vec1(exn), okx ? 1u : 0u, n, fl);
+        post_e<T, ACC, ADJ, KB, 1>(A, s, 1, q, vec1(ey), vec1(eyn), oky ? 1u : 0u, n, fl);
+        post_e<T, ACC, ADJ, KB, 1>(A, s, 2, q, vec1(ez), vec1(ezn), okz ? 1u : 0u, n, fl);
+      }
+      // ---- carry to the next plane ----
+      hxm = hxn;
+      hym = hyn;
+      ex = ex1;
+      ey = ey1;
+      ez = ez1;
+      exa = exa1;
+      eyb = eyb1;
+    }
   }
+  finish_step(A, n);
 }
 
 // Flush: add the samples of the incomplete last block (m_last % KB != 0)
 // that are newer than *flushed; the caller then moves *flushed to m_last
-// with k_set_flushed.  One thread per node of the padded layout.
+// with k_set_flushed.  One thread per node of the padded layout.  The last
+// sample E^{m_last} sits in half m_last % 2.
 template <typename T, int ACC, bool ADJ, int KB>
 __global__ void __launch_bounds__(256) k_flush(StepArgs<T> A) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -581,14 +972,14 @@ __global__ void __launch_bounds__(256) k_flush(StepArgs<T> A) {
   const int nf = A.nf;
   double g[3] = {0.0, 0.0, 0.0};
   for (int s = 0; s < A.ns; ++s) {
-    const T *f = A.fields + (int64_t)s * 6 * A.F;
+    const T *f = A.fields + (m_last & 1) * A.fbuf + (int64_t)s * 6 * A.F;
     for (int c = 0; c < 3; ++c) {
       if (!ok[c]) continue;
       const T *h = A.hist + (int64_t)s * A.hist_src + (int64_t)c * A.F + q;
       const int64_t base = ((int64_t)s * nf * 3 + c) * A.F + q;
       for (int rr = 1; rr <= r_end; ++rr) {
         const int mm = m_last - r_end + rr;
-        if (mm <= fl) continue;
+        if (mm <= fl || mm > A.nt) continue;
         const double v = rr <= KB - 2 ? (double)h[(int64_t)(rr - 1) * 3 * A.F]
                                       : (double)f[(int64_t)c * A.F + q];
         for (int kf = 0; kf < nf; ++kf) {
@@ -893,10 +1284,11 @@ static void ensure_tables(Plan &p, hipStream_t stream) {
 // workspace carving
 // ---------------------------------------------------------------------------
 struct WS {
-  void *fields, *psi;
+  void *fields, *psi;   // two halves each
   double2 *racc;
-  int *step;      // current step index
-  int *flushed;   // last sample already added by a flush
+  int *step;            // index of the last completed step
+  int *flushed;         // last sample already added by a flush
+  unsigned *done;       // finished blocks of the running launch
   void *hist;
   double *gedge;
 };
@@ -907,13 +1299,14 @@ static WS carve(const Plan &p, void *ws) {
   WS w;
   char *b = static_cast<char *>(ws);
   w.fields = b;
-  b += a256((size_t)p.ns * 6 * p.field_elems() * p.tsize());
+  b += a256(2 * (size_t)p.ns * 6 * p.field_elems() * p.tsize());
   w.psi = b;
-  b += a256((size_t)p.ns * p.psi_elems_per_source() * p.tsize());
+  b += a256(2 * (size_t)p.ns * p.psi_elems_per_source() * p.tsize());
   w.racc = reinterpret_cast<double2 *>(b);
   b += a256((size_t)p.ns * p.rn_c.size() * p.nf() * 16);
   w.step = reinterpret_cast<int *>(b);
   w.flushed = w.step + 1;
+  w.done = reinterpret_cast<unsigned *>(w.step + 2);
   b += 256;
   w.hist = b;
   b += a256((size_t)p.ns * p.hist_elems_per_source() * p.tsize());
@@ -922,22 +1315,32 @@ static WS carve(const Plan &p, void *ws) {
 }
 
 // ---------------------------------------------------------------------------
-// one step = four launches
+// one step = two launches (H, E) or one fused launch
 // ---------------------------------------------------------------------------
-// Tiling of the stencil kernels: (bx x by) threads over x-y, each thread a
-// 16-byte vector of VX x nodes, one plane per block row of tiles;
-// tile b = (bz * nby + by) * nbx + bx.
+// Tiling: (bx x by) threads over x-y; tile b = (bz * nby + by) * nbx + bx.
+// Two kernels: each thread a vector of VX x nodes, one plane per tile row
+// (bz = k).  Fused: one x node per thread, kz planes per tile (bz = chunk).
 struct Tiling {
   int nbx, nby, nbz, nblocks, vx;
+  size_t lds;   // dynamic LDS bytes per block (fused)
 };
 
 static Tiling tiling(const Plan &p) {
   if (p.bx * p.by > 256) fail(FWD_ERR_INVALID_ARG, "block x * block y must be <= 256");
   Tiling t;
-  t.vx = p.vx == 1 ? 1 : (int)(16 / p.tsize());
-  t.nbx = (p.NX + p.bx * t.vx - 1) / (p.bx * t.vx);
-  t.nby = (p.NY + p.by - 1) / p.by;
-  t.nbz = p.NZ;
+  if (p.sched == 1) {
+    t.vx = 1;
+    t.nbx = (p.NX + p.bx - 1) / p.bx;
+    t.nby = (p.NY + p.by - 1) / p.by;
+    t.nbz = (p.nz + p.kz - 1) / p.kz;
+    t.lds = 3 * ((size_t)(p.bx + 2) * (p.by + 2) + (size_t)(p.bx + 1) * (p.by + 1)) * p.tsize();
+  } else {
+    t.vx = p.vx == 1 ? 1 : (int)(16 / p.tsize());
+    t.nbx = (p.NX + p.bx * t.vx - 1) / (p.bx * t.vx);
+    t.nby = (p.NY + p.by - 1) / p.by;
+    t.nbz = p.NZ;
+    t.lds = 0;
+  }
   t.nblocks = t.nbx * t.nby * t.nbz;
   return t;
 }
@@ -946,12 +1349,13 @@ static Tiling tiling(const Plan &p) {
 // (kind 0: component c of source s; ref = first coefficient row) or a
 // receiver node (kind 1: component c; ref = node index), attached to the
 // thread of the tiling that owns its edge (with the element of that
-// thread's vector), so that the E update finds its own entries with two
-// loads and no search.
+// thread's vector, or the plane within the fused chunk), so that the E
+// update finds its own entries with two loads and no search.
 static void build_lists(Plan &p, Dev &d) {
   const Tiling t = tiling(p);
   char key[128];
-  snprintf(key, sizeof key, "%d/%d/%d/%llu", p.bx, p.by, p.vx, (unsigned long long)p.model_version);
+  snprintf(key, sizeof key, "%d/%d/%d/%d/%d/%llu", p.bx, p.by, p.vx, p.sched, p.kz,
+           (unsigned long long)p.model_version);
   if (d.list_key == key) return;
   free_lists(d);
   const int nn = (int)p.rn_c.size(), nf = p.nf();
@@ -965,11 +1369,21 @@ static void build_lists(Plan &p, Dev &d) {
     auto place = [&](int c, int kind, int s, int64_t idx, int ref) {
       const int64_t plane = (int64_t)p.NY * p.PX;
       const int k = (int)(idx / plane), j = (int)((idx % plane) / p.PX), i = (int)(idx % p.PX);
-      const int tx = i / t.vx, elem = i % t.vx;
-      const int bxi = tx / p.bx, byi = j / p.by, bzi = k;
-      const int b = (bzi * t.nby + byi) * t.nbx + bxi;
-      const int slot = (j % p.by) * p.bx + (tx % p.bx);
-      ents.push_back({b, slot, make_int2(c | (kind << 2) | (elem << 3) | (s << 5), ref)});
+      if (i > p.nx || j > p.ny || k > p.nz) fail(FWD_ERR_INVALID_ARG, "entry outside the grid");
+      int b, slot, sub;
+      if (p.sched == 1) {
+        if (k >= p.nz) return;   // no E update on the top plane: never used
+        const int zc = k / p.kz;
+        sub = k % p.kz;
+        b = (zc * t.nby + j / p.by) * t.nbx + i / p.bx;
+        slot = (j % p.by) * p.bx + (i % p.bx);
+      } else {
+        const int tx = i / t.vx;
+        sub = i % t.vx;
+        b = (k * t.nby + j / p.by) * t.nbx + tx / p.bx;
+        slot = (j % p.by) * p.bx + (tx % p.bx);
+      }
+      ents.push_back({b, slot, make_int2(c | (kind << 2) | (sub << 3) | (s << 9), ref)});
     };
     if (mode == 0) {
       for (size_t q = 0; q < p.src_tg.size(); ++q)
@@ -1045,15 +1459,19 @@ static StepArgs<T> make_args(Plan &p, Dev &d, const WS &w, void *vol, bool adj) 
     A.ax[a].bh = static_cast<const T *>(d.bh[a]);
     A.ax[a].ah = static_cast<const T *>(d.ah[a]);
   }
+  A.fbuf = (int64_t)p.ns * 6 * A.F;
+  A.pbuf = (int64_t)p.ns * A.psi_src;
   A.dtmu = (T)(p.dt / kMu0);
   A.step = w.step;
   A.step_w = w.step;
+  A.done = w.done;
   const Tiling t = tiling(p);
   A.nbx = t.nbx;
   A.nby = t.nby;
   A.nbz = t.nbz;
   A.nblocks = t.nblocks;
   A.xcd = p.xcd;
+  A.kz = p.kz;
   A.nf = p.nf();
   A.zE = d.zE;
   A.vol = vol;
@@ -1126,6 +1544,40 @@ static void launch_e(const StepArgs<T> &A, int kb, int vx, int acc, bool adj, bo
   }
 }
 
+// fused step launch, by accumulator flavour and transform block
+template <typename T, int KB>
+static void launch_step_kb(const StepArgs<T> &A, int acc, bool adj, dim3 grid, dim3 block,
+                           size_t lds, hipStream_t st) {
+  if (!A.vol) {
+    hipLaunchKernelGGL((k_step<T, ACC_NONE, false, 1>), grid, block, lds, st, A);
+    return;
+  }
+  switch (acc) {
+    case FWD_ACC_F64:
+      if (adj) hipLaunchKernelGGL((k_step<T, ACC_F64, true, KB>), grid, block, lds, st, A);
+      else hipLaunchKernelGGL((k_step<T, ACC_F64, false, KB>), grid, block, lds, st, A);
+      break;
+    case FWD_ACC_KAHAN:
+      if (adj) hipLaunchKernelGGL((k_step<T, ACC_KAHAN, true, KB>), grid, block, lds, st, A);
+      else hipLaunchKernelGGL((k_step<T, ACC_KAHAN, false, KB>), grid, block, lds, st, A);
+      break;
+    default:
+      if (adj) hipLaunchKernelGGL((k_step<T, ACC_F32, true, KB>), grid, block, lds, st, A);
+      else hipLaunchKernelGGL((k_step<T, ACC_F32, false, KB>), grid, block, lds, st, A);
+  }
+}
+
+template <typename T>
+static void launch_step(const StepArgs<T> &A, int kb, int acc, bool adj, dim3 grid, dim3 block,
+                        size_t lds, hipStream_t st) {
+  switch (kb) {
+    case 1: launch_step_kb<T, 1>(A, acc, adj, grid, block, lds, st); break;
+    case 2: launch_step_kb<T, 2>(A, acc, adj, grid, block, lds, st); break;
+    case 4: launch_step_kb<T, 4>(A, acc, adj, grid, block, lds, st); break;
+    default: launch_step_kb<T, 8>(A, acc, adj, grid, block, lds, st);
+  }
+}
+
 template <typename T>
 static void launch_h(const StepArgs<T> &A, int vx, dim3 grid, dim3 block, hipStream_t st) {
   constexpr int VV = (int)(16 / sizeof(T));
@@ -1133,17 +1585,23 @@ static void launch_h(const StepArgs<T> &A, int vx, dim3 grid, dim3 block, hipStr
   else hipLaunchKernelGGL((k_update_h<T, VV>), grid, block, 0, st, A);
 }
 
-// enqueue one step (H update, E update); if ev != nullptr, record ev[0..2]
-// around the two kernels
+// enqueue one step (H update, E update; or the fused step); if ev !=
+// nullptr, record ev[0..2] around the two kernels (fused: ev[0] and ev[1]
+// before the one launch, ev[2] after it)
 template <typename T>
 static void enqueue_step(Plan &p, Dev &d, const WS &w, void *vol, bool adj, hipStream_t st,
                          hipEvent_t *ev) {
   StepArgs<T> A = make_args<T>(p, d, w, vol, adj);
   const dim3 block(p.bx, p.by), grid(A.nblocks);
   if (ev) (void)hipEventRecord(ev[0], st);
-  launch_h<T>(A, p.vx, grid, block, st);
-  if (ev) (void)hipEventRecord(ev[1], st);
-  launch_e<T>(A, p.kb, p.vx, p.acc, adj, false, grid, block, st);
+  if (p.sched == 1) {
+    if (ev) (void)hipEventRecord(ev[1], st);
+    launch_step<T>(A, p.kb, p.acc, adj, grid, block, tiling(p).lds, st);
+  } else {
+    launch_h<T>(A, p.vx, grid, block, st);
+    if (ev) (void)hipEventRecord(ev[1], st);
+    launch_e<T>(A, p.kb, p.vx, p.acc, adj, false, grid, block, st);
+  }
   if (ev) (void)hipEventRecord(ev[2], st);
 }
 
@@ -1194,8 +1652,8 @@ static void run_steps_t(Plan &p, Dev &d, const WS &w, void *vol, bool adj, int n
   }
   // graph of K steps, captured on a private stream and replayed on st
   char key[256];
-  snprintf(key, sizeof key, "%p/%p/%d/%d/%d/%d/%d/%d/%d/%llu/%llu", w.fields, vol, (int)adj, K,
-           p.bx, p.by, p.xcd, p.kb, p.vx, (unsigned long long)p.model_version,
+  snprintf(key, sizeof key, "%p/%p/%d/%d/%d/%d/%d/%d/%d/%d/%d/%llu/%llu", w.fields, vol, (int)adj,
+           K, p.bx, p.by, p.xcd, p.kb, p.vx, p.sched, p.kz, (unsigned long long)p.model_version,
            (unsigned long long)p.basis_version);
   if (!d.exec || d.exec_key != key) {
     if (d.exec) {
@@ -1288,7 +1746,7 @@ void dev_run_begin(Plan &p, void *ws, size_t ws_bytes, void *vol, size_t vol_byt
 void dev_run_steps(Plan &p, void *ws, void *vol, int nsteps, void *stream) {
   hipStream_t st = static_cast<hipStream_t>(stream);
   ensure_tables(p, st);
-  if (nsteps < 0) fail(FWD_ERR_INVALID_ARG, "nsteps < 0");
+  if (nsteps < 0 || nsteps > p.nt) fail(FWD_ERR_INVALID_ARG, "nsteps outside [0, nt]");
   Dev &d = D(p);
   run_steps_any(p, d, carve(p, ws), vol, false, nsteps, st);
 }
@@ -1427,7 +1885,7 @@ void dev_adjoint(Plan &p, void *ws, size_t ws_bytes, const void *vol, const doub
 }
 
 // ---------------------------------------------------------------------------
-// autotuner: time each (block shape, XCD remap) candidate on the real buffers
+// autotuner: time each candidate schedule and tiling on the real buffers
 // ---------------------------------------------------------------------------
 double dev_autotune(Plan &p, void *ws, size_t ws_bytes, void *vol, size_t vol_bytes, int mode,
                     int steps, void *stream) {
@@ -1438,23 +1896,34 @@ double dev_autotune(Plan &p, void *ws, size_t ws_bytes, void *vol, size_t vol_by
   ensure_tables(p, st);
   Dev &d = D(p);
   WS w = carve(p, ws);
-  const int cand[][2] = {{64, 4}, {64, 2}, {64, 1}, {32, 8}, {32, 4}, {32, 2}, {16, 16},
-                         {16, 4}, {128, 2}, {128, 1}, {256, 1}};
-  const int save_bx = p.bx, save_by = p.by, save_xcd = p.xcd, save_vx = p.vx,
-            save_sample = d.sample_every;
+  struct Cand {
+    int sched, bx, by, vx, kz;
+  };
+  std::vector<Cand> cand;
+  const int two[][2] = {{64, 4}, {64, 2}, {64, 1}, {32, 8}, {32, 4}, {32, 2}, {16, 16},
+                        {16, 4}, {128, 2}, {128, 1}, {256, 1}};
+  for (auto &c : two)
+    for (int vx : {1, 4}) cand.push_back({0, c[0], c[1], vx, p.kz});
+  const int fused[][2] = {{64, 4}, {64, 2}, {32, 8}, {32, 4}, {16, 16}, {16, 8}, {128, 2}};
+  for (auto &c : fused)
+    for (int kz : {4, 8, 16, 32}) cand.push_back({1, c[0], c[1], 1, kz});
+  const Cand save{p.sched, p.bx, p.by, p.vx, p.kz};
+  const int save_xcd = p.xcd, save_sample = d.sample_every;
   d.sample_every = 0;
   double best = 1e300;
-  int bbx = save_bx, bby = save_by, bxcd = save_xcd, bvx = save_vx;
+  Cand bc = save;
+  int bxcd = save_xcd;
   hipEvent_t e0, e1;
   HIP_CHECK(hipEventCreate(&e0));
   HIP_CHECK(hipEventCreate(&e1));
-  for (auto &c : cand)
-  for (int vx = 0; vx <= 1; ++vx) {
+  for (const Cand &c : cand) {
     for (int xc = 0; xc <= 1; ++xc) {
-      p.bx = c[0];
-      p.by = c[1];
+      p.sched = c.sched;
+      p.bx = c.bx;
+      p.by = c.by;
+      p.vx = c.vx;
+      p.kz = c.kz;
       p.xcd = xc;
-      p.vx = vx ? 4 : 1;
       zero_state(p, w, ws, adj ? nullptr : vol, mode, st);
       run_steps_any(p, d, w, vol, adj, 4, st);   // warm-up (graph capture)
       HIP_CHECK(hipEventRecord(e0, st));
@@ -1466,19 +1935,19 @@ double dev_autotune(Plan &p, void *ws, size_t ws_bytes, void *vol, size_t vol_by
       const double per = ms / steps;
       if (per < best) {
         best = per;
-        bbx = c[0];
-        bby = c[1];
+        bc = c;
         bxcd = xc;
-        bvx = p.vx;
       }
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  p.bx = bbx;
-  p.by = bby;
+  p.sched = bc.sched;
+  p.bx = bc.bx;
+  p.by = bc.by;
+  p.vx = bc.vx;
+  p.kz = bc.kz;
   p.xcd = bxcd;
-  p.vx = bvx;
   d.sample_every = save_sample;
   return best;
 }

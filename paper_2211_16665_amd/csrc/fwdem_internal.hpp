@@ -103,6 +103,8 @@ struct Plan {
   int graph_steps = 32, bx = 64, by = 4, xcd = 1, strict_cfl = 1;   // bx: threads along x
   int kb = 8;                            // samples per volume-transform block (1, 2, 4, 8)
   int vx = 1;                            // 1: one x node per thread; 4: a 16-byte vector
+  int sched = 0;                         // 0: H and E launches per step; 1: one fused launch
+  int kz = 8;                            // planes per block of the fused schedule
 
   // ---- device side (managed in device.hip) ----
   void *dev = nullptr;
@@ -118,7 +120,7 @@ struct Plan {
   size_t acc_bytes() const { return acc == FWD_ACC_F32 ? 8 : 16; }
   int64_t psi_elems_per_source() const;
   int64_t hist_elems_per_source() const { return kb > 2 ? (int64_t)(kb - 2) * 3 * field_elems() : 0; }
-  size_t state_bytes() const;       // fields + psi + receiver sums + step index
+  size_t state_bytes() const;       // fields + psi (double-buffered) + receiver sums + step index
   size_t workspace_bytes(int mode) const;
   size_t volume_bytes() const;
 };

@@ -28,10 +28,12 @@ int64_t Plan::psi_elems_per_source() const {
 }
 
 size_t Plan::state_bytes() const {
-  size_t b = align256((size_t)ns * 6 * field_elems() * tsize());
-  b += align256((size_t)ns * psi_elems_per_source() * tsize());
+  // fields and CPML memory are double-buffered: step n reads half n % 2 and
+  // writes the other half
+  size_t b = align256(2 * (size_t)ns * 6 * field_elems() * tsize());
+  b += align256(2 * (size_t)ns * psi_elems_per_source() * tsize());
   b += align256((size_t)ns * rn_c.size() * nf() * 16);
-  b += 256;  // step index and flush marker
+  b += 256;  // step index, flush marker, block counter
   b += align256((size_t)ns * hist_elems_per_source() * tsize());
   return b;
 }

@@ -305,27 +305,97 @@ def test_flush_midway_then_continue():
 # --------------------------------------------------------------------------
 # tiling and autotuning: the arithmetic of a cell does not depend on them
 # --------------------------------------------------------------------------
+TILINGS = [
+    dict(block_y=4, block_x=64, xcd_remap=1, vector=1),
+    dict(block_y=1, block_x=64, xcd_remap=0, vector=4),
+    dict(block_y=2, block_x=128, xcd_remap=1, vector=4),
+    dict(block_y=1, block_x=256, xcd_remap=0, vector=1),
+    dict(block_y=16, block_x=16, xcd_remap=1, vector=4),
+    dict(block_y=8, block_x=32, xcd_remap=0, vector=1),
+    # fused schedule: tiles of every shape, chunks of 1 plane to more than the grid
+    dict(schedule=1, block_y=4, block_x=64, xcd_remap=1, zchunk=8),
+    dict(schedule=1, block_y=8, block_x=32, xcd_remap=0, zchunk=3),
+    dict(schedule=1, block_y=1, block_x=64, xcd_remap=1, zchunk=1),
+    dict(schedule=1, block_y=16, block_x=16, xcd_remap=1, zchunk=64),
+    dict(schedule=1, block_y=2, block_x=128, xcd_remap=0, zchunk=5),
+    dict(schedule=1, block_y=4, block_x=16, xcd_remap=1, zchunk=2),
+]
+
+
+def _run_all(w, d, opts, adjoint, dtype="f32", acc="kahan"):
+    p = fw.Plan.from_workload(w, field_dtype=dtype, acc_mode=acc)
+    for key, v in opts.items():
+        p.set_option(getattr(fw, "FWD_OPT_" + key.upper()), v)
+    p.set_model(w.rho)
+    E, vol = p.forward(want_volume=True)
+    out = [E.cpu().numpy(), p.volume_export(vol).cpu().numpy()]
+    if adjoint:
+        p.basis_build(gamma_rel=1e-12)
+        g, Ea = p.adjoint(vol, torch.from_numpy(d).cuda() - E, want_adjoint_rec=True)
+        out += [g.cpu().numpy(), Ea.cpu().numpy()]
+    return out
+
+
 @pytest.mark.parametrize("adjoint", [False, True])
 def test_tilings_are_bitwise_identical(adjoint):
     w0, d = _inverse_problem(seed=6, ns=2)
-    say(f"tilings adjoint={adjoint}")
     results = []
-    for (by, bx, xcd, vx) in [(4, 64, 1, 1), (1, 64, 0, 4), (2, 128, 1, 4), (1, 256, 0, 1),
-                              (16, 16, 1, 4), (8, 32, 0, 1)]:
-        p = fw.Plan.from_workload(w0, field_dtype="f32", acc_mode="kahan")
-        for key, v in (("BLOCK_Y", by), ("BLOCK_X", bx), ("XCD_REMAP", xcd), ("VECTOR", vx)):
-            p.set_option(getattr(fw, "FWD_OPT_" + key), v)
-        p.set_model(w0.rho)
-        E, vol = p.forward(want_volume=True)
-        out = [E.cpu().numpy(), p.volume_export(vol).cpu().numpy()]
-        if adjoint:
-            p.basis_build(gamma_rel=1e-12)
-            g, Ea = p.adjoint(vol, torch.from_numpy(d).cuda() - E, want_adjoint_rec=True)
-            out += [g.cpu().numpy(), Ea.cpu().numpy()]
-        results.append(out)
+    for opts in TILINGS:
+        say(f"tilings adjoint={adjoint} {opts}")
+        results.append(_run_all(w0, d, opts, adjoint))
     for r in results[1:]:
         for a, b in zip(results[0], r):
             assert same(a, b)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_fused_schedule_on_the_marine_grid(dtype):
+    """Fused against two-kernel schedule on a window of the full marine grid
+    (many tiles and chunks, stretched axes, CPML on all sides): receivers,
+    volume transform, gradient and adjoint receiver transform bit for bit."""
+    w = with_window(c2_marine1d(), 96)
+    say(f"fused schedule on the marine grid, {dtype}")
+    p = fw.Plan.from_workload(w, field_dtype="f64")
+    p.set_model(w.rho)
+    d = p.forward().cpu().numpy() * 1.01
+    ref = _run_all(w, d, dict(schedule=0), True, dtype, "f64")
+    for opts in (dict(schedule=1, block_x=64, block_y=4, zchunk=8),
+                 dict(schedule=1, block_x=32, block_y=8, zchunk=7, xcd_remap=0)):
+        say(f"  {opts}")
+        out = _run_all(w, d, opts, True, dtype, "f64")
+        for a, b in zip(ref, out):
+            assert same(a, b)
+
+
+def test_fused_graph_odd_chunks_and_schedule_switch():
+    """Graphs of an odd number of steps (the double-buffer half alternates
+    between replays), eager launches, and a run that switches schedule
+    midway through a checkpoint: all equal bit for bit."""
+    w = tiny(seed=8, npml=3, ns=2)
+    say("fused: odd graph chunks, eager, schedule switch")
+    _, E1, _ = gpu_forward(w, "f32", "f64", schedule=1, graph_steps=7, zchunk=4)
+    _, E2, _ = gpu_forward(w, "f32", "f64", schedule=1, graph_steps=0, zchunk=4)
+    _, E3, _ = gpu_forward(w, "f32", "f64", schedule=0, graph_steps=16)
+    assert same(E1, E2) and same(E1, E3)
+    p = fw.Plan.from_workload(w, field_dtype="f32", acc_mode="f64")
+    p.set_model(w.rho)
+    nt = p.info.nt
+    E_full, vol_full = p.forward(want_volume=True)
+    vfull = p.volume_export(vol_full).cpu().numpy()
+    vol = p.volume_buffer()
+    p.run_begin(vol)
+    k = nt // 3 + 1                                 # odd number of steps done
+    p.run_steps(k, vol)
+    snap = torch.empty(p.checkpoint_size(True), dtype=torch.uint8, device="cuda")
+    p.checkpoint_save(snap, vol)
+    p.run_steps(5, vol)                             # diverge
+    p.checkpoint_restore(snap, vol)
+    p.set_option(fw.FWD_OPT_SCHEDULE, 1)
+    p.set_option(fw.FWD_OPT_GRAPH_STEPS, 9)
+    p.run_steps(nt - k, vol)
+    p.run_flush(vol)
+    assert same(p.run_receivers().cpu().numpy(), E_full.cpu().numpy())
+    assert same(p.volume_export(vol).cpu().numpy(), vfull)
 
 
 def test_autotune_keeps_results():
@@ -337,7 +407,8 @@ def test_autotune_keeps_results():
     E0 = E0.cpu().numpy()
     ms = p.autotune(fw.FWD_MODE_FORWARD, vol=vol, steps=8)
     assert ms > 0
-    cfg = [p.get_option(getattr(fw, "FWD_OPT_" + k)) for k in ("BLOCK_X", "BLOCK_Y", "XCD_REMAP", "VECTOR")]
-    say(f"autotuned: block {cfg[0]:.0f}x{cfg[1]:.0f}, xcd {cfg[2]:.0f}, vector {cfg[3]:.0f}: {ms:.4f} ms/step")
+    cfg = {k: int(p.get_option(getattr(fw, "FWD_OPT_" + k)))
+           for k in ("SCHEDULE", "BLOCK_X", "BLOCK_Y", "XCD_REMAP", "VECTOR", "ZCHUNK")}
+    say(f"autotuned: {cfg}: {ms:.4f} ms/step")
     E1 = p.forward(vol=vol, want_volume=True)[0].cpu().numpy()
     assert same(E0, E1)
