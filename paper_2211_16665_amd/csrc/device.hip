@@ -16,9 +16,12 @@
 //                the plane below carried in registers.
 // Fields and CPML memory are double-buffered: step n reads half n % 2 and
 // writes the other half, so no block of a launch reads a value that another
-// block has already overwritten.  The step index lives in device memory and
-// the last block of a step's final launch advances it, so a captured HIP
-// graph of K steps replays for any position in the run.
+// block has already overwritten.  The step index lives in device memory, in
+// two counters: the launches of a step read one (the last completed step)
+// and block 0 of its final launch writes the other, so no launch writes a
+// counter it reads; the host alternates the pair from step to step and
+// equalises them when it starts stepping.  A captured HIP graph of an even
+// number of steps therefore replays for any position in the run.
 //
 // The kernels are bound by memory traffic and latency (a 3D stencil plus an
 // accumulator sweep, ~0.1-0.8 flop/byte): no matrix cores.  Field layout
@@ -47,13 +50,10 @@ namespace fwdem {
 // ---------------------------------------------------------------------------
 // kernel parameter blocks
 // ---------------------------------------------------------------------------
-template <typename T>
-struct AxisDev {
-  const T *ih;     // 1/h   (n)
-  const T *ihd;    // 1/hd  (n+1)
-  const T *kn, *bn, *an;   // CPML at integer nodes: 1/kappa, b, a
-  const T *kh, *bh, *ah;   // CPML at half nodes
-};
+// Axis tables, one array [3 axes][8 tables][LA] (few pointers keep the
+// kernel arguments in scalar registers): 1/h (n), 1/hd (n+1), CPML 1/kappa,
+// b, a at integer nodes (n+1) and at half nodes (n).
+enum { AX_IH = 0, AX_IHD, AX_KN, AX_BN, AX_AN, AX_KH, AX_BH, AX_AH, AX_TABLES };
 
 template <typename T>
 struct StepArgs {
@@ -63,12 +63,12 @@ struct StepArgs {
   T *fields;          // [2][ns][6][F]: Ex Ey Ez Hx Hy Hz per source, two halves
   T *psi;             // [2][ns][psi_src]
   int64_t fbuf, pbuf; // elements per half of fields and of psi
-  const T *ce[3];     // dt/eps per edge component
-  AxisDev<T> ax[3];
+  const T *ce;        // [3][F] dt/eps per edge component
+  const T *axt;       // [3][AX_TABLES][LA] axis tables
+  int LA;
   T dtmu;             // dt / mu0
-  const int *step;    // index of the last completed step (device)
-  int *step_w;        // same, advanced by the last block of the step
-  unsigned *done;     // blocks of the current launch that have finished
+  const int *step;    // index of the last completed step (read by the step)
+  int *step_w;        // the other counter: set to this step by block 0
   // tiling: (bx x by) threads over x-y; two kernels: one plane per block,
   // each thread a vector of x nodes; fused: kz planes per block
   int nbx, nby, nbz, nblocks, xcd, kz;
@@ -151,20 +151,6 @@ __device__ __forceinline__ Half<T> half_of(const StepArgs<T> &A, int par, int s)
   return h;
 }
 
-// The last block to finish a step's final launch advances the step index
-// (every block read it at its start, before its own count) and re-arms the
-// block counter for the next launch.
-template <typename T>
-__device__ __forceinline__ void finish_step(const StepArgs<T> &A, int n) {
-  if (threadIdx.x == 0 && threadIdx.y == 0) {
-    const unsigned prev = atomicAdd(A.done, 1u);
-    if (prev + 1u == (unsigned)A.nblocks) {
-      atomicExch(A.done, 0u);
-      atomicExch(A.step_w, n);
-    }
-  }
-}
-
 // Vector of N consecutive x values of a field: N = 1 (one element per
 // thread) or N = 16 / sizeof(T) (one 16-byte access per field)
 template <typename T, int N_>
@@ -216,6 +202,11 @@ __device__ __forceinline__ Vec<T, 1> vec1(T x) {
   return r;
 }
 
+template <typename T>
+__device__ __forceinline__ T axv(const StepArgs<T> &A, int a, int t, int i) {
+  return A.axt[(a * AX_TABLES + t) * A.LA + i];
+}
+
 // ---------------------------------------------------------------------------
 // Per-node arithmetic shared by both schedules.  Explicit fused multiply-adds
 // fix the rounding, so both schedules give the same bits whatever the
@@ -234,31 +225,28 @@ __device__ __forceinline__ T stretch(T d, T &psi, T b, T a, T kinv) {
 template <typename T>
 __device__ __forceinline__ T hx_node(const StepArgs<T> &A, int j, int k, T h, T ez, T ez_jp, T ey,
                                      T ey_kp, bool py, T &psy, bool pz, T &psz) {
-  const AxisDev<T> &Y = A.ax[1], &Z = A.ax[2];
-  T d1 = (ez_jp - ez) * Y.ih[j];
-  T d2 = (ey_kp - ey) * Z.ih[k];
-  if (py) d1 = stretch(d1, psy, Y.bh[j], Y.ah[j], Y.kh[j]);
-  if (pz) d2 = stretch(d2, psz, Z.bh[k], Z.ah[k], Z.kh[k]);
+  T d1 = (ez_jp - ez) * axv(A, 1, AX_IH, j);
+  T d2 = (ey_kp - ey) * axv(A, 2, AX_IH, k);
+  if (py) d1 = stretch(d1, psy, axv(A, 1, AX_BH, j), axv(A, 1, AX_AH, j), axv(A, 1, AX_KH, j));
+  if (pz) d2 = stretch(d2, psz, axv(A, 2, AX_BH, k), axv(A, 2, AX_AH, k), axv(A, 2, AX_KH, k));
   return fma(-A.dtmu, d1 - d2, h);
 }
 template <typename T>
 __device__ __forceinline__ T hy_node(const StepArgs<T> &A, int i, int k, T h, T ex, T ex_kp, T ez,
                                      T ez_ip, bool pz, T &psz, bool px, T &psx) {
-  const AxisDev<T> &X = A.ax[0], &Z = A.ax[2];
-  T d1 = (ex_kp - ex) * Z.ih[k];
-  T d2 = (ez_ip - ez) * X.ih[i];
-  if (pz) d1 = stretch(d1, psz, Z.bh[k], Z.ah[k], Z.kh[k]);
-  if (px) d2 = stretch(d2, psx, X.bh[i], X.ah[i], X.kh[i]);
+  T d1 = (ex_kp - ex) * axv(A, 2, AX_IH, k);
+  T d2 = (ez_ip - ez) * axv(A, 0, AX_IH, i);
+  if (pz) d1 = stretch(d1, psz, axv(A, 2, AX_BH, k), axv(A, 2, AX_AH, k), axv(A, 2, AX_KH, k));
+  if (px) d2 = stretch(d2, psx, axv(A, 0, AX_BH, i), axv(A, 0, AX_AH, i), axv(A, 0, AX_KH, i));
   return fma(-A.dtmu, d1 - d2, h);
 }
 template <typename T>
 __device__ __forceinline__ T hz_node(const StepArgs<T> &A, int i, int j, T h, T ey, T ey_ip, T ex,
                                      T ex_jp, bool px, T &psx, bool py, T &psy) {
-  const AxisDev<T> &X = A.ax[0], &Y = A.ax[1];
-  T d1 = (ey_ip - ey) * X.ih[i];
-  T d2 = (ex_jp - ex) * Y.ih[j];
-  if (px) d1 = stretch(d1, psx, X.bh[i], X.ah[i], X.kh[i]);
-  if (py) d2 = stretch(d2, psy, Y.bh[j], Y.ah[j], Y.kh[j]);
+  T d1 = (ey_ip - ey) * axv(A, 0, AX_IH, i);
+  T d2 = (ex_jp - ex) * axv(A, 1, AX_IH, j);
+  if (px) d1 = stretch(d1, psx, axv(A, 0, AX_BH, i), axv(A, 0, AX_AH, i), axv(A, 0, AX_KH, i));
+  if (py) d2 = stretch(d2, psy, axv(A, 1, AX_BH, j), axv(A, 1, AX_AH, j), axv(A, 1, AX_KH, j));
   return fma(-A.dtmu, d1 - d2, h);
 }
 
@@ -268,31 +256,28 @@ __device__ __forceinline__ T hz_node(const StepArgs<T> &A, int i, int j, T h, T 
 template <typename T>
 __device__ __forceinline__ T ex_node(const StepArgs<T> &A, int j, int k, T e, T c, T hz, T hz_jm,
                                      T hy, T hy_km, bool py, T &psy, bool pz, T &psz) {
-  const AxisDev<T> &Y = A.ax[1], &Z = A.ax[2];
-  T d1 = (hz - hz_jm) * Y.ihd[j];
-  T d2 = (hy - hy_km) * Z.ihd[k];
-  if (py) d1 = stretch(d1, psy, Y.bn[j], Y.an[j], Y.kn[j]);
-  if (pz) d2 = stretch(d2, psz, Z.bn[k], Z.an[k], Z.kn[k]);
+  T d1 = (hz - hz_jm) * axv(A, 1, AX_IHD, j);
+  T d2 = (hy - hy_km) * axv(A, 2, AX_IHD, k);
+  if (py) d1 = stretch(d1, psy, axv(A, 1, AX_BN, j), axv(A, 1, AX_AN, j), axv(A, 1, AX_KN, j));
+  if (pz) d2 = stretch(d2, psz, axv(A, 2, AX_BN, k), axv(A, 2, AX_AN, k), axv(A, 2, AX_KN, k));
   return fma(c, d1 - d2, e);
 }
 template <typename T>
 __device__ __forceinline__ T ey_node(const StepArgs<T> &A, int i, int k, T e, T c, T hx, T hx_km,
                                      T hz, T hz_im, bool pz, T &psz, bool px, T &psx) {
-  const AxisDev<T> &X = A.ax[0], &Z = A.ax[2];
-  T d1 = (hx - hx_km) * Z.ihd[k];
-  T d2 = (hz - hz_im) * X.ihd[i];
-  if (pz) d1 = stretch(d1, psz, Z.bn[k], Z.an[k], Z.kn[k]);
-  if (px) d2 = stretch(d2, psx, X.bn[i], X.an[i], X.kn[i]);
+  T d1 = (hx - hx_km) * axv(A, 2, AX_IHD, k);
+  T d2 = (hz - hz_im) * axv(A, 0, AX_IHD, i);
+  if (pz) d1 = stretch(d1, psz, axv(A, 2, AX_BN, k), axv(A, 2, AX_AN, k), axv(A, 2, AX_KN, k));
+  if (px) d2 = stretch(d2, psx, axv(A, 0, AX_BN, i), axv(A, 0, AX_AN, i), axv(A, 0, AX_KN, i));
   return fma(c, d1 - d2, e);
 }
 template <typename T>
 __device__ __forceinline__ T ez_node(const StepArgs<T> &A, int i, int j, T e, T c, T hy, T hy_im,
                                      T hx, T hx_jm, bool px, T &psx, bool py, T &psy) {
-  const AxisDev<T> &X = A.ax[0], &Y = A.ax[1];
-  T d1 = (hy - hy_im) * X.ihd[i];
-  T d2 = (hx - hx_jm) * Y.ihd[j];
-  if (px) d1 = stretch(d1, psx, X.bn[i], X.an[i], X.kn[i]);
-  if (py) d2 = stretch(d2, psy, Y.bn[j], Y.an[j], Y.kn[j]);
+  T d1 = (hy - hy_im) * axv(A, 0, AX_IHD, i);
+  T d2 = (hx - hx_jm) * axv(A, 1, AX_IHD, j);
+  if (px) d1 = stretch(d1, psx, axv(A, 0, AX_BN, i), axv(A, 0, AX_AN, i), axv(A, 0, AX_KN, i));
+  if (py) d2 = stretch(d2, psy, axv(A, 1, AX_BN, j), axv(A, 1, AX_AN, j), axv(A, 1, AX_KN, j));
   return fma(c, d1 - d2, e);
 }
 
@@ -574,9 +559,9 @@ __device__ __forceinline__ void e_vec(const StepArgs<T> &A, int s, const Half<T>
   const V hxk = k >= 1 ? vload<VX>(O.hx + q - plane) : vzero<T, VX>();
   const T hzp = i0 >= 1 ? O.hz[q - 1] : T(0), hyp = i0 >= 1 ? O.hy[q - 1] : T(0);
   const V e0x = vload<VX>(I.ex + q), e0y = vload<VX>(I.ey + q), e0z = vload<VX>(I.ez + q);
-  const V cx = okx ? vload<VX>(A.ce[0] + q) : vzero<T, VX>();
-  const V cy = oky ? vload<VX>(A.ce[1] + q) : vzero<T, VX>();
-  const V cz = okz ? vload<VX>(A.ce[2] + q) : vzero<T, VX>();
+  const V cx = okx ? vload<VX>(A.ce + q) : vzero<T, VX>();
+  const V cy = oky ? vload<VX>(A.ce + A.F + q) : vzero<T, VX>();
+  const V cz = okz ? vload<VX>(A.ce + 2 * A.F + q) : vzero<T, VX>();
   const int64_t iY = ((int64_t)k * W + ly) * PX + i0;
   const int64_t iZ = ((int64_t)lz * NY + j) * PX + i0;
   V ps_ex_y = py && okx ? vload<VX>(P.psY + 2 * sY + iY) : vzero<T, VX>();
@@ -644,7 +629,10 @@ __global__ void __launch_bounds__(256) k_update_e(StepArgs<T> A) {
   __shared__ int s_n;
   int bx, by, bz;
   const int b = tile_of(A.nblocks, A.xcd, A.nbx, A.nby, bx, by, bz);
-  if (threadIdx.x == 0 && threadIdx.y == 0) s_n = A.step[0] + 1;
+  if (threadIdx.x == 0 && threadIdx.y == 0) {
+    s_n = A.step[0] + 1;
+    if (blockIdx.x == 0) A.step_w[0] = s_n;   // the step this launch completes
+  }
   __syncthreads();
   const int n = s_n;
   const int i0 = (bx * blockDim.x + threadIdx.x) * VX;
@@ -665,7 +653,6 @@ __global__ void __launch_bounds__(256) k_update_e(StepArgs<T> A) {
       e_vec<T, ACC, ADJ, KB, VX>(A, s, half_of(A, par, s), half_of(A, par ^ 1, s),
                                  half_of(A, 0, s), i0, j, k, n, fl, lo, hi);
   }
-  finish_step(A, n);
 }
 
 // ---------------------------------------------------------------------------
@@ -710,7 +697,10 @@ __global__ void __launch_bounds__(256) k_step(StepArgs<T> A) {
   const int x0 = tbx * BX, y0 = tby * BY;
   const int i = x0 + tx, j = y0 + ty;
   const int z0 = tbz * A.kz, z1 = min(z0 + A.kz, A.nz);
-  if (tx == 0 && ty == 0) s_n = A.step[0] + 1;
+  if (tx == 0 && ty == 0) {
+    s_n = A.step[0] + 1;
+    if (blockIdx.x == 0) A.step_w[0] = s_n;   // the step this launch completes
+  }
   __syncthreads();
   const int n = s_n, par = n & 1;
   const int fl = A.flushed[0];
@@ -901,8 +891,8 @@ __global__ void __launch_bounds__(256) k_step(StepArgs<T> A) {
         const bool okx = i_in && j_int && k_int;
         const bool oky = i_int && j_in && k_int;
         const bool okz = i_int && j_int;
-        const T cx = okx ? A.ce[0][q] : T(0), cy = oky ? A.ce[1][q] : T(0);
-        const T cz = okz ? A.ce[2][q] : T(0);
+        const T cx = okx ? A.ce[q] : T(0), cy = oky ? A.ce[A.F + q] : T(0);
+        const T cz = okz ? A.ce[2 * A.F + q] : T(0);
         const int64_t iYn = ((int64_t)k * W + lyn) * PX + i, iZn = ((int64_t)lzn * NY + j) * PX + i;
         const int64_t iXn = ((int64_t)k * NY + j) * W + lxn;
         T dummy = T(0);
@@ -948,7 +938,6 @@ __global__ void __launch_bounds__(256) k_step(StepArgs<T> A) {
       eyb = eyb1;
     }
   }
-  finish_step(A, n);
 }
 
 // Flush: add the samples of the incomplete last block (m_last % KB != 0)
@@ -1003,6 +992,15 @@ __global__ void __launch_bounds__(256) k_flush(StepArgs<T> A) {
 
 __global__ void k_set_flushed(int *flushed, const int *step) {
   if (threadIdx.x == 0 && blockIdx.x == 0) flushed[0] = step[0] + 1;
+}
+
+// both step counters to the last completed step (the larger of the two)
+__global__ void k_equalize(int *cnt) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    const int v = max(cnt[0], cnt[1]);
+    cnt[0] = v;
+    cnt[1] = v;
+  }
 }
 
 // receiver output: interpolate node transforms and scale per frequency
@@ -1082,9 +1080,9 @@ struct Dev {
   uint64_t model_version = 0, basis_version = 0;
   std::vector<DevBuf> bufs;     // everything allocated for the tables
   // typed views
-  void *ce[3] = {};
-  void *ih[3] = {}, *ihd[3] = {};
-  void *kn[3] = {}, *bn[3] = {}, *an[3] = {}, *kh[3] = {}, *bh[3] = {}, *ah[3] = {};
+  void *ce = nullptr;    // [3][F]
+  void *axt = nullptr;   // [3][AX_TABLES][LA]
+  int LA = 0;
   double2 *zE = nullptr, *Q = nullptr;
   double *wavelet = nullptr, *basis = nullptr;
   int *src_s = nullptr, *src_c = nullptr, *src_toff = nullptr;
@@ -1176,21 +1174,26 @@ void dev_release(Plan &p) {
 
 template <typename T>
 static void upload_model_tables(Plan &p, Dev &d) {
-  for (int c = 0; c < 3; ++c) d.ce[c] = upload_as<T>(d, p.ce[c]);
+  const int64_t F = p.field_elems();
+  std::vector<double> ce(3 * F);
+  for (int c = 0; c < 3; ++c) std::copy(p.ce[c].begin(), p.ce[c].end(), ce.begin() + c * F);
+  d.ce = upload_as<T>(d, ce);
+  const int LA = std::max(p.nx, std::max(p.ny, p.nz)) + 2;
+  std::vector<double> t((size_t)3 * AX_TABLES * LA, 0.0);
   for (int a = 0; a < 3; ++a) {
     const Axis &ax = p.ax[a];
-    std::vector<double> ih(ax.n), ihd(ax.n + 1);
-    for (int i = 0; i < ax.n; ++i) ih[i] = 1.0 / ax.h[i];
-    for (int i = 0; i <= ax.n; ++i) ihd[i] = 1.0 / ax.hd[i];
-    d.ih[a] = upload_as<T>(d, ih);
-    d.ihd[a] = upload_as<T>(d, ihd);
-    d.kn[a] = upload_as<T>(d, ax.kinv_n);
-    d.bn[a] = upload_as<T>(d, ax.b_n);
-    d.an[a] = upload_as<T>(d, ax.a_n);
-    d.kh[a] = upload_as<T>(d, ax.kinv_h);
-    d.bh[a] = upload_as<T>(d, ax.b_h);
-    d.ah[a] = upload_as<T>(d, ax.a_h);
+    double *b = t.data() + (size_t)a * AX_TABLES * LA;
+    for (int i = 0; i < ax.n; ++i) b[AX_IH * LA + i] = 1.0 / ax.h[i];
+    for (int i = 0; i <= ax.n; ++i) b[AX_IHD * LA + i] = 1.0 / ax.hd[i];
+    std::copy(ax.kinv_n.begin(), ax.kinv_n.end(), b + AX_KN * LA);
+    std::copy(ax.b_n.begin(), ax.b_n.end(), b + AX_BN * LA);
+    std::copy(ax.a_n.begin(), ax.a_n.end(), b + AX_AN * LA);
+    std::copy(ax.kinv_h.begin(), ax.kinv_h.end(), b + AX_KH * LA);
+    std::copy(ax.b_h.begin(), ax.b_h.end(), b + AX_BH * LA);
+    std::copy(ax.a_h.begin(), ax.a_h.end(), b + AX_AH * LA);
   }
+  d.axt = upload_as<T>(d, t);
+  d.LA = LA;
 }
 
 static void ensure_tables(Plan &p, hipStream_t stream) {
@@ -1286,9 +1289,8 @@ static void ensure_tables(Plan &p, hipStream_t stream) {
 struct WS {
   void *fields, *psi;   // two halves each
   double2 *racc;
-  int *step;            // index of the last completed step
+  int *step;            // [2] step counters (last completed step)
   int *flushed;         // last sample already added by a flush
-  unsigned *done;       // finished blocks of the running launch
   void *hist;
   double *gedge;
 };
@@ -1305,8 +1307,7 @@ static WS carve(const Plan &p, void *ws) {
   w.racc = reinterpret_cast<double2 *>(b);
   b += a256((size_t)p.ns * p.rn_c.size() * p.nf() * 16);
   w.step = reinterpret_cast<int *>(b);
-  w.flushed = w.step + 1;
-  w.done = reinterpret_cast<unsigned *>(w.step + 2);
+  w.flushed = w.step + 2;
   b += 256;
   w.hist = b;
   b += a256((size_t)p.ns * p.hist_elems_per_source() * p.tsize());
@@ -1433,8 +1434,10 @@ static void build_lists(Plan &p, Dev &d) {
   d.list_key = key;
 }
 
+// r: which step counter holds the last completed step (the launches read
+// counter r and write counter r ^ 1)
 template <typename T>
-static StepArgs<T> make_args(Plan &p, Dev &d, const WS &w, void *vol, bool adj) {
+static StepArgs<T> make_args(Plan &p, Dev &d, const WS &w, void *vol, bool adj, int r = 0) {
   StepArgs<T> A{};
   A.nx = p.nx;
   A.ny = p.ny;
@@ -1448,23 +1451,14 @@ static StepArgs<T> make_args(Plan &p, Dev &d, const WS &w, void *vol, bool adj) 
   A.psi_src = p.psi_elems_per_source();
   A.fields = static_cast<T *>(w.fields);
   A.psi = static_cast<T *>(w.psi);
-  for (int c = 0; c < 3; ++c) A.ce[c] = static_cast<const T *>(d.ce[c]);
-  for (int a = 0; a < 3; ++a) {
-    A.ax[a].ih = static_cast<const T *>(d.ih[a]);
-    A.ax[a].ihd = static_cast<const T *>(d.ihd[a]);
-    A.ax[a].kn = static_cast<const T *>(d.kn[a]);
-    A.ax[a].bn = static_cast<const T *>(d.bn[a]);
-    A.ax[a].an = static_cast<const T *>(d.an[a]);
-    A.ax[a].kh = static_cast<const T *>(d.kh[a]);
-    A.ax[a].bh = static_cast<const T *>(d.bh[a]);
-    A.ax[a].ah = static_cast<const T *>(d.ah[a]);
-  }
+  A.ce = static_cast<const T *>(d.ce);
+  A.axt = static_cast<const T *>(d.axt);
+  A.LA = d.LA;
   A.fbuf = (int64_t)p.ns * 6 * A.F;
   A.pbuf = (int64_t)p.ns * A.psi_src;
   A.dtmu = (T)(p.dt / kMu0);
-  A.step = w.step;
-  A.step_w = w.step;
-  A.done = w.done;
+  A.step = w.step + r;
+  A.step_w = w.step + (r ^ 1);
   const Tiling t = tiling(p);
   A.nbx = t.nbx;
   A.nby = t.nby;
@@ -1590,8 +1584,8 @@ static void launch_h(const StepArgs<T> &A, int vx, dim3 grid, dim3 block, hipStr
 // before the one launch, ev[2] after it)
 template <typename T>
 static void enqueue_step(Plan &p, Dev &d, const WS &w, void *vol, bool adj, hipStream_t st,
-                         hipEvent_t *ev) {
-  StepArgs<T> A = make_args<T>(p, d, w, vol, adj);
+                         hipEvent_t *ev, int r) {
+  StepArgs<T> A = make_args<T>(p, d, w, vol, adj, r);
   const dim3 block(p.bx, p.by), grid(A.nblocks);
   if (ev) (void)hipEventRecord(ev[0], st);
   if (p.sched == 1) {
@@ -1609,6 +1603,7 @@ template <typename T>
 static void flush_t(Plan &p, Dev &d, const WS &w, void *vol, bool adj, hipStream_t st) {
   if (p.kb == 1 || !vol) return;
   build_lists(p, d);
+  hipLaunchKernelGGL(k_equalize, dim3(1), dim3(64), 0, st, w.step);
   StepArgs<T> A = make_args<T>(p, d, w, vol, adj);
   launch_e<T>(A, p.kb, 1, p.acc, adj, true, dim3((p.NX + 63) / 64, p.NY, p.NZ), dim3(64), st);
   hipLaunchKernelGGL(k_set_flushed, dim3(1), dim3(64), 0, st, w.flushed, (const int *)w.step);
@@ -1626,7 +1621,11 @@ template <typename T>
 static void run_steps_t(Plan &p, Dev &d, const WS &w, void *vol, bool adj, int nsteps,
                         hipStream_t st) {
   build_lists(p, d);
-  const int K = p.graph_steps;
+  // both counters hold the last completed step; the steps then alternate
+  // (r = counter read by the next step)
+  hipLaunchKernelGGL(k_equalize, dim3(1), dim3(64), 0, st, w.step);
+  int r = 0;
+  const int K = p.graph_steps & ~1;   // graphs of an even number of steps start and end at r = 0
   const int sample = d.sample_every;
   // eager launches of m steps, each bracketed by events if asked
   auto eager = [&](int m, bool timed) {
@@ -1642,7 +1641,8 @@ static void run_steps_t(Plan &p, Dev &d, const WS &w, void *vol, bool adj, int n
         ev = &d.ev[(size_t)d.kstat_n * 3];
         d.kstat_n++;
       }
-      enqueue_step<T>(p, d, w, vol, adj, st, ev);
+      enqueue_step<T>(p, d, w, vol, adj, st, ev, r);
+      r ^= 1;
     }
     HIP_CHECK(hipGetLastError());
   };
@@ -1662,7 +1662,7 @@ static void run_steps_t(Plan &p, Dev &d, const WS &w, void *vol, bool adj, int n
     }
     hipGraph_t g = nullptr;
     HIP_CHECK(hipStreamBeginCapture(d.cap, hipStreamCaptureModeRelaxed));
-    for (int t = 0; t < K; ++t) enqueue_step<T>(p, d, w, vol, adj, d.cap, nullptr);
+    for (int t = 0; t < K; ++t) enqueue_step<T>(p, d, w, vol, adj, d.cap, nullptr, t & 1);
     const hipError_t le = hipGetLastError();
     const hipError_t ce = hipStreamEndCapture(d.cap, &g);   // always end the capture
     if (le != hipSuccess || ce != hipSuccess) {
@@ -1716,6 +1716,7 @@ static void zero_state(Plan &p, const WS &w, void *ws, void *vol, int mode, hipS
   HIP_CHECK(hipMemsetAsync(ws, 0, p.workspace_bytes(mode), st));
   if (vol && mode == FWD_MODE_FORWARD) HIP_CHECK(hipMemsetAsync(vol, 0, p.volume_bytes(), st));
   hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, st, w.step, -1);
+  hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, st, w.step + 1, -1);
   HIP_CHECK(hipGetLastError());
 }
 

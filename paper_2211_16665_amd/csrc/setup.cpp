@@ -33,7 +33,7 @@ size_t Plan::state_bytes() const {
   size_t b = align256(2 * (size_t)ns * 6 * field_elems() * tsize());
   b += align256(2 * (size_t)ns * psi_elems_per_source() * tsize());
   b += align256((size_t)ns * rn_c.size() * nf() * 16);
-  b += 256;  // step index, flush marker, block counter
+  b += 256;  // two step counters and the flush marker
   b += align256((size_t)ns * hist_elems_per_source() * tsize());
   return b;
 }
