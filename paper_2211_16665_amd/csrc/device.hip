@@ -25,10 +25,14 @@
 //
 // The kernels are bound by memory traffic and latency (a 3D stencil plus an
 // accumulator sweep, ~0.1-0.8 flop/byte): no matrix cores.  Field layout
-// [k][j][PX] (x fastest, PX a multiple of 64).  Threads loop over the batched
-// sources, so per-edge coefficients are shared by all sources.  A 1D grid is
-// remapped so that consecutive tiles of one XCD are spatial neighbours (their
-// halos hit the same L2).
+// [k][j][PX] (x fastest, PX a multiple of 64).  The batched sources are a
+// grid dimension (fastest), so the blocks of one tile for all sources run
+// side by side and share the per-edge coefficients in cache, and no thread
+// loops over sources (on this GPU a loop whose stores precede the next
+// iteration's loads waits for the stores: loads and stores share one
+// in-order completion counter).  The 1D grid is remapped so that the
+// consecutive blocks of one XCD are spatial neighbours (their halos hit the
+// same L2).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -71,13 +75,13 @@ struct StepArgs {
   int *step_w;        // the other counter: set to this step by block 0
   // tiling: (bx x by) threads over x-y; two kernels: one plane per block,
   // each thread a vector of x nodes; fused: kz planes per block
-  int nbx, nby, nbz, nblocks, xcd, kz;
+  int nbx, nby, nbz, nblocks, xcd, kz;   // nblocks = tiles * ns (the grid)
   // volume transform / gradient
   int nf;
   const double2 *zE;  // [nt][nf] z^{n+1}
   void *vol;          // [ns][nf][3][F] accumulators (forward) or forward transform (adjoint)
   const double2 *Q;   // [nt][nf] gradient weights (adjoint)
-  double *gedge;      // [3][F] gradient accumulators (adjoint)
+  double *gedge;      // [ns][3][F] gradient accumulators per source (adjoint)
   T *hist;            // [ns][kb-2][3][F] samples of the current transform block
   int64_t hist_src;   // history elements per source
   const int *flushed; // last sample already in the volume transform / gradient
@@ -92,21 +96,27 @@ struct StepArgs {
   int nn;               // receiver nodes
 };
 
-__device__ __forceinline__ int tile_of(int nblocks, int xcd, int nbx, int nby, int &bx, int &by,
-                                       int &bz) {
+// Block -> (tile, source).  Blocks b = tile * ns + s, sources fastest, so
+// the sources of a tile run side by side and share its coefficients in
+// cache.  With xcd on, the blocks (dealt round-robin to the 8 XCDs) are
+// remapped so that XCD x gets the contiguous range [base_x, base_x + cnt_x)
+// of b: spatial neighbours (and all sources of a tile) share one L2.
+// Returns the tile index; tile t = (bz * nby + by) * nbx + bx.
+__device__ __forceinline__ int tile_of(int nblocks, int xcd, int ns, int nbx, int nby, int &bx,
+                                       int &by, int &bz, int &s) {
   int b = blockIdx.x;
   if (xcd) {
-    // blocks are dealt round-robin to the 8 XCDs: give XCD x the tiles
-    // [base_x, base_x + cnt_x) so its blocks are spatial neighbours
     const int q = nblocks >> 3, r = nblocks & 7;
     const int x = b & 7, local = b >> 3;
     b = x * q + min(x, r) + local;
   }
-  bx = b % nbx;
-  const int t = b / nbx;
+  s = b % ns;
+  const int tile = b / ns;
+  bx = tile % nbx;
+  const int t = tile / nbx;
   by = t % nby;
   bz = t / nby;
-  return b;
+  return tile;
 }
 
 // slab index of a CPML node: half nodes i+1/2 with i < npml or i >= n-npml;
@@ -353,15 +363,14 @@ __device__ __forceinline__ void h_vec(const StepArgs<T> &A, const Half<T> &I, co
 
 template <typename T, int VX>
 __global__ void __launch_bounds__(256) k_update_h(StepArgs<T> A) {
-  int bx, by, bz;
-  tile_of(A.nblocks, A.xcd, A.nbx, A.nby, bx, by, bz);
+  int bx, by, bz, s;
+  tile_of(A.nblocks, A.xcd, A.ns, A.nbx, A.nby, bx, by, bz, s);
   const int par = (A.step[0] + 1) & 1;   // this step reads half par
   const int i0 = (bx * blockDim.x + threadIdx.x) * VX;
   const int j = by * blockDim.y + threadIdx.y;
   const int k = bz;
   if (i0 > A.nx || j > A.ny || k > A.nz) return;
-  for (int s = 0; s < A.ns; ++s)
-    h_vec<T, VX>(A, half_of(A, par, s), half_of(A, par ^ 1, s), i0, j, k);
+  h_vec<T, VX>(A, half_of(A, par, s), half_of(A, par ^ 1, s), i0, j, k);
 }
 
 // ---------------------------------------------------------------------------
@@ -477,7 +486,7 @@ __device__ __forceinline__ void post_e(const StepArgs<T> &A, int s, int c, int64
             re = fma(val[t], Qt.x * v.x - Qt.y * v.y, re);
           }
         }
-        A.gedge[(int64_t)c * A.F + q + e] += re;
+        A.gedge[((int64_t)s * 3 + c) * A.F + q + e] += re;
       }
     }
   }
@@ -627,8 +636,8 @@ __device__ __forceinline__ void e_vec(const StepArgs<T> &A, int s, const Half<T>
 template <typename T, int ACC, bool ADJ, int KB, int VX>
 __global__ void __launch_bounds__(256) k_update_e(StepArgs<T> A) {
   __shared__ int s_n;
-  int bx, by, bz;
-  const int b = tile_of(A.nblocks, A.xcd, A.nbx, A.nby, bx, by, bz);
+  int bx, by, bz, s;
+  const int b = tile_of(A.nblocks, A.xcd, A.ns, A.nbx, A.nby, bx, by, bz, s);
   if (threadIdx.x == 0 && threadIdx.y == 0) {
     s_n = A.step[0] + 1;
     if (blockIdx.x == 0) A.step_w[0] = s_n;   // the step this launch completes
@@ -649,9 +658,8 @@ __global__ void __launch_bounds__(256) k_update_e(StepArgs<T> A) {
       hi = A.tl_off[tt + slot + 1];
     }
     const int par = n & 1;
-    for (int s = 0; s < A.ns; ++s)
-      e_vec<T, ACC, ADJ, KB, VX>(A, s, half_of(A, par, s), half_of(A, par ^ 1, s),
-                                 half_of(A, 0, s), i0, j, k, n, fl, lo, hi);
+    e_vec<T, ACC, ADJ, KB, VX>(A, s, half_of(A, par, s), half_of(A, par ^ 1, s), half_of(A, 0, s),
+                               i0, j, k, n, fl, lo, hi);
   }
 }
 
@@ -691,8 +699,8 @@ __global__ void __launch_bounds__(256) k_step(StepArgs<T> A) {
   const int SE = WE * (BY + 2), SH = WH * (BY + 1);
   T *sEx = reinterpret_cast<T *>(lds_raw), *sEy = sEx + SE, *sEz = sEy + SE;
   T *sHx = sEz + SE, *sHy = sHx + SH, *sHz = sHy + SH;
-  int tbx, tby, tbz;
-  const int b = tile_of(A.nblocks, A.xcd, A.nbx, A.nby, tbx, tby, tbz);
+  int tbx, tby, tbz, s;
+  const int b = tile_of(A.nblocks, A.xcd, A.ns, A.nbx, A.nby, tbx, tby, tbz, s);
   const int tx = threadIdx.x, ty = threadIdx.y;
   const int x0 = tbx * BX, y0 = tby * BY;
   const int i = x0 + tx, j = y0 + ty;
@@ -730,7 +738,7 @@ __global__ void __launch_bounds__(256) k_step(StepArgs<T> A) {
   const bool pyb = npml > 0 && haloB && pml_half(jb, A.ny, npml, lyb);
   const int own = (ty + 1) * WE + tx + 1, ownH = (ty + 1) * WH + tx + 1;
 
-  for (int s = 0; s < A.ns; ++s) {
+  {
     const Half<T> I = half_of(A, par, s), O = half_of(A, par ^ 1, s), P = half_of(A, 0, s);
     const int kbeg = z0 > 0 ? z0 - 1 : 0;
     T ex = ld(A, I.ex, i, j, kbeg), ey = ld(A, I.ey, i, j, kbeg), ez = ld(A, I.ez, i, j, kbeg);
@@ -959,11 +967,11 @@ __global__ void __launch_bounds__(256) k_flush(StepArgs<T> A) {
                       i >= 1 && i < A.nx && j < A.ny && k >= 1 && k < A.nz,
                       i >= 1 && i < A.nx && j >= 1 && j < A.ny && k < A.nz};
   const int nf = A.nf;
-  double g[3] = {0.0, 0.0, 0.0};
   for (int s = 0; s < A.ns; ++s) {
     const T *f = A.fields + (m_last & 1) * A.fbuf + (int64_t)s * 6 * A.F;
     for (int c = 0; c < 3; ++c) {
       if (!ok[c]) continue;
+      double g = 0.0;
       const T *h = A.hist + (int64_t)s * A.hist_src + (int64_t)c * A.F + q;
       const int64_t base = ((int64_t)s * nf * 3 + c) * A.F + q;
       for (int rr = 1; rr <= r_end; ++rr) {
@@ -978,15 +986,12 @@ __global__ void __launch_bounds__(256) k_flush(StepArgs<T> A) {
           } else {
             const double2 Vk = acc_read<ACC>(A.vol, base + (int64_t)kf * 3 * A.F);
             const double2 Qt = A.Q[(int64_t)(mm - 1) * nf + kf];
-            g[c] += v * (Qt.x * Vk.x - Qt.y * Vk.y);
+            g += v * (Qt.x * Vk.x - Qt.y * Vk.y);
           }
         }
       }
+      if constexpr (ADJ) A.gedge[((int64_t)s * 3 + c) * A.F + q] += g;
     }
-  }
-  if constexpr (ADJ) {
-    for (int c = 0; c < 3; ++c)
-      if (ok[c]) A.gedge[(int64_t)c * A.F + q] += g[c];
   }
 }
 
@@ -1023,7 +1028,8 @@ __global__ void k_rec_out(int ns, int nrows, int nn, int nf, const int *ptr, con
 // gradient per cell from the 12 edges of the cell: with volume-weighted
 // edge averaging, dV_e * d sigma_e / d sigma_c = V_c / 4 for every edge of
 // the cell, so d phi / d ln rho_c = sigma_c V_c / 4 * sum_edges gacc * gscale
-__global__ void k_grad_cells(int nx, int ny, int nz, int PX, int NY, int64_t F,
+// (gacc summed over the sources)
+__global__ void k_grad_cells(int nx, int ny, int nz, int ns, int PX, int NY, int64_t F,
                              const double *gedge, const double *cellfac, double gscale,
                              double *grad, int accumulate) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1032,10 +1038,20 @@ __global__ void k_grad_cells(int nx, int ny, int nz, int PX, int NY, int64_t F,
   if (i >= nx) return;
   const int64_t plane = (int64_t)NY * PX;
   const int64_t q = (int64_t)k * plane + (int64_t)j * PX + i;
-  const double *gx = gedge, *gy = gedge + F, *gz = gedge + 2 * F;
-  const double sx = gx[q] + gx[q + PX] + gx[q + plane] + gx[q + plane + PX];
-  const double sy = gy[q] + gy[q + 1] + gy[q + plane] + gy[q + plane + 1];
-  const double sz = gz[q] + gz[q + 1] + gz[q + PX] + gz[q + PX + 1];
+  const int64_t ox[4] = {0, PX, plane, plane + PX}, oy[4] = {0, 1, plane, plane + 1},
+                oz[4] = {0, 1, PX, PX + 1};
+  double ex[4] = {0, 0, 0, 0}, ey[4] = {0, 0, 0, 0}, ez[4] = {0, 0, 0, 0};
+  for (int s = 0; s < ns; ++s) {
+    const double *gx = gedge + (int64_t)s * 3 * F, *gy = gx + F, *gz = gx + 2 * F;
+    for (int e = 0; e < 4; ++e) {
+      ex[e] += gx[q + ox[e]];
+      ey[e] += gy[q + oy[e]];
+      ez[e] += gz[q + oz[e]];
+    }
+  }
+  const double sx = ex[0] + ex[1] + ex[2] + ex[3];
+  const double sy = ey[0] + ey[1] + ey[2] + ey[3];
+  const double sz = ez[0] + ez[1] + ez[2] + ez[3];
   const int64_t c = ((int64_t)k * ny + j) * nx + i;
   const double v = cellfac[c] * (sx + sy + sz) * gscale;
   grad[c] = accumulate ? grad[c] + v : v;
@@ -1463,7 +1479,7 @@ static StepArgs<T> make_args(Plan &p, Dev &d, const WS &w, void *vol, bool adj, 
   A.nbx = t.nbx;
   A.nby = t.nby;
   A.nbz = t.nbz;
-  A.nblocks = t.nblocks;
+  A.nblocks = t.nblocks * p.ns;
   A.xcd = p.xcd;
   A.kz = p.kz;
   A.nf = p.nf();
@@ -1866,7 +1882,7 @@ void dev_adjoint(Plan &p, void *ws, size_t ws_bytes, const void *vol, const doub
   // gradient on cells
   const double gscale = 1.0 / (p.src_scale * adj_scale);
   hipLaunchKernelGGL(k_grad_cells, dim3((p.nx + 127) / 128, p.ny, p.nz), dim3(128), 0, st, p.nx,
-                     p.ny, p.nz, p.PX, p.NY, p.field_elems(), w.gedge, d.cellfac, gscale, grad,
+                     p.ny, p.nz, p.ns, p.PX, p.NY, p.field_elems(), w.gedge, d.cellfac, gscale, grad,
                      accumulate);
   HIP_CHECK(hipGetLastError());
   const int nrows = p.nr * p.ncomp, nn = (int)p.rn_c.size(), n = p.ns * nrows * p.nf();

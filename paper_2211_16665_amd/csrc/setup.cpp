@@ -40,7 +40,8 @@ size_t Plan::state_bytes() const {
 
 size_t Plan::workspace_bytes(int mode) const {
   size_t b = state_bytes();
-  if (mode == FWD_MODE_ADJOINT) b += align256((size_t)3 * field_elems() * 8);
+  // adjoint: gradient accumulators per source and edge (FP64)
+  if (mode == FWD_MODE_ADJOINT) b += align256((size_t)ns * 3 * field_elems() * 8);
   return b;
 }
 
