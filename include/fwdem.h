@@ -228,7 +228,7 @@ enum {
   FWD_OPT_STRICT_CFL = 5,    /* 1 (default): fwd_set_model rejects a fixed dt above the CFL
                                 bound with FWD_ERR_CFL; 0 lets it run (and typically end in
                                 FWD_ERR_NONFINITE) */
-  FWD_OPT_DFT_BLOCK = 6,     /* 1, 2, 4 or 8 (default): samples per read-modify-write of the
+  FWD_OPT_DFT_BLOCK = 6,     /* 1, 2, 4, 8 (default) or 16: samples per read-modify-write of the
                                 volume transform (and of the gradient product).  The E update
                                 holds the last two samples; the others wait in a history buffer
                                 of the workspace.  Changes only the order of the sums.  Set it
@@ -242,7 +242,9 @@ enum {
                                 E and H planes with their halo in LDS and marches up in z,
                                 recomputing the H halo of its tile.  Same arithmetic per edge:
                                 results equal those of schedule 0 bit for bit */
-  FWD_OPT_ZCHUNK = 9         /* planes per block of the fused schedule: 1 .. 64 (default 8) */
+  FWD_OPT_ZCHUNK = 9,        /* planes per block of the fused schedule: 1 .. 64 (default 8) */
+  FWD_OPT_TILE_ORDER = 10    /* 0 (default): tiles numbered x fastest; 1: z fastest, so the
+                                blocks of neighbouring planes run side by side */
 };
 fwd_status fwd_set_option(fwd_plan *plan, int key, double value);
 fwd_status fwd_get_option(const fwd_plan *plan, int key, double *value);

@@ -258,7 +258,8 @@ fwd_status fwd_set_option(fwd_plan *h, int key, double value) {
         p.strict_cfl = v ? 1 : 0;
         break;
       case FWD_OPT_DFT_BLOCK:
-        if (v != 1 && v != 2 && v != 4 && v != 8) fail(FWD_ERR_INVALID_ARG, "block in {1,2,4,8}");
+        if (v != 1 && v != 2 && v != 4 && v != 8 && v != 16)
+          fail(FWD_ERR_INVALID_ARG, "transform block in {1,2,4,8,16}");
         p.kb = v;
         break;
 
@@ -273,6 +274,10 @@ fwd_status fwd_set_option(fwd_plan *h, int key, double value) {
       case FWD_OPT_ZCHUNK:
         if (v < 1 || v > 64) fail(FWD_ERR_INVALID_ARG, "planes per block in [1, 64]");
         p.kz = v;
+        break;
+      case FWD_OPT_TILE_ORDER:
+        if (v != 0 && v != 1) fail(FWD_ERR_INVALID_ARG, "tile order in {0, 1}");
+        p.order = v;
         break;
       default:
         fail(FWD_ERR_INVALID_ARG, "unknown option");
@@ -295,6 +300,7 @@ fwd_status fwd_get_option(const fwd_plan *h, int key, double *value) {
       case FWD_OPT_VECTOR: *value = p.vx; break;
       case FWD_OPT_SCHEDULE: *value = p.sched; break;
       case FWD_OPT_ZCHUNK: *value = p.kz; break;
+      case FWD_OPT_TILE_ORDER: *value = p.order; break;
       default: fail(FWD_ERR_INVALID_ARG, "unknown option");
     }
   });

@@ -76,6 +76,7 @@ struct StepArgs {
   // tiling: (bx x by) threads over x-y; two kernels: one plane per block,
   // each thread a vector of x nodes; fused: kz planes per block
   int nbx, nby, nbz, nblocks, xcd, kz;   // nblocks = tiles * ns (the grid)
+  int order;          // tile numbering: 0 x fastest, 1 z fastest
   // volume transform / gradient
   int nf;
   const double2 *zE;  // [nt][nf] z^{n+1}
@@ -101,9 +102,12 @@ struct StepArgs {
 // cache.  With xcd on, the blocks (dealt round-robin to the 8 XCDs) are
 // remapped so that XCD x gets the contiguous range [base_x, base_x + cnt_x)
 // of b: spatial neighbours (and all sources of a tile) share one L2.
-// Returns the tile index; tile t = (bz * nby + by) * nbx + bx.
-__device__ __forceinline__ int tile_of(int nblocks, int xcd, int ns, int nbx, int nby, int &bx,
-                                       int &by, int &bz, int &s) {
+// Tiles are numbered x fastest, t = (bz * nby + by) * nbx + bx (order 0),
+// or z fastest, t = (by * nbx + bx) * nbz + bz (order 1: the blocks of
+// consecutive planes of a column tile run side by side, so the plane
+// neighbours a stencil reads are still in L2).  Returns the tile index.
+__device__ __forceinline__ int tile_of(int nblocks, int xcd, int order, int ns, int nbx, int nby,
+                                       int nbz, int &bx, int &by, int &bz, int &s) {
   int b = blockIdx.x;
   if (xcd) {
     const int q = nblocks >> 3, r = nblocks & 7;
@@ -112,10 +116,17 @@ __device__ __forceinline__ int tile_of(int nblocks, int xcd, int ns, int nbx, in
   }
   s = b % ns;
   const int tile = b / ns;
-  bx = tile % nbx;
-  const int t = tile / nbx;
-  by = t % nby;
-  bz = t / nby;
+  if (order) {
+    bz = tile % nbz;
+    const int t = tile / nbz;
+    bx = t % nbx;
+    by = t / nbx;
+  } else {
+    bx = tile % nbx;
+    const int t = tile / nbx;
+    by = t % nby;
+    bz = t / nby;
+  }
   return tile;
 }
 
@@ -364,7 +375,7 @@ __device__ __forceinline__ void h_vec(const StepArgs<T> &A, const Half<T> &I, co
 template <typename T, int VX>
 __global__ void __launch_bounds__(256) k_update_h(StepArgs<T> A) {
   int bx, by, bz, s;
-  tile_of(A.nblocks, A.xcd, A.ns, A.nbx, A.nby, bx, by, bz, s);
+  tile_of(A.nblocks, A.xcd, A.order, A.ns, A.nbx, A.nby, A.nbz, bx, by, bz, s);
   const int par = (A.step[0] + 1) & 1;   // this step reads half par
   const int i0 = (bx * blockDim.x + threadIdx.x) * VX;
   const int j = by * blockDim.y + threadIdx.y;
@@ -457,22 +468,24 @@ __device__ __forceinline__ void post_e(const StepArgs<T> &A, int s, int c, int64
 #pragma unroll
     for (int e = 0; e < VX; ++e) {
       if (!((ok >> e) & 1u)) continue;
-      double val[KB];
+      // the samples in the field type; those already added by a flush are
+      // zeroed with a select (the condition is the same for every thread),
+      // so the twiddle loads stay free to be issued together
+      T val[KB];
 #pragma unroll
-      for (int t = 0; t < KB - 2; ++t) val[t] = (double)hv[t].v[e];
-      if constexpr (KB >= 2) val[KB - 2] = (double)e0.v[e];
-      val[KB - 1] = (double)e1.v[e];
+      for (int t = 0; t < KB - 2; ++t) val[t] = hv[t].v[e];
+      if constexpr (KB >= 2) val[KB - 2] = e0.v[e];
+      val[KB - 1] = e1.v[e];
 #pragma unroll
-      for (int t = 0; t < KB; ++t)
-        if (first + t <= fl) val[t] = 0.0;
+      for (int t = 0; t < KB; ++t) val[t] = first + t <= fl ? T(0) : val[t];
       if constexpr (!ADJ) {
         for (int kf = 0; kf < nf; ++kf) {
           double2 sum = make_double2(0.0, 0.0);
 #pragma unroll
           for (int t = 0; t < KB; ++t) {
             const double2 z = A.zE[(int64_t)(first - 1 + t) * nf + kf];
-            sum.x = fma(val[t], z.x, sum.x);
-            sum.y = fma(val[t], z.y, sum.y);
+            sum.x = fma((double)val[t], z.x, sum.x);
+            sum.y = fma((double)val[t], z.y, sum.y);
           }
           acc_add<ACC>(A.vol, base + (int64_t)kf * 3 * A.F + e, sum);
         }
@@ -483,7 +496,7 @@ __device__ __forceinline__ void post_e(const StepArgs<T> &A, int s, int c, int64
 #pragma unroll
           for (int t = 0; t < KB; ++t) {
             const double2 Qt = A.Q[(int64_t)(first - 1 + t) * nf + kf];
-            re = fma(val[t], Qt.x * v.x - Qt.y * v.y, re);
+            re = fma((double)val[t], Qt.x * v.x - Qt.y * v.y, re);
           }
         }
         A.gedge[((int64_t)s * 3 + c) * A.F + q + e] += re;
@@ -637,7 +650,7 @@ template <typename T, int ACC, bool ADJ, int KB, int VX>
 __global__ void __launch_bounds__(256) k_update_e(StepArgs<T> A) {
   __shared__ int s_n;
   int bx, by, bz, s;
-  const int b = tile_of(A.nblocks, A.xcd, A.ns, A.nbx, A.nby, bx, by, bz, s);
+  const int b = tile_of(A.nblocks, A.xcd, A.order, A.ns, A.nbx, A.nby, A.nbz, bx, by, bz, s);
   if (threadIdx.x == 0 && threadIdx.y == 0) {
     s_n = A.step[0] + 1;
     if (blockIdx.x == 0) A.step_w[0] = s_n;   // the step this launch completes
@@ -700,7 +713,7 @@ __global__ void __launch_bounds__(256) k_step(StepArgs<T> A) {
   T *sEx = reinterpret_cast<T *>(lds_raw), *sEy = sEx + SE, *sEz = sEy + SE;
   T *sHx = sEz + SE, *sHy = sHx + SH, *sHz = sHy + SH;
   int tbx, tby, tbz, s;
-  const int b = tile_of(A.nblocks, A.xcd, A.ns, A.nbx, A.nby, tbx, tby, tbz, s);
+  const int b = tile_of(A.nblocks, A.xcd, A.order, A.ns, A.nbx, A.nby, A.nbz, tbx, tby, tbz, s);
   const int tx = threadIdx.x, ty = threadIdx.y;
   const int x0 = tbx * BX, y0 = tby * BY;
   const int i = x0 + tx, j = y0 + ty;
@@ -1371,7 +1384,7 @@ static Tiling tiling(const Plan &p) {
 static void build_lists(Plan &p, Dev &d) {
   const Tiling t = tiling(p);
   char key[128];
-  snprintf(key, sizeof key, "%d/%d/%d/%d/%d/%llu", p.bx, p.by, p.vx, p.sched, p.kz,
+  snprintf(key, sizeof key, "%d/%d/%d/%d/%d/%d/%llu", p.bx, p.by, p.vx, p.sched, p.kz, p.order,
            (unsigned long long)p.model_version);
   if (d.list_key == key) return;
   free_lists(d);
@@ -1387,19 +1400,22 @@ static void build_lists(Plan &p, Dev &d) {
       const int64_t plane = (int64_t)p.NY * p.PX;
       const int k = (int)(idx / plane), j = (int)((idx % plane) / p.PX), i = (int)(idx % p.PX);
       if (i > p.nx || j > p.ny || k > p.nz) fail(FWD_ERR_INVALID_ARG, "entry outside the grid");
-      int b, slot, sub;
+      int bxi, byi, bzi, slot, sub;
       if (p.sched == 1) {
         if (k >= p.nz) return;   // no E update on the top plane: never used
-        const int zc = k / p.kz;
+        bzi = k / p.kz;
         sub = k % p.kz;
-        b = (zc * t.nby + j / p.by) * t.nbx + i / p.bx;
+        bxi = i / p.bx;
         slot = (j % p.by) * p.bx + (i % p.bx);
       } else {
         const int tx = i / t.vx;
         sub = i % t.vx;
-        b = (k * t.nby + j / p.by) * t.nbx + tx / p.bx;
+        bzi = k;
+        bxi = tx / p.bx;
         slot = (j % p.by) * p.bx + (tx % p.bx);
       }
+      byi = j / p.by;
+      const int b = p.order ? (byi * t.nbx + bxi) * t.nbz + bzi : (bzi * t.nby + byi) * t.nbx + bxi;
       ents.push_back({b, slot, make_int2(c | (kind << 2) | (sub << 3) | (s << 9), ref)});
     };
     if (mode == 0) {
@@ -1482,6 +1498,7 @@ static StepArgs<T> make_args(Plan &p, Dev &d, const WS &w, void *vol, bool adj, 
   A.nblocks = t.nblocks * p.ns;
   A.xcd = p.xcd;
   A.kz = p.kz;
+  A.order = p.order;
   A.nf = p.nf();
   A.zE = d.zE;
   A.vol = vol;
@@ -1550,7 +1567,8 @@ static void launch_e(const StepArgs<T> &A, int kb, int vx, int acc, bool adj, bo
     case 1: launch_e_kb<T, 1>(A, vx, acc, adj, flush, grid, block, st); break;
     case 2: launch_e_kb<T, 2>(A, vx, acc, adj, flush, grid, block, st); break;
     case 4: launch_e_kb<T, 4>(A, vx, acc, adj, flush, grid, block, st); break;
-    default: launch_e_kb<T, 8>(A, vx, acc, adj, flush, grid, block, st);
+    case 8: launch_e_kb<T, 8>(A, vx, acc, adj, flush, grid, block, st); break;
+    default: launch_e_kb<T, 16>(A, vx, acc, adj, flush, grid, block, st);
   }
 }
 
@@ -1584,7 +1602,8 @@ static void launch_step(const StepArgs<T> &A, int kb, int acc, bool adj, dim3 gr
     case 1: launch_step_kb<T, 1>(A, acc, adj, grid, block, lds, st); break;
     case 2: launch_step_kb<T, 2>(A, acc, adj, grid, block, lds, st); break;
     case 4: launch_step_kb<T, 4>(A, acc, adj, grid, block, lds, st); break;
-    default: launch_step_kb<T, 8>(A, acc, adj, grid, block, lds, st);
+    case 8: launch_step_kb<T, 8>(A, acc, adj, grid, block, lds, st); break;
+    default: launch_step_kb<T, 16>(A, acc, adj, grid, block, lds, st);
   }
 }
 
@@ -1668,9 +1687,9 @@ static void run_steps_t(Plan &p, Dev &d, const WS &w, void *vol, bool adj, int n
   }
   // graph of K steps, captured on a private stream and replayed on st
   char key[256];
-  snprintf(key, sizeof key, "%p/%p/%d/%d/%d/%d/%d/%d/%d/%d/%d/%llu/%llu", w.fields, vol, (int)adj,
-           K, p.bx, p.by, p.xcd, p.kb, p.vx, p.sched, p.kz, (unsigned long long)p.model_version,
-           (unsigned long long)p.basis_version);
+  snprintf(key, sizeof key, "%p/%p/%d/%d/%d/%d/%d/%d/%d/%d/%d/%d/%llu/%llu", w.fields, vol,
+           (int)adj, K, p.bx, p.by, p.xcd, p.kb, p.vx, p.sched, p.kz, p.order,
+           (unsigned long long)p.model_version, (unsigned long long)p.basis_version);
   if (!d.exec || d.exec_key != key) {
     if (d.exec) {
       HIP_CHECK(hipGraphExecDestroy(d.exec));
@@ -1914,17 +1933,19 @@ double dev_autotune(Plan &p, void *ws, size_t ws_bytes, void *vol, size_t vol_by
   Dev &d = D(p);
   WS w = carve(p, ws);
   struct Cand {
-    int sched, bx, by, vx, kz;
+    int sched, bx, by, vx, kz, order;
   };
   std::vector<Cand> cand;
-  const int two[][2] = {{64, 4}, {64, 2}, {64, 1}, {32, 8}, {32, 4}, {32, 2}, {16, 16},
-                        {16, 4}, {128, 2}, {128, 1}, {256, 1}};
-  for (auto &c : two)
-    for (int vx : {1, 4}) cand.push_back({0, c[0], c[1], vx, p.kz});
-  const int fused[][2] = {{64, 4}, {64, 2}, {32, 8}, {32, 4}, {16, 16}, {16, 8}, {128, 2}};
-  for (auto &c : fused)
-    for (int kz : {4, 8, 16, 32}) cand.push_back({1, c[0], c[1], 1, kz});
-  const Cand save{p.sched, p.bx, p.by, p.vx, p.kz};
+  const int two[][2] = {{64, 4}, {64, 2}, {64, 1}, {32, 8}, {32, 4}, {16, 16},
+                        {16, 8}, {16, 4}, {128, 2}, {256, 1}};
+  for (int order : {0, 1}) {
+    for (auto &c : two)
+      for (int vx : {1, 4}) cand.push_back({0, c[0], c[1], vx, p.kz, order});
+    const int fused[][2] = {{64, 4}, {32, 8}, {16, 16}, {16, 8}};
+    for (auto &c : fused)
+      for (int kz : {2, 4, 8}) cand.push_back({1, c[0], c[1], 1, kz, order});
+  }
+  const Cand save{p.sched, p.bx, p.by, p.vx, p.kz, p.order};
   const int save_xcd = p.xcd, save_sample = d.sample_every;
   d.sample_every = 0;
   double best = 1e300;
@@ -1940,6 +1961,7 @@ double dev_autotune(Plan &p, void *ws, size_t ws_bytes, void *vol, size_t vol_by
       p.by = c.by;
       p.vx = c.vx;
       p.kz = c.kz;
+      p.order = c.order;
       p.xcd = xc;
       zero_state(p, w, ws, adj ? nullptr : vol, mode, st);
       run_steps_any(p, d, w, vol, adj, 4, st);   // warm-up (graph capture)
@@ -1964,6 +1986,7 @@ double dev_autotune(Plan &p, void *ws, size_t ws_bytes, void *vol, size_t vol_by
   p.by = bc.by;
   p.vx = bc.vx;
   p.kz = bc.kz;
+  p.order = bc.order;
   p.xcd = bxcd;
   d.sample_every = save_sample;
   return best;

@@ -262,7 +262,7 @@ def test_autograd_gradient_matches_finite_differences():
 # --------------------------------------------------------------------------
 # transform blocking (FWD_OPT_DFT_BLOCK): changes only the order of the sums
 # --------------------------------------------------------------------------
-@pytest.mark.parametrize("kb", [1, 2, 4, 8])
+@pytest.mark.parametrize("kb", [1, 2, 4, 8, 16])
 def test_transform_block_sizes_agree(kb):
     w0, d = _inverse_problem(seed=5, ns=2)
     w0 = w0.replace(nt=w0.nt + 3)            # not a multiple of the block: flush path
@@ -282,10 +282,13 @@ def test_transform_block_sizes_agree(kb):
     assert np.linalg.norm(g - go) / np.linalg.norm(go) < 1e-7
 
 
-def test_flush_midway_then_continue():
+@pytest.mark.parametrize("kb,sched", [(8, 0), (16, 0), (16, 1)])
+def test_flush_midway_then_continue(kb, sched):
     w = tiny(seed=12, npml=3, ns=1)
-    say("flush midway")
+    say(f"flush midway, transform block {kb}, schedule {sched}")
     p = fw.Plan.from_workload(w, field_dtype="f64")
+    p.set_option(fw.FWD_OPT_DFT_BLOCK, kb)
+    p.set_option(fw.FWD_OPT_SCHEDULE, sched)
     p.set_model(w.rho)
     nt = p.info.nt
     E_full, vol_full = p.forward(want_volume=True)
@@ -319,6 +322,9 @@ TILINGS = [
     dict(schedule=1, block_y=16, block_x=16, xcd_remap=1, zchunk=64),
     dict(schedule=1, block_y=2, block_x=128, xcd_remap=0, zchunk=5),
     dict(schedule=1, block_y=4, block_x=16, xcd_remap=1, zchunk=2),
+    dict(schedule=0, block_y=4, block_x=16, xcd_remap=1, vector=1, tile_order=1),
+    dict(schedule=0, block_y=2, block_x=64, xcd_remap=0, vector=4, tile_order=1),
+    dict(schedule=1, block_y=8, block_x=16, xcd_remap=1, zchunk=3, tile_order=1),
 ]
 
 
@@ -408,7 +414,7 @@ def test_autotune_keeps_results():
     ms = p.autotune(fw.FWD_MODE_FORWARD, vol=vol, steps=8)
     assert ms > 0
     cfg = {k: int(p.get_option(getattr(fw, "FWD_OPT_" + k)))
-           for k in ("SCHEDULE", "BLOCK_X", "BLOCK_Y", "XCD_REMAP", "VECTOR", "ZCHUNK")}
+           for k in ("SCHEDULE", "BLOCK_X", "BLOCK_Y", "XCD_REMAP", "VECTOR", "ZCHUNK", "TILE_ORDER")}
     say(f"autotuned: {cfg}: {ms:.4f} ms/step")
     E1 = p.forward(vol=vol, want_volume=True)[0].cpu().numpy()
     assert same(E0, E1)
