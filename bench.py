@@ -59,6 +59,23 @@ def algorithmic_bytes_e_forward(nx, ny, nz, npml, nf, tsize=4, accsize=16, kb=8)
     return int(edges * per_edge + psi * 2 * tsize), edges
 
 
+def algorithmic_bytes_h(nx, ny, nz, npml, tsize=4):
+    """Algorithmic HBM bytes of one launch of the H update: each H node read
+    and written (2 tsize), each E node read once (tsize), a CPML memory
+    variable read + write (2 tsize) per derivative taken inside a layer."""
+    n_hx, n_hy, n_hz = (nx + 1) * ny * nz, nx * (ny + 1) * nz, nx * ny * (nz + 1)
+    n_ex, n_ey, n_ez = nx * (ny + 1) * (nz + 1), (nx + 1) * ny * (nz + 1), (nx + 1) * (ny + 1) * nz
+
+    def in_pml_half(n):     # half nodes 0..n-1 inside a layer
+        return sum(1 for i in range(n) if i < npml or i >= n - npml)
+
+    px, py, pz = in_pml_half(nx), in_pml_half(ny), in_pml_half(nz)
+    # derivatives along y and z for H_x, z and x for H_y, x and y for H_z
+    psi = ((nx + 1) * py * nz + (nx + 1) * ny * pz + nx * (ny + 1) * pz + px * (ny + 1) * nz
+           + px * ny * (nz + 1) + nx * py * (nz + 1))
+    return int((n_hx + n_hy + n_hz) * 2 * tsize + (n_ex + n_ey + n_ez) * tsize + psi * 2 * tsize)
+
+
 def cpu_baseline(w, steps=400):
     """Oracle (NumPy FP64, single process) stepping the full grid of the
     workload with the volume transform for a bounded window of steps."""
@@ -79,7 +96,8 @@ def cpu_baseline(w, steps=400):
                       f"one process ({dt:.1f} s); host {os.cpu_count()} logical CPUs"}
 
 
-TILING_KEYS = ("BLOCK_X", "BLOCK_Y", "XCD_REMAP", "VECTOR")
+TILING_KEYS = ("SCHEDULE", "BLOCK_X", "BLOCK_Y", "XCD_REMAP", "VECTOR", "VECTOR_H", "TILE_ORDER",
+               "ZCHUNK")
 
 
 def set_tiling(plan, spec):
@@ -235,7 +253,7 @@ def main():
     else:
         tune_ms = plan.autotune(fw.FWD_MODE_FORWARD, vol=vol, steps=32)
     tuned = {k.lower(): int(plan.get_option(getattr(fw, "FWD_OPT_" + k)))
-             for k in ("BLOCK_X", "BLOCK_Y", "XCD_REMAP", "DFT_BLOCK", "VECTOR")}
+             for k in TILING_KEYS + ("DFT_BLOCK",)}
     tuned["ms_per_forward_step"] = tune_ms
     plan.set_option(fw.FWD_OPT_SAMPLE_EVERY, args.sample_every)
     grad = torch.zeros(plan.shape, dtype=torch.float64, device="cuda")
@@ -277,14 +295,26 @@ def main():
     kb = int(plan.get_option(fw.FWD_OPT_DFT_BLOCK))
     bytes_e, edges = algorithmic_bytes_e_forward(nx, ny, nz, w_true.npml, len(w_true.freqs),
                                                  tsize, accsize, kb)
+    bytes_h = algorithmic_bytes_h(nx, ny, nz, w_true.npml, tsize)
+    h_ms = avg("fwd", 0)[0]
     e_ms, n_samp = avg("fwd", 1)
+    fused = tuned["schedule"] == 1
+    if fused:
+        # one launch per step: E and H each read once (no re-read of E by the
+        # H update nor of H by the E update)
+        n_cells_nodes = (nx + 1) * (ny + 1) * (nz + 1)
+        bytes_e = bytes_e + bytes_h - 2 * 3 * n_cells_nodes * tsize
     achieved = bytes_e / (e_ms * 1e-3) / 1e9
     tiling = ",".join(str(tuned[k.lower()]) for k in TILING_KEYS)
-    kernel_tag = f"k_update_e<float,F64,fwd,{kb}>"
+    kernel_tag = f"k_step<float,F64,fwd,{kb}>" if fused else f"k_update_e<float,F64,fwd,{kb}>"
     mt = measured_traffic(kernel_tag) if args.field_dtype == "f32" and args.acc == "f64" else None
     traffic, traffic_tiling = mt if mt else (None, None)
     kern = {name: {"fwd_ms": avg("fwd", k)[0], "adj_ms": avg("adj", k)[0]}
             for k, name in enumerate(("update_h", "update_e"))}
+    if not fused:
+        kern["update_h"]["fwd_algorithmic_gbs"] = bytes_h / (h_ms * 1e-3) / 1e9
+        kern["update_h"]["bytes_per_launch"] = bytes_h
+    kern["update_e"]["fwd_algorithmic_gbs"] = achieved
     out = {
         "metric": "Mcell-updates/s",
         "value": value,

@@ -233,9 +233,9 @@ enum {
                                 holds the last two samples; the others wait in a history buffer
                                 of the workspace.  Changes only the order of the sums.  Set it
                                 before fwd_workspace_size. */
-  FWD_OPT_VECTOR = 7,        /* 1 (default): each stencil thread updates one x node; 4: a
-                                16-byte vector of consecutive x nodes (4 in FP32, 2 in FP64);
-                                two-kernel schedule only */
+  FWD_OPT_VECTOR = 7,        /* 1 (default): each thread of the E update updates one x node;
+                                4: a 16-byte vector of consecutive x nodes (4 in FP32, 2 in
+                                FP64); two-kernel schedule only */
   FWD_OPT_SCHEDULE = 8,      /* 0 (default): two launches per step (H update, then E update);
                                 1: one fused launch per step -- each block owns a block_x x
                                 block_y column tile and a chunk of FWD_OPT_ZCHUNK planes, stages
@@ -243,8 +243,9 @@ enum {
                                 recomputing the H halo of its tile.  Same arithmetic per edge:
                                 results equal those of schedule 0 bit for bit */
   FWD_OPT_ZCHUNK = 9,        /* planes per block of the fused schedule: 1 .. 64 (default 8) */
-  FWD_OPT_TILE_ORDER = 10    /* 0 (default): tiles numbered x fastest; 1: z fastest, so the
+  FWD_OPT_TILE_ORDER = 10,   /* 0 (default): tiles numbered x fastest; 1: z fastest, so the
                                 blocks of neighbouring planes run side by side */
+  FWD_OPT_VECTOR_H = 11      /* as FWD_OPT_VECTOR, for the H update */
 };
 fwd_status fwd_set_option(fwd_plan *plan, int key, double value);
 fwd_status fwd_get_option(const fwd_plan *plan, int key, double *value);

@@ -279,6 +279,10 @@ fwd_status fwd_set_option(fwd_plan *h, int key, double value) {
         if (v != 0 && v != 1) fail(FWD_ERR_INVALID_ARG, "tile order in {0, 1}");
         p.order = v;
         break;
+      case FWD_OPT_VECTOR_H:
+        if (v != 1 && v != 4) fail(FWD_ERR_INVALID_ARG, "vector option in {1, 4}");
+        p.vxh = v;
+        break;
       default:
         fail(FWD_ERR_INVALID_ARG, "unknown option");
     }
@@ -301,6 +305,7 @@ fwd_status fwd_get_option(const fwd_plan *h, int key, double *value) {
       case FWD_OPT_SCHEDULE: *value = p.sched; break;
       case FWD_OPT_ZCHUNK: *value = p.kz; break;
       case FWD_OPT_TILE_ORDER: *value = p.order; break;
+      case FWD_OPT_VECTOR_H: *value = p.vxh; break;
       default: fail(FWD_ERR_INVALID_ARG, "unknown option");
     }
   });

@@ -1355,7 +1355,7 @@ struct Tiling {
   size_t lds;   // dynamic LDS bytes per block (fused)
 };
 
-static Tiling tiling(const Plan &p) {
+static Tiling tiling(const Plan &p, bool h_update = false) {
   if (p.bx * p.by > 256) fail(FWD_ERR_INVALID_ARG, "block x * block y must be <= 256");
   Tiling t;
   if (p.sched == 1) {
@@ -1365,7 +1365,8 @@ static Tiling tiling(const Plan &p) {
     t.nbz = (p.nz + p.kz - 1) / p.kz;
     t.lds = 3 * ((size_t)(p.bx + 2) * (p.by + 2) + (size_t)(p.bx + 1) * (p.by + 1)) * p.tsize();
   } else {
-    t.vx = p.vx == 1 ? 1 : (int)(16 / p.tsize());
+    const int v = h_update ? p.vxh : p.vx;   // the H update has its own vector width
+    t.vx = v == 1 ? 1 : (int)(16 / p.tsize());
     t.nbx = (p.NX + p.bx * t.vx - 1) / (p.bx * t.vx);
     t.nby = (p.NY + p.by - 1) / p.by;
     t.nbz = p.NZ;
@@ -1627,7 +1628,11 @@ static void enqueue_step(Plan &p, Dev &d, const WS &w, void *vol, bool adj, hipS
     if (ev) (void)hipEventRecord(ev[1], st);
     launch_step<T>(A, p.kb, p.acc, adj, grid, block, tiling(p).lds, st);
   } else {
-    launch_h<T>(A, p.vx, grid, block, st);
+    StepArgs<T> Ah = A;
+    const Tiling th = tiling(p, true);
+    Ah.nbx = th.nbx;
+    Ah.nblocks = th.nblocks * p.ns;
+    launch_h<T>(Ah, p.vxh, dim3(Ah.nblocks), block, st);
     if (ev) (void)hipEventRecord(ev[1], st);
     launch_e<T>(A, p.kb, p.vx, p.acc, adj, false, grid, block, st);
   }
@@ -1687,8 +1692,8 @@ static void run_steps_t(Plan &p, Dev &d, const WS &w, void *vol, bool adj, int n
   }
   // graph of K steps, captured on a private stream and replayed on st
   char key[256];
-  snprintf(key, sizeof key, "%p/%p/%d/%d/%d/%d/%d/%d/%d/%d/%d/%d/%llu/%llu", w.fields, vol,
-           (int)adj, K, p.bx, p.by, p.xcd, p.kb, p.vx, p.sched, p.kz, p.order,
+  snprintf(key, sizeof key, "%p/%p/%d/%d/%d/%d/%d/%d/%d/%d/%d/%d/%d/%llu/%llu", w.fields, vol,
+           (int)adj, K, p.bx, p.by, p.xcd, p.kb, p.vx, p.vxh, p.sched, p.kz, p.order,
            (unsigned long long)p.model_version, (unsigned long long)p.basis_version);
   if (!d.exec || d.exec_key != key) {
     if (d.exec) {
@@ -1933,19 +1938,20 @@ double dev_autotune(Plan &p, void *ws, size_t ws_bytes, void *vol, size_t vol_by
   Dev &d = D(p);
   WS w = carve(p, ws);
   struct Cand {
-    int sched, bx, by, vx, kz, order;
+    int sched, bx, by, vx, vxh, kz, order;
   };
   std::vector<Cand> cand;
   const int two[][2] = {{64, 4}, {64, 2}, {64, 1}, {32, 8}, {32, 4}, {16, 16},
                         {16, 8}, {16, 4}, {128, 2}, {256, 1}};
   for (int order : {0, 1}) {
     for (auto &c : two)
-      for (int vx : {1, 4}) cand.push_back({0, c[0], c[1], vx, p.kz, order});
+      for (int v : {0, 1, 2})   // vector widths (E, H): (1, 1), (1, 4), (4, 4)
+        cand.push_back({0, c[0], c[1], v == 2 ? 4 : 1, v ? 4 : 1, p.kz, order});
     const int fused[][2] = {{64, 4}, {32, 8}, {16, 16}, {16, 8}};
     for (auto &c : fused)
-      for (int kz : {2, 4, 8}) cand.push_back({1, c[0], c[1], 1, kz, order});
+      for (int kz : {2, 4, 8}) cand.push_back({1, c[0], c[1], 1, 1, kz, order});
   }
-  const Cand save{p.sched, p.bx, p.by, p.vx, p.kz, p.order};
+  const Cand save{p.sched, p.bx, p.by, p.vx, p.vxh, p.kz, p.order};
   const int save_xcd = p.xcd, save_sample = d.sample_every;
   d.sample_every = 0;
   double best = 1e300;
@@ -1960,6 +1966,7 @@ double dev_autotune(Plan &p, void *ws, size_t ws_bytes, void *vol, size_t vol_by
       p.bx = c.bx;
       p.by = c.by;
       p.vx = c.vx;
+      p.vxh = c.vxh;
       p.kz = c.kz;
       p.order = c.order;
       p.xcd = xc;
@@ -1985,6 +1992,7 @@ double dev_autotune(Plan &p, void *ws, size_t ws_bytes, void *vol, size_t vol_by
   p.bx = bc.bx;
   p.by = bc.by;
   p.vx = bc.vx;
+  p.vxh = bc.vxh;
   p.kz = bc.kz;
   p.order = bc.order;
   p.xcd = bxcd;

@@ -102,7 +102,8 @@ struct Plan {
   // ---- options ----
   int graph_steps = 32, bx = 64, by = 4, xcd = 1, strict_cfl = 1;   // bx: threads along x
   int kb = 8;                            // samples per volume-transform block (1, 2, 4, 8, 16)
-  int vx = 1;                            // 1: one x node per thread; 4: a 16-byte vector
+  int vx = 1;                            // E update: 1 x node per thread; 4: a 16-byte vector
+  int vxh = 1;                           // the same for the H update
   int sched = 0;                         // 0: H and E launches per step; 1: one fused launch
   int kz = 8;                            // planes per block of the fused schedule
   int order = 0;                         // tile numbering: 0 x fastest, 1 z fastest

@@ -28,7 +28,7 @@ FWD_MODE_FORWARD, FWD_MODE_ADJOINT = 0, 1
  FWD_TAB_CPML_Z, FWD_TAB_BASIS, FWD_TAB_EDGE_SIGMA) = range(8)
 (FWD_OPT_GRAPH_STEPS, FWD_OPT_BLOCK_X, FWD_OPT_BLOCK_Y, FWD_OPT_XCD_REMAP,
  FWD_OPT_SAMPLE_EVERY, FWD_OPT_STRICT_CFL, FWD_OPT_DFT_BLOCK, FWD_OPT_VECTOR,
- FWD_OPT_SCHEDULE, FWD_OPT_ZCHUNK, FWD_OPT_TILE_ORDER) = range(11)
+ FWD_OPT_SCHEDULE, FWD_OPT_ZCHUNK, FWD_OPT_TILE_ORDER, FWD_OPT_VECTOR_H) = range(12)
 
 ACC_MODES = {"f64": FWD_ACC_F64, "kahan": FWD_ACC_KAHAN, "f32": FWD_ACC_F32}
 DTYPES = {"f32": FWD_F32, "f64": FWD_F64}

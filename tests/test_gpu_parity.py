@@ -324,6 +324,8 @@ TILINGS = [
     dict(schedule=1, block_y=4, block_x=16, xcd_remap=1, zchunk=2),
     dict(schedule=0, block_y=4, block_x=16, xcd_remap=1, vector=1, tile_order=1),
     dict(schedule=0, block_y=2, block_x=64, xcd_remap=0, vector=4, tile_order=1),
+    dict(schedule=0, block_y=4, block_x=16, xcd_remap=1, vector=1, vector_h=4),
+    dict(schedule=0, block_y=8, block_x=32, xcd_remap=0, vector=4, vector_h=4, tile_order=1),
     dict(schedule=1, block_y=8, block_x=16, xcd_remap=1, zchunk=3, tile_order=1),
 ]
 
@@ -414,7 +416,7 @@ def test_autotune_keeps_results():
     ms = p.autotune(fw.FWD_MODE_FORWARD, vol=vol, steps=8)
     assert ms > 0
     cfg = {k: int(p.get_option(getattr(fw, "FWD_OPT_" + k)))
-           for k in ("SCHEDULE", "BLOCK_X", "BLOCK_Y", "XCD_REMAP", "VECTOR", "ZCHUNK", "TILE_ORDER")}
+           for k in ("SCHEDULE", "BLOCK_X", "BLOCK_Y", "XCD_REMAP", "VECTOR", "VECTOR_H", "ZCHUNK", "TILE_ORDER")}
     say(f"autotuned: {cfg}: {ms:.4f} ms/step")
     E1 = p.forward(vol=vol, want_volume=True)[0].cpu().numpy()
     assert same(E0, E1)
