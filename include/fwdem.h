@@ -216,6 +216,31 @@ fwd_status fwd_adjoint(fwd_plan *plan, void *ws_dev, size_t ws_bytes,
                        double *grad_dev, int accumulate, double *E_adj_dev,
                        void *stream);
 
+/* Time-domain adjoint and gradient (Appendix, alternative adjoint
+ * formulation, applied to the stepped system): the exact derivative of
+ * phi = 1/2 ||W (d - E)||^2 with respect to ln rho, with no basis
+ * functions.  A forward run stores the core state (fields, CPML memory,
+ * counters) every `segment` steps; then, from the last segment to the first,
+ * the segment is replayed from its checkpoint and the transposed leapfrog
+ * steps (including the transposed CPML recursions) run backward, driven at
+ * the receiver nodes by d phi / d E^m = -Re sum_k C_k z_k^m, C_k = sum
+ * w conj(resid) norm_k.  The gradient product on every updated edge is
+ * sum_n Eadj^{n+1} (E^{n+1} - E^n) / sigma_e (discrete eq. chainrule),
+ * mapped to cells by the transpose of the conductivity averaging.  Unlike
+ * fwd_adjoint (eq. gradsigmaij) it is exact inside the CPML layers too.
+ *   ws_dev       forward workspace, fwd_workspace_size(FWD_MODE_FORWARD)
+ *   scratch_dev  fwd_adjoint_td_size(segment) bytes of device memory
+ *                (checkpoints, the E of one segment, adjoint state)
+ *   segment      steps between checkpoints (>= 1)
+ *   resid_dev    complex [nsrc][nrec][ncomp][nfreq], W^2 (d - E)
+ *   grad_dev     double [nz][ny][nx], added to if accumulate != 0
+ * Errors: STATE (no model), INVALID_ARG (sizes, segment), HIP.  Costs about
+ * three forward runs (forward, replay, reverse sweep). */
+fwd_status fwd_adjoint_td_size(const fwd_plan *plan, int segment, size_t *bytes);
+fwd_status fwd_adjoint_td(fwd_plan *plan, void *ws_dev, size_t ws_bytes, void *scratch_dev,
+                          size_t scratch_bytes, int segment, const double *resid_dev,
+                          double *grad_dev, int accumulate, void *stream);
+
 /* Tuning knobs (FWD_OPT_*); value semantics per key.  Host only. */
 enum {
   FWD_OPT_GRAPH_STEPS = 0,   /* steps per captured HIP graph (0 or 1: launch eagerly); default 32 */

@@ -228,6 +228,29 @@ fwd_status fwd_adjoint(fwd_plan *h, void *ws, size_t ws_bytes, const void *vol,
   });
 }
 
+fwd_status fwd_adjoint_td_size(const fwd_plan *h, int segment, size_t *bytes) {
+  return guard([&] {
+    const Plan &p = P(h);
+    if (!bytes) fail(FWD_ERR_INVALID_ARG, "bytes is NULL");
+    if (!p.have_model) fail(FWD_ERR_STATE, "no model set");
+    if (segment < 1) fail(FWD_ERR_INVALID_ARG, "segment must be >= 1");
+    *bytes = p.td_scratch_bytes(segment);
+  });
+}
+
+fwd_status fwd_adjoint_td(fwd_plan *h, void *ws, size_t ws_bytes, void *scratch,
+                          size_t scratch_bytes, int segment, const double *resid, double *grad,
+                          int accumulate, void *stream) {
+  return guard([&] {
+    Plan &p = P(h);
+    if (!p.have_model) fail(FWD_ERR_STATE, "no model set");
+    if (!ws || !scratch || !resid || !grad)
+      fail(FWD_ERR_INVALID_ARG, "workspace, scratch, residual and gradient are required");
+    dev_adjoint_td(p, ws, ws_bytes, scratch, scratch_bytes, segment, resid, grad, accumulate,
+                   stream);
+  });
+}
+
 fwd_status fwd_set_option(fwd_plan *h, int key, double value) {
   return guard([&] {
     Plan &p = P(h);

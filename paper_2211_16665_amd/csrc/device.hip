@@ -1021,6 +1021,232 @@ __global__ void k_equalize(int *cnt) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Time-domain adjoint (the Appendix formulation applied to the stepped
+// system).  Reverse step n is the transpose of forward step n, undone in
+// reverse order: first its E update, then its H update.  The adjoint state
+// holds a multiplier per field value and per CPML memory variable (same
+// layout as one half of the forward state).  For one stretched derivative
+// d = D kinv + psi', psi' = b psi + a D (inside a layer; else d = D), the
+// transpose maps the multiplier ad of d and apsi' of psi' to
+//     aD = ad kinv + a (ad + apsi'),   apsi = b (ad + apsi').
+//   k_td_e     per H node: the deferred update of its own H multipliers,
+//              then aH += D_h^T aD over the E edges that difference it
+//              (ad = +-ce aE on those edges);
+//   k_td_h     per E edge: the update of its own E multipliers and the
+//              gradient product aE (E^{n+1} - E^n) / (sigma_e dV_e), then
+//              aE += D_e^T aD over the H nodes that difference it
+//              (ad = -+dt/mu aH);
+//   k_td_sens  the sensitivity of the misfit to E^m at the receiver nodes.
+// Every kernel reads its neighbours' multipliers and writes only its own;
+// each node's own update is deferred to the next kernel, so no neighbour
+// reads a value that has already moved on.
+// ---------------------------------------------------------------------------
+
+// aD / hd of derivative d (1 or 2) of the E update of component c at edge
+// (i, j, k); 0 where the edge is not updated.  Derivatives: E_x d1 = d/dy,
+// d2 = d/dz; E_y d1 = d/dz, d2 = d/dx; E_z d1 = d/dx, d2 = d/dy.
+template <typename T>
+__device__ __forceinline__ T td_ad_e(const StepArgs<T> &A, const Half<T> &Ad, int c, int d, int i,
+                                     int j, int k) {
+  bool ok;
+  if (c == 0) ok = i >= 0 && i < A.nx && j >= 1 && j < A.ny && k >= 1 && k < A.nz;
+  else if (c == 1) ok = i >= 1 && i < A.nx && j >= 0 && j < A.ny && k >= 1 && k < A.nz;
+  else ok = i >= 1 && i < A.nx && j >= 1 && j < A.ny && k >= 0 && k < A.nz;
+  if (!ok) return T(0);
+  const int W = 2 * A.npml;
+  const int64_t sX = (int64_t)A.NZ * A.NY * W, sY = (int64_t)A.NZ * W * A.PX,
+                sZ = (int64_t)W * A.NY * A.PX;
+  const int64_t q = ((int64_t)k * A.NY + j) * A.PX + i;
+  const T ae = (c == 0 ? Ad.ex : c == 1 ? Ad.ey : Ad.ez)[q];
+  const T add = (d == 1 ? T(1) : T(-1)) * A.ce[c * A.F + q] * ae;
+  // axis of the derivative (0 x, 1 y, 2 z) and its node index
+  const int ax = c == 0 ? (d == 1 ? 1 : 2) : c == 1 ? (d == 1 ? 2 : 0) : (d == 1 ? 0 : 1);
+  const int idx = ax == 0 ? i : ax == 1 ? j : k;
+  const int nax = ax == 0 ? A.nx : ax == 1 ? A.ny : A.nz;
+  int l = 0;
+  T aD = add;
+  if (A.npml > 0 && pml_int(idx, nax, A.npml, l)) {
+    const T *ps;
+    if (ax == 1) ps = Ad.psY + (c == 0 ? 2 : 3) * sY + ((int64_t)k * W + l) * A.PX + i;
+    else if (ax == 2) ps = Ad.psZ + (c == 0 ? 2 : 3) * sZ + ((int64_t)l * A.NY + j) * A.PX + i;
+    else ps = Ad.psX + (c == 1 ? 2 : 3) * sX + ((int64_t)k * A.NY + j) * W + l;
+    aD = add * axv(A, ax, AX_KN, idx) + axv(A, ax, AX_AN, idx) * (add + *ps);
+  }
+  return aD * axv(A, ax, AX_IHD, idx);
+}
+
+// aD / h of derivative d of the H update of component c at node (i, j, k);
+// 0 where the node does not exist.  H_x d1 = d/dy, d2 = d/dz; H_y d1 = d/dz,
+// d2 = d/dx; H_z d1 = d/dx, d2 = d/dy.
+template <typename T>
+__device__ __forceinline__ T td_ad_h(const StepArgs<T> &A, const Half<T> &Ad, int c, int d, int i,
+                                     int j, int k) {
+  bool ok;
+  if (c == 0) ok = i >= 0 && i <= A.nx && j >= 0 && j < A.ny && k >= 0 && k < A.nz;
+  else if (c == 1) ok = i >= 0 && i < A.nx && j >= 0 && j <= A.ny && k >= 0 && k < A.nz;
+  else ok = i >= 0 && i < A.nx && j >= 0 && j < A.ny && k >= 0 && k <= A.nz;
+  if (!ok) return T(0);
+  const int W = 2 * A.npml;
+  const int64_t sX = (int64_t)A.NZ * A.NY * W, sY = (int64_t)A.NZ * W * A.PX,
+                sZ = (int64_t)W * A.NY * A.PX;
+  const int64_t q = ((int64_t)k * A.NY + j) * A.PX + i;
+  const T ah = (c == 0 ? Ad.hx : c == 1 ? Ad.hy : Ad.hz)[q];
+  const T add = (d == 1 ? -A.dtmu : A.dtmu) * ah;
+  const int ax = c == 0 ? (d == 1 ? 1 : 2) : c == 1 ? (d == 1 ? 2 : 0) : (d == 1 ? 0 : 1);
+  const int idx = ax == 0 ? i : ax == 1 ? j : k;
+  const int nax = ax == 0 ? A.nx : ax == 1 ? A.ny : A.nz;
+  int l = 0;
+  T aD = add;
+  if (A.npml > 0 && pml_half(idx, nax, A.npml, l)) {
+    const T *ps;
+    if (ax == 1) ps = Ad.psY + (c == 0 ? 0 : 1) * sY + ((int64_t)k * W + l) * A.PX + i;
+    else if (ax == 2) ps = Ad.psZ + (c == 0 ? 0 : 1) * sZ + ((int64_t)l * A.NY + j) * A.PX + i;
+    else ps = Ad.psX + (c == 1 ? 0 : 1) * sX + ((int64_t)k * A.NY + j) * W + l;
+    aD = add * axv(A, ax, AX_KH, idx) + axv(A, ax, AX_AH, idx) * (add + *ps);
+  }
+  return aD * axv(A, ax, AX_IH, idx);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_td_e(StepArgs<T> A) {
+  int bx, by, bz, s;
+  tile_of(A.nblocks, A.xcd, A.order, A.ns, A.nbx, A.nby, A.nbz, bx, by, bz, s);
+  const int i = bx * blockDim.x + threadIdx.x, j = by * blockDim.y + threadIdx.y, k = bz;
+  if (i > A.nx || j > A.ny || k > A.nz) return;
+  const Half<T> Ad = half_of(A, 0, s);
+  const int npml = A.npml, W = 2 * npml;
+  const int64_t sX = (int64_t)A.NZ * A.NY * W, sY = (int64_t)A.NZ * W * A.PX,
+                sZ = (int64_t)W * A.NY * A.PX;
+  const int64_t q = ((int64_t)k * A.NY + j) * A.PX + i;
+  const bool hx = j < A.ny && k < A.nz, hy = i < A.nx && k < A.nz, hz = i < A.nx && j < A.ny;
+  int lx = 0, ly = 0, lz = 0;
+  const bool px = npml > 0 && i < A.nx && pml_half(i, A.nx, npml, lx);
+  const bool py = npml > 0 && j < A.ny && pml_half(j, A.ny, npml, ly);
+  const bool pz = npml > 0 && k < A.nz && pml_half(k, A.nz, npml, lz);
+  const int64_t iX = ((int64_t)k * A.NY + j) * W + lx, iY = ((int64_t)k * W + ly) * A.PX + i,
+                iZ = ((int64_t)lz * A.NY + j) * A.PX + i;
+  const T dtmu = A.dtmu;
+  // deferred update of the own H multipliers (transpose of the previous
+  // reverse step's H update: apsi = b (ad + apsi'))
+  if (hx) {
+    const T a = Ad.hx[q];
+    if (py) { T &p = Ad.psY[0 * sY + iY]; p = axv(A, 1, AX_BH, j) * (-dtmu * a + p); }
+    if (pz) { T &p = Ad.psZ[0 * sZ + iZ]; p = axv(A, 2, AX_BH, k) * (dtmu * a + p); }
+  }
+  if (hy) {
+    const T a = Ad.hy[q];
+    if (pz) { T &p = Ad.psZ[1 * sZ + iZ]; p = axv(A, 2, AX_BH, k) * (-dtmu * a + p); }
+    if (px) { T &p = Ad.psX[0 * sX + iX]; p = axv(A, 0, AX_BH, i) * (dtmu * a + p); }
+  }
+  if (hz) {
+    const T a = Ad.hz[q];
+    if (px) { T &p = Ad.psX[1 * sX + iX]; p = axv(A, 0, AX_BH, i) * (-dtmu * a + p); }
+    if (py) { T &p = Ad.psY[1 * sY + iY]; p = axv(A, 1, AX_BH, j) * (dtmu * a + p); }
+  }
+  // aH += D_h^T aD: H_z is differenced by E_x d1 at j, j+1 and E_y d2 at
+  // i, i+1; H_y by E_x d2 at k, k+1 and E_z d1 at i, i+1; H_x by E_y d1 at
+  // k, k+1 and E_z d2 at j, j+1
+  if (hz)
+    Ad.hz[q] += td_ad_e(A, Ad, 0, 1, i, j, k) - td_ad_e(A, Ad, 0, 1, i, j + 1, k) +
+                td_ad_e(A, Ad, 1, 2, i, j, k) - td_ad_e(A, Ad, 1, 2, i + 1, j, k);
+  if (hy)
+    Ad.hy[q] += td_ad_e(A, Ad, 0, 2, i, j, k) - td_ad_e(A, Ad, 0, 2, i, j, k + 1) +
+                td_ad_e(A, Ad, 2, 1, i, j, k) - td_ad_e(A, Ad, 2, 1, i + 1, j, k);
+  if (hx)
+    Ad.hx[q] += td_ad_e(A, Ad, 1, 1, i, j, k) - td_ad_e(A, Ad, 1, 1, i, j, k + 1) +
+                td_ad_e(A, Ad, 2, 2, i, j, k) - td_ad_e(A, Ad, 2, 2, i, j + 1, k);
+}
+
+// Enew, Eold: E^{n+1} and E^n, [ns][3][F]; tdw: 1/(sigma_e dV_e) [3][F]
+template <typename T>
+__global__ void __launch_bounds__(256) k_td_h(StepArgs<T> A, const T *Enew, const T *Eold,
+                                              const double *tdw) {
+  int bx, by, bz, s;
+  tile_of(A.nblocks, A.xcd, A.order, A.ns, A.nbx, A.nby, A.nbz, bx, by, bz, s);
+  const int i = bx * blockDim.x + threadIdx.x, j = by * blockDim.y + threadIdx.y, k = bz;
+  if (i > A.nx || j > A.ny || k > A.nz) return;
+  const Half<T> Ad = half_of(A, 0, s);
+  const int npml = A.npml, W = 2 * npml;
+  const int64_t F = A.F;
+  const int64_t sX = (int64_t)A.NZ * A.NY * W, sY = (int64_t)A.NZ * W * A.PX,
+                sZ = (int64_t)W * A.NY * A.PX;
+  const int64_t q = ((int64_t)k * A.NY + j) * A.PX + i;
+  const bool i_int = i >= 1 && i < A.nx, j_int = j >= 1 && j < A.ny, k_int = k >= 1 && k < A.nz;
+  const bool okx = i < A.nx && j_int && k_int, oky = i_int && j < A.ny && k_int,
+             okz = i_int && j_int && k < A.nz;
+  int lx = 0, ly = 0, lz = 0;
+  const bool px = npml > 0 && i_int && pml_int(i, A.nx, npml, lx);
+  const bool py = npml > 0 && j_int && pml_int(j, A.ny, npml, ly);
+  const bool pz = npml > 0 && k_int && pml_int(k, A.nz, npml, lz);
+  const int64_t iX = ((int64_t)k * A.NY + j) * W + lx, iY = ((int64_t)k * W + ly) * A.PX + i,
+                iZ = ((int64_t)lz * A.NY + j) * A.PX + i;
+  const int64_t e0 = (int64_t)s * 3 * F;
+  double *g = A.gedge + e0;
+  // own E multipliers: deferred CPML update (ad = +ce aE for d1, -ce aE for
+  // d2) and the gradient product
+  if (okx) {
+    const T a = Ad.ex[q], ca = A.ce[q] * a;
+    if (py) { T &p = Ad.psY[2 * sY + iY]; p = axv(A, 1, AX_BN, j) * (ca + p); }
+    if (pz) { T &p = Ad.psZ[2 * sZ + iZ]; p = axv(A, 2, AX_BN, k) * (-ca + p); }
+    g[q] += (double)a * ((double)Enew[e0 + q] - (double)Eold[e0 + q]) * tdw[q];
+  }
+  if (oky) {
+    const T a = Ad.ey[q], ca = A.ce[F + q] * a;
+    if (pz) { T &p = Ad.psZ[3 * sZ + iZ]; p = axv(A, 2, AX_BN, k) * (ca + p); }
+    if (px) { T &p = Ad.psX[2 * sX + iX]; p = axv(A, 0, AX_BN, i) * (-ca + p); }
+    g[F + q] += (double)a * ((double)Enew[e0 + F + q] - (double)Eold[e0 + F + q]) * tdw[F + q];
+  }
+  if (okz) {
+    const T a = Ad.ez[q], ca = A.ce[2 * F + q] * a;
+    if (px) { T &p = Ad.psX[3 * sX + iX]; p = axv(A, 0, AX_BN, i) * (ca + p); }
+    if (py) { T &p = Ad.psY[3 * sY + iY]; p = axv(A, 1, AX_BN, j) * (-ca + p); }
+    g[2 * F + q] +=
+        (double)a * ((double)Enew[e0 + 2 * F + q] - (double)Eold[e0 + 2 * F + q]) * tdw[2 * F + q];
+  }
+  // aE += D_e^T aD: E_x is differenced by H_y d1 at k-1, k and H_z d2 at
+  // j-1, j; E_y by H_x d2 at k-1, k and H_z d1 at i-1, i; E_z by H_x d1 at
+  // j-1, j and H_y d2 at i-1, i
+  if (okx)
+    Ad.ex[q] += td_ad_h(A, Ad, 1, 1, i, j, k - 1) - td_ad_h(A, Ad, 1, 1, i, j, k) +
+                td_ad_h(A, Ad, 2, 2, i, j - 1, k) - td_ad_h(A, Ad, 2, 2, i, j, k);
+  if (oky)
+    Ad.ey[q] += td_ad_h(A, Ad, 0, 2, i, j, k - 1) - td_ad_h(A, Ad, 0, 2, i, j, k) +
+                td_ad_h(A, Ad, 2, 1, i - 1, j, k) - td_ad_h(A, Ad, 2, 1, i, j, k);
+  if (okz)
+    Ad.ez[q] += td_ad_h(A, Ad, 0, 1, i, j - 1, k) - td_ad_h(A, Ad, 0, 1, i, j, k) +
+                td_ad_h(A, Ad, 1, 2, i - 1, j, k) - td_ad_h(A, Ad, 1, 2, i, j, k);
+}
+
+// aE[s][node] += -Re sum_k C[s][node][k] z_k^m (sensitivity of the misfit to
+// the sample E^m; z_k^m = zE[m-1][k]).  One thread per (source, node).
+template <typename T>
+__global__ void k_td_sens(T *adj, int64_t F, int ns, int nn, int nf, const int *rn_c,
+                          const int64_t *rn_idx, const double2 *C, const double2 *zE, int m) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ns * nn) return;
+  const int s = t / nn, node = t % nn;
+  double g = 0.0;
+  for (int kf = 0; kf < nf; ++kf) {
+    const double2 c = C[((int64_t)s * nn + node) * nf + kf];
+    const double2 z = zE[(int64_t)(m - 1) * nf + kf];
+    g -= c.x * z.x - c.y * z.y;
+  }
+  T *a = adj + (int64_t)s * 6 * F + (int64_t)rn_c[node] * F + rn_idx[node];
+  *a += (T)g;
+}
+
+// dst [ns][3][F] <- E of every source in half `half` of the double buffer
+template <typename T>
+__global__ void k_copy_e(T *dst, const T *fields, int64_t fbuf, int half, int ns, int64_t F) {
+  const int64_t n3 = 3 * F, total = (int64_t)ns * n3;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int s = (int)(t / n3);
+    dst[t] = fields[half * fbuf + (int64_t)s * 6 * F + (t - s * n3)];
+  }
+}
+
 // receiver output: interpolate node transforms and scale per frequency
 __global__ void k_rec_out(int ns, int nrows, int nn, int nf, const int *ptr, const int *node,
                           const double *w, const double2 *racc, const double2 *scale,
@@ -1923,6 +2149,143 @@ void dev_adjoint(Plan &p, void *ws, size_t ws_bytes, const void *vol, const doub
   p.last_steps = p.nt;
   collect_kernel_stats(d);
   check_finite(dst, (size_t)n, st);
+}
+
+// ---------------------------------------------------------------------------
+// time-domain adjoint: forward with checkpoints of the core state every
+// `segment` steps; then, from the last segment to the first, replay the
+// segment forward (keeping E after every step) and run its reverse steps.
+// ---------------------------------------------------------------------------
+template <typename T>
+static void adjoint_td_t(Plan &p, Dev &d, const WS &w, void *ws, char *scratch, int L,
+                         const std::vector<double> &C, const std::vector<double> &Wt,
+                         double gscale, double *grad, int accumulate, hipStream_t st) {
+  const int64_t F = p.field_elems();
+  const int nt = p.nt, ns = p.ns, nn = (int)p.rn_c.size(), nf = p.nf();
+  const int nseg = (nt + L - 1) / L;
+  const size_t core = p.core_state_bytes(), ckb = a256(core);
+  char *b = scratch;
+  char *ckpt = b;
+  b += (size_t)nseg * ckb;
+  T *eseg = reinterpret_cast<T *>(b);
+  b += a256((size_t)(L + 1) * ns * 3 * F * sizeof(T));
+  T *afld = reinterpret_cast<T *>(b);
+  const size_t afld_b = (size_t)ns * 6 * F * sizeof(T);
+  b += a256(afld_b);
+  T *apsi = reinterpret_cast<T *>(b);
+  const size_t apsi_b = (size_t)ns * p.psi_elems_per_source() * sizeof(T);
+  b += a256(apsi_b);
+  double *gedge = reinterpret_cast<double *>(b);
+  b += a256((size_t)ns * 3 * F * 8);
+  double2 *coef = reinterpret_cast<double2 *>(b);
+  b += a256((size_t)ns * nn * nf * 16);
+  double *tdw = reinterpret_cast<double *>(b);
+  HIP_CHECK(hipMemcpyAsync(coef, C.data(), C.size() * sizeof(double), hipMemcpyHostToDevice, st));
+  HIP_CHECK(hipMemcpyAsync(tdw, Wt.data(), Wt.size() * sizeof(double), hipMemcpyHostToDevice, st));
+  // forward run, checkpointing the core state at the start of every segment
+  zero_state(p, w, ws, nullptr, FWD_MODE_FORWARD, st);
+  for (int sg = 0; sg < nseg; ++sg) {
+    HIP_CHECK(hipMemcpyAsync(ckpt + (size_t)sg * ckb, ws, core, hipMemcpyDeviceToDevice, st));
+    run_steps_t<T>(p, d, w, nullptr, false, std::min(L, nt - sg * L), st);
+  }
+  // adjoint state at zero; the sensitivity to the last sample E^nt
+  HIP_CHECK(hipMemsetAsync(afld, 0, afld_b, st));
+  HIP_CHECK(hipMemsetAsync(apsi, 0, apsi_b, st));
+  HIP_CHECK(hipMemsetAsync(gedge, 0, (size_t)ns * 3 * F * 8, st));
+  StepArgs<T> A = make_args<T>(p, d, w, nullptr, false);
+  {
+    // one node per thread on the plan's block shape
+    const int nbx = (p.NX + p.bx - 1) / p.bx, nby = (p.NY + p.by - 1) / p.by;
+    A.nbx = nbx;
+    A.nby = nby;
+    A.nbz = p.NZ;
+    A.nblocks = nbx * nby * p.NZ * ns;
+  }
+  A.fields = afld;
+  A.fbuf = 0;
+  A.psi = apsi;
+  A.pbuf = 0;
+  A.gedge = gedge;
+  const dim3 block(p.bx, p.by), grid(A.nblocks);
+  const dim3 sgrid((ns * nn + 127) / 128), sblock(128);
+  const int cgrid = (int)std::min<int64_t>(((int64_t)ns * 3 * F + 255) / 256, 65536);
+  auto sens = [&](int m) {
+    hipLaunchKernelGGL((k_td_sens<T>), sgrid, sblock, 0, st, afld, F, ns, nn, nf, d.rn_c, d.rn_idx,
+                       coef, d.zE, m);
+  };
+  sens(nt);
+  T *fields = static_cast<T *>(w.fields);
+  const int64_t fbuf = (int64_t)ns * 6 * F, eslice = (int64_t)ns * 3 * F;
+  for (int sg = nseg - 1; sg >= 0; --sg) {
+    const int n0 = sg * L, len = std::min(L, nt - n0);
+    // replay the segment from its checkpoint, keeping E^{n0} .. E^{n0+len}
+    HIP_CHECK(hipMemcpyAsync(ws, ckpt + (size_t)sg * ckb, core, hipMemcpyDeviceToDevice, st));
+    hipLaunchKernelGGL(k_equalize, dim3(1), dim3(64), 0, st, w.step);
+    hipLaunchKernelGGL((k_copy_e<T>), dim3(cgrid), dim3(256), 0, st, eseg, fields, fbuf, n0 & 1, ns,
+                       F);
+    int r = 0;
+    for (int t = 1; t <= len; ++t) {
+      enqueue_step<T>(p, d, w, nullptr, false, st, nullptr, r);
+      r ^= 1;
+      hipLaunchKernelGGL((k_copy_e<T>), dim3(cgrid), dim3(256), 0, st, eseg + t * eslice, fields,
+                         fbuf, (n0 + t) & 1, ns, F);
+    }
+    // reverse steps n0 + len - 1 .. n0
+    for (int n = n0 + len - 1; n >= n0; --n) {
+      const int t = n - n0;
+      hipLaunchKernelGGL((k_td_e<T>), grid, block, 0, st, A);
+      hipLaunchKernelGGL((k_td_h<T>), grid, block, 0, st, A, eseg + (t + 1) * eslice,
+                         eseg + t * eslice, (const double *)tdw);
+      if (n >= 1) sens(n);
+    }
+    HIP_CHECK(hipGetLastError());
+  }
+  hipLaunchKernelGGL(k_grad_cells, dim3((p.nx + 127) / 128, p.ny, p.nz), dim3(128), 0, st, p.nx,
+                     p.ny, p.nz, p.ns, p.PX, p.NY, p.field_elems(), gedge, d.cellfac, gscale, grad,
+                     accumulate);
+  HIP_CHECK(hipGetLastError());
+}
+
+void dev_adjoint_td(Plan &p, void *ws, size_t ws_bytes, void *scratch, size_t scratch_bytes,
+                    int segment, const double *resid, double *grad, int accumulate, void *stream) {
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (segment < 1) fail(FWD_ERR_INVALID_ARG, "segment must be >= 1");
+  check_sizes(p, ws_bytes, FWD_MODE_FORWARD, nullptr, 0);
+  if (scratch_bytes < p.td_scratch_bytes(segment))
+    fail(FWD_ERR_INVALID_ARG, "time-domain adjoint scratch too small");
+  if (p.bx * p.by > 256) fail(FWD_ERR_INVALID_ARG, "block x * block y must be <= 256");
+  ensure_tables(p, st);
+  Dev &d = D(p);
+  WS w = carve(p, ws);
+  const size_t nres = (size_t)p.ns * p.nr * p.ncomp * p.nf();
+  std::vector<double> rh(2 * nres);
+  HIP_CHECK(hipMemcpyAsync(rh.data(), resid, rh.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_CHECK(hipStreamSynchronize(st));
+  std::vector<double> C, Wt;
+  double scale = 1.0;
+  td_coefficients(p, rh.data(), C, scale);
+  td_edge_weights(p, Wt);
+  build_lists(p, d);
+  d.kstat_n = 0;
+  const double gscale = 1.0 / (p.src_scale * scale);
+  hipEvent_t e0, e1;
+  HIP_CHECK(hipEventCreate(&e0));
+  HIP_CHECK(hipEventCreate(&e1));
+  HIP_CHECK(hipEventRecord(e0, st));
+  if (p.dtype == FWD_F64)
+    adjoint_td_t<double>(p, d, w, ws, static_cast<char *>(scratch), segment, C, Wt, gscale, grad,
+                         accumulate, st);
+  else
+    adjoint_td_t<float>(p, d, w, ws, static_cast<char *>(scratch), segment, C, Wt, gscale, grad,
+                        accumulate, st);
+  HIP_CHECK(hipEventRecord(e1, st));
+  HIP_CHECK(hipEventSynchronize(e1));   // C and Wt (host) stay alive until here
+  float ms = 0;
+  HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  p.last_ms = ms;
+  p.last_steps = p.nt;
 }
 
 // ---------------------------------------------------------------------------

@@ -122,7 +122,9 @@ struct Plan {
   size_t acc_bytes() const { return acc == FWD_ACC_F32 ? 8 : 16; }
   int64_t psi_elems_per_source() const;
   int64_t hist_elems_per_source() const { return kb > 2 ? (int64_t)(kb - 2) * 3 * field_elems() : 0; }
-  size_t state_bytes() const;       // fields + psi (double-buffered) + receiver sums + step index
+  size_t core_state_bytes() const;  // fields + psi (double-buffered) + receiver sums + counters
+  size_t state_bytes() const;       // core state + transform-block history
+  size_t td_scratch_bytes(int segment) const;   // time-domain adjoint scratch
   size_t workspace_bytes(int mode) const;
   size_t volume_bytes() const;
 };
@@ -135,6 +137,11 @@ void basis_build(Plan &p, double gamma_rel, double gamma_abs, int max_iter, doub
 void adjoint_coefficients(const Plan &p, const double *resid_host, std::vector<double> &T,
                           double &scale);
 void get_table(const Plan &p, int which, double *out, size_t n);
+// time-domain adjoint: receiver-node sensitivity coefficients [ns][nn][nf]
+// (complex, scaled by a power of two) and 1/(sigma_e dV_e) per updated edge
+void td_coefficients(const Plan &p, const double *resid, std::vector<double> &C,
+                     double &scale);
+void td_edge_weights(const Plan &p, std::vector<double> &W);
 
 // device driver (device.hip)
 void dev_release(Plan &p);
@@ -150,6 +157,9 @@ void dev_checkpoint(Plan &p, const void *ws, const void *vol, void *snap, int sa
 void dev_volume_export(Plan &p, const void *vol, double *out, void *stream);
 void dev_adjoint(Plan &p, void *ws, size_t ws_bytes, const void *vol, const double *resid,
                  double *grad, int accumulate, double *E_adj, void *stream);
+void dev_adjoint_td(Plan &p, void *ws, size_t ws_bytes, void *scratch, size_t scratch_bytes,
+                    int segment, const double *resid, double *grad, int accumulate,
+                    void *stream);
 double dev_autotune(Plan &p, void *ws, size_t ws_bytes, void *vol, size_t vol_bytes,
                     int mode, int steps, void *stream);
 void dev_set_sampling(Plan &p, int every);

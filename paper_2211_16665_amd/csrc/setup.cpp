@@ -27,14 +27,29 @@ int64_t Plan::psi_elems_per_source() const {
   return 4 * ((int64_t)NZ * NY * W + (int64_t)NZ * W * PX + W * (int64_t)NY * PX);
 }
 
-size_t Plan::state_bytes() const {
+size_t Plan::core_state_bytes() const {
   // fields and CPML memory are double-buffered: step n reads half n % 2 and
   // writes the other half
   size_t b = align256(2 * (size_t)ns * 6 * field_elems() * tsize());
   b += align256(2 * (size_t)ns * psi_elems_per_source() * tsize());
   b += align256((size_t)ns * rn_c.size() * nf() * 16);
   b += 256;  // two step counters and the flush marker
-  b += align256((size_t)ns * hist_elems_per_source() * tsize());
+  return b;
+}
+
+size_t Plan::state_bytes() const {
+  return core_state_bytes() + align256((size_t)ns * hist_elems_per_source() * tsize());
+}
+
+size_t Plan::td_scratch_bytes(int segment) const {
+  const size_t F = (size_t)field_elems(), nseg = ((size_t)nt + segment - 1) / segment;
+  size_t b = nseg * align256(core_state_bytes());                        // checkpoints
+  b += align256((size_t)(segment + 1) * ns * 3 * F * tsize());           // E of a segment
+  b += align256((size_t)ns * 6 * F * tsize());                           // adjoint fields
+  b += align256((size_t)ns * psi_elems_per_source() * tsize());          // adjoint CPML
+  b += align256((size_t)ns * 3 * F * 8);                                 // gradient products
+  b += align256((size_t)ns * rn_c.size() * nf() * 16);                   // sensitivities
+  b += align256(3 * F * 8);                                              // edge weights
   return b;
 }
 
@@ -599,6 +614,45 @@ void adjoint_coefficients(const Plan &p, const double *resid, std::vector<double
     }
   scale = big > 0 ? std::exp2(std::round(std::log2(1.0 / big))) : 1.0;  // power of two: exact
   for (double &v : T) v *= scale;
+}
+
+void td_coefficients(const Plan &p, const double *resid, std::vector<double> &C,
+                     double &scale) {
+  // E_rec[s][r][c][k] = norm_k sum_nodes w sum_m E^m z_k^m, so the misfit's
+  // sensitivity to E^m at a node is -Re sum_k C_k z_k^m with
+  // C_k = sum over the (receiver, component) rows touching the node of
+  // w conj(resid) norm_k
+  const int nf = p.nf(), nn = (int)p.rn_c.size(), rows = p.nr * p.ncomp;
+  C.assign((size_t)p.ns * nn * nf * 2, 0.0);
+  for (int s = 0; s < p.ns; ++s)
+    for (int row = 0; row < rows; ++row)
+      for (int e = p.ri_ptr[row]; e < p.ri_ptr[row + 1]; ++e) {
+        const int node = p.ri_node[e];
+        for (int k = 0; k < nf; ++k) {
+          const double *rr = &resid[2 * (((size_t)s * rows + row) * nf + k)];
+          const cplx v = p.ri_w[e] * std::conj(cplx(rr[0], rr[1])) * p.norm[k];
+          double *c = &C[2 * (((size_t)s * nn + node) * nf + k)];
+          c[0] += v.real();
+          c[1] += v.imag();
+        }
+      }
+  double big = 0;
+  for (double v : C) big = std::max(big, std::fabs(v));
+  scale = big > 0 ? std::exp2(std::round(std::log2(1.0 / big))) : 1.0;   // power of two: exact
+  for (double &v : C) v *= scale;
+}
+
+void td_edge_weights(const Plan &p, std::vector<double> &W) {
+  const int64_t F = p.field_elems();
+  W.assign(3 * F, 0.0);
+  for (int c = 0; c < 3; ++c)
+    for (int k = 0; k <= p.nz; ++k)
+      for (int j = 0; j <= p.ny; ++j)
+        for (int i = 0; i <= p.nx; ++i)
+          if (interior_edge(p, c, k, j, i)) {
+            const int64_t q = p.lin(k, j, i);
+            W[c * F + q] = 1.0 / (p.sig_e[c][q] * dual_volume(p, c, k, j, i));
+          }
 }
 
 void get_table(const Plan &p, int which, double *out, size_t n) {

@@ -93,6 +93,9 @@ SIGNATURES = {
                                 POINTER(c_double), POINTER(c_int)]),
     "fwd_adjoint": (c_int, [c_void_p, c_void_p, c_size_t, c_void_p, c_void_p, c_void_p, c_int,
                             c_void_p, c_void_p]),
+    "fwd_adjoint_td_size": (c_int, [c_void_p, c_int, POINTER(c_size_t)]),
+    "fwd_adjoint_td": (c_int, [c_void_p, c_void_p, c_size_t, c_void_p, c_size_t, c_int, c_void_p,
+                               c_void_p, c_int, c_void_p]),
     "fwd_set_option": (c_int, [c_void_p, c_int, c_double]),
     "fwd_get_option": (c_int, [c_void_p, c_int, POINTER(c_double)]),
     "fwd_autotune": (c_int, [c_void_p, c_void_p, c_size_t, c_void_p, c_size_t, c_int, c_int,
@@ -325,6 +328,29 @@ class Plan:
         check(self.lib.fwd_adjoint(self.handle, _ptr(ws), ws.numel(), _ptr(vol), _ptr(resid),
                                    _ptr(grad), int(accumulate), _ptr(Ea), _stream(stream)))
         return (grad, Ea) if want_adjoint_rec else grad
+
+    def adjoint_td_size(self, segment=200):
+        n = c_size_t()
+        check(self.lib.fwd_adjoint_td_size(self.handle, int(segment), ctypes.byref(n)))
+        return n.value
+
+    def adjoint_td(self, resid, grad=None, accumulate=False, segment=200, scratch=None,
+                   stream=None):
+        """Gradient d phi / d ln rho [nz][ny][nx] (float64) by the time-domain
+        adjoint (checkpoints every ``segment`` steps) for the weighted
+        residual ``resid`` = W^2 (d - E), complex128 [ns][nr][ncomp][nf]."""
+        import torch
+        ws = self.workspace(FWD_MODE_FORWARD)
+        need = self.adjoint_td_size(segment)
+        if scratch is None or scratch.numel() < need:
+            scratch = torch.empty(need, dtype=torch.uint8, device="cuda")
+        resid = resid.to(device="cuda", dtype=torch.complex128).contiguous()
+        if grad is None:
+            grad = torch.zeros(self.shape, dtype=torch.float64, device="cuda")
+        check(self.lib.fwd_adjoint_td(self.handle, _ptr(ws), ws.numel(), _ptr(scratch),
+                                      scratch.numel(), int(segment), _ptr(resid), _ptr(grad),
+                                      int(accumulate), _stream(stream)))
+        return grad
 
     def autotune(self, mode=FWD_MODE_FORWARD, vol=None, steps=20, stream=None):
         ws = self.workspace(mode)

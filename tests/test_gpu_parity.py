@@ -420,3 +420,66 @@ def test_autotune_keeps_results():
     say(f"autotuned: {cfg}: {ms:.4f} ms/step")
     E1 = p.forward(vol=vol, want_volume=True)[0].cpu().numpy()
     assert same(E0, E1)
+
+
+# --------------------------------------------------------------------------
+# time-domain adjoint (Appendix formulation on the stepped system)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-9), ("f32", 1e-3)])
+def test_td_gradient_matches_oracle(dtype, tol):
+    w0, d = _inverse_problem(ns=2)
+    say(f"time-domain adjoint gradient, {dtype}")
+    fwd = oracle.forward(w0)
+    resid = d - fwd["E_rec"]
+    from oracle.adjoint_td import adjoint_gradient_td
+    go = adjoint_gradient_td(w0, resid)["grad"]
+    p = fw.Plan.from_workload(w0, field_dtype=dtype)
+    p.set_model(w0.rho)
+    g = p.adjoint_td(torch.from_numpy(resid).cuda(), segment=37).cpu().numpy()
+    err = np.linalg.norm(g - go) / np.linalg.norm(go)
+    say(f"  relative L2 {err:.2e}")
+    assert err < tol, err
+
+
+def test_td_gradient_matches_basis_gradient_outside_cpml():
+    """The two adjoints of the library agree outside the CPML layers (inside
+    them only the time-domain one is the derivative of the stepped system)."""
+    w0, d = _inverse_problem(seed=4, ns=1)
+    say("time-domain against basis-function gradient on the GPU")
+    p = fw.Plan.from_workload(w0, field_dtype="f64")
+    p.set_model(w0.rho)
+    p.basis_build(gamma_rel=1e-12)
+    E, vol = p.forward(want_volume=True)
+    r = torch.from_numpy(d).cuda() - E
+    g1 = p.adjoint(vol, r).cpu().numpy()
+    g2 = p.adjoint_td(r, segment=100).cpu().numpy()
+    m = w0.npml
+    inner = (slice(m, -m),) * 3
+    err = np.linalg.norm((g1 - g2)[inner]) / np.linalg.norm(g1[inner])
+    say(f"  relative L2 outside the layers {err:.2e}")
+    assert err < 1e-8
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_td_gradient_independent_of_segments_and_schedule(dtype):
+    """Checkpoint spacing and the step schedule change only where the forward
+    states are recomputed, never their values: gradients equal bit for bit;
+    accumulate adds."""
+    w0, d = _inverse_problem(seed=6, ns=2)
+    say(f"time-domain adjoint: segments and schedules, {dtype}")
+    p = fw.Plan.from_workload(w0, field_dtype=dtype)
+    p.set_model(w0.rho)
+    nt = p.info.nt
+    r = torch.from_numpy(d).cuda() - p.forward()
+    ref = p.adjoint_td(r, segment=nt).cpu().numpy()
+    for seg in (1, 7, 64, nt - 1):
+        assert same(p.adjoint_td(r, segment=seg).cpu().numpy(), ref), seg
+    p.set_option(fw.FWD_OPT_SCHEDULE, 1)
+    p.set_option(fw.FWD_OPT_ZCHUNK, 3)
+    assert same(p.adjoint_td(r, segment=50).cpu().numpy(), ref)
+    p.set_option(fw.FWD_OPT_SCHEDULE, 0)
+    p.set_option(fw.FWD_OPT_TILE_ORDER, 1)
+    p.set_option(fw.FWD_OPT_BLOCK_X, 32)
+    g = torch.from_numpy(ref).cuda()
+    p.adjoint_td(r, grad=g, accumulate=True, segment=50)
+    assert same(g.cpu().numpy(), 2 * ref)
