@@ -16,6 +16,8 @@ HIP events on sampled steps inside the timed region.  cpu_baseline: the CPU
 oracle stepping the same grid for a bounded window of steps.
 batched_vs_plain: gradient time of the 16-source batched workload on a
 window, one batched plan against one single-source plan per source.
+adjoint_td: the time-domain adjoint gradient of the same step (after the
+timed region) against the basis-function one.
 """
 from __future__ import annotations
 
@@ -180,6 +182,30 @@ def batched_vs_plain(window=200):
             "max_rel_grad_diff": diff}
 
 
+def adjoint_td_study(plan, resid, grad_basis, basis_s, npml, segment=500):
+    """The time-domain adjoint (Appendix) on the bench workload: gradient time
+    (forward with checkpoints, replay, reverse sweep) against the
+    basis-function gradient of the timed step, and their agreement outside
+    the CPML layers (inside them only the time-domain gradient is the
+    derivative of the stepped system)."""
+    import torch
+    scratch = torch.empty(plan.adjoint_td_size(segment), dtype=torch.uint8, device="cuda")
+    plan.adjoint_td(resid, segment=segment, scratch=scratch)          # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g = plan.adjoint_td(resid, segment=segment, scratch=scratch)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    inner = (slice(npml, -npml),) * 3
+    gb = grad_basis[inner]
+    diff = float((g[inner] - gb).norm() / gb.norm())
+    nz, ny, nx = plan.shape
+    return {"segment": segment, "gradient_s": t, "basis_gradient_s": basis_s,
+            "scratch_gb": scratch.numel() / 1e9,
+            "mcell_per_s_three_sweeps": 3.0 * plan.ns * nx * ny * nz * plan.info.nt / t / 1e6,
+            "rel_l2_vs_basis_outside_cpml": diff}
+
+
 def profile_mode(args, w_true):
     """A short run for hardware-counter collection: one elementwise kernel of
     a known size (256 MiB read + 256 MiB written, the calibration of the byte
@@ -217,6 +243,8 @@ def main():
     ap.add_argument("--sample-every", type=int, default=2048)
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched-vs-plain gradient-time comparison")
+    ap.add_argument("--no-td", action="store_true",
+                    help="skip the time-domain adjoint study")
     ap.add_argument("--tiling", default="",
                     help="fixed tiling instead of autotuning: block_x,block_y,xcd_remap,vector")
     ap.add_argument("--profile-steps", type=int, default=0,
@@ -258,6 +286,7 @@ def main():
     plan.set_option(fw.FWD_OPT_SAMPLE_EVERY, args.sample_every)
     grad = torch.zeros(plan.shape, dtype=torch.float64, device="cuda")
     stats = {"fwd": [], "adj": []}
+    resid_last = []
 
     def step():
         plan.set_model(rho0)
@@ -265,6 +294,7 @@ def main():
         E, _ = plan.forward(vol=vol, want_volume=True)
         stats["fwd"].append(plan.kernel_stats())
         resid = d_obs - E
+        resid_last[:] = [resid]
         plan.adjoint(vol, resid, grad=grad)
         stats["adj"].append(plan.kernel_stats())
 
@@ -341,6 +371,9 @@ def main():
                      "bytes_per_launch": bytes_e, "avg_launch_ms": e_ms, "samples": n_samp},
         "kernels_ms": kern,
     }
+    if not args.no_td:
+        out["adjoint_td"] = adjoint_td_study(plan, resid_last[0], grad, elapsed / args.steps,
+                                             w_true.npml)
     if not args.no_batched:
         del vol, grad
         torch.cuda.empty_cache()

@@ -2,11 +2,17 @@
 
 ``FictitiousForward.apply(log_rho, plan)`` returns E at the receivers
 (complex128 [ns][nr][ncomp][nf]) for the resistivity exp(log_rho); its
-backward runs one adjoint simulation driven by the basis-function adjoint
-sources (Section 3.3) and returns d loss / d log_rho (Section 3.5 chain
-rule).  The forward keeps the volume transform of E as the frequency-domain
-checkpoint the gradient needs; with ``snapshot_every`` > 0 it also keeps
-device snapshots of the full time-domain state every that many steps.
+backward returns d loss / d log_rho (Section 3.5 chain rule) by one of two
+adjoints:
+  method="basis" (default)  one adjoint simulation driven by the
+      basis-function adjoint sources (Section 3.3); the forward keeps the
+      volume transform of E as the frequency-domain checkpoint the gradient
+      needs and, with ``snapshot_every`` > 0, device snapshots of the full
+      time-domain state every that many steps;
+  method="time"  the time-domain adjoint of the Appendix on the stepped
+      system (exact, also inside the CPML): the backward reruns the forward
+      with checkpoints every ``snapshot_every`` steps (200 if 0) and steps the
+      transposed system backward.
 
 PyTorch hands the backward the conjugate Wirtinger gradient
 gE = dL/dRe E + i dL/dIm E; for the data misfit L = 1/2 ||W (d - E)||^2
@@ -23,9 +29,20 @@ from .fwdem import Plan
 class FictitiousForward(torch.autograd.Function):
     @staticmethod
     def forward(ctx, log_rho: torch.Tensor, plan: Plan, snapshot_every: int = 0,
-                gamma_rel: float = 1e-12):
+                gamma_rel: float = 1e-12, method: str = "basis"):
         rho = torch.exp(log_rho.detach().to(torch.float64)).cpu().numpy()
         plan.set_model(rho)
+        ctx.plan = plan
+        ctx.method = method
+        ctx.snapshot_every = snapshot_every
+        ctx.in_dtype = log_rho.dtype
+        ctx.in_device = log_rho.device
+        if method == "time":
+            ctx.vol = None
+            ctx.snapshots = []
+            return plan.forward()
+        if method != "basis":
+            raise ValueError(f"unknown adjoint method {method!r}")
         if not plan.info.have_basis:
             plan.basis_build(gamma_rel=gamma_rel)
         vol = plan.volume_buffer()
@@ -43,22 +60,23 @@ class FictitiousForward(torch.autograd.Function):
                                        device="cuda")
                     plan.checkpoint_save(snap)
                     snaps.append((done, snap))
+            plan.run_flush(vol)              # the incomplete last transform block
             E = plan.run_receivers()
         else:
             E, vol = plan.forward(vol=vol, want_volume=True)
-        ctx.plan = plan
         ctx.vol = vol
         ctx.snapshots = snaps
-        ctx.in_dtype = log_rho.dtype
-        ctx.in_device = log_rho.device
         return E
 
     @staticmethod
     def backward(ctx, gE):
         plan: Plan = ctx.plan
         resid = (-gE).to(torch.complex128).contiguous()
-        grad = plan.adjoint(ctx.vol, resid)
-        return grad.to(dtype=ctx.in_dtype, device=ctx.in_device), None, None, None
+        if ctx.method == "time":
+            grad = plan.adjoint_td(resid, segment=ctx.snapshot_every or 200)
+        else:
+            grad = plan.adjoint(ctx.vol, resid)
+        return grad.to(dtype=ctx.in_dtype, device=ctx.in_device), None, None, None, None
 
 
 def misfit(E: torch.Tensor, d: torch.Tensor, W=1.0) -> torch.Tensor:

@@ -177,3 +177,50 @@ def test_large_window_accumulators():
     w = with_window(w.replace(src_pos=w.src_pos[:1], src_mom=w.src_mom[:1]), 2000)
     say("large grid (~32M cells), 1 source, 2000-step window: volume per accumulator mode")
     accumulator_study(w, 1e-7, 1e-5)
+
+
+def test_blocks_td_gradient_finite_differences_and_basis():
+    """Three blocks, FP64: the time-domain adjoint gradient (checkpoints every
+    200 steps) against central differences on 6 interior cells and the 2
+    largest-gradient cells of the CPML layers, and against the basis-function
+    gradient outside the layers."""
+    from paper_2211_16665_amd.autograd import FictitiousForward, misfit
+    w0, d = _blocks_problem()
+    say(f"three blocks: time-domain adjoint, nt={w0.nt}")
+    p = fw.Plan.from_workload(w0, field_dtype="f64")
+    m0 = np.log(w0.rho)
+    m = torch.tensor(m0, dtype=torch.float64, device="cuda", requires_grad=True)
+    L = misfit(FictitiousForward.apply(m, p, 200, 1e-12, "time"), d)
+    L.backward()
+    g = m.grad.cpu().numpy()
+    p.basis_build(gamma_rel=1e-12)
+    E, vol = p.forward(want_volume=True)
+    gb = p.adjoint(vol, d - E).cpu().numpy()
+    npml = w0.npml
+    inner = (slice(npml, -npml),) * 3
+    e = np.linalg.norm((g - gb)[inner]) / np.linalg.norm(gb[inner])
+    say(f"  against the basis-function gradient outside the layers: {e:.2e}")
+    assert e < 1e-6
+    rng = np.random.default_rng(3)
+    nz, ny, nx = w0.shape
+    cells = []
+    while len(cells) < 6:
+        c = (int(rng.integers(12, nz - 12)), int(rng.integers(12, ny - 12)), int(rng.integers(12, nx - 12)))
+        if abs(g[c]) > 1e-3 * np.abs(g).max():
+            cells.append((c, 1e-3, 1e-3))
+    layer = np.abs(g).copy()
+    layer[inner] = 0.0                       # cells of the six CPML layers only
+    for q in np.argsort(layer.ravel())[-2:]:
+        cells.append((tuple(int(v) for v in np.unravel_index(q, layer.shape)), 1e-2, 1e-2))
+    for c, h, tol in cells:
+        vals = []
+        for sgn in (1, -1):
+            mm = m0.copy()
+            mm[c] += sgn * h
+            with torch.no_grad():
+                Ec = FictitiousForward.apply(torch.from_numpy(mm).cuda(), p)
+            vals.append(float(misfit(Ec, d)))
+        fd = (vals[0] - vals[1]) / (2 * h)
+        err = abs(fd - g[c]) / abs(fd)
+        say(f"  cell {c}: fd {fd:.6e} time-domain adjoint {g[c]:.6e} rel {err:.2e}")
+        assert err < tol
