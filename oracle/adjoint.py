@@ -25,7 +25,7 @@ from __future__ import annotations
 import numpy as np
 
 from .basis import basis_matrix, basis_pinv, gamma_from_rel, synthesize
-from .discretization import Setup, dual_volumes, edge_sigma_transpose
+from .discretization import Setup, cell_gradient, dual_volumes, edge_sigma_transpose
 from .stepping import point_entries, run_stepping
 
 
@@ -80,8 +80,11 @@ def adjoint_gradient(p, fwd: dict, resid: np.ndarray, gamma_rel: float = 1e-12,
             prod = np.einsum("k,k...->...", corr, v[c] * E[c])
             g -= np.real(prod) * vols[c]
     g_sigma = edge_sigma_transpose(gx, gy, gz, s.hx, s.hy, s.hz)
-    grad = -s.sigma * g_sigma
-    grad[s.capped] = 0.0                         # capped cells do not see rho
-    return {"grad": grad, "grad_sigma": g_sigma, "grad_edges": (gx, gy, gz),
+    # capped cells do not see rho; in VTI the x, y edges give rho_h, the z
+    # edges rho_v (Section 3.1); grad = d / d ln rho with rho_h, rho_v scaled
+    # together
+    grad_h, grad_v = cell_gradient(s, gx, gy, gz)
+    return {"grad": grad_h + grad_v, "grad_h": grad_h, "grad_v": grad_v,
+            "grad_sigma": g_sigma, "grad_edges": (gx, gy, gz),
             "basis": b, "B": B, "gamma": gamma, "fit": fit,
             "probe": np.array(probes)}

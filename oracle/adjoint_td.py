@@ -33,7 +33,7 @@ from types import SimpleNamespace
 
 import numpy as np
 
-from .discretization import MU0, Setup, edge_sigma_transpose, make_setup
+from .discretization import MU0, Setup, cell_gradient, edge_sigma_transpose, make_setup
 from .stepping import receiver_nodes, source_injection
 
 FIELDS = ("Ex", "Ey", "Ez", "Hx", "Hy", "Hz")
@@ -235,6 +235,6 @@ def adjoint_gradient_td(p, resid: np.ndarray, setup: Setup | None = None,
                 ge[c][sl] -= ad[names[c]][sl] * dE / s.sig_e[c][sl]
             adj_step(o, ad)
     g_sigma = edge_sigma_transpose(ge[0], ge[1], ge[2], s.hx, s.hy, s.hz)
-    grad = -s.sigma * g_sigma
-    grad[s.capped] = 0.0
-    return {"grad": grad, "grad_sigma": g_sigma, "grad_edges": tuple(ge)}
+    grad_h, grad_v = cell_gradient(s, ge[0], ge[1], ge[2])
+    return {"grad": grad_h + grad_v, "grad_h": grad_h, "grad_v": grad_v,
+            "grad_sigma": g_sigma, "grad_edges": tuple(ge)}

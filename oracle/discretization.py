@@ -76,6 +76,22 @@ def edge_sigma(sig: np.ndarray, hx, hy, hz):
     return sx, sy, sz
 
 
+def cell_gradient(s, gx, gy, gz):
+    """d phi / d ln rho on cells from d phi / d sigma_e on the edges:
+    through the transpose of the averaging and the chain rule
+    d / d ln rho = -sigma d / d sigma (Section 3.5).  In VTI (Section 3.1)
+    the x and y edges give the gradient for rho_h, the z edges for rho_v.
+    Returns (grad_h, grad_v); capped cells get zero."""
+    zx, zy, zz = np.zeros_like(gx), np.zeros_like(gy), np.zeros_like(gz)
+    g_h = edge_sigma_transpose(gx, gy, zz, s.hx, s.hy, s.hz)
+    g_v = edge_sigma_transpose(zx, zy, gz, s.hx, s.hy, s.hz)
+    grad_h = -s.sigma * g_h
+    grad_v = -s.sigma_v * g_v
+    grad_h[s.capped] = 0.0
+    grad_v[s.capped_v] = 0.0
+    return grad_h, grad_v
+
+
 def edge_sigma_transpose(gx, gy, gz, hx, hy, hz):
     """Exact transpose of ``edge_sigma``: maps edge quantities g_e to cells,
     sum_e g_e d sigma_e / d sigma_c (used to scatter the edge gradient)."""
@@ -178,7 +194,7 @@ class Setup:
     hdx: np.ndarray
     hdy: np.ndarray
     hdz: np.ndarray
-    sigma: np.ndarray          # capped cell conductivity
+    sigma: np.ndarray          # capped cell conductivity (horizontal, sigma_h, in VTI)
     capped: np.ndarray         # bool: cell resistivity above the cap
     sig_e: tuple               # edge conductivities (x, y, z)
     ce: tuple                  # dt / eps on the edges (x, y, z)
@@ -199,6 +215,8 @@ class Setup:
     t0: float
     What: np.ndarray           # sum_n w^{n+1/2} z^{n+1/2}
     norm: np.ndarray           # sqrt(-i omega / 2 omega0) / What
+    sigma_v: np.ndarray = None  # vertical conductivity (VTI); = sigma when isotropic
+    capped_v: np.ndarray = None
 
 
 def make_setup(p, dt: float | None = None, nt: int | None = None) -> Setup:
@@ -213,6 +231,15 @@ def make_setup(p, dt: float | None = None, nt: int | None = None) -> Setup:
     cap = float(p.rho_air_cap)
     capped = rho > cap
     sigma = 1.0 / np.minimum(rho, cap)                   # reading: air as capped cells
+    # VTI (Section 2): sigma_h = sigma_xx = sigma_yy, sigma_v = sigma_zz
+    rho_v = getattr(p, "rho_v", None)
+    if rho_v is None:
+        sigma_v, capped_v = sigma, capped
+    else:
+        rho_v = np.asarray(rho_v, dtype=np.float64)
+        assert rho_v.shape == rho.shape
+        capped_v = rho_v > cap
+        sigma_v = 1.0 / np.minimum(rho_v, cap)
     f0 = float(p.f0)
     omega0 = 2.0 * np.pi * f0
     freqs = np.asarray(p.freqs, dtype=np.float64)
@@ -220,13 +247,17 @@ def make_setup(p, dt: float | None = None, nt: int | None = None) -> Setup:
     a = np.sqrt(omega * omega0)
     wprime = (1.0 + 1.0j) * a                            # eq. mittet correspondence
 
-    dt_cfl, vmax = cfl_dt(sigma, hx, hy, hz, omega0, float(p.cfl))
+    # reading (VTI): the bound of each cell taken with its faster (more
+    # resistive) direction
+    dt_cfl, vmax = cfl_dt(np.minimum(sigma, sigma_v), hx, hy, hz, omega0, float(p.cfl))
     if dt is None:
         dt = float(p.dt) if getattr(p, "dt", 0.0) else dt_cfl
     if nt is None:
         nt = int(p.nt) if getattr(p, "nt", 0) else int(np.ceil(np.log(1.0 / NT_TOL) / (a.min() * dt)))
 
     sx, sy, sz = edge_sigma(sigma, hx, hy, hz)
+    if rho_v is not None:
+        sz = edge_sigma(sigma_v, hx, hy, hz)[2]      # z edges see sigma_v
     ce = tuple(dt * 2.0 * omega0 / s for s in (sx, sy, sz))   # dt/eps, eps = sigma/(2 omega0)
 
     vref = float(getattr(p, "cpml_vref", 0.0) or vmax)
@@ -257,7 +288,8 @@ def make_setup(p, dt: float | None = None, nt: int | None = None) -> Setup:
                  sig_e=(sx, sy, sz), ce=ce, dt=dt, nt=nt, f0=f0,
                  omega0=omega0, freqs=freqs, omega=omega, a=a, wprime=wprime,
                  Omega=Omega, vmax=vmax, vref=vref, cpml=cp, wavelet=wav,
-                 tau=tau, t0=t0, What=What, norm=norm)
+                 tau=tau, t0=t0, What=What, norm=norm, sigma_v=sigma_v,
+                 capped_v=capped_v)
 
 
 def lattices(s: Setup):

@@ -75,7 +75,7 @@ def _dual(nodes):
 
 def solve(x, y, z, rho, npml, f0, freq, dt, sources, receivers, rec_comp,
           vref, cpml_order=2.0, cpml_R=1e-6, kappa_max=1.0, alpha_max=0.0,
-          rho_cap=1e8):
+          rho_cap=1e8, rho_v=None):
     """Frequency-domain E at ``receivers`` for each dipole in ``sources``
     (list of (pos, moment)); returns complex [ns][nr][ncomp].  The field is
     that of J (not J'): the right-hand side is sqrt(-i w/2w0) p w_l / V_l."""
@@ -177,6 +177,8 @@ def solve(x, y, z, rho, npml, f0, freq, dt, sources, receivers, rec_comp,
 
     # edge permittivity: volume-weighted cell average, eps = sigma / (2 w0)
     sig = 1.0 / np.minimum(rho, rho_cap)
+    # VTI: x and y edges average the horizontal, z edges the vertical value
+    sigv = sig if rho_v is None else 1.0 / np.minimum(rho_v, rho_cap)
     eps = np.zeros(g.eoff[-1])
     vol = np.zeros(g.eoff[-1])
     for k in range(nz):
@@ -193,7 +195,7 @@ def solve(x, y, z, rho, npml, f0, freq, dt, sources, receivers, rec_comp,
                     vol[g.e(1, kk, j, ii)] += w
                 for (jj, ii) in ((j, i), (j + 1, i), (j, i + 1), (j + 1, i + 1)):
                     w = hy[j] * hx[i]
-                    eps[g.e(2, k, jj, ii)] += s * w
+                    eps[g.e(2, k, jj, ii)] += sigv[k, j, i] * w
                     vol[g.e(2, k, jj, ii)] += w
     eps = eps / vol / (2.0 * w0)
 

@@ -7,8 +7,8 @@ CPU oracle and the HIP path.
 """
 from .configs import (Workload, axis_nodes, c1_wholespace, c2_marine1d,
                       c3_blocks, c4_batched, c5_large, tiny, by_name,
-                      with_window)
+                      with_vti, with_window)
 
 __all__ = ["Workload", "axis_nodes", "c1_wholespace", "c2_marine1d",
            "c3_blocks", "c4_batched", "c5_large", "tiny", "by_name",
-           "with_window"]
+           "with_vti", "with_window"]

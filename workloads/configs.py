@@ -25,7 +25,7 @@ class Workload:
     x: np.ndarray                 # node coordinates, nx+1
     y: np.ndarray                 # ny+1
     z: np.ndarray                 # nz+1
-    rho: np.ndarray               # cell resistivity [nz][ny][nx]
+    rho: np.ndarray               # cell resistivity [nz][ny][nx] (horizontal, if rho_v is set)
     freqs: np.ndarray             # Hz
     src_pos: np.ndarray           # [ns][3]
     src_mom: np.ndarray           # [ns][3]  (A m)
@@ -40,6 +40,7 @@ class Workload:
     field_dtype: str = "f32"      # hint: the precision the workload is run in
     acc_mode: str = "f64"
     extra: dict = field(default_factory=dict)
+    rho_v: np.ndarray | None = None   # vertical resistivity (VTI); None: isotropic
 
     @property
     def shape(self):
@@ -282,6 +283,22 @@ def tiny(seed: int = 0, n=(14, 12, 10), npml: int = 3, ns: int = 1,
                     src_pos=srcs, src_mom=moms, rec_pos=recs,
                     rec_comp=tuple(rec_comp), npml=npml, field_dtype="f64",
                     rho_air_cap=1.0e8)
+
+
+def with_vti(w: Workload, ratio: float = 2.0, seed: int | None = None,
+             rho_min: float = 0.9) -> Workload:
+    """The same workload made vertically transverse isotropic (VTI): the
+    vertical resistivity of every cell with rho >= rho_min (sediment,
+    reservoir; not water or air) is ``ratio`` times the horizontal one, or,
+    with a seed, times a random factor in [1, ratio]."""
+    rv = w.rho.copy()
+    sel = w.rho >= rho_min
+    if seed is None:
+        rv[sel] *= ratio
+    else:
+        rng = np.random.default_rng(seed)
+        rv[sel] *= rng.uniform(1.0, ratio, int(sel.sum()))
+    return w.replace(rho_v=rv, name=f"{w.name}_vti")
 
 
 def with_window(w: Workload, nt: int) -> Workload:
