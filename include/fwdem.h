@@ -126,6 +126,18 @@ void fwd_plan_destroy(fwd_plan *plan);
  * device tables are refreshed by the next device call. */
 fwd_status fwd_set_model(fwd_plan *plan, const double *rho_host);
 
+/* VTI model (Section 2: sigma_h = sigma_xx = sigma_yy, sigma_v = sigma_zz):
+ * rho_h_host and rho_v_host [nz][ny][nx] (ohm m, > 0).  x and y edges average
+ * 1/rho_h, z edges 1/rho_v; the CFL bound of a cell uses its faster (more
+ * resistive) direction.  Otherwise as fwd_set_model.  Gradients
+ * (fwd_adjoint, fwd_adjoint_td) are d phi / d ln rho with rho_h and rho_v
+ * scaled together, or, with FWD_OPT_VTI_GRADIENT = 1, the pair
+ * [d phi / d ln rho_h, d phi / d ln rho_v] (Section 3.1 VTI gradient: x and
+ * y edges for rho_h, z edges for rho_v) in grad_dev [2][nz][ny][nx].
+ * Errors: INVALID_ARG (NULL, non-positive or non-finite values), CFL. */
+fwd_status fwd_set_model_vti(fwd_plan *plan, const double *rho_h_host,
+                             const double *rho_v_host);
+
 fwd_status fwd_get_info(const fwd_plan *plan, fwd_info *info);
 
 /* Copy table `which` (FWD_TAB_*) into out_host (capacity n doubles). */
@@ -270,7 +282,9 @@ enum {
   FWD_OPT_ZCHUNK = 9,        /* planes per block of the fused schedule: 1 .. 64 (default 8) */
   FWD_OPT_TILE_ORDER = 10,   /* 0 (default): tiles numbered x fastest; 1: z fastest, so the
                                 blocks of neighbouring planes run side by side */
-  FWD_OPT_VECTOR_H = 11      /* as FWD_OPT_VECTOR, for the H update */
+  FWD_OPT_VECTOR_H = 11,     /* as FWD_OPT_VECTOR, for the H update */
+  FWD_OPT_VTI_GRADIENT = 12  /* 0 (default): gradients [nz][ny][nx], d / d ln rho; 1: [2][nz][ny][nx],
+                                d / d ln rho_h then d / d ln rho_v (see fwd_set_model_vti) */
 };
 fwd_status fwd_set_option(fwd_plan *plan, int key, double value);
 fwd_status fwd_get_option(const fwd_plan *plan, int key, double *value);

@@ -1,7 +1,9 @@
 """torch.autograd wrapper: forward modelling with the adjoint gradient.
 
 ``FictitiousForward.apply(log_rho, plan)`` returns E at the receivers
-(complex128 [ns][nr][ncomp][nf]) for the resistivity exp(log_rho); its
+(complex128 [ns][nr][ncomp][nf]) for the resistivity exp(log_rho) (shape
+[nz][ny][nx]; or [2][nz][ny][nx] = (ln rho_h, ln rho_v) for a VTI model,
+whose gradient then has the same two parts, Section 3.1); its
 backward returns d loss / d log_rho (Section 3.5 chain rule) by one of two
 adjoints:
   method="basis" (default)  one adjoint simulation driven by the
@@ -30,8 +32,14 @@ class FictitiousForward(torch.autograd.Function):
     @staticmethod
     def forward(ctx, log_rho: torch.Tensor, plan: Plan, snapshot_every: int = 0,
                 gamma_rel: float = 1e-12, method: str = "basis"):
+        from .fwdem import FWD_OPT_VTI_GRADIENT
         rho = torch.exp(log_rho.detach().to(torch.float64)).cpu().numpy()
-        plan.set_model(rho)
+        vti = rho.ndim == 4
+        if vti:
+            plan.set_model(rho[0], rho[1])
+        else:
+            plan.set_model(rho)
+        plan.set_option(FWD_OPT_VTI_GRADIENT, 1 if vti else 0)
         ctx.plan = plan
         ctx.method = method
         ctx.snapshot_every = snapshot_every

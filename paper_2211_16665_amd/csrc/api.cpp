@@ -70,6 +70,13 @@ fwd_status fwd_set_model(fwd_plan *h, const double *rho) {
   return guard([&] { set_model(P(h), rho); });
 }
 
+fwd_status fwd_set_model_vti(fwd_plan *h, const double *rho_h, const double *rho_v) {
+  return guard([&] {
+    if (!rho_v) fail(FWD_ERR_INVALID_ARG, "rho_v is NULL");
+    set_model(P(h), rho_h, rho_v);
+  });
+}
+
 fwd_status fwd_get_info(const fwd_plan *h, fwd_info *info) {
   return guard([&] {
     const Plan &p = P(h);
@@ -306,6 +313,10 @@ fwd_status fwd_set_option(fwd_plan *h, int key, double value) {
         if (v != 1 && v != 4) fail(FWD_ERR_INVALID_ARG, "vector option in {1, 4}");
         p.vxh = v;
         break;
+      case FWD_OPT_VTI_GRADIENT:
+        if (v != 0 && v != 1) fail(FWD_ERR_INVALID_ARG, "VTI gradient option in {0, 1}");
+        p.vti_grad = v;
+        break;
       default:
         fail(FWD_ERR_INVALID_ARG, "unknown option");
     }
@@ -329,6 +340,7 @@ fwd_status fwd_get_option(const fwd_plan *h, int key, double *value) {
       case FWD_OPT_ZCHUNK: *value = p.kz; break;
       case FWD_OPT_TILE_ORDER: *value = p.order; break;
       case FWD_OPT_VECTOR_H: *value = p.vxh; break;
+      case FWD_OPT_VTI_GRADIENT: *value = p.vti_grad; break;
       default: fail(FWD_ERR_INVALID_ARG, "unknown option");
     }
   });

@@ -1267,10 +1267,13 @@ __global__ void k_rec_out(int ns, int nrows, int nn, int nf, const int *ptr, con
 // gradient per cell from the 12 edges of the cell: with volume-weighted
 // edge averaging, dV_e * d sigma_e / d sigma_c = V_c / 4 for every edge of
 // the cell, so d phi / d ln rho_c = sigma_c V_c / 4 * sum_edges gacc * gscale
-// (gacc summed over the sources)
+// (gacc summed over the sources).  VTI (Section 3.1): the x and y edges give
+// d / d ln rho_h (factor sigma_h V / 4), the z edges d / d ln rho_v (factor
+// sigma_v V / 4); split = 1 writes the two as grad[0], grad[1], else their
+// sum (rho_h and rho_v scaled together).
 __global__ void k_grad_cells(int nx, int ny, int nz, int ns, int PX, int NY, int64_t F,
-                             const double *gedge, const double *cellfac, double gscale,
-                             double *grad, int accumulate) {
+                             const double *gedge, const double *cellfac, const double *cellfac_v,
+                             double gscale, double *grad, int accumulate, int split) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y;
   const int k = blockIdx.z;
@@ -1292,8 +1295,14 @@ __global__ void k_grad_cells(int nx, int ny, int nz, int ns, int PX, int NY, int
   const double sy = ey[0] + ey[1] + ey[2] + ey[3];
   const double sz = ez[0] + ez[1] + ez[2] + ez[3];
   const int64_t c = ((int64_t)k * ny + j) * nx + i;
-  const double v = cellfac[c] * (sx + sy + sz) * gscale;
-  grad[c] = accumulate ? grad[c] + v : v;
+  const double vh = cellfac[c] * (sx + sy) * gscale, vv = cellfac_v[c] * sz * gscale;
+  if (split) {
+    const int64_t nc = (int64_t)nx * ny * nz;
+    grad[c] = accumulate ? grad[c] + vh : vh;
+    grad[nc + c] = accumulate ? grad[nc + c] + vv : vv;
+  } else {
+    grad[c] = accumulate ? grad[c] + (vh + vv) : vh + vv;
+  }
 }
 
 // normalised volume export: out[s][k][c][z][y][x] = V * scale_k; the
@@ -1356,7 +1365,7 @@ struct Dev {
   int2 *tl_ent[2] = {nullptr, nullptr};
   std::string list_key;
   std::vector<DevBuf> list_bufs;
-  double *cellfac = nullptr;
+  double *cellfac = nullptr, *cellfac_v = nullptr;   // sigma_h V / 4, sigma_v V / 4
   double2 *eadj = nullptr;      // adjoint receiver transform when the caller passes none
   // graphs
   hipStream_t cap = nullptr;
@@ -1508,17 +1517,20 @@ static void ensure_tables(Plan &p, hipStream_t stream) {
     d.at_coef = static_cast<double *>(dalloc(d, (size_t)p.ns * nn * 2 * nf * sizeof(double)));
     d.eadj = static_cast<double2 *>(dalloc(d, (size_t)p.ns * p.nr * p.ncomp * nf * sizeof(double2)));
   }
-  // per-cell factor sigma V / 4 (zero for cells above the resistivity cap)
+  // per-cell factors sigma_h V / 4 and sigma_v V / 4 (zero for cells above
+  // the resistivity cap)
   {
-    std::vector<double> cf((size_t)p.nx * p.ny * p.nz);
+    std::vector<double> cf((size_t)p.nx * p.ny * p.nz), cv(cf.size());
     for (int k = 0; k < p.nz; ++k)
       for (int j = 0; j < p.ny; ++j)
         for (int i = 0; i < p.nx; ++i) {
           const size_t c = ((size_t)k * p.ny + j) * p.nx + i;
           const double V = p.ax[0].h[i] * p.ax[1].h[j] * p.ax[2].h[k];
           cf[c] = p.capped[c] ? 0.0 : p.sigma[c] * V * 0.25;
+          cv[c] = p.capped_v[c] ? 0.0 : p.sigma_v[c] * V * 0.25;
         }
     d.cellfac = upload(d, cf);
+    d.cellfac_v = upload(d, cv);
   }
   if (p.have_basis) {
     d.basis = upload(d, p.basis);
@@ -2132,8 +2144,8 @@ void dev_adjoint(Plan &p, void *ws, size_t ws_bytes, const void *vol, const doub
   // gradient on cells
   const double gscale = 1.0 / (p.src_scale * adj_scale);
   hipLaunchKernelGGL(k_grad_cells, dim3((p.nx + 127) / 128, p.ny, p.nz), dim3(128), 0, st, p.nx,
-                     p.ny, p.nz, p.ns, p.PX, p.NY, p.field_elems(), w.gedge, d.cellfac, gscale, grad,
-                     accumulate);
+                     p.ny, p.nz, p.ns, p.PX, p.NY, p.field_elems(), w.gedge, d.cellfac,
+                     d.cellfac_v, gscale, grad, accumulate, p.vti_grad);
   HIP_CHECK(hipGetLastError());
   const int nrows = p.nr * p.ncomp, nn = (int)p.rn_c.size(), n = p.ns * nrows * p.nf();
   double2 *dst = E_adj ? reinterpret_cast<double2 *>(E_adj) : d.eadj;
@@ -2241,8 +2253,8 @@ static void adjoint_td_t(Plan &p, Dev &d, const WS &w, void *ws, char *scratch, 
     HIP_CHECK(hipGetLastError());
   }
   hipLaunchKernelGGL(k_grad_cells, dim3((p.nx + 127) / 128, p.ny, p.nz), dim3(128), 0, st, p.nx,
-                     p.ny, p.nz, p.ns, p.PX, p.NY, p.field_elems(), gedge, d.cellfac, gscale, grad,
-                     accumulate);
+                     p.ny, p.nz, p.ns, p.PX, p.NY, p.field_elems(), gedge, d.cellfac, d.cellfac_v,
+                     gscale, grad, accumulate, p.vti_grad);
   HIP_CHECK(hipGetLastError());
 }
 

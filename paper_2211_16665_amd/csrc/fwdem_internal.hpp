@@ -70,8 +70,11 @@ struct Plan {
 
   // ---- derived from the model ----
   bool have_model = false;
-  std::vector<double> rho, sigma;
+  std::vector<double> rho, sigma;        // rho_h and sigma_h in VTI
   std::vector<uint8_t> capped;
+  bool vti = false;                      // vertical resistivity given
+  std::vector<double> sigma_v;           // = sigma when isotropic
+  std::vector<uint8_t> capped_v;
   std::vector<double> sig_e[3];          // edge conductivity, padded layout
   std::vector<double> ce[3];             // dt/eps on updated edges, 0 elsewhere
   double dt = 0, dt_cfl = 0, vmax = 0, vref = 0, amax = 0;
@@ -107,6 +110,7 @@ struct Plan {
   int sched = 0;                         // 0: H and E launches per step; 1: one fused launch
   int kz = 8;                            // planes per block of the fused schedule
   int order = 0;                         // tile numbering: 0 x fastest, 1 z fastest
+  int vti_grad = 0;                      // 1: gradients as [d/d ln rho_h, d/d ln rho_v]
 
   // ---- device side (managed in device.hip) ----
   void *dev = nullptr;
@@ -131,7 +135,7 @@ struct Plan {
 
 // host setup (setup.cpp)
 Plan *plan_create(const fwd_plan_desc *d);
-void set_model(Plan &p, const double *rho);
+void set_model(Plan &p, const double *rho, const double *rho_v = nullptr);
 void basis_build(Plan &p, double gamma_rel, double gamma_abs, int max_iter, double tol,
                  double *fit_err, int *iters);
 void adjoint_coefficients(const Plan &p, const double *resid_host, std::vector<double> &T,

@@ -265,12 +265,16 @@ static double dual_volume(const Plan &p, int c, int k, int j, int i) {
   return X.hd[i] * Y.hd[j] * Z.h[k];
 }
 
-void set_model(Plan &p, const double *rho) {
+void set_model(Plan &p, const double *rho, const double *rho_v) {
   if (!rho) fail(FWD_ERR_INVALID_ARG, "rho is NULL");
   const int nx = p.nx, ny = p.ny, nz = p.nz;
   const int64_t nc = (int64_t)nx * ny * nz;
   for (int64_t q = 0; q < nc; ++q)
     if (!(rho[q] > 0) || !std::isfinite(rho[q])) fail(FWD_ERR_INVALID_ARG, "rho must be finite and > 0");
+  if (rho_v)
+    for (int64_t q = 0; q < nc; ++q)
+      if (!(rho_v[q] > 0) || !std::isfinite(rho_v[q]))
+        fail(FWD_ERR_INVALID_ARG, "rho_v must be finite and > 0");
   const Axis &X = p.ax[0], &Y = p.ax[1], &Z = p.ax[2];
   const double old_dt = p.dt;
   const int old_nt = p.nt;
@@ -278,6 +282,11 @@ void set_model(Plan &p, const double *rho) {
   p.rho.assign(rho, rho + nc);
   p.sigma.resize(nc);
   p.capped.resize(nc);
+  // VTI (Section 2): sigma_h = sigma_xx = sigma_yy from rho, sigma_v =
+  // sigma_zz from rho_v (isotropic when rho_v is NULL)
+  p.vti = rho_v != nullptr;
+  p.sigma_v.resize(nc);
+  p.capped_v.resize(nc);
   double bound = std::numeric_limits<double>::infinity(), vmax = 0;
   for (int k = 0; k < nz; ++k)
     for (int j = 0; j < ny; ++j)
@@ -286,8 +295,12 @@ void set_model(Plan &p, const double *rho) {
         const double r = std::min(rho[q], p.cap);    // air as cells at the capped resistivity
         p.capped[q] = rho[q] > p.cap;
         p.sigma[q] = 1.0 / r;
-        // fictitious wave speed v = 1/sqrt(mu eps), eps = sigma / (2 omega0)
-        const double v = std::sqrt(2.0 * p.omega0 / (kMu0 * p.sigma[q]));
+        const double rv = rho_v ? rho_v[q] : rho[q];
+        p.capped_v[q] = rv > p.cap;
+        p.sigma_v[q] = 1.0 / std::min(rv, p.cap);
+        // fictitious wave speed v = 1/sqrt(mu eps), eps = sigma / (2 omega0),
+        // taken along the faster (more resistive) direction of the cell
+        const double v = std::sqrt(2.0 * p.omega0 / (kMu0 * std::min(p.sigma[q], p.sigma_v[q])));
         vmax = std::max(vmax, v);
         const double inv = std::sqrt(1.0 / (X.h[i] * X.h[i]) + 1.0 / (Y.h[j] * Y.h[j]) +
                                      1.0 / (Z.h[k] * Z.h[k]));
@@ -323,6 +336,7 @@ void set_model(Plan &p, const double *rho) {
     p.ce[c].assign(F, 0.0);
   }
   auto cellsig = [&](int k, int j, int i) { return p.sigma[((int64_t)k * ny + j) * nx + i]; };
+  auto cellsig_v = [&](int k, int j, int i) { return p.sigma_v[((int64_t)k * ny + j) * nx + i]; };
   for (int k = 0; k <= nz; ++k)
     for (int j = 0; j <= ny; ++j)
       for (int i = 0; i <= nx; ++i) {
@@ -358,7 +372,7 @@ void set_model(Plan &p, const double *rho) {
             for (int ii = i - 1; ii <= i; ++ii)
               if (jj >= 0 && jj < ny && ii >= 0 && ii < nx) {
                 const double w = Y.h[jj] * X.h[ii];
-                num += w * cellsig(k, jj, ii);
+                num += w * cellsig_v(k, jj, ii);   // z edges: vertical conductivity
                 den += w;
               }
           p.sig_e[2][q] = num / den;

@@ -28,7 +28,8 @@ FWD_MODE_FORWARD, FWD_MODE_ADJOINT = 0, 1
  FWD_TAB_CPML_Z, FWD_TAB_BASIS, FWD_TAB_EDGE_SIGMA) = range(8)
 (FWD_OPT_GRAPH_STEPS, FWD_OPT_BLOCK_X, FWD_OPT_BLOCK_Y, FWD_OPT_XCD_REMAP,
  FWD_OPT_SAMPLE_EVERY, FWD_OPT_STRICT_CFL, FWD_OPT_DFT_BLOCK, FWD_OPT_VECTOR,
- FWD_OPT_SCHEDULE, FWD_OPT_ZCHUNK, FWD_OPT_TILE_ORDER, FWD_OPT_VECTOR_H) = range(12)
+ FWD_OPT_SCHEDULE, FWD_OPT_ZCHUNK, FWD_OPT_TILE_ORDER, FWD_OPT_VECTOR_H,
+ FWD_OPT_VTI_GRADIENT) = range(13)
 
 ACC_MODES = {"f64": FWD_ACC_F64, "kahan": FWD_ACC_KAHAN, "f32": FWD_ACC_F32}
 DTYPES = {"f32": FWD_F32, "f64": FWD_F64}
@@ -76,6 +77,7 @@ SIGNATURES = {
     "fwd_plan_create": (c_int, [POINTER(fwd_plan_desc), POINTER(c_void_p)]),
     "fwd_plan_destroy": (None, [c_void_p]),
     "fwd_set_model": (c_int, [c_void_p, POINTER(c_double)]),
+    "fwd_set_model_vti": (c_int, [c_void_p, POINTER(c_double), POINTER(c_double)]),
     "fwd_get_info": (c_int, [c_void_p, POINTER(fwd_info)]),
     "fwd_get_table": (c_int, [c_void_p, c_int, POINTER(c_double), c_size_t]),
     "fwd_workspace_size": (c_int, [c_void_p, c_int, POINTER(c_size_t)]),
@@ -207,11 +209,25 @@ class Plan:
             self.handle = None
 
     # ---- host-side calls --------------------------------------------------
-    def set_model(self, rho):
+    def set_model(self, rho, rho_v=None):
+        """Cell resistivity [nz][ny][nx]; with ``rho_v`` a VTI model (rho is
+        then the horizontal resistivity)."""
         r = np.ascontiguousarray(np.asarray(rho, dtype=np.float64))
         if r.shape != self.shape:
             raise ValueError(f"rho must have shape {self.shape}")
-        check(self.lib.fwd_set_model(self.handle, _dptr(r)))
+        if rho_v is None:
+            check(self.lib.fwd_set_model(self.handle, _dptr(r)))
+            return
+        rv = np.ascontiguousarray(np.asarray(rho_v, dtype=np.float64))
+        if rv.shape != self.shape:
+            raise ValueError(f"rho_v must have shape {self.shape}")
+        check(self.lib.fwd_set_model_vti(self.handle, _dptr(r), _dptr(rv)))
+
+    @property
+    def grad_shape(self):
+        """Shape of a gradient: (nz, ny, nx), or (2, nz, ny, nx) for the split
+        VTI gradient (FWD_OPT_VTI_GRADIENT = 1)."""
+        return ((2,) + self.shape) if self.get_option(FWD_OPT_VTI_GRADIENT) else self.shape
 
     @property
     def info(self) -> fwd_info:
@@ -323,7 +339,9 @@ class Plan:
         ws = self.workspace(FWD_MODE_ADJOINT)
         resid = resid.to(device="cuda", dtype=torch.complex128).contiguous()
         if grad is None:
-            grad = torch.zeros(self.shape, dtype=torch.float64, device="cuda")
+            grad = torch.zeros(self.grad_shape, dtype=torch.float64, device="cuda")
+        elif tuple(grad.shape) != tuple(self.grad_shape) or grad.dtype != torch.float64:
+            raise ValueError(f"grad must be float64 of shape {self.grad_shape}")
         Ea = self.rec_buffer() if want_adjoint_rec else None
         check(self.lib.fwd_adjoint(self.handle, _ptr(ws), ws.numel(), _ptr(vol), _ptr(resid),
                                    _ptr(grad), int(accumulate), _ptr(Ea), _stream(stream)))
@@ -346,7 +364,9 @@ class Plan:
             scratch = torch.empty(need, dtype=torch.uint8, device="cuda")
         resid = resid.to(device="cuda", dtype=torch.complex128).contiguous()
         if grad is None:
-            grad = torch.zeros(self.shape, dtype=torch.float64, device="cuda")
+            grad = torch.zeros(self.grad_shape, dtype=torch.float64, device="cuda")
+        elif tuple(grad.shape) != tuple(self.grad_shape) or grad.dtype != torch.float64:
+            raise ValueError(f"grad must be float64 of shape {self.grad_shape}")
         check(self.lib.fwd_adjoint_td(self.handle, _ptr(ws), ws.numel(), _ptr(scratch),
                                       scratch.numel(), int(segment), _ptr(resid), _ptr(grad),
                                       int(accumulate), _stream(stream)))

@@ -491,3 +491,90 @@ def test_td_gradient_independent_of_segments_and_schedule(dtype):
     g = torch.from_numpy(ref).cuda()
     p.adjoint_td(r, grad=g, accumulate=True, segment=50)
     assert same(g.cpu().numpy(), 2 * ref)
+
+
+# --------------------------------------------------------------------------
+# VTI (Section 2 sigma_h / sigma_v; Section 3.1 split gradient)
+# --------------------------------------------------------------------------
+def _vti_problem(seed=3, ns=2):
+    from workloads import with_vti
+    w_true = with_vti(tiny(seed=seed, n=(14, 12, 10), npml=3, contrast=1.0, nr=8, nfreq=2, ns=ns),
+                      ratio=3.0, seed=seed, rho_min=0.0)
+    rng = np.random.default_rng(seed + 200)
+    w0 = w_true.replace(rho=w_true.rho * np.exp(0.3 * rng.standard_normal(w_true.rho.shape)),
+                        rho_v=w_true.rho_v * np.exp(0.3 * rng.standard_normal(w_true.rho.shape)))
+    d = oracle.forward(w_true)["E_rec"]
+    s0 = make_setup(w0)
+    w0 = w0.replace(dt=s0.dt, nt=s0.nt)
+    w0.cpml_vref = s0.vref
+    return w0, d
+
+
+def test_vti_forward_and_gradients_match_oracle():
+    from oracle.adjoint_td import adjoint_gradient_td
+    w0, d = _vti_problem()
+    say("VTI forward and split gradients against the oracle (fp64)")
+    fwd = oracle.forward(w0, want_volume=True)
+    resid = d - fwd["E_rec"]
+    gb = oracle.adjoint_gradient(w0, fwd, resid)
+    gt = adjoint_gradient_td(w0, resid)
+    p = fw.Plan.from_workload(w0, field_dtype="f64")
+    p.set_model(w0.rho, w0.rho_v)
+    p.set_option(fw.FWD_OPT_VTI_GRADIENT, 1)
+    p.basis_build(gamma_rel=1e-12)
+    E, vol = p.forward(want_volume=True)
+    assert rel(E.cpu().numpy(), fwd["E_rec"]) < 1e-11
+    r = torch.from_numpy(resid).cuda()
+    g = p.adjoint(vol, r).cpu().numpy()
+    g2 = p.adjoint_td(r, segment=50).cpu().numpy()
+    for k, name in enumerate(("grad_h", "grad_v")):
+        eb = np.linalg.norm(g[k] - gb[name]) / np.linalg.norm(gb[name])
+        et = np.linalg.norm(g2[k] - gt[name]) / np.linalg.norm(gt[name])
+        say(f"  {name}: basis {eb:.2e}, time-domain {et:.2e}")
+        assert eb < 1e-7 and et < 1e-9
+    # option 0: the sum (rho_h and rho_v scaled together)
+    p.set_option(fw.FWD_OPT_VTI_GRADIENT, 0)
+    g0 = p.adjoint(vol, r).cpu().numpy()
+    assert np.allclose(g0, g[0] + g[1], rtol=1e-13, atol=1e-13 * np.abs(g0).max())
+
+
+def test_vti_with_equal_resistivities_is_bitwise_isotropic():
+    w0, d = _inverse_problem(seed=5, ns=2)
+    say("VTI with rho_v = rho against the isotropic path")
+    out = []
+    for vti in (False, True):
+        p = fw.Plan.from_workload(w0, field_dtype="f32")
+        p.set_model(w0.rho, w0.rho if vti else None)
+        p.basis_build(gamma_rel=1e-12)
+        E, vol = p.forward(want_volume=True)
+        r = torch.from_numpy(d).cuda() - E
+        out.append([E.cpu().numpy(), p.adjoint(vol, r).cpu().numpy(),
+                    p.adjoint_td(r, segment=64).cpu().numpy()])
+    for a, b in zip(*out):
+        assert same(a, b)
+
+
+@pytest.mark.parametrize("method", ["basis", "time"])
+def test_vti_autograd_matches_finite_differences(method):
+    from paper_2211_16665_amd.autograd import FictitiousForward, misfit
+    w0, d = _vti_problem(seed=4, ns=1)
+    say(f"VTI autograd ({method}) against finite differences (fp64)")
+    p = fw.Plan.from_workload(w0, field_dtype="f64")
+    dd = torch.from_numpy(d).cuda()
+    m0 = np.log(np.stack([w0.rho, w0.rho_v]))
+    m = torch.tensor(m0, dtype=torch.float64, device="cuda", requires_grad=True)
+    L = misfit(FictitiousForward.apply(m, p, 64, 1e-12, method), dd)
+    L.backward()
+    g = m.grad.cpu().numpy()
+    h = 1e-3
+    for c in [(0, 4, 5, 6), (1, 4, 5, 6), (0, 5, 6, 7), (1, 6, 4, 8)]:
+        vals = []
+        for sgn in (1, -1):
+            mm = m0.copy()
+            mm[c] += sgn * h
+            with torch.no_grad():
+                E = FictitiousForward.apply(torch.from_numpy(mm).cuda(), p)
+            vals.append(float(misfit(E, dd)))
+        fd = (vals[0] - vals[1]) / (2 * h)
+        say(f"  {c}: fd {fd:.6e} adjoint {g[c]:.6e}")
+        assert abs(fd - g[c]) < 1e-4 * abs(fd), (c, fd, g[c])

@@ -12,7 +12,7 @@ import pytest
 import oracle
 from oracle.basis import basis_matrix, basis_pinv, gamma_from_rel
 from oracle.discretization import make_setup
-from workloads import c1_wholespace, c2_marine1d, c3_blocks, tiny
+from workloads import with_vti, c1_wholespace, c2_marine1d, c3_blocks, tiny
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 fw = pytest.importorskip("paper_2211_16665_amd.fwdem")
@@ -88,11 +88,14 @@ def test_errors_before_any_device_call(lib):
 
 
 @pytest.mark.parametrize("make", [c1_wholespace, c2_marine1d, c3_blocks,
-                                  lambda: tiny(seed=3, stretch=1.3, contrast=2.0)])
+                                  lambda: tiny(seed=3, stretch=1.3, contrast=2.0),
+                                  lambda: with_vti(tiny(seed=4, stretch=1.3, contrast=1.0),
+                                                   ratio=5.0, seed=4, rho_min=0.0),
+                                  lambda: with_vti(c2_marine1d(), ratio=2.0)])
 def test_setup_matches_oracle(lib, make):
     w = make()
     p = _plan(w)
-    p.set_model(w.rho)
+    p.set_model(w.rho, getattr(w, "rho_v", None))
     s = make_setup(w)
     i = p.info
     assert np.isclose(i.dt, s.dt, rtol=1e-13)
