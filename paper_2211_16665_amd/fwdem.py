@@ -14,6 +14,10 @@ from ctypes import (POINTER, Structure, c_double, c_int, c_size_t, c_void_p,
                     byref)
 
 import numpy as np
+# torch first: libfwdem.so then binds the HIP runtime torch has loaded, so
+# the library and the torch tensors it is handed share one runtime (loading
+# the library first would bind the system runtime and torch a second one)
+import torch  # noqa: F401
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "lib", "libfwdem.so")
