@@ -17,7 +17,8 @@ oracle stepping the same grid for a bounded window of steps.
 batched_vs_plain: gradient time of the 16-source batched workload on a
 window, one batched plan against one single-source plan per source.
 adjoint_td: the time-domain adjoint gradient of the same step (after the
-timed region) against the basis-function one.
+timed region) against the basis-function one.  vti: the same step on a VTI
+version of the model, with the split gradient.
 """
 from __future__ import annotations
 
@@ -182,6 +183,42 @@ def batched_vs_plain(window=200):
             "max_rel_grad_diff": diff}
 
 
+def vti_study(plan, w_true, rho0, iso_s):
+    """The same gradient step on a VTI version of the marine model (vertical
+    resistivity twice the horizontal one below the sea floor), with the split
+    gradient: time against the isotropic step (same kernels; only the edge
+    conductivities and the gradient scatter differ)."""
+    import torch
+    from paper_2211_16665_amd import fwdem as fw
+    from workloads import with_vti
+    wv = with_vti(w_true, ratio=2.0)
+    plan.set_model(wv.rho, wv.rho_v)
+    d_obs = plan.forward()
+    rv0 = rho0.copy()
+    rv0[rho0 >= 0.9] *= 2.0
+    plan.set_option(fw.FWD_OPT_VTI_GRADIENT, 1)
+    vol = plan.volume_buffer()
+    grad = torch.zeros(plan.grad_shape, dtype=torch.float64, device="cuda")
+
+    def step():
+        plan.set_model(rho0, rv0)
+        plan.basis_build(gamma_rel=1e-12)
+        E, _ = plan.forward(vol=vol, want_volume=True)
+        plan.adjoint(vol, d_obs - E, grad=grad)
+
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    step()
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    plan.set_option(fw.FWD_OPT_VTI_GRADIENT, 0)
+    g = grad.abs().amax(dim=(1, 2, 3)).tolist()
+    return {"model": "c2_marine1d with rho_v = 2 rho_h below the sea floor", "gradient_s": t,
+            "isotropic_gradient_s": iso_s, "nt": plan.info.nt,
+            "max_abs_grad_h": g[0], "max_abs_grad_v": g[1]}
+
+
 def adjoint_td_study(plan, resid, grad_basis, basis_s, npml, segment=500):
     """The time-domain adjoint (Appendix) on the bench workload: gradient time
     (forward with checkpoints, replay, reverse sweep) against the
@@ -245,6 +282,8 @@ def main():
                     help="skip the batched-vs-plain gradient-time comparison")
     ap.add_argument("--no-td", action="store_true",
                     help="skip the time-domain adjoint study")
+    ap.add_argument("--no-vti", action="store_true",
+                    help="skip the VTI gradient timing")
     ap.add_argument("--tiling", default="",
                     help="fixed tiling instead of autotuning: block_x,block_y,xcd_remap,vector")
     ap.add_argument("--profile-steps", type=int, default=0,
@@ -374,6 +413,8 @@ def main():
     if not args.no_td:
         out["adjoint_td"] = adjoint_td_study(plan, resid_last[0], grad, elapsed / args.steps,
                                              w_true.npml)
+    if not args.no_vti:                 # changes the plan's model: after the studies above
+        out["vti"] = vti_study(plan, w_true, rho0, elapsed / args.steps)
     if not args.no_batched:
         del vol, grad
         torch.cuda.empty_cache()
