@@ -11,8 +11,9 @@ Printed: one JSON line.  value = cell updates per second over the two
 simulations of the step (forward + adjoint), in Mcell-updates/s; a cell
 update advances all six field components of one cell by one step.
 roofline: the forward E-update kernel (fused with the volume transform),
-its algorithmic bytes per launch over its average device time measured with
-HIP events on sampled steps inside the timed region.  cpu_baseline: the CPU
+its algorithmic bytes per launch over its average device time, from HIP
+events that the sampled launches inside the timed region stamp from their
+own dispatch (hipExtLaunchKernel).  cpu_baseline: the CPU
 oracle stepping the same grid for a bounded window of steps.
 batched_vs_plain: gradient time of the 16-source batched workload on a
 window, one batched plan against one single-source plan per source.

@@ -306,8 +306,10 @@ fwd_status fwd_last_timing(const fwd_plan *plan, double *ms, int *steps);
  * E update fused with injection, receiver transform and volume transform or
  * gradient product -- over the steps sampled in the last fwd_forward /
  * fwd_adjoint (FWD_OPT_SAMPLE_EVERY > 0), measured with HIP events on the
- * caller's stream.  With the fused schedule the first value is 0 and the
- * second is the one launch of the step.  avg_ms has room for 2 values. */
+ * caller's stream that hipExtLaunchKernel stamps from each sampled kernel's
+ * own dispatch (the kernel alone, as a kernel trace reports it).  With the
+ * fused schedule the first value is 0 and the second is the one launch of
+ * the step.  avg_ms has room for 2 values. */
 fwd_status fwd_kernel_stats(const fwd_plan *plan, double *avg_ms, int *samples);
 
 const char *fwd_last_error(void);

@@ -33,6 +33,7 @@
 // in-order completion counter).  The 1D grid is remapped so that the
 // consecutive blocks of one XCD are spatial neighbours (their halos hit the
 // same L2).
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -1765,16 +1766,31 @@ static StepArgs<T> make_args(Plan &p, Dev &d, const WS &w, void *vol, bool adj, 
   return A;
 }
 
+// start/stop events of one timed launch; hipExtLaunchKernel stamps them
+// from the kernel's own dispatch, so the interval covers the kernel alone
+// (no event-marker or dispatch latency around it)
+struct KTime {
+  hipEvent_t start, stop;
+};
+
+template <typename F, typename A_>
+static void go(F kernel, dim3 grid, dim3 block, size_t lds, hipStream_t st, const KTime *kt,
+               const A_ &a) {
+  if (kt) hipExtLaunchKernelGGL(kernel, grid, block, (std::uint32_t)lds, st, kt->start, kt->stop,
+                                0u, a);
+  else hipLaunchKernelGGL(kernel, grid, block, lds, st, a);
+}
+
 template <typename T, int KB, int VX>
 static void launch_e_vx(const StepArgs<T> &A, int acc, bool adj, bool flush, dim3 grid, dim3 block,
-                        hipStream_t st) {
+                        hipStream_t st, const KTime *kt) {
 #define FWD_LAUNCH(ACCV, ADJV)                                                                 \
   do {                                                                                         \
-    if (flush) hipLaunchKernelGGL((k_flush<T, ACCV, ADJV, KB>), grid, block, 0, st, A);        \
-    else hipLaunchKernelGGL((k_update_e<T, ACCV, ADJV, KB, VX>), grid, block, 0, st, A);       \
+    if (flush) go(k_flush<T, ACCV, ADJV, KB>, grid, block, 0, st, kt, A);                      \
+    else go(k_update_e<T, ACCV, ADJV, KB, VX>, grid, block, 0, st, kt, A);                     \
   } while (0)
   if (!A.vol) {
-    if (!flush) hipLaunchKernelGGL((k_update_e<T, ACC_NONE, false, 1, VX>), grid, block, 0, st, A);
+    if (!flush) go(k_update_e<T, ACC_NONE, false, 1, VX>, grid, block, 0, st, kt, A);
     return;
   }
   switch (acc) {
@@ -1789,92 +1805,91 @@ static void launch_e_vx(const StepArgs<T> &A, int acc, bool adj, bool flush, dim
   }
 #undef FWD_LAUNCH
 }
-
 template <typename T, int KB>
 static void launch_e_kb(const StepArgs<T> &A, int vx, int acc, bool adj, bool flush, dim3 grid,
-                        dim3 block, hipStream_t st) {
+                        dim3 block, hipStream_t st, const KTime *kt) {
   constexpr int VV = (int)(16 / sizeof(T));
-  if (vx == 1) launch_e_vx<T, KB, 1>(A, acc, adj, flush, grid, block, st);
-  else launch_e_vx<T, KB, VV>(A, acc, adj, flush, grid, block, st);
+  if (vx == 1) launch_e_vx<T, KB, 1>(A, acc, adj, flush, grid, block, st, kt);
+  else launch_e_vx<T, KB, VV>(A, acc, adj, flush, grid, block, st, kt);
 }
-
-// E update (flush = false) or the flush of an incomplete transform block
 template <typename T>
 static void launch_e(const StepArgs<T> &A, int kb, int vx, int acc, bool adj, bool flush,
-                     dim3 grid, dim3 block, hipStream_t st) {
+                     dim3 grid, dim3 block, hipStream_t st, const KTime *kt = nullptr) {
   switch (kb) {
-    case 1: launch_e_kb<T, 1>(A, vx, acc, adj, flush, grid, block, st); break;
-    case 2: launch_e_kb<T, 2>(A, vx, acc, adj, flush, grid, block, st); break;
-    case 4: launch_e_kb<T, 4>(A, vx, acc, adj, flush, grid, block, st); break;
-    case 8: launch_e_kb<T, 8>(A, vx, acc, adj, flush, grid, block, st); break;
-    default: launch_e_kb<T, 16>(A, vx, acc, adj, flush, grid, block, st);
+    case 1: launch_e_kb<T, 1>(A, vx, acc, adj, flush, grid, block, st, kt); break;
+    case 2: launch_e_kb<T, 2>(A, vx, acc, adj, flush, grid, block, st, kt); break;
+    case 4: launch_e_kb<T, 4>(A, vx, acc, adj, flush, grid, block, st, kt); break;
+    case 8: launch_e_kb<T, 8>(A, vx, acc, adj, flush, grid, block, st, kt); break;
+    default: launch_e_kb<T, 16>(A, vx, acc, adj, flush, grid, block, st, kt);
   }
 }
 
-// fused step launch, by accumulator flavour and transform block
 template <typename T, int KB>
 static void launch_step_kb(const StepArgs<T> &A, int acc, bool adj, dim3 grid, dim3 block,
-                           size_t lds, hipStream_t st) {
+                           size_t lds, hipStream_t st, const KTime *kt) {
   if (!A.vol) {
-    hipLaunchKernelGGL((k_step<T, ACC_NONE, false, 1>), grid, block, lds, st, A);
+    go(k_step<T, ACC_NONE, false, 1>, grid, block, lds, st, kt, A);
     return;
   }
   switch (acc) {
     case FWD_ACC_F64:
-      if (adj) hipLaunchKernelGGL((k_step<T, ACC_F64, true, KB>), grid, block, lds, st, A);
-      else hipLaunchKernelGGL((k_step<T, ACC_F64, false, KB>), grid, block, lds, st, A);
+      if (adj) go(k_step<T, ACC_F64, true, KB>, grid, block, lds, st, kt, A);
+      else go(k_step<T, ACC_F64, false, KB>, grid, block, lds, st, kt, A);
       break;
     case FWD_ACC_KAHAN:
-      if (adj) hipLaunchKernelGGL((k_step<T, ACC_KAHAN, true, KB>), grid, block, lds, st, A);
-      else hipLaunchKernelGGL((k_step<T, ACC_KAHAN, false, KB>), grid, block, lds, st, A);
+      if (adj) go(k_step<T, ACC_KAHAN, true, KB>, grid, block, lds, st, kt, A);
+      else go(k_step<T, ACC_KAHAN, false, KB>, grid, block, lds, st, kt, A);
       break;
     default:
-      if (adj) hipLaunchKernelGGL((k_step<T, ACC_F32, true, KB>), grid, block, lds, st, A);
-      else hipLaunchKernelGGL((k_step<T, ACC_F32, false, KB>), grid, block, lds, st, A);
+      if (adj) go(k_step<T, ACC_F32, true, KB>, grid, block, lds, st, kt, A);
+      else go(k_step<T, ACC_F32, false, KB>, grid, block, lds, st, kt, A);
   }
 }
 
 template <typename T>
 static void launch_step(const StepArgs<T> &A, int kb, int acc, bool adj, dim3 grid, dim3 block,
-                        size_t lds, hipStream_t st) {
+                        size_t lds, hipStream_t st, const KTime *kt = nullptr) {
   switch (kb) {
-    case 1: launch_step_kb<T, 1>(A, acc, adj, grid, block, lds, st); break;
-    case 2: launch_step_kb<T, 2>(A, acc, adj, grid, block, lds, st); break;
-    case 4: launch_step_kb<T, 4>(A, acc, adj, grid, block, lds, st); break;
-    case 8: launch_step_kb<T, 8>(A, acc, adj, grid, block, lds, st); break;
-    default: launch_step_kb<T, 16>(A, acc, adj, grid, block, lds, st);
+    case 1: launch_step_kb<T, 1>(A, acc, adj, grid, block, lds, st, kt); break;
+    case 2: launch_step_kb<T, 2>(A, acc, adj, grid, block, lds, st, kt); break;
+    case 4: launch_step_kb<T, 4>(A, acc, adj, grid, block, lds, st, kt); break;
+    case 8: launch_step_kb<T, 8>(A, acc, adj, grid, block, lds, st, kt); break;
+    default: launch_step_kb<T, 16>(A, acc, adj, grid, block, lds, st, kt);
   }
 }
 
 template <typename T>
-static void launch_h(const StepArgs<T> &A, int vx, dim3 grid, dim3 block, hipStream_t st) {
+static void launch_h(const StepArgs<T> &A, int vx, dim3 grid, dim3 block, hipStream_t st,
+                     const KTime *kt = nullptr) {
   constexpr int VV = (int)(16 / sizeof(T));
-  if (vx == 1) hipLaunchKernelGGL((k_update_h<T, 1>), grid, block, 0, st, A);
-  else hipLaunchKernelGGL((k_update_h<T, VV>), grid, block, 0, st, A);
+  if (vx == 1) go(k_update_h<T, 1>, grid, block, 0, st, kt, A);
+  else go(k_update_h<T, VV>, grid, block, 0, st, kt, A);
 }
 
 // enqueue one step (H update, E update; or the fused step); if ev !=
-// nullptr, record ev[0..2] around the two kernels (fused: ev[0] and ev[1]
-// before the one launch, ev[2] after it)
+// nullptr, ev[0..1] time the H kernel and ev[2..3] the E kernel (fused: the
+// one kernel in ev[2..3], ev[0..1] recorded back to back)
 template <typename T>
 static void enqueue_step(Plan &p, Dev &d, const WS &w, void *vol, bool adj, hipStream_t st,
                          hipEvent_t *ev, int r) {
   StepArgs<T> A = make_args<T>(p, d, w, vol, adj, r);
   const dim3 block(p.bx, p.by), grid(A.nblocks);
-  if (ev) (void)hipEventRecord(ev[0], st);
+  const KTime th_ev = ev ? KTime{ev[0], ev[1]} : KTime{}, te_ev = ev ? KTime{ev[2], ev[3]} : KTime{};
+  const KTime *kh = ev ? &th_ev : nullptr, *ke = ev ? &te_ev : nullptr;
   if (p.sched == 1) {
-    if (ev) (void)hipEventRecord(ev[1], st);
-    launch_step<T>(A, p.kb, p.acc, adj, grid, block, tiling(p).lds, st);
+    if (ev) {
+      (void)hipEventRecord(ev[0], st);
+      (void)hipEventRecord(ev[1], st);
+    }
+    launch_step<T>(A, p.kb, p.acc, adj, grid, block, tiling(p).lds, st, ke);
   } else {
     StepArgs<T> Ah = A;
     const Tiling th = tiling(p, true);
     Ah.nbx = th.nbx;
     Ah.nblocks = th.nblocks * p.ns;
-    launch_h<T>(Ah, p.vxh, dim3(Ah.nblocks), block, st);
-    if (ev) (void)hipEventRecord(ev[1], st);
-    launch_e<T>(A, p.kb, p.vx, p.acc, adj, false, grid, block, st);
+    launch_h<T>(Ah, p.vxh, dim3(Ah.nblocks), block, st, kh);
+    launch_e<T>(A, p.kb, p.vx, p.acc, adj, false, grid, block, st, ke);
   }
-  if (ev) (void)hipEventRecord(ev[2], st);
 }
 
 template <typename T>
@@ -1910,13 +1925,13 @@ static void run_steps_t(Plan &p, Dev &d, const WS &w, void *vol, bool adj, int n
     for (int t = 0; t < m; ++t) {
       hipEvent_t *ev = nullptr;
       if (timed) {
-        const size_t need = (size_t)(d.kstat_n + 1) * 3;
+        const size_t need = (size_t)(d.kstat_n + 1) * 4;
         while (d.ev.size() < need) {
           hipEvent_t e;
           HIP_CHECK(hipEventCreate(&e));
           d.ev.push_back(e);
         }
-        ev = &d.ev[(size_t)d.kstat_n * 3];
+        ev = &d.ev[(size_t)d.kstat_n * 4];
         d.kstat_n++;
       }
       enqueue_step<T>(p, d, w, vol, adj, st, ev, r);
@@ -1980,10 +1995,10 @@ static void run_steps_any(Plan &p, Dev &d, const WS &w, void *vol, bool adj, int
 static void collect_kernel_stats(Dev &d) {
   double tot[2] = {0, 0};
   for (int s = 0; s < d.kstat_n; ++s) {
-    hipEvent_t *ev = &d.ev[(size_t)s * 3];
+    hipEvent_t *ev = &d.ev[(size_t)s * 4];
     for (int k = 0; k < 2; ++k) {
       float ms = 0;
-      HIP_CHECK(hipEventElapsedTime(&ms, ev[k], ev[k + 1]));
+      HIP_CHECK(hipEventElapsedTime(&ms, ev[2 * k], ev[2 * k + 1]));
       tot[k] += ms;
     }
   }
