@@ -34,6 +34,7 @@ from types import SimpleNamespace
 import numpy as np
 
 from .discretization import MU0, Setup, cell_gradient, edge_sigma_transpose, make_setup
+from .stencil import diff_e, diff_e_t, diff_h, diff_h_t
 from .stepping import receiver_nodes, source_injection
 
 FIELDS = ("Ex", "Ey", "Ez", "Hx", "Hy", "Hz")
@@ -66,8 +67,10 @@ def ops(s: Setup) -> SimpleNamespace:
         "Ey_z": (nz - 1, ny, nx - 1), "Ey_x": (nz - 1, ny, nx - 1),
         "Ez_x": (nz, ny - 1, nx - 1), "Ez_y": (nz, ny - 1, nx - 1),
     }
-    o.h = {"x": _b(s.hx, 2), "y": _b(s.hy, 1), "z": _b(s.hz, 0)}
-    o.hd = {"x": _b(s.hdx[1:-1], 2), "y": _b(s.hdy[1:-1], 1), "z": _b(s.hdz[1:-1], 0)}
+    # metric lengths of the differences (cell and dual widths for order 2)
+    o.h = {"x": _b(s.mx, 2), "y": _b(s.my, 1), "z": _b(s.mz, 0)}
+    o.hd = {"x": _b(s.mdx[1:-1], 2), "y": _b(s.mdy[1:-1], 1), "z": _b(s.mdz[1:-1], 0)}
+    o.order = s.order
     # CPML (1/kappa is applied as a division by kappa, as in the stepping)
     o.cp_half = {}
     o.cp_int = {}
@@ -84,14 +87,6 @@ def ops(s: Setup) -> SimpleNamespace:
 
 def zero_state(o) -> dict:
     return {k: np.zeros(sh) for k, sh in o.shapes.items()}
-
-
-def _diff(f, axis):
-    if axis == 0:
-        return f[1:] - f[:-1]
-    if axis == 1:
-        return f[:, 1:] - f[:, :-1]
-    return f[:, :, 1:] - f[:, :, :-1]
 
 
 def _interior(name):
@@ -124,7 +119,7 @@ def fwd_step(o, st: dict) -> None:
         dd = []
         for key, src, ax, sl, sign in terms:
             kap, b, a = o.cp_half[ax]
-            D = _diff(st[src][sl], AXIS[ax]) / o.h[ax]
+            D = diff_e(st[src][sl], AXIS[ax], o.order) / o.h[ax]
             st[key] = b * st[key] + a * D
             dd.append(sign * (D / kap + st[key]))
         st[hname] -= o.dtmu * (dd[0] + dd[1])
@@ -132,25 +127,15 @@ def fwd_step(o, st: dict) -> None:
         dd = []
         for key, src, ax, sl, sign in terms:
             kap, b, a = o.cp_int[ax]
-            D = _diff(st[src][sl], AXIS[ax]) / o.hd[ax]
+            D = diff_h(st[src][sl], AXIS[ax], o.order) / o.hd[ax]
             st[key] = b * st[key] + a * D
             dd.append(sign * (D / kap + st[key]))
         st[ename][_interior(ename)] += o.ci[ename] * (dd[0] + dd[1])
 
 
-def _scatter_diff(target, sl, axis, g):
-    """Transpose of D = diff(target[sl], axis): target[sl][hi] += g,
-    target[sl][lo] -= g."""
+def _scatter(target, sl, g):
     view = target[sl]
-    if axis == 0:
-        view[1:] += g
-        view[:-1] -= g
-    elif axis == 1:
-        view[:, 1:] += g
-        view[:, :-1] -= g
-    else:
-        view[:, :, 1:] += g
-        view[:, :, :-1] -= g
+    view += g
 
 
 def adj_step(o, ad: dict) -> None:
@@ -167,7 +152,7 @@ def adj_step(o, ad: dict) -> None:
             tot = ad[key] + add
             aD = add / kap + a * tot
             ad[key] = b * tot
-            _scatter_diff(ad[src], sl, AXIS[ax], aD / o.hd[ax])
+            _scatter(ad[src], sl, diff_h_t(aD / o.hd[ax], AXIS[ax], o.order))
     for hname in ("Hz", "Hy", "Hx"):
         g = -o.dtmu * ad[hname]
         for key, src, ax, sl, sign in H_TERMS[hname]:
@@ -176,7 +161,7 @@ def adj_step(o, ad: dict) -> None:
             tot = ad[key] + add
             aD = add / kap + a * tot
             ad[key] = b * tot
-            _scatter_diff(ad[src], sl, AXIS[ax], aD / o.h[ax])
+            _scatter(ad[src], sl, diff_e_t(aD / o.h[ax], AXIS[ax], o.order))
 
 
 def forward_states(s: Setup, inj: list, tfun: np.ndarray, nt: int):

@@ -26,6 +26,8 @@ from dataclasses import dataclass
 
 import numpy as np
 
+from .stencil import metric_half, metric_node
+
 MU0 = 4.0e-7 * np.pi
 
 # CPML defaults (the paper cites Komatitsch & Martin 2007 without values).
@@ -105,16 +107,19 @@ def edge_sigma_transpose(gx, gy, gz, hx, hy, hz):
     return out
 
 
-def cfl_dt(sig, hx, hy, hz, omega0, cfl):
+def cfl_dt(sig, hx, hy, hz, omega0, cfl, order=2):
     """Time step from the CFL bound of the fictitious wave system, taken cell
     by cell: dt <= 1 / (v sqrt(1/hx^2 + 1/hy^2 + 1/hz^2)) with
     v = 1/sqrt(mu eps) and eps = sigma / (2 omega0) (Section 2; the paper
     notes dt ~ dx in the fictitious domain and that resistive cells shrink
-    it, Section 5)."""
+    it, Section 5).  Order 4 divides the bound by |9/8| + |1/24| = 7/6, the
+    growth of the largest symbol of the staggered difference."""
     eps = sig / (2.0 * omega0)
     v = 1.0 / np.sqrt(MU0 * eps)
     inv = np.sqrt(hx[None, None, :] ** -2 + hy[None, :, None] ** -2
                   + hz[:, None, None] ** -2)
+    if order == 4:
+        inv = inv * (7.0 / 6.0)
     return cfl * float(np.min(1.0 / (v * inv))), float(np.max(v))
 
 
@@ -217,6 +222,13 @@ class Setup:
     norm: np.ndarray           # sqrt(-i omega / 2 omega0) / What
     sigma_v: np.ndarray = None  # vertical conductivity (VTI); = sigma when isotropic
     capped_v: np.ndarray = None
+    order: int = 2             # order of the staggered differences (2 or 4)
+    mx: np.ndarray = None      # metric lengths at the half nodes (= hx for order 2)
+    my: np.ndarray = None
+    mz: np.ndarray = None
+    mdx: np.ndarray = None     # metric lengths at the nodes (= hdx for order 2)
+    mdy: np.ndarray = None
+    mdz: np.ndarray = None
 
 
 def make_setup(p, dt: float | None = None, nt: int | None = None) -> Setup:
@@ -247,9 +259,12 @@ def make_setup(p, dt: float | None = None, nt: int | None = None) -> Setup:
     a = np.sqrt(omega * omega0)
     wprime = (1.0 + 1.0j) * a                            # eq. mittet correspondence
 
+    order = int(getattr(p, "fd_order", 2) or 2)
+    if order not in (2, 4):
+        raise ValueError("fd_order must be 2 or 4")
     # reading (VTI): the bound of each cell taken with its faster (more
     # resistive) direction
-    dt_cfl, vmax = cfl_dt(np.minimum(sigma, sigma_v), hx, hy, hz, omega0, float(p.cfl))
+    dt_cfl, vmax = cfl_dt(np.minimum(sigma, sigma_v), hx, hy, hz, omega0, float(p.cfl), order)
     if dt is None:
         dt = float(p.dt) if getattr(p, "dt", 0.0) else dt_cfl
     if nt is None:
@@ -261,12 +276,12 @@ def make_setup(p, dt: float | None = None, nt: int | None = None) -> Setup:
     ce = tuple(dt * 2.0 * omega0 / s for s in (sx, sy, sz))   # dt/eps, eps = sigma/(2 omega0)
 
     vref = float(getattr(p, "cpml_vref", 0.0) or vmax)
-    order = float(getattr(p, "cpml_order", CPML_ORDER))
+    cpml_order = float(getattr(p, "cpml_order", CPML_ORDER))
     R = float(getattr(p, "cpml_R", CPML_R))
     kmax = float(getattr(p, "cpml_kappa_max", CPML_KAPPA_MAX))
     amax = float(getattr(p, "cpml_alpha_max", 0.0) or CPML_ALPHA_MAX_FACTOR * a.min())
     npml = int(p.npml)
-    cp = {ax: cpml_profile(nodes, npml, dt, vref, order, R, kmax, amax)
+    cp = {ax: cpml_profile(nodes, npml, dt, vref, cpml_order, R, kmax, amax)
           for ax, nodes in (("x", x), ("y", y), ("z", z))}
 
     # source wavelet: derivative of a Gaussian, sampled at (n+1/2) dt
@@ -289,7 +304,9 @@ def make_setup(p, dt: float | None = None, nt: int | None = None) -> Setup:
                  omega0=omega0, freqs=freqs, omega=omega, a=a, wprime=wprime,
                  Omega=Omega, vmax=vmax, vref=vref, cpml=cp, wavelet=wav,
                  tau=tau, t0=t0, What=What, norm=norm, sigma_v=sigma_v,
-                 capped_v=capped_v)
+                 capped_v=capped_v, order=order,
+                 mx=metric_half(x, order), my=metric_half(y, order), mz=metric_half(z, order),
+                 mdx=metric_node(x, order), mdy=metric_node(y, order), mdz=metric_node(z, order))
 
 
 def lattices(s: Setup):
@@ -301,8 +318,10 @@ def lattices(s: Setup):
 
 
 def dual_volumes(s: Setup):
-    """Dual volume of every E edge: edge length times dual face area."""
-    vx = s.hdz[:, None, None] * s.hdy[None, :, None] * s.hx[None, None, :]
-    vy = s.hdz[:, None, None] * s.hy[None, :, None] * s.hdx[None, None, :]
-    vz = s.hz[:, None, None] * s.hdy[None, :, None] * s.hdx[None, None, :]
+    """Dual volume of every E edge: edge length times dual face area, in
+    the metric lengths of the differences (the weights under which the
+    discrete curl pair is adjoint; cell and dual widths for order 2)."""
+    vx = s.mdz[:, None, None] * s.mdy[None, :, None] * s.mx[None, None, :]
+    vy = s.mdz[:, None, None] * s.my[None, :, None] * s.mdx[None, None, :]
+    vz = s.mz[:, None, None] * s.mdy[None, :, None] * s.mdx[None, None, :]
     return vx, vy, vz

@@ -25,6 +25,7 @@ from __future__ import annotations
 import numpy as np
 
 from .discretization import MU0, Setup, dual_volumes, lattices, make_setup, trilinear
+from .stencil import diff_e, diff_h
 
 
 def _b(arr, axis, ndim=3):
@@ -63,8 +64,10 @@ def run_stepping(s: Setup, inj: list, tfun: np.ndarray, rec_nodes: list,
     (kxn, bxn, axn), (kxh, bxh, axh) = s.cpml["x"]
     (kyn, byn, ayn), (kyh, byh, ayh) = s.cpml["y"]
     (kzn, bzn, azn), (kzh, bzh, azh) = s.cpml["z"]
-    hx, hy, hz = _b(s.hx, 2), _b(s.hy, 1), _b(s.hz, 0)
-    hdx, hdy, hdz = _b(s.hdx[1:-1], 2), _b(s.hdy[1:-1], 1), _b(s.hdz[1:-1], 0)
+    # metric lengths of the differences (cell and dual widths for order 2)
+    hx, hy, hz = _b(s.mx, 2), _b(s.my, 1), _b(s.mz, 0)
+    hdx, hdy, hdz = _b(s.mdx[1:-1], 2), _b(s.mdy[1:-1], 1), _b(s.mdz[1:-1], 0)
+    od = s.order
 
     # CPML memory variables, one per derivative (full size for clarity)
     psi = {
@@ -97,30 +100,30 @@ def run_stepping(s: Setup, inj: list, tfun: np.ndarray, rec_nodes: list,
 
     for n in range(nt):
         # H^{n+1/2} = H^{n-1/2} - dt/mu curl E^n
-        dEz_dy = stretched((Ez[:, 1:, :] - Ez[:, :-1, :]) / hy, "Hx_y", kyh, byh, ayh, 1)
-        dEy_dz = stretched((Ey[1:, :, :] - Ey[:-1, :, :]) / hz, "Hx_z", kzh, bzh, azh, 0)
+        dEz_dy = stretched(diff_e(Ez, 1, od) / hy, "Hx_y", kyh, byh, ayh, 1)
+        dEy_dz = stretched(diff_e(Ey, 0, od) / hz, "Hx_z", kzh, bzh, azh, 0)
         Hx -= dtmu * (dEz_dy - dEy_dz)
-        dEx_dz = stretched((Ex[1:, :, :] - Ex[:-1, :, :]) / hz, "Hy_z", kzh, bzh, azh, 0)
-        dEz_dx = stretched((Ez[:, :, 1:] - Ez[:, :, :-1]) / hx, "Hy_x", kxh, bxh, axh, 2)
+        dEx_dz = stretched(diff_e(Ex, 0, od) / hz, "Hy_z", kzh, bzh, azh, 0)
+        dEz_dx = stretched(diff_e(Ez, 2, od) / hx, "Hy_x", kxh, bxh, axh, 2)
         Hy -= dtmu * (dEx_dz - dEz_dx)
-        dEy_dx = stretched((Ey[:, :, 1:] - Ey[:, :, :-1]) / hx, "Hz_x", kxh, bxh, axh, 2)
-        dEx_dy = stretched((Ex[:, 1:, :] - Ex[:, :-1, :]) / hy, "Hz_y", kyh, byh, ayh, 1)
+        dEy_dx = stretched(diff_e(Ey, 2, od) / hx, "Hz_x", kxh, bxh, axh, 2)
+        dEx_dy = stretched(diff_e(Ex, 1, od) / hy, "Hz_y", kyh, byh, ayh, 1)
         Hz -= dtmu * (dEy_dx - dEx_dy)
 
         # E^{n+1} = E^n + dt/eps (curl H^{n+1/2} - J'^{n+1/2}); interior edges only
-        dHz_dy = stretched((Hz[1:-1, 1:, :] - Hz[1:-1, :-1, :]) / hdy, "Ex_y",
+        dHz_dy = stretched(diff_h(Hz[1:-1], 1, od) / hdy, "Ex_y",
                            kyn[1:-1], byn[1:-1], ayn[1:-1], 1)
-        dHy_dz = stretched((Hy[1:, 1:-1, :] - Hy[:-1, 1:-1, :]) / hdz, "Ex_z",
+        dHy_dz = stretched(diff_h(Hy[:, 1:-1], 0, od) / hdz, "Ex_z",
                            kzn[1:-1], bzn[1:-1], azn[1:-1], 0)
         Ex[1:-1, 1:-1, :] += cxi * (dHz_dy - dHy_dz)
-        dHx_dz = stretched((Hx[1:, :, 1:-1] - Hx[:-1, :, 1:-1]) / hdz, "Ey_z",
+        dHx_dz = stretched(diff_h(Hx[:, :, 1:-1], 0, od) / hdz, "Ey_z",
                            kzn[1:-1], bzn[1:-1], azn[1:-1], 0)
-        dHz_dx = stretched((Hz[1:-1, :, 1:] - Hz[1:-1, :, :-1]) / hdx, "Ey_x",
+        dHz_dx = stretched(diff_h(Hz[1:-1], 2, od) / hdx, "Ey_x",
                            kxn[1:-1], bxn[1:-1], axn[1:-1], 2)
         Ey[1:-1, :, 1:-1] += cyi * (dHx_dz - dHz_dx)
-        dHy_dx = stretched((Hy[:, 1:-1, 1:] - Hy[:, 1:-1, :-1]) / hdx, "Ez_x",
+        dHy_dx = stretched(diff_h(Hy[:, 1:-1], 2, od) / hdx, "Ez_x",
                            kxn[1:-1], bxn[1:-1], axn[1:-1], 2)
-        dHx_dy = stretched((Hx[:, 1:, 1:-1] - Hx[:, :-1, 1:-1]) / hdy, "Ez_y",
+        dHx_dy = stretched(diff_h(Hx[:, :, 1:-1], 1, od) / hdy, "Ez_y",
                            kyn[1:-1], byn[1:-1], ayn[1:-1], 1)
         Ez[:, 1:-1, 1:-1] += czi * (dHy_dx - dHx_dy)
         for (c, k, j, i, w, row) in inj:

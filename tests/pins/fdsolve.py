@@ -13,6 +13,12 @@ which is eq. mittet with w' replaced by Omega.  A CPML memory variable
 psi <- b psi + a D transforms to psi^ = a D^ / (1 - b z), so every
 stretched derivative becomes D^ (1/kappa + a/(1 - b z)) at its node.
 Eliminating H^:  (curl_h curl_h / (i Omega mu) + i Omega eps) E^ = J^.
+
+Order 4 (``order=4``): each one-dimensional difference is the pair
+(9/8, -1/24) over the four nearest samples, divided by a metric length (the
+same pair applied to the coordinates); samples beyond a wall are images
+(tangential E odd, H even, coordinates odd).  Rows are assembled here from
+those rules, entry by entry.
 """
 from __future__ import annotations
 
@@ -73,16 +79,82 @@ def _dual(nodes):
     return d
 
 
+A1, A2 = 9.0 / 8.0, -1.0 / 24.0
+
+
+def _e_to_h(r, n, order):
+    """Entries (node, weight) of the difference at half node r (between
+    nodes r and r+1) of a field on nodes 0..n that vanishes at 0 and n."""
+    if order == 2:
+        terms = [(r + 1, 1.0), (r, -1.0)]
+    else:
+        terms = [(r + 1, A1), (r, -A1), (r + 2, A2), (r - 1, -A2)]
+    out = []
+    for m, w in terms:
+        if m < 0:
+            m, w = -m, -w                    # odd image across node 0
+        elif m > n:
+            m, w = 2 * n - m, -w             # odd image across node n
+        out.append((m, w))
+    return out
+
+
+def _h_to_e(i, n, order):
+    """Entries (half node, weight) of the difference at node i (1..n-1) of a
+    field on the half nodes 0..n-1."""
+    if order == 2:
+        terms = [(i, 1.0), (i - 1, -1.0)]
+    else:
+        terms = [(i, A1), (i - 1, -A1), (i + 1, A2), (i - 2, -A2)]
+    out = []
+    for m, w in terms:
+        if m < 0:
+            m = -1 - m                       # even image across node 0
+        elif m > n - 1:
+            m = 2 * n - 1 - m                # even image across node n
+        out.append((m, w))
+    return out
+
+
+def _metrics(nodes, order):
+    """(metric at the half nodes, metric at the nodes)."""
+    n = len(nodes) - 1
+    if order == 2:
+        return np.diff(nodes), _dual(nodes)
+    x0, xn = nodes[0], nodes[-1]
+
+    def X(m):                                # node coordinate with odd images
+        if m < 0:
+            return 2 * x0 - nodes[-m]
+        if m > n:
+            return 2 * xn - nodes[2 * n - m]
+        return nodes[m]
+    c = 0.5 * (nodes[:-1] + nodes[1:])
+
+    def Cc(m):                               # cell centre with odd images
+        if m < 0:
+            return 2 * x0 - c[-1 - m]
+        if m > n - 1:
+            return 2 * xn - c[2 * n - 1 - m]
+        return c[m]
+    mh = np.array([A1 * (X(r + 1) - X(r)) + A2 * (X(r + 2) - X(r - 1)) for r in range(n)])
+    mn = _dual(nodes)
+    for i in range(1, n):
+        mn[i] = A1 * (Cc(i) - Cc(i - 1)) + A2 * (Cc(i + 1) - Cc(i - 2))
+    return mh, mn
+
+
 def solve(x, y, z, rho, npml, f0, freq, dt, sources, receivers, rec_comp,
           vref, cpml_order=2.0, cpml_R=1e-6, kappa_max=1.0, alpha_max=0.0,
-          rho_cap=1e8, rho_v=None):
+          rho_cap=1e8, rho_v=None, order=2):
     """Frequency-domain E at ``receivers`` for each dipole in ``sources``
     (list of (pos, moment)); returns complex [ns][nr][ncomp].  The field is
     that of J (not J'): the right-hand side is sqrt(-i w/2w0) p w_l / V_l."""
     g = Grid(x, y, z)
     nx, ny, nz = g.nx, g.ny, g.nz
     hx, hy, hz = np.diff(x), np.diff(y), np.diff(z)
-    dx, dy, dz = _dual(x), _dual(y), _dual(z)
+    # metric lengths of the differences (= cell and dual widths for order 2)
+    (mx, dx), (my, dy), (mz, dz) = _metrics(x, order), _metrics(y, order), _metrics(z, order)
     w0 = 2 * np.pi * f0
     om = 2 * np.pi * freq
     wp = (1 + 1j) * np.sqrt(om * w0)
@@ -109,32 +181,32 @@ def solve(x, y, z, rho, npml, f0, freq, dt, sources, receivers, rec_comp,
         for j in range(ny):
             for i in range(nx + 1):          # H_x = dEz/dy - dEy/dz
                 r = g.h(0, k, j, i)
-                fy = isy_h[j] / hy[j]
-                fz = isz_h[k] / hz[k]
-                add(r, g.e(2, k, j + 1, i), fy)
-                add(r, g.e(2, k, j, i), -fy)
-                add(r, g.e(1, k + 1, j, i), -fz)
-                add(r, g.e(1, k, j, i), fz)
+                fy = isy_h[j] / my[j]
+                fz = isz_h[k] / mz[k]
+                for m, w in _e_to_h(j, ny, order):
+                    add(r, g.e(2, k, m, i), fy * w)
+                for m, w in _e_to_h(k, nz, order):
+                    add(r, g.e(1, m, j, i), -fz * w)
     for k in range(nz):
         for j in range(ny + 1):
             for i in range(nx):              # H_y = dEx/dz - dEz/dx
                 r = g.h(1, k, j, i)
-                fz = isz_h[k] / hz[k]
-                fx = isx_h[i] / hx[i]
-                add(r, g.e(0, k + 1, j, i), fz)
-                add(r, g.e(0, k, j, i), -fz)
-                add(r, g.e(2, k, j, i + 1), -fx)
-                add(r, g.e(2, k, j, i), fx)
+                fz = isz_h[k] / mz[k]
+                fx = isx_h[i] / mx[i]
+                for m, w in _e_to_h(k, nz, order):
+                    add(r, g.e(0, m, j, i), fz * w)
+                for m, w in _e_to_h(i, nx, order):
+                    add(r, g.e(2, k, j, m), -fx * w)
     for k in range(nz + 1):
         for j in range(ny):
             for i in range(nx):              # H_z = dEy/dx - dEx/dy
                 r = g.h(2, k, j, i)
-                fx = isx_h[i] / hx[i]
-                fy = isy_h[j] / hy[j]
-                add(r, g.e(1, k, j, i + 1), fx)
-                add(r, g.e(1, k, j, i), -fx)
-                add(r, g.e(0, k, j + 1, i), -fy)
-                add(r, g.e(0, k, j, i), fy)
+                fx = isx_h[i] / mx[i]
+                fy = isy_h[j] / my[j]
+                for m, w in _e_to_h(i, nx, order):
+                    add(r, g.e(1, k, j, m), fx * w)
+                for m, w in _e_to_h(j, ny, order):
+                    add(r, g.e(0, k, m, i), -fy * w)
     CE = sp.csr_matrix((vals, (rows, cols)), shape=(g.hoff[-1], g.eoff[-1]))
 
     # curl H -> interior edges
@@ -147,10 +219,10 @@ def solve(x, y, z, rho, npml, f0, freq, dt, sources, receivers, rec_comp,
                 interior.append(r)
                 fy = isy_n[j] / dy[j]
                 fz = isz_n[k] / dz[k]
-                add(r, g.h(2, k, j, i), fy)
-                add(r, g.h(2, k, j - 1, i), -fy)
-                add(r, g.h(1, k, j, i), -fz)
-                add(r, g.h(1, k - 1, j, i), fz)
+                for m, w in _h_to_e(j, ny, order):
+                    add(r, g.h(2, k, m, i), fy * w)
+                for m, w in _h_to_e(k, nz, order):
+                    add(r, g.h(1, m, j, i), -fz * w)
     for k in range(1, nz):
         for j in range(ny):
             for i in range(1, nx):           # E_y: dHx/dz - dHz/dx
@@ -158,10 +230,10 @@ def solve(x, y, z, rho, npml, f0, freq, dt, sources, receivers, rec_comp,
                 interior.append(r)
                 fz = isz_n[k] / dz[k]
                 fx = isx_n[i] / dx[i]
-                add(r, g.h(0, k, j, i), fz)
-                add(r, g.h(0, k - 1, j, i), -fz)
-                add(r, g.h(2, k, j, i), -fx)
-                add(r, g.h(2, k, j, i - 1), fx)
+                for m, w in _h_to_e(k, nz, order):
+                    add(r, g.h(0, m, j, i), fz * w)
+                for m, w in _h_to_e(i, nx, order):
+                    add(r, g.h(2, k, j, m), -fx * w)
     for k in range(nz):
         for j in range(1, ny):
             for i in range(1, nx):           # E_z: dHy/dx - dHx/dy
@@ -169,10 +241,10 @@ def solve(x, y, z, rho, npml, f0, freq, dt, sources, receivers, rec_comp,
                 interior.append(r)
                 fx = isx_n[i] / dx[i]
                 fy = isy_n[j] / dy[j]
-                add(r, g.h(1, k, j, i), fx)
-                add(r, g.h(1, k, j, i - 1), -fx)
-                add(r, g.h(0, k, j, i), -fy)
-                add(r, g.h(0, k, j - 1, i), fy)
+                for m, w in _h_to_e(i, nx, order):
+                    add(r, g.h(1, k, j, m), fx * w)
+                for m, w in _h_to_e(j, ny, order):
+                    add(r, g.h(0, k, m, i), -fy * w)
     CH = sp.csr_matrix((vals, (rows, cols)), shape=(g.eoff[-1], g.hoff[-1]))
 
     # edge permittivity: volume-weighted cell average, eps = sigma / (2 w0)
@@ -212,10 +284,10 @@ def solve(x, y, z, rho, npml, f0, freq, dt, sources, receivers, rec_comp,
 
     def dualvol(c, k, j, i):
         if c == 0:
-            return hx[i] * dy[j] * dz[k]
+            return mx[i] * dy[j] * dz[k]
         if c == 1:
-            return dx[i] * hy[j] * dz[k]
-        return dx[i] * dy[j] * hz[k]
+            return dx[i] * my[j] * dz[k]
+        return dx[i] * dy[j] * mz[k]
 
     def weights(c, p):
         out = []

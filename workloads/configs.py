@@ -41,6 +41,7 @@ class Workload:
     acc_mode: str = "f64"
     extra: dict = field(default_factory=dict)
     rho_v: np.ndarray | None = None   # vertical resistivity (VTI); None: isotropic
+    fd_order: int = 2             # order of the staggered differences (2 or 4)
 
     @property
     def shape(self):
