@@ -110,7 +110,11 @@ enum {
   FWD_TAB_CPML_Y = 4,
   FWD_TAB_CPML_Z = 5,
   FWD_TAB_BASIS = 6,     /* [2 nfreq][nt] basis functions b_k (rows) */
-  FWD_TAB_EDGE_SIGMA = 7 /* [3][nz+1][ny+1][nx+1] edge conductivity (x, y, z edges; unused slots 0) */
+  FWD_TAB_EDGE_SIGMA = 7, /* [3][nz+1][ny+1][nx+1] edge conductivity (x, y, z edges; unused slots 0) */
+  FWD_TAB_METRIC_X = 8,   /* [2][nx+1]: metric lengths of the differences at the half nodes (last
+                             unused), then at the nodes; cell and dual widths for order 2 */
+  FWD_TAB_METRIC_Y = 9,
+  FWD_TAB_METRIC_Z = 10
 };
 
 /* Validate `desc` and create a plan.  Host only.  Errors: INVALID_ARG. */
@@ -283,8 +287,17 @@ enum {
   FWD_OPT_TILE_ORDER = 10,   /* 0 (default): tiles numbered x fastest; 1: z fastest, so the
                                 blocks of neighbouring planes run side by side */
   FWD_OPT_VECTOR_H = 11,     /* as FWD_OPT_VECTOR, for the H update */
-  FWD_OPT_VTI_GRADIENT = 12  /* 0 (default): gradients [nz][ny][nx], d / d ln rho; 1: [2][nz][ny][nx],
+  FWD_OPT_VTI_GRADIENT = 12, /* 0 (default): gradients [nz][ny][nx], d / d ln rho; 1: [2][nz][ny][nx],
                                 d / d ln rho_h then d / d ln rho_v (see fwd_set_model_vti) */
+  FWD_OPT_FD_ORDER = 13      /* order of the staggered differences, 2 (default) or 4 (Section 2:
+                                the paper's engine is high order on the stretched grid).  Order
+                                4 uses the pair (9/8, -1/24) over the four nearest samples,
+                                divided by metric lengths from the same pair on the
+                                coordinates, with tangential E odd and H even across the walls;
+                                the time step bound shrinks by 6/7.  Changing it drops the model
+                                and the basis (call fwd_set_model again); order 4 runs the
+                                two-kernel schedule with vector widths 1 and rejects other
+                                SCHEDULE / VECTOR / VECTOR_H values. */
 };
 fwd_status fwd_set_option(fwd_plan *plan, int key, double value);
 fwd_status fwd_get_option(const fwd_plan *plan, int key, double *value);

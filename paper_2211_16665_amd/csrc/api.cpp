@@ -295,10 +295,12 @@ fwd_status fwd_set_option(fwd_plan *h, int key, double value) {
 
       case FWD_OPT_VECTOR:
         if (v != 1 && v != 4) fail(FWD_ERR_INVALID_ARG, "vector option in {1, 4}");
+        if (v != 1 && p.fd_order == 4) fail(FWD_ERR_INVALID_ARG, "order 4 runs with vector 1");
         p.vx = v;
         break;
       case FWD_OPT_SCHEDULE:
         if (v != 0 && v != 1) fail(FWD_ERR_INVALID_ARG, "schedule option in {0, 1}");
+        if (v != 0 && p.fd_order == 4) fail(FWD_ERR_INVALID_ARG, "order 4 runs with schedule 0");
         p.sched = v;
         break;
       case FWD_OPT_ZCHUNK:
@@ -311,11 +313,26 @@ fwd_status fwd_set_option(fwd_plan *h, int key, double value) {
         break;
       case FWD_OPT_VECTOR_H:
         if (v != 1 && v != 4) fail(FWD_ERR_INVALID_ARG, "vector option in {1, 4}");
+        if (v != 1 && p.fd_order == 4) fail(FWD_ERR_INVALID_ARG, "order 4 runs with vector 1");
         p.vxh = v;
         break;
       case FWD_OPT_VTI_GRADIENT:
         if (v != 0 && v != 1) fail(FWD_ERR_INVALID_ARG, "VTI gradient option in {0, 1}");
         p.vti_grad = v;
+        break;
+      case FWD_OPT_FD_ORDER:
+        if (v != 2 && v != 4) fail(FWD_ERR_INVALID_ARG, "difference order in {2, 4}");
+        if (v != p.fd_order) {
+          p.fd_order = v;
+          p.have_model = false;          // the tables depend on it: set the model again
+          p.have_basis = false;
+          ++p.model_version;
+        }
+        if (v == 4) {
+          p.sched = 0;
+          p.vx = 1;
+          p.vxh = 1;
+        }
         break;
       default:
         fail(FWD_ERR_INVALID_ARG, "unknown option");
@@ -341,6 +358,7 @@ fwd_status fwd_get_option(const fwd_plan *h, int key, double *value) {
       case FWD_OPT_TILE_ORDER: *value = p.order; break;
       case FWD_OPT_VECTOR_H: *value = p.vxh; break;
       case FWD_OPT_VTI_GRADIENT: *value = p.vti_grad; break;
+      case FWD_OPT_FD_ORDER: *value = p.fd_order; break;
       default: fail(FWD_ERR_INVALID_ARG, "unknown option");
     }
   });

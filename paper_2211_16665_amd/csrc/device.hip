@@ -678,6 +678,180 @@ __global__ void __launch_bounds__(256) k_update_e(StepArgs<T> A) {
 }
 
 // ---------------------------------------------------------------------------
+// Fourth-order differences (Section 2: the paper's engine is high order on
+// the stretched grid).  The pair (9/8, -1/24) over the four nearest samples
+// along the axis, in the index coordinate; AX_IH / AX_IHD then hold the
+// inverse metric lengths (the same pair applied to the coordinates).
+// Samples beyond a wall are images: tangential E (zero on the wall) odd, H
+// even.  One element per thread; the raw differences go through the same
+// per-node CPML and update arithmetic as order 2 (a difference (D - 0)
+// scaled by the table is D scaled by it exactly).
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T e_img(const T *f, int64_t base, int64_t st, int m, int n) {
+  if (m < 0) return -f[base - (int64_t)m * st];
+  if (m > n) return -f[base + (int64_t)(2 * n - m) * st];
+  return f[base + (int64_t)m * st];
+}
+template <typename T>
+__device__ __forceinline__ T h_img(const T *f, int64_t base, int64_t st, int m, int n) {
+  m = m < 0 ? -1 - m : (m > n - 1 ? 2 * n - 1 - m : m);
+  return f[base + (int64_t)m * st];
+}
+// E -> H at half node r (0 .. n-1) of E on the nodes 0 .. n
+template <typename T>
+__device__ __forceinline__ T d4_eh(const T *f, int64_t base, int64_t st, int r, int n) {
+  const T a = e_img(f, base, st, r - 1, n), b = f[base + (int64_t)r * st];
+  const T c = f[base + (int64_t)(r + 1) * st], d = e_img(f, base, st, r + 2, n);
+  return fma(T(-1.0 / 24.0), d - a, T(9.0 / 8.0) * (c - b));
+}
+// H -> E at node i (1 .. n-1) of H on the half nodes 0 .. n-1
+template <typename T>
+__device__ __forceinline__ T d4_he(const T *f, int64_t base, int64_t st, int i, int n) {
+  const T a = h_img(f, base, st, i - 2, n), b = f[base + (int64_t)(i - 1) * st];
+  const T c = f[base + (int64_t)i * st], d = h_img(f, base, st, i + 1, n);
+  return fma(T(-1.0 / 24.0), d - a, T(9.0 / 8.0) * (c - b));
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_update_h4(StepArgs<T> A) {
+  int bx, by, bz, s;
+  tile_of(A.nblocks, A.xcd, A.order, A.ns, A.nbx, A.nby, A.nbz, bx, by, bz, s);
+  const int par = (A.step[0] + 1) & 1;   // this step reads half par
+  const int i = bx * blockDim.x + threadIdx.x;
+  const int j = by * blockDim.y + threadIdx.y;
+  const int k = bz;
+  if (i > A.nx || j > A.ny || k > A.nz) return;
+  const Half<T> I = half_of(A, par, s), O = half_of(A, par ^ 1, s);
+  const int PX = A.PX, NY = A.NY, NZ = A.NZ, npml = A.npml, W = 2 * npml;
+  const int64_t plane = (int64_t)NY * PX;
+  const int64_t sX = (int64_t)NZ * NY * W, sY = (int64_t)NZ * W * PX, sZ = (int64_t)W * NY * PX;
+  const bool i_in = i < A.nx, j_in = j < A.ny, k_in = k < A.nz;
+  int lx = 0, ly = 0, lz = 0;
+  const bool py = npml > 0 && pml_half(j, A.ny, npml, ly);
+  const bool pz = npml > 0 && pml_half(k, A.nz, npml, lz);
+  const bool px = npml > 0 && i_in && pml_half(i, A.nx, npml, lx);
+  const int64_t q = (int64_t)k * plane + (int64_t)j * PX + i;
+  const int64_t iX = ((int64_t)k * NY + j) * W + lx;
+  const int64_t iY = ((int64_t)k * W + ly) * PX + i;
+  const int64_t iZ = ((int64_t)lz * NY + j) * PX + i;
+  const T zero = T(0);
+  if (j_in && k_in) {                    // H_x = H_x - dt/mu (dEz/dy - dEy/dz)
+    const T D1 = d4_eh(I.ez, (int64_t)k * plane + i, (int64_t)PX, j, A.ny);
+    const T D2 = d4_eh(I.ey, (int64_t)j * PX + i, plane, k, A.nz);
+    T psy = py ? I.psY[0 * sY + iY] : zero, psz = pz ? I.psZ[0 * sZ + iZ] : zero;
+    O.hx[q] = hx_node(A, j, k, I.hx[q], zero, D1, zero, D2, py, psy, pz, psz);
+    if (py) O.psY[0 * sY + iY] = psy;
+    if (pz) O.psZ[0 * sZ + iZ] = psz;
+  }
+  if (i_in && k_in) {                    // H_y: dEx/dz - dEz/dx
+    const T D1 = d4_eh(I.ex, (int64_t)j * PX + i, plane, k, A.nz);
+    const T D2 = d4_eh(I.ez, (int64_t)k * plane + (int64_t)j * PX, (int64_t)1, i, A.nx);
+    T psz = pz ? I.psZ[1 * sZ + iZ] : zero, psx = px ? I.psX[0 * sX + iX] : zero;
+    O.hy[q] = hy_node(A, i, k, I.hy[q], zero, D1, zero, D2, pz, psz, px, psx);
+    if (pz) O.psZ[1 * sZ + iZ] = psz;
+    if (px) O.psX[0 * sX + iX] = psx;
+  }
+  if (i_in && j_in) {                    // H_z: dEy/dx - dEx/dy
+    const T D1 = d4_eh(I.ey, (int64_t)k * plane + (int64_t)j * PX, (int64_t)1, i, A.nx);
+    const T D2 = d4_eh(I.ex, (int64_t)k * plane + i, (int64_t)PX, j, A.ny);
+    T psx = px ? I.psX[1 * sX + iX] : zero, psy = py ? I.psY[1 * sY + iY] : zero;
+    O.hz[q] = hz_node(A, i, j, I.hz[q], zero, D1, zero, D2, px, psx, py, psy);
+    if (px) O.psX[1 * sX + iX] = psx;
+    if (py) O.psY[1 * sY + iY] = psy;
+  }
+}
+
+template <typename T, int ACC, bool ADJ, int KB>
+__global__ void __launch_bounds__(256) k_update_e4(StepArgs<T> A) {
+  __shared__ int s_n;
+  int bx, by, bz, s;
+  const int b = tile_of(A.nblocks, A.xcd, A.order, A.ns, A.nbx, A.nby, A.nbz, bx, by, bz, s);
+  if (threadIdx.x == 0 && threadIdx.y == 0) {
+    s_n = A.step[0] + 1;
+    if (blockIdx.x == 0) A.step_w[0] = s_n;   // the step this launch completes
+  }
+  __syncthreads();
+  const int n = s_n;
+  const int i = bx * blockDim.x + threadIdx.x;
+  const int j = by * blockDim.y + threadIdx.y;
+  const int k = bz;
+  if (i > A.nx || j > A.ny || k > A.nz) return;
+  const int fl = A.flushed[0];
+  const int tt = A.tile_tab[b];
+  int lo = 0, hi = 0;
+  if (tt >= 0 && n < A.nt) {
+    const int slot = threadIdx.y * blockDim.x + threadIdx.x;
+    lo = A.tl_off[tt + slot];
+    hi = A.tl_off[tt + slot + 1];
+  }
+  const int par = n & 1;
+  const Half<T> I = half_of(A, par, s), O = half_of(A, par ^ 1, s), P = half_of(A, 0, s);
+  const int PX = A.PX, NY = A.NY, NZ = A.NZ, npml = A.npml, W = 2 * npml;
+  const int64_t plane = (int64_t)NY * PX;
+  const int64_t sX = (int64_t)NZ * NY * W, sY = (int64_t)NZ * W * PX, sZ = (int64_t)W * NY * PX;
+  const bool i_int = i >= 1 && i < A.nx, j_int = j >= 1 && j < A.ny, k_int = k >= 1 && k < A.nz;
+  const bool okx = i < A.nx && j_int && k_int;
+  const bool oky = i_int && j < A.ny && k_int;
+  const bool okz = i_int && j_int && k < A.nz;
+  int lx = 0, ly = 0, lz = 0;
+  const bool py = npml > 0 && pml_int(j, A.ny, npml, ly);
+  const bool pz = npml > 0 && pml_int(k, A.nz, npml, lz);
+  const bool px = npml > 0 && i_int && pml_int(i, A.nx, npml, lx);
+  const int64_t q = (int64_t)k * plane + (int64_t)j * PX + i;
+  const int64_t iX = ((int64_t)k * NY + j) * W + lx;
+  const int64_t iY = ((int64_t)k * W + ly) * PX + i;
+  const int64_t iZ = ((int64_t)lz * NY + j) * PX + i;
+  const T zero = T(0);
+  const Vec<T, 1> e0x = vec1(I.ex[q]), e0y = vec1(I.ey[q]), e0z = vec1(I.ez[q]);
+  Vec<T, 1> e1x = e0x, e1y = e0y, e1z = e0z;
+  if (okx) {                             // E_x: dHz/dy - dHy/dz
+    const T D1 = d4_he(O.hz, (int64_t)k * plane + i, (int64_t)PX, j, A.ny);
+    const T D2 = d4_he(O.hy, (int64_t)j * PX + i, plane, k, A.nz);
+    T psy = py ? P.psY[2 * sY + iY] : zero, psz = pz ? P.psZ[2 * sZ + iZ] : zero;
+    const T c = A.ce[q];
+    T v = ex_node(A, j, k, e0x.v[0], c, D1, zero, D2, zero, py, psy, pz, psz);
+    if (lo < hi) v -= (T)((double)c * inject_value(A, lo, hi, s, 0, 0, n));
+    e1x.v[0] = v;
+    if (py) P.psY[2 * sY + iY] = psy;
+    if (pz) P.psZ[2 * sZ + iZ] = psz;
+  }
+  if (oky) {                             // E_y: dHx/dz - dHz/dx
+    const T D1 = d4_he(O.hx, (int64_t)j * PX + i, plane, k, A.nz);
+    const T D2 = d4_he(O.hz, (int64_t)k * plane + (int64_t)j * PX, (int64_t)1, i, A.nx);
+    T psz = pz ? P.psZ[3 * sZ + iZ] : zero, psx = px ? P.psX[2 * sX + iX] : zero;
+    const T c = A.ce[A.F + q];
+    T v = ey_node(A, i, k, e0y.v[0], c, D1, zero, D2, zero, pz, psz, px, psx);
+    if (lo < hi) v -= (T)((double)c * inject_value(A, lo, hi, s, 1, 0, n));
+    e1y.v[0] = v;
+    if (pz) P.psZ[3 * sZ + iZ] = psz;
+    if (px) P.psX[2 * sX + iX] = psx;
+  }
+  if (okz) {                             // E_z: dHy/dx - dHx/dy
+    const T D1 = d4_he(O.hy, (int64_t)k * plane + (int64_t)j * PX, (int64_t)1, i, A.nx);
+    const T D2 = d4_he(O.hx, (int64_t)k * plane + i, (int64_t)PX, j, A.ny);
+    T psx = px ? P.psX[3 * sX + iX] : zero, psy = py ? P.psY[3 * sY + iY] : zero;
+    const T c = A.ce[2 * A.F + q];
+    T v = ez_node(A, i, j, e0z.v[0], c, D1, zero, D2, zero, px, psx, py, psy);
+    if (lo < hi) v -= (T)((double)c * inject_value(A, lo, hi, s, 2, 0, n));
+    e1z.v[0] = v;
+    if (px) P.psX[3 * sX + iX] = psx;
+    if (py) P.psY[3 * sY + iY] = psy;
+  }
+  if (okx) O.ex[q] = e1x.v[0];
+  if (oky) O.ey[q] = e1y.v[0];
+  if (okz) O.ez[q] = e1z.v[0];
+  if (lo < hi) {
+    if (okx) record(A, lo, hi, s, 0, 0, n, (double)e1x.v[0]);
+    if (oky) record(A, lo, hi, s, 1, 0, n, (double)e1y.v[0]);
+    if (okz) record(A, lo, hi, s, 2, 0, n, (double)e1z.v[0]);
+  }
+  post_e<T, ACC, ADJ, KB, 1>(A, s, 0, q, e0x, e1x, okx ? 1u : 0u, n, fl);
+  post_e<T, ACC, ADJ, KB, 1>(A, s, 1, q, e0y, e1y, oky ? 1u : 0u, n, fl);
+  post_e<T, ACC, ADJ, KB, 1>(A, s, 2, q, e0z, e1z, okz ? 1u : 0u, n, fl);
+}
+
+// ---------------------------------------------------------------------------
 // Fused step (one launch per leapfrog step).  A block of bx x by threads
 // owns the columns (i, j) = (x0 + tx, y0 + ty) of a tile and the planes
 // k in [z0, z1) of a chunk.  For each plane:
@@ -1109,7 +1283,32 @@ __device__ __forceinline__ T td_ad_h(const StepArgs<T> &A, const Half<T> &Ad, in
   return aD * axv(A, ax, AX_IH, idx);
 }
 
-template <typename T>
+// Transposed gathers of the fourth-order differences.  An H node at half
+// index r along the axis is used by the H -> E differences at nodes r (9/8),
+// r+1 (-9/8), r-1 (-1/24 of H[r] = H[(r-1)+1] enters with +c2) and r+2; the
+// even images add the node-1 term to r = 0 and the node-(n-1) term to
+// r = n-1.  An E node at index m is used by the E -> H differences at half
+// nodes m-1, m, m-2 and m+1; the odd images add the half-node-0 term to
+// m = 1 and the half-node-(n-1) term to m = n-1.  at(x) is the multiplier
+// of the difference at index x (zero where none is updated).
+template <typename T, typename F>
+__device__ __forceinline__ T gather_h4(F at, int r, int n) {
+  const T c1 = T(9.0 / 8.0), c2 = T(-1.0 / 24.0);
+  T v = c1 * (at(r) - at(r + 1)) + c2 * (at(r - 1) - at(r + 2));
+  if (r == 0) v -= c2 * at(1);
+  if (r == n - 1) v += c2 * at(n - 1);
+  return v;
+}
+template <typename T, typename F>
+__device__ __forceinline__ T gather_e4(F at, int m, int n) {
+  const T c1 = T(9.0 / 8.0), c2 = T(-1.0 / 24.0);
+  T v = c1 * (at(m - 1) - at(m)) + c2 * (at(m - 2) - at(m + 1));
+  if (m == 1) v += c2 * at(0);
+  if (m == n - 1) v -= c2 * at(n - 1);
+  return v;
+}
+
+template <typename T, int ORD>
 __global__ void __launch_bounds__(256) k_td_e(StepArgs<T> A) {
   int bx, by, bz, s;
   tile_of(A.nblocks, A.xcd, A.order, A.ns, A.nbx, A.nby, A.nbz, bx, by, bz, s);
@@ -1148,19 +1347,30 @@ __global__ void __launch_bounds__(256) k_td_e(StepArgs<T> A) {
   // aH += D_h^T aD: H_z is differenced by E_x d1 at j, j+1 and E_y d2 at
   // i, i+1; H_y by E_x d2 at k, k+1 and E_z d1 at i, i+1; H_x by E_y d1 at
   // k, k+1 and E_z d2 at j, j+1
-  if (hz)
-    Ad.hz[q] += td_ad_e(A, Ad, 0, 1, i, j, k) - td_ad_e(A, Ad, 0, 1, i, j + 1, k) +
-                td_ad_e(A, Ad, 1, 2, i, j, k) - td_ad_e(A, Ad, 1, 2, i + 1, j, k);
-  if (hy)
-    Ad.hy[q] += td_ad_e(A, Ad, 0, 2, i, j, k) - td_ad_e(A, Ad, 0, 2, i, j, k + 1) +
-                td_ad_e(A, Ad, 2, 1, i, j, k) - td_ad_e(A, Ad, 2, 1, i + 1, j, k);
-  if (hx)
-    Ad.hx[q] += td_ad_e(A, Ad, 1, 1, i, j, k) - td_ad_e(A, Ad, 1, 1, i, j, k + 1) +
-                td_ad_e(A, Ad, 2, 2, i, j, k) - td_ad_e(A, Ad, 2, 2, i, j + 1, k);
+  if constexpr (ORD == 2) {
+    if (hz)
+      Ad.hz[q] += td_ad_e(A, Ad, 0, 1, i, j, k) - td_ad_e(A, Ad, 0, 1, i, j + 1, k) +
+                  td_ad_e(A, Ad, 1, 2, i, j, k) - td_ad_e(A, Ad, 1, 2, i + 1, j, k);
+    if (hy)
+      Ad.hy[q] += td_ad_e(A, Ad, 0, 2, i, j, k) - td_ad_e(A, Ad, 0, 2, i, j, k + 1) +
+                  td_ad_e(A, Ad, 2, 1, i, j, k) - td_ad_e(A, Ad, 2, 1, i + 1, j, k);
+    if (hx)
+      Ad.hx[q] += td_ad_e(A, Ad, 1, 1, i, j, k) - td_ad_e(A, Ad, 1, 1, i, j, k + 1) +
+                  td_ad_e(A, Ad, 2, 2, i, j, k) - td_ad_e(A, Ad, 2, 2, i, j + 1, k);
+  } else {
+    auto ax = [&](int c, int d) { return [&A, &Ad, c, d, i, j, k](int m) -> T {
+      // the derivative's axis: E_x d1 y, d2 z; E_y d1 z, d2 x; E_z d1 x, d2 y
+      const int a = c == 0 ? (d == 1 ? 1 : 2) : c == 1 ? (d == 1 ? 2 : 0) : (d == 1 ? 0 : 1);
+      return td_ad_e(A, Ad, c, d, a == 0 ? m : i, a == 1 ? m : j, a == 2 ? m : k);
+    }; };
+    if (hz) Ad.hz[q] += gather_h4<T>(ax(0, 1), j, A.ny) + gather_h4<T>(ax(1, 2), i, A.nx);
+    if (hy) Ad.hy[q] += gather_h4<T>(ax(0, 2), k, A.nz) + gather_h4<T>(ax(2, 1), i, A.nx);
+    if (hx) Ad.hx[q] += gather_h4<T>(ax(1, 1), k, A.nz) + gather_h4<T>(ax(2, 2), j, A.ny);
+  }
 }
 
 // Enew, Eold: E^{n+1} and E^n, [ns][3][F]; tdw: 1/(sigma_e dV_e) [3][F]
-template <typename T>
+template <typename T, int ORD>
 __global__ void __launch_bounds__(256) k_td_h(StepArgs<T> A, const T *Enew, const T *Eold,
                                               const double *tdw) {
   int bx, by, bz, s;
@@ -1208,15 +1418,26 @@ __global__ void __launch_bounds__(256) k_td_h(StepArgs<T> A, const T *Enew, cons
   // aE += D_e^T aD: E_x is differenced by H_y d1 at k-1, k and H_z d2 at
   // j-1, j; E_y by H_x d2 at k-1, k and H_z d1 at i-1, i; E_z by H_x d1 at
   // j-1, j and H_y d2 at i-1, i
-  if (okx)
-    Ad.ex[q] += td_ad_h(A, Ad, 1, 1, i, j, k - 1) - td_ad_h(A, Ad, 1, 1, i, j, k) +
-                td_ad_h(A, Ad, 2, 2, i, j - 1, k) - td_ad_h(A, Ad, 2, 2, i, j, k);
-  if (oky)
-    Ad.ey[q] += td_ad_h(A, Ad, 0, 2, i, j, k - 1) - td_ad_h(A, Ad, 0, 2, i, j, k) +
-                td_ad_h(A, Ad, 2, 1, i - 1, j, k) - td_ad_h(A, Ad, 2, 1, i, j, k);
-  if (okz)
-    Ad.ez[q] += td_ad_h(A, Ad, 0, 1, i, j - 1, k) - td_ad_h(A, Ad, 0, 1, i, j, k) +
-                td_ad_h(A, Ad, 1, 2, i - 1, j, k) - td_ad_h(A, Ad, 1, 2, i, j, k);
+  if constexpr (ORD == 2) {
+    if (okx)
+      Ad.ex[q] += td_ad_h(A, Ad, 1, 1, i, j, k - 1) - td_ad_h(A, Ad, 1, 1, i, j, k) +
+                  td_ad_h(A, Ad, 2, 2, i, j - 1, k) - td_ad_h(A, Ad, 2, 2, i, j, k);
+    if (oky)
+      Ad.ey[q] += td_ad_h(A, Ad, 0, 2, i, j, k - 1) - td_ad_h(A, Ad, 0, 2, i, j, k) +
+                  td_ad_h(A, Ad, 2, 1, i - 1, j, k) - td_ad_h(A, Ad, 2, 1, i, j, k);
+    if (okz)
+      Ad.ez[q] += td_ad_h(A, Ad, 0, 1, i, j - 1, k) - td_ad_h(A, Ad, 0, 1, i, j, k) +
+                  td_ad_h(A, Ad, 1, 2, i - 1, j, k) - td_ad_h(A, Ad, 1, 2, i, j, k);
+  } else {
+    auto ax = [&](int c, int d) { return [&A, &Ad, c, d, i, j, k](int m) -> T {
+      // H_x d1 y, d2 z; H_y d1 z, d2 x; H_z d1 x, d2 y
+      const int a = c == 0 ? (d == 1 ? 1 : 2) : c == 1 ? (d == 1 ? 2 : 0) : (d == 1 ? 0 : 1);
+      return td_ad_h(A, Ad, c, d, a == 0 ? m : i, a == 1 ? m : j, a == 2 ? m : k);
+    }; };
+    if (okx) Ad.ex[q] += gather_e4<T>(ax(1, 1), k, A.nz) + gather_e4<T>(ax(2, 2), j, A.ny);
+    if (oky) Ad.ey[q] += gather_e4<T>(ax(0, 2), k, A.nz) + gather_e4<T>(ax(2, 1), i, A.nx);
+    if (okz) Ad.ez[q] += gather_e4<T>(ax(0, 1), j, A.ny) + gather_e4<T>(ax(1, 2), i, A.nx);
+  }
 }
 
 // aE[s][node] += -Re sum_k C[s][node][k] z_k^m (sensitivity of the misfit to
@@ -1271,10 +1492,14 @@ __global__ void k_rec_out(int ns, int nrows, int nn, int nf, const int *ptr, con
 // (gacc summed over the sources).  VTI (Section 3.1): the x and y edges give
 // d / d ln rho_h (factor sigma_h V / 4), the z edges d / d ln rho_v (factor
 // sigma_v V / 4); split = 1 writes the two as grad[0], grad[1], else their
-// sum (rho_h and rho_v scaled together).
+// sum (rho_h and rho_v scaled together).  With fourth-order differences the
+// dual volume of an edge is in metric lengths; vr then holds, per axis, the
+// ratios metric / cell width (half nodes) and metric / dual width (nodes) at
+// stride LA, and each edge term is scaled by the product of its three.
 __global__ void k_grad_cells(int nx, int ny, int nz, int ns, int PX, int NY, int64_t F,
                              const double *gedge, const double *cellfac, const double *cellfac_v,
-                             double gscale, double *grad, int accumulate, int split) {
+                             double gscale, double *grad, int accumulate, int split,
+                             const double *vr, int LA) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y;
   const int k = blockIdx.z;
@@ -1290,6 +1515,16 @@ __global__ void k_grad_cells(int nx, int ny, int nz, int ns, int PX, int NY, int
       ex[e] += gx[q + ox[e]];
       ey[e] += gy[q + oy[e]];
       ez[e] += gz[q + oz[e]];
+    }
+  }
+  if (vr) {
+    const double *hx = vr, *nxr = vr + LA, *hy = vr + 2 * LA, *nyr = vr + 3 * LA,
+                 *hz = vr + 4 * LA, *nzr = vr + 5 * LA;
+    for (int e = 0; e < 4; ++e) {
+      const int a = e & 1, b = e >> 1;
+      ex[e] *= hx[i] * nyr[j + a] * nzr[k + b];
+      ey[e] *= hy[j] * nxr[i + a] * nzr[k + b];
+      ez[e] *= hz[k] * nxr[i + a] * nyr[j + b];
     }
   }
   const double sx = ex[0] + ex[1] + ex[2] + ex[3];
@@ -1367,6 +1602,7 @@ struct Dev {
   std::string list_key;
   std::vector<DevBuf> list_bufs;
   double *cellfac = nullptr, *cellfac_v = nullptr;   // sigma_h V / 4, sigma_v V / 4
+  double *vratio = nullptr;     // order 4: metric / plain dual-volume ratios per axis
   double2 *eadj = nullptr;      // adjoint receiver transform when the caller passes none
   // graphs
   hipStream_t cap = nullptr;
@@ -1448,8 +1684,8 @@ static void upload_model_tables(Plan &p, Dev &d) {
   for (int a = 0; a < 3; ++a) {
     const Axis &ax = p.ax[a];
     double *b = t.data() + (size_t)a * AX_TABLES * LA;
-    for (int i = 0; i < ax.n; ++i) b[AX_IH * LA + i] = 1.0 / ax.h[i];
-    for (int i = 0; i <= ax.n; ++i) b[AX_IHD * LA + i] = 1.0 / ax.hd[i];
+    for (int i = 0; i < ax.n; ++i) b[AX_IH * LA + i] = 1.0 / ax.m[i];
+    for (int i = 0; i <= ax.n; ++i) b[AX_IHD * LA + i] = 1.0 / ax.md[i];
     std::copy(ax.kinv_n.begin(), ax.kinv_n.end(), b + AX_KN * LA);
     std::copy(ax.b_n.begin(), ax.b_n.end(), b + AX_BN * LA);
     std::copy(ax.a_n.begin(), ax.a_n.end(), b + AX_AN * LA);
@@ -1470,6 +1706,7 @@ static void ensure_tables(Plan &p, hipStream_t stream) {
     return;
   HIP_CHECK(hipStreamSynchronize(stream));
   free_tables(d);
+  d.vratio = nullptr;
   d.device = dev;
   if (!d.cap) HIP_CHECK(hipStreamCreateWithFlags(&d.cap, hipStreamNonBlocking));
   if (p.dtype == FWD_F64)
@@ -1532,6 +1769,19 @@ static void ensure_tables(Plan &p, hipStream_t stream) {
         }
     d.cellfac = upload(d, cf);
     d.cellfac_v = upload(d, cv);
+  }
+  // order 4: the dual volume of an edge in metric lengths over the one the
+  // cell factors assume (cell and dual widths), per axis: [axis][half n |
+  // node n+1] at stride LA; the ratio of an edge is a product of three
+  if (p.fd_order == 4) {
+    const int LA = d.LA;
+    std::vector<double> r((size_t)3 * 2 * LA, 1.0);
+    for (int a = 0; a < 3; ++a) {
+      const Axis &ax = p.ax[a];
+      for (int i = 0; i < ax.n; ++i) r[(size_t)(2 * a) * LA + i] = ax.m[i] / ax.h[i];
+      for (int i = 0; i <= ax.n; ++i) r[(size_t)(2 * a + 1) * LA + i] = ax.md[i] / ax.hd[i];
+    }
+    d.vratio = upload(d, r);
   }
   if (p.have_basis) {
     d.basis = upload(d, p.basis);
@@ -1812,9 +2062,49 @@ static void launch_e_kb(const StepArgs<T> &A, int vx, int acc, bool adj, bool fl
   if (vx == 1) launch_e_vx<T, KB, 1>(A, acc, adj, flush, grid, block, st, kt);
   else launch_e_vx<T, KB, VV>(A, acc, adj, flush, grid, block, st, kt);
 }
+// fourth-order E update (one element per thread)
+template <typename T, int KB>
+static void launch_e4_kb(const StepArgs<T> &A, int acc, bool adj, dim3 grid, dim3 block,
+                         hipStream_t st, const KTime *kt) {
+  if (!A.vol) {
+    go(k_update_e4<T, ACC_NONE, false, 1>, grid, block, 0, st, kt, A);
+    return;
+  }
+  switch (acc) {
+    case FWD_ACC_F64:
+      if (adj) go(k_update_e4<T, ACC_F64, true, KB>, grid, block, 0, st, kt, A);
+      else go(k_update_e4<T, ACC_F64, false, KB>, grid, block, 0, st, kt, A);
+      break;
+    case FWD_ACC_KAHAN:
+      if (adj) go(k_update_e4<T, ACC_KAHAN, true, KB>, grid, block, 0, st, kt, A);
+      else go(k_update_e4<T, ACC_KAHAN, false, KB>, grid, block, 0, st, kt, A);
+      break;
+    default:
+      if (adj) go(k_update_e4<T, ACC_F32, true, KB>, grid, block, 0, st, kt, A);
+      else go(k_update_e4<T, ACC_F32, false, KB>, grid, block, 0, st, kt, A);
+  }
+}
+template <typename T>
+static void launch_e4(const StepArgs<T> &A, int kb, int acc, bool adj, dim3 grid, dim3 block,
+                      hipStream_t st, const KTime *kt) {
+  switch (kb) {
+    case 1: launch_e4_kb<T, 1>(A, acc, adj, grid, block, st, kt); break;
+    case 2: launch_e4_kb<T, 2>(A, acc, adj, grid, block, st, kt); break;
+    case 4: launch_e4_kb<T, 4>(A, acc, adj, grid, block, st, kt); break;
+    case 8: launch_e4_kb<T, 8>(A, acc, adj, grid, block, st, kt); break;
+    default: launch_e4_kb<T, 16>(A, acc, adj, grid, block, st, kt);
+  }
+}
+
+// E update (order 2 or 4) or, with flush, the transform flush (either order)
 template <typename T>
 static void launch_e(const StepArgs<T> &A, int kb, int vx, int acc, bool adj, bool flush,
-                     dim3 grid, dim3 block, hipStream_t st, const KTime *kt = nullptr) {
+                     dim3 grid, dim3 block, hipStream_t st, const KTime *kt = nullptr,
+                     bool o4 = false) {
+  if (o4 && !flush) {
+    launch_e4<T>(A, kb, acc, adj, grid, block, st, kt);
+    return;
+  }
   switch (kb) {
     case 1: launch_e_kb<T, 1>(A, vx, acc, adj, flush, grid, block, st, kt); break;
     case 2: launch_e_kb<T, 2>(A, vx, acc, adj, flush, grid, block, st, kt); break;
@@ -1860,9 +2150,10 @@ static void launch_step(const StepArgs<T> &A, int kb, int acc, bool adj, dim3 gr
 
 template <typename T>
 static void launch_h(const StepArgs<T> &A, int vx, dim3 grid, dim3 block, hipStream_t st,
-                     const KTime *kt = nullptr) {
+                     const KTime *kt = nullptr, bool o4 = false) {
   constexpr int VV = (int)(16 / sizeof(T));
-  if (vx == 1) go(k_update_h<T, 1>, grid, block, 0, st, kt, A);
+  if (o4) go(k_update_h4<T>, grid, block, 0, st, kt, A);
+  else if (vx == 1) go(k_update_h<T, 1>, grid, block, 0, st, kt, A);
   else go(k_update_h<T, VV>, grid, block, 0, st, kt, A);
 }
 
@@ -1887,8 +2178,9 @@ static void enqueue_step(Plan &p, Dev &d, const WS &w, void *vol, bool adj, hipS
     const Tiling th = tiling(p, true);
     Ah.nbx = th.nbx;
     Ah.nblocks = th.nblocks * p.ns;
-    launch_h<T>(Ah, p.vxh, dim3(Ah.nblocks), block, st, kh);
-    launch_e<T>(A, p.kb, p.vx, p.acc, adj, false, grid, block, st, ke);
+    const bool o4 = p.fd_order == 4;
+    launch_h<T>(Ah, p.vxh, dim3(Ah.nblocks), block, st, kh, o4);
+    launch_e<T>(A, p.kb, p.vx, p.acc, adj, false, grid, block, st, ke, o4);
   }
 }
 
@@ -2160,7 +2452,7 @@ void dev_adjoint(Plan &p, void *ws, size_t ws_bytes, const void *vol, const doub
   const double gscale = 1.0 / (p.src_scale * adj_scale);
   hipLaunchKernelGGL(k_grad_cells, dim3((p.nx + 127) / 128, p.ny, p.nz), dim3(128), 0, st, p.nx,
                      p.ny, p.nz, p.ns, p.PX, p.NY, p.field_elems(), w.gedge, d.cellfac,
-                     d.cellfac_v, gscale, grad, accumulate, p.vti_grad);
+                     d.cellfac_v, gscale, grad, accumulate, p.vti_grad, d.vratio, d.LA);
   HIP_CHECK(hipGetLastError());
   const int nrows = p.nr * p.ncomp, nn = (int)p.rn_c.size(), n = p.ns * nrows * p.nf();
   double2 *dst = E_adj ? reinterpret_cast<double2 *>(E_adj) : d.eadj;
@@ -2260,16 +2552,22 @@ static void adjoint_td_t(Plan &p, Dev &d, const WS &w, void *ws, char *scratch, 
     // reverse steps n0 + len - 1 .. n0
     for (int n = n0 + len - 1; n >= n0; --n) {
       const int t = n - n0;
-      hipLaunchKernelGGL((k_td_e<T>), grid, block, 0, st, A);
-      hipLaunchKernelGGL((k_td_h<T>), grid, block, 0, st, A, eseg + (t + 1) * eslice,
-                         eseg + t * eslice, (const double *)tdw);
+      if (p.fd_order == 4) {
+        hipLaunchKernelGGL((k_td_e<T, 4>), grid, block, 0, st, A);
+        hipLaunchKernelGGL((k_td_h<T, 4>), grid, block, 0, st, A, eseg + (t + 1) * eslice,
+                           eseg + t * eslice, (const double *)tdw);
+      } else {
+        hipLaunchKernelGGL((k_td_e<T, 2>), grid, block, 0, st, A);
+        hipLaunchKernelGGL((k_td_h<T, 2>), grid, block, 0, st, A, eseg + (t + 1) * eslice,
+                           eseg + t * eslice, (const double *)tdw);
+      }
       if (n >= 1) sens(n);
     }
     HIP_CHECK(hipGetLastError());
   }
   hipLaunchKernelGGL(k_grad_cells, dim3((p.nx + 127) / 128, p.ny, p.nz), dim3(128), 0, st, p.nx,
                      p.ny, p.nz, p.ns, p.PX, p.NY, p.field_elems(), gedge, d.cellfac, d.cellfac_v,
-                     gscale, grad, accumulate, p.vti_grad);
+                     gscale, grad, accumulate, p.vti_grad, d.vratio, d.LA);
   HIP_CHECK(hipGetLastError());
 }
 
@@ -2333,13 +2631,17 @@ double dev_autotune(Plan &p, void *ws, size_t ws_bytes, void *vol, size_t vol_by
   std::vector<Cand> cand;
   const int two[][2] = {{64, 4}, {64, 2}, {64, 1}, {32, 8}, {32, 4}, {16, 16},
                         {16, 8}, {16, 4}, {128, 2}, {256, 1}};
+  const bool o4 = p.fd_order == 4;      // order 4: two-kernel schedule, scalar threads
   for (int order : {0, 1}) {
     for (auto &c : two)
-      for (int v : {0, 1, 2})   // vector widths (E, H): (1, 1), (1, 4), (4, 4)
+      for (int v : {0, 1, 2}) {  // vector widths (E, H): (1, 1), (1, 4), (4, 4)
+        if (o4 && v) continue;
         cand.push_back({0, c[0], c[1], v == 2 ? 4 : 1, v ? 4 : 1, p.kz, order});
+      }
     const int fused[][2] = {{64, 4}, {32, 8}, {16, 16}, {16, 8}};
-    for (auto &c : fused)
-      for (int kz : {2, 4, 8}) cand.push_back({1, c[0], c[1], 1, 1, kz, order});
+    if (!o4)
+      for (auto &c : fused)
+        for (int kz : {2, 4, 8}) cand.push_back({1, c[0], c[1], 1, 1, kz, order});
   }
   const Cand save{p.sched, p.bx, p.by, p.vx, p.vxh, p.kz, p.order};
   const int save_xcd = p.xcd, save_sample = d.sample_every;

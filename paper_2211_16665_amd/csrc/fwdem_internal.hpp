@@ -37,6 +37,10 @@ struct Axis {
   std::vector<double> nodes;     // n+1
   std::vector<double> h;         // n   cell widths
   std::vector<double> hd;        // n+1 dual widths (half a cell at the ends)
+  // metric lengths dividing the differences: n at the half nodes, n+1 at the
+  // nodes (h and hd for order 2; the fourth-order pair applied to the
+  // coordinates for order 4)
+  std::vector<double> m, md;
   // CPML: 1/kappa, b, a at integer nodes (n+1) and half nodes (n)
   std::vector<double> kinv_n, b_n, a_n;
   std::vector<double> kinv_h, b_h, a_h;
@@ -111,6 +115,7 @@ struct Plan {
   int kz = 8;                            // planes per block of the fused schedule
   int order = 0;                         // tile numbering: 0 x fastest, 1 z fastest
   int vti_grad = 0;                      // 1: gradients as [d/d ln rho_h, d/d ln rho_v]
+  int fd_order = 2;                      // order of the staggered differences: 2 or 4
 
   // ---- device side (managed in device.hip) ----
   void *dev = nullptr;

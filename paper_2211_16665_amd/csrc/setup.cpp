@@ -76,6 +76,34 @@ static void check_axis(const double *v, int n, const char *name) {
   }
 }
 
+// Metric lengths of the differences along one axis.  Order 2: cell widths
+// and dual widths.  Order 4 (reading of the paper's high-order engine on a
+// stretched grid, Section 2): the staggered pair (9/8, -1/24) in the index
+// coordinate, so the metric is the same pair applied to the coordinates --
+// of the nodes for the half-node metric, of the cell centres for the node
+// metric -- with coordinates continued oddly across the two walls.
+static void axis_metrics(Axis &ax, int order) {
+  const int n = ax.n;
+  ax.m = ax.h;
+  ax.md = ax.hd;
+  if (order != 4) return;
+  const double c1 = 9.0 / 8.0, c2 = -1.0 / 24.0;
+  const double x0 = ax.nodes[0], xn = ax.nodes[n];
+  auto X = [&](int q) {                  // node coordinate, q in -1 .. n+1
+    if (q < 0) return 2.0 * x0 - ax.nodes[-q];
+    if (q > n) return 2.0 * xn - ax.nodes[2 * n - q];
+    return ax.nodes[q];
+  };
+  auto C = [&](int q) {                  // cell centre, q in -2 .. n+1
+    auto c = [&](int r) { return 0.5 * (ax.nodes[r] + ax.nodes[r + 1]); };
+    if (q < 0) return 2.0 * x0 - c(-1 - q);
+    if (q > n - 1) return 2.0 * xn - c(2 * n - 1 - q);
+    return c(q);
+  };
+  for (int r = 0; r < n; ++r) ax.m[r] = c1 * (X(r + 1) - X(r)) + c2 * (X(r + 2) - X(r - 1));
+  for (int i = 1; i < n; ++i) ax.md[i] = c1 * (C(i) - C(i - 1)) + c2 * (C(i + 1) - C(i - 2));
+}
+
 static void make_axis(Axis &ax, const double *v, int n) {
   ax.n = n;
   ax.nodes.assign(v, v + n + 1);
@@ -85,6 +113,7 @@ static void make_axis(Axis &ax, const double *v, int n) {
   ax.hd[0] = 0.5 * ax.h[0];
   ax.hd[n] = 0.5 * ax.h[n - 1];
   for (int i = 1; i < n; ++i) ax.hd[i] = 0.5 * (ax.h[i - 1] + ax.h[i]);
+  axis_metrics(ax, 2);
 }
 
 Plan *plan_create(const fwd_plan_desc *d) {
@@ -260,9 +289,11 @@ static bool interior_edge(const Plan &p, int c, int k, int j, int i) {
 
 static double dual_volume(const Plan &p, int c, int k, int j, int i) {
   const Axis &X = p.ax[0], &Y = p.ax[1], &Z = p.ax[2];
-  if (c == 0) return X.h[i] * Y.hd[j] * Z.hd[k];
-  if (c == 1) return X.hd[i] * Y.h[j] * Z.hd[k];
-  return X.hd[i] * Y.hd[j] * Z.h[k];
+  // in the metric lengths: the weights under which the discrete curl pair is
+  // adjoint (cell and dual widths for order 2)
+  if (c == 0) return X.m[i] * Y.md[j] * Z.md[k];
+  if (c == 1) return X.md[i] * Y.m[j] * Z.md[k];
+  return X.md[i] * Y.md[j] * Z.m[k];
 }
 
 void set_model(Plan &p, const double *rho, const double *rho_v) {
@@ -275,6 +306,7 @@ void set_model(Plan &p, const double *rho, const double *rho_v) {
     for (int64_t q = 0; q < nc; ++q)
       if (!(rho_v[q] > 0) || !std::isfinite(rho_v[q]))
         fail(FWD_ERR_INVALID_ARG, "rho_v must be finite and > 0");
+  for (int a = 0; a < 3; ++a) axis_metrics(p.ax[a], p.fd_order);
   const Axis &X = p.ax[0], &Y = p.ax[1], &Z = p.ax[2];
   const double old_dt = p.dt;
   const int old_nt = p.nt;
@@ -302,7 +334,9 @@ void set_model(Plan &p, const double *rho, const double *rho_v) {
         // taken along the faster (more resistive) direction of the cell
         const double v = std::sqrt(2.0 * p.omega0 / (kMu0 * std::min(p.sigma[q], p.sigma_v[q])));
         vmax = std::max(vmax, v);
-        const double inv = std::sqrt(1.0 / (X.h[i] * X.h[i]) + 1.0 / (Y.h[j] * Y.h[j]) +
+        // order 4: the largest symbol of the difference grows by 9/8 + 1/24
+        const double inv = (p.fd_order == 4 ? 7.0 / 6.0 : 1.0) *
+                           std::sqrt(1.0 / (X.h[i] * X.h[i]) + 1.0 / (Y.h[j] * Y.h[j]) +
                                      1.0 / (Z.h[k] * Z.h[k]));
         bound = std::min(bound, 1.0 / (v * inv));
       }
@@ -721,6 +755,17 @@ void get_table(const Plan &p, int which, double *out, size_t n) {
           for (int j = 0; j < p.NY; ++j)
             for (int i = 0; i < p.NX; ++i)
               out[c * cells + ((size_t)k * p.NY + j) * p.NX + i] = p.sig_e[c][p.lin(k, j, i)];
+      break;
+    }
+    case FWD_TAB_METRIC_X:
+    case FWD_TAB_METRIC_Y:
+    case FWD_TAB_METRIC_Z: {
+      const Axis &ax = p.ax[which - FWD_TAB_METRIC_X];
+      const size_t w = ax.n + 1;
+      need(2 * w);
+      std::fill(out, out + 2 * w, 0.0);
+      std::copy(ax.m.begin(), ax.m.end(), out);
+      std::copy(ax.md.begin(), ax.md.end(), out + w);
       break;
     }
     default:

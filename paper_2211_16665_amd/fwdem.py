@@ -29,11 +29,12 @@ FWD_F32, FWD_F64 = 0, 1
 FWD_ACC_F64, FWD_ACC_KAHAN, FWD_ACC_F32 = 0, 1, 2
 FWD_MODE_FORWARD, FWD_MODE_ADJOINT = 0, 1
 (FWD_TAB_WAVELET, FWD_TAB_NORM, FWD_TAB_OMEGA, FWD_TAB_CPML_X, FWD_TAB_CPML_Y,
- FWD_TAB_CPML_Z, FWD_TAB_BASIS, FWD_TAB_EDGE_SIGMA) = range(8)
+ FWD_TAB_CPML_Z, FWD_TAB_BASIS, FWD_TAB_EDGE_SIGMA, FWD_TAB_METRIC_X, FWD_TAB_METRIC_Y,
+ FWD_TAB_METRIC_Z) = range(11)
 (FWD_OPT_GRAPH_STEPS, FWD_OPT_BLOCK_X, FWD_OPT_BLOCK_Y, FWD_OPT_XCD_REMAP,
  FWD_OPT_SAMPLE_EVERY, FWD_OPT_STRICT_CFL, FWD_OPT_DFT_BLOCK, FWD_OPT_VECTOR,
  FWD_OPT_SCHEDULE, FWD_OPT_ZCHUNK, FWD_OPT_TILE_ORDER, FWD_OPT_VECTOR_H,
- FWD_OPT_VTI_GRADIENT) = range(13)
+ FWD_OPT_VTI_GRADIENT, FWD_OPT_FD_ORDER) = range(14)
 
 ACC_MODES = {"f64": FWD_ACC_F64, "kahan": FWD_ACC_KAHAN, "f32": FWD_ACC_F32}
 DTYPES = {"f32": FWD_F32, "f64": FWD_F64}
@@ -160,7 +161,7 @@ class Plan:
     def __init__(self, x, y, z, freqs, src_pos, src_mom, rec_pos, rec_comp=(0, 1), npml=8,
                  f0=1.0, field_dtype="f32", acc_mode="f64", rho_air_cap=1e4, cfl=0.95,
                  dt=0.0, nt=0, cpml_order=0.0, cpml_R=0.0, cpml_kappa_max=0.0,
-                 cpml_alpha_max=0.0, cpml_vref=0.0):
+                 cpml_alpha_max=0.0, cpml_vref=0.0, fd_order=2):
         self.lib = load()
         self._keep = [np.ascontiguousarray(a, dtype=np.float64) for a in
                       (x, y, z, freqs, src_pos, src_mom, rec_pos)]
@@ -188,12 +189,14 @@ class Plan:
         self.ns, self.nr, self.ncomp, self.nf = d.nsrc, d.nrec, d.ncomp, d.nfreq
         self._ws = {}
         self._vol = None
+        if int(fd_order) != 2:
+            self.set_option(FWD_OPT_FD_ORDER, int(fd_order))
 
     @classmethod
     def from_workload(cls, w, field_dtype=None, acc_mode=None, **kw):
         args = dict(npml=w.npml, f0=w.f0, rho_air_cap=w.rho_air_cap, cfl=w.cfl, dt=w.dt,
                     nt=w.nt, field_dtype=field_dtype or w.field_dtype,
-                    acc_mode=acc_mode or w.acc_mode)
+                    acc_mode=acc_mode or w.acc_mode, fd_order=getattr(w, "fd_order", 2))
         for k in ("cpml_order", "cpml_R", "cpml_kappa_max", "cpml_alpha_max", "cpml_vref"):
             if hasattr(w, k):
                 args[k] = getattr(w, k)

@@ -91,7 +91,9 @@ def test_errors_before_any_device_call(lib):
                                   lambda: tiny(seed=3, stretch=1.3, contrast=2.0),
                                   lambda: with_vti(tiny(seed=4, stretch=1.3, contrast=1.0),
                                                    ratio=5.0, seed=4, rho_min=0.0),
-                                  lambda: with_vti(c2_marine1d(), ratio=2.0)])
+                                  lambda: with_vti(c2_marine1d(), ratio=2.0),
+                                  lambda: tiny(seed=5, stretch=1.3, contrast=2.0).replace(fd_order=4),
+                                  lambda: c2_marine1d().replace(fd_order=4)])
 def test_setup_matches_oracle(lib, make):
     w = make()
     p = _plan(w)
@@ -118,6 +120,11 @@ def test_setup_matches_oracle(lib, make):
         assert np.allclose(t[4, :n], bh, rtol=1e-12, atol=1e-300)
         assert np.allclose(t[2], an, rtol=1e-12, atol=1e-300)
         assert np.allclose(t[5, :n], ah, rtol=1e-12, atol=1e-300)
+    for ax, n, mh, mn in ((fw.FWD_TAB_METRIC_X, s.nx, s.mx, s.mdx),
+                          (fw.FWD_TAB_METRIC_Y, s.ny, s.my, s.mdy),
+                          (fw.FWD_TAB_METRIC_Z, s.nz, s.mz, s.mdz)):
+        t = p.table(ax, 2 * (n + 1)).reshape(2, n + 1)
+        assert np.allclose(t[0, :n], mh, rtol=1e-13) and np.allclose(t[1], mn, rtol=1e-13)
     if s.nx * s.ny * s.nz < 2e6:
         es = p.table(fw.FWD_TAB_EDGE_SIGMA, 3 * (s.nx + 1) * (s.ny + 1) * (s.nz + 1))
         es = es.reshape(3, s.nz + 1, s.ny + 1, s.nx + 1)
@@ -172,3 +179,25 @@ def test_paper_basis_demo_cg_iterations(lib):
         bo = basis_pinv(B, pr["gamma"])
         b = p.table(fw.FWD_TAB_BASIS, 6 * pr["nt"]).reshape(6, pr["nt"])
         assert np.abs(b - bo).max() < 1e-6 * np.abs(bo).max()
+
+
+def test_order4_option_rules(lib):
+    """Host-only: order 4 forces the two-kernel schedule with scalar threads,
+    refuses the others, and drops the model (tables depend on the order)."""
+    w = tiny(seed=1)
+    p = _plan(w)
+    p.set_option(fw.FWD_OPT_SCHEDULE, 1)
+    p.set_option(fw.FWD_OPT_VECTOR, 4)
+    p.set_model(w.rho)
+    dt2 = p.info.dt
+    p.set_option(fw.FWD_OPT_FD_ORDER, 4)
+    assert p.get_option(fw.FWD_OPT_SCHEDULE) == 0 and p.get_option(fw.FWD_OPT_VECTOR) == 1
+    for key, v in ((fw.FWD_OPT_SCHEDULE, 1), (fw.FWD_OPT_VECTOR, 4), (fw.FWD_OPT_VECTOR_H, 4),
+                   (fw.FWD_OPT_FD_ORDER, 3)):
+        with pytest.raises(fw.FwdError):
+            p.set_option(key, v)
+    with pytest.raises(fw.FwdError) as e:
+        p.table(fw.FWD_TAB_WAVELET, 10)
+    assert e.value.status == 8
+    p.set_model(w.rho)
+    assert np.isclose(p.info.dt, dt2 * 6.0 / 7.0, rtol=1e-12)
