@@ -19,7 +19,8 @@ batched_vs_plain: gradient time of the 16-source batched workload on a
 window, one batched plan against one single-source plan per source.
 adjoint_td: the time-domain adjoint gradient of the same step (after the
 timed region) against the basis-function one.  vti: the same step on a VTI
-version of the model, with the split gradient.
+version of the model, with the split gradient.  order4: the same step with
+fourth-order differences.
 """
 from __future__ import annotations
 
@@ -220,6 +221,56 @@ def vti_study(plan, w_true, rho0, iso_s):
             "max_abs_grad_h": g[0], "max_abs_grad_v": g[1]}
 
 
+def order4_study(w_true, rho0, order2_s, tsize, accsize):
+    """The same gradient step with fourth-order differences (a plan of its
+    own: the order changes dt, nt and the tables): time against the
+    second-order step, and the order-4 kernels against the same algorithmic
+    bytes (each field value is still read and written once per step)."""
+    import torch
+    from paper_2211_16665_amd import fwdem as fw
+    w4 = w_true.replace(fd_order=4)
+    plan = fw.Plan.from_workload(w4, field_dtype="f32", acc_mode="f64")
+    plan.set_model(w4.rho)
+    d_obs = plan.forward()
+    vol = plan.volume_buffer()
+    plan.autotune(fw.FWD_MODE_FORWARD, vol=vol, steps=16)
+    plan.set_option(fw.FWD_OPT_SAMPLE_EVERY, 2048)
+    grad = torch.zeros(plan.shape, dtype=torch.float64, device="cuda")
+    ks = []
+
+    def step():
+        plan.set_model(rho0)
+        plan.basis_build(gamma_rel=1e-12)
+        E, _ = plan.forward(vol=vol, want_volume=True)
+        ks.append(plan.kernel_stats())
+        plan.adjoint(vol, d_obs - E, grad=grad)
+
+    step()
+    ks.clear()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    step()
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    nz, ny, nx = plan.shape
+    kb = int(plan.get_option(fw.FWD_OPT_DFT_BLOCK))
+    bytes_e, _ = algorithmic_bytes_e_forward(nx, ny, nz, w_true.npml, len(w_true.freqs),
+                                             tsize, accsize, kb)
+    bytes_h = algorithmic_bytes_h(nx, ny, nz, w_true.npml, tsize)
+    (h_ms, e_ms), n = ks[0]
+    nt = plan.info.nt
+    out = {"gradient_s": t, "order2_gradient_s": order2_s, "nt": nt, "dt": plan.info.dt,
+           "mcell_per_s": 2.0 * nx * ny * nz * nt / t / 1e6,
+           "tiling": {k.lower(): int(plan.get_option(getattr(fw, "FWD_OPT_" + k)))
+                      for k in ("BLOCK_X", "BLOCK_Y", "XCD_REMAP", "TILE_ORDER")},
+           "update_e_ms": e_ms, "update_h_ms": h_ms, "samples": n,
+           "update_e_algorithmic_gbs": bytes_e / (e_ms * 1e-3) / 1e9,
+           "update_h_algorithmic_gbs": bytes_h / (h_ms * 1e-3) / 1e9}
+    del plan, vol, grad
+    torch.cuda.empty_cache()
+    return out
+
+
 def adjoint_td_study(plan, resid, grad_basis, basis_s, npml, segment=500):
     """The time-domain adjoint (Appendix) on the bench workload: gradient time
     (forward with checkpoints, replay, reverse sweep) against the
@@ -285,6 +336,10 @@ def main():
                     help="skip the time-domain adjoint study")
     ap.add_argument("--no-vti", action="store_true",
                     help="skip the VTI gradient timing")
+    ap.add_argument("--fd-order", type=int, default=2, choices=(2, 4),
+                    help="order of the staggered differences of the timed step")
+    ap.add_argument("--no-order4", action="store_true",
+                    help="skip the fourth-order gradient timing")
     ap.add_argument("--tiling", default="",
                     help="fixed tiling instead of autotuning: block_x,block_y,xcd_remap,vector")
     ap.add_argument("--profile-steps", type=int, default=0,
@@ -303,7 +358,7 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
     torch.cuda.set_device(0)
-    w_true = c2_marine1d()
+    w_true = c2_marine1d().replace(fd_order=args.fd_order)
     if args.profile_steps > 0:
         profile_mode(args, w_true)
         return
@@ -376,7 +431,8 @@ def main():
         bytes_e = bytes_e + bytes_h - 2 * 3 * n_cells_nodes * tsize
     achieved = bytes_e / (e_ms * 1e-3) / 1e9
     tiling = ",".join(str(tuned[k.lower()]) for k in TILING_KEYS)
-    kernel_tag = f"k_step<float,F64,fwd,{kb}>" if fused else f"k_update_e<float,F64,fwd,{kb}>"
+    kernel_tag = (f"k_step<float,F64,fwd,{kb}>" if fused else
+                  f"k_update_e{'4' if args.fd_order == 4 else ''}<float,F64,fwd,{kb}>")
     mt = measured_traffic(kernel_tag) if args.field_dtype == "f32" and args.acc == "f64" else None
     traffic, traffic_tiling = mt if mt else (None, None)
     kern = {name: {"fwd_ms": avg("fwd", k)[0], "adj_ms": avg("adj", k)[0]}
@@ -401,7 +457,8 @@ def main():
         "config": {"workload": "c2_marine1d gradient: 101x101x61 stretched grid (100 m core, "
                                "ratio 1.05), air/0.3 ohm-m water/1 ohm-m sediment/100 ohm-m "
                                "reservoir, 3 freqs 0.25-1.25 Hz, 1 x-dipole, 50 seabed receivers; "
-                               "forward + adjoint + gradient",
+                               "forward + adjoint + gradient"
+                               + (", fourth-order differences" if args.fd_order == 4 else ""),
                    "cells": ncells, "nt": nt, "dt": info.dt, "sources": plan.ns,
                    "field_dtype": args.field_dtype, "accumulators": args.acc,
                    "basis_fit": info.basis_fit, "tuning": tuned},
@@ -416,6 +473,8 @@ def main():
                                              w_true.npml)
     if not args.no_vti:                 # changes the plan's model: after the studies above
         out["vti"] = vti_study(plan, w_true, rho0, elapsed / args.steps)
+    if not args.no_order4 and args.fd_order == 2:
+        out["order4"] = order4_study(w_true, rho0, elapsed / args.steps, tsize, accsize)
     if not args.no_batched:
         del vol, grad
         torch.cuda.empty_cache()
