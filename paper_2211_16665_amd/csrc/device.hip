@@ -60,6 +60,26 @@ namespace fwdem {
 // b, a at integer nodes (n+1) and at half nodes (n).
 enum { AX_IH = 0, AX_IHD, AX_KN, AX_BN, AX_AN, AX_KH, AX_BH, AX_AH, AX_TABLES };
 
+// Division of numerators 0 <= n < 2^31 by a runtime divisor 1 <= d < 2^31 as
+// a multiply-high (round-up method of Granlund and Montgomery, 1994): with
+// l = ceil(log2 d) and m = ceil(2^(32+l) / d) - 2^32 (< 2^32),
+//     n / d = (mulhi(n, m) + n) >> l,
+// exact because the rounding of m adds less than n / 2^(32+l) < 1 / (2d)
+// to n / d.  The block decode runs on the scalar unit, where a plain
+// integer division is a long instruction sequence.
+struct FDiv {
+  uint32_t d, m, l;
+};
+static inline FDiv fdiv_make(uint32_t d) {
+  uint32_t l = 0;
+  while ((1ull << l) < d) ++l;
+  const uint64_t num = 1ull << (32 + l);
+  return FDiv{d, (uint32_t)((num + d - 1) / d - (1ull << 32)), l};
+}
+__device__ __forceinline__ uint32_t fdiv(uint32_t n, const FDiv &f) {
+  return (__umulhi(n, f.m) + n) >> f.l;
+}
+
 template <typename T>
 struct StepArgs {
   int nx, ny, nz, npml, PX, NY, NZ, ns;
@@ -78,6 +98,11 @@ struct StepArgs {
   // each thread a vector of x nodes; fused: kz planes per block
   int nbx, nby, nbz, nblocks, xcd, kz;   // nblocks = tiles * ns (the grid)
   int order;          // tile numbering: 0 x fastest, 1 z fastest
+  FDiv dns, dnbx, dnby, dnbz;             // dividers of the block decode (set_grid)
+  // strides, precomputed on the host: plane = NY PX; CPML slabs sX (x), sY
+  // (y), sZ (z) per variable; per-source field stride 6F; the y and z slab
+  // offsets inside a source's psi block
+  int64_t plane, sX, sY, sZ, F6, oY, oZ;
   // volume transform / gradient
   int nf;
   const double2 *zE;  // [nt][nf] z^{n+1}
@@ -107,28 +132,28 @@ struct StepArgs {
 // or z fastest, t = (by * nbx + bx) * nbz + bz (order 1: the blocks of
 // consecutive planes of a column tile run side by side, so the plane
 // neighbours a stencil reads are still in L2).  Returns the tile index.
-__device__ __forceinline__ int tile_of(int nblocks, int xcd, int order, int ns, int nbx, int nby,
-                                       int nbz, int &bx, int &by, int &bz, int &s) {
-  int b = blockIdx.x;
-  if (xcd) {
-    const int q = nblocks >> 3, r = nblocks & 7;
-    const int x = b & 7, local = b >> 3;
+template <typename T>
+__device__ __forceinline__ int tile_of(const StepArgs<T> &A, int &bx, int &by, int &bz, int &s) {
+  uint32_t b = blockIdx.x;
+  if (A.xcd) {
+    const uint32_t q = (uint32_t)A.nblocks >> 3, r = (uint32_t)A.nblocks & 7u;
+    const uint32_t x = b & 7u, local = b >> 3;
     b = x * q + min(x, r) + local;
   }
-  s = b % ns;
-  const int tile = b / ns;
-  if (order) {
-    bz = tile % nbz;
-    const int t = tile / nbz;
-    bx = t % nbx;
-    by = t / nbx;
+  const uint32_t tile = fdiv(b, A.dns);
+  s = (int)(b - tile * (uint32_t)A.ns);
+  if (A.order) {
+    const uint32_t t = fdiv(tile, A.dnbz), u = fdiv(t, A.dnbx);
+    bz = (int)(tile - t * (uint32_t)A.nbz);
+    bx = (int)(t - u * (uint32_t)A.nbx);
+    by = (int)u;
   } else {
-    bx = tile % nbx;
-    const int t = tile / nbx;
-    by = t % nby;
-    bz = t / nby;
+    const uint32_t t = fdiv(tile, A.dnbx), u = fdiv(t, A.dnby);
+    bx = (int)(tile - t * (uint32_t)A.nbx);
+    by = (int)(t - u * (uint32_t)A.nby);
+    bz = (int)u;
   }
-  return tile;
+  return (int)tile;
 }
 
 // slab index of a CPML node: half nodes i+1/2 with i < npml or i >= n-npml;
@@ -157,19 +182,17 @@ struct Half {
 template <typename T>
 __device__ __forceinline__ Half<T> half_of(const StepArgs<T> &A, int par, int s) {
   Half<T> h;
-  T *f = A.fields + par * A.fbuf + (int64_t)s * 6 * A.F;
+  T *f = A.fields + (par ? A.fbuf : 0) + (int64_t)s * A.F6;
   h.ex = f;
   h.ey = f + A.F;
   h.ez = f + 2 * A.F;
   h.hx = f + 3 * A.F;
   h.hy = f + 4 * A.F;
   h.hz = f + 5 * A.F;
-  const int W = 2 * A.npml;
-  const int64_t sX = (int64_t)A.NZ * A.NY * W, sY = (int64_t)A.NZ * W * A.PX;
-  T *ps = A.psi + par * A.pbuf + (int64_t)s * A.psi_src;
+  T *ps = A.psi + (par ? A.pbuf : 0) + (int64_t)s * A.psi_src;
   h.psX = ps;
-  h.psY = ps + 4 * sX;
-  h.psZ = ps + 4 * sX + 4 * sY;
+  h.psY = ps + A.oY;
+  h.psZ = ps + A.oZ;
   return h;
 }
 
@@ -314,8 +337,8 @@ __device__ __forceinline__ void h_vec(const StepArgs<T> &A, const Half<T> &I, co
                                       int i0, int j, int k) {
   using V = Vec<T, VX>;
   const int PX = A.PX, NY = A.NY, NZ = A.NZ, npml = A.npml, W = 2 * npml;
-  const int64_t plane = (int64_t)NY * PX;
-  const int64_t sX = (int64_t)NZ * NY * W, sY = (int64_t)NZ * W * PX, sZ = (int64_t)W * NY * PX;
+  const int64_t plane = A.plane;
+  const int64_t sX = A.sX, sY = A.sY, sZ = A.sZ;
   const bool j_in = j < A.ny, k_in = k < A.nz;
   int ly = 0, lz = 0;
   const bool py = npml > 0 && pml_half(j, A.ny, npml, ly);
@@ -376,7 +399,7 @@ __device__ __forceinline__ void h_vec(const StepArgs<T> &A, const Half<T> &I, co
 template <typename T, int VX>
 __global__ void __launch_bounds__(256) k_update_h(StepArgs<T> A) {
   int bx, by, bz, s;
-  tile_of(A.nblocks, A.xcd, A.order, A.ns, A.nbx, A.nby, A.nbz, bx, by, bz, s);
+  tile_of(A, bx, by, bz, s);
   const int par = (A.step[0] + 1) & 1;   // this step reads half par
   const int i0 = (bx * blockDim.x + threadIdx.x) * VX;
   const int j = by * blockDim.y + threadIdx.y;
@@ -557,8 +580,8 @@ __device__ __forceinline__ void e_vec(const StepArgs<T> &A, int s, const Half<T>
                                       int n, int fl, int lo, int hi) {
   using V = Vec<T, VX>;
   const int PX = A.PX, NY = A.NY, NZ = A.NZ, npml = A.npml, W = 2 * npml;
-  const int64_t plane = (int64_t)NY * PX;
-  const int64_t sX = (int64_t)NZ * NY * W, sY = (int64_t)NZ * W * PX, sZ = (int64_t)W * NY * PX;
+  const int64_t plane = A.plane;
+  const int64_t sX = A.sX, sY = A.sY, sZ = A.sZ;
   const bool j_int = j >= 1 && j < A.ny, k_int = k >= 1 && k < A.nz;
   const bool j_in = j < A.ny, k_in = k < A.nz;
   int ly = 0, lz = 0;
@@ -651,7 +674,7 @@ template <typename T, int ACC, bool ADJ, int KB, int VX>
 __global__ void __launch_bounds__(256) k_update_e(StepArgs<T> A) {
   __shared__ int s_n;
   int bx, by, bz, s;
-  const int b = tile_of(A.nblocks, A.xcd, A.order, A.ns, A.nbx, A.nby, A.nbz, bx, by, bz, s);
+  const int b = tile_of(A, bx, by, bz, s);
   if (threadIdx.x == 0 && threadIdx.y == 0) {
     s_n = A.step[0] + 1;
     if (blockIdx.x == 0) A.step_w[0] = s_n;   // the step this launch completes
@@ -716,7 +739,7 @@ __device__ __forceinline__ T d4_he(const T *f, int64_t base, int64_t st, int i, 
 template <typename T>
 __global__ void __launch_bounds__(256) k_update_h4(StepArgs<T> A) {
   int bx, by, bz, s;
-  tile_of(A.nblocks, A.xcd, A.order, A.ns, A.nbx, A.nby, A.nbz, bx, by, bz, s);
+  tile_of(A, bx, by, bz, s);
   const int par = (A.step[0] + 1) & 1;   // this step reads half par
   const int i = bx * blockDim.x + threadIdx.x;
   const int j = by * blockDim.y + threadIdx.y;
@@ -724,8 +747,8 @@ __global__ void __launch_bounds__(256) k_update_h4(StepArgs<T> A) {
   if (i > A.nx || j > A.ny || k > A.nz) return;
   const Half<T> I = half_of(A, par, s), O = half_of(A, par ^ 1, s);
   const int PX = A.PX, NY = A.NY, NZ = A.NZ, npml = A.npml, W = 2 * npml;
-  const int64_t plane = (int64_t)NY * PX;
-  const int64_t sX = (int64_t)NZ * NY * W, sY = (int64_t)NZ * W * PX, sZ = (int64_t)W * NY * PX;
+  const int64_t plane = A.plane;
+  const int64_t sX = A.sX, sY = A.sY, sZ = A.sZ;
   const bool i_in = i < A.nx, j_in = j < A.ny, k_in = k < A.nz;
   int lx = 0, ly = 0, lz = 0;
   const bool py = npml > 0 && pml_half(j, A.ny, npml, ly);
@@ -766,7 +789,7 @@ template <typename T, int ACC, bool ADJ, int KB>
 __global__ void __launch_bounds__(256) k_update_e4(StepArgs<T> A) {
   __shared__ int s_n;
   int bx, by, bz, s;
-  const int b = tile_of(A.nblocks, A.xcd, A.order, A.ns, A.nbx, A.nby, A.nbz, bx, by, bz, s);
+  const int b = tile_of(A, bx, by, bz, s);
   if (threadIdx.x == 0 && threadIdx.y == 0) {
     s_n = A.step[0] + 1;
     if (blockIdx.x == 0) A.step_w[0] = s_n;   // the step this launch completes
@@ -788,8 +811,8 @@ __global__ void __launch_bounds__(256) k_update_e4(StepArgs<T> A) {
   const int par = n & 1;
   const Half<T> I = half_of(A, par, s), O = half_of(A, par ^ 1, s), P = half_of(A, 0, s);
   const int PX = A.PX, NY = A.NY, NZ = A.NZ, npml = A.npml, W = 2 * npml;
-  const int64_t plane = (int64_t)NY * PX;
-  const int64_t sX = (int64_t)NZ * NY * W, sY = (int64_t)NZ * W * PX, sZ = (int64_t)W * NY * PX;
+  const int64_t plane = A.plane;
+  const int64_t sX = A.sX, sY = A.sY, sZ = A.sZ;
   const bool i_int = i >= 1 && i < A.nx, j_int = j >= 1 && j < A.ny, k_int = k >= 1 && k < A.nz;
   const bool okx = i < A.nx && j_int && k_int;
   const bool oky = i_int && j < A.ny && k_int;
@@ -888,7 +911,7 @@ __global__ void __launch_bounds__(256) k_step(StepArgs<T> A) {
   T *sEx = reinterpret_cast<T *>(lds_raw), *sEy = sEx + SE, *sEz = sEy + SE;
   T *sHx = sEz + SE, *sHy = sHx + SH, *sHz = sHy + SH;
   int tbx, tby, tbz, s;
-  const int b = tile_of(A.nblocks, A.xcd, A.order, A.ns, A.nbx, A.nby, A.nbz, tbx, tby, tbz, s);
+  const int b = tile_of(A, tbx, tby, tbz, s);
   const int tx = threadIdx.x, ty = threadIdx.y;
   const int x0 = tbx * BX, y0 = tby * BY;
   const int i = x0 + tx, j = y0 + ty;
@@ -908,7 +931,7 @@ __global__ void __launch_bounds__(256) k_step(StepArgs<T> A) {
     hi = A.tl_off[tt + slot + 1];
   }
   const int npml = A.npml, W = 2 * npml, PX = A.PX, NY = A.NY, NZ = A.NZ;
-  const int64_t sX = (int64_t)NZ * NY * W, sY = (int64_t)NZ * W * PX, sZ = (int64_t)W * NY * PX;
+  const int64_t sX = A.sX, sY = A.sY, sZ = A.sZ;
   // column geometry of the own node and of the low-side halo nodes
   const bool act = i <= A.nx && j <= A.ny;
   const bool i_in = i < A.nx, j_in = j < A.ny;
@@ -1230,8 +1253,7 @@ __device__ __forceinline__ T td_ad_e(const StepArgs<T> &A, const Half<T> &Ad, in
   else ok = i >= 1 && i < A.nx && j >= 1 && j < A.ny && k >= 0 && k < A.nz;
   if (!ok) return T(0);
   const int W = 2 * A.npml;
-  const int64_t sX = (int64_t)A.NZ * A.NY * W, sY = (int64_t)A.NZ * W * A.PX,
-                sZ = (int64_t)W * A.NY * A.PX;
+  const int64_t sX = A.sX, sY = A.sY, sZ = A.sZ;
   const int64_t q = ((int64_t)k * A.NY + j) * A.PX + i;
   const T ae = (c == 0 ? Ad.ex : c == 1 ? Ad.ey : Ad.ez)[q];
   const T add = (d == 1 ? T(1) : T(-1)) * A.ce[c * A.F + q] * ae;
@@ -1263,8 +1285,7 @@ __device__ __forceinline__ T td_ad_h(const StepArgs<T> &A, const Half<T> &Ad, in
   else ok = i >= 0 && i < A.nx && j >= 0 && j < A.ny && k >= 0 && k <= A.nz;
   if (!ok) return T(0);
   const int W = 2 * A.npml;
-  const int64_t sX = (int64_t)A.NZ * A.NY * W, sY = (int64_t)A.NZ * W * A.PX,
-                sZ = (int64_t)W * A.NY * A.PX;
+  const int64_t sX = A.sX, sY = A.sY, sZ = A.sZ;
   const int64_t q = ((int64_t)k * A.NY + j) * A.PX + i;
   const T ah = (c == 0 ? Ad.hx : c == 1 ? Ad.hy : Ad.hz)[q];
   const T add = (d == 1 ? -A.dtmu : A.dtmu) * ah;
@@ -1311,13 +1332,12 @@ __device__ __forceinline__ T gather_e4(F at, int m, int n) {
 template <typename T, int ORD>
 __global__ void __launch_bounds__(256) k_td_e(StepArgs<T> A) {
   int bx, by, bz, s;
-  tile_of(A.nblocks, A.xcd, A.order, A.ns, A.nbx, A.nby, A.nbz, bx, by, bz, s);
+  tile_of(A, bx, by, bz, s);
   const int i = bx * blockDim.x + threadIdx.x, j = by * blockDim.y + threadIdx.y, k = bz;
   if (i > A.nx || j > A.ny || k > A.nz) return;
   const Half<T> Ad = half_of(A, 0, s);
   const int npml = A.npml, W = 2 * npml;
-  const int64_t sX = (int64_t)A.NZ * A.NY * W, sY = (int64_t)A.NZ * W * A.PX,
-                sZ = (int64_t)W * A.NY * A.PX;
+  const int64_t sX = A.sX, sY = A.sY, sZ = A.sZ;
   const int64_t q = ((int64_t)k * A.NY + j) * A.PX + i;
   const bool hx = j < A.ny && k < A.nz, hy = i < A.nx && k < A.nz, hz = i < A.nx && j < A.ny;
   int lx = 0, ly = 0, lz = 0;
@@ -1374,14 +1394,13 @@ template <typename T, int ORD>
 __global__ void __launch_bounds__(256) k_td_h(StepArgs<T> A, const T *Enew, const T *Eold,
                                               const double *tdw) {
   int bx, by, bz, s;
-  tile_of(A.nblocks, A.xcd, A.order, A.ns, A.nbx, A.nby, A.nbz, bx, by, bz, s);
+  tile_of(A, bx, by, bz, s);
   const int i = bx * blockDim.x + threadIdx.x, j = by * blockDim.y + threadIdx.y, k = bz;
   if (i > A.nx || j > A.ny || k > A.nz) return;
   const Half<T> Ad = half_of(A, 0, s);
   const int npml = A.npml, W = 2 * npml;
   const int64_t F = A.F;
-  const int64_t sX = (int64_t)A.NZ * A.NY * W, sY = (int64_t)A.NZ * W * A.PX,
-                sZ = (int64_t)W * A.NY * A.PX;
+  const int64_t sX = A.sX, sY = A.sY, sZ = A.sZ;
   const int64_t q = ((int64_t)k * A.NY + j) * A.PX + i;
   const bool i_int = i >= 1 && i < A.nx, j_int = j >= 1 && j < A.ny, k_int = k >= 1 && k < A.nz;
   const bool okx = i < A.nx && j_int && k_int, oky = i_int && j < A.ny && k_int,
@@ -1958,6 +1977,22 @@ static void build_lists(Plan &p, Dev &d) {
 
 // r: which step counter holds the last completed step (the launches read
 // counter r and write counter r ^ 1)
+// grid of a launch: tile counts, the block count (tiles * sources) and the
+// dividers of the block decode (A.ns must be set)
+template <typename T>
+static void set_grid(StepArgs<T> &A, int nbx, int nby, int nbz) {
+  A.nbx = nbx;
+  A.nby = nby;
+  A.nbz = nbz;
+  const int64_t nb = (int64_t)nbx * nby * nbz * A.ns;
+  if (nb >= ((int64_t)1 << 31)) fail(FWD_ERR_INVALID_ARG, "too many blocks for one launch");
+  A.nblocks = (int)nb;
+  A.dns = fdiv_make((uint32_t)A.ns);
+  A.dnbx = fdiv_make((uint32_t)nbx);
+  A.dnby = fdiv_make((uint32_t)nby);
+  A.dnbz = fdiv_make((uint32_t)nbz);
+}
+
 template <typename T>
 static StepArgs<T> make_args(Plan &p, Dev &d, const WS &w, void *vol, bool adj, int r = 0) {
   StepArgs<T> A{};
@@ -1978,14 +2013,21 @@ static StepArgs<T> make_args(Plan &p, Dev &d, const WS &w, void *vol, bool adj, 
   A.LA = d.LA;
   A.fbuf = (int64_t)p.ns * 6 * A.F;
   A.pbuf = (int64_t)p.ns * A.psi_src;
+  {
+    const int64_t W = 2 * p.npml;
+    A.plane = (int64_t)p.NY * p.PX;
+    A.sX = (int64_t)p.NZ * p.NY * W;
+    A.sY = (int64_t)p.NZ * W * p.PX;
+    A.sZ = W * p.NY * p.PX;
+    A.F6 = 6 * A.F;
+    A.oY = 4 * A.sX;
+    A.oZ = 4 * A.sX + 4 * A.sY;
+  }
   A.dtmu = (T)(p.dt / kMu0);
   A.step = w.step + r;
   A.step_w = w.step + (r ^ 1);
   const Tiling t = tiling(p);
-  A.nbx = t.nbx;
-  A.nby = t.nby;
-  A.nbz = t.nbz;
-  A.nblocks = t.nblocks * p.ns;
+  set_grid(A, t.nbx, t.nby, t.nbz);
   A.xcd = p.xcd;
   A.kz = p.kz;
   A.order = p.order;
@@ -2176,8 +2218,7 @@ static void enqueue_step(Plan &p, Dev &d, const WS &w, void *vol, bool adj, hipS
   } else {
     StepArgs<T> Ah = A;
     const Tiling th = tiling(p, true);
-    Ah.nbx = th.nbx;
-    Ah.nblocks = th.nblocks * p.ns;
+    set_grid(Ah, th.nbx, th.nby, th.nbz);
     const bool o4 = p.fd_order == 4;
     launch_h<T>(Ah, p.vxh, dim3(Ah.nblocks), block, st, kh, o4);
     launch_e<T>(A, p.kb, p.vx, p.acc, adj, false, grid, block, st, ke, o4);
@@ -2515,10 +2556,7 @@ static void adjoint_td_t(Plan &p, Dev &d, const WS &w, void *ws, char *scratch, 
   {
     // one node per thread on the plan's block shape
     const int nbx = (p.NX + p.bx - 1) / p.bx, nby = (p.NY + p.by - 1) / p.by;
-    A.nbx = nbx;
-    A.nby = nby;
-    A.nbz = p.NZ;
-    A.nblocks = nbx * nby * p.NZ * ns;
+    set_grid(A, nbx, nby, p.NZ);
   }
   A.fields = afld;
   A.fbuf = 0;
