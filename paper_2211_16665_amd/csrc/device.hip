@@ -456,74 +456,187 @@ __device__ __forceinline__ double2 acc_read(const void *base, int64_t idx) {
   }
 }
 
-// After the E update of component c at q .. q+VX-1 (old values e0 = sample
-// m-1, new values e1 = sample m, m = n+1): the transform over a block of KB
-// samples is added in one read-modify-write when the block closes
-// (m % KB == 0); samples with m % KB in 1..KB-2 wait in the history buffer,
-// the sample with m % KB == KB-1 is the old value of the closing step.
-// KB = 1 adds every sample as it comes.  Forward: volume transform
-// acc_k += sum E z_k^m (eq. dft).  Adjoint: gedge += sum_m u^m Re(sum_k
-// Q_k^m V_k), the gradient product of eq. gradsigmaij accumulated over time
-// (Q on the host).  Samples at or before *flushed were already added by a
-// flush.  Elements outside the component's lattice (ok bit clear) are
-// skipped.
+// Accumulator flavours as load / add / store, so that a closing step can
+// issue all its loads before any store (loads and stores share one in-order
+// completion counter: a load behind a store waits for the store).  The add
+// is the same arithmetic as acc_add.
+template <int ACC>
+struct Acc;
+template <>
+struct Acc<ACC_F64> {
+  using S = double2;
+  static __device__ __forceinline__ S load(const void *b, int64_t i) {
+    return reinterpret_cast<const double2 *>(b)[i];
+  }
+  static __device__ __forceinline__ void store(void *b, int64_t i, S v) {
+    reinterpret_cast<double2 *>(b)[i] = v;
+  }
+  static __device__ __forceinline__ S add(S v, double2 x) {
+    v.x += x.x;
+    v.y += x.y;
+    return v;
+  }
+  static __device__ __forceinline__ double2 value(S v) { return v; }
+};
+template <>
+struct Acc<ACC_KAHAN> {
+  using S = float4;
+  static __device__ __forceinline__ S load(const void *b, int64_t i) {
+    return reinterpret_cast<const float4 *>(b)[i];
+  }
+  static __device__ __forceinline__ void store(void *b, int64_t i, S v) {
+    reinterpret_cast<float4 *>(b)[i] = v;
+  }
+  static __device__ __forceinline__ S add(S v, double2 x) {
+    const float xr = (float)x.x, xi = (float)x.y;
+    float yr = xr - v.z, tr = v.x + yr;
+    v.z = (tr - v.x) - yr;
+    v.x = tr;
+    float yi = xi - v.w, ti = v.y + yi;
+    v.w = (ti - v.y) - yi;
+    v.y = ti;
+    return v;
+  }
+  static __device__ __forceinline__ double2 value(S v) {
+    return make_double2((double)v.x - (double)v.z, (double)v.y - (double)v.w);
+  }
+};
+template <>
+struct Acc<ACC_F32> {
+  using S = float2;
+  static __device__ __forceinline__ S load(const void *b, int64_t i) {
+    return reinterpret_cast<const float2 *>(b)[i];
+  }
+  static __device__ __forceinline__ void store(void *b, int64_t i, S v) {
+    reinterpret_cast<float2 *>(b)[i] = v;
+  }
+  static __device__ __forceinline__ S add(S v, double2 x) {
+    v.x += (float)x.x;
+    v.y += (float)x.y;
+    return v;
+  }
+  static __device__ __forceinline__ double2 value(S v) {
+    return make_double2((double)v.x, (double)v.y);
+  }
+};
+
+// After the E update of the three components at q .. q+VX-1 (old values
+// e0[c] = sample m-1, new values e1[c] = sample m, m = n+1): the transform
+// over a block of KB samples is added in one read-modify-write when the
+// block closes (m % KB == 0); samples with m % KB in 1..KB-2 wait in the
+// history buffer, the sample with m % KB == KB-1 is the old value of the
+// closing step.  KB = 1 adds every sample as it comes.  Forward: volume
+// transform acc_k += sum E z_k^m (eq. dft).  Adjoint: gedge += sum_m u^m
+// Re(sum_k Q_k^m V_k), the gradient product of eq. gradsigmaij accumulated
+// over time (Q on the host).  Samples at or before *flushed were already
+// added by a flush.  Elements outside a component's lattice (ok bit clear)
+// are skipped.  A closing step loads the whole history first, and per
+// frequency the twiddles once for the three components and the three
+// accumulators before their stores, so the memory round trips do not
+// serialise.
 template <typename T, int ACC, bool ADJ, int KB, int VX>
-__device__ __forceinline__ void post_e(const StepArgs<T> &A, int s, int c, int64_t q,
-                                       const Vec<T, VX> &e0, const Vec<T, VX> &e1, unsigned ok,
-                                       int n, int fl) {
+__device__ __forceinline__ void post_e(const StepArgs<T> &A, int s, int64_t q,
+                                       const Vec<T, VX> (&e0)[3], const Vec<T, VX> (&e1)[3],
+                                       const unsigned (&ok)[3], int n, int fl,
+                                       const double2 *__restrict__ tw) {
   if constexpr (ACC != ACC_NONE) {
-    if (!ok || n >= A.nt) return;   // steps past the run add nothing
+    if (!(ok[0] | ok[1] | ok[2]) || n >= A.nt) return;   // steps past the run add nothing
     const int nf = A.nf;
     const int m = n + 1;
     const int r = m & (KB - 1);
-    T *h = A.hist + (int64_t)s * A.hist_src + (int64_t)c * A.F + q;
+    const int64_t F = A.F, F3 = 3 * A.F;
+    T *h = A.hist + (int64_t)s * A.hist_src + q;
     if constexpr (KB > 1) {
       if (r != 0) {
-        if (r <= KB - 2) vstore(h + (int64_t)(r - 1) * 3 * A.F, e1);
+        if (r <= KB - 2) {
+#pragma unroll
+          for (int c = 0; c < 3; ++c)
+            if (ok[c]) vstore(h + c * F + (int64_t)(r - 1) * F3, e1[c]);
+        }
         return;
       }
     }
-    // the KB samples of the block: m-KB+1 .. m; zE / Q index = sample - 1
-    Vec<T, VX> hv[KB > 2 ? KB - 2 : 1];
+    // the KB samples of the block: m-KB+1 .. m; zE / Q index = sample - 1.
+    // History and accumulators span every node of the padded layout, so
+    // they are loaded without the lattice masks (which would split the
+    // loads into one masked round trip each); only stores are masked.
+    Vec<T, VX> hv[3][KB > 2 ? KB - 2 : 1];
 #pragma unroll
-    for (int t = 0; t < KB - 2; ++t) hv[t] = vload<VX>(h + (int64_t)t * 3 * A.F);
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int t = 0; t < KB - 2; ++t) hv[c][t] = vload<VX>(h + c * F + (int64_t)t * F3);
     const int first = m - KB + 1;
-    const int64_t base = ((int64_t)s * nf * 3 + c) * A.F + q;
+    const int64_t base = (int64_t)s * nf * F3 + q;   // + (kf * 3 + c) F + e
 #pragma unroll
     for (int e = 0; e < VX; ++e) {
-      if (!((ok >> e) & 1u)) continue;
+      bool on[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) on[c] = (ok[c] >> e) & 1u;
+      if (!(on[0] | on[1] | on[2])) continue;
       // the samples in the field type; those already added by a flush are
-      // zeroed with a select (the condition is the same for every thread),
-      // so the twiddle loads stay free to be issued together
-      T val[KB];
+      // zeroed with a select (the condition is the same for every thread)
+      T val[3][KB];
 #pragma unroll
-      for (int t = 0; t < KB - 2; ++t) val[t] = hv[t].v[e];
-      if constexpr (KB >= 2) val[KB - 2] = e0.v[e];
-      val[KB - 1] = e1.v[e];
+      for (int c = 0; c < 3; ++c) {
 #pragma unroll
-      for (int t = 0; t < KB; ++t) val[t] = first + t <= fl ? T(0) : val[t];
+        for (int t = 0; t < KB - 2; ++t) val[c][t] = hv[c][t].v[e];
+        if constexpr (KB >= 2) val[c][KB - 2] = e0[c].v[e];
+        val[c][KB - 1] = e1[c].v[e];
+#pragma unroll
+        for (int t = 0; t < KB; ++t) val[c][t] = first + t <= fl ? T(0) : val[c][t];
+      }
       if constexpr (!ADJ) {
+        using Ac = Acc<ACC>;
         for (int kf = 0; kf < nf; ++kf) {
-          double2 sum = make_double2(0.0, 0.0);
+          double2 z[KB];
 #pragma unroll
-          for (int t = 0; t < KB; ++t) {
-            const double2 z = A.zE[(int64_t)(first - 1 + t) * nf + kf];
-            sum.x = fma((double)val[t], z.x, sum.x);
-            sum.y = fma((double)val[t], z.y, sum.y);
+          for (int t = 0; t < KB; ++t) z[t] = tw[(int64_t)(first - 1 + t) * nf + kf];
+          typename Ac::S a[3];
+#pragma unroll
+          for (int c = 0; c < 3; ++c) a[c] = Ac::load(A.vol, base + (int64_t)(kf * 3 + c) * F + e);
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            if (!on[c]) continue;
+            double2 sum = make_double2(0.0, 0.0);
+#pragma unroll
+            for (int t = 0; t < KB; ++t) {
+              sum.x = fma((double)val[c][t], z[t].x, sum.x);
+              sum.y = fma((double)val[c][t], z[t].y, sum.y);
+            }
+            Ac::store(A.vol, base + (int64_t)(kf * 3 + c) * F + e, Ac::add(a[c], sum));
           }
-          acc_add<ACC>(A.vol, base + (int64_t)kf * 3 * A.F + e, sum);
         }
       } else {
-        double re = 0.0;
+        // per frequency Re(S V) with S = sum_t u^t Q^t, formed from the
+        // samples and Q while the forward transform V is loading
+        using Ac = Acc<ACC>;
+        double re[3] = {0.0, 0.0, 0.0};
         for (int kf = 0; kf < nf; ++kf) {
-          const double2 v = acc_read<ACC>(A.vol, base + (int64_t)kf * 3 * A.F + e);
+          double2 v[3];
 #pragma unroll
-          for (int t = 0; t < KB; ++t) {
-            const double2 Qt = A.Q[(int64_t)(first - 1 + t) * nf + kf];
-            re = fma((double)val[t], Qt.x * v.x - Qt.y * v.y, re);
+          for (int c = 0; c < 3; ++c)
+            v[c] = Ac::value(Ac::load(A.vol, base + (int64_t)(kf * 3 + c) * F + e));
+          double2 Qt[KB];
+#pragma unroll
+          for (int t = 0; t < KB; ++t) Qt[t] = tw[(int64_t)(first - 1 + t) * nf + kf];
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            double sx = 0.0, sy = 0.0;
+#pragma unroll
+            for (int t = 0; t < KB; ++t) {
+              sx = fma((double)val[c][t], Qt[t].x, sx);
+              sy = fma((double)val[c][t], Qt[t].y, sy);
+            }
+            re[c] = fma(sx, v[c].x, fma(-sy, v[c].y, re[c]));
           }
         }
-        A.gedge[((int64_t)s * 3 + c) * A.F + q + e] += re;
+        double *g = A.gedge + (int64_t)s * F3 + q + e;
+        double g0[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) g0[c] = g[c * F];
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+          if (on[c]) g[c * F] = g0[c] + re[c];
       }
     }
   }
@@ -577,7 +690,8 @@ __device__ __forceinline__ void record(const StepArgs<T> &A, int lo, int hi, int
 template <typename T, int ACC, bool ADJ, int KB, int VX>
 __device__ __forceinline__ void e_vec(const StepArgs<T> &A, int s, const Half<T> &I,
                                       const Half<T> &O, const Half<T> &P, int i0, int j, int k,
-                                      int n, int fl, int lo, int hi) {
+                                      int n, int fl, int lo, int hi,
+                                      const double2 *__restrict__ tw) {
   using V = Vec<T, VX>;
   const int PX = A.PX, NY = A.NY, NZ = A.NZ, npml = A.npml, W = 2 * npml;
   const int64_t plane = A.plane;
@@ -665,13 +779,16 @@ __device__ __forceinline__ void e_vec(const StepArgs<T> &A, int s, const Half<T>
     }
   }
   // ---- volume transform / gradient product ----
-  post_e<T, ACC, ADJ, KB, VX>(A, s, 0, q, e0x, e1x, okx, n, fl);
-  post_e<T, ACC, ADJ, KB, VX>(A, s, 1, q, e0y, e1y, oky, n, fl);
-  post_e<T, ACC, ADJ, KB, VX>(A, s, 2, q, e0z, e1z, okz, n, fl);
+  {
+    const Vec<T, VX> e0[3] = {e0x, e0y, e0z}, e1[3] = {e1x, e1y, e1z};
+    const unsigned ok[3] = {okx, oky, okz};
+    post_e<T, ACC, ADJ, KB, VX>(A, s, q, e0, e1, ok, n, fl, tw);
+  }
 }
 
 template <typename T, int ACC, bool ADJ, int KB, int VX>
-__global__ void __launch_bounds__(256) k_update_e(StepArgs<T> A) {
+__global__ void __launch_bounds__(256) k_update_e(StepArgs<T> A,
+                                                  const double2 *__restrict__ tw) {
   __shared__ int s_n;
   int bx, by, bz, s;
   const int b = tile_of(A, bx, by, bz, s);
@@ -696,7 +813,7 @@ __global__ void __launch_bounds__(256) k_update_e(StepArgs<T> A) {
     }
     const int par = n & 1;
     e_vec<T, ACC, ADJ, KB, VX>(A, s, half_of(A, par, s), half_of(A, par ^ 1, s), half_of(A, 0, s),
-                               i0, j, k, n, fl, lo, hi);
+                               i0, j, k, n, fl, lo, hi, tw);
   }
 }
 
@@ -786,7 +903,8 @@ __global__ void __launch_bounds__(256) k_update_h4(StepArgs<T> A) {
 }
 
 template <typename T, int ACC, bool ADJ, int KB>
-__global__ void __launch_bounds__(256) k_update_e4(StepArgs<T> A) {
+__global__ void __launch_bounds__(256) k_update_e4(StepArgs<T> A,
+                                                   const double2 *__restrict__ tw) {
   __shared__ int s_n;
   int bx, by, bz, s;
   const int b = tile_of(A, bx, by, bz, s);
@@ -869,9 +987,11 @@ __global__ void __launch_bounds__(256) k_update_e4(StepArgs<T> A) {
     if (oky) record(A, lo, hi, s, 1, 0, n, (double)e1y.v[0]);
     if (okz) record(A, lo, hi, s, 2, 0, n, (double)e1z.v[0]);
   }
-  post_e<T, ACC, ADJ, KB, 1>(A, s, 0, q, e0x, e1x, okx ? 1u : 0u, n, fl);
-  post_e<T, ACC, ADJ, KB, 1>(A, s, 1, q, e0y, e1y, oky ? 1u : 0u, n, fl);
-  post_e<T, ACC, ADJ, KB, 1>(A, s, 2, q, e0z, e1z, okz ? 1u : 0u, n, fl);
+  {
+    const Vec<T, 1> e0[3] = {e0x, e0y, e0z}, e1[3] = {e1x, e1y, e1z};
+    const unsigned ok[3] = {okx ? 1u : 0u, oky ? 1u : 0u, okz ? 1u : 0u};
+    post_e<T, ACC, ADJ, KB, 1>(A, s, q, e0, e1, ok, n, fl, tw);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1143,9 +1263,12 @@ __global__ void __launch_bounds__(256) k_step(StepArgs<T> A) {
           if (oky) record(A, lo, hi, s, 1, sub, n, (double)eyn);
           if (okz) record(A, lo, hi, s, 2, sub, n, (double)ezn);
         }
-        post_e<T, ACC, ADJ, KB, 1>(A, s, 0, q, vec1(ex), vec1(exn), okx ? 1u : 0u, n, fl);
-        post_e<T, ACC, ADJ, KB, 1>(A, s, 1, q, vec1(ey), vec1(eyn), oky ? 1u : 0u, n, fl);
-        post_e<T, ACC, ADJ, KB, 1>(A, s, 2, q, vec1(ez), vec1(ezn), okz ? 1u : 0u, n, fl);
+        {
+          const Vec<T, 1> e0[3] = {vec1(ex), vec1(ey), vec1(ez)};
+          const Vec<T, 1> e1[3] = {vec1(exn), vec1(eyn), vec1(ezn)};
+          const unsigned ok[3] = {okx ? 1u : 0u, oky ? 1u : 0u, okz ? 1u : 0u};
+          post_e<T, ACC, ADJ, KB, 1>(A, s, q, e0, e1, ok, n, fl, ADJ ? A.Q : A.zE);
+        }
       }
       // ---- carry to the next plane ----
       hxm = hxn;
@@ -2065,12 +2188,12 @@ struct KTime {
   hipEvent_t start, stop;
 };
 
-template <typename F, typename A_>
+template <typename F, typename... Args>
 static void go(F kernel, dim3 grid, dim3 block, size_t lds, hipStream_t st, const KTime *kt,
-               const A_ &a) {
+               Args... args) {
   if (kt) hipExtLaunchKernelGGL(kernel, grid, block, (std::uint32_t)lds, st, kt->start, kt->stop,
-                                0u, a);
-  else hipLaunchKernelGGL(kernel, grid, block, lds, st, a);
+                                0u, args...);
+  else hipLaunchKernelGGL(kernel, grid, block, lds, st, args...);
 }
 
 template <typename T, int KB, int VX>
@@ -2079,10 +2202,10 @@ static void launch_e_vx(const StepArgs<T> &A, int acc, bool adj, bool flush, dim
 #define FWD_LAUNCH(ACCV, ADJV)                                                                 \
   do {                                                                                         \
     if (flush) go(k_flush<T, ACCV, ADJV, KB>, grid, block, 0, st, kt, A);                      \
-    else go(k_update_e<T, ACCV, ADJV, KB, VX>, grid, block, 0, st, kt, A);                     \
+    else go(k_update_e<T, ACCV, ADJV, KB, VX>, grid, block, 0, st, kt, A, ADJV ? A.Q : A.zE);  \
   } while (0)
   if (!A.vol) {
-    if (!flush) go(k_update_e<T, ACC_NONE, false, 1, VX>, grid, block, 0, st, kt, A);
+    if (!flush) go(k_update_e<T, ACC_NONE, false, 1, VX>, grid, block, 0, st, kt, A, A.zE);
     return;
   }
   switch (acc) {
@@ -2109,21 +2232,21 @@ template <typename T, int KB>
 static void launch_e4_kb(const StepArgs<T> &A, int acc, bool adj, dim3 grid, dim3 block,
                          hipStream_t st, const KTime *kt) {
   if (!A.vol) {
-    go(k_update_e4<T, ACC_NONE, false, 1>, grid, block, 0, st, kt, A);
+    go(k_update_e4<T, ACC_NONE, false, 1>, grid, block, 0, st, kt, A, A.zE);
     return;
   }
   switch (acc) {
     case FWD_ACC_F64:
-      if (adj) go(k_update_e4<T, ACC_F64, true, KB>, grid, block, 0, st, kt, A);
-      else go(k_update_e4<T, ACC_F64, false, KB>, grid, block, 0, st, kt, A);
+      if (adj) go(k_update_e4<T, ACC_F64, true, KB>, grid, block, 0, st, kt, A, A.Q);
+      else go(k_update_e4<T, ACC_F64, false, KB>, grid, block, 0, st, kt, A, A.zE);
       break;
     case FWD_ACC_KAHAN:
-      if (adj) go(k_update_e4<T, ACC_KAHAN, true, KB>, grid, block, 0, st, kt, A);
-      else go(k_update_e4<T, ACC_KAHAN, false, KB>, grid, block, 0, st, kt, A);
+      if (adj) go(k_update_e4<T, ACC_KAHAN, true, KB>, grid, block, 0, st, kt, A, A.Q);
+      else go(k_update_e4<T, ACC_KAHAN, false, KB>, grid, block, 0, st, kt, A, A.zE);
       break;
     default:
-      if (adj) go(k_update_e4<T, ACC_F32, true, KB>, grid, block, 0, st, kt, A);
-      else go(k_update_e4<T, ACC_F32, false, KB>, grid, block, 0, st, kt, A);
+      if (adj) go(k_update_e4<T, ACC_F32, true, KB>, grid, block, 0, st, kt, A, A.Q);
+      else go(k_update_e4<T, ACC_F32, false, KB>, grid, block, 0, st, kt, A, A.zE);
   }
 }
 template <typename T>
