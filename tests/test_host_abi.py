@@ -63,6 +63,26 @@ def test_rejects_bad_descriptions(lib):
         pb.set_model(bad.rho)
 
 
+@pytest.mark.parametrize("kw,msg", [
+    (dict(rec_pos=np.zeros((0, 3))), "receiver"),
+    (dict(freqs=np.zeros(0)), "nfreq"),
+    (dict(freqs=np.array([-1.0])), "> 0"),
+    (dict(src_pos=np.zeros((0, 3)), src_mom=np.zeros((0, 3))), "source"),
+    (dict(src_mom=np.zeros((1, 3))), "zero"),
+    (dict(rec_pos=np.array([[1e6, 0.0, 0.0]])), "outside"),
+    (dict(rec_comp=()), "ncomp"),
+])
+def test_degenerate_inputs_are_refused(lib, kw, msg):
+    """Empty source, receiver, frequency or component sets, zero moments and
+    points outside the grid are refused with INVALID_ARG before any device
+    call (at plan creation or when the model's tables are built)."""
+    w = tiny(seed=0).replace(**kw)
+    with pytest.raises(fw.FwdError) as e:
+        p = _plan(w)
+        p.set_model(w.rho)
+    assert e.value.status == 1 and msg in str(e.value)
+
+
 def test_strict_cfl(lib):
     w = tiny(seed=1)
     s = make_setup(w)
