@@ -336,7 +336,7 @@ template <typename T, int VX>
 __device__ __forceinline__ void h_vec(const StepArgs<T> &A, const Half<T> &I, const Half<T> &O,
                                       int i0, int j, int k) {
   using V = Vec<T, VX>;
-  const int PX = A.PX, NY = A.NY, NZ = A.NZ, npml = A.npml, W = 2 * npml;
+  const int PX = A.PX, NY = A.NY, npml = A.npml, W = 2 * npml;
   const int64_t plane = A.plane;
   const int64_t sX = A.sX, sY = A.sY, sZ = A.sZ;
   const bool j_in = j < A.ny, k_in = k < A.nz;
@@ -693,7 +693,7 @@ __device__ __forceinline__ void e_vec(const StepArgs<T> &A, int s, const Half<T>
                                       int n, int fl, int lo, int hi,
                                       const double2 *__restrict__ tw) {
   using V = Vec<T, VX>;
-  const int PX = A.PX, NY = A.NY, NZ = A.NZ, npml = A.npml, W = 2 * npml;
+  const int PX = A.PX, NY = A.NY, npml = A.npml, W = 2 * npml;
   const int64_t plane = A.plane;
   const int64_t sX = A.sX, sY = A.sY, sZ = A.sZ;
   const bool j_int = j >= 1 && j < A.ny, k_int = k >= 1 && k < A.nz;
@@ -863,7 +863,7 @@ __global__ void __launch_bounds__(256) k_update_h4(StepArgs<T> A) {
   const int k = bz;
   if (i > A.nx || j > A.ny || k > A.nz) return;
   const Half<T> I = half_of(A, par, s), O = half_of(A, par ^ 1, s);
-  const int PX = A.PX, NY = A.NY, NZ = A.NZ, npml = A.npml, W = 2 * npml;
+  const int PX = A.PX, NY = A.NY, npml = A.npml, W = 2 * npml;
   const int64_t plane = A.plane;
   const int64_t sX = A.sX, sY = A.sY, sZ = A.sZ;
   const bool i_in = i < A.nx, j_in = j < A.ny, k_in = k < A.nz;
@@ -928,7 +928,7 @@ __global__ void __launch_bounds__(256) k_update_e4(StepArgs<T> A,
   }
   const int par = n & 1;
   const Half<T> I = half_of(A, par, s), O = half_of(A, par ^ 1, s), P = half_of(A, 0, s);
-  const int PX = A.PX, NY = A.NY, NZ = A.NZ, npml = A.npml, W = 2 * npml;
+  const int PX = A.PX, NY = A.NY, npml = A.npml, W = 2 * npml;
   const int64_t plane = A.plane;
   const int64_t sX = A.sX, sY = A.sY, sZ = A.sZ;
   const bool i_int = i >= 1 && i < A.nx, j_int = j >= 1 && j < A.ny, k_int = k >= 1 && k < A.nz;
@@ -1050,7 +1050,7 @@ __global__ void __launch_bounds__(256) k_step(StepArgs<T> A) {
     lo = A.tl_off[tt + slot];
     hi = A.tl_off[tt + slot + 1];
   }
-  const int npml = A.npml, W = 2 * npml, PX = A.PX, NY = A.NY, NZ = A.NZ;
+  const int npml = A.npml, W = 2 * npml, PX = A.PX, NY = A.NY;
   const int64_t sX = A.sX, sY = A.sY, sZ = A.sZ;
   // column geometry of the own node and of the low-side halo nodes
   const bool act = i <= A.nx && j <= A.ny;
