@@ -136,8 +136,10 @@ def batched_vs_plain(window=200):
     batched workload over a window of steps: all sources in one plan with
     graph replay, against the plain path of one single-source plan per source
     run one after the other with eager launches; FP32 fields, FP64
-    accumulators, default tiling.  Also the largest relative gradient
-    difference between the two (the same arithmetic per source: 0)."""
+    accumulators, default tiling.  Then the batched plan again with the
+    autotuned tiling, and its E update against its algorithmic bytes.  Also
+    the largest relative gradient difference between batched and plain (the
+    same arithmetic per source: 0)."""
     import torch
     from paper_2211_16665_amd import fwdem as fw
     from workloads import c4_batched, with_window
@@ -178,9 +180,36 @@ def batched_vs_plain(window=200):
     t_plain = time.perf_counter() - t0
     diff = float((g_b - g_p).abs().max() / g_p.abs().max())
     nz, ny, nx = p.shape
+    # the batched plan with the autotuned tiling, then its E update against
+    # its algorithmic bytes: per source as in the single-source model, dt/eps
+    # read once per launch for all sources
+    del plans
+    vol = p.volume_buffer()
+    p.autotune(fw.FWD_MODE_FORWARD, vol=vol, steps=16)
+    tuned = {k.lower(): int(p.get_option(getattr(fw, "FWD_OPT_" + k))) for k in TILING_KEYS}
+    gradient(p, vol, g_b)                        # warm-up with the tuned tiling
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gradient(p, vol, g_b)
+    torch.cuda.synchronize()
+    t_tuned = time.perf_counter() - t0
+    p.set_option(fw.FWD_OPT_SAMPLE_EVERY, 64)
+    p.forward(vol=vol, want_volume=True)
+    (h_ms, e_ms), n_samp = p.kernel_stats()
+    bytes_e, edges = algorithmic_bytes_e_forward(nx, ny, nz, w.npml, len(w.freqs), 4, 16,
+                                                 int(p.get_option(fw.FWD_OPT_DFT_BLOCK)))
+    bytes_b = w.ns * bytes_e - (w.ns - 1) * edges * 4
+    bytes_h = w.ns * algorithmic_bytes_h(nx, ny, nz, w.npml, 4)
+    del vol
     return {"workload": f"c4_batched window: {nx}x{ny}x{nz}, {w.ns} sources, {len(w.freqs)} freqs, "
                         f"{window} forward + {window} adjoint steps",
             "batched_s": t_batched, "plain_s": t_plain, "speedup": t_plain / t_batched,
+            "batched_tuned_s": t_tuned, "speedup_tuned": t_plain / t_tuned, "tuning": tuned,
+            "update_e_ms": e_ms, "update_h_ms": h_ms, "samples": n_samp,
+            "update_e_bytes_per_launch": bytes_b,
+            "update_e_algorithmic_gbs": bytes_b / (e_ms * 1e-3) / 1e9,
+            "update_e_frac_of_peak": bytes_b / (e_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "update_h_algorithmic_gbs": bytes_h / (h_ms * 1e-3) / 1e9,
             "batched_mcell_per_s": 2 * w.ns * nx * ny * nz * window / t_batched / 1e6,
             "max_rel_grad_diff": diff}
 
@@ -342,6 +371,8 @@ def main():
                     help="skip the fourth-order gradient timing")
     ap.add_argument("--tiling", default="",
                     help="fixed tiling instead of autotuning: block_x,block_y,xcd_remap,vector")
+    ap.add_argument("--profile-workload", default="marine", choices=("marine", "batched"),
+                    help="workload of the counter-collection mode")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="counter-collection mode: a 256 MiB device copy (calibration of the "
                          "byte counters) then this many forward and adjoint steps of the "
@@ -360,7 +391,8 @@ def main():
     torch.cuda.set_device(0)
     w_true = c2_marine1d().replace(fd_order=args.fd_order)
     if args.profile_steps > 0:
-        profile_mode(args, w_true)
+        from workloads import c4_batched
+        profile_mode(args, c4_batched() if args.profile_workload == "batched" else w_true)
         return
     # background model of the step: the same column without the reservoir
     rho0 = w_true.rho.copy()
