@@ -134,6 +134,59 @@ def test_inversion_iterates_match_the_oracle(method):
     assert err < 1e-8
 
 
+def test_vti_inversion_iterates_match_the_oracle():
+    """Two-parameter (ln rho_h, ln rho_v) inversion, two iterations on a
+    14x12x10 VTI problem (FP64 fields, basis-function adjoint with the split
+    gradient of Section 3.1): the library's driver on the GPU gradient takes
+    the oracle driver's steps on the oracle gradient."""
+    import oracle
+    from oracle import inversion as oinv
+    from oracle.discretization import make_setup
+    from workloads import with_vti
+    w = with_vti(tiny(seed=13, n=(14, 12, 10), npml=3, contrast=0.0, nr=16, nfreq=2, ns=2,
+                      rec_comp=(0, 1)), ratio=1.0, seed=13, rho_min=0.0)
+    rho_h = np.ones(w.shape)
+    rho_v = np.ones(w.shape)
+    rho_v[4:6, 5:8, 5:9] = 8.0                      # a vertically resistive block
+    s = make_setup(w.replace(rho=np.full(w.shape, RHO_MAX), rho_v=np.full(w.shape, RHO_MAX)))
+    w0 = w.replace(rho=np.ones(w.shape), rho_v=np.ones(w.shape), dt=s.dt, nt=s.nt)
+    w0.cpml_vref = s.vref
+    wt = w0.replace(rho=rho_h, rho_v=rho_v)
+    wt.cpml_vref = s.vref
+    d = oracle.forward(wt)["E_rec"]
+    W = 1.0 / (0.03 * np.abs(d) + 1e-3 * np.abs(d).max())
+    shape = (2,) + w.shape
+    active = np.zeros(shape, bool)
+    active[:, 3:-3, 3:-3, 3:-3] = True
+    n = int(active.sum())
+
+    def oracle_term(m):
+        wm = w0.replace(rho=np.exp(m[0]), rho_v=np.exp(m[1]))
+        wm.cpml_vref = w0.cpml_vref
+        f = oracle.forward(wm, want_volume=True)
+        g = oracle.adjoint_gradient(wm, f, W ** 2 * (d - f["E_rec"]))
+        return oracle.misfit(f["E_rec"], d, W), np.stack([g["grad_h"], g["grad_v"]])
+    kw = dict(max_iter=2, first_step=0.5, m_min=np.log(0.1), m_max=np.log(RHO_MAX))
+    say(f"VTI inversion parity, {n} active parameters")
+    plan = fw.Plan.from_workload(w0, field_dtype="f64")
+    obj = inv.Objective(inv.gpu_data_term(plan, d, W), np.zeros(shape), active=active,
+                        alpha=(1.0, 1.0, 1.0), beta=1e-3)
+    res = inv.lbfgs(obj, np.zeros(n), **kw)
+    ref = oinv.invert(oracle_term, np.zeros(shape), active, np.zeros(n), alpha=(1.0, 1.0, 1.0),
+                      beta=1e-3, **kw)
+    lib_phi = ["%.9g" % h["phi"] for h in res.history]
+    ora_phi = ["%.9g" % h["phi"] for h in ref["history"]]
+    say(f"  phi: library {lib_phi}, oracle {ora_phi}")
+    assert len(res.history) == len(ref["history"]) and res.evaluations == ref["evaluations"]
+    for h, o in zip(res.history, ref["history"]):
+        assert h["step"] == o["step"] and h["restart"] == o["restart"]
+        assert abs(h["phi"] - o["phi"]) <= 1e-9 * o["phi"]
+    assert ref["history"][-1]["phi"] < ref["history"][0]["phi"]
+    err = np.abs(res.m - ref["m"]).max()
+    say(f"  max |m_library - m_oracle| = {err:.2e}")
+    assert err < 1e-8
+
+
 def test_inversion_iteration_time_on_the_marine_grid():
     """Two l-BFGS iterations on the marine workload (FP32 fields): the
     starting model without the reservoir; time per gradient evaluation."""
