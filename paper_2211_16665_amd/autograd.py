@@ -19,6 +19,11 @@ adjoints:
 PyTorch hands the backward the conjugate Wirtinger gradient
 gE = dL/dRe E + i dL/dIm E; for the data misfit L = 1/2 ||W (d - E)||^2
 this is -W^2 (d - E), so the library's weighted residual is -gE.
+
+One plan may serve several forwards before their backwards (a loss summed
+over models): a backward whose model is no longer the plan's (the plan's
+model serial moved on) sets it again, and rebuilds the basis if the time
+step changed, before the adjoint.
 """
 from __future__ import annotations
 
@@ -32,14 +37,11 @@ class FictitiousForward(torch.autograd.Function):
     @staticmethod
     def forward(ctx, log_rho: torch.Tensor, plan: Plan, snapshot_every: int = 0,
                 gamma_rel: float = 1e-12, method: str = "basis"):
-        from .fwdem import FWD_OPT_VTI_GRADIENT
         rho = torch.exp(log_rho.detach().to(torch.float64)).cpu().numpy()
-        vti = rho.ndim == 4
-        if vti:
-            plan.set_model(rho[0], rho[1])
-        else:
-            plan.set_model(rho)
-        plan.set_option(FWD_OPT_VTI_GRADIENT, 1 if vti else 0)
+        _set_model(plan, rho)
+        ctx.serial = plan.model_serial
+        ctx.rho = rho
+        ctx.gamma_rel = gamma_rel
         ctx.plan = plan
         ctx.method = method
         ctx.snapshot_every = snapshot_every
@@ -79,12 +81,30 @@ class FictitiousForward(torch.autograd.Function):
     @staticmethod
     def backward(ctx, gE):
         plan: Plan = ctx.plan
+        if plan.model_serial != ctx.serial:
+            # the plan's model changed since this forward: restore ours
+            _set_model(plan, ctx.rho)
+            if ctx.method == "basis" and not plan.info.have_basis:
+                plan.basis_build(gamma_rel=ctx.gamma_rel)
+            ctx.serial = plan.model_serial
         resid = (-gE).to(torch.complex128).contiguous()
         if ctx.method == "time":
             grad = plan.adjoint_td(resid, segment=ctx.snapshot_every or 200)
         else:
             grad = plan.adjoint(ctx.vol, resid)
         return grad.to(dtype=ctx.in_dtype, device=ctx.in_device), None, None, None, None
+
+
+def _set_model(plan: Plan, rho: np.ndarray) -> None:
+    """rho [nz][ny][nx], or [2][nz][ny][nx] = (rho_h, rho_v) for VTI, whose
+    gradient is then split (FWD_OPT_VTI_GRADIENT)."""
+    from .fwdem import FWD_OPT_VTI_GRADIENT
+    vti = rho.ndim == 4
+    if vti:
+        plan.set_model(rho[0], rho[1])
+    else:
+        plan.set_model(rho)
+    plan.set_option(FWD_OPT_VTI_GRADIENT, 1 if vti else 0)
 
 
 def misfit(E: torch.Tensor, d: torch.Tensor, W=1.0) -> torch.Tensor:

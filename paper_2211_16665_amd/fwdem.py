@@ -189,6 +189,7 @@ class Plan:
         self.ns, self.nr, self.ncomp, self.nf = d.nsrc, d.nrec, d.ncomp, d.nfreq
         self._ws = {}
         self._vol = None
+        self.model_serial = 0
         if int(fd_order) != 2:
             self.set_option(FWD_OPT_FD_ORDER, int(fd_order))
 
@@ -218,7 +219,9 @@ class Plan:
     # ---- host-side calls --------------------------------------------------
     def set_model(self, rho, rho_v=None):
         """Cell resistivity [nz][ny][nx]; with ``rho_v`` a VTI model (rho is
-        then the horizontal resistivity)."""
+        then the horizontal resistivity).  ``model_serial`` counts the
+        calls (and order changes, which drop the model)."""
+        self.model_serial += 1
         r = np.ascontiguousarray(np.asarray(rho, dtype=np.float64))
         if r.shape != self.shape:
             raise ValueError(f"rho must have shape {self.shape}")
@@ -254,6 +257,8 @@ class Plan:
         return fit.value, it.value
 
     def set_option(self, key: int, value: float):
+        if key == FWD_OPT_FD_ORDER:
+            self.model_serial += 1
         check(self.lib.fwd_set_option(self.handle, key, float(value)))
 
     def get_option(self, key: int) -> float:

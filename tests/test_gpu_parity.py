@@ -267,6 +267,36 @@ def test_autograd_gradient_matches_finite_differences(method, snap):
         assert abs(fd - g[c]) < tol * abs(fd), (c, fd, g[c])
 
 
+@pytest.mark.parametrize("method,fixed_dt", [("basis", True), ("basis", False),
+                                             ("time", True)])
+def test_autograd_two_models_through_one_plan(method, fixed_dt):
+    """A loss over two models that share one plan: each backward runs on its
+    own model (the plan's model is restored when a later forward moved it, and
+    with a model-derived time step the basis is rebuilt), and the gradients
+    equal those of a fresh plan per model to rounding."""
+    from paper_2211_16665_amd.autograd import FictitiousForward, misfit
+    w0, d = _inverse_problem(seed=7, ns=1)
+    if not fixed_dt:
+        w0 = w0.replace(dt=0.0, nt=0)
+    say(f"autograd, two models through one plan, {method}, fixed dt {fixed_dt}")
+    rng = np.random.default_rng(70)
+    base = np.log(w0.rho)
+    # the second model is nowhere faster than the first (the CFL bound is per
+    # cell), so a fixed dt stays stable
+    models = [base, base - 0.3 * np.abs(rng.standard_normal(base.shape))]
+    dd = torch.from_numpy(d).cuda()
+    plan = fw.Plan.from_workload(w0, field_dtype="f64")
+    ms = [torch.tensor(m, device="cuda", requires_grad=True) for m in models]
+    loss = sum(misfit(FictitiousForward.apply(m, plan, 0, 1e-12, method), dd) for m in ms)
+    loss.backward()
+    for m, mt in zip(models, ms):
+        q = fw.Plan.from_workload(w0, field_dtype="f64")
+        mr = torch.tensor(m, device="cuda", requires_grad=True)
+        misfit(FictitiousForward.apply(mr, q, 0, 1e-12, method), dd).backward()
+        ref = mr.grad.cpu().numpy()
+        assert np.abs(mt.grad.cpu().numpy() - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
 # --------------------------------------------------------------------------
 # transform blocking (FWD_OPT_DFT_BLOCK): changes only the order of the sums
 # --------------------------------------------------------------------------
