@@ -10,6 +10,18 @@ matches the gradient formula eq. gradsigmaij and the finite-difference
 check).  The adjoint spectrum at each receiver is turned into a time series
 with the basis functions (eq. basis) and injected there.
 
+Magnetic data (receiver components 3-5, weighted by W2 in eq. phid) follow
+from the same reading: the magnetic residual is a magnetic current source in
+the M' slot.  The forward field is H = u_H / W_k (M' = M and H' = sqrt(-i
+w/2w0) H leave no factor), so its adjoint spectrum is conj(resid) alone
+against the electric sqrt(-i w/2w0) conj(resid) (the common 1/W_k is
+carried by the normalised forward field in the gradient).  M' acts at n dt
+while the basis functions are built on the injection times (n+1/2) dt of
+J': a series with sum_n b^n z^{n+1/2} = c has sum_n b^n z^n = c z^{-1/2},
+so the magnetic coefficients are conj(resid) z^{1/2}.  The node weights are
+w / (dual volume of the H node), the weights under which the discrete
+Faraday and Ampere rows form a symmetric system.
+
 Gradient (eq. gradsigmaij, isotropic case; cell volume scaling as the text
 after eq. adj0 allows): on every E edge
     d phi / d sigma_e = - Re sum_s sum_k (Omega_k / w'_k) conj(E_adj)_e E_e dV_e
@@ -25,23 +37,35 @@ from __future__ import annotations
 import numpy as np
 
 from .basis import basis_matrix, basis_pinv, gamma_from_rel, synthesize
-from .discretization import Setup, cell_gradient, dual_volumes, edge_sigma_transpose
+from .discretization import Setup, cell_gradient, dual_volumes, edge_sigma_transpose, h_volumes
 from .stepping import point_entries, run_stepping
 
 
 def misfit(E: np.ndarray, d: np.ndarray, W: np.ndarray | float = 1.0) -> float:
-    """phi_d = 1/2 sum |W (d - E)|^2 (eq. phid, electric data only)."""
+    """phi_d = 1/2 sum |W (d - E)|^2 (eq. phid, over whichever electric and
+    magnetic components the data hold)."""
     return 0.5 * float(np.sum(np.abs(W * (d - E)) ** 2))
+
+
+def source_factors(s: Setup, rec_comp) -> np.ndarray:
+    """Per component and frequency, the factor between conj(resid) and the
+    coefficients handed to the basis functions [ncomp][nf]: sqrt(-i w/2w0)
+    for E (the J' slot), z^{1/2} for H (the M' slot, acting at n dt)."""
+    magnetic = np.asarray(rec_comp) >= 3
+    fac_e = np.sqrt(-1j * s.omega / (2.0 * s.omega0))
+    fac_h = np.exp(0.5j * s.wprime * s.dt)
+    return np.where(magnetic[:, None], fac_h[None, :], fac_e[None, :])
 
 
 def adjoint_sources(s: Setup, rec_pos, rec_comp, resid_s: np.ndarray,
                     b: np.ndarray):
     """Injection entries and time series of the adjoint sources of one
     forward source.  resid_s [nr][ncomp][nf] is the weighted residual
-    W^2 (d - E)."""
-    spec = np.sqrt(-1j * s.omega / (2.0 * s.omega0)) * np.conj(resid_s)
+    W^2 (d - E).  Returns (entries, series [nr * ncomp][nt], coefficients
+    [nr][ncomp][nf] handed to the basis functions)."""
+    spec = source_factors(s, rec_comp)[None] * np.conj(resid_s)
     ts = synthesize(spec, b)                    # [nr][ncomp][nt]
-    vols = dual_volumes(s)
+    vols = dual_volumes(s) + h_volumes(s)
     inj = []
     ncomp = len(rec_comp)
     for r, pos in enumerate(rec_pos):

@@ -195,8 +195,12 @@ def adjoint_gradient_td(p, resid: np.ndarray, setup: Setup | None = None,
         norm = np.sqrt(-1j * s.omega / (2.0 * s.omega0)) / What
     else:
         norm = s.norm
+    # magnetic rows (components 3-5): H = norm_h sum_n H^{n+1/2} z^{n+1/2}
+    norm_h = norm / np.sqrt(-1j * s.omega / (2.0 * s.omega0))
     zm = np.exp(1j * np.outer(np.arange(nt + 1) * s.dt, s.wprime))   # z^m, m = 0..nt
-    names = ("Ex", "Ey", "Ez")
+    zh = np.exp(1j * np.outer((np.arange(nt) + 0.5) * s.dt, s.wprime))   # z^{n+1/2}
+    names = ("Ex", "Ey", "Ez", "Hx", "Hy", "Hz")
+    mag = np.array([c >= 3 for (c, _, _, _) in nodes], dtype=bool)
     ge = [np.zeros(s.sig_e[c].shape) for c in range(3)]
     for si in range(len(p.src_pos)):
         inj = source_injection(s, p.src_pos[si], p.src_mom[si])
@@ -206,12 +210,16 @@ def adjoint_gradient_td(p, resid: np.ndarray, setup: Setup | None = None,
         cnode = np.zeros((len(nodes), len(norm)), dtype=np.complex128)
         for r in range(len(p.rec_pos)):
             for ci in range(len(p.rec_comp)):
+                nrm = norm_h if p.rec_comp[ci] >= 3 else norm
                 for ni, w in interp[r][ci]:
-                    cnode[ni] += w * np.conj(resid[si, r, ci]) * norm
+                    cnode[ni] += w * np.conj(resid[si, r, ci]) * nrm
         ad = zero_state(o)
         for n in range(nt - 1, -1, -1):
             m = n + 1
-            gm = -np.real(cnode @ zm[m])
+            # d phi / d E^{n+1} at E nodes, d phi / d H^{n+1/2} at H nodes
+            # (H^{n+1/2} is produced by the H part of step n, which the
+            # transposed step undoes after its E part)
+            gm = np.where(mag, -np.real(cnode @ zh[n]), -np.real(cnode @ zm[m]))
             for ni, (c, k, j, i) in enumerate(nodes):
                 ad[names[c]][k, j, i] += gm[ni]
             for c in range(3):

@@ -317,6 +317,28 @@ def lattices(s: Setup):
     return ((xh, s.y, s.z), (s.x, yh, s.z), (s.x, s.y, zh))
 
 
+def h_lattices(s: Setup):
+    """Coordinates of the H_x, H_y, H_z lattices (component 3, 4, 5 of a
+    receiver): each H component sits on the node of its own axis and at the
+    cell centres of the other two."""
+    xh = 0.5 * (s.x[:-1] + s.x[1:])
+    yh = 0.5 * (s.y[:-1] + s.y[1:])
+    zh = 0.5 * (s.z[:-1] + s.z[1:])
+    return ((s.x, yh, zh), (xh, s.y, zh), (xh, yh, s.z))
+
+
+def h_volumes(s: Setup):
+    """Dual volume of every H node: the metric node length along its own
+    axis times the metric cell lengths of the other two.  Under these weights
+    and those of dual_volumes the Faraday and Ampere rows form a symmetric
+    system, so a magnetic adjoint source is spread with w / volume exactly
+    as an electric one."""
+    vx = s.mz[:, None, None] * s.my[None, :, None] * s.mdx[None, None, :]
+    vy = s.mz[:, None, None] * s.mdy[None, :, None] * s.mx[None, None, :]
+    vz = s.mdz[:, None, None] * s.my[None, :, None] * s.mx[None, None, :]
+    return vx, vy, vz
+
+
 def dual_volumes(s: Setup):
     """Dual volume of every E edge: edge length times dual face area, in
     the metric lengths of the differences (the weights under which the

@@ -18,13 +18,20 @@ Follows Section 2 of the paper:
     fictitious source J' = sqrt(-i omega / 2 omega0) J (correspondence
     below eq. mittet): E(omega_k) = u(omega_k) sqrt(-i omega_k/2omega0)/W_k
     with W_k = sum_n w^{n+1/2} z_k^{n+1/2} the transform of the injected
-    wavelet.
+    wavelet.  The same correspondence has H' = sqrt(-i omega/2omega0) H, so
+    the magnetic field of the same source is H(omega_k) = u_H(omega_k)/W_k,
+    u_H = sum_n H^{n+1/2} z_k^{n+1/2} (eq. dtft lists H' among the
+    transformed fields; magnetic data enter the misfit eq. phid);
+  * a magnetic current M' (the adjoint source of magnetic data) enters the
+    H update at n dt, the time of the curl E it sits beside.
+Receiver components: 0, 1, 2 = E_x, E_y, E_z; 3, 4, 5 = H_x, H_y, H_z.
 """
 from __future__ import annotations
 
 import numpy as np
 
-from .discretization import MU0, Setup, dual_volumes, lattices, make_setup, trilinear
+from .discretization import (MU0, Setup, dual_volumes, h_lattices, lattices, make_setup,
+                             trilinear)
 from .stencil import diff_e, diff_h
 
 
@@ -36,9 +43,9 @@ def _b(arr, axis, ndim=3):
 
 
 def point_entries(s: Setup, comp: int, point) -> list:
-    """Trilinear (k, j, i, weight) entries of a point on the lattice of E
-    component ``comp``."""
-    lat = lattices(s)[comp]
+    """Trilinear (k, j, i, weight) entries of a point on the lattice of
+    component ``comp`` (0-2: E, 3-5: H)."""
+    lat = lattices(s)[comp] if comp < 3 else h_lattices(s)[comp - 3]
     return [(k, j, i, w) for (k, j, i), w in trilinear(point, *lat)]
 
 
@@ -46,12 +53,14 @@ def run_stepping(s: Setup, inj: list, tfun: np.ndarray, rec_nodes: list,
                  want_volume: bool, nt: int | None = None):
     """Run the leapfrog for ``nt`` steps (default s.nt).
 
-    inj       list of (comp, k, j, i, weight, row): at step n the edge
-              receives J'^{n+1/2} = weight * tfun[row, n] (weight already
-              divided by the dual volume of the edge).
+    inj       list of (comp, k, j, i, weight, row): at step n an E edge
+              (comp 0-2) receives J'^{n+1/2} = weight * tfun[row, n], an H
+              node (comp 3-5) M'^n = weight * tfun[row, n] (weights already
+              divided by the dual volume of the edge or node).
     rec_nodes list of (comp, k, j, i) whose raw transforms are returned.
     Returns (rec_acc [len(rec_nodes), nf], volume [3][nf, ...] or None) with
-    the raw sums sum_n E^n z^n."""
+    the raw sums sum_n E^n z^n (E nodes) and sum_n H^{n+1/2} z^{n+1/2}
+    (H nodes)."""
     nt = s.nt if nt is None else nt
     nx, ny, nz = s.nx, s.ny, s.nz
     nf = len(s.freqs)
@@ -93,13 +102,18 @@ def run_stepping(s: Setup, inj: list, tfun: np.ndarray, rec_nodes: list,
     ce_full = (cx, cy, cz)
 
     zE = np.exp(1j * np.outer((np.arange(nt) + 1.0) * s.dt, s.wprime))   # z^{n+1}
+    zH = np.exp(1j * np.outer((np.arange(nt) + 0.5) * s.dt, s.wprime))   # z^{n+1/2}
+    H = (Hx, Hy, Hz)
     rec_acc = np.zeros((len(rec_nodes), nf), dtype=np.complex128)
     vol = None
     if want_volume:
         vol = [np.zeros((nf,) + a.shape, dtype=np.complex128) for a in E]
 
     for n in range(nt):
-        # H^{n+1/2} = H^{n-1/2} - dt/mu curl E^n
+        # H^{n+1/2} = H^{n-1/2} - dt/mu (curl E^n - M'^n)
+        for (c, k, j, i, w, row) in inj:
+            if c >= 3:
+                H[c - 3][k, j, i] += dtmu * w * tfun[row, n]
         dEz_dy = stretched(diff_e(Ez, 1, od) / hy, "Hx_y", kyh, byh, ayh, 1)
         dEy_dz = stretched(diff_e(Ey, 0, od) / hz, "Hx_z", kzh, bzh, azh, 0)
         Hx -= dtmu * (dEz_dy - dEy_dz)
@@ -109,6 +123,10 @@ def run_stepping(s: Setup, inj: list, tfun: np.ndarray, rec_nodes: list,
         dEy_dx = stretched(diff_e(Ey, 2, od) / hx, "Hz_x", kxh, bxh, axh, 2)
         dEx_dy = stretched(diff_e(Ex, 1, od) / hy, "Hz_y", kyh, byh, ayh, 1)
         Hz -= dtmu * (dEy_dx - dEx_dy)
+        # damped DFT of H^{n+1/2}
+        for r, (c, k, j, i) in enumerate(rec_nodes):
+            if c >= 3:
+                rec_acc[r] += H[c - 3][k, j, i] * zH[n]
 
         # E^{n+1} = E^n + dt/eps (curl H^{n+1/2} - J'^{n+1/2}); interior edges only
         dHz_dy = stretched(diff_h(Hz[1:-1], 1, od) / hdy, "Ex_y",
@@ -127,12 +145,14 @@ def run_stepping(s: Setup, inj: list, tfun: np.ndarray, rec_nodes: list,
                            kyn[1:-1], byn[1:-1], ayn[1:-1], 1)
         Ez[:, 1:-1, 1:-1] += czi * (dHy_dx - dHx_dy)
         for (c, k, j, i, w, row) in inj:
-            E[c][k, j, i] -= ce_full[c][k, j, i] * w * tfun[row, n]
+            if c < 3:
+                E[c][k, j, i] -= ce_full[c][k, j, i] * w * tfun[row, n]
 
         # damped DFT of E^{n+1}
         zn = zE[n]
         for r, (c, k, j, i) in enumerate(rec_nodes):
-            rec_acc[r] += E[c][k, j, i] * zn
+            if c < 3:
+                rec_acc[r] += E[c][k, j, i] * zn
         if vol is not None:
             for c in range(3):
                 vol[c] += zn[:, None, None, None] * E[c][None]
@@ -175,12 +195,13 @@ def receiver_nodes(s: Setup, rec_pos, rec_comp):
 
 def forward(p, want_volume: bool = False, setup: Setup | None = None,
             nt: int | None = None):
-    """Frequency-domain E at the receivers (and optionally in the volume)
-    for every source of problem ``p``: one leapfrog run per source.
+    """Frequency-domain fields at the receivers (and optionally E in the
+    volume) for every source of problem ``p``: one leapfrog run per source.
 
     Returns dict with
       setup  the Setup used
-      E_rec  complex [ns][nr][ncomp][nf]  (eq. freq field of the dipole)
+      E_rec  complex [ns][nr][ncomp][nf]  (eq. freq field of the dipole;
+             the components p.rec_comp, E or H)
       vol    per source, [3][nf, ...] normalised volume fields (if asked)."""
     s = setup if setup is not None else make_setup(p)
     nt = s.nt if nt is None else nt
@@ -195,6 +216,8 @@ def forward(p, want_volume: bool = False, setup: Setup | None = None,
         norm = np.sqrt(-1j * s.omega / (2.0 * s.omega0)) / What
     else:
         norm = s.norm
+    # H = H' / sqrt(-i omega / 2 omega0): the magnetic field needs 1 / W_k
+    norm_h = norm / np.sqrt(-1j * s.omega / (2.0 * s.omega0))
     E_rec = np.zeros((ns, len(p.rec_pos), ncomp, nf), dtype=np.complex128)
     vols = []
     for si in range(ns):
@@ -203,7 +226,7 @@ def forward(p, want_volume: bool = False, setup: Setup | None = None,
         for r in range(len(p.rec_pos)):
             for ci in range(ncomp):
                 val = sum(w * acc[ni] for ni, w in interp[r][ci])
-                E_rec[si, r, ci] = val * norm
+                E_rec[si, r, ci] = val * (norm if p.rec_comp[ci] < 3 else norm_h)
         if vol is not None:
             vols.append([v * norm[:, None, None, None] for v in vol])
     return {"setup": s, "E_rec": E_rec, "vol": vols if want_volume else None,

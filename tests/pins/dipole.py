@@ -9,6 +9,9 @@ sigma, Im k > 0.  For J = p delta(x) its solution is
 which written out is
     E_i = G/(sigma r^2) [ (x_i x_j / r^2)(3 - 3ikr - k^2 r^2)
                           + delta_ij (ikr - 1 + k^2 r^2) ] p_j.
+The magnetic field is H = curl (G p) = G'(r) (r_hat x p) with
+G' = (ik - 1/r) G; then curl E = (k^2 / sigma) H = i omega mu H, the
+Faraday row of eq. freq with M = 0.
 """
 from __future__ import annotations
 
@@ -49,3 +52,25 @@ def dipole_field_discrete_time(r_vec, p, sigma, omega, omega0, Omega, mu=MU0):
     k = np.where(np.imag(k) < 0, -k, k)
     wp = (1.0 + 1.0j) * np.sqrt(omega * omega0)
     return (wp / Omega) * dipole_field(r_vec, p, k, sigma)
+
+
+def magnetic_field(r_vec, p, k):
+    """H at offsets ``r_vec`` [..., 3] from an electric dipole of moment
+    ``p`` [3] with wavenumber ``k``: (ik - 1/r) G (r_hat x p)."""
+    r_vec = np.asarray(r_vec, dtype=np.float64)
+    p = np.asarray(p, dtype=np.float64)
+    r = np.linalg.norm(r_vec, axis=-1)
+    G = np.exp(1j * k * r) / (4.0 * np.pi * r)
+    dG = (1j * k - 1.0 / r) * G
+    return (dG / r)[..., None] * np.cross(r_vec, p)
+
+
+def magnetic_field_discrete_time(r_vec, p, sigma, omega0, Omega, mu=MU0):
+    """H of the stepped system at complex frequency Omega.  The Faraday row
+    of the stepped system gives H' = curl E' / (i Omega mu); with E' from
+    dipole_field_discrete_time and H = H' / sqrt(-i omega / 2 omega0) every
+    factor cancels: H is the closed form above at k^2 = Omega^2 mu sigma /
+    (2 omega0)."""
+    k = np.sqrt(Omega ** 2 * mu * sigma / (2.0 * omega0) + 0j)
+    k = np.where(np.imag(k) < 0, -k, k)
+    return magnetic_field(r_vec, p, k)

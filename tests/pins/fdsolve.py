@@ -147,9 +147,11 @@ def _metrics(nodes, order):
 def solve(x, y, z, rho, npml, f0, freq, dt, sources, receivers, rec_comp,
           vref, cpml_order=2.0, cpml_R=1e-6, kappa_max=1.0, alpha_max=0.0,
           rho_cap=1e8, rho_v=None, order=2):
-    """Frequency-domain E at ``receivers`` for each dipole in ``sources``
+    """Frequency-domain field at ``receivers`` for each dipole in ``sources``
     (list of (pos, moment)); returns complex [ns][nr][ncomp].  The field is
-    that of J (not J'): the right-hand side is sqrt(-i w/2w0) p w_l / V_l."""
+    that of J (not J'): the right-hand side is sqrt(-i w/2w0) p w_l / V_l.
+    Components 0-2 are E, 3-5 are H, taken from the Faraday row
+    H' = curl E' / (i Omega mu) and H = H' / sqrt(-i w/2w0)."""
     g = Grid(x, y, z)
     nx, ny, nz = g.nx, g.ny, g.nz
     hx, hy, hz = np.diff(x), np.diff(y), np.diff(z)
@@ -279,7 +281,7 @@ def solve(x, y, z, rho, npml, f0, freq, dt, sources, receivers, rec_comp,
 
     # lattices of the three E components and dual volumes
     xh, yh, zh = 0.5 * (x[1:] + x[:-1]), 0.5 * (y[1:] + y[:-1]), 0.5 * (z[1:] + z[:-1])
-    lat = [(xh, y, z), (x, yh, z), (x, y, zh)]
+    lat = [(xh, y, z), (x, yh, z), (x, y, zh), (x, yh, zh), (xh, y, zh), (xh, yh, z)]
     edge_len = [(hx, None), (hy, None), (hz, None)]
 
     def dualvol(c, k, j, i):
@@ -313,10 +315,16 @@ def solve(x, y, z, rho, npml, f0, freq, dt, sources, receivers, rec_comp,
             for (k, j, i, w) in weights(c, pos):
                 rhs[pos_of[int(g.e(c, k, j, i))]] += src_fac * mom[c] * w / dualvol(c, k, j, i)
         sol = lu.solve(rhs)
+        e_full = np.zeros(g.eoff[-1], dtype=np.complex128)
+        e_full[idx] = sol
+        h_full = (CE @ e_full) / (1j * Om * MU0) / src_fac
         for ri, rp in enumerate(receivers):
             for ci, c in enumerate(rec_comp):
                 val = 0j
                 for (k, j, i, w) in weights(c, rp):
+                    if c >= 3:
+                        val += w * h_full[int(g.h(c - 3, k, j, i))]
+                        continue
                     m = pos_of.get(int(g.e(c, k, j, i)))
                     if m is not None:
                         val += w * sol[m]
