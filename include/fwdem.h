@@ -79,7 +79,8 @@ typedef struct {
   const double *src_pos;          /* host [nsrc][3] dipole positions (m) */
   const double *src_mom;          /* host [nsrc][3] dipole moments (A m) */
   int nrec; const double *rec_pos;/* host [nrec][3] receiver positions (m) */
-  int ncomp; const int *rec_comp; /* recorded E components, each 0 (x), 1 (y) or 2 (z) */
+  int ncomp; const int *rec_comp; /* recorded components, distinct: 0, 1, 2 = E_x, E_y, E_z;
+                                     3, 4, 5 = H_x, H_y, H_z (magnetic data, eq. phid W2) */
   int field_dtype;                /* FWD_F32 or FWD_F64 */
   int acc_mode;                   /* FWD_ACC_* for the volume transform */
   double rho_air_cap;             /* resistivities above the cap are stepped at the cap (<= 0: 1e4) */
@@ -104,7 +105,7 @@ typedef struct {
 /* Tables readable by fwd_get_table (host copies; for tests and tools). */
 enum {
   FWD_TAB_WAVELET = 0,   /* [nt] w((n+1/2) dt) */
-  FWD_TAB_NORM = 1,      /* complex [nfreq]: sqrt(-i w / 2 w0) / W_k */
+  FWD_TAB_NORM = 1,      /* complex [nfreq]: sqrt(-i w / 2 w0) / W_k (E rows; H rows: 1 / W_k) */
   FWD_TAB_OMEGA = 2,     /* complex [nfreq]: Omega_k = (2/dt) sin(w'_k dt/2) */
   FWD_TAB_CPML_X = 3,    /* [6][nx+1]: kappa, b, a at integer nodes, then at half nodes (last unused) */
   FWD_TAB_CPML_Y = 4,
@@ -159,7 +160,11 @@ fwd_status fwd_volume_size(const fwd_plan *plan, size_t *bytes);
  *   vol_dev     NULL, or fwd_volume_size bytes: receives the raw volume
  *               transform (layout private; read it with fwd_volume_export)
  *   E_rec_dev   complex [nsrc][nrec][ncomp][nfreq]: E(omega_k) of J = p delta
- *               (eq. freq) at the receivers, trilinear interpolation
+ *               (eq. freq) at the receivers, trilinear interpolation; rows
+ *               of a magnetic component hold H(omega_k): the transform of
+ *               H^{n+1/2} with z^{n+1/2} (eq. dtft lists H'), scaled by
+ *               1 / W_k, since H' = sqrt(-i w/2w0) H (correspondence below
+ *               eq. mittet) cancels the factor the E rows carry
  * Errors: STATE (no model), INVALID_ARG (sizes), HIP, NONFINITE. */
 fwd_status fwd_forward(fwd_plan *plan, void *ws_dev, size_t ws_bytes,
                        void *vol_dev, size_t vol_bytes, double *E_rec_dev,
@@ -225,8 +230,12 @@ fwd_status fwd_basis_build(fwd_plan *plan, double gamma_rel, double gamma_abs,
  * The adjoint source at receiver r, component c is the time series
  * sum_k Re s_k b_k + Im s_k b_{k+nfreq} (eq. basis) of the spectrum
  * s_k = sqrt(-i omega_k / 2 omega0) conj(resid) (eq. adj2, electric
- * residual in the J' slot).  Errors: STATE (no model / no basis), HIP,
- * NONFINITE. */
+ * residual in the J' slot).  A magnetic residual (components 3-5) is a
+ * magnetic current in the M' slot (M' = M), added to H at n dt before the
+ * H update: its spectrum is s_k = conj(resid) z_k^{1/2}, because the basis
+ * functions reproduce spectra at the J' times (n+1/2) dt, and its node
+ * weights are w / (dual volume of the H node).  Errors: STATE (no model /
+ * no basis), HIP, NONFINITE. */
 fwd_status fwd_adjoint(fwd_plan *plan, void *ws_dev, size_t ws_bytes,
                        const void *vol_fwd_dev, const double *resid_dev,
                        double *grad_dev, int accumulate, double *E_adj_dev,
@@ -250,8 +259,9 @@ fwd_status fwd_adjoint(fwd_plan *plan, void *ws_dev, size_t ws_bytes,
  *   segment      steps between checkpoints (>= 1)
  *   resid_dev    complex [nsrc][nrec][ncomp][nfreq], W^2 (d - E)
  *   grad_dev     double [nz][ny][nx], added to if accumulate != 0
- * Errors: STATE (no model), INVALID_ARG (sizes, segment), HIP.  Costs about
- * three forward runs (forward, replay, reverse sweep). */
+ * Errors: STATE (no model), INVALID_ARG (sizes, segment), UNSUPPORTED
+ * (magnetic receiver components), HIP.  Costs about three forward runs
+ * (forward, replay, reverse sweep). */
 fwd_status fwd_adjoint_td_size(const fwd_plan *plan, int segment, size_t *bytes);
 fwd_status fwd_adjoint_td(fwd_plan *plan, void *ws_dev, size_t ws_bytes, void *scratch_dev,
                           size_t scratch_bytes, int segment, const double *resid_dev,

@@ -1600,6 +1600,56 @@ __global__ void k_td_sens(T *adj, int64_t F, int ns, int nn, int nf, const int *
   *a += (T)g;
 }
 
+// Magnetic receivers and magnetic adjoint sources, one thread per (source, H
+// receiver node); both run beside the step's own launches and read the step
+// index like them (n = last completed step + 1).
+//   k_hrec, after the H update of step n: racc[s][node] += H^{n+1/2}
+//     z^{n+1/2} (eq. dtft transforms H' too; H^{n+1/2} is in half (n&1)^1).
+//   k_hinj, before the H update of step n (adjoint runs): H^{n-1/2} +=
+//     (dt/mu) M'^n with M'^n = sum_r coef[s][node][r] F[r][n], the magnetic
+//     current of the Faraday row (eq. fictitiouswave) acting at n dt; the H
+//     update then reads it from half n&1.
+template <typename T>
+__device__ __forceinline__ T *h_comp(const Half<T> &H, int c) {
+  return c == 3 ? H.hx : (c == 4 ? H.hy : H.hz);
+}
+
+template <typename T>
+__global__ void k_hrec(StepArgs<T> A, const int *hn, int nh, const int *rn_c,
+                       const int64_t *rn_idx, const double2 *zH) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= A.ns * nh) return;
+  const int n = A.step[0] + 1;
+  if (n >= A.nt) return;                    // no recording past the run
+  const int s = t / nh, node = hn[t - s * nh];
+  const T *f = h_comp(half_of(A, (n & 1) ^ 1, s), rn_c[node]);
+  const double v = (double)f[rn_idx[node]];
+  double2 *a = A.racc + ((int64_t)s * A.nn + node) * A.nf;
+  const double2 *z = zH + (int64_t)n * A.nf;
+  for (int kf = 0; kf < A.nf; ++kf) {
+    double2 x = a[kf];
+    x.x = fma(v, z[kf].x, x.x);
+    x.y = fma(v, z[kf].y, x.y);
+    a[kf] = x;
+  }
+}
+
+template <typename T>
+__global__ void k_hinj(StepArgs<T> A, const int *hn, int nh, const int *rn_c,
+                       const int64_t *rn_idx, double dtmu) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= A.ns * nh) return;
+  const int n = A.step[0] + 1;
+  if (n >= A.nt) return;
+  const int s = t / nh, node = hn[t - s * nh];
+  const double *cf = A.coef + ((int64_t)s * A.nn + node) * A.nrow;
+  double v = 0.0;
+  for (int r = 0; r < A.nrow; ++r) v = fma(cf[r], A.Ftab[(int64_t)r * A.nt + n], v);
+  T *f = h_comp(half_of(A, n & 1, s), rn_c[node]);
+  const int64_t q = rn_idx[node];
+  f[q] = (T)((double)f[q] + dtmu * v);
+}
+
 // dst [ns][3][F] <- E of every source in half `half` of the double buffer
 template <typename T>
 __global__ void k_copy_e(T *dst, const T *fields, int64_t fbuf, int half, int ns, int64_t F) {
@@ -1611,13 +1661,16 @@ __global__ void k_copy_e(T *dst, const T *fields, int64_t fbuf, int half, int ns
   }
 }
 
-// receiver output: interpolate node transforms and scale per frequency
+// receiver output: interpolate node transforms and scale per frequency; a
+// row (receiver r, component position ci = row % ncomp) takes scale_h when
+// its component is magnetic (rcomp >= 3), scale otherwise
 __global__ void k_rec_out(int ns, int nrows, int nn, int nf, const int *ptr, const int *node,
                           const double *w, const double2 *racc, const double2 *scale,
-                          double2 *out) {
+                          const double2 *scale_h, const int *rcomp, int ncomp, double2 *out) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= ns * nrows * nf) return;
   const int kf = t % nf, row = (t / nf) % nrows, s = t / (nf * nrows);
+  if (rcomp[row % ncomp] >= 3) scale = scale_h;
   double re = 0, im = 0;
   for (int e = ptr[row]; e < ptr[row + 1]; ++e) {
     const double2 a = racc[((int64_t)s * nn + node[e]) * nf + kf];
@@ -1735,6 +1788,13 @@ struct Dev {
   int *ri_ptr = nullptr, *ri_node = nullptr;
   double *ri_w = nullptr;
   double2 *fwd_scale = nullptr, *adj_scale_v = nullptr, *vol_scale = nullptr;
+  // magnetic receivers: the receiver nodes on H lattices (node ids), their
+  // twiddles z^{n+1/2}, the forward scale of H rows, and the component of
+  // each row position (k_rec_out picks the scale per row)
+  int *hn = nullptr;
+  int nh = 0;
+  double2 *zH = nullptr, *fwd_scale_h = nullptr;
+  int *rcomp = nullptr;
   // adjoint injection coefficients (rebuilt per call)
   double *at_coef = nullptr;
   // per-thread entry tables of the E update for the current tiling, forward
@@ -1883,12 +1943,25 @@ static void ensure_tables(Plan &p, hipStream_t stream) {
   d.ri_ptr = upload(d, p.ri_ptr);
   d.ri_node = upload(d, p.ri_node);
   d.ri_w = upload(d, p.ri_w);
-  std::vector<double2> sc(nf), vs(nf);
+  std::vector<double2> sc(nf), vs(nf), sh(nf);
   for (int k = 0; k < nf; ++k) {
-    const cplx v = p.norm[k] / p.src_scale;
+    const cplx v = p.norm[k] / p.src_scale, vh = p.norm_h[k] / p.src_scale;
     sc[k] = make_double2(v.real(), v.imag());
+    sh[k] = make_double2(vh.real(), vh.imag());
   }
   d.fwd_scale = upload(d, sc);
+  d.fwd_scale_h = upload(d, sh);
+  d.rcomp = upload(d, p.comp);
+  {
+    std::vector<int> hn;
+    for (size_t node = 0; node < p.rn_c.size(); ++node)
+      if (p.rn_c[node] >= 3) hn.push_back((int)node);
+    d.nh = (int)hn.size();
+    d.hn = upload(d, hn);
+    std::vector<double2> zH(p.zH.size());
+    for (size_t q = 0; q < zH.size(); ++q) zH[q] = make_double2(p.zH[q].real(), p.zH[q].imag());
+    d.zH = upload(d, zH);
+  }
   d.vol_scale = d.fwd_scale;
   d.adj_scale_v = static_cast<double2 *>(dalloc(d, nf * sizeof(double2)));
   // adjoint injection coefficients [ns][node][2nf] (filled per adjoint call)
@@ -2056,9 +2129,11 @@ static void build_lists(Plan &p, Dev &d) {
     } else {
       for (int s = 0; s < p.ns; ++s)
         for (int node = 0; node < nn; ++node)
-          place(p.rn_c[node], 0, s, p.rn_idx[node], (s * nn + node) * 2 * nf);
+          if (p.rn_c[node] < 3) place(p.rn_c[node], 0, s, p.rn_idx[node], (s * nn + node) * 2 * nf);
     }
-    for (int node = 0; node < nn; ++node) place(p.rn_c[node], 1, 0, p.rn_idx[node], node);
+    // H receiver nodes are recorded and driven by k_hrec / k_hinj
+    for (int node = 0; node < nn; ++node)
+      if (p.rn_c[node] < 3) place(p.rn_c[node], 1, 0, p.rn_idx[node], node);
     std::stable_sort(ents.begin(), ents.end(), [](const E &a, const E &b) {
       return a.b != b.b ? a.b < b.b : a.slot < b.slot;
     });
@@ -2332,18 +2407,28 @@ static void enqueue_step(Plan &p, Dev &d, const WS &w, void *vol, bool adj, hipS
   const dim3 block(p.bx, p.by), grid(A.nblocks);
   const KTime th_ev = ev ? KTime{ev[0], ev[1]} : KTime{}, te_ev = ev ? KTime{ev[2], ev[3]} : KTime{};
   const KTime *kh = ev ? &th_ev : nullptr, *ke = ev ? &te_ev : nullptr;
+  // magnetic receiver nodes: adjoint sources before the H update, the H
+  // transform after it (the E update does not touch H)
+  const dim3 hgrid((p.ns * d.nh + 63) / 64), hblock(64);
+  if (d.nh > 0 && adj)
+    hipLaunchKernelGGL((k_hinj<T>), hgrid, hblock, 0, st, A, d.hn, d.nh, d.rn_c, d.rn_idx,
+                       p.dt / kMu0);
   if (p.sched == 1) {
     if (ev) {
       (void)hipEventRecord(ev[0], st);
       (void)hipEventRecord(ev[1], st);
     }
     launch_step<T>(A, p.kb, p.acc, adj, grid, block, tiling(p).lds, st, ke);
+    if (d.nh > 0)
+      hipLaunchKernelGGL((k_hrec<T>), hgrid, hblock, 0, st, A, d.hn, d.nh, d.rn_c, d.rn_idx, d.zH);
   } else {
     StepArgs<T> Ah = A;
     const Tiling th = tiling(p, true);
     set_grid(Ah, th.nbx, th.nby, th.nbz);
     const bool o4 = p.fd_order == 4;
     launch_h<T>(Ah, p.vxh, dim3(Ah.nblocks), block, st, kh, o4);
+    if (d.nh > 0)
+      hipLaunchKernelGGL((k_hrec<T>), hgrid, hblock, 0, st, A, d.hn, d.nh, d.rn_c, d.rn_idx, d.zH);
     launch_e<T>(A, p.kb, p.vx, p.acc, adj, false, grid, block, st, ke, o4);
   }
 }
@@ -2508,8 +2593,8 @@ void dev_run_receivers(Plan &p, void *ws, double *E_rec, void *stream) {
   WS w = carve(p, ws);
   const int nrows = p.nr * p.ncomp, nn = (int)p.rn_c.size(), n = p.ns * nrows * p.nf();
   hipLaunchKernelGGL(k_rec_out, dim3((n + 127) / 128), dim3(128), 0, st, p.ns, nrows, nn, p.nf(),
-                     d.ri_ptr, d.ri_node, d.ri_w, w.racc, d.fwd_scale,
-                     reinterpret_cast<double2 *>(E_rec));
+                     d.ri_ptr, d.ri_node, d.ri_w, w.racc, d.fwd_scale, d.fwd_scale_h, d.rcomp,
+                     p.ncomp, reinterpret_cast<double2 *>(E_rec));
   HIP_CHECK(hipGetLastError());
 }
 
@@ -2621,7 +2706,8 @@ void dev_adjoint(Plan &p, void *ws, size_t ws_bytes, const void *vol, const doub
   const int nrows = p.nr * p.ncomp, nn = (int)p.rn_c.size(), n = p.ns * nrows * p.nf();
   double2 *dst = E_adj ? reinterpret_cast<double2 *>(E_adj) : d.eadj;
   hipLaunchKernelGGL(k_rec_out, dim3((n + 127) / 128), dim3(128), 0, st, p.ns, nrows, nn, p.nf(),
-                     d.ri_ptr, d.ri_node, d.ri_w, w.racc, d.adj_scale_v, dst);
+                     d.ri_ptr, d.ri_node, d.ri_w, w.racc, d.adj_scale_v, d.adj_scale_v, d.rcomp,
+                     p.ncomp, dst);
   HIP_CHECK(hipGetLastError());
   HIP_CHECK(hipEventSynchronize(e1));
   float ms = 0;

@@ -87,12 +87,14 @@ struct Plan {
   double tau = 0, t0 = 0;
   std::vector<cplx> What, norm, Omega;   // [nf]
   std::vector<cplx> zE;                  // [nt][nf] z^{n+1}
+  std::vector<cplx> zH;                  // [nt][nf] z^{n+1/2} (H samples)
+  std::vector<cplx> norm_h;              // [nf] 1 / What: magnetic receivers
   // forward injection (per source, merged duplicates)
   std::vector<Target> src_tg;
   std::vector<double> src_coef;          // one coefficient per target
   double src_scale = 1.0;
   // receiver nodes (shared by all sources)
-  std::vector<int> rn_c;
+  std::vector<int> rn_c;                 // component 0..2 (E) or 3..5 (H)
   std::vector<int64_t> rn_idx;
   std::vector<int> ri_ptr, ri_node;      // CSR over (r, ci) -> nodes
   std::vector<double> ri_w;

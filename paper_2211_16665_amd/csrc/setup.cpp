@@ -138,9 +138,12 @@ Plan *plan_create(const fwd_plan_desc *d) {
   }
   if (d->nsrc < 1 || !d->src_pos || !d->src_mom) fail(FWD_ERR_INVALID_ARG, "need >= 1 source");
   if (d->nrec < 1 || !d->rec_pos) fail(FWD_ERR_INVALID_ARG, "need >= 1 receiver");
-  if (d->ncomp < 1 || d->ncomp > 3 || !d->rec_comp) fail(FWD_ERR_INVALID_ARG, "ncomp in [1,3]");
-  for (int c = 0; c < d->ncomp; ++c)
-    if (d->rec_comp[c] < 0 || d->rec_comp[c] > 2) fail(FWD_ERR_INVALID_ARG, "rec_comp in {0,1,2}");
+  if (d->ncomp < 1 || d->ncomp > 6 || !d->rec_comp) fail(FWD_ERR_INVALID_ARG, "ncomp in [1,6]");
+  for (int c = 0; c < d->ncomp; ++c) {
+    if (d->rec_comp[c] < 0 || d->rec_comp[c] > 5) fail(FWD_ERR_INVALID_ARG, "rec_comp in {0,...,5}");
+    for (int e = 0; e < c; ++e)
+      if (d->rec_comp[e] == d->rec_comp[c]) fail(FWD_ERR_INVALID_ARG, "duplicate receiver component");
+  }
   if (d->field_dtype != FWD_F32 && d->field_dtype != FWD_F64)
     fail(FWD_ERR_INVALID_ARG, "field_dtype");
   if (d->acc_mode < FWD_ACC_F64 || d->acc_mode > FWD_ACC_F32) fail(FWD_ERR_INVALID_ARG, "acc_mode");
@@ -253,12 +256,14 @@ struct NodeW {
   double w;
 };
 
-// Lattice of E component c: E_x at (x_{i+1/2}, y_j, z_k) etc.
+// Lattice of component c: E_x at (x_{i+1/2}, y_j, z_k) etc. for c = 0..2;
+// H_x at (x_i, y_{j+1/2}, z_{k+1/2}) etc. for c = 3..5 (half nodes on the
+// axes an E component has nodes on, and the reverse)
 static std::vector<NodeW> point_weights(const Plan &p, int c, const double *q) {
   std::vector<double> lat[3];
   for (int d = 0; d < 3; ++d) {
     const Axis &ax = p.ax[d];
-    if (d == c) {
+    if (c < 3 ? d == c : d != c - 3) {
       lat[d].resize(ax.n);
       for (int i = 0; i < ax.n; ++i) lat[d][i] = 0.5 * (ax.nodes[i] + ax.nodes[i + 1]);
     } else {
@@ -290,10 +295,16 @@ static bool interior_edge(const Plan &p, int c, int k, int j, int i) {
 static double dual_volume(const Plan &p, int c, int k, int j, int i) {
   const Axis &X = p.ax[0], &Y = p.ax[1], &Z = p.ax[2];
   // in the metric lengths: the weights under which the discrete curl pair is
-  // adjoint (cell and dual widths for order 2)
-  if (c == 0) return X.m[i] * Y.md[j] * Z.md[k];
-  if (c == 1) return X.md[i] * Y.m[j] * Z.md[k];
-  return X.md[i] * Y.md[j] * Z.m[k];
+  // adjoint (cell and dual widths for order 2); an H node (c = 3..5) has the
+  // node length on its own axis and cell lengths on the other two
+  switch (c) {
+    case 0: return X.m[i] * Y.md[j] * Z.md[k];
+    case 1: return X.md[i] * Y.m[j] * Z.md[k];
+    case 2: return X.md[i] * Y.md[j] * Z.m[k];
+    case 3: return X.md[i] * Y.m[j] * Z.m[k];
+    case 4: return X.m[i] * Y.md[j] * Z.m[k];
+    default: return X.m[i] * Y.m[j] * Z.md[k];
+  }
 }
 
 void set_model(Plan &p, const double *rho, const double *rho_v) {
@@ -429,6 +440,8 @@ void set_model(Plan &p, const double *rho, const double *rho_v) {
   p.norm.resize(nf);
   p.Omega.resize(nf);
   p.zE.resize((size_t)nt * nf);
+  p.zH.resize((size_t)nt * nf);
+  p.norm_h.resize(nf);
   const cplx I(0.0, 1.0);
   for (int k = 0; k < nf; ++k) {
     cplx acc = 0;
@@ -436,8 +449,14 @@ void set_model(Plan &p, const double *rho, const double *rho_v) {
     p.What[k] = acc;
     // J' = sqrt(-i omega / 2 omega0) J (correspondence below eq. mittet)
     p.norm[k] = std::sqrt(cplx(0.0, -p.omega[k] / (2.0 * p.omega0))) / acc;
+    // H' = sqrt(-i omega / 2 omega0) H: the magnetic field of the same source
+    // carries no sqrt factor
+    p.norm_h[k] = 1.0 / acc;
     p.Omega[k] = (2.0 / p.dt) * std::sin(p.wprime[k] * p.dt * 0.5);
-    for (int n = 0; n < nt; ++n) p.zE[(size_t)n * nf + k] = std::exp(I * p.wprime[k] * ((n + 1.0) * p.dt));
+    for (int n = 0; n < nt; ++n) {
+      p.zE[(size_t)n * nf + k] = std::exp(I * p.wprime[k] * ((n + 1.0) * p.dt));
+      p.zH[(size_t)n * nf + k] = std::exp(I * p.wprime[k] * ((n + 0.5) * p.dt));
+    }
   }
 
   // forward injection: J = p delta(x - x_s) spread with trilinear weights
@@ -490,10 +509,11 @@ void set_model(Plan &p, const double *rho, const double *rho_v) {
     for (int ci = 0; ci < p.ncomp; ++ci) {
       const int c = p.comp[ci];
       for (const NodeW &nw : point_weights(p, c, &p.rec_pos[3 * r])) {
-        if (!interior_edge(p, c, nw.k, nw.j, nw.i))
+        // every H node is updated; E nodes on the outer walls are not
+        if (c < 3 && !interior_edge(p, c, nw.k, nw.j, nw.i))
           fail(FWD_ERR_INVALID_ARG, "receiver touches the outer boundary of the grid");
         const int64_t idx = p.lin(nw.k, nw.j, nw.i);
-        const int64_t key = idx * 3 + c;
+        const int64_t key = idx * 6 + c;
         auto it = node_of.find(key);
         int node = it == node_of.end() ? -1 : it->second;
         if (node < 0) {
@@ -631,14 +651,20 @@ void basis_build(Plan &p, double gamma_rel, double gamma_abs, int max_iter, doub
 // residual is an electric current source carrying sqrt(-i w / 2 w0)):
 // spectrum s = sqrt(-i w_k / 2 w0) conj(resid), real coefficient vector
 // C = [Re s_1..Re s_nf, Im s_1..Im s_nf] (eq. basis), spread onto the
-// receiver nodes with the trilinear weights over the dual volume.
+// receiver nodes with the trilinear weights over the dual volume.  A
+// magnetic residual (H nodes) is a magnetic current M' = M, injected into H
+// at n dt: its spectrum is conj(resid) z_k^{1/2}, since the basis functions
+// reproduce spectra at the injection times (n+1/2) dt of J'.
 // T[s][node][2nf]; scale keeps the injected increments near 1.
 void adjoint_coefficients(const Plan &p, const double *resid, std::vector<double> &T,
                           double &scale) {
   const int nf = p.nf(), m = 2 * nf, nn = (int)p.rn_c.size();
   T.assign((size_t)p.ns * nn * m, 0.0);
-  std::vector<cplx> fac(nf);
-  for (int k = 0; k < nf; ++k) fac[k] = std::sqrt(cplx(0.0, -p.omega[k] / (2.0 * p.omega0)));
+  std::vector<cplx> fac(nf), fac_h(nf);
+  for (int k = 0; k < nf; ++k) {
+    fac[k] = std::sqrt(cplx(0.0, -p.omega[k] / (2.0 * p.omega0)));
+    fac_h[k] = std::exp(cplx(0.0, 1.0) * p.wprime[k] * (0.5 * p.dt));
+  }
   std::vector<double> bmax(m, 0.0);
   for (int r = 0; r < m; ++r)
     for (int n = 0; n < p.nt; ++n) bmax[r] = std::max(bmax[r], std::fabs(p.basis[(size_t)r * p.nt + n]));
@@ -646,19 +672,20 @@ void adjoint_coefficients(const Plan &p, const double *resid, std::vector<double
   for (int s = 0; s < p.ns; ++s)
     for (int node = 0; node < nn; ++node) {
       double *t = &T[((size_t)s * nn + node) * m];
+      const bool mag = p.rn_c[node] >= 3;
       for (int e = p.at_ptr[node]; e < p.at_ptr[node + 1]; ++e) {
         const int row = p.at_row[e];
         const double w = p.at_w[e];
         for (int k = 0; k < nf; ++k) {
           const double *rr = &resid[2 * (((size_t)s * p.nr * p.ncomp + row) * nf + k)];
-          const cplx sp = fac[k] * std::conj(cplx(rr[0], rr[1]));
+          const cplx sp = (mag ? fac_h[k] : fac[k]) * std::conj(cplx(rr[0], rr[1]));
           t[k] += w * sp.real();
           t[nf + k] += w * sp.imag();
         }
       }
       double inc = 0;
       for (int r = 0; r < m; ++r) inc += std::fabs(t[r]) * bmax[r];
-      big = std::max(big, inc * p.ce[p.rn_c[node]][p.rn_idx[node]]);
+      big = std::max(big, inc * (mag ? p.dt / kMu0 : p.ce[p.rn_c[node]][p.rn_idx[node]]));
     }
   scale = big > 0 ? std::exp2(std::round(std::log2(1.0 / big))) : 1.0;  // power of two: exact
   for (double &v : T) v *= scale;

@@ -156,7 +156,8 @@ def _stream(stream=None):
 class Plan:
     """A plan of libfwdem: grid, frequencies, sources and receivers fixed at
     creation; the model set by ``set_model``.  Large device buffers are torch
-    tensors owned here or by the caller."""
+    tensors owned here or by the caller.  ``rec_comp`` lists the recorded
+    components: 0-2 for E_x, E_y, E_z, 3-5 for H_x, H_y, H_z."""
 
     def __init__(self, x, y, z, freqs, src_pos, src_mom, rec_pos, rec_comp=(0, 1), npml=8,
                  f0=1.0, field_dtype="f32", acc_mode="f64", rho_air_cap=1e4, cfl=0.95,

@@ -6,6 +6,8 @@ import json
 import os
 import re
 
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -48,7 +50,9 @@ def test_rejects_bad_descriptions(lib):
     with pytest.raises(fw.FwdError):
         fw.Plan(w.x, w.y, w.z, w.freqs, w.src_pos, w.src_mom, w.rec_pos, npml=8)   # grid too small
     with pytest.raises(fw.FwdError):
-        fw.Plan(w.x, w.y, w.z, w.freqs, w.src_pos, w.src_mom, w.rec_pos, rec_comp=(3,), npml=3)
+        fw.Plan(w.x, w.y, w.z, w.freqs, w.src_pos, w.src_mom, w.rec_pos, rec_comp=(6,), npml=3)
+    with pytest.raises(fw.FwdError):
+        fw.Plan(w.x, w.y, w.z, w.freqs, w.src_pos, w.src_mom, w.rec_pos, rec_comp=(0, 0), npml=3)
     p = _plan(w)
     with pytest.raises(fw.FwdError) as e:
         p.set_model(-w.rho)
@@ -81,6 +85,39 @@ def test_degenerate_inputs_are_refused(lib, kw, msg):
         p = _plan(w)
         p.set_model(w.rho)
     assert e.value.status == 1 and msg in str(e.value)
+
+
+def test_magnetic_receiver_components(lib):
+    """Components 3-5 (H_x, H_y, H_z) are accepted: the library's unique H
+    receiver nodes are the oracle's (trilinear on the H lattices); E and H
+    nodes are distinct entries, so E and H components together give the sum
+    of the two counts.  A receiver on the first x node plane is refused for
+    E_y (wall edges are not updated) but not for H_x.  The time-domain
+    adjoint refuses magnetic components (UNSUPPORTED) before any device
+    call."""
+    from oracle.stepping import receiver_nodes
+    w = tiny(seed=0, rec_comp=(3, 4, 5))
+    p = _plan(w)
+    p.set_model(w.rho)
+    nh = p.info.n_rec_nodes
+    assert nh == len(receiver_nodes(make_setup(w), w.rec_pos, w.rec_comp)[0])
+    pe = _plan(w.replace(rec_comp=(0, 1, 2)))
+    pe.set_model(w.rho)
+    pm = _plan(w.replace(rec_comp=(0, 1, 2, 3, 4, 5)))
+    pm.set_model(w.rho)
+    assert pm.info.n_rec_nodes == pe.info.n_rec_nodes + nh
+    assert pm.info.n_adj_targets == pm.info.n_rec_nodes
+    # a receiver on the grid's first node plane: E nodes there are on the wall
+    # (refused), H nodes are not
+    edge = w.replace(rec_pos=np.array([[w.x[0], 0.5 * (w.y[3] + w.y[4]), 0.5 * (w.z[3] + w.z[4])]]))
+    q = _plan(edge.replace(rec_comp=(3,)))
+    q.set_model(w.rho)
+    with pytest.raises(fw.FwdError):
+        qe = _plan(edge.replace(rec_comp=(1,)))
+        qe.set_model(w.rho)
+    dummy = ctypes.c_char_p(b"x" * 64)
+    st = p.lib.fwd_adjoint_td(p.handle, dummy, 64, dummy, 64, 10, dummy, dummy, 0, None)
+    assert st == 7 and b"magnetic" in p.lib.fwd_last_error()
 
 
 def test_strict_cfl(lib):

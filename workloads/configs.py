@@ -30,7 +30,7 @@ class Workload:
     src_pos: np.ndarray           # [ns][3]
     src_mom: np.ndarray           # [ns][3]  (A m)
     rec_pos: np.ndarray           # [nr][3]
-    rec_comp: tuple = (0, 1)      # recorded E components (0=x,1=y,2=z)
+    rec_comp: tuple = (0, 1)      # recorded components (0-2: E_x,E_y,E_z; 3-5: H_x,H_y,H_z)
     npml: int = 8
     f0: float = 1.0
     nt: int = 0                   # 0: derived from the damping of the lowest frequency
