@@ -250,6 +250,42 @@ def vti_study(plan, w_true, rho0, iso_s):
             "max_abs_grad_h": g[0], "max_abs_grad_v": g[1]}
 
 
+def magnetic_study(w_true, rho0, tuned, electric_s):
+    """The same gradient step with magnetic data: receivers recording E_x,
+    E_y, H_x, H_y (a plan of its own, with the tiling of the main plan).
+    The H transform and the magnetic adjoint source run as one small kernel
+    per step each, beside the step's own kernels; the time against the
+    electric-only step measures their cost."""
+    import torch
+    from paper_2211_16665_amd import fwdem as fw
+    wm = w_true.replace(rec_comp=(0, 1, 3, 4))
+    plan = fw.Plan.from_workload(wm, field_dtype="f32", acc_mode="f64")
+    for k in TILING_KEYS:
+        plan.set_option(getattr(fw, "FWD_OPT_" + k), tuned[k.lower()])
+    plan.set_model(wm.rho)
+    d_obs = plan.forward()
+    vol = plan.volume_buffer()
+    grad = torch.zeros(plan.shape, dtype=torch.float64, device="cuda")
+
+    def step():
+        plan.set_model(rho0)
+        plan.basis_build(gamma_rel=1e-12)
+        E, _ = plan.forward(vol=vol, want_volume=True)
+        plan.adjoint(vol, d_obs - E, grad=grad)
+
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    step()
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    out = {"receivers": "E_x, E_y, H_x, H_y", "gradient_s": t, "electric_gradient_s": electric_s,
+           "overhead": t / electric_s - 1.0, "rec_nodes": plan.info.n_rec_nodes}
+    del plan, vol, grad
+    torch.cuda.empty_cache()
+    return out
+
+
 def order4_study(w_true, rho0, order2_s, tsize, accsize):
     """The same gradient step with fourth-order differences (a plan of its
     own: the order changes dt, nt and the tables): time against the
@@ -367,6 +403,8 @@ def main():
                     help="skip the VTI gradient timing")
     ap.add_argument("--fd-order", type=int, default=2, choices=(2, 4),
                     help="order of the staggered differences of the timed step")
+    ap.add_argument("--no-magnetic", action="store_true",
+                    help="skip the gradient step with magnetic receivers")
     ap.add_argument("--no-order4", action="store_true",
                     help="skip the fourth-order gradient timing")
     ap.add_argument("--tiling", default="",
@@ -507,6 +545,8 @@ def main():
         out["vti"] = vti_study(plan, w_true, rho0, elapsed / args.steps)
     if not args.no_order4 and args.fd_order == 2:
         out["order4"] = order4_study(w_true, rho0, elapsed / args.steps, tsize, accsize)
+    if not args.no_magnetic and args.fd_order == 2 and args.field_dtype == "f32":
+        out["magnetic"] = magnetic_study(w_true, rho0, tuned, elapsed / args.steps)
     if not args.no_batched:
         del vol, grad
         torch.cuda.empty_cache()

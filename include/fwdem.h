@@ -259,9 +259,10 @@ fwd_status fwd_adjoint(fwd_plan *plan, void *ws_dev, size_t ws_bytes,
  *   segment      steps between checkpoints (>= 1)
  *   resid_dev    complex [nsrc][nrec][ncomp][nfreq], W^2 (d - E)
  *   grad_dev     double [nz][ny][nx], added to if accumulate != 0
- * Errors: STATE (no model), INVALID_ARG (sizes, segment), UNSUPPORTED
- * (magnetic receiver components), HIP.  Costs about three forward runs
- * (forward, replay, reverse sweep). */
+ * Magnetic receiver components add d phi / d H^{n+1/2} = -Re sum_k C_k
+ * z_k^{n+1/2} (C_k with 1 / W_k) to the H multipliers of reverse step n.
+ * Errors: STATE (no model), INVALID_ARG (sizes, segment), HIP.  Costs about
+ * three forward runs (forward, replay, reverse sweep). */
 fwd_status fwd_adjoint_td_size(const fwd_plan *plan, int segment, size_t *bytes);
 fwd_status fwd_adjoint_td(fwd_plan *plan, void *ws_dev, size_t ws_bytes, void *scratch_dev,
                           size_t scratch_bytes, int segment, const double *resid_dev,

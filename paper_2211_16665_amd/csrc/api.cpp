@@ -253,8 +253,6 @@ fwd_status fwd_adjoint_td(fwd_plan *h, void *ws, size_t ws_bytes, void *scratch,
     if (!p.have_model) fail(FWD_ERR_STATE, "no model set");
     if (!ws || !scratch || !resid || !grad)
       fail(FWD_ERR_INVALID_ARG, "workspace, scratch, residual and gradient are required");
-    for (int c : p.comp)
-      if (c >= 3) fail(FWD_ERR_UNSUPPORTED, "time-domain adjoint of magnetic receivers");
     dev_adjoint_td(p, ws, ws_bytes, scratch, scratch_bytes, segment, resid, grad, accumulate,
                    stream);
   });

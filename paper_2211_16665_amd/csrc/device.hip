@@ -1582,19 +1582,22 @@ __global__ void __launch_bounds__(256) k_td_h(StepArgs<T> A, const T *Enew, cons
   }
 }
 
-// aE[s][node] += -Re sum_k C[s][node][k] z_k^m (sensitivity of the misfit to
-// the sample E^m; z_k^m = zE[m-1][k]).  One thread per (source, node).
+// a[s][node] += -Re sum_k C[s][node][k] z[k]: the sensitivity of the misfit
+// to the sample at the receiver nodes of one kind, E (magnetic = 0: the
+// sample E^m, z = zE row m-1 = z^m) or H (magnetic = 1: the sample
+// H^{n+1/2}, z = zH row n = z^{n+1/2}).  One thread per (source, node).
 template <typename T>
 __global__ void k_td_sens(T *adj, int64_t F, int ns, int nn, int nf, const int *rn_c,
-                          const int64_t *rn_idx, const double2 *C, const double2 *zE, int m) {
+                          const int64_t *rn_idx, const double2 *C, const double2 *z,
+                          int magnetic) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= ns * nn) return;
   const int s = t / nn, node = t % nn;
+  if ((rn_c[node] >= 3) != (magnetic != 0)) return;
   double g = 0.0;
   for (int kf = 0; kf < nf; ++kf) {
     const double2 c = C[((int64_t)s * nn + node) * nf + kf];
-    const double2 z = zE[(int64_t)(m - 1) * nf + kf];
-    g -= c.x * z.x - c.y * z.y;
+    g -= c.x * z[kf].x - c.y * z[kf].y;
   }
   T *a = adj + (int64_t)s * 6 * F + (int64_t)rn_c[node] * F + rn_idx[node];
   *a += (T)g;
@@ -2777,7 +2780,15 @@ static void adjoint_td_t(Plan &p, Dev &d, const WS &w, void *ws, char *scratch, 
   const int cgrid = (int)std::min<int64_t>(((int64_t)ns * 3 * F + 255) / 256, 65536);
   auto sens = [&](int m) {
     hipLaunchKernelGGL((k_td_sens<T>), sgrid, sblock, 0, st, afld, F, ns, nn, nf, d.rn_c, d.rn_idx,
-                       coef, d.zE, m);
+                       coef, d.zE + (int64_t)(m - 1) * nf, 0);
+  };
+  // magnetic receivers: d phi / d H^{n+1/2} joins the H multipliers after
+  // k_td_e (whose deferred CPML update still needs the previous value) and
+  // before k_td_h reads them
+  auto hsens = [&](int n) {
+    if (d.nh > 0)
+      hipLaunchKernelGGL((k_td_sens<T>), sgrid, sblock, 0, st, afld, F, ns, nn, nf, d.rn_c,
+                         d.rn_idx, coef, d.zH + (int64_t)n * nf, 1);
   };
   sens(nt);
   T *fields = static_cast<T *>(w.fields);
@@ -2801,10 +2812,12 @@ static void adjoint_td_t(Plan &p, Dev &d, const WS &w, void *ws, char *scratch, 
       const int t = n - n0;
       if (p.fd_order == 4) {
         hipLaunchKernelGGL((k_td_e<T, 4>), grid, block, 0, st, A);
+        hsens(n);
         hipLaunchKernelGGL((k_td_h<T, 4>), grid, block, 0, st, A, eseg + (t + 1) * eslice,
                            eseg + t * eslice, (const double *)tdw);
       } else {
         hipLaunchKernelGGL((k_td_e<T, 2>), grid, block, 0, st, A);
+        hsens(n);
         hipLaunchKernelGGL((k_td_h<T, 2>), grid, block, 0, st, A, eseg + (t + 1) * eslice,
                            eseg + t * eslice, (const double *)tdw);
       }

@@ -696,16 +696,18 @@ void td_coefficients(const Plan &p, const double *resid, std::vector<double> &C,
   // E_rec[s][r][c][k] = norm_k sum_nodes w sum_m E^m z_k^m, so the misfit's
   // sensitivity to E^m at a node is -Re sum_k C_k z_k^m with
   // C_k = sum over the (receiver, component) rows touching the node of
-  // w conj(resid) norm_k
+  // w conj(resid) norm_k; magnetic rows likewise with norm_h and the samples
+  // H^{n+1/2} z_k^{n+1/2}
   const int nf = p.nf(), nn = (int)p.rn_c.size(), rows = p.nr * p.ncomp;
   C.assign((size_t)p.ns * nn * nf * 2, 0.0);
   for (int s = 0; s < p.ns; ++s)
     for (int row = 0; row < rows; ++row)
       for (int e = p.ri_ptr[row]; e < p.ri_ptr[row + 1]; ++e) {
         const int node = p.ri_node[e];
+        const bool mag = p.comp[row % p.ncomp] >= 3;   // H rows: H = norm_h sum H^{n+1/2} z^{n+1/2}
         for (int k = 0; k < nf; ++k) {
           const double *rr = &resid[2 * (((size_t)s * rows + row) * nf + k)];
-          const cplx v = p.ri_w[e] * std::conj(cplx(rr[0], rr[1])) * p.norm[k];
+          const cplx v = p.ri_w[e] * std::conj(cplx(rr[0], rr[1])) * (mag ? p.norm_h[k] : p.norm[k]);
           double *c = &C[2 * (((size_t)s * nn + node) * nf + k)];
           c[0] += v.real();
           c[1] += v.imag();

@@ -6,8 +6,6 @@ import json
 import os
 import re
 
-import ctypes
-
 import numpy as np
 import pytest
 
@@ -92,9 +90,7 @@ def test_magnetic_receiver_components(lib):
     receiver nodes are the oracle's (trilinear on the H lattices); E and H
     nodes are distinct entries, so E and H components together give the sum
     of the two counts.  A receiver on the first x node plane is refused for
-    E_y (wall edges are not updated) but not for H_x.  The time-domain
-    adjoint refuses magnetic components (UNSUPPORTED) before any device
-    call."""
+    E_y (wall edges are not updated) but not for H_x."""
     from oracle.stepping import receiver_nodes
     w = tiny(seed=0, rec_comp=(3, 4, 5))
     p = _plan(w)
@@ -115,9 +111,6 @@ def test_magnetic_receiver_components(lib):
     with pytest.raises(fw.FwdError):
         qe = _plan(edge.replace(rec_comp=(1,)))
         qe.set_model(w.rho)
-    dummy = ctypes.c_char_p(b"x" * 64)
-    st = p.lib.fwd_adjoint_td(p.handle, dummy, 64, dummy, 64, 10, dummy, dummy, 0, None)
-    assert st == 7 and b"magnetic" in p.lib.fwd_last_error()
 
 
 def test_strict_cfl(lib):
