@@ -121,6 +121,8 @@ struct StepArgs {
   const double *Ftab;   // [nrow][nt] time functions (wavelet or basis functions)
   double2 *racc;        // [ns][nn][nf] receiver-node transforms
   int nn;               // receiver nodes
+  const int *rn_c;      // [nn] component of each receiver node (3..5: H)
+  const double2 *zH;    // [nt][nf] z^{n+1/2} (H samples)
 };
 
 // Block -> (tile, source).  Blocks b = tile * ns + s, sources fastest, so
@@ -646,7 +648,10 @@ __device__ __forceinline__ void post_e(const StepArgs<T> &A, int s, int64_t q,
 // sub is the vector element (two-kernel schedule) or the plane within the
 // block's chunk (fused schedule): kind 0 = injection J'^{n+1/2} into
 // component c of source s, value sum_r coef[ref + r] F[r][n]; kind 1 =
-// receiver node (racc[s][node = ref] += E^{n+1} z^{n+1}, every source).
+// receiver node (racc[s][node = ref] += E^{n+1} z^{n+1}, every source);
+// kind 1 with c = 3 = H receiver node (two-kernel schedule: the E update of
+// step n holds H^{n+1/2} of its own node, its curl operand, and adds
+// H^{n+1/2} z^{n+1/2} for the node's H component, rn_c[ref]).
 template <typename T>
 __device__ __forceinline__ double inject_value(const StepArgs<T> &A, int lo, int hi, int s, int c,
                                                int sub, int n) {
@@ -655,10 +660,75 @@ __device__ __forceinline__ double inject_value(const StepArgs<T> &A, int lo, int
     const int2 en = A.tl_ent[e];
     if ((en.x & 511) == (c | (sub << 3)) && (en.x >> 9) == s) {
       const double *cf = A.coef + en.y;
-      for (int r = 0; r < A.nrow; ++r) v += cf[r] * A.Ftab[(int64_t)r * A.nt + n];
+      for (int r = 0; r < A.nrow; ++r) v = fma(cf[r], A.Ftab[(int64_t)r * A.nt + n], v);
     }
   }
   return v;
+}
+
+// The same walks done once per thread (two-kernel schedule): every thread
+// that owns entries makes one pass before the update for all injections
+// (per component c and vector element e, slot c * VX + e, summed in entry
+// order as inject_value does) and one pass after it for all records (E
+// nodes with E^{n+1} z^{n+1}, H nodes with H^{n+1/2} z^{n+1/2}).  Each walk
+// costs dependent memory round trips, and the threads of the receiver and
+// source tiles set the tail of the launch.
+template <typename T, int VX>
+__device__ __forceinline__ void inject_all(const StepArgs<T> &A, int lo, int hi, int s, int n,
+                                           double (&inj)[3 * VX]) {
+#pragma unroll
+  for (int q = 0; q < 3 * VX; ++q) inj[q] = 0.0;
+  for (int e = lo; e < hi; ++e) {
+    const int2 en = A.tl_ent[e];
+    if ((en.x & 4) || (en.x >> 9) != s) continue;           // kind 0 of this source
+    const int slot = (en.x & 3) * VX + ((en.x >> 3) & 63);
+    double cur = 0.0;
+#pragma unroll
+    for (int q = 0; q < 3 * VX; ++q) cur = q == slot ? inj[q] : cur;
+    const double *cf = A.coef + en.y;
+    for (int r = 0; r < A.nrow; ++r) cur = fma(cf[r], A.Ftab[(int64_t)r * A.nt + n], cur);
+#pragma unroll
+    for (int q = 0; q < 3 * VX; ++q) inj[q] = q == slot ? cur : inj[q];
+  }
+}
+
+template <typename T, int VX>
+__device__ __forceinline__ void record_all(const StepArgs<T> &A, int lo, int hi, int s, int n,
+                                           const Vec<T, VX> (&e1)[3], const unsigned (&ok)[3],
+                                           const Vec<T, VX> (&h)[3]) {
+  for (int e2 = lo; e2 < hi; ++e2) {
+    const int2 en = A.tl_ent[e2];
+    if (!(en.x & 4)) continue;                                // kind 1: receiver node
+    const int c = en.x & 3, sub = (en.x >> 3) & 63;
+    const int ch = c < 3 ? -1 : A.rn_c[en.y] - 3;
+    // select with compile-time indices only (no addressable arrays)
+    T val = T(0);
+    bool on = false;
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+#pragma unroll
+      for (int e = 0; e < VX; ++e) {
+        if (e != sub) continue;
+        if (q == c) {
+          val = e1[q].v[e];
+          on = (ok[q] >> e) & 1u;
+        }
+        if (q == ch) {
+          val = h[q].v[e];
+          on = true;
+        }
+      }
+    if (!on) continue;
+    const double v = (double)val;
+    double2 *a = A.racc + ((int64_t)s * A.nn + en.y) * A.nf;
+    const double2 *z = (c < 3 ? A.zE : A.zH) + (int64_t)n * A.nf;
+    for (int kf = 0; kf < A.nf; ++kf) {
+      double2 x = a[kf];
+      x.x = fma(v, z[kf].x, x.x);
+      x.y = fma(v, z[kf].y, x.y);
+      a[kf] = x;
+    }
+  }
 }
 
 template <typename T>
@@ -728,6 +798,8 @@ __device__ __forceinline__ void e_vec(const StepArgs<T> &A, int s, const Half<T>
   V ps_ez_y = py && okz ? vload<VX>(P.psY + 3 * sY + iY) : vzero<T, VX>();
   V ps_ex_z = pz && okx ? vload<VX>(P.psZ + 2 * sZ + iZ) : vzero<T, VX>();
   V ps_ey_z = pz && oky ? vload<VX>(P.psZ + 3 * sZ + iZ) : vzero<T, VX>();
+  double inj[3 * VX];
+  if (lo < hi) inject_all<T, VX>(A, lo, hi, s, n, inj);
   // ---- compute ----
   V e1x = e0x, e1y = e0y, e1z = e0z;
 #pragma unroll
@@ -742,7 +814,7 @@ __device__ __forceinline__ void e_vec(const StepArgs<T> &A, int s, const Half<T>
     if ((okx >> e) & 1u) {
       T v = ex_node(A, j, k, e0x.v[e], cx.v[e], hz0.v[e], hzj.v[e], hy0.v[e], hyk.v[e], py,
                     ps_ex_y.v[e], pz, ps_ex_z.v[e]);
-      if (lo < hi) v -= (T)((double)cx.v[e] * inject_value(A, lo, hi, s, 0, e, n));
+      if (lo < hi) v -= (T)((double)cx.v[e] * inj[0 * VX + e]);
       e1x.v[e] = v;
     }
     if ((oky >> e) & 1u) {
@@ -750,7 +822,7 @@ __device__ __forceinline__ void e_vec(const StepArgs<T> &A, int s, const Half<T>
       T &psx = px ? P.psX[2 * sX + iX] : dummy;
       T v = ey_node(A, i, k, e0y.v[e], cy.v[e], hx0.v[e], hxk.v[e], hz0.v[e], hz_im, pz,
                     ps_ey_z.v[e], px, psx);
-      if (lo < hi) v -= (T)((double)cy.v[e] * inject_value(A, lo, hi, s, 1, e, n));
+      if (lo < hi) v -= (T)((double)cy.v[e] * inj[1 * VX + e]);
       e1y.v[e] = v;
     }
     if ((okz >> e) & 1u) {
@@ -758,7 +830,7 @@ __device__ __forceinline__ void e_vec(const StepArgs<T> &A, int s, const Half<T>
       T &psx = px ? P.psX[3 * sX + iX] : dummy;
       T v = ez_node(A, i, j, e0z.v[e], cz.v[e], hy0.v[e], hy_im, hx0.v[e], hxj.v[e], px, psx, py,
                     ps_ez_y.v[e]);
-      if (lo < hi) v -= (T)((double)cz.v[e] * inject_value(A, lo, hi, s, 2, e, n));
+      if (lo < hi) v -= (T)((double)cz.v[e] * inj[2 * VX + e]);
       e1z.v[e] = v;
     }
   }
@@ -771,12 +843,9 @@ __device__ __forceinline__ void e_vec(const StepArgs<T> &A, int s, const Half<T>
   if (pz && okx) vstore(P.psZ + 2 * sZ + iZ, ps_ex_z);
   if (pz && oky) vstore(P.psZ + 3 * sZ + iZ, ps_ey_z);
   if (lo < hi) {
-#pragma unroll
-    for (int e = 0; e < VX; ++e) {
-      if ((okx >> e) & 1u) record(A, lo, hi, s, 0, e, n, (double)e1x.v[e]);
-      if ((oky >> e) & 1u) record(A, lo, hi, s, 1, e, n, (double)e1y.v[e]);
-      if ((okz >> e) & 1u) record(A, lo, hi, s, 2, e, n, (double)e1z.v[e]);
-    }
+    const Vec<T, VX> e1[3] = {e1x, e1y, e1z}, hh[3] = {hx0, hy0, hz0};
+    const unsigned ok[3] = {okx, oky, okz};
+    record_all<T, VX>(A, lo, hi, s, n, e1, ok, hh);
   }
   // ---- volume transform / gradient product ----
   {
@@ -946,13 +1015,15 @@ __global__ void __launch_bounds__(256) k_update_e4(StepArgs<T> A,
   const T zero = T(0);
   const Vec<T, 1> e0x = vec1(I.ex[q]), e0y = vec1(I.ey[q]), e0z = vec1(I.ez[q]);
   Vec<T, 1> e1x = e0x, e1y = e0y, e1z = e0z;
+  double inj[3];
+  if (lo < hi) inject_all<T, 1>(A, lo, hi, s, n, inj);
   if (okx) {                             // E_x: dHz/dy - dHy/dz
     const T D1 = d4_he(O.hz, (int64_t)k * plane + i, (int64_t)PX, j, A.ny);
     const T D2 = d4_he(O.hy, (int64_t)j * PX + i, plane, k, A.nz);
     T psy = py ? P.psY[2 * sY + iY] : zero, psz = pz ? P.psZ[2 * sZ + iZ] : zero;
     const T c = A.ce[q];
     T v = ex_node(A, j, k, e0x.v[0], c, D1, zero, D2, zero, py, psy, pz, psz);
-    if (lo < hi) v -= (T)((double)c * inject_value(A, lo, hi, s, 0, 0, n));
+    if (lo < hi) v -= (T)((double)c * inj[0]);
     e1x.v[0] = v;
     if (py) P.psY[2 * sY + iY] = psy;
     if (pz) P.psZ[2 * sZ + iZ] = psz;
@@ -963,7 +1034,7 @@ __global__ void __launch_bounds__(256) k_update_e4(StepArgs<T> A,
     T psz = pz ? P.psZ[3 * sZ + iZ] : zero, psx = px ? P.psX[2 * sX + iX] : zero;
     const T c = A.ce[A.F + q];
     T v = ey_node(A, i, k, e0y.v[0], c, D1, zero, D2, zero, pz, psz, px, psx);
-    if (lo < hi) v -= (T)((double)c * inject_value(A, lo, hi, s, 1, 0, n));
+    if (lo < hi) v -= (T)((double)c * inj[1]);
     e1y.v[0] = v;
     if (pz) P.psZ[3 * sZ + iZ] = psz;
     if (px) P.psX[2 * sX + iX] = psx;
@@ -974,7 +1045,7 @@ __global__ void __launch_bounds__(256) k_update_e4(StepArgs<T> A,
     T psx = px ? P.psX[3 * sX + iX] : zero, psy = py ? P.psY[3 * sY + iY] : zero;
     const T c = A.ce[2 * A.F + q];
     T v = ez_node(A, i, j, e0z.v[0], c, D1, zero, D2, zero, px, psx, py, psy);
-    if (lo < hi) v -= (T)((double)c * inject_value(A, lo, hi, s, 2, 0, n));
+    if (lo < hi) v -= (T)((double)c * inj[2]);
     e1z.v[0] = v;
     if (px) P.psX[3 * sX + iX] = psx;
     if (py) P.psY[3 * sY + iY] = psy;
@@ -983,9 +1054,10 @@ __global__ void __launch_bounds__(256) k_update_e4(StepArgs<T> A,
   if (oky) O.ey[q] = e1y.v[0];
   if (okz) O.ez[q] = e1z.v[0];
   if (lo < hi) {
-    if (okx) record(A, lo, hi, s, 0, 0, n, (double)e1x.v[0]);
-    if (oky) record(A, lo, hi, s, 1, 0, n, (double)e1y.v[0]);
-    if (okz) record(A, lo, hi, s, 2, 0, n, (double)e1z.v[0]);
+    const Vec<T, 1> e1[3] = {e1x, e1y, e1z};
+    const Vec<T, 1> hh[3] = {vec1(O.hx[q]), vec1(O.hy[q]), vec1(O.hz[q])};
+    const unsigned ok[3] = {okx ? 1u : 0u, oky ? 1u : 0u, okz ? 1u : 0u};
+    record_all<T, 1>(A, lo, hi, s, n, e1, ok, hh);
   }
   {
     const Vec<T, 1> e0[3] = {e0x, e0y, e0z}, e1[3] = {e1x, e1y, e1z};
@@ -1606,8 +1678,9 @@ __global__ void k_td_sens(T *adj, int64_t F, int ns, int nn, int nf, const int *
 // Magnetic receivers and magnetic adjoint sources, one thread per (source, H
 // receiver node); both run beside the step's own launches and read the step
 // index like them (n = last completed step + 1).
-//   k_hrec, after the H update of step n: racc[s][node] += H^{n+1/2}
-//     z^{n+1/2} (eq. dtft transforms H' too; H^{n+1/2} is in half (n&1)^1).
+//   k_hrec, after the fused step n: racc[s][node] += H^{n+1/2} z^{n+1/2}
+//     (eq. dtft transforms H' too; H^{n+1/2} is in half (n&1)^1).  The
+//     two-kernel schedule records in the E update instead (record_h).
 //   k_hinj, before the H update of step n (adjoint runs): H^{n-1/2} +=
 //     (dt/mu) M'^n with M'^n = sum_r coef[s][node][r] F[r][n], the magnetic
 //     current of the Faraday row (eq. fictitiouswave) acting at n dt; the H
@@ -2134,9 +2207,13 @@ static void build_lists(Plan &p, Dev &d) {
         for (int node = 0; node < nn; ++node)
           if (p.rn_c[node] < 3) place(p.rn_c[node], 0, s, p.rn_idx[node], (s * nn + node) * 2 * nf);
     }
-    // H receiver nodes are recorded and driven by k_hrec / k_hinj
-    for (int node = 0; node < nn; ++node)
+    // H receiver nodes: recorded by the E update (entry c = 3; the node's
+    // table gives the component), or by k_hrec under the fused schedule;
+    // their adjoint sources come from k_hinj
+    for (int node = 0; node < nn; ++node) {
       if (p.rn_c[node] < 3) place(p.rn_c[node], 1, 0, p.rn_idx[node], node);
+      else if (p.sched != 1) place(3, 1, 0, p.rn_idx[node], node);
+    }
     std::stable_sort(ents.begin(), ents.end(), [](const E &a, const E &b) {
       return a.b != b.b ? a.b < b.b : a.slot < b.slot;
     });
@@ -2256,6 +2333,8 @@ static StepArgs<T> make_args(Plan &p, Dev &d, const WS &w, void *vol, bool adj, 
   }
   A.racc = w.racc;
   A.nn = (int)p.rn_c.size();
+  A.rn_c = d.rn_c;
+  A.zH = d.zH;
   return A;
 }
 
@@ -2410,8 +2489,9 @@ static void enqueue_step(Plan &p, Dev &d, const WS &w, void *vol, bool adj, hipS
   const dim3 block(p.bx, p.by), grid(A.nblocks);
   const KTime th_ev = ev ? KTime{ev[0], ev[1]} : KTime{}, te_ev = ev ? KTime{ev[2], ev[3]} : KTime{};
   const KTime *kh = ev ? &th_ev : nullptr, *ke = ev ? &te_ev : nullptr;
-  // magnetic receiver nodes: adjoint sources before the H update, the H
-  // transform after it (the E update does not touch H)
+  // magnetic receiver nodes: adjoint sources before the H update; under the
+  // fused schedule the H transform after the step (the E update does not
+  // touch H)
   const dim3 hgrid((p.ns * d.nh + 63) / 64), hblock(64);
   if (d.nh > 0 && adj)
     hipLaunchKernelGGL((k_hinj<T>), hgrid, hblock, 0, st, A, d.hn, d.nh, d.rn_c, d.rn_idx,
@@ -2425,13 +2505,12 @@ static void enqueue_step(Plan &p, Dev &d, const WS &w, void *vol, bool adj, hipS
     if (d.nh > 0)
       hipLaunchKernelGGL((k_hrec<T>), hgrid, hblock, 0, st, A, d.hn, d.nh, d.rn_c, d.rn_idx, d.zH);
   } else {
+    // the E update records the H receiver nodes itself (record_h)
     StepArgs<T> Ah = A;
     const Tiling th = tiling(p, true);
     set_grid(Ah, th.nbx, th.nby, th.nbz);
     const bool o4 = p.fd_order == 4;
     launch_h<T>(Ah, p.vxh, dim3(Ah.nblocks), block, st, kh, o4);
-    if (d.nh > 0)
-      hipLaunchKernelGGL((k_hrec<T>), hgrid, hblock, 0, st, A, d.hn, d.nh, d.rn_c, d.rn_idx, d.zH);
     launch_e<T>(A, p.kb, p.vx, p.acc, adj, false, grid, block, st, ke, o4);
   }
 }
