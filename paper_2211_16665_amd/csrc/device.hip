@@ -122,6 +122,7 @@ struct StepArgs {
   double2 *racc;        // [ns][nn][nf] receiver-node transforms
   int nn;               // receiver nodes
   const int *rn_c;      // [nn] component of each receiver node (3..5: H)
+  double dtmu64;        // dt / mu in double (magnetic sources)
   const double2 *zH;    // [nt][nf] z^{n+1/2} (H samples)
 };
 
@@ -328,15 +329,64 @@ __device__ __forceinline__ T ez_node(const StepArgs<T> &A, int i, int j, T e, T 
   return fma(c, d1 - d2, e);
 }
 
+template <typename T, int VX>
+__device__ __forceinline__ void inject_all(const StepArgs<T> &A, int lo, int hi, int s, int n,
+                                           double (&inj)[3 * VX]) {
+#pragma unroll
+  for (int q = 0; q < 3 * VX; ++q) inj[q] = 0.0;
+  for (int e = lo; e < hi; ++e) {
+    const int2 en = A.tl_ent[e];
+    if ((en.x & 4) || (en.x >> 9) != s) continue;           // kind 0 of this source
+    const int slot = (en.x & 3) * VX + ((en.x >> 3) & 63);
+    double cur = 0.0;
+#pragma unroll
+    for (int q = 0; q < 3 * VX; ++q) cur = q == slot ? inj[q] : cur;
+    const double *cf = A.coef + en.y;
+#pragma unroll 4
+    for (int r = 0; r < A.nrow; ++r) cur = fma(cf[r], A.Ftab[(int64_t)r * A.nt + n], cur);
+#pragma unroll
+    for (int q = 0; q < 3 * VX; ++q) inj[q] = q == slot ? cur : inj[q];
+  }
+}
+
+// This thread's slice of the H update's entry table (adjoint runs with
+// magnetic receivers, two-kernel schedule), or an empty one.
+template <typename T>
+__device__ __forceinline__ void h_entries(const StepArgs<T> &A, int b, int n, int &lo, int &hi) {
+  if (!A.tile_tab || n >= A.nt) return;
+  const int tt = A.tile_tab[b];
+  if (tt < 0) return;
+  const int slot = threadIdx.y * blockDim.x + threadIdx.x;
+  lo = A.tl_off[tt + slot];
+  hi = A.tl_off[tt + slot + 1];
+}
+
+// Magnetic adjoint source M'^n (Faraday row of eq. fictitiouswave) added to
+// H^{n-1/2} of the thread's own nodes before their update: the arithmetic
+// of k_hinj, (T)(H + (dt/mu) M'), on the values in registers.  Nodes with
+// no entry are left alone.
+template <typename T, int VX>
+__device__ __forceinline__ void inject_h(const StepArgs<T> &A, int lo, int hi, int s, int n,
+                                         Vec<T, VX> &hx, Vec<T, VX> &hy, Vec<T, VX> &hz) {
+  double inj[3 * VX];
+  inject_all<T, VX>(A, lo, hi, s, n, inj);
+#pragma unroll
+  for (int e = 0; e < VX; ++e) {
+    if (inj[e] != 0.0) hx.v[e] = (T)((double)hx.v[e] + A.dtmu64 * inj[e]);
+    if (inj[VX + e] != 0.0) hy.v[e] = (T)((double)hy.v[e] + A.dtmu64 * inj[VX + e]);
+    if (inj[2 * VX + e] != 0.0) hz.v[e] = (T)((double)hz.v[e] + A.dtmu64 * inj[2 * VX + e]);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // H update (two-kernel schedule): each thread owns VX consecutive x nodes
 // (one 16-byte vector per field); the x neighbour beyond the vector is one
 // extra element load.  All loads are issued before any store (loads and
 // stores share one in-order completion counter on this GPU).
 // ---------------------------------------------------------------------------
-template <typename T, int VX>
+template <typename T, int VX, bool INJ>
 __device__ __forceinline__ void h_vec(const StepArgs<T> &A, const Half<T> &I, const Half<T> &O,
-                                      int i0, int j, int k) {
+                                      int i0, int j, int k, int lo, int hi, int s, int n) {
   using V = Vec<T, VX>;
   const int PX = A.PX, NY = A.NY, npml = A.npml, W = 2 * npml;
   const int64_t plane = A.plane;
@@ -362,6 +412,8 @@ __device__ __forceinline__ void h_vec(const StepArgs<T> &A, const Half<T> &I, co
   V ps_hz_y = pyv ? vload<VX>(I.psY + 1 * sY + iY) : vzero<T, VX>();
   V ps_hx_z = pzv && j_in ? vload<VX>(I.psZ + 0 * sZ + iZ) : vzero<T, VX>();
   V ps_hy_z = pzv ? vload<VX>(I.psZ + 1 * sZ + iZ) : vzero<T, VX>();
+  if constexpr (INJ)
+    if (lo < hi) inject_h<T, VX>(A, lo, hi, s, n, hxv, hyv, hzv);
   // ---- compute ----
 #pragma unroll
   for (int e = 0; e < VX; ++e) {
@@ -398,16 +450,21 @@ __device__ __forceinline__ void h_vec(const StepArgs<T> &A, const Half<T> &I, co
   if (pzv) vstore(O.psZ + 1 * sZ + iZ, ps_hy_z);
 }
 
-template <typename T, int VX>
+// INJ: adjoint runs with magnetic receivers (the H update adds the magnetic
+// sources of its nodes); otherwise the plain update
+template <typename T, int VX, bool INJ>
 __global__ void __launch_bounds__(256) k_update_h(StepArgs<T> A) {
   int bx, by, bz, s;
-  tile_of(A, bx, by, bz, s);
-  const int par = (A.step[0] + 1) & 1;   // this step reads half par
+  const int b = tile_of(A, bx, by, bz, s);
+  const int n = A.step[0] + 1;
+  const int par = n & 1;                 // this step reads half par
   const int i0 = (bx * blockDim.x + threadIdx.x) * VX;
   const int j = by * blockDim.y + threadIdx.y;
   const int k = bz;
   if (i0 > A.nx || j > A.ny || k > A.nz) return;
-  h_vec<T, VX>(A, half_of(A, par, s), half_of(A, par ^ 1, s), i0, j, k);
+  int lo = 0, hi = 0;
+  if constexpr (INJ) h_entries(A, b, n, lo, hi);
+  h_vec<T, VX, INJ>(A, half_of(A, par, s), half_of(A, par ^ 1, s), i0, j, k, lo, hi, s, n);
 }
 
 // ---------------------------------------------------------------------------
@@ -674,25 +731,6 @@ __device__ __forceinline__ double inject_value(const StepArgs<T> &A, int lo, int
 // costs dependent memory round trips, and the threads of the receiver and
 // source tiles set the tail of the launch.
 template <typename T, int VX>
-__device__ __forceinline__ void inject_all(const StepArgs<T> &A, int lo, int hi, int s, int n,
-                                           double (&inj)[3 * VX]) {
-#pragma unroll
-  for (int q = 0; q < 3 * VX; ++q) inj[q] = 0.0;
-  for (int e = lo; e < hi; ++e) {
-    const int2 en = A.tl_ent[e];
-    if ((en.x & 4) || (en.x >> 9) != s) continue;           // kind 0 of this source
-    const int slot = (en.x & 3) * VX + ((en.x >> 3) & 63);
-    double cur = 0.0;
-#pragma unroll
-    for (int q = 0; q < 3 * VX; ++q) cur = q == slot ? inj[q] : cur;
-    const double *cf = A.coef + en.y;
-    for (int r = 0; r < A.nrow; ++r) cur = fma(cf[r], A.Ftab[(int64_t)r * A.nt + n], cur);
-#pragma unroll
-    for (int q = 0; q < 3 * VX; ++q) inj[q] = q == slot ? cur : inj[q];
-  }
-}
-
-template <typename T, int VX>
 __device__ __forceinline__ void record_all(const StepArgs<T> &A, int lo, int hi, int s, int n,
                                            const Vec<T, VX> (&e1)[3], const unsigned (&ok)[3],
                                            const Vec<T, VX> (&h)[3]) {
@@ -720,8 +758,11 @@ __device__ __forceinline__ void record_all(const StepArgs<T> &A, int lo, int hi,
       }
     if (!on) continue;
     const double v = (double)val;
-    double2 *a = A.racc + ((int64_t)s * A.nn + en.y) * A.nf;
-    const double2 *z = (c < 3 ? A.zE : A.zH) + (int64_t)n * A.nf;
+    // the sums and the twiddles never overlap: their loads can be issued
+    // together
+    double2 *__restrict__ a = A.racc + ((int64_t)s * A.nn + en.y) * A.nf;
+    const double2 *__restrict__ z = (c < 3 ? A.zE : A.zH) + (int64_t)n * A.nf;
+#pragma unroll 4
     for (int kf = 0; kf < A.nf; ++kf) {
       double2 x = a[kf];
       x.x = fma(v, z[kf].x, x.x);
@@ -922,11 +963,12 @@ __device__ __forceinline__ T d4_he(const T *f, int64_t base, int64_t st, int i, 
   return fma(T(-1.0 / 24.0), d - a, T(9.0 / 8.0) * (c - b));
 }
 
-template <typename T>
+template <typename T, bool INJ>
 __global__ void __launch_bounds__(256) k_update_h4(StepArgs<T> A) {
   int bx, by, bz, s;
-  tile_of(A, bx, by, bz, s);
-  const int par = (A.step[0] + 1) & 1;   // this step reads half par
+  const int b = tile_of(A, bx, by, bz, s);
+  const int n = A.step[0] + 1;
+  const int par = n & 1;                 // this step reads half par
   const int i = bx * blockDim.x + threadIdx.x;
   const int j = by * blockDim.y + threadIdx.y;
   const int k = bz;
@@ -945,11 +987,21 @@ __global__ void __launch_bounds__(256) k_update_h4(StepArgs<T> A) {
   const int64_t iY = ((int64_t)k * W + ly) * PX + i;
   const int64_t iZ = ((int64_t)lz * NY + j) * PX + i;
   const T zero = T(0);
+  // magnetic adjoint sources of this node (adjoint runs), else the stored H
+  int lo = 0, hi = 0;
+  if constexpr (INJ) h_entries(A, b, n, lo, hi);
+  Vec<T, 1> hxo = vec1(zero), hyo = vec1(zero), hzo = vec1(zero);
+  if (INJ && lo < hi) {
+    hxo = vec1(I.hx[q]);
+    hyo = vec1(I.hy[q]);
+    hzo = vec1(I.hz[q]);
+    inject_h<T, 1>(A, lo, hi, s, n, hxo, hyo, hzo);
+  }
   if (j_in && k_in) {                    // H_x = H_x - dt/mu (dEz/dy - dEy/dz)
     const T D1 = d4_eh(I.ez, (int64_t)k * plane + i, (int64_t)PX, j, A.ny);
     const T D2 = d4_eh(I.ey, (int64_t)j * PX + i, plane, k, A.nz);
     T psy = py ? I.psY[0 * sY + iY] : zero, psz = pz ? I.psZ[0 * sZ + iZ] : zero;
-    O.hx[q] = hx_node(A, j, k, I.hx[q], zero, D1, zero, D2, py, psy, pz, psz);
+    O.hx[q] = hx_node(A, j, k, lo < hi ? hxo.v[0] : I.hx[q], zero, D1, zero, D2, py, psy, pz, psz);
     if (py) O.psY[0 * sY + iY] = psy;
     if (pz) O.psZ[0 * sZ + iZ] = psz;
   }
@@ -957,7 +1009,7 @@ __global__ void __launch_bounds__(256) k_update_h4(StepArgs<T> A) {
     const T D1 = d4_eh(I.ex, (int64_t)j * PX + i, plane, k, A.nz);
     const T D2 = d4_eh(I.ez, (int64_t)k * plane + (int64_t)j * PX, (int64_t)1, i, A.nx);
     T psz = pz ? I.psZ[1 * sZ + iZ] : zero, psx = px ? I.psX[0 * sX + iX] : zero;
-    O.hy[q] = hy_node(A, i, k, I.hy[q], zero, D1, zero, D2, pz, psz, px, psx);
+    O.hy[q] = hy_node(A, i, k, lo < hi ? hyo.v[0] : I.hy[q], zero, D1, zero, D2, pz, psz, px, psx);
     if (pz) O.psZ[1 * sZ + iZ] = psz;
     if (px) O.psX[0 * sX + iX] = psx;
   }
@@ -965,7 +1017,7 @@ __global__ void __launch_bounds__(256) k_update_h4(StepArgs<T> A) {
     const T D1 = d4_eh(I.ey, (int64_t)k * plane + (int64_t)j * PX, (int64_t)1, i, A.nx);
     const T D2 = d4_eh(I.ex, (int64_t)k * plane + i, (int64_t)PX, j, A.ny);
     T psx = px ? I.psX[1 * sX + iX] : zero, psy = py ? I.psY[1 * sY + iY] : zero;
-    O.hz[q] = hz_node(A, i, j, I.hz[q], zero, D1, zero, D2, px, psx, py, psy);
+    O.hz[q] = hz_node(A, i, j, lo < hi ? hzo.v[0] : I.hz[q], zero, D1, zero, D2, px, psx, py, psy);
     if (px) O.psX[1 * sX + iX] = psx;
     if (py) O.psY[1 * sY + iY] = psy;
   }
@@ -1681,10 +1733,11 @@ __global__ void k_td_sens(T *adj, int64_t F, int ns, int nn, int nf, const int *
 //   k_hrec, after the fused step n: racc[s][node] += H^{n+1/2} z^{n+1/2}
 //     (eq. dtft transforms H' too; H^{n+1/2} is in half (n&1)^1).  The
 //     two-kernel schedule records in the E update instead (record_h).
-//   k_hinj, before the H update of step n (adjoint runs): H^{n-1/2} +=
-//     (dt/mu) M'^n with M'^n = sum_r coef[s][node][r] F[r][n], the magnetic
-//     current of the Faraday row (eq. fictitiouswave) acting at n dt; the H
-//     update then reads it from half n&1.
+//   k_hinj, before the fused step n (adjoint runs): H^{n-1/2} += (dt/mu)
+//     M'^n with M'^n = sum_r coef[s][node][r] F[r][n], the magnetic current
+//     of the Faraday row (eq. fictitiouswave) acting at n dt; the step then
+//     reads it from half n&1.  The two-kernel schedule adds it inside the H
+//     update instead (inject_h).
 template <typename T>
 __device__ __forceinline__ T *h_comp(const Half<T> &H, int c) {
   return c == 3 ? H.hx : (c == 4 ? H.hy : H.hz);
@@ -1873,10 +1926,11 @@ struct Dev {
   int *rcomp = nullptr;
   // adjoint injection coefficients (rebuilt per call)
   double *at_coef = nullptr;
-  // per-thread entry tables of the E update for the current tiling, forward
-  // (index 0) and adjoint (index 1); see build_lists
-  int *tile_tab[2] = {nullptr, nullptr}, *tl_off[2] = {nullptr, nullptr};
-  int2 *tl_ent[2] = {nullptr, nullptr};
+  // per-thread entry tables for the current tiling: the E update's forward
+  // (index 0) and adjoint (index 1) tables, and the H update's adjoint table
+  // of magnetic sources (index 2, two-kernel schedule); see build_lists
+  int *tile_tab[3] = {nullptr, nullptr, nullptr}, *tl_off[3] = {nullptr, nullptr, nullptr};
+  int2 *tl_ent[3] = {nullptr, nullptr, nullptr};
   std::string list_key;
   std::vector<DevBuf> list_bufs;
   double *cellfac = nullptr, *cellfac_v = nullptr;   // sigma_h V / 4, sigma_v V / 4
@@ -2163,15 +2217,15 @@ static Tiling tiling(const Plan &p, bool h_update = false) {
 // thread's vector, or the plane within the fused chunk), so that the E
 // update finds its own entries with two loads and no search.
 static void build_lists(Plan &p, Dev &d) {
-  const Tiling t = tiling(p);
   char key[128];
-  snprintf(key, sizeof key, "%d/%d/%d/%d/%d/%d/%llu", p.bx, p.by, p.vx, p.sched, p.kz, p.order,
-           (unsigned long long)p.model_version);
+  snprintf(key, sizeof key, "%d/%d/%d/%d/%d/%d/%d/%llu", p.bx, p.by, p.vx, p.vxh, p.sched, p.kz,
+           p.order, (unsigned long long)p.model_version);
   if (d.list_key == key) return;
   free_lists(d);
   const int nn = (int)p.rn_c.size(), nf = p.nf();
   const int slots = p.bx * p.by;
-  for (int mode = 0; mode < 2; ++mode) {
+  for (int mode = 0; mode < 3; ++mode) {
+    const Tiling t = tiling(p, mode == 2);   // mode 2 lives on the H update's grid
     struct E {
       int b, slot;
       int2 v;
@@ -2202,18 +2256,25 @@ static void build_lists(Plan &p, Dev &d) {
     if (mode == 0) {
       for (size_t q = 0; q < p.src_tg.size(); ++q)
         place(p.src_tg[q].c, 0, p.src_tg[q].s, p.src_tg[q].idx, (int)q);
-    } else {
+    } else if (mode == 1) {
       for (int s = 0; s < p.ns; ++s)
         for (int node = 0; node < nn; ++node)
           if (p.rn_c[node] < 3) place(p.rn_c[node], 0, s, p.rn_idx[node], (s * nn + node) * 2 * nf);
+    } else if (p.sched != 1) {
+      // magnetic adjoint sources M'^n, added by the H update (component c of
+      // H = rn_c - 3); the fused schedule uses k_hinj instead
+      for (int s = 0; s < p.ns; ++s)
+        for (int node = 0; node < nn; ++node)
+          if (p.rn_c[node] >= 3)
+            place(p.rn_c[node] - 3, 0, s, p.rn_idx[node], (s * nn + node) * 2 * nf);
     }
     // H receiver nodes: recorded by the E update (entry c = 3; the node's
-    // table gives the component), or by k_hrec under the fused schedule;
-    // their adjoint sources come from k_hinj
-    for (int node = 0; node < nn; ++node) {
-      if (p.rn_c[node] < 3) place(p.rn_c[node], 1, 0, p.rn_idx[node], node);
-      else if (p.sched != 1) place(3, 1, 0, p.rn_idx[node], node);
-    }
+    // table gives the component), or by k_hrec under the fused schedule
+    if (mode < 2)
+      for (int node = 0; node < nn; ++node) {
+        if (p.rn_c[node] < 3) place(p.rn_c[node], 1, 0, p.rn_idx[node], node);
+        else if (p.sched != 1) place(3, 1, 0, p.rn_idx[node], node);
+      }
     std::stable_sort(ents.begin(), ents.end(), [](const E &a, const E &b) {
       return a.b != b.b ? a.b < b.b : a.slot < b.slot;
     });
@@ -2335,6 +2396,7 @@ static StepArgs<T> make_args(Plan &p, Dev &d, const WS &w, void *vol, bool adj, 
   A.nn = (int)p.rn_c.size();
   A.rn_c = d.rn_c;
   A.zH = d.zH;
+  A.dtmu64 = p.dt / kMu0;
   return A;
 }
 
@@ -2472,11 +2534,17 @@ static void launch_step(const StepArgs<T> &A, int kb, int acc, bool adj, dim3 gr
 
 template <typename T>
 static void launch_h(const StepArgs<T> &A, int vx, dim3 grid, dim3 block, hipStream_t st,
-                     const KTime *kt = nullptr, bool o4 = false) {
+                     const KTime *kt = nullptr, bool o4 = false, bool inj = false) {
   constexpr int VV = (int)(16 / sizeof(T));
-  if (o4) go(k_update_h4<T>, grid, block, 0, st, kt, A);
-  else if (vx == 1) go(k_update_h<T, 1>, grid, block, 0, st, kt, A);
-  else go(k_update_h<T, VV>, grid, block, 0, st, kt, A);
+  if (inj) {
+    if (o4) go(k_update_h4<T, true>, grid, block, 0, st, kt, A);
+    else if (vx == 1) go(k_update_h<T, 1, true>, grid, block, 0, st, kt, A);
+    else go(k_update_h<T, VV, true>, grid, block, 0, st, kt, A);
+    return;
+  }
+  if (o4) go(k_update_h4<T, false>, grid, block, 0, st, kt, A);
+  else if (vx == 1) go(k_update_h<T, 1, false>, grid, block, 0, st, kt, A);
+  else go(k_update_h<T, VV, false>, grid, block, 0, st, kt, A);
 }
 
 // enqueue one step (H update, E update; or the fused step); if ev !=
@@ -2493,7 +2561,7 @@ static void enqueue_step(Plan &p, Dev &d, const WS &w, void *vol, bool adj, hipS
   // fused schedule the H transform after the step (the E update does not
   // touch H)
   const dim3 hgrid((p.ns * d.nh + 63) / 64), hblock(64);
-  if (d.nh > 0 && adj)
+  if (d.nh > 0 && adj && p.sched == 1)
     hipLaunchKernelGGL((k_hinj<T>), hgrid, hblock, 0, st, A, d.hn, d.nh, d.rn_c, d.rn_idx,
                        p.dt / kMu0);
   if (p.sched == 1) {
@@ -2505,12 +2573,17 @@ static void enqueue_step(Plan &p, Dev &d, const WS &w, void *vol, bool adj, hipS
     if (d.nh > 0)
       hipLaunchKernelGGL((k_hrec<T>), hgrid, hblock, 0, st, A, d.hn, d.nh, d.rn_c, d.rn_idx, d.zH);
   } else {
-    // the E update records the H receiver nodes itself (record_h)
+    // the E update records the H receiver nodes itself; in adjoint runs the
+    // H update adds the magnetic sources from its own entry table
     StepArgs<T> Ah = A;
     const Tiling th = tiling(p, true);
     set_grid(Ah, th.nbx, th.nby, th.nbz);
+    const bool hinj = adj && d.nh > 0;
+    Ah.tile_tab = hinj ? d.tile_tab[2] : nullptr;
+    Ah.tl_off = hinj ? d.tl_off[2] : nullptr;
+    Ah.tl_ent = hinj ? d.tl_ent[2] : nullptr;
     const bool o4 = p.fd_order == 4;
-    launch_h<T>(Ah, p.vxh, dim3(Ah.nblocks), block, st, kh, o4);
+    launch_h<T>(Ah, p.vxh, dim3(Ah.nblocks), block, st, kh, o4, hinj);
     launch_e<T>(A, p.kb, p.vx, p.acc, adj, false, grid, block, st, ke, o4);
   }
 }
