@@ -267,20 +267,28 @@ def magnetic_study(w_true, rho0, tuned, electric_s):
     vol = plan.volume_buffer()
     grad = torch.zeros(plan.shape, dtype=torch.float64, device="cuda")
 
+    plan.set_option(fw.FWD_OPT_SAMPLE_EVERY, 2048)
+    ks = []
+
     def step():
         plan.set_model(rho0)
         plan.basis_build(gamma_rel=1e-12)
         E, _ = plan.forward(vol=vol, want_volume=True)
+        ks.append(plan.kernel_stats())
         plan.adjoint(vol, d_obs - E, grad=grad)
+        ks.append(plan.kernel_stats())
 
     step()
+    ks.clear()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     step()
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
     out = {"receivers": "E_x, E_y, H_x, H_y", "gradient_s": t, "electric_gradient_s": electric_s,
-           "overhead": t / electric_s - 1.0, "rec_nodes": plan.info.n_rec_nodes}
+           "overhead": t / electric_s - 1.0, "rec_nodes": plan.info.n_rec_nodes,
+           "kernels_ms": {"update_h": {"fwd_ms": ks[0][0][0], "adj_ms": ks[1][0][0]},
+                          "update_e": {"fwd_ms": ks[0][0][1], "adj_ms": ks[1][0][1]}}}
     del plan, vol, grad
     torch.cuda.empty_cache()
     return out
