@@ -198,3 +198,4 @@ def test_magnetic_adjoint_graph_replay_and_checkpoint_bitwise():
     p.checkpoint_restore(snap)
     p.run_steps(nt - k)
     assert np.array_equal(p.run_receivers().cpu().numpy(), E_full)
+
