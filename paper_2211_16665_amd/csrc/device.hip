@@ -329,6 +329,11 @@ __device__ __forceinline__ T ez_node(const StepArgs<T> &A, int i, int j, T e, T 
   return fma(c, d1 - d2, e);
 }
 
+// One walk of a thread's entry list (entry format with inject_value below)
+// for every injection of kind 0 into its own nodes: per component c and
+// vector element e, slot c * VX + e, summed in entry order with the fused
+// multiply-adds of inject_value, so both give the same bits.  Used by the E
+// update (J') and, on its own grid, by the H update (magnetic M').
 template <typename T, int VX>
 __device__ __forceinline__ void inject_all(const StepArgs<T> &A, int lo, int hi, int s, int n,
                                            double (&inj)[3 * VX]) {
@@ -725,11 +730,10 @@ __device__ __forceinline__ double inject_value(const StepArgs<T> &A, int lo, int
 
 // The same walks done once per thread (two-kernel schedule): every thread
 // that owns entries makes one pass before the update for all injections
-// (per component c and vector element e, slot c * VX + e, summed in entry
-// order as inject_value does) and one pass after it for all records (E
-// nodes with E^{n+1} z^{n+1}, H nodes with H^{n+1/2} z^{n+1/2}).  Each walk
-// costs dependent memory round trips, and the threads of the receiver and
-// source tiles set the tail of the launch.
+// (inject_all, with the H update above) and one pass after it for all
+// records (E nodes with E^{n+1} z^{n+1}, H nodes with H^{n+1/2} z^{n+1/2}).
+// Each walk costs dependent memory round trips, and the threads of the
+// receiver and source tiles set the tail of the launch.
 template <typename T, int VX>
 __device__ __forceinline__ void record_all(const StepArgs<T> &A, int lo, int hi, int s, int n,
                                            const Vec<T, VX> (&e1)[3], const unsigned (&ok)[3],
