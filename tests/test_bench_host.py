@@ -1,0 +1,69 @@
+"""Host logic of bench.py: the one-GPU contract and the algorithmic-byte model
+of the roofline (counts of updated edges, H nodes and CPML memory variables
+checked against explicit loops over the lattices)."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+import bench
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def _in_int(i, n, npml):        # integer node inside a layer (interior nodes 1..n-1)
+    return npml > 0 and (i < npml or i > n - npml)
+
+
+def _in_half(i, n, npml):       # half node inside a layer (0..n-1)
+    return npml > 0 and (i < npml or i >= n - npml)
+
+
+@pytest.mark.parametrize("nx,ny,nz,npml", [(12, 10, 9, 3), (9, 11, 8, 0), (14, 12, 13, 4)])
+def test_e_update_byte_model(nx, ny, nz, npml):
+    tsize, accsize, kb, nf = 4, 16, 8, 3
+    edges = psi = 0
+    for k in range(nz + 1):
+        for j in range(ny + 1):
+            for i in range(nx + 1):
+                if i < nx and 1 <= j < ny and 1 <= k < nz:          # E_x: d/dy, d/dz
+                    edges += 1
+                    psi += _in_int(j, ny, npml) + _in_int(k, nz, npml)
+                if 1 <= i < nx and j < ny and 1 <= k < nz:          # E_y: d/dz, d/dx
+                    edges += 1
+                    psi += _in_int(k, nz, npml) + _in_int(i, nx, npml)
+                if 1 <= i < nx and 1 <= j < ny and k < nz:          # E_z: d/dx, d/dy
+                    edges += 1
+                    psi += _in_int(i, nx, npml) + _in_int(j, ny, npml)
+    per_edge = 4 * tsize + 2 * nf * accsize / kb + 2 * (kb - 2) * tsize / kb
+    b, e = bench.algorithmic_bytes_e_forward(nx, ny, nz, npml, nf, tsize, accsize, kb)
+    assert e == edges
+    assert b == int(edges * per_edge + psi * 2 * tsize)
+
+
+@pytest.mark.parametrize("nx,ny,nz,npml", [(12, 10, 9, 3), (9, 11, 8, 0)])
+def test_h_update_byte_model(nx, ny, nz, npml):
+    tsize = 4
+    hnodes = enodes = psi = 0
+    for k in range(nz + 1):
+        for j in range(ny + 1):
+            for i in range(nx + 1):
+                if j < ny and k < nz:                               # H_x: d/dy, d/dz
+                    hnodes += 1
+                    psi += _in_half(j, ny, npml) + _in_half(k, nz, npml)
+                if i < nx and k < nz:                               # H_y: d/dz, d/dx
+                    hnodes += 1
+                    psi += _in_half(k, nz, npml) + _in_half(i, nx, npml)
+                if i < nx and j < ny:                               # H_z: d/dx, d/dy
+                    hnodes += 1
+                    psi += _in_half(i, nx, npml) + _in_half(j, ny, npml)
+                enodes += (i < nx) + (j < ny) + (k < nz)            # every E node, read once
+    assert bench.algorithmic_bytes_h(nx, ny, nz, npml, tsize) == \
+        hnodes * 2 * tsize + enodes * tsize + psi * 2 * tsize
