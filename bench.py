@@ -39,14 +39,19 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 
 
-def algorithmic_bytes_e_forward(nx, ny, nz, npml, nf, tsize=4, accsize=16, kb=8):
-    """Algorithmic HBM bytes of one launch of the forward E update fused with
-    the volume transform, averaged over the kb-step cycle of the transform
-    block: per updated edge E read + write and dt/eps read (3 tsize), one H
-    value (tsize), the accumulator read-modify-write of nf complex values
-    once per cycle (2 nf accsize / kb), the history of the cycle (kb-2
-    samples written once and read once: 2 (kb-2) tsize / kb); a CPML memory
-    variable read + write (2 tsize) per derivative taken inside a layer."""
+def log(msg):
+    """Progress line on stderr (the JSON record is the only stdout line)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes_e(nx, ny, nz, npml, tsize=4, kb=8, hist=True):
+    """Algorithmic HBM bytes of one launch of the E update, averaged over the
+    kb-step cycle of the transform block: per updated edge E read + write
+    and dt/eps read (3 tsize), one H value (tsize), and, in runs with the
+    volume transform or the gradient product, the sample kept in the history
+    on kb-1 of kb steps ((kb-1) tsize / kb); a CPML memory variable read +
+    write (2 tsize) per derivative taken inside a layer.  Returns (bytes,
+    updated edges)."""
     n_ex = nx * (ny - 1) * (nz - 1)
     n_ey = (nx - 1) * ny * (nz - 1)
     n_ez = (nx - 1) * (ny - 1) * nz
@@ -59,9 +64,26 @@ def algorithmic_bytes_e_forward(nx, ny, nz, npml, nf, tsize=4, accsize=16, kb=8)
     # derivatives along y and z for E_x, x and z for E_y, x and y for E_z
     psi = (nx * py * (nz - 1) + nx * (ny - 1) * pz + px * ny * (nz - 1) + (nx - 1) * ny * pz
            + px * (ny - 1) * nz + (nx - 1) * py * nz)
-    hist = 2 * max(kb - 2, 0) * tsize / kb
-    per_edge = 4 * tsize + 2 * nf * accsize / kb + hist
-    return int(edges * per_edge + psi * 2 * tsize), edges
+    keep = (kb - 1) * tsize / kb if hist else 0.0
+    return int(edges * (4 * tsize + keep) + psi * 2 * tsize), edges
+
+
+def algorithmic_bytes_transform(edges, nf, tsize=4, accsize=16, kb=8, adjoint=False):
+    """Algorithmic HBM bytes of one launch of the block transform (once per
+    kb steps): per updated edge the block's kb samples (kb-1 from the
+    history, the newest from the fields) and the accumulators -- forward,
+    read + write of nf complex values (2 nf accsize); adjoint, a read of the
+    forward transform (nf accsize) and the FP64 gradient accumulator's read
+    + write (16)."""
+    acc = nf * accsize + 16 if adjoint else 2 * nf * accsize
+    return int(edges * (kb * tsize + acc))
+
+
+def algorithmic_bytes_e_forward(nx, ny, nz, npml, nf, tsize=4, accsize=16, kb=8):
+    """The E update and the block transform of the forward run together, per
+    step (the transform's bytes spread over its kb steps)."""
+    be, edges = algorithmic_bytes_e(nx, ny, nz, npml, tsize, kb, True)
+    return int(be + algorithmic_bytes_transform(edges, nf, tsize, accsize, kb) / kb), edges
 
 
 def algorithmic_bytes_h(nx, ny, nz, npml, tsize=4):
@@ -81,24 +103,131 @@ def algorithmic_bytes_h(nx, ny, nz, npml, tsize=4):
     return int((n_hx + n_hy + n_hz) * 2 * tsize + (n_ex + n_ey + n_ez) * tsize + psi * 2 * tsize)
 
 
-def cpu_baseline(w, steps=400):
-    """Oracle (NumPy FP64, single process) stepping the full grid of the
-    workload with the volume transform for a bounded window of steps."""
-    import oracle
-    from oracle.discretization import make_setup
+def host_cpu_model():
+    """The model line of the host CPU (lscpu's "Model name", else /proc/cpuinfo)."""
+    try:
+        import subprocess
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except Exception:
+        pass
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def host_cores():
+    """CPUs this process may run on, at most 16 (the host share of one GPU)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(n, 16))
+
+
+def cpu_slab(w, planes, k0=None):
+    """A slab of ``planes`` cell layers of workload ``w`` (full x-y extent)
+    holding its first source and the receivers nearest to it, with its own
+    absorbing layers: a bounded sample of the workload for the CPU oracle."""
+    nz = w.shape[0]
+    zs = float(w.src_pos[0, 2])
+    if k0 is None:
+        kc = int(np.searchsorted(w.z, zs)) - 1
+        k0 = max(0, min(nz - planes, kc - planes // 2))
+    z = w.z[k0:k0 + planes + 1]
+    inside = (w.rec_pos[:, 2] > z[w.npml + 1]) & (w.rec_pos[:, 2] < z[-w.npml - 2])
+    rec = w.rec_pos[inside]
+    d = np.hypot(rec[:, 0] - w.src_pos[0, 0], rec[:, 1] - w.src_pos[0, 1])
+    rec = rec[np.argsort(d)[:16]]
+    return w.replace(z=z, rho=np.ascontiguousarray(w.rho[k0:k0 + planes]),
+                     src_pos=w.src_pos[:1], src_mom=w.src_mom[:1], rec_pos=rec,
+                     name=f"{w.name}_slab{planes}")
+
+
+def _oracle_gradient_window(w, steps):
+    """Set up the oracle's gradient window on the one-source workload ``w``:
+    returns the setup and a function that runs it -- the forward run with the
+    volume transform of every frequency, then the adjoint run (basis-function
+    adjoint sources, adjoint volume transform) and the gradient product, over
+    ``steps`` steps each."""
+    from oracle.adjoint import adjoint_sources
+    from oracle.basis import basis_matrix, basis_pinv, gamma_from_rel
+    from oracle.discretization import dual_volumes, make_setup
     from oracle.stepping import receiver_nodes, run_stepping, source_injection
     s = make_setup(w, nt=steps)
-    inj = source_injection(s, w.src_pos[0], w.src_mom[0])
-    nodes, _ = receiver_nodes(s, w.rec_pos, w.rec_comp)
+
+    def run():
+        inj = source_injection(s, w.src_pos[0], w.src_mom[0])
+        nodes, interp = receiver_nodes(s, w.rec_pos, w.rec_comp)
+        acc, vol = run_stepping(s, inj, s.wavelet[None, :], nodes, True, steps)
+        resid = np.zeros((len(w.rec_pos), len(w.rec_comp), len(s.freqs)), dtype=np.complex128)
+        for r in range(len(w.rec_pos)):
+            for ci in range(len(w.rec_comp)):
+                resid[r, ci] = -sum(wt * acc[ni] for ni, wt in interp[r][ci]) * s.norm
+        B = basis_matrix(s.a, s.dt, steps)
+        b = basis_pinv(B, gamma_from_rel(B, 1e-12))
+        inj_a, ts, _ = adjoint_sources(s, w.rec_pos, w.rec_comp, resid, b)
+        _, v = run_stepping(s, inj_a, ts, [], True, steps)
+        corr = s.Omega / s.wprime
+        g = [np.real(np.einsum("k,k...->...", corr, v[c] * vol[c])) * dv
+             for c, dv in enumerate(dual_volumes(s))]
+        if not all(np.isfinite(x).all() for x in g):
+            raise RuntimeError("oracle window produced a non-finite gradient")
+
+    return s, run
+
+
+def _cpu_worker(w, steps, barrier, out):
+    """One process of the N-core leg: set up, wait for the others, run."""
+    s, run = _oracle_gradient_window(w, steps)
+    barrier.wait()
+    t0 = time.time()
+    run()
+    out.put((t0, time.time(), s.nx * s.ny * s.nz))
+
+
+def cpu_baseline(wname="c5_large", planes=24, steps=8):
+    """The CPU oracle (NumPy FP64) on a bounded sample of the workload: a slab
+    of ``planes`` cell layers (full x-y extent, one source, every frequency),
+    ``steps`` forward steps with the volume transform plus ``steps`` adjoint
+    steps with the gradient product -- the GPU's unit of work.  One process,
+    then one process per core, each on its own copy of the slab (the slabs
+    of a domain decomposition, with the halo exchange left out in the CPU's
+    favour), started together after a barrier.  Runs before the GPU is
+    touched (the worker processes are spawned)."""
+    import multiprocessing as mp
+    from workloads import by_name
+    w = cpu_slab(by_name(wname), planes)
+    s, run = _oracle_gradient_window(w, steps)
+    cells = s.nx * s.ny * s.nz
     t0 = time.perf_counter()
-    run_stepping(s, inj, s.wavelet[None, :], nodes, True, steps)
-    dt = time.perf_counter() - t0
-    ncells = s.nx * s.ny * s.nz
-    return {"value": ncells * steps / dt / 1e6, "unit": "Mcell-updates/s", "cores": 1,
-            "kind": "oracle",
-            "sample": f"{w.name}: full {s.nx}x{s.ny}x{s.nz} grid, {steps} forward steps with "
-                      f"the volume transform of {len(s.freqs)} frequencies, FP64 NumPy, "
-                      f"one process ({dt:.1f} s); host {os.cpu_count()} logical CPUs"}
+    run()
+    t1 = time.perf_counter() - t0
+    one = 2.0 * cells * steps / t1 / 1e6
+    n = host_cores()
+    ctx = mp.get_context("spawn")
+    barrier, out = ctx.Barrier(n), ctx.Queue()
+    procs = [ctx.Process(target=_cpu_worker, args=(w, steps, barrier, out)) for _ in range(n)]
+    for p in procs:
+        p.start()
+    res = [out.get(timeout=900) for _ in range(n)]
+    for p in procs:
+        p.join()
+    wall = max(r[1] for r in res) - min(r[0] for r in res)
+    many = 2.0 * sum(r[2] for r in res) * steps / wall / 1e6
+    return {"value": many, "unit": "Mcell-updates/s", "cores": n, "kind": "oracle",
+            "value_1core": one, "cpu_model": host_cpu_model(),
+            "sample": f"{wname}: slab of {planes} cell layers around the first source "
+                      f"({cells} cells, full x-y extent, every frequency), {steps} forward "
+                      f"steps with the volume transform + {steps} adjoint steps with the "
+                      f"gradient product, FP64 NumPy; one process {t1:.1f} s, then {n} "
+                      f"processes on one slab each {wall:.1f} s wall"}
 
 
 TILING_KEYS = ("SCHEDULE", "BLOCK_X", "BLOCK_Y", "XCD_REMAP", "VECTOR", "VECTOR_H", "TILE_ORDER",
@@ -112,11 +241,12 @@ def set_tiling(plan, spec):
             plan.set_option(getattr(fw, "FWD_OPT_" + key), int(v))
 
 
-def measured_traffic(kernel_tag):
-    """HBM bytes per launch of a kernel from the committed counter summary
-    (profiles/), or None if the device source changed since it was taken."""
+def measured_traffic(kernel_tag, summary):
+    """HBM bytes per launch of a kernel from a committed counter summary
+    (profiles/<summary>), or None if there is none, it covers another
+    kernel, or the device source changed since it was taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "pmc_marine1d_e_update.md")
+    path = os.path.join(ROOT, "profiles", summary)
     src = os.path.join(ROOT, "paper_2211_16665_amd", "csrc", "device.hip")
     if not os.path.exists(path):
         return None
@@ -195,21 +325,14 @@ def batched_vs_plain(window=200):
     t_tuned = time.perf_counter() - t0
     p.set_option(fw.FWD_OPT_SAMPLE_EVERY, 64)
     p.forward(vol=vol, want_volume=True)
-    (h_ms, e_ms), n_samp = p.kernel_stats()
-    bytes_e, edges = algorithmic_bytes_e_forward(nx, ny, nz, w.npml, len(w.freqs), 4, 16,
-                                                 int(p.get_option(fw.FWD_OPT_DFT_BLOCK)))
-    bytes_b = w.ns * bytes_e - (w.ns - 1) * edges * 4
-    bytes_h = w.ns * algorithmic_bytes_h(nx, ny, nz, w.npml, 4)
+    kern = kernel_records([p.kernel_stats()], w.ns, nx, ny, nz, w.npml, len(w.freqs), 4, 16,
+                          int(p.get_option(fw.FWD_OPT_DFT_BLOCK)), "F64")
     del vol
     return {"workload": f"c4_batched window: {nx}x{ny}x{nz}, {w.ns} sources, {len(w.freqs)} freqs, "
                         f"{window} forward + {window} adjoint steps",
             "batched_s": t_batched, "plain_s": t_plain, "speedup": t_plain / t_batched,
             "batched_tuned_s": t_tuned, "speedup_tuned": t_plain / t_tuned, "tuning": tuned,
-            "update_e_ms": e_ms, "update_h_ms": h_ms, "samples": n_samp,
-            "update_e_bytes_per_launch": bytes_b,
-            "update_e_algorithmic_gbs": bytes_b / (e_ms * 1e-3) / 1e9,
-            "update_e_frac_of_peak": bytes_b / (e_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-            "update_h_algorithmic_gbs": bytes_h / (h_ms * 1e-3) / 1e9,
+            "kernels_ms": kern,
             "batched_mcell_per_s": 2 * w.ns * nx * ny * nz * window / t_batched / 1e6,
             "max_rel_grad_diff": diff}
 
@@ -343,7 +466,8 @@ def magnetic_study(w_true, rho0, tuned, electric_s):
     out = {"receivers": "E_x, E_y, H_x, H_y", "gradient_s": t, "electric_gradient_s": electric_s,
            "overhead": t / electric_s - 1.0, "rec_nodes": plan.info.n_rec_nodes,
            "kernels_ms": {"update_h": {"fwd_ms": ks[0][0][0], "adj_ms": ks[1][0][0]},
-                          "update_e": {"fwd_ms": ks[0][0][1], "adj_ms": ks[1][0][1]}}}
+                          "update_e": {"fwd_ms": ks[0][0][1], "adj_ms": ks[1][0][1]},
+                          "transform": {"fwd_ms": ks[0][0][2], "adj_ms": ks[1][0][2]}}}
     del plan, vol, grad
     torch.cuda.empty_cache()
     return out
@@ -382,18 +506,14 @@ def order4_study(w_true, rho0, order2_s, tsize, accsize):
     t = time.perf_counter() - t0
     nz, ny, nx = plan.shape
     kb = int(plan.get_option(fw.FWD_OPT_DFT_BLOCK))
-    bytes_e, _ = algorithmic_bytes_e_forward(nx, ny, nz, w_true.npml, len(w_true.freqs),
-                                             tsize, accsize, kb)
-    bytes_h = algorithmic_bytes_h(nx, ny, nz, w_true.npml, tsize)
-    (h_ms, e_ms), n = ks[0]
+    kern = kernel_records(ks[:1], 1, nx, ny, nz, w_true.npml, len(w_true.freqs), tsize, accsize,
+                          kb, "F64")
     nt = plan.info.nt
     out = {"gradient_s": t, "order2_gradient_s": order2_s, "nt": nt, "dt": plan.info.dt,
            "mcell_per_s": 2.0 * nx * ny * nz * nt / t / 1e6,
            "tiling": {k.lower(): int(plan.get_option(getattr(fw, "FWD_OPT_" + k)))
                       for k in ("BLOCK_X", "BLOCK_Y", "XCD_REMAP", "TILE_ORDER")},
-           "update_e_ms": e_ms, "update_h_ms": h_ms, "samples": n,
-           "update_e_algorithmic_gbs": bytes_e / (e_ms * 1e-3) / 1e9,
-           "update_h_algorithmic_gbs": bytes_h / (h_ms * 1e-3) / 1e9}
+           "kernels_ms": kern}
     del plan, vol, grad
     torch.cuda.empty_cache()
     return out
@@ -423,162 +543,165 @@ def adjoint_td_study(plan, resid, grad_basis, basis_s, npml, segment=500):
             "rel_l2_vs_basis_outside_cpml": diff}
 
 
-def profile_mode(args, w_true):
-    """A short run for hardware-counter collection: one elementwise kernel of
-    a known size (256 MiB read + 256 MiB written, the calibration of the byte
-    counters), then a forward and an adjoint run of
-    ``profile_steps`` steps on the full grid of the workload."""
-    import torch
-    from paper_2211_16665_amd import fwdem as fw
-    n = 256 * 1024 * 1024 // 4
-    a = torch.ones(n, dtype=torch.float32, device="cuda")
-    b = torch.empty_like(a)
-    torch.cuda.synchronize()
-    torch.mul(a, 2.0, out=b)          # one elementwise kernel: 256 MiB read, 256 MiB written
-    torch.cuda.synchronize()
-    w = w_true.replace(nt=args.profile_steps)
-    plan = fw.Plan.from_workload(w, field_dtype=args.field_dtype, acc_mode=args.acc)
-    plan.set_option(fw.FWD_OPT_GRAPH_STEPS, 0)
-    set_tiling(plan, args.tiling)
-    plan.set_model(w.rho)
-    plan.basis_build(gamma_rel=1e-12)
-    E, vol = plan.forward(want_volume=True)
-    plan.adjoint(vol, -E)
-    torch.cuda.synchronize()
-    print(json.dumps({"profile_steps": args.profile_steps, "copy_bytes": 4 * n,
-                      "workload": w.name}), flush=True)
-
-
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--field-dtype", default="f32")
-    ap.add_argument("--acc", default="f64")
-    ap.add_argument("--sample-every", type=int, default=2048)
-    ap.add_argument("--no-batched", action="store_true",
-                    help="skip the batched-vs-plain gradient-time comparison")
-    ap.add_argument("--no-td", action="store_true",
-                    help="skip the time-domain adjoint study")
-    ap.add_argument("--no-vti", action="store_true",
-                    help="skip the VTI gradient timing")
-    ap.add_argument("--fd-order", type=int, default=2, choices=(2, 4),
-                    help="order of the staggered differences of the timed step")
-    ap.add_argument("--no-reciprocity", action="store_true",
-                    help="skip the towline study of the source-receiver swap")
-    ap.add_argument("--no-magnetic", action="store_true",
-                    help="skip the gradient step with magnetic receivers")
-    ap.add_argument("--no-order4", action="store_true",
-                    help="skip the fourth-order gradient timing")
-    ap.add_argument("--tiling", default="",
-                    help="fixed tiling instead of autotuning: block_x,block_y,xcd_remap,vector")
-    ap.add_argument("--profile-workload", default="marine", choices=("marine", "batched"),
-                    help="workload of the counter-collection mode")
-    ap.add_argument("--profile-steps", type=int, default=0,
-                    help="counter-collection mode: a 256 MiB device copy (calibration of the "
-                         "byte counters) then this many forward and adjoint steps of the "
-                         "workload; prints a short JSON line, no metric")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU: the path has no multi-GPU mode "
-              f"(--gpus {args.gpus} requested)", file=sys.stderr)
-        sys.exit(2)
-
-    import torch
-    from paper_2211_16665_amd import fwdem as fw
-    from workloads import c2_marine1d
-
-    assert torch.cuda.is_available(), "bench.py needs a HIP device"
-    torch.cuda.set_device(0)
-    w_true = c2_marine1d().replace(fd_order=args.fd_order)
-    if args.profile_steps > 0:
-        from workloads import c4_batched
-        profile_mode(args, c4_batched() if args.profile_workload == "batched" else w_true)
-        return
-    # background model of the step: the same column without the reservoir
-    rho0 = w_true.rho.copy()
+def background_model(w):
+    """The start model of the gradient step: the true model with its
+    100 ohm-m reservoir cells replaced by 1 ohm-m sediment."""
+    rho0 = w.rho.copy()
     rho0[rho0 == 100.0] = 1.0
-    plan = fw.Plan.from_workload(w_true, field_dtype=args.field_dtype, acc_mode=args.acc)
-    plan.set_model(w_true.rho)
-    d_obs = plan.forward()                               # data of the true model (untimed)
-    vol = plan.volume_buffer()
-    # tile/schedule autotuning on this workload (untimed setup)
+    return rho0
+
+
+def kernel_records(stats, ns, nx, ny, nz, npml, nf, tsize, accsize, kb, acc_tag):
+    """Per kernel of a forward step (H update, E update, block transform):
+    the average launch time over the sampled steps of the forward runs in
+    ``stats`` (kernel_stats() results), its algorithmic bytes per launch for
+    ``ns`` sources (dt/eps read once for all of them) and the time per step
+    (the block transform runs once in kb steps)."""
+    ok = [s_ for s_ in stats if s_[1] > 0]
+    ms = [float(np.mean([s_[0][k] for s_ in ok])) if ok else float("nan") for k in range(3)]
+    samples = sum(s_[1] for s_ in stats)
+    per_e, edges = algorithmic_bytes_e(nx, ny, nz, npml, tsize, kb, True)
+    t = "float" if tsize == 4 else "double"
+    out = {
+        "update_h": {"kernel": f"k_update_h<{t}>",
+                     "bytes_per_launch": ns * algorithmic_bytes_h(nx, ny, nz, npml, tsize),
+                     "avg_launch_ms": ms[0], "ms_per_step": ms[0]},
+        "update_e": {"kernel": f"k_update_e<{t},hist>",
+                     "bytes_per_launch": ns * per_e - (ns - 1) * edges * tsize,
+                     "avg_launch_ms": ms[1], "ms_per_step": ms[1]},
+        "transform": {"kernel": f"k_transform<{t},{acc_tag},fwd,{kb}>",
+                      "bytes_per_launch": ns * algorithmic_bytes_transform(edges, nf, tsize,
+                                                                           accsize, kb),
+                      "avg_launch_ms": ms[2], "ms_per_step": ms[2] / kb},
+    }
+    for v in out.values():
+        v["samples"] = samples
+        v["algorithmic_gbs"] = v["bytes_per_launch"] / (v["avg_launch_ms"] * 1e-3) / 1e9
+        v["frac_of_hbm_peak"] = v["algorithmic_gbs"] / HBM_PEAK_GBS
+    return out
+
+
+def source_groups(ns, per_source_bytes, free_bytes, frac=0.8):
+    """Split ``ns`` sources into groups of near-equal size whose workspace and
+    volume transform fit in ``frac`` of the free device memory."""
+    g = max(1, min(ns, int(frac * free_bytes // per_source_bytes)))
+    ng = -(-ns // g)
+    base, extra = divmod(ns, ng)
+    sizes = [base + (1 if i < extra else 0) for i in range(ng)]
+    out, s0 = [], 0
+    for n in sizes:
+        out.append((s0, s0 + n))
+        s0 += n
+    return out
+
+
+def large_window(args):
+    """The headline: one gradient window of the 400x400x200 workload (32M
+    cells, 8 frequencies, 32 x-dipoles, 400 seabed receivers).  The sources
+    run in groups sized to the device memory (one plan per group, all
+    sources of a group advanced together in every launch, one shared
+    workspace and volume buffer); a step is, for every group, the forward
+    run with the receiver and volume transforms, the residual against data
+    of the true model, and the adjoint run with the gradient product,
+    accumulated into one gradient.  The model, the basis functions and the
+    data are set up once, untimed (over a full-length run they are a
+    one-time cost; in a window they would be counted once per window)."""
+    import torch
+    from paper_2211_16665_amd import fwdem as fw
+    from workloads import c5_large, with_window
+    t_setup = time.perf_counter()
+    w = with_window(c5_large(), args.window)
+    acc = args.acc or w.acc_mode
+    rho0 = background_model(w)
+    # workspaces sized for the longer transform block (16 samples), so that
+    # the autotuner may choose either block
+    one = fw.Plan.from_workload(w.replace(src_pos=w.src_pos[:1], src_mom=w.src_mom[:1]),
+                                field_dtype=args.field_dtype, acc_mode=acc)
+    one.set_option(fw.FWD_OPT_DFT_BLOCK, 16)
+    one.set_model(w.rho)
+    per_src = one.workspace_size(fw.FWD_MODE_ADJOINT) + one.volume_size()
+    del one
+    free, total = torch.cuda.mem_get_info()
+    groups = source_groups(w.ns, per_src, free) if not args.group else \
+        [(a, min(a + args.group, w.ns)) for a in range(0, w.ns, args.group)]
+    plans = []
+    for a, b in groups:
+        wg = w.replace(src_pos=w.src_pos[a:b], src_mom=w.src_mom[a:b])
+        p = fw.Plan.from_workload(wg, field_dtype=args.field_dtype, acc_mode=acc)
+        p.set_option(fw.FWD_OPT_DFT_BLOCK, 16)
+        p.set_model(w.rho)
+        plans.append(p)
+    gmax = max(b - a for a, b in groups)
+    big = max(range(len(plans)), key=lambda i: groups[i][1] - groups[i][0])
+    ws = torch.empty(plans[big].workspace_size(fw.FWD_MODE_ADJOINT), dtype=torch.uint8,
+                     device="cuda")
+    vol = torch.empty(plans[big].volume_size(), dtype=torch.uint8, device="cuda")
+    for p in plans:
+        p.use_workspace(ws)
+    log(f"large workload: {len(groups)} groups {[b - a for a, b in groups]}, "
+        f"{per_src / 1e9:.1f} GB per source, {free / 1e9:.0f} GB free")
+    d_obs = [p.forward() for p in plans]            # data of the true model
     if args.tiling:
-        set_tiling(plan, args.tiling)
+        set_tiling(plans[big], args.tiling)
         tune_ms = float("nan")
     else:
-        tune_ms = plan.autotune(fw.FWD_MODE_FORWARD, vol=vol, steps=32)
-    tuned = {k.lower(): int(plan.get_option(getattr(fw, "FWD_OPT_" + k)))
+        tune_ms = plans[big].autotune(fw.FWD_MODE_FORWARD, vol=vol, steps=args.tune_steps)
+    tuned = {k.lower(): int(plans[big].get_option(getattr(fw, "FWD_OPT_" + k)))
              for k in TILING_KEYS + ("DFT_BLOCK",)}
+    for p in plans:
+        for k in TILING_KEYS + ("DFT_BLOCK",):
+            p.set_option(getattr(fw, "FWD_OPT_" + k), tuned[k.lower()])
+        p.set_model(rho0)
+        p.basis_build(gamma_rel=1e-12)
+        p.set_option(fw.FWD_OPT_SAMPLE_EVERY, args.sample_every)
     tuned["ms_per_forward_step"] = tune_ms
-    plan.set_option(fw.FWD_OPT_SAMPLE_EVERY, args.sample_every)
-    grad = torch.zeros(plan.shape, dtype=torch.float64, device="cuda")
-    stats = {"fwd": [], "adj": []}
-    resid_last = []
+    grad = torch.zeros(plans[0].shape, dtype=torch.float64, device="cuda")
+    stats = []
 
     def step():
-        plan.set_model(rho0)
-        plan.basis_build(gamma_rel=1e-12)
-        E, _ = plan.forward(vol=vol, want_volume=True)
-        stats["fwd"].append(plan.kernel_stats())
-        resid = d_obs - E
-        resid_last[:] = [resid]
-        plan.adjoint(vol, resid, grad=grad)
-        stats["adj"].append(plan.kernel_stats())
+        for gi, p in enumerate(plans):
+            E, _ = p.forward(vol=vol, want_volume=True)
+            if p is plans[big]:
+                stats.append(p.kernel_stats())
+            p.adjoint(vol, d_obs[gi] - E, grad=grad, accumulate=gi > 0)
 
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t_setup
+    log(f"setup {t_setup:.1f} s (tuning {tuned})")
     for _ in range(args.warmup):
         step()
-    stats = {"fwd": [], "adj": []}
+    stats.clear()
     torch.cuda.synchronize()
+    log("warm-up done")
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for i in range(args.steps):
         step()
+        if i % 5 == 4 or i == args.steps - 1:
+            log(f"step {i + 1}/{args.steps}")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-
-    info = plan.info
-    nz, ny, nx = plan.shape
+    if not torch.isfinite(grad).all():
+        raise RuntimeError("non-finite gradient")
+    nz, ny, nx = plans[0].shape
     ncells = nx * ny * nz
-    nt = info.nt
-    updates = 2.0 * plan.ns * ncells * nt * args.steps
-    value = updates / elapsed / 1e6
-
-    # roofline of the forward E update (dominant kernel)
-    def avg(key, k):
-        v = [s[0][k] for s in stats[key] if s[1] > 0]
-        n = sum(s[1] for s in stats[key])
-        return (float(np.mean(v)) if v else float("nan")), n
+    updates = 2.0 * w.ns * ncells * args.window * args.steps
     tsize = 4 if args.field_dtype == "f32" else 8
-    accsize = 8 if args.acc == "f32" else 16
-    kb = int(plan.get_option(fw.FWD_OPT_DFT_BLOCK))
-    bytes_e, edges = algorithmic_bytes_e_forward(nx, ny, nz, w_true.npml, len(w_true.freqs),
-                                                 tsize, accsize, kb)
-    bytes_h = algorithmic_bytes_h(nx, ny, nz, w_true.npml, tsize)
-    h_ms = avg("fwd", 0)[0]
-    e_ms, n_samp = avg("fwd", 1)
-    fused = tuned["schedule"] == 1
-    if fused:
-        # one launch per step: E and H each read once (no re-read of E by the
-        # H update nor of H by the E update)
-        n_cells_nodes = (nx + 1) * (ny + 1) * (nz + 1)
-        bytes_e = bytes_e + bytes_h - 2 * 3 * n_cells_nodes * tsize
-    achieved = bytes_e / (e_ms * 1e-3) / 1e9
-    tiling = ",".join(str(tuned[k.lower()]) for k in TILING_KEYS)
-    kernel_tag = (f"k_step<float,F64,fwd,{kb}>" if fused else
-                  f"k_update_e{'4' if args.fd_order == 4 else ''}<float,F64,fwd,{kb}>")
-    mt = measured_traffic(kernel_tag) if args.field_dtype == "f32" and args.acc == "f64" else None
-    traffic, traffic_tiling = mt if mt else (None, None)
-    kern = {name: {"fwd_ms": avg("fwd", k)[0], "adj_ms": avg("adj", k)[0]}
-            for k, name in enumerate(("update_h", "update_e"))}
-    if not fused:
-        kern["update_h"]["fwd_algorithmic_gbs"] = bytes_h / (h_ms * 1e-3) / 1e9
-        kern["update_h"]["bytes_per_launch"] = bytes_h
-    kern["update_e"]["fwd_algorithmic_gbs"] = achieved
+    accsize = 8 if acc == "f32" else 16
+    kb = tuned["dft_block"]
+    nf = len(w.freqs)
+    kern = kernel_records(stats, gmax, nx, ny, nz, w.npml, nf, tsize, accsize, kb, "KAHAN"
+                          if acc == "kahan" else acc.upper())
+    dom = max(kern, key=lambda k: kern[k]["ms_per_step"])
+    mt = measured_traffic(kern[dom]["kernel"], "pmc_large_e_update.md")
+    desc = (f"c5_large gradient window: 400x400x200 stretched grid (100 m core, ratio 1.05), "
+            f"random log-normal sediment (corr. 500 m) with a 100 ohm-m 2x2 km reservoir, "
+            f"8 freqs 0.1-2 Hz, {w.ns} x-dipoles in {len(groups)} groups of <= {gmax} "
+            f"(one plan per group, sources of a group batched in every launch), "
+            f"400 seabed receivers; {args.window} forward + {args.window} adjoint steps with "
+            f"receiver and volume transforms and the gradient product, summed over groups")
     out = {
         "metric": "Mcell-updates/s",
-        "value": value,
+        "value": updates / elapsed / 1e6,
         "unit": "Mcell-updates/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -589,37 +712,219 @@ def main():
         "vs_baseline": None,
         "dtype": args.field_dtype,
         "data": "synthetic",
-        "config": {"workload": "c2_marine1d gradient: 101x101x61 stretched grid (100 m core, "
-                               "ratio 1.05), air/0.3 ohm-m water/1 ohm-m sediment/100 ohm-m "
-                               "reservoir, 3 freqs 0.25-1.25 Hz, 1 x-dipole, 50 seabed receivers; "
-                               "forward + adjoint + gradient"
-                               + (", fourth-order differences" if args.fd_order == 4 else ""),
-                   "cells": ncells, "nt": nt, "dt": info.dt, "sources": plan.ns,
-                   "field_dtype": args.field_dtype, "accumulators": args.acc,
-                   "basis_fit": info.basis_fit, "tuning": tuned},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": kernel_tag, "tiling": tiling, "traffic_tiling": traffic_tiling,
-                     "bytes_per_launch": bytes_e, "avg_launch_ms": e_ms, "samples": n_samp},
+        "config": {"workload": desc, "cells": ncells, "window_steps": args.window,
+                   "dt": plans[0].info.dt, "sources": w.ns,
+                   "groups": [b - a for a, b in groups], "field_dtype": args.field_dtype,
+                   "accumulators": acc, "tuning": tuned,
+                   "setup_s": t_setup,
+                   "device_bytes_per_source": per_src},
+        "roofline": {"bound": "hbm", "achieved": kern[dom]["algorithmic_gbs"],
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": kern[dom]["algorithmic_gbs"] / HBM_PEAK_GBS,
+                     "traffic": mt[0] if mt else None, "kernel": kern[dom]["kernel"],
+                     "tiling": ",".join(str(tuned[k.lower()]) for k in TILING_KEYS),
+                     "sources_per_launch": gmax,
+                     "bytes_per_launch": kern[dom]["bytes_per_launch"],
+                     "avg_launch_ms": kern[dom]["avg_launch_ms"],
+                     "samples": kern[dom]["samples"]},
         "kernels_ms": kern,
     }
-    if not args.no_td:
-        out["adjoint_td"] = adjoint_td_study(plan, resid_last[0], grad, elapsed / args.steps,
-                                             w_true.npml)
-    if not args.no_vti:                 # changes the plan's model: after the studies above
-        out["vti"] = vti_study(plan, w_true, rho0, elapsed / args.steps)
-    if not args.no_order4 and args.fd_order == 2:
-        out["order4"] = order4_study(w_true, rho0, elapsed / args.steps, tsize, accsize)
-    if not args.no_magnetic and args.fd_order == 2 and args.field_dtype == "f32":
-        out["magnetic"] = magnetic_study(w_true, rho0, tuned, elapsed / args.steps)
+    del plans, ws, vol, grad
+    torch.cuda.empty_cache()
+    return out
+
+
+def marine_gradient(args):
+    """The full gradient of the 101x101x61 marine workload (every one of its
+    steps), the configuration the oracle checks end to end.  Its working set
+    (~110 MB) lives in the 256 MB Infinity Cache, so its roofline is that of
+    the last-level cache, not HBM.  Returns the record and what the studies
+    that reuse its plan need."""
+    import torch
+    from paper_2211_16665_amd import fwdem as fw
+    from workloads import c2_marine1d
+    w_true = c2_marine1d().replace(fd_order=args.fd_order)
+    rho0 = background_model(w_true)
+    plan = fw.Plan.from_workload(w_true, field_dtype=args.field_dtype, acc_mode=args.acc or "f64")
+    plan.set_model(w_true.rho)
+    d_obs = plan.forward()
+    vol = plan.volume_buffer()
+    tune_ms = plan.autotune(fw.FWD_MODE_FORWARD, vol=vol, steps=32)
+    tuned = {k.lower(): int(plan.get_option(getattr(fw, "FWD_OPT_" + k)))
+             for k in TILING_KEYS + ("DFT_BLOCK",)}
+    tuned["ms_per_forward_step"] = tune_ms
+    plan.set_option(fw.FWD_OPT_SAMPLE_EVERY, args.sample_every)
+    grad = torch.zeros(plan.shape, dtype=torch.float64, device="cuda")
+    stats = []
+    resid_last = []
+
+    def step():
+        plan.set_model(rho0)
+        plan.basis_build(gamma_rel=1e-12)
+        E, _ = plan.forward(vol=vol, want_volume=True)
+        stats.append(plan.kernel_stats())
+        resid = d_obs - E
+        resid_last[:] = [resid]
+        plan.adjoint(vol, resid, grad=grad)
+
+    step()
+    stats.clear()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.marine_steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = (time.perf_counter() - t0) / args.marine_steps
+    nz, ny, nx = plan.shape
+    nt = plan.info.nt
+    tsize = 4 if args.field_dtype == "f32" else 8
+    accsize = 8 if args.acc == "f32" else 16
+    kb = tuned["dft_block"]
+    kern = kernel_records(stats, 1, nx, ny, nz, w_true.npml, len(w_true.freqs), tsize, accsize,
+                          kb, "F64")
+    dom = max(kern, key=lambda k: kern[k]["ms_per_step"])
+    mt = measured_traffic(kern[dom]["kernel"], "pmc_marine1d_e_update.md")
+    out = {"workload": "c2_marine1d gradient: 101x101x61 stretched grid, 3 freqs, 1 x-dipole, "
+                       "50 seabed receivers; full forward + adjoint + gradient "
+                       "(setting the model and the basis functions included)",
+           "gradient_s": elapsed, "nt": nt, "cells": nx * ny * nz,
+           "mcell_per_s": 2.0 * nx * ny * nz * nt / elapsed / 1e6, "tuning": tuned,
+           "basis_fit": plan.info.basis_fit,
+           "roofline": {"bound": "llc", "achieved": kern[dom]["algorithmic_gbs"],
+                        "unit": "GB/s", "kernel": kern[dom]["kernel"],
+                        "bytes_per_launch": kern[dom]["bytes_per_launch"],
+                        "avg_launch_ms": kern[dom]["avg_launch_ms"],
+                        "frac_of_hbm_peak": kern[dom]["frac_of_hbm_peak"],
+                        "traffic": mt[0] if mt else None,
+                        "note": "working set ~110 MB, resident in the 256 MB Infinity Cache"},
+           "kernels_ms": kern}
+    return out, plan, w_true, rho0, resid_last[0], grad, vol, tuned
+
+
+def profile_mode(args):
+    """A short run for hardware-counter collection: one elementwise kernel of
+    a known size (256 MiB read + 256 MiB written, the calibration of the byte
+    counters), then a forward and an adjoint run of ``profile_steps`` steps
+    on the full grid of the workload (for the large workload: one group of
+    ``--group`` sources), with eager launches."""
+    import torch
+    from paper_2211_16665_amd import fwdem as fw
+    from workloads import c2_marine1d, c4_batched, c5_large
+    n = 256 * 1024 * 1024 // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    torch.mul(a, 2.0, out=b)          # one elementwise kernel: 256 MiB read, 256 MiB written
+    torch.cuda.synchronize()
+    del a, b
+    if args.profile_workload == "large":
+        w = c5_large()
+        g = args.group or 8
+        w = w.replace(src_pos=w.src_pos[:g], src_mom=w.src_mom[:g])
+    elif args.profile_workload == "batched":
+        w = c4_batched()
+    else:
+        w = c2_marine1d().replace(fd_order=args.fd_order)
+    w = w.replace(nt=args.profile_steps)
+    plan = fw.Plan.from_workload(w, field_dtype=args.field_dtype, acc_mode=args.acc or w.acc_mode)
+    plan.set_option(fw.FWD_OPT_GRAPH_STEPS, 0)
+    set_tiling(plan, args.tiling)
+    plan.set_model(w.rho)
+    plan.basis_build(gamma_rel=1e-12)
+    E, vol = plan.forward(want_volume=True)
+    plan.adjoint(vol, -E)
+    torch.cuda.synchronize()
+    print(json.dumps({"profile_steps": args.profile_steps, "copy_bytes": 4 * n,
+                      "workload": w.name, "sources": w.ns}), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--window", type=int, default=64,
+                    help="forward (and adjoint) steps of the large workload's gradient window")
+    ap.add_argument("--group", type=int, default=0,
+                    help="sources per plan of the large workload (0: sized to the memory)")
+    ap.add_argument("--tune-steps", type=int, default=16)
+    ap.add_argument("--marine-steps", type=int, default=3,
+                    help="timed full gradients of the marine workload (extra record)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--field-dtype", default="f32")
+    ap.add_argument("--acc", default="",
+                    help="volume accumulators f64 / kahan / f32 (default: the workload's)")
+    ap.add_argument("--sample-every", type=int, default=64)
+    ap.add_argument("--no-marine", action="store_true",
+                    help="skip the marine workload's full gradient and the studies built on it")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched-vs-plain gradient-time comparison")
+    ap.add_argument("--no-td", action="store_true",
+                    help="skip the time-domain adjoint study")
+    ap.add_argument("--no-vti", action="store_true",
+                    help="skip the VTI gradient timing")
+    ap.add_argument("--fd-order", type=int, default=2, choices=(2, 4),
+                    help="order of the staggered differences of the marine step")
+    ap.add_argument("--no-reciprocity", action="store_true",
+                    help="skip the towline study of the source-receiver swap")
+    ap.add_argument("--no-magnetic", action="store_true",
+                    help="skip the gradient step with magnetic receivers")
+    ap.add_argument("--no-order4", action="store_true",
+                    help="skip the fourth-order gradient timing")
+    ap.add_argument("--extras", default="all",
+                    help="'none' skips every extra record (marine, studies, CPU baseline)")
+    ap.add_argument("--tiling", default="",
+                    help="fixed tiling instead of autotuning: " + ",".join(TILING_KEYS).lower())
+    ap.add_argument("--profile-workload", default="large", choices=("large", "marine", "batched"),
+                    help="workload of the counter-collection mode")
+    ap.add_argument("--profile-steps", type=int, default=0,
+                    help="counter-collection mode: a 256 MiB device copy (calibration of the "
+                         "byte counters) then this many forward and adjoint steps of the "
+                         "workload; prints a short JSON line, no metric")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU: the path has no multi-GPU mode "
+              f"(--gpus {args.gpus} requested)", file=sys.stderr)
+        sys.exit(2)
+    if args.extras == "none":
+        args.no_cpu = args.no_marine = args.no_batched = args.no_reciprocity = True
+
+    # the CPU leg first: its worker processes are started before anything
+    # touches the GPU
+    cpu = None if args.no_cpu or args.profile_steps > 0 else cpu_baseline()
+    if cpu is not None:
+        log(f"CPU baseline: {cpu['value']:.1f} Mcell-updates/s on {cpu['cores']} cores")
+
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    torch.cuda.set_device(0)
+    if args.profile_steps > 0:
+        profile_mode(args)
+        return
+    out = large_window(args)
+    log(f"headline: {out['value']:.0f} Mcell-updates/s, {out['ms_per_step']:.0f} ms per step")
+    if not args.no_marine:
+        marine, plan, w_true, rho0, resid, grad, vol, tuned = marine_gradient(args)
+        out["marine1d"] = marine
+        base_s = marine["gradient_s"]
+        tsize = 4 if args.field_dtype == "f32" else 8
+        if not args.no_td:
+            out["adjoint_td"] = adjoint_td_study(plan, resid, grad, base_s, w_true.npml)
+        if not args.no_vti:             # changes the plan's model: after the studies above
+            out["vti"] = vti_study(plan, w_true, rho0, base_s)
+        del plan, vol, grad
+        torch.cuda.empty_cache()
+        if not args.no_order4 and args.fd_order == 2:
+            out["order4"] = order4_study(w_true, rho0, base_s, tsize, 16)
+        if not args.no_magnetic and args.fd_order == 2 and args.field_dtype == "f32":
+            out["magnetic"] = magnetic_study(w_true, rho0, tuned, base_s)
     if not args.no_batched:
-        del vol, grad
         torch.cuda.empty_cache()
         out["batched_vs_plain"] = batched_vs_plain()
     if not args.no_reciprocity:
         out["reciprocity"] = reciprocity_study()
-    if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(w_true)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 
 

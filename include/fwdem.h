@@ -282,9 +282,11 @@ enum {
                                 FWD_ERR_NONFINITE) */
   FWD_OPT_DFT_BLOCK = 6,     /* 1, 2, 4, 8 (default) or 16: samples per read-modify-write of the
                                 volume transform (and of the gradient product).  The E update
-                                holds the last two samples; the others wait in a history buffer
-                                of the workspace.  Changes only the order of the sums.  Set it
-                                before fwd_workspace_size. */
+                                keeps samples 1 .. K-1 of a block in a history buffer of the
+                                workspace; after the step whose sample closes the block, a
+                                block-transform launch sums the K samples (FP64) and adds them
+                                to the accumulators.  Changes only the order of the sums.  Set
+                                it before fwd_workspace_size. */
   FWD_OPT_VECTOR = 7,        /* 1 (default): each thread of the E update updates one x node;
                                 4: a 16-byte vector of consecutive x nodes (4 in FP32, 2 in
                                 FP64); two-kernel schedule only */
@@ -300,7 +302,7 @@ enum {
   FWD_OPT_VECTOR_H = 11,     /* as FWD_OPT_VECTOR, for the H update */
   FWD_OPT_VTI_GRADIENT = 12, /* 0 (default): gradients [nz][ny][nx], d / d ln rho; 1: [2][nz][ny][nx],
                                 d / d ln rho_h then d / d ln rho_v (see fwd_set_model_vti) */
-  FWD_OPT_FD_ORDER = 13      /* order of the staggered differences, 2 (default) or 4 (Section 2:
+  FWD_OPT_FD_ORDER = 13,     /* order of the staggered differences, 2 (default) or 4 (Section 2:
                                 the paper's engine is high order on the stretched grid).  Order
                                 4 uses the pair (9/8, -1/24) over the four nearest samples,
                                 divided by metric lengths from the same pair on the
@@ -309,14 +311,27 @@ enum {
                                 and the basis (call fwd_set_model again); order 4 runs the
                                 two-kernel schedule with vector widths 1 and rejects other
                                 SCHEDULE / VECTOR / VECTOR_H values. */
+  FWD_OPT_LEAN = 14          /* 1 (default): blocks of the two-kernel schedule whose tile lies
+                                inside the CPML layers' inner boundary take an update path with
+                                no CPML or wall logic; 0: every block takes the general path.
+                                The arithmetic per edge is the same: results are equal bit for
+                                bit. */
 };
 fwd_status fwd_set_option(fwd_plan *plan, int key, double value);
 fwd_status fwd_get_option(const fwd_plan *plan, int key, double *value);
 
-/* Self-written tile/schedule autotuner: times every candidate (schedule,
- * block shape, vector width or planes per block, XCD remap) for a few steps
- * of the given mode on the given buffers, keeps the fastest and returns its
- * time per step (ms).  The state in ws/vol is clobbered.  */
+/* Self-written tile/schedule autotuner.  A staged search on the given
+ * buffers: block shape, then vector widths, then tile order and XCD remap,
+ * then the fused schedule (shapes, planes per block), then the transform
+ * block FWD_OPT_DFT_BLOCK in {8, 16} when vol_dev is given and ws_bytes holds
+ * the workspace of the longer block.  Each candidate runs `steps` steps of
+ * the given mode untimed (graph capture) and then the same number timed; the
+ * fastest is kept (as options of the plan) and its time per step (ms)
+ * returned.  Results are cached for the life of the process, keyed by the
+ * grid, sources, frequencies, precisions, order, mode and `steps`: a second
+ * call with the same key only applies the cached choice.  The state in
+ * ws/vol is clobbered.  The workspace size may change with the transform
+ * block: query fwd_workspace_size again before the next run.  */
 fwd_status fwd_autotune(fwd_plan *plan, void *ws_dev, size_t ws_bytes,
                         void *vol_dev, size_t vol_bytes, int mode, int steps,
                         double *best_ms, void *stream);
@@ -326,14 +341,16 @@ fwd_status fwd_autotune(fwd_plan *plan, void *ws_dev, size_t ws_bytes,
  * milliseconds and number of steps. */
 fwd_status fwd_last_timing(const fwd_plan *plan, double *ms, int *steps);
 
-/* Average device time (ms) of the two kernels of one step -- H update, and
- * E update fused with injection, receiver transform and volume transform or
- * gradient product -- over the steps sampled in the last fwd_forward /
- * fwd_adjoint (FWD_OPT_SAMPLE_EVERY > 0), measured with HIP events on the
- * caller's stream that hipExtLaunchKernel stamps from each sampled kernel's
- * own dispatch (the kernel alone, as a kernel trace reports it).  With the
- * fused schedule the first value is 0 and the second is the one launch of
- * the step.  avg_ms has room for 2 values. */
+/* Average device time (ms) per launch of the kernels of a step over the
+ * steps sampled in the last fwd_forward / fwd_adjoint (FWD_OPT_SAMPLE_EVERY >
+ * 0): [0] H update, [1] E update (fused with injection and the receiver
+ * transform; it keeps each sample for the volume transform), [2] block
+ * transform (volume transform or gradient product of one transform block,
+ * averaged over the sampled steps that closed a block; 0 if none).  Measured
+ * with HIP events on the caller's stream that hipExtLaunchKernel stamps from
+ * each sampled kernel's own dispatch (the kernel alone, as a kernel trace
+ * reports it).  With the fused schedule [0] is 0 and [1] is the one launch
+ * of the step.  avg_ms has room for 3 values. */
 fwd_status fwd_kernel_stats(const fwd_plan *plan, double *avg_ms, int *samples);
 
 const char *fwd_last_error(void);

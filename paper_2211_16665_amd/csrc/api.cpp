@@ -334,6 +334,10 @@ fwd_status fwd_set_option(fwd_plan *h, int key, double value) {
           p.vxh = 1;
         }
         break;
+      case FWD_OPT_LEAN:
+        if (v != 0 && v != 1) fail(FWD_ERR_INVALID_ARG, "lean option in {0, 1}");
+        p.lean = v;
+        break;
       default:
         fail(FWD_ERR_INVALID_ARG, "unknown option");
     }
@@ -359,6 +363,7 @@ fwd_status fwd_get_option(const fwd_plan *h, int key, double *value) {
       case FWD_OPT_VECTOR_H: *value = p.vxh; break;
       case FWD_OPT_VTI_GRADIENT: *value = p.vti_grad; break;
       case FWD_OPT_FD_ORDER: *value = p.fd_order; break;
+      case FWD_OPT_LEAN: *value = p.lean; break;
       default: fail(FWD_ERR_INVALID_ARG, "unknown option");
     }
   });

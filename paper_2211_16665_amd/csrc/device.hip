@@ -39,6 +39,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -97,6 +99,9 @@ struct StepArgs {
   // tiling: (bx x by) threads over x-y; two kernels: one plane per block,
   // each thread a vector of x nodes; fused: kz planes per block
   int nbx, nby, nbz, nblocks, xcd, kz;   // nblocks = tiles * ns (the grid)
+  int lean;           // interior tiles take the lean paths (npml >= 1)
+  int kb;             // samples per transform block
+  FDiv dplane, dpx;   // node decode of the block transform (q -> k, j, i)
   int order;          // tile numbering: 0 x fastest, 1 z fastest
   FDiv dns, dnbx, dnby, dnbz;             // dividers of the block decode (set_grid)
   // strides, precomputed on the host: plane = NY PX; CPML slabs sX (x), sY
@@ -157,6 +162,32 @@ __device__ __forceinline__ int tile_of(const StepArgs<T> &A, int &bx, int &by, i
     bz = (int)u;
   }
   return (int)tile;
+}
+
+// Index of the step a launch computes: one uniform scalar load of the
+// counter the previous step wrote.  In the launch that ends a step, the
+// first thread of block 0 stores it in the other counter (no launch writes
+// a counter it reads, so no block waits on another).
+template <typename T>
+__device__ __forceinline__ int step_of(const StepArgs<T> &A, bool last_launch) {
+  const int n = A.step[0] + 1;
+  if (last_launch && blockIdx.x == 0 && threadIdx.x == 0 && threadIdx.y == 0) A.step_w[0] = n;
+  return n;
+}
+
+// This thread's slice [lo, hi) of its tile's entry list; empty for the
+// tiles without entries (most of them).  The tile's table index is one
+// uniform scalar load; callers ask for the slice after issuing their
+// stencil loads, so its round trip overlaps theirs.
+template <typename T>
+__device__ __forceinline__ void entry_slice(const StepArgs<T> &A, int b, int n, int &lo, int &hi) {
+  lo = hi = 0;
+  if (!A.tile_tab || n >= A.nt) return;   // no injection or recording past the run
+  const int tt = A.tile_tab[__builtin_amdgcn_readfirstlane(b)];
+  if (tt < 0) return;
+  const int slot = threadIdx.y * blockDim.x + threadIdx.x;
+  lo = A.tl_off[tt + slot];
+  hi = A.tl_off[tt + slot + 1];
 }
 
 // slab index of a CPML node: half nodes i+1/2 with i < npml or i >= n-npml;
@@ -354,18 +385,6 @@ __device__ __forceinline__ void inject_all(const StepArgs<T> &A, int lo, int hi,
   }
 }
 
-// This thread's slice of the H update's entry table (adjoint runs with
-// magnetic receivers, two-kernel schedule), or an empty one.
-template <typename T>
-__device__ __forceinline__ void h_entries(const StepArgs<T> &A, int b, int n, int &lo, int &hi) {
-  if (!A.tile_tab || n >= A.nt) return;
-  const int tt = A.tile_tab[b];
-  if (tt < 0) return;
-  const int slot = threadIdx.y * blockDim.x + threadIdx.x;
-  lo = A.tl_off[tt + slot];
-  hi = A.tl_off[tt + slot + 1];
-}
-
 // Magnetic adjoint source M'^n (Faraday row of eq. fictitiouswave) added to
 // H^{n-1/2} of the thread's own nodes before their update: the arithmetic
 // of k_hinj, (T)(H + (dt/mu) M'), on the values in registers.  Nodes with
@@ -383,26 +402,41 @@ __device__ __forceinline__ void inject_h(const StepArgs<T> &A, int lo, int hi, i
   }
 }
 
+// Interior tile of the two-kernel schedule (uniform per block): every node of
+// the block lies at least npml nodes from the low walls and npml + 1 from
+// the high ones (so it is no CPML node, and every H component and E edge it
+// owns is updated), on a plane of the same kind.  Such blocks take the lean
+// paths below; A.lean is off when npml == 0 (walls next to the interior).
+template <typename T>
+__device__ __forceinline__ bool interior_tile(const StepArgs<T> &A, int bx, int by, int k, int wx) {
+  const int wy = blockDim.y;
+  return A.lean && k >= A.npml && k < A.nz - A.npml && bx * wx >= A.npml &&
+         (bx + 1) * wx <= A.nx - A.npml && by * wy >= A.npml && (by + 1) * wy <= A.ny - A.npml;
+}
+
 // ---------------------------------------------------------------------------
 // H update (two-kernel schedule): each thread owns VX consecutive x nodes
 // (one 16-byte vector per field); the x neighbour beyond the vector is one
 // extra element load.  All loads are issued before any store (loads and
 // stores share one in-order completion counter on this GPU).
 // ---------------------------------------------------------------------------
-template <typename T, int VX, bool INJ>
+// LEAN: the block's tile is interior (see interior_tile): every lattice mask
+// and bounds test is true and no node is inside a CPML layer, as compile-time
+// constants; the per-node arithmetic is the same helpers' (same bits).
+template <typename T, int VX, bool INJ, bool LEAN>
 __device__ __forceinline__ void h_vec(const StepArgs<T> &A, const Half<T> &I, const Half<T> &O,
                                       int i0, int j, int k, int lo, int hi, int s, int n) {
   using V = Vec<T, VX>;
   const int PX = A.PX, NY = A.NY, npml = A.npml, W = 2 * npml;
   const int64_t plane = A.plane;
   const int64_t sX = A.sX, sY = A.sY, sZ = A.sZ;
-  const bool j_in = j < A.ny, k_in = k < A.nz;
+  const bool j_in = LEAN || j < A.ny, k_in = LEAN || k < A.nz;
   int ly = 0, lz = 0;
-  const bool py = npml > 0 && pml_half(j, A.ny, npml, ly);
-  const bool pz = npml > 0 && pml_half(k, A.nz, npml, lz);
+  const bool py = !LEAN && npml > 0 && pml_half(j, A.ny, npml, ly);
+  const bool pz = !LEAN && npml > 0 && pml_half(k, A.nz, npml, lz);
   const bool pyv = py && j_in, pzv = pz && k_in;
   const int64_t q = (int64_t)k * plane + (int64_t)j * PX + i0;
-  const bool nbr = i0 + VX <= A.nx;       // the x neighbour of the last element is used
+  const bool nbr = LEAN || i0 + VX <= A.nx;   // the x neighbour of the last element is used
   // ---- loads ----
   const V ex0 = vload<VX>(I.ex + q), ey0 = vload<VX>(I.ey + q), ez0 = vload<VX>(I.ez + q);
   const V exk = k_in ? vload<VX>(I.ex + q + plane) : vzero<T, VX>();
@@ -423,13 +457,13 @@ __device__ __forceinline__ void h_vec(const StepArgs<T> &A, const Half<T> &I, co
 #pragma unroll
   for (int e = 0; e < VX; ++e) {
     const int i = i0 + e;
-    const bool i_in = i < A.nx;
+    const bool i_in = LEAN || i < A.nx;
     const T ey_ip = e + 1 < VX ? ey0.v[(e + 1) % VX] : eyn;
     const T ez_ip = e + 1 < VX ? ez0.v[(e + 1) % VX] : ezn;
     int lx = 0;
-    const bool px = npml > 0 && i_in && pml_half(i, A.nx, npml, lx);
+    const bool px = !LEAN && npml > 0 && i_in && pml_half(i, A.nx, npml, lx);
     const int64_t iX = ((int64_t)k * NY + j) * W + lx;
-    if (i <= A.nx && j_in && k_in)
+    if (LEAN || (i <= A.nx && j_in && k_in))
       hxv.v[e] = hx_node(A, j, k, hxv.v[e], ez0.v[e], ezj.v[e], ey0.v[e], eyk.v[e], py,
                          ps_hx_y.v[e], pz, ps_hx_z.v[e]);
     if (i_in && k_in) {
@@ -461,51 +495,25 @@ template <typename T, int VX, bool INJ>
 __global__ void __launch_bounds__(256) k_update_h(StepArgs<T> A) {
   int bx, by, bz, s;
   const int b = tile_of(A, bx, by, bz, s);
-  const int n = A.step[0] + 1;
+  const int n = step_of(A, false);
   const int par = n & 1;                 // this step reads half par
   const int i0 = (bx * blockDim.x + threadIdx.x) * VX;
   const int j = by * blockDim.y + threadIdx.y;
   const int k = bz;
   if (i0 > A.nx || j > A.ny || k > A.nz) return;
   int lo = 0, hi = 0;
-  if constexpr (INJ) h_entries(A, b, n, lo, hi);
-  h_vec<T, VX, INJ>(A, half_of(A, par, s), half_of(A, par ^ 1, s), i0, j, k, lo, hi, s, n);
+  if constexpr (INJ) entry_slice(A, b, n, lo, hi);
+  if (interior_tile(A, bx, by, k, blockDim.x * VX))
+    h_vec<T, VX, INJ, true>(A, half_of(A, par, s), half_of(A, par ^ 1, s), i0, j,
+                            __builtin_amdgcn_readfirstlane(k), lo, hi, s, n);
+  else
+    h_vec<T, VX, INJ, false>(A, half_of(A, par, s), half_of(A, par ^ 1, s), i0, j, k, lo, hi, s, n);
 }
 
 // ---------------------------------------------------------------------------
 // accumulator flavours for the volume transform acc += E z (eq. dft)
 // ---------------------------------------------------------------------------
 enum { ACC_NONE = 0, ACC_F64 = 1, ACC_KAHAN = 2, ACC_F32 = 3 };
-
-template <int ACC>
-__device__ __forceinline__ void acc_add(void *base, int64_t idx, double2 x) {
-  if constexpr (ACC == ACC_F64) {
-    double2 *p = reinterpret_cast<double2 *>(base) + idx;
-    double2 v = *p;
-    v.x += x.x;
-    v.y += x.y;
-    *p = v;
-  } else if constexpr (ACC == ACC_KAHAN) {
-    // compensated single precision: (hi, lo) per real component, the sum is
-    // hi - lo (Kahan's running compensation)
-    float4 *p = reinterpret_cast<float4 *>(base) + idx;
-    float4 v = *p;
-    const float xr = (float)x.x, xi = (float)x.y;
-    float yr = xr - v.z, tr = v.x + yr;
-    v.z = (tr - v.x) - yr;
-    v.x = tr;
-    float yi = xi - v.w, ti = v.y + yi;
-    v.w = (ti - v.y) - yi;
-    v.y = ti;
-    *p = v;
-  } else if constexpr (ACC == ACC_F32) {
-    float2 *p = reinterpret_cast<float2 *>(base) + idx;
-    float2 v = *p;
-    v.x += (float)x.x;
-    v.y += (float)x.y;
-    *p = v;
-  }
-}
 
 template <int ACC>
 __device__ __forceinline__ double2 acc_read(const void *base, int64_t idx) {
@@ -520,10 +528,11 @@ __device__ __forceinline__ double2 acc_read(const void *base, int64_t idx) {
   }
 }
 
-// Accumulator flavours as load / add / store, so that a closing step can
-// issue all its loads before any store (loads and stores share one in-order
-// completion counter: a load behind a store waits for the store).  The add
-// is the same arithmetic as acc_add.
+// Accumulator flavours as load / add / store, so that the block transform
+// can issue all its loads before any store (loads and stores share one
+// in-order completion counter: a load behind a store waits for the store).
+// Compensated FP32 keeps (hi, lo) per real component, the sum being hi - lo
+// (Kahan's running compensation).
 template <int ACC>
 struct Acc;
 template <>
@@ -584,126 +593,25 @@ struct Acc<ACC_F32> {
   }
 };
 
-// After the E update of the three components at q .. q+VX-1 (old values
-// e0[c] = sample m-1, new values e1[c] = sample m, m = n+1): the transform
-// over a block of KB samples is added in one read-modify-write when the
-// block closes (m % KB == 0); samples with m % KB in 1..KB-2 wait in the
-// history buffer, the sample with m % KB == KB-1 is the old value of the
-// closing step.  KB = 1 adds every sample as it comes.  Forward: volume
-// transform acc_k += sum E z_k^m (eq. dft).  Adjoint: gedge += sum_m u^m
-// Re(sum_k Q_k^m V_k), the gradient product of eq. gradsigmaij accumulated
-// over time (Q on the host).  Samples at or before *flushed were already
-// added by a flush.  Elements outside a component's lattice (ok bit clear)
-// are skipped.  A closing step loads the whole history first, and per
-// frequency the twiddles once for the three components and the three
-// accumulators before their stores, so the memory round trips do not
-// serialise.
-template <typename T, int ACC, bool ADJ, int KB, int VX>
-__device__ __forceinline__ void post_e(const StepArgs<T> &A, int s, int64_t q,
-                                       const Vec<T, VX> (&e0)[3], const Vec<T, VX> (&e1)[3],
-                                       const unsigned (&ok)[3], int n, int fl,
-                                       const double2 *__restrict__ tw) {
-  if constexpr (ACC != ACC_NONE) {
-    if (!(ok[0] | ok[1] | ok[2]) || n >= A.nt) return;   // steps past the run add nothing
-    const int nf = A.nf;
-    const int m = n + 1;
-    const int r = m & (KB - 1);
-    const int64_t F = A.F, F3 = 3 * A.F;
-    T *h = A.hist + (int64_t)s * A.hist_src + q;
-    if constexpr (KB > 1) {
-      if (r != 0) {
-        if (r <= KB - 2) {
+// After the E update of the three components at q .. q+VX-1 (new values e1
+// = sample m = n+1 of eq. dft): the samples of the current transform block
+// wait in the history buffer until the block closes (m % KB == 0); sample
+// m with m % KB = r (1 .. KB-1) goes to slot r-1.  The closing sample stays
+// in the field buffer, where the block transform k_transform reads it.
+// Elements outside a component's lattice (ok bit clear) keep garbage that
+// k_transform never reads; steps past the run keep nothing.
+template <typename T, int VX>
+__device__ __forceinline__ void hist_store(const StepArgs<T> &A, int s, int64_t q,
+                                           const Vec<T, VX> (&e1)[3], const unsigned (&ok)[3],
+                                           int n) {
+  const int kb = A.kb;
+  if (kb <= 1 || n >= A.nt || !(ok[0] | ok[1] | ok[2])) return;
+  const int r = (n + 1) & (kb - 1);
+  if (r == 0) return;
+  T *h = A.hist + (int64_t)s * A.hist_src + q + (int64_t)(r - 1) * 3 * A.F;
 #pragma unroll
-          for (int c = 0; c < 3; ++c)
-            if (ok[c]) vstore(h + c * F + (int64_t)(r - 1) * F3, e1[c]);
-        }
-        return;
-      }
-    }
-    // the KB samples of the block: m-KB+1 .. m; zE / Q index = sample - 1.
-    // History and accumulators span every node of the padded layout, so
-    // they are loaded without the lattice masks (which would split the
-    // loads into one masked round trip each); only stores are masked.
-    Vec<T, VX> hv[3][KB > 2 ? KB - 2 : 1];
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-#pragma unroll
-      for (int t = 0; t < KB - 2; ++t) hv[c][t] = vload<VX>(h + c * F + (int64_t)t * F3);
-    const int first = m - KB + 1;
-    const int64_t base = (int64_t)s * nf * F3 + q;   // + (kf * 3 + c) F + e
-#pragma unroll
-    for (int e = 0; e < VX; ++e) {
-      bool on[3];
-#pragma unroll
-      for (int c = 0; c < 3; ++c) on[c] = (ok[c] >> e) & 1u;
-      if (!(on[0] | on[1] | on[2])) continue;
-      // the samples in the field type; those already added by a flush are
-      // zeroed with a select (the condition is the same for every thread)
-      T val[3][KB];
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-#pragma unroll
-        for (int t = 0; t < KB - 2; ++t) val[c][t] = hv[c][t].v[e];
-        if constexpr (KB >= 2) val[c][KB - 2] = e0[c].v[e];
-        val[c][KB - 1] = e1[c].v[e];
-#pragma unroll
-        for (int t = 0; t < KB; ++t) val[c][t] = first + t <= fl ? T(0) : val[c][t];
-      }
-      if constexpr (!ADJ) {
-        using Ac = Acc<ACC>;
-        for (int kf = 0; kf < nf; ++kf) {
-          double2 z[KB];
-#pragma unroll
-          for (int t = 0; t < KB; ++t) z[t] = tw[(int64_t)(first - 1 + t) * nf + kf];
-          typename Ac::S a[3];
-#pragma unroll
-          for (int c = 0; c < 3; ++c) a[c] = Ac::load(A.vol, base + (int64_t)(kf * 3 + c) * F + e);
-#pragma unroll
-          for (int c = 0; c < 3; ++c) {
-            if (!on[c]) continue;
-            double2 sum = make_double2(0.0, 0.0);
-#pragma unroll
-            for (int t = 0; t < KB; ++t) {
-              sum.x = fma((double)val[c][t], z[t].x, sum.x);
-              sum.y = fma((double)val[c][t], z[t].y, sum.y);
-            }
-            Ac::store(A.vol, base + (int64_t)(kf * 3 + c) * F + e, Ac::add(a[c], sum));
-          }
-        }
-      } else {
-        // per frequency Re(S V) with S = sum_t u^t Q^t, formed from the
-        // samples and Q while the forward transform V is loading
-        using Ac = Acc<ACC>;
-        double re[3] = {0.0, 0.0, 0.0};
-        for (int kf = 0; kf < nf; ++kf) {
-          double2 v[3];
-#pragma unroll
-          for (int c = 0; c < 3; ++c)
-            v[c] = Ac::value(Ac::load(A.vol, base + (int64_t)(kf * 3 + c) * F + e));
-          double2 Qt[KB];
-#pragma unroll
-          for (int t = 0; t < KB; ++t) Qt[t] = tw[(int64_t)(first - 1 + t) * nf + kf];
-#pragma unroll
-          for (int c = 0; c < 3; ++c) {
-            double sx = 0.0, sy = 0.0;
-#pragma unroll
-            for (int t = 0; t < KB; ++t) {
-              sx = fma((double)val[c][t], Qt[t].x, sx);
-              sy = fma((double)val[c][t], Qt[t].y, sy);
-            }
-            re[c] = fma(sx, v[c].x, fma(-sy, v[c].y, re[c]));
-          }
-        }
-        double *g = A.gedge + (int64_t)s * F3 + q + e;
-        double g0[3];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) g0[c] = g[c * F];
-#pragma unroll
-        for (int c = 0; c < 3; ++c)
-          if (on[c]) g[c * F] = g0[c] + re[c];
-      }
-    }
-  }
+  for (int c = 0; c < 3; ++c)
+    if (ok[c]) vstore(h + c * A.F, e1[c]);
 }
 
 // per-thread list walk.  Entry x = c | kind << 2 | sub << 3 | s << 9, where
@@ -802,37 +710,40 @@ __device__ __forceinline__ void record(const StepArgs<T> &A, int lo, int hi, int
 // VX consecutive x nodes; the x neighbour before the vector is one extra
 // element load; all stencil loads precede the stores.
 // ---------------------------------------------------------------------------
-template <typename T, int ACC, bool ADJ, int KB, int VX>
-__device__ __forceinline__ void e_vec(const StepArgs<T> &A, int s, const Half<T> &I,
+template <typename T, bool HIST, int VX, bool LEAN>
+__device__ __forceinline__ void e_vec(const StepArgs<T> &A, int s, int b, const Half<T> &I,
                                       const Half<T> &O, const Half<T> &P, int i0, int j, int k,
-                                      int n, int fl, int lo, int hi,
-                                      const double2 *__restrict__ tw) {
+                                      int n) {
   using V = Vec<T, VX>;
   const int PX = A.PX, NY = A.NY, npml = A.npml, W = 2 * npml;
   const int64_t plane = A.plane;
   const int64_t sX = A.sX, sY = A.sY, sZ = A.sZ;
-  const bool j_int = j >= 1 && j < A.ny, k_int = k >= 1 && k < A.nz;
-  const bool j_in = j < A.ny, k_in = k < A.nz;
+  const bool j_int = LEAN || (j >= 1 && j < A.ny), k_int = LEAN || (k >= 1 && k < A.nz);
+  const bool j_in = LEAN || j < A.ny, k_in = LEAN || k < A.nz;
   int ly = 0, lz = 0;
-  const bool py = npml > 0 && pml_int(j, A.ny, npml, ly);
-  const bool pz = npml > 0 && pml_int(k, A.nz, npml, lz);
+  const bool py = !LEAN && npml > 0 && pml_int(j, A.ny, npml, ly);
+  const bool pz = !LEAN && npml > 0 && pml_int(k, A.nz, npml, lz);
   const int64_t q = (int64_t)k * plane + (int64_t)j * PX + i0;
   // lattice masks per element
   unsigned okx = 0, oky = 0, okz = 0;
+  if constexpr (LEAN) {
+    okx = oky = okz = (1u << VX) - 1u;
+  } else {
 #pragma unroll
-  for (int e = 0; e < VX; ++e) {
-    const int i = i0 + e;
-    if (i < A.nx && j_int && k_int) okx |= 1u << e;
-    if (i >= 1 && i < A.nx && j_in && k_int) oky |= 1u << e;
-    if (i >= 1 && i < A.nx && j_int && k_in) okz |= 1u << e;
+    for (int e = 0; e < VX; ++e) {
+      const int i = i0 + e;
+      if (i < A.nx && j_int && k_int) okx |= 1u << e;
+      if (i >= 1 && i < A.nx && j_in && k_int) oky |= 1u << e;
+      if (i >= 1 && i < A.nx && j_int && k_in) okz |= 1u << e;
+    }
   }
   // ---- loads ----
   const V hx0 = vload<VX>(O.hx + q), hy0 = vload<VX>(O.hy + q), hz0 = vload<VX>(O.hz + q);
-  const V hzj = j >= 1 ? vload<VX>(O.hz + q - PX) : vzero<T, VX>();
-  const V hxj = j >= 1 ? vload<VX>(O.hx + q - PX) : vzero<T, VX>();
-  const V hyk = k >= 1 ? vload<VX>(O.hy + q - plane) : vzero<T, VX>();
-  const V hxk = k >= 1 ? vload<VX>(O.hx + q - plane) : vzero<T, VX>();
-  const T hzp = i0 >= 1 ? O.hz[q - 1] : T(0), hyp = i0 >= 1 ? O.hy[q - 1] : T(0);
+  const V hzj = LEAN || j >= 1 ? vload<VX>(O.hz + q - PX) : vzero<T, VX>();
+  const V hxj = LEAN || j >= 1 ? vload<VX>(O.hx + q - PX) : vzero<T, VX>();
+  const V hyk = LEAN || k >= 1 ? vload<VX>(O.hy + q - plane) : vzero<T, VX>();
+  const V hxk = LEAN || k >= 1 ? vload<VX>(O.hx + q - plane) : vzero<T, VX>();
+  const T hzp = LEAN || i0 >= 1 ? O.hz[q - 1] : T(0), hyp = LEAN || i0 >= 1 ? O.hy[q - 1] : T(0);
   const V e0x = vload<VX>(I.ex + q), e0y = vload<VX>(I.ey + q), e0z = vload<VX>(I.ez + q);
   const V cx = okx ? vload<VX>(A.ce + q) : vzero<T, VX>();
   const V cy = oky ? vload<VX>(A.ce + A.F + q) : vzero<T, VX>();
@@ -843,6 +754,8 @@ __device__ __forceinline__ void e_vec(const StepArgs<T> &A, int s, const Half<T>
   V ps_ez_y = py && okz ? vload<VX>(P.psY + 3 * sY + iY) : vzero<T, VX>();
   V ps_ex_z = pz && okx ? vload<VX>(P.psZ + 2 * sZ + iZ) : vzero<T, VX>();
   V ps_ey_z = pz && oky ? vload<VX>(P.psZ + 3 * sZ + iZ) : vzero<T, VX>();
+  int lo, hi;
+  entry_slice(A, b, n, lo, hi);
   double inj[3 * VX];
   if (lo < hi) inject_all<T, VX>(A, lo, hi, s, n, inj);
   // ---- compute ----
@@ -850,11 +763,11 @@ __device__ __forceinline__ void e_vec(const StepArgs<T> &A, int s, const Half<T>
 #pragma unroll
   for (int e = 0; e < VX; ++e) {
     const int i = i0 + e;
-    const bool i_int = i >= 1 && i < A.nx;
+    const bool i_int = LEAN || (i >= 1 && i < A.nx);
     const T hz_im = e > 0 ? hz0.v[(e + VX - 1) % VX] : hzp;
     const T hy_im = e > 0 ? hy0.v[(e + VX - 1) % VX] : hyp;
     int lx = 0;
-    const bool px = npml > 0 && i_int && pml_int(i, A.nx, npml, lx);
+    const bool px = !LEAN && npml > 0 && i_int && pml_int(i, A.nx, npml, lx);
     const int64_t iX = ((int64_t)k * NY + j) * W + lx;
     if ((okx >> e) & 1u) {
       T v = ex_node(A, j, k, e0x.v[e], cx.v[e], hz0.v[e], hzj.v[e], hy0.v[e], hyk.v[e], py,
@@ -892,42 +805,32 @@ __device__ __forceinline__ void e_vec(const StepArgs<T> &A, int s, const Half<T>
     const unsigned ok[3] = {okx, oky, okz};
     record_all<T, VX>(A, lo, hi, s, n, e1, ok, hh);
   }
-  // ---- volume transform / gradient product ----
-  {
-    const Vec<T, VX> e0[3] = {e0x, e0y, e0z}, e1[3] = {e1x, e1y, e1z};
+  // ---- the sample's place in the transform block ----
+  if constexpr (HIST) {
+    const Vec<T, VX> e1[3] = {e1x, e1y, e1z};
     const unsigned ok[3] = {okx, oky, okz};
-    post_e<T, ACC, ADJ, KB, VX>(A, s, q, e0, e1, ok, n, fl, tw);
+    hist_store<T, VX>(A, s, q, e1, ok, n);
   }
 }
 
-template <typename T, int ACC, bool ADJ, int KB, int VX>
-__global__ void __launch_bounds__(256) k_update_e(StepArgs<T> A,
-                                                  const double2 *__restrict__ tw) {
-  __shared__ int s_n;
+// HIST: the run takes the volume transform (forward) or the gradient
+// product (adjoint): each sample is kept for the block transform
+template <typename T, bool HIST, int VX>
+__global__ void __launch_bounds__(256) k_update_e(StepArgs<T> A) {
   int bx, by, bz, s;
   const int b = tile_of(A, bx, by, bz, s);
-  if (threadIdx.x == 0 && threadIdx.y == 0) {
-    s_n = A.step[0] + 1;
-    if (blockIdx.x == 0) A.step_w[0] = s_n;   // the step this launch completes
-  }
-  __syncthreads();
-  const int n = s_n;
+  const int n = step_of(A, true);        // this launch completes step n
   const int i0 = (bx * blockDim.x + threadIdx.x) * VX;
   const int j = by * blockDim.y + threadIdx.y;
   const int k = bz;
   if (i0 <= A.nx && j <= A.ny && k <= A.nz) {
-    const int fl = A.flushed[0];
-    // this thread's slice of the tile's entry table (if the tile has one)
-    const int tt = A.tile_tab[b];
-    int lo = 0, hi = 0;
-    if (tt >= 0 && n < A.nt) {   // no injection or recording past the run
-      const int slot = threadIdx.y * blockDim.x + threadIdx.x;
-      lo = A.tl_off[tt + slot];
-      hi = A.tl_off[tt + slot + 1];
-    }
     const int par = n & 1;
-    e_vec<T, ACC, ADJ, KB, VX>(A, s, half_of(A, par, s), half_of(A, par ^ 1, s), half_of(A, 0, s),
-                               i0, j, k, n, fl, lo, hi, tw);
+    if (interior_tile(A, bx, by, k, blockDim.x * VX))
+      e_vec<T, HIST, VX, true>(A, s, b, half_of(A, par, s), half_of(A, par ^ 1, s),
+                               half_of(A, 0, s), i0, j, __builtin_amdgcn_readfirstlane(k), n);
+    else
+      e_vec<T, HIST, VX, false>(A, s, b, half_of(A, par, s), half_of(A, par ^ 1, s),
+                                half_of(A, 0, s), i0, j, k, n);
   }
 }
 
@@ -971,7 +874,7 @@ template <typename T, bool INJ>
 __global__ void __launch_bounds__(256) k_update_h4(StepArgs<T> A) {
   int bx, by, bz, s;
   const int b = tile_of(A, bx, by, bz, s);
-  const int n = A.step[0] + 1;
+  const int n = step_of(A, false);
   const int par = n & 1;                 // this step reads half par
   const int i = bx * blockDim.x + threadIdx.x;
   const int j = by * blockDim.y + threadIdx.y;
@@ -993,7 +896,7 @@ __global__ void __launch_bounds__(256) k_update_h4(StepArgs<T> A) {
   const T zero = T(0);
   // magnetic adjoint sources of this node (adjoint runs), else the stored H
   int lo = 0, hi = 0;
-  if constexpr (INJ) h_entries(A, b, n, lo, hi);
+  if constexpr (INJ) entry_slice(A, b, n, lo, hi);
   Vec<T, 1> hxo = vec1(zero), hyo = vec1(zero), hzo = vec1(zero);
   if (INJ && lo < hi) {
     hxo = vec1(I.hx[q]);
@@ -1027,30 +930,17 @@ __global__ void __launch_bounds__(256) k_update_h4(StepArgs<T> A) {
   }
 }
 
-template <typename T, int ACC, bool ADJ, int KB>
-__global__ void __launch_bounds__(256) k_update_e4(StepArgs<T> A,
-                                                   const double2 *__restrict__ tw) {
-  __shared__ int s_n;
+template <typename T, bool HIST>
+__global__ void __launch_bounds__(256) k_update_e4(StepArgs<T> A) {
   int bx, by, bz, s;
   const int b = tile_of(A, bx, by, bz, s);
-  if (threadIdx.x == 0 && threadIdx.y == 0) {
-    s_n = A.step[0] + 1;
-    if (blockIdx.x == 0) A.step_w[0] = s_n;   // the step this launch completes
-  }
-  __syncthreads();
-  const int n = s_n;
+  const int n = step_of(A, true);        // this launch completes step n
   const int i = bx * blockDim.x + threadIdx.x;
   const int j = by * blockDim.y + threadIdx.y;
   const int k = bz;
   if (i > A.nx || j > A.ny || k > A.nz) return;
-  const int fl = A.flushed[0];
-  const int tt = A.tile_tab[b];
-  int lo = 0, hi = 0;
-  if (tt >= 0 && n < A.nt) {
-    const int slot = threadIdx.y * blockDim.x + threadIdx.x;
-    lo = A.tl_off[tt + slot];
-    hi = A.tl_off[tt + slot + 1];
-  }
+  int lo, hi;
+  entry_slice(A, b, n, lo, hi);
   const int par = n & 1;
   const Half<T> I = half_of(A, par, s), O = half_of(A, par ^ 1, s), P = half_of(A, 0, s);
   const int PX = A.PX, NY = A.NY, npml = A.npml, W = 2 * npml;
@@ -1115,10 +1005,10 @@ __global__ void __launch_bounds__(256) k_update_e4(StepArgs<T> A,
     const unsigned ok[3] = {okx ? 1u : 0u, oky ? 1u : 0u, okz ? 1u : 0u};
     record_all<T, 1>(A, lo, hi, s, n, e1, ok, hh);
   }
-  {
-    const Vec<T, 1> e0[3] = {e0x, e0y, e0z}, e1[3] = {e1x, e1y, e1z};
+  if constexpr (HIST) {
+    const Vec<T, 1> e1[3] = {e1x, e1y, e1z};
     const unsigned ok[3] = {okx ? 1u : 0u, oky ? 1u : 0u, okz ? 1u : 0u};
-    post_e<T, ACC, ADJ, KB, 1>(A, s, q, e0, e1, ok, n, fl, tw);
+    hist_store<T, 1>(A, s, q, e1, ok, n);
   }
 }
 
@@ -1149,10 +1039,9 @@ __device__ __forceinline__ T ld(const StepArgs<T> &A, const T *f, int i, int j, 
              : T(0);
 }
 
-template <typename T, int ACC, bool ADJ, int KB>
+template <typename T, bool HIST>
 __global__ void __launch_bounds__(256) k_step(StepArgs<T> A) {
   extern __shared__ double lds_raw[];
-  __shared__ int s_n;
   const int BX = blockDim.x, BY = blockDim.y;
   const int WE = BX + 2, WH = BX + 1;
   const int SE = WE * (BY + 2), SH = WH * (BY + 1);
@@ -1164,20 +1053,9 @@ __global__ void __launch_bounds__(256) k_step(StepArgs<T> A) {
   const int x0 = tbx * BX, y0 = tby * BY;
   const int i = x0 + tx, j = y0 + ty;
   const int z0 = tbz * A.kz, z1 = min(z0 + A.kz, A.nz);
-  if (tx == 0 && ty == 0) {
-    s_n = A.step[0] + 1;
-    if (blockIdx.x == 0) A.step_w[0] = s_n;   // the step this launch completes
-  }
-  __syncthreads();
-  const int n = s_n, par = n & 1;
-  const int fl = A.flushed[0];
-  const int tt = A.tile_tab[b];
-  int lo = 0, hi = 0;
-  if (tt >= 0 && n < A.nt) {   // no injection or recording past the run
-    const int slot = ty * BX + tx;
-    lo = A.tl_off[tt + slot];
-    hi = A.tl_off[tt + slot + 1];
-  }
+  const int n = step_of(A, true), par = n & 1;   // this launch completes step n
+  int lo, hi;
+  entry_slice(A, b, n, lo, hi);
   const int npml = A.npml, W = 2 * npml, PX = A.PX, NY = A.NY;
   const int64_t sX = A.sX, sY = A.sY, sZ = A.sZ;
   // column geometry of the own node and of the low-side halo nodes
@@ -1391,11 +1269,10 @@ __global__ void __launch_bounds__(256) k_step(StepArgs<T> A) {
           if (oky) record(A, lo, hi, s, 1, sub, n, (double)eyn);
           if (okz) record(A, lo, hi, s, 2, sub, n, (double)ezn);
         }
-        {
-          const Vec<T, 1> e0[3] = {vec1(ex), vec1(ey), vec1(ez)};
+        if constexpr (HIST) {
           const Vec<T, 1> e1[3] = {vec1(exn), vec1(eyn), vec1(ezn)};
           const unsigned ok[3] = {okx ? 1u : 0u, oky ? 1u : 0u, okz ? 1u : 0u};
-          post_e<T, ACC, ADJ, KB, 1>(A, s, q, e0, e1, ok, n, fl, ADJ ? A.Q : A.zE);
+          hist_store<T, 1>(A, s, q, e1, ok, n);
         }
       }
       // ---- carry to the next plane ----
@@ -1410,50 +1287,113 @@ __global__ void __launch_bounds__(256) k_step(StepArgs<T> A) {
   }
 }
 
-// Flush: add the samples of the incomplete last block (m_last % KB != 0)
-// that are newer than *flushed; the caller then moves *flushed to m_last
-// with k_set_flushed.  One thread per node of the padded layout.  The last
-// sample E^{m_last} sits in half m_last % 2.
-template <typename T, int ACC, bool ADJ, int KB>
-__global__ void __launch_bounds__(256) k_flush(StepArgs<T> A) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y;
-  const int k = blockIdx.z;
-  if (i > A.nx) return;
-  const int m_last = A.step[0] + 1;
+// Block transform (eq. dft, KB samples per read-modify-write of the
+// accumulators).  Launched after the E update whose sample m_last closes a
+// block (FLUSH false: m_last % KB == 0, the KB samples m_last-KB+1 ..
+// m_last), or to add an incomplete last block (FLUSH true: the m_last % KB
+// newest samples; the caller then moves *flushed to m_last).  Samples at or
+// before *flushed were added by an earlier flush and samples past the run
+// are zero.  The block's samples are in history slots 0 .. cnt-2 and, the
+// newest, in the field half m_last % 2.
+//   forward  acc_k += sum_t E^{first+t} z_k^{first+t}, the sum over the
+//            block formed in FP64 first, then added in the accumulator's
+//            precision
+//   adjoint  gedge += sum_k Re(S_k V_k), S_k = sum_t u^t Q_k^t: the
+//            gradient product of eq. gradsigmaij over the block, V the
+//            forward transform (Q on the host)
+// One thread per node of the padded layout (grid x), source (grid y) and
+// E component (grid z); threads off the component's lattice return.  A
+// thread holds only its KB samples; the block's twiddles (all frequencies)
+// are staged once in LDS and read as broadcasts.
+template <typename T, int ACC, bool ADJ, int KB, bool FLUSH>
+__global__ void __launch_bounds__(256) k_transform(StepArgs<T> A) {
+  extern __shared__ double2 s_tw[];          // [nf][KB] twiddles of the block
+  const int s = blockIdx.y, c = blockIdx.z;
+  const int m_last = A.step[0] + 1;          // the newest sample
   const int r_end = m_last & (KB - 1);
-  if (KB == 1 || r_end == 0) return;
-  const int fl = A.flushed[0];
-  const int64_t q = ((int64_t)k * A.NY + j) * A.PX + i;
-  const bool ok[3] = {i < A.nx && j >= 1 && j < A.ny && k >= 1 && k < A.nz,
-                      i >= 1 && i < A.nx && j < A.ny && k >= 1 && k < A.nz,
-                      i >= 1 && i < A.nx && j >= 1 && j < A.ny && k < A.nz};
-  const int nf = A.nf;
-  for (int s = 0; s < A.ns; ++s) {
-    const T *f = A.fields + (m_last & 1) * A.fbuf + (int64_t)s * 6 * A.F;
-    for (int c = 0; c < 3; ++c) {
-      if (!ok[c]) continue;
-      double g = 0.0;
-      const T *h = A.hist + (int64_t)s * A.hist_src + (int64_t)c * A.F + q;
-      const int64_t base = ((int64_t)s * nf * 3 + c) * A.F + q;
-      for (int rr = 1; rr <= r_end; ++rr) {
-        const int mm = m_last - r_end + rr;
-        if (mm <= fl || mm > A.nt) continue;
-        const double v = rr <= KB - 2 ? (double)h[(int64_t)(rr - 1) * 3 * A.F]
-                                      : (double)f[(int64_t)c * A.F + q];
-        for (int kf = 0; kf < nf; ++kf) {
-          if constexpr (!ADJ) {
-            const double2 z = A.zE[(int64_t)(mm - 1) * nf + kf];
-            acc_add<ACC>(A.vol, base + (int64_t)kf * 3 * A.F, make_double2(v * z.x, v * z.y));
-          } else {
-            const double2 Vk = acc_read<ACC>(A.vol, base + (int64_t)kf * 3 * A.F);
-            const double2 Qt = A.Q[(int64_t)(mm - 1) * nf + kf];
-            g += v * (Qt.x * Vk.x - Qt.y * Vk.y);
-          }
-        }
-      }
-      if constexpr (ADJ) A.gedge[((int64_t)s * 3 + c) * A.F + q] += g;
+  const int cnt = FLUSH ? r_end : KB;
+  if (FLUSH ? cnt == 0 : r_end != 0) return; // uniform: the whole grid returns
+  const int nf = A.nf, nt = A.nt, first = m_last - cnt + 1;
+  {
+    const double2 *tw = ADJ ? A.Q : A.zE;
+    for (int e = threadIdx.x; e < nf * KB; e += blockDim.x) {
+      const int kf = e / KB, t = e - kf * KB;
+      s_tw[e] = t < cnt ? tw[(int64_t)(first - 1 + t) * nf + kf] : make_double2(0.0, 0.0);
     }
+  }
+  __syncthreads();
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= A.F) return;
+  const uint32_t qq = (uint32_t)q;
+  const uint32_t k = fdiv(qq, A.dplane), rem = qq - k * (uint32_t)A.plane;
+  const uint32_t j = fdiv(rem, A.dpx), i = rem - j * (uint32_t)A.PX;
+  const bool iin = i < (uint32_t)A.nx, jin = j < (uint32_t)A.ny, kin = k < (uint32_t)A.nz;
+  const bool ii = i >= 1 && iin, ji = j >= 1 && jin, ki = k >= 1 && kin;
+  const bool on = c == 0 ? iin && ji && ki : (c == 1 ? ii && jin && ki : ii && ji && kin);
+  if (!on) return;
+  const int fl = A.flushed[0];
+  const int64_t F = A.F, F3 = 3 * A.F;
+  const T *h = A.hist + (int64_t)s * A.hist_src + (int64_t)c * F + q;
+  const T *f = A.fields + ((m_last & 1) ? A.fbuf : 0) + (int64_t)s * A.F6 + (int64_t)c * F + q;
+  // the samples in the field type; those outside (fl, nt] are zeroed with a
+  // select (the condition is the same for every thread)
+  T val[KB];
+#pragma unroll
+  for (int t = 0; t < KB; ++t) {
+    T v = T(0);
+    if (t < cnt - 1) v = h[(int64_t)t * F3];
+    else if (t == cnt - 1) v = f[0];
+    const int idx = first + t;
+    val[t] = idx <= fl || idx > nt ? T(0) : v;
+  }
+  const int64_t base = ((int64_t)s * nf * 3 + c) * F + q;    // + kf * 3 F
+  using Ac = Acc<ACC>;
+  if constexpr (!ADJ) {
+    // two frequencies at a time: both accumulators are loaded before either
+    // store (loads and stores share one in-order completion counter)
+    auto block_sum = [&](int kf) {
+      const double2 *z = s_tw + kf * KB;
+      double2 sum = make_double2(0.0, 0.0);
+#pragma unroll
+      for (int t = 0; t < KB; ++t) {
+        if (t >= cnt) break;
+        const double2 zt = z[t];
+        sum.x = fma((double)val[t], zt.x, sum.x);
+        sum.y = fma((double)val[t], zt.y, sum.y);
+      }
+      return sum;
+    };
+    int kf = 0;
+    for (; kf + 1 < nf; kf += 2) {
+      const typename Ac::S a0 = Ac::load(A.vol, base + (int64_t)kf * F3);
+      const typename Ac::S a1 = Ac::load(A.vol, base + (int64_t)(kf + 1) * F3);
+      const double2 s0 = block_sum(kf), s1 = block_sum(kf + 1);
+      Ac::store(A.vol, base + (int64_t)kf * F3, Ac::add(a0, s0));
+      Ac::store(A.vol, base + (int64_t)(kf + 1) * F3, Ac::add(a1, s1));
+    }
+    if (kf < nf) {
+      const typename Ac::S a = Ac::load(A.vol, base + (int64_t)kf * F3);
+      Ac::store(A.vol, base + (int64_t)kf * F3, Ac::add(a, block_sum(kf)));
+    }
+  } else {
+    // per frequency Re(S V), S formed from the samples and Q while the
+    // forward transform V is loading
+    double re = 0.0;
+    for (int kf = 0; kf < nf; ++kf) {
+      const double2 v = Ac::value(Ac::load(A.vol, base + (int64_t)kf * F3));
+      const double2 *Qt = s_tw + kf * KB;
+      double sx = 0.0, sy = 0.0;
+#pragma unroll
+      for (int t = 0; t < KB; ++t) {
+        if (t >= cnt) break;
+        const double2 qt = Qt[t];
+        sx = fma((double)val[t], qt.x, sx);
+        sy = fma((double)val[t], qt.y, sy);
+      }
+      re = fma(sx, v.x, fma(-sy, v.y, re));
+    }
+    double *g = A.gedge + ((int64_t)s * 3 + c) * F + q;
+    *g = *g + re;
   }
 }
 
@@ -1945,9 +1885,10 @@ struct Dev {
   hipGraphExec_t exec = nullptr;
   std::string exec_key;
   // sampled per-kernel timing
-  std::vector<hipEvent_t> ev;
-  double kstat_ms[2] = {0, 0};
-  int kstat_n = 0;
+  std::vector<hipEvent_t> ev;                  // six per sampled step
+  std::vector<uint8_t> kstat_closed;           // the sampled step closed a transform block
+  double kstat_ms[3] = {0, 0, 0};
+  int kstat_n = 0, kstat_ntr = 0;
   int sample_every = 0;
 };
 
@@ -1982,7 +1923,7 @@ static void free_lists(Dev &d) {
   for (auto &b : d.list_bufs) (void)hipFree(b.p);
   d.list_bufs.clear();
   d.list_key.clear();
-  for (int m = 0; m < 2; ++m) {
+  for (int m = 0; m < 3; ++m) {
     d.tile_tab[m] = d.tl_off[m] = nullptr;
     d.tl_ent[m] = nullptr;
   }
@@ -2374,6 +2315,10 @@ static StepArgs<T> make_args(Plan &p, Dev &d, const WS &w, void *vol, bool adj, 
   A.xcd = p.xcd;
   A.kz = p.kz;
   A.order = p.order;
+  A.lean = p.npml >= 1 && p.lean ? 1 : 0;
+  A.kb = p.kb;
+  A.dplane = fdiv_make((uint32_t)A.plane);
+  A.dpx = fdiv_make((uint32_t)p.PX);
   A.nf = p.nf();
   A.zE = d.zE;
   A.vol = vol;
@@ -2419,121 +2364,59 @@ static void go(F kernel, dim3 grid, dim3 block, size_t lds, hipStream_t st, cons
   else hipLaunchKernelGGL(kernel, grid, block, lds, st, args...);
 }
 
-template <typename T, int KB, int VX>
-static void launch_e_vx(const StepArgs<T> &A, int acc, bool adj, bool flush, dim3 grid, dim3 block,
-                        hipStream_t st, const KTime *kt) {
-#define FWD_LAUNCH(ACCV, ADJV)                                                                 \
-  do {                                                                                         \
-    if (flush) go(k_flush<T, ACCV, ADJV, KB>, grid, block, 0, st, kt, A);                      \
-    else go(k_update_e<T, ACCV, ADJV, KB, VX>, grid, block, 0, st, kt, A, ADJV ? A.Q : A.zE);  \
-  } while (0)
-  if (!A.vol) {
-    if (!flush) go(k_update_e<T, ACC_NONE, false, 1, VX>, grid, block, 0, st, kt, A, A.zE);
-    return;
-  }
-  switch (acc) {
-    case FWD_ACC_F64:
-      if (adj) FWD_LAUNCH(ACC_F64, true); else FWD_LAUNCH(ACC_F64, false);
-      break;
-    case FWD_ACC_KAHAN:
-      if (adj) FWD_LAUNCH(ACC_KAHAN, true); else FWD_LAUNCH(ACC_KAHAN, false);
-      break;
-    default:
-      if (adj) FWD_LAUNCH(ACC_F32, true); else FWD_LAUNCH(ACC_F32, false);
-  }
-#undef FWD_LAUNCH
-}
-template <typename T, int KB>
-static void launch_e_kb(const StepArgs<T> &A, int vx, int acc, bool adj, bool flush, dim3 grid,
-                        dim3 block, hipStream_t st, const KTime *kt) {
+// E update (order 2 or 4); hist: the run keeps every sample for the block
+// transform
+template <typename T>
+static void launch_e(const StepArgs<T> &A, int vx, bool hist, dim3 grid, dim3 block,
+                     hipStream_t st, const KTime *kt = nullptr, bool o4 = false) {
   constexpr int VV = (int)(16 / sizeof(T));
-  if (vx == 1) launch_e_vx<T, KB, 1>(A, acc, adj, flush, grid, block, st, kt);
-  else launch_e_vx<T, KB, VV>(A, acc, adj, flush, grid, block, st, kt);
-}
-// fourth-order E update (one element per thread)
-template <typename T, int KB>
-static void launch_e4_kb(const StepArgs<T> &A, int acc, bool adj, dim3 grid, dim3 block,
-                         hipStream_t st, const KTime *kt) {
-  if (!A.vol) {
-    go(k_update_e4<T, ACC_NONE, false, 1>, grid, block, 0, st, kt, A, A.zE);
-    return;
+  if (o4) {
+    if (hist) go(k_update_e4<T, true>, grid, block, 0, st, kt, A);
+    else go(k_update_e4<T, false>, grid, block, 0, st, kt, A);
+  } else if (vx == 1) {
+    if (hist) go(k_update_e<T, true, 1>, grid, block, 0, st, kt, A);
+    else go(k_update_e<T, false, 1>, grid, block, 0, st, kt, A);
+  } else {
+    if (hist) go(k_update_e<T, true, VV>, grid, block, 0, st, kt, A);
+    else go(k_update_e<T, false, VV>, grid, block, 0, st, kt, A);
   }
+}
+
+// the block transform: grid (nodes of the padded layout / 256, sources)
+template <typename T, int KB, bool FLUSH>
+static void launch_transform_kb(const StepArgs<T> &A, int acc, bool adj, hipStream_t st,
+                                const KTime *kt) {
+  const dim3 grid((unsigned)((A.F + 255) / 256), A.ns, 3), block(256);
+  const size_t lds = (size_t)A.nf * KB * sizeof(double2);
+#define FWD_TR(ACCV) \
+  do { \
+    if (adj) go(k_transform<T, ACCV, true, KB, FLUSH>, grid, block, lds, st, kt, A); \
+    else go(k_transform<T, ACCV, false, KB, FLUSH>, grid, block, lds, st, kt, A); \
+  } while (0)
   switch (acc) {
-    case FWD_ACC_F64:
-      if (adj) go(k_update_e4<T, ACC_F64, true, KB>, grid, block, 0, st, kt, A, A.Q);
-      else go(k_update_e4<T, ACC_F64, false, KB>, grid, block, 0, st, kt, A, A.zE);
-      break;
-    case FWD_ACC_KAHAN:
-      if (adj) go(k_update_e4<T, ACC_KAHAN, true, KB>, grid, block, 0, st, kt, A, A.Q);
-      else go(k_update_e4<T, ACC_KAHAN, false, KB>, grid, block, 0, st, kt, A, A.zE);
-      break;
-    default:
-      if (adj) go(k_update_e4<T, ACC_F32, true, KB>, grid, block, 0, st, kt, A, A.Q);
-      else go(k_update_e4<T, ACC_F32, false, KB>, grid, block, 0, st, kt, A, A.zE);
+    case FWD_ACC_F64: FWD_TR(ACC_F64); break;
+    case FWD_ACC_KAHAN: FWD_TR(ACC_KAHAN); break;
+    default: FWD_TR(ACC_F32);
   }
+#undef FWD_TR
 }
-template <typename T>
-static void launch_e4(const StepArgs<T> &A, int kb, int acc, bool adj, dim3 grid, dim3 block,
-                      hipStream_t st, const KTime *kt) {
+template <typename T, bool FLUSH>
+static void launch_transform(const StepArgs<T> &A, int kb, int acc, bool adj, hipStream_t st,
+                             const KTime *kt = nullptr) {
   switch (kb) {
-    case 1: launch_e4_kb<T, 1>(A, acc, adj, grid, block, st, kt); break;
-    case 2: launch_e4_kb<T, 2>(A, acc, adj, grid, block, st, kt); break;
-    case 4: launch_e4_kb<T, 4>(A, acc, adj, grid, block, st, kt); break;
-    case 8: launch_e4_kb<T, 8>(A, acc, adj, grid, block, st, kt); break;
-    default: launch_e4_kb<T, 16>(A, acc, adj, grid, block, st, kt);
-  }
-}
-
-// E update (order 2 or 4) or, with flush, the transform flush (either order)
-template <typename T>
-static void launch_e(const StepArgs<T> &A, int kb, int vx, int acc, bool adj, bool flush,
-                     dim3 grid, dim3 block, hipStream_t st, const KTime *kt = nullptr,
-                     bool o4 = false) {
-  if (o4 && !flush) {
-    launch_e4<T>(A, kb, acc, adj, grid, block, st, kt);
-    return;
-  }
-  switch (kb) {
-    case 1: launch_e_kb<T, 1>(A, vx, acc, adj, flush, grid, block, st, kt); break;
-    case 2: launch_e_kb<T, 2>(A, vx, acc, adj, flush, grid, block, st, kt); break;
-    case 4: launch_e_kb<T, 4>(A, vx, acc, adj, flush, grid, block, st, kt); break;
-    case 8: launch_e_kb<T, 8>(A, vx, acc, adj, flush, grid, block, st, kt); break;
-    default: launch_e_kb<T, 16>(A, vx, acc, adj, flush, grid, block, st, kt);
-  }
-}
-
-template <typename T, int KB>
-static void launch_step_kb(const StepArgs<T> &A, int acc, bool adj, dim3 grid, dim3 block,
-                           size_t lds, hipStream_t st, const KTime *kt) {
-  if (!A.vol) {
-    go(k_step<T, ACC_NONE, false, 1>, grid, block, lds, st, kt, A);
-    return;
-  }
-  switch (acc) {
-    case FWD_ACC_F64:
-      if (adj) go(k_step<T, ACC_F64, true, KB>, grid, block, lds, st, kt, A);
-      else go(k_step<T, ACC_F64, false, KB>, grid, block, lds, st, kt, A);
-      break;
-    case FWD_ACC_KAHAN:
-      if (adj) go(k_step<T, ACC_KAHAN, true, KB>, grid, block, lds, st, kt, A);
-      else go(k_step<T, ACC_KAHAN, false, KB>, grid, block, lds, st, kt, A);
-      break;
-    default:
-      if (adj) go(k_step<T, ACC_F32, true, KB>, grid, block, lds, st, kt, A);
-      else go(k_step<T, ACC_F32, false, KB>, grid, block, lds, st, kt, A);
+    case 1: launch_transform_kb<T, 1, FLUSH>(A, acc, adj, st, kt); break;
+    case 2: launch_transform_kb<T, 2, FLUSH>(A, acc, adj, st, kt); break;
+    case 4: launch_transform_kb<T, 4, FLUSH>(A, acc, adj, st, kt); break;
+    case 8: launch_transform_kb<T, 8, FLUSH>(A, acc, adj, st, kt); break;
+    default: launch_transform_kb<T, 16, FLUSH>(A, acc, adj, st, kt);
   }
 }
 
 template <typename T>
-static void launch_step(const StepArgs<T> &A, int kb, int acc, bool adj, dim3 grid, dim3 block,
-                        size_t lds, hipStream_t st, const KTime *kt = nullptr) {
-  switch (kb) {
-    case 1: launch_step_kb<T, 1>(A, acc, adj, grid, block, lds, st, kt); break;
-    case 2: launch_step_kb<T, 2>(A, acc, adj, grid, block, lds, st, kt); break;
-    case 4: launch_step_kb<T, 4>(A, acc, adj, grid, block, lds, st, kt); break;
-    case 8: launch_step_kb<T, 8>(A, acc, adj, grid, block, lds, st, kt); break;
-    default: launch_step_kb<T, 16>(A, acc, adj, grid, block, lds, st, kt);
-  }
+static void launch_step(const StepArgs<T> &A, bool hist, dim3 grid, dim3 block, size_t lds,
+                        hipStream_t st, const KTime *kt = nullptr) {
+  if (hist) go(k_step<T, true>, grid, block, lds, st, kt, A);
+  else go(k_step<T, false>, grid, block, lds, st, kt, A);
 }
 
 template <typename T>
@@ -2551,12 +2434,14 @@ static void launch_h(const StepArgs<T> &A, int vx, dim3 grid, dim3 block, hipStr
   else go(k_update_h<T, VV, false>, grid, block, 0, st, kt, A);
 }
 
-// enqueue one step (H update, E update; or the fused step); if ev !=
-// nullptr, ev[0..1] time the H kernel and ev[2..3] the E kernel (fused: the
-// one kernel in ev[2..3], ev[0..1] recorded back to back)
+// enqueue step n (H update, E update; or the fused step), followed by the
+// block transform when sample n+1 closes a transform block.  If ev !=
+// nullptr, ev[0..1] time the H kernel, ev[2..3] the E kernel (fused: the one
+// kernel in ev[2..3], ev[0..1] recorded back to back) and ev[4..5] the block
+// transform (recorded back to back when there is none); *closed says which.
 template <typename T>
 static void enqueue_step(Plan &p, Dev &d, const WS &w, void *vol, bool adj, hipStream_t st,
-                         hipEvent_t *ev, int r) {
+                         hipEvent_t *ev, int r, int n, bool *closed = nullptr) {
   StepArgs<T> A = make_args<T>(p, d, w, vol, adj, r);
   const dim3 block(p.bx, p.by), grid(A.nblocks);
   const KTime th_ev = ev ? KTime{ev[0], ev[1]} : KTime{}, te_ev = ev ? KTime{ev[2], ev[3]} : KTime{};
@@ -2573,7 +2458,7 @@ static void enqueue_step(Plan &p, Dev &d, const WS &w, void *vol, bool adj, hipS
       (void)hipEventRecord(ev[0], st);
       (void)hipEventRecord(ev[1], st);
     }
-    launch_step<T>(A, p.kb, p.acc, adj, grid, block, tiling(p).lds, st, ke);
+    launch_step<T>(A, vol != nullptr, grid, block, tiling(p).lds, st, ke);
     if (d.nh > 0)
       hipLaunchKernelGGL((k_hrec<T>), hgrid, hblock, 0, st, A, d.hn, d.nh, d.rn_c, d.rn_idx, d.zH);
   } else {
@@ -2588,17 +2473,33 @@ static void enqueue_step(Plan &p, Dev &d, const WS &w, void *vol, bool adj, hipS
     Ah.tl_ent = hinj ? d.tl_ent[2] : nullptr;
     const bool o4 = p.fd_order == 4;
     launch_h<T>(Ah, p.vxh, dim3(Ah.nblocks), block, st, kh, o4, hinj);
-    launch_e<T>(A, p.kb, p.vx, p.acc, adj, false, grid, block, st, ke, o4);
+    launch_e<T>(A, p.vx, vol != nullptr, grid, block, st, ke, o4);
+  }
+  // the block transform after the step whose sample closes a block; it reads
+  // the counter the E update has just written (step n)
+  const bool close = vol != nullptr && (n + 1) % p.kb == 0;
+  if (closed) *closed = close;
+  if (close) {
+    StepArgs<T> At = A;
+    At.step = A.step_w;
+    const KTime tt_ev = ev ? KTime{ev[4], ev[5]} : KTime{};
+    launch_transform<T, false>(At, p.kb, p.acc, adj, st, ev ? &tt_ev : nullptr);
+  } else if (ev) {
+    (void)hipEventRecord(ev[4], st);
+    (void)hipEventRecord(ev[5], st);
   }
 }
 
+// Add the samples of an incomplete last transform block (the host's step
+// count says whether there is one); the device reads the newest sample's
+// index from the equalised counters.
 template <typename T>
 static void flush_t(Plan &p, Dev &d, const WS &w, void *vol, bool adj, hipStream_t st) {
-  if (p.kb == 1 || !vol) return;
+  if (p.kb == 1 || !vol || p.host_step % p.kb == 0) return;
   build_lists(p, d);
   hipLaunchKernelGGL(k_equalize, dim3(1), dim3(64), 0, st, w.step);
   StepArgs<T> A = make_args<T>(p, d, w, vol, adj);
-  launch_e<T>(A, p.kb, 1, p.acc, adj, true, dim3((p.NX + 63) / 64, p.NY, p.NZ), dim3(64), st);
+  launch_transform<T, true>(A, p.kb, p.acc, adj, st);
   hipLaunchKernelGGL(k_set_flushed, dim3(1), dim3(64), 0, st, w.flushed, (const int *)w.step);
   HIP_CHECK(hipGetLastError());
 }
@@ -2610,6 +2511,9 @@ static void flush_any(Plan &p, Dev &d, const WS &w, void *vol, bool adj, hipStre
     flush_t<float>(p, d, w, vol, adj, st);
 }
 
+// Run nsteps steps from the current position.  The device counters hold the
+// step index for the kernels; the host keeps the same count (p.host_step)
+// to know which steps close a transform block.
 template <typename T>
 static void run_steps_t(Plan &p, Dev &d, const WS &w, void *vol, bool adj, int nsteps,
                         hipStream_t st) {
@@ -2618,36 +2522,46 @@ static void run_steps_t(Plan &p, Dev &d, const WS &w, void *vol, bool adj, int n
   // (r = counter read by the next step)
   hipLaunchKernelGGL(k_equalize, dim3(1), dim3(64), 0, st, w.step);
   int r = 0;
-  const int K = p.graph_steps & ~1;   // graphs of an even number of steps start and end at r = 0
+  // graphs hold an even number of steps (they start and end at r = 0) and a
+  // whole number of transform blocks (every replay starts at the same phase)
+  const int unit = std::max(2, p.kb);
+  const int K = (p.graph_steps & ~1) / unit * unit;
   const int sample = d.sample_every;
   // eager launches of m steps, each bracketed by events if asked
   auto eager = [&](int m, bool timed) {
     for (int t = 0; t < m; ++t) {
       hipEvent_t *ev = nullptr;
       if (timed) {
-        const size_t need = (size_t)(d.kstat_n + 1) * 4;
+        const size_t need = (size_t)(d.kstat_n + 1) * 6;
         while (d.ev.size() < need) {
           hipEvent_t e;
           HIP_CHECK(hipEventCreate(&e));
           d.ev.push_back(e);
         }
-        ev = &d.ev[(size_t)d.kstat_n * 4];
+        ev = &d.ev[(size_t)d.kstat_n * 6];
+      }
+      bool closed = false;
+      enqueue_step<T>(p, d, w, vol, adj, st, ev, r, p.host_step, &closed);
+      if (timed) {
+        d.kstat_closed.resize((size_t)d.kstat_n + 1);
+        d.kstat_closed[d.kstat_n] = closed ? 1 : 0;
         d.kstat_n++;
       }
-      enqueue_step<T>(p, d, w, vol, adj, st, ev, r);
+      p.host_step++;
       r ^= 1;
     }
     HIP_CHECK(hipGetLastError());
   };
-  if (K <= 1 || nsteps < K) {
+  if (K < 2 || nsteps < K) {
     for (int t = 0; t < nsteps; ++t) eager(1, sample > 0 && t % sample == 0);
     return;
   }
   // graph of K steps, captured on a private stream and replayed on st
+  const int phase = p.host_step % p.kb;
   char key[256];
-  snprintf(key, sizeof key, "%p/%p/%d/%d/%d/%d/%d/%d/%d/%d/%d/%d/%d/%llu/%llu", w.fields, vol,
-           (int)adj, K, p.bx, p.by, p.xcd, p.kb, p.vx, p.vxh, p.sched, p.kz, p.order,
-           (unsigned long long)p.model_version, (unsigned long long)p.basis_version);
+  snprintf(key, sizeof key, "%p/%p/%d/%d/%d/%d/%d/%d/%d/%d/%d/%d/%d/%d/%d/%llu/%llu", w.fields,
+           vol, (int)adj, K, phase, p.bx, p.by, p.xcd, p.kb, p.vx, p.vxh, p.sched, p.kz, p.order,
+           p.lean, (unsigned long long)p.model_version, (unsigned long long)p.basis_version);
   if (!d.exec || d.exec_key != key) {
     if (d.exec) {
       HIP_CHECK(hipGraphExecDestroy(d.exec));
@@ -2655,7 +2569,8 @@ static void run_steps_t(Plan &p, Dev &d, const WS &w, void *vol, bool adj, int n
     }
     hipGraph_t g = nullptr;
     HIP_CHECK(hipStreamBeginCapture(d.cap, hipStreamCaptureModeRelaxed));
-    for (int t = 0; t < K; ++t) enqueue_step<T>(p, d, w, vol, adj, d.cap, nullptr, t & 1);
+    for (int t = 0; t < K; ++t)
+      enqueue_step<T>(p, d, w, vol, adj, d.cap, nullptr, t & 1, p.host_step + t);
     const hipError_t le = hipGetLastError();
     const hipError_t ce = hipStreamEndCapture(d.cap, &g);   // always end the capture
     if (le != hipSuccess || ce != hipSuccess) {
@@ -2677,6 +2592,7 @@ static void run_steps_t(Plan &p, Dev &d, const WS &w, void *vol, bool adj, int n
       eager(K, true);
     } else {
       HIP_CHECK(hipGraphLaunch(d.exec, st));
+      p.host_step += K;
     }
     done += K;
     ++chunk;
@@ -2692,20 +2608,28 @@ static void run_steps_any(Plan &p, Dev &d, const WS &w, void *vol, bool adj, int
     run_steps_t<float>(p, d, w, vol, adj, nsteps, st);
 }
 
+// averages over the sampled steps: H update, E update (every sampled step),
+// block transform (the sampled steps that closed a block)
 static void collect_kernel_stats(Dev &d) {
-  double tot[2] = {0, 0};
+  double tot[3] = {0, 0, 0};
+  int ntr = 0;
   for (int s = 0; s < d.kstat_n; ++s) {
-    hipEvent_t *ev = &d.ev[(size_t)s * 4];
-    for (int k = 0; k < 2; ++k) {
+    hipEvent_t *ev = &d.ev[(size_t)s * 6];
+    for (int k = 0; k < 3; ++k) {
+      if (k == 2 && !d.kstat_closed[s]) continue;
       float ms = 0;
       HIP_CHECK(hipEventElapsedTime(&ms, ev[2 * k], ev[2 * k + 1]));
       tot[k] += ms;
     }
+    ntr += d.kstat_closed[s];
   }
   for (int k = 0; k < 2; ++k) d.kstat_ms[k] = d.kstat_n ? tot[k] / d.kstat_n : 0.0;
+  d.kstat_ms[2] = ntr ? tot[2] / ntr : 0.0;
+  d.kstat_ntr = ntr;
 }
 
 static void zero_state(Plan &p, const WS &w, void *ws, void *vol, int mode, hipStream_t st) {
+  p.host_step = 0;
   HIP_CHECK(hipMemsetAsync(ws, 0, p.workspace_bytes(mode), st));
   if (vol && mode == FWD_MODE_FORWARD) HIP_CHECK(hipMemsetAsync(vol, 0, p.volume_bytes(), st));
   hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, st, w.step, -1);
@@ -2800,6 +2724,13 @@ void dev_checkpoint(Plan &p, const void *ws, const void *vol, void *snap, int sa
     if (vol)
       HIP_CHECK(hipMemcpyAsync(const_cast<void *>(vol), sn + sb, p.volume_bytes(),
                                hipMemcpyDeviceToDevice, st));
+    // the host's step count follows the restored counters (last completed
+    // step: the larger of the two)
+    int cnt[2] = {0, 0};
+    const WS w = carve(p, const_cast<void *>(ws));
+    HIP_CHECK(hipMemcpyAsync(cnt, w.step, sizeof cnt, hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipStreamSynchronize(st));
+    p.host_step = std::max(cnt[0], cnt[1]) + 1;
   }
 }
 
@@ -2958,7 +2889,7 @@ static void adjoint_td_t(Plan &p, Dev &d, const WS &w, void *ws, char *scratch, 
                        F);
     int r = 0;
     for (int t = 1; t <= len; ++t) {
-      enqueue_step<T>(p, d, w, nullptr, false, st, nullptr, r);
+      enqueue_step<T>(p, d, w, nullptr, false, st, nullptr, r, n0 + t - 1);
       r ^= 1;
       hipLaunchKernelGGL((k_copy_e<T>), dim3(cgrid), dim3(256), 0, st, eseg + t * eslice, fields,
                          fbuf, (n0 + t) & 1, ns, F);
@@ -3030,8 +2961,42 @@ void dev_adjoint_td(Plan &p, void *ws, size_t ws_bytes, void *scratch, size_t sc
 }
 
 // ---------------------------------------------------------------------------
-// autotuner: time each candidate schedule and tiling on the real buffers
+// autotuner: time candidate schedules and tilings on the real buffers.  A
+// staged search (coordinate descent) instead of the full product: block
+// shape; vector widths; tile order x XCD remap; the fused schedule's shapes
+// and planes per block; the transform block K (8 or 16, when the workspace
+// holds the longer history).  Each candidate first runs `steps` steps
+// untimed (its HIP graph is captured and instantiated there), then the same
+// number timed, so the timed interval holds the replays only.  Results are
+// cached for the process, keyed by everything that shapes the work.
 // ---------------------------------------------------------------------------
+namespace {
+struct TuneCand {
+  int sched, bx, by, vx, vxh, kz, order, xcd, kb;
+};
+struct TuneHit {
+  TuneCand c;
+  double ms;
+};
+std::mutex g_tune_mu;
+std::map<std::string, TuneHit> g_tune_cache;
+
+TuneCand cand_of(const Plan &p) {
+  return {p.sched, p.bx, p.by, p.vx, p.vxh, p.kz, p.order, p.xcd, p.kb};
+}
+void apply_cand(Plan &p, const TuneCand &c) {
+  p.sched = c.sched;
+  p.bx = c.bx;
+  p.by = c.by;
+  p.vx = c.vx;
+  p.vxh = c.vxh;
+  p.kz = c.kz;
+  p.order = c.order;
+  p.xcd = c.xcd;
+  p.kb = c.kb;
+}
+}  // namespace
+
 double dev_autotune(Plan &p, void *ws, size_t ws_bytes, void *vol, size_t vol_bytes, int mode,
                     int steps, void *stream) {
   hipStream_t st = static_cast<hipStream_t>(stream);
@@ -3040,85 +3005,148 @@ double dev_autotune(Plan &p, void *ws, size_t ws_bytes, void *vol, size_t vol_by
   check_sizes(p, ws_bytes, mode, vol, vol_bytes);
   ensure_tables(p, st);
   Dev &d = D(p);
-  WS w = carve(p, ws);
-  struct Cand {
-    int sched, bx, by, vx, vxh, kz, order;
-  };
-  std::vector<Cand> cand;
-  const int two[][2] = {{64, 4}, {64, 2}, {64, 1}, {32, 8}, {32, 4}, {16, 16},
-                        {16, 8}, {16, 4}, {128, 2}, {256, 1}};
   const bool o4 = p.fd_order == 4;      // order 4: two-kernel schedule, scalar threads
-  for (int order : {0, 1}) {
-    for (auto &c : two)
-      for (int v : {0, 1, 2}) {  // vector widths (E, H): (1, 1), (1, 4), (4, 4)
-        if (o4 && v) continue;
-        cand.push_back({0, c[0], c[1], v == 2 ? 4 : 1, v ? 4 : 1, p.kz, order});
-      }
-    const int fused[][2] = {{64, 4}, {32, 8}, {16, 16}, {16, 8}};
-    if (!o4)
-      for (auto &c : fused)
-        for (int kz : {2, 4, 8}) cand.push_back({1, c[0], c[1], 1, 1, kz, order});
+  // transform blocks the caller's workspace can hold (the history grows with K)
+  std::vector<int> kbs{p.kb};
+  if (vol) {
+    const int keep = p.kb;
+    for (int kb : {8, 16}) {
+      p.kb = kb;
+      if (kb != keep && p.workspace_bytes(mode) <= ws_bytes) kbs.push_back(kb);
+    }
+    p.kb = keep;
   }
-  const Cand save{p.sched, p.bx, p.by, p.vx, p.vxh, p.kz, p.order};
-  const int save_xcd = p.xcd, save_sample = d.sample_every;
+  char key[256];
+  snprintf(key, sizeof key, "%d/%d/%d/%d/%d/%d/%d/%d/%d/%d/%d/%d/%d/%d", p.nx, p.ny, p.nz, p.npml,
+           p.ns, p.nf(), p.dtype, p.acc, p.fd_order, mode, vol ? 1 : 0, (int)kbs.size(),
+           (int)p.rn_c.size(), steps);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
+      apply_cand(p, it->second.c);
+      return it->second.ms;
+    }
+  }
+  const int save_sample = d.sample_every;
   d.sample_every = 0;
-  double best = 1e300;
-  Cand bc = save;
-  int bxcd = save_xcd;
   hipEvent_t e0, e1;
   HIP_CHECK(hipEventCreate(&e0));
   HIP_CHECK(hipEventCreate(&e1));
-  for (const Cand &c : cand) {
-    for (int xc = 0; xc <= 1; ++xc) {
-      p.sched = c.sched;
-      p.bx = c.bx;
-      p.by = c.by;
-      p.vx = c.vx;
-      p.vxh = c.vxh;
-      p.kz = c.kz;
-      p.order = c.order;
-      p.xcd = xc;
-      zero_state(p, w, ws, adj ? nullptr : vol, mode, st);
-      run_steps_any(p, d, w, vol, adj, 4, st);   // warm-up (graph capture)
-      HIP_CHECK(hipEventRecord(e0, st));
-      run_steps_any(p, d, w, vol, adj, steps, st);
-      HIP_CHECK(hipEventRecord(e1, st));
-      HIP_CHECK(hipEventSynchronize(e1));
-      float ms = 0;
-      HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
-      const double per = ms / steps;
-      if (per < best) {
-        best = per;
-        bc = c;
-        bxcd = xc;
+  // one clean state (the whole workspace: a longer transform block lays the
+  // history out further); between candidates only the step counters and
+  // the flush marker are reset (stepping on from any state costs the same)
+  HIP_CHECK(hipMemsetAsync(ws, 0, ws_bytes, st));
+  if (vol && !adj) HIP_CHECK(hipMemsetAsync(vol, 0, p.volume_bytes(), st));
+  auto time_cand = [&](const TuneCand &c) {
+    apply_cand(p, c);
+    const WS wc = carve(p, ws);
+    for (int t = 0; t < 2; ++t) {
+      hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, st, wc.step, -1);
+      hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, st, wc.step + 1, -1);
+      hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, st, wc.flushed, 0);
+      p.host_step = 0;
+      if (t == 1) HIP_CHECK(hipEventRecord(e0, st));
+      run_steps_any(p, d, wc, vol, adj, steps, st);
+    }
+    HIP_CHECK(hipEventRecord(e1, st));
+    HIP_CHECK(hipEventSynchronize(e1));
+    float ms = 0;
+    HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+    return (double)ms / steps;
+  };
+  TuneCand best = cand_of(p);
+  best.sched = 0;
+  best.vx = best.vxh = 1;
+  double best_ms = 1e300;
+  auto consider = [&](const TuneCand &c) {
+    const double ms = time_cand(c);
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = c;
+    }
+  };
+  // stage 1: block shapes (two-kernel schedule, one node per thread)
+  const int shapes[][2] = {{64, 4}, {64, 2}, {64, 1}, {32, 8}, {32, 4}, {16, 16},
+                           {16, 8}, {16, 4}, {128, 2}, {256, 1}};
+  {
+    const TuneCand base = best;
+    for (auto &sh : shapes) {
+      TuneCand c = base;
+      c.bx = sh[0];
+      c.by = sh[1];
+      consider(c);
+    }
+  }
+  // stage 2: 16-byte vectors (H only, then both)
+  if (!o4) {
+    const TuneCand base = best;
+    for (int v : {1, 2}) {
+      TuneCand c = base;
+      c.vxh = 4;
+      c.vx = v == 2 ? 4 : 1;
+      consider(c);
+    }
+  }
+  // stage 3: tile order and XCD remap
+  {
+    const TuneCand base = best;
+    for (int order : {0, 1})
+      for (int xc : {0, 1}) {
+        if (order == base.order && xc == base.xcd) continue;
+        TuneCand c = base;
+        c.order = order;
+        c.xcd = xc;
+        consider(c);
       }
+  }
+  // stage 4: the fused schedule
+  if (!o4) {
+    const TuneCand base = best;
+    const int fused[][2] = {{64, 4}, {32, 8}, {16, 16}, {16, 8}};
+    for (auto &sh : fused)
+      for (int kz : {2, 4, 8}) {
+        TuneCand c = base;
+        c.sched = 1;
+        c.bx = sh[0];
+        c.by = sh[1];
+        c.vx = c.vxh = 1;
+        c.kz = kz;
+        consider(c);
+      }
+  }
+  // stage 5: the transform block
+  {
+    const TuneCand base = best;
+    for (int kb : kbs) {
+      if (kb == base.kb) continue;
+      TuneCand c = base;
+      c.kb = kb;
+      consider(c);
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  p.sched = bc.sched;
-  p.bx = bc.bx;
-  p.by = bc.by;
-  p.vx = bc.vx;
-  p.vxh = bc.vxh;
-  p.kz = bc.kz;
-  p.order = bc.order;
-  p.xcd = bxcd;
+  apply_cand(p, best);
   d.sample_every = save_sample;
-  return best;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[key] = {best, best_ms};
+  }
+  return best_ms;
 }
 
 // option plumbing for the sampled timing lives with the device state
 void dev_set_sampling(Plan &p, int every) { D(p).sample_every = every; }
 int dev_get_sampling(Plan &p) { return p.dev ? D(p).sample_every : 0; }
-void dev_kernel_stats(Plan &p, double *ms2, int *count) {
+void dev_kernel_stats(Plan &p, double *ms3, int *count) {
   if (!p.dev) {
-    for (int k = 0; k < 2; ++k) ms2[k] = 0;
+    for (int k = 0; k < 3; ++k) ms3[k] = 0;
     *count = 0;
     return;
   }
   Dev &d = D(p);
-  for (int k = 0; k < 2; ++k) ms2[k] = d.kstat_ms[k];
+  for (int k = 0; k < 3; ++k) ms3[k] = d.kstat_ms[k];
   *count = d.kstat_n;
 }
 

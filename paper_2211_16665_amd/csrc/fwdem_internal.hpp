@@ -117,6 +117,7 @@ struct Plan {
   int kz = 8;                            // planes per block of the fused schedule
   int order = 0;                         // tile numbering: 0 x fastest, 1 z fastest
   int vti_grad = 0;                      // 1: gradients as [d/d ln rho_h, d/d ln rho_v]
+  int lean = 1;                          // interior tiles take the lean update paths
   int fd_order = 2;                      // order of the staggered differences: 2 or 4
 
   // ---- device side (managed in device.hip) ----
@@ -124,6 +125,7 @@ struct Plan {
   uint64_t model_version = 0, basis_version = 0;
   double last_ms = 0;
   int last_steps = 0;
+  int host_step = 0;          // steps completed in the current run (the device counters' value + 1)
 
   int64_t plane() const { return (int64_t)NY * PX; }
   int64_t field_elems() const { return (int64_t)NZ * NY * PX; }
@@ -132,7 +134,9 @@ struct Plan {
   size_t tsize() const { return dtype == FWD_F64 ? 8 : 4; }
   size_t acc_bytes() const { return acc == FWD_ACC_F32 ? 8 : 16; }
   int64_t psi_elems_per_source() const;
-  int64_t hist_elems_per_source() const { return kb > 2 ? (int64_t)(kb - 2) * 3 * field_elems() : 0; }
+  // transform-block history: samples 1 .. kb-1 of a block (the closing one
+  // is read from the fields)
+  int64_t hist_elems_per_source() const { return kb > 1 ? (int64_t)(kb - 1) * 3 * field_elems() : 0; }
   size_t core_state_bytes() const;  // fields + psi (double-buffered) + receiver sums + counters
   size_t state_bytes() const;       // core state + transform-block history
   size_t td_scratch_bytes(int segment) const;   // time-domain adjoint scratch
@@ -175,7 +179,7 @@ double dev_autotune(Plan &p, void *ws, size_t ws_bytes, void *vol, size_t vol_by
                     int mode, int steps, void *stream);
 void dev_set_sampling(Plan &p, int every);
 int dev_get_sampling(Plan &p);
-void dev_kernel_stats(Plan &p, double *ms2, int *count);
+void dev_kernel_stats(Plan &p, double *ms3, int *count);
 
 }  // namespace fwdem
 

@@ -34,7 +34,7 @@ FWD_MODE_FORWARD, FWD_MODE_ADJOINT = 0, 1
 (FWD_OPT_GRAPH_STEPS, FWD_OPT_BLOCK_X, FWD_OPT_BLOCK_Y, FWD_OPT_XCD_REMAP,
  FWD_OPT_SAMPLE_EVERY, FWD_OPT_STRICT_CFL, FWD_OPT_DFT_BLOCK, FWD_OPT_VECTOR,
  FWD_OPT_SCHEDULE, FWD_OPT_ZCHUNK, FWD_OPT_TILE_ORDER, FWD_OPT_VECTOR_H,
- FWD_OPT_VTI_GRADIENT, FWD_OPT_FD_ORDER) = range(14)
+ FWD_OPT_VTI_GRADIENT, FWD_OPT_FD_ORDER, FWD_OPT_LEAN) = range(15)
 
 ACC_MODES = {"f64": FWD_ACC_F64, "kahan": FWD_ACC_KAHAN, "f32": FWD_ACC_F32}
 DTYPES = {"f32": FWD_F32, "f64": FWD_F64}
@@ -188,8 +188,8 @@ class Plan:
         self.handle = h
         self.shape = (d.nz, d.ny, d.nx)
         self.ns, self.nr, self.ncomp, self.nf = d.nsrc, d.nrec, d.ncomp, d.nfreq
-        self._ws = {}
-        self._vol = None
+        self._ws = None          # the plan's own workspace (both modes; see workspace)
+        self._ext_ws = None      # a caller's buffer in its place (use_workspace)
         self.model_serial = 0
         if int(fd_order) != 2:
             self.set_option(FWD_OPT_FD_ORDER, int(fd_order))
@@ -268,21 +268,43 @@ class Plan:
         return v.value
 
     # ---- device buffers ----------------------------------------------------
-    def workspace(self, mode=FWD_MODE_FORWARD):
-        import torch
+    def workspace_size(self, mode=FWD_MODE_FORWARD) -> int:
         n = c_size_t()
         check(self.lib.fwd_workspace_size(self.handle, mode, byref(n)))
-        t = self._ws.get(mode)
-        if t is None or t.numel() < n.value:
-            t = torch.empty(n.value, dtype=torch.uint8, device="cuda")
-            self._ws[mode] = t
-        return t
+        return n.value
+
+    def volume_size(self) -> int:
+        n = c_size_t()
+        check(self.lib.fwd_volume_size(self.handle, byref(n)))
+        return n.value
+
+    def use_workspace(self, buf):
+        """Run on the caller's device buffer ``buf`` (uint8 tensor) instead of
+        a workspace owned by the plan -- e.g. one buffer for several plans run
+        one after the other on one stream; None returns to the plan's own."""
+        self._ext_ws = buf
+        self._ws = None
+
+    def workspace(self, mode=FWD_MODE_FORWARD):
+        """Device workspace of a ``mode`` run.  One buffer serves both modes
+        (the runs of a plan are enqueued on one stream and never overlap; each
+        run starts by zeroing the state it uses), grown to the largest size
+        asked for."""
+        import torch
+        need = self.workspace_size(mode)
+        if self._ext_ws is not None:
+            if self._ext_ws.numel() < need:
+                raise ValueError(f"external workspace holds {self._ext_ws.numel()} bytes, "
+                                 f"the run needs {need}")
+            return self._ext_ws
+        if self._ws is None or self._ws.numel() < need:
+            self._ws = None
+            self._ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+        return self._ws
 
     def volume_buffer(self):
         import torch
-        n = c_size_t()
-        check(self.lib.fwd_volume_size(self.handle, byref(n)))
-        return torch.empty(n.value, dtype=torch.uint8, device="cuda")
+        return torch.empty(self.volume_size(), dtype=torch.uint8, device="cuda")
 
     def rec_buffer(self):
         import torch
@@ -399,7 +421,9 @@ class Plan:
         return ms.value, n.value
 
     def kernel_stats(self):
-        arr = (c_double * 2)()
+        """([H update, E update, block transform] average ms per launch, sampled
+        steps) of the last forward / adjoint (FWD_OPT_SAMPLE_EVERY > 0)."""
+        arr = (c_double * 3)()
         n = c_int()
         check(self.lib.fwd_kernel_stats(self.handle, arr, byref(n)))
         return list(arr), n.value

@@ -42,10 +42,16 @@ def test_e_update_byte_model(nx, ny, nz, npml):
                 if 1 <= i < nx and 1 <= j < ny and k < nz:          # E_z: d/dx, d/dy
                     edges += 1
                     psi += _in_int(i, nx, npml) + _in_int(j, ny, npml)
-    per_edge = 4 * tsize + 2 * nf * accsize / kb + 2 * (kb - 2) * tsize / kb
-    b, e = bench.algorithmic_bytes_e_forward(nx, ny, nz, npml, nf, tsize, accsize, kb)
+    b, e = bench.algorithmic_bytes_e(nx, ny, nz, npml, tsize, kb)
     assert e == edges
-    assert b == int(edges * per_edge + psi * 2 * tsize)
+    assert b == int(edges * (4 * tsize + (kb - 1) * tsize / kb) + psi * 2 * tsize)
+    b0, _ = bench.algorithmic_bytes_e(nx, ny, nz, npml, tsize, kb, hist=False)
+    assert b0 == edges * 4 * tsize + psi * 2 * tsize
+    # block transform: kb samples and the accumulators' read + write per edge
+    assert bench.algorithmic_bytes_transform(edges, nf, tsize, accsize, kb) == \
+        edges * (kb * tsize + 2 * nf * accsize)
+    assert bench.algorithmic_bytes_transform(edges, nf, tsize, accsize, kb, adjoint=True) == \
+        edges * (kb * tsize + nf * accsize + 16)
 
 
 @pytest.mark.parametrize("nx,ny,nz,npml", [(12, 10, 9, 3), (9, 11, 8, 0)])

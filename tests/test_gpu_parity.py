@@ -413,6 +413,31 @@ def test_fused_schedule_on_the_marine_grid(dtype):
             assert same(a, b)
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_lean_interior_path_on_the_marine_grid(dtype):
+    """The interior tiles' lean update path (no CPML or wall logic) against
+    the general path everywhere (FWD_OPT_LEAN = 0), on a window of the full
+    marine grid with several tilings (different tiles are interior):
+    receivers, volume transform, gradient and adjoint receiver transform bit
+    for bit."""
+    w = with_window(c2_marine1d(), 48)
+    say(f"lean interior path on the marine grid, {dtype}")
+    p = fw.Plan.from_workload(w, field_dtype="f64")
+    p.set_model(w.rho)
+    d = p.forward().cpu().numpy() * 1.01
+    ref = _run_all(w, d, dict(lean=0), True, dtype, "f64")
+    for opts in (dict(lean=1), dict(lean=1, block_x=32, block_y=8, xcd_remap=0, tile_order=1),
+                 dict(lean=1, block_x=16, block_y=16, vector=4, vector_h=4),
+                 dict(lean=1, block_x=128, block_y=2, dft_block=16)):
+        say(f"  {opts}")
+        out = _run_all(w, d, opts, True, dtype, "f64")
+        for a, b in zip(ref, out):
+            if opts.get("dft_block"):      # another transform block: the sums' order differs
+                assert rel(a, b) < 1e-12
+            else:
+                assert same(a, b)
+
+
 def test_fused_graph_odd_chunks_and_schedule_switch():
     """Graphs of an odd number of steps (the double-buffer half alternates
     between replays), eager launches, and a run that switches schedule
