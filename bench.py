@@ -643,6 +643,8 @@ def large_window(args):
     d_obs = [p.forward() for p in plans]            # data of the true model
     if args.tiling:
         set_tiling(plans[big], args.tiling)
+        if args.dft_block:
+            plans[big].set_option(fw.FWD_OPT_DFT_BLOCK, args.dft_block)
         tune_ms = float("nan")
     else:
         tune_ms = plans[big].autotune(fw.FWD_MODE_FORWARD, vol=vol, steps=args.tune_steps)
@@ -803,18 +805,18 @@ def marine_gradient(args):
 
 def profile_mode(args):
     """A short run for hardware-counter collection: one elementwise kernel of
-    a known size (256 MiB read + 256 MiB written, the calibration of the byte
-    counters), then a forward and an adjoint run of ``profile_steps`` steps
+    a known size (1 GiB read + 1 GiB written, the calibration of the byte
+    counters; larger than the 256 MB Infinity Cache), then a forward and an adjoint run of ``profile_steps`` steps
     on the full grid of the workload (for the large workload: one group of
     ``--group`` sources), with eager launches."""
     import torch
     from paper_2211_16665_amd import fwdem as fw
     from workloads import c2_marine1d, c4_batched, c5_large
-    n = 256 * 1024 * 1024 // 4
+    n = 1024 * 1024 * 1024 // 4
     a = torch.ones(n, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
     torch.cuda.synchronize()
-    torch.mul(a, 2.0, out=b)          # one elementwise kernel: 256 MiB read, 256 MiB written
+    torch.mul(a, 2.0, out=b)          # one elementwise kernel: 1 GiB read, 1 GiB written
     torch.cuda.synchronize()
     del a, b
     if args.profile_workload == "large":
@@ -829,6 +831,8 @@ def profile_mode(args):
     plan = fw.Plan.from_workload(w, field_dtype=args.field_dtype, acc_mode=args.acc or w.acc_mode)
     plan.set_option(fw.FWD_OPT_GRAPH_STEPS, 0)
     set_tiling(plan, args.tiling)
+    if args.dft_block:
+        plan.set_option(fw.FWD_OPT_DFT_BLOCK, args.dft_block)
     plan.set_model(w.rho)
     plan.basis_build(gamma_rel=1e-12)
     E, vol = plan.forward(want_volume=True)
@@ -873,12 +877,14 @@ def main():
                     help="skip the fourth-order gradient timing")
     ap.add_argument("--extras", default="all",
                     help="'none' skips every extra record (marine, studies, CPU baseline)")
+    ap.add_argument("--dft-block", type=int, default=0,
+                    help="with --tiling: the transform block (0: the plan's default)")
     ap.add_argument("--tiling", default="",
                     help="fixed tiling instead of autotuning: " + ",".join(TILING_KEYS).lower())
     ap.add_argument("--profile-workload", default="large", choices=("large", "marine", "batched"),
                     help="workload of the counter-collection mode")
     ap.add_argument("--profile-steps", type=int, default=0,
-                    help="counter-collection mode: a 256 MiB device copy (calibration of the "
+                    help="counter-collection mode: a 1 GiB device copy (calibration of the "
                          "byte counters) then this many forward and adjoint steps of the "
                          "workload; prints a short JSON line, no metric")
     args = ap.parse_args()
