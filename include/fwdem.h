@@ -170,6 +170,29 @@ fwd_status fwd_forward(fwd_plan *plan, void *ws_dev, size_t ws_bytes,
                        void *vol_dev, size_t vol_bytes, double *E_rec_dev,
                        void *stream);
 
+/* fwd_forward for callers that cannot allocate device memory (code under
+ * HIP stream or graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same run, with the workspace in a static array of the
+ * library's device code, FWD_STATIC_SCRATCH_BYTES per device, held by each
+ * device the library runs on until the process ends.  It calls no hipMalloc,
+ * hipFree or allocating routine: steps are launched one by one (no HIP
+ * graph) and no timing is recorded (fwd_last_timing and fwd_kernel_stats
+ * keep the values of the last fwd_forward / fwd_adjoint).
+ *   vol_dev, vol_bytes, E_rec_dev, stream  as for fwd_forward (caller-owned)
+ * Every call on one device uses that device's array, which keeps the last
+ * call's contents (each call clears what it uses first): calls that overlap
+ * on one device race.  The plan's device tables and entry lists must already
+ * be on the current device for its current model and tiling options -- run
+ * fwd_forward (or fwd_run_begin and fwd_run_steps) once after fwd_set_model
+ * and after changing a tiling option; otherwise FWD_ERR_STATE.
+ * Errors: STATE (no model, tables not resident), INVALID_ARG (the forward
+ * workspace, fwd_workspace_size(FORWARD), needs more than
+ * FWD_STATIC_SCRATCH_BYTES - 256 bytes; volume buffer too small), HIP,
+ * NONFINITE. */
+#define FWD_STATIC_SCRATCH_BYTES (32u << 20)
+fwd_status fwd_forward_static(fwd_plan *plan, void *vol_dev, size_t vol_bytes, double *E_rec_dev,
+                              void *stream);
+
 /* Partial runs for checkpointing.  fwd_run_begin zeroes the state in ws
  * (and vol, if given); fwd_run_steps advances it by nsteps (the step index
  * lives in the workspace, so runs may be split anywhere); fwd_run_receivers

@@ -144,6 +144,16 @@ fwd_status fwd_forward(fwd_plan *h, void *ws, size_t ws_bytes, void *vol, size_t
   });
 }
 
+fwd_status fwd_forward_static(fwd_plan *h, void *vol, size_t vol_bytes, double *E_rec,
+                              void *stream) {
+  return guard([&] {
+    Plan &p = P(h);
+    if (!p.have_model) fail(FWD_ERR_STATE, "no model set");
+    if (!E_rec) fail(FWD_ERR_INVALID_ARG, "E_rec is required");
+    dev_forward_static(p, vol, vol_bytes, E_rec, stream);
+  });
+}
+
 fwd_status fwd_run_begin(fwd_plan *h, void *ws, size_t ws_bytes, void *vol, size_t vol_bytes,
                          void *stream) {
   return guard([&] {

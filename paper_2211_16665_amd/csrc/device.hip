@@ -2161,10 +2161,15 @@ static Tiling tiling(const Plan &p, bool h_update = false) {
 // thread of the tiling that owns its edge (with the element of that
 // thread's vector, or the plane within the fused chunk), so that the E
 // update finds its own entries with two loads and no search.
-static void build_lists(Plan &p, Dev &d) {
+static std::string lists_key(const Plan &p) {
   char key[128];
   snprintf(key, sizeof key, "%d/%d/%d/%d/%d/%d/%d/%llu", p.bx, p.by, p.vx, p.vxh, p.sched, p.kz,
            p.order, (unsigned long long)p.model_version);
+  return key;
+}
+
+static void build_lists(Plan &p, Dev &d) {
+  const std::string key = lists_key(p);
   if (d.list_key == key) return;
   free_lists(d);
   const int nn = (int)p.rn_c.size(), nf = p.nf();
@@ -2514,9 +2519,11 @@ static void flush_any(Plan &p, Dev &d, const WS &w, void *vol, bool adj, hipStre
 // Run nsteps steps from the current position.  The device counters hold the
 // step index for the kernels; the host keeps the same count (p.host_step)
 // to know which steps close a transform block.
+// plain: every step launched eagerly, no timing (no graph or event is
+// created: the path of the entry point that allocates nothing)
 template <typename T>
 static void run_steps_t(Plan &p, Dev &d, const WS &w, void *vol, bool adj, int nsteps,
-                        hipStream_t st) {
+                        hipStream_t st, bool plain = false) {
   build_lists(p, d);
   // both counters hold the last completed step; the steps then alternate
   // (r = counter read by the next step)
@@ -2525,8 +2532,8 @@ static void run_steps_t(Plan &p, Dev &d, const WS &w, void *vol, bool adj, int n
   // graphs hold an even number of steps (they start and end at r = 0) and a
   // whole number of transform blocks (every replay starts at the same phase)
   const int unit = std::max(2, p.kb);
-  const int K = (p.graph_steps & ~1) / unit * unit;
-  const int sample = d.sample_every;
+  const int K = plain ? 0 : (p.graph_steps & ~1) / unit * unit;
+  const int sample = plain ? 0 : d.sample_every;
   // eager launches of m steps, each bracketed by events if asked
   auto eager = [&](int m, bool timed) {
     for (int t = 0; t < m; ++t) {
@@ -2601,11 +2608,11 @@ static void run_steps_t(Plan &p, Dev &d, const WS &w, void *vol, bool adj, int n
 }
 
 static void run_steps_any(Plan &p, Dev &d, const WS &w, void *vol, bool adj, int nsteps,
-                          hipStream_t st) {
+                          hipStream_t st, bool plain = false) {
   if (p.dtype == FWD_F64)
-    run_steps_t<double>(p, d, w, vol, adj, nsteps, st);
+    run_steps_t<double>(p, d, w, vol, adj, nsteps, st, plain);
   else
-    run_steps_t<float>(p, d, w, vol, adj, nsteps, st);
+    run_steps_t<float>(p, d, w, vol, adj, nsteps, st, plain);
 }
 
 // averages over the sampled steps: H update, E update (every sampled step),
@@ -2710,6 +2717,74 @@ void dev_forward(Plan &p, void *ws, size_t ws_bytes, void *vol, size_t vol_bytes
   p.last_steps = p.nt;
   collect_kernel_stats(d);
   check_finite(reinterpret_cast<double2 *>(E_rec), (size_t)p.ns * p.nr * p.ncomp * p.nf(), st);
+}
+
+// ---------------------------------------------------------------------------
+// Forward run with the workspace in a static device array, for callers that
+// cannot allocate (code under stream capture, serving loops).  One array per
+// device, shared by every call on that device (overlapping calls race);
+// its device address is taken once per device with hipGetSymbolAddress.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[FWD_STATIC_SCRATCH_BYTES];
+
+namespace {
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[64] = {};
+}  // namespace
+
+static void *static_scratch(int dev) {
+  if (dev < 0 || dev >= 64) fail(FWD_ERR_UNSUPPORTED, "device index above 63");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      fail(FWD_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  return g_scratch_ptr[dev];
+}
+
+__global__ void k_nonfinite(const double *v, size_t n, int *flag) {
+  const size_t st = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += st)
+    if (!isfinite(v[i])) flag[0] = 1;
+}
+
+void dev_forward_static(Plan &p, void *vol, size_t vol_bytes, double *E_rec, void *stream) {
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  int dev = 0;
+  HIP_CHECK(hipGetDevice(&dev));
+  void *ws = static_scratch(dev);
+  const size_t need = p.workspace_bytes(FWD_MODE_FORWARD), flag_off = a256(need);
+  if (flag_off + 256 > (size_t)FWD_STATIC_SCRATCH_BYTES)
+    fail(FWD_ERR_INVALID_ARG, "forward workspace of " + std::to_string(need) +
+                                  " bytes exceeds the static scratch of " +
+                                  std::to_string((size_t)FWD_STATIC_SCRATCH_BYTES) + " bytes");
+  if (vol && vol_bytes < p.volume_bytes()) fail(FWD_ERR_INVALID_ARG, "volume buffer too small");
+  // everything the run uses must already be on this device: building the
+  // tables or the entry lists would allocate
+  Dev *dp = static_cast<Dev *>(p.dev);
+  if (!dp || dp->device != dev || dp->model_version != p.model_version ||
+      dp->basis_version != p.basis_version || dp->list_key != lists_key(p))
+    fail(FWD_ERR_STATE, "plan tables not resident on this device for the current model and "
+                        "tiling: run fwd_forward once first");
+  Dev &d = *dp;
+  const WS w = carve(p, ws);
+  zero_state(p, w, ws, vol, FWD_MODE_FORWARD, st);
+  run_steps_any(p, d, w, vol, false, p.nt, st, true);
+  flush_any(p, d, w, vol, false, st);
+  dev_run_receivers(p, ws, E_rec, stream);
+  int *flag = reinterpret_cast<int *>(static_cast<char *>(ws) + flag_off);
+  hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, st, flag, 0);
+  const size_t n = 2 * (size_t)p.ns * p.nr * p.ncomp * p.nf();
+  hipLaunchKernelGGL(k_nonfinite, dim3((unsigned)std::min<size_t>((n + 255) / 256, 1024)),
+                     dim3(256), 0, st, E_rec, n, flag);
+  HIP_CHECK(hipGetLastError());
+  int bad = 0;
+  HIP_CHECK(hipMemcpyAsync(&bad, flag, sizeof bad, hipMemcpyDeviceToHost, st));
+  HIP_CHECK(hipStreamSynchronize(st));
+  if (bad) fail(FWD_ERR_NONFINITE, "non-finite field: unstable run (dt above the CFL bound?)");
 }
 
 void dev_checkpoint(Plan &p, const void *ws, const void *vol, void *snap, int save, void *stream) {

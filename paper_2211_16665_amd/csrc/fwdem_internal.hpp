@@ -162,6 +162,7 @@ void td_edge_weights(const Plan &p, std::vector<double> &W);
 void dev_release(Plan &p);
 void dev_forward(Plan &p, void *ws, size_t ws_bytes, void *vol, size_t vol_bytes,
                  double *E_rec, void *stream);
+void dev_forward_static(Plan &p, void *vol, size_t vol_bytes, double *E_rec, void *stream);
 void dev_run_begin(Plan &p, void *ws, size_t ws_bytes, void *vol, size_t vol_bytes,
                    void *stream);
 void dev_run_steps(Plan &p, void *ws, void *vol, int nsteps, void *stream);

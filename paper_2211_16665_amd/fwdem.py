@@ -36,6 +36,8 @@ FWD_MODE_FORWARD, FWD_MODE_ADJOINT = 0, 1
  FWD_OPT_SCHEDULE, FWD_OPT_ZCHUNK, FWD_OPT_TILE_ORDER, FWD_OPT_VECTOR_H,
  FWD_OPT_VTI_GRADIENT, FWD_OPT_FD_ORDER, FWD_OPT_LEAN) = range(15)
 
+FWD_STATIC_SCRATCH_BYTES = 32 << 20       # the static workspace of fwd_forward_static
+
 ACC_MODES = {"f64": FWD_ACC_F64, "kahan": FWD_ACC_KAHAN, "f32": FWD_ACC_F32}
 DTYPES = {"f32": FWD_F32, "f64": FWD_F64}
 
@@ -88,6 +90,7 @@ SIGNATURES = {
     "fwd_workspace_size": (c_int, [c_void_p, c_int, POINTER(c_size_t)]),
     "fwd_volume_size": (c_int, [c_void_p, POINTER(c_size_t)]),
     "fwd_forward": (c_int, [c_void_p, c_void_p, c_size_t, c_void_p, c_size_t, c_void_p, c_void_p]),
+    "fwd_forward_static": (c_int, [c_void_p, c_void_p, c_size_t, c_void_p, c_void_p]),
     "fwd_run_begin": (c_int, [c_void_p, c_void_p, c_size_t, c_void_p, c_size_t, c_void_p]),
     "fwd_run_steps": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_void_p]),
     "fwd_run_receivers": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
@@ -322,6 +325,17 @@ class Plan:
         check(self.lib.fwd_forward(self.handle, _ptr(ws), ws.numel(), _ptr(vol),
                                    0 if vol is None else vol.numel(), _ptr(E), _stream(stream)))
         return (E, vol) if want_volume else E
+
+    def forward_static(self, vol=None, out=None, stream=None):
+        """fwd_forward_static: the forward run with the workspace in the
+        library's static device array (no device allocation inside the
+        call; ``out``, a complex128 [ns][nr][ncomp][nf] tensor, avoids the
+        binding's own).  The plan's tables must be resident: call
+        ``forward`` once first."""
+        E = self.rec_buffer() if out is None else out
+        check(self.lib.fwd_forward_static(self.handle, _ptr(vol), 0 if vol is None else vol.numel(),
+                                          _ptr(E), _stream(stream)))
+        return E
 
     def run_begin(self, vol=None, stream=None):
         ws = self.workspace(FWD_MODE_FORWARD)

@@ -251,3 +251,9 @@ def test_order4_option_rules(lib):
     assert e.value.status == 8
     p.set_model(w.rho)
     assert np.isclose(p.info.dt, dt2 * 6.0 / 7.0, rtol=1e-12)
+
+
+def test_static_scratch_size_matches_header():
+    hdr = open(os.path.join(ROOT, "include", "fwdem.h")).read()
+    m = re.search(r"#define FWD_STATIC_SCRATCH_BYTES \((\d+)u << (\d+)\)", hdr)
+    assert m and int(m.group(1)) << int(m.group(2)) == fw.FWD_STATIC_SCRATCH_BYTES
