@@ -241,10 +241,11 @@ def set_tiling(plan, spec):
             plan.set_option(getattr(fw, "FWD_OPT_" + key), int(v))
 
 
-def measured_traffic(kernel_tag, summary):
+def measured_traffic(kernel_tag, summary, tiling=None):
     """HBM bytes per launch of a kernel from a committed counter summary
-    (profiles/<summary>), or None if there is none, it covers another
-    kernel, or the device source changed since it was taken."""
+    (profiles/<summary>, lines "- traffic `<kernel>`: `<bytes>`"), or None if
+    there is none, it covers no such kernel or another tiling, or the device
+    source changed since it was taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", summary)
     src = os.path.join(ROOT, "paper_2211_16665_amd", "csrc", "device.hip")
@@ -254,11 +255,14 @@ def measured_traffic(kernel_tag, summary):
     for line in open(path):
         if ":" in line and line.startswith("- "):
             k, v = line[2:].split(":", 1)
-            vals[k.strip()] = v.strip().strip("`")
+            vals[k.strip().replace("`", "")] = v.strip().strip("`")
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    if vals.get("device_source_sha256") != sha or vals.get("kernel") != kernel_tag:
+    key = "traffic " + kernel_tag
+    if vals.get("device_source_sha256") != sha or key not in vals:
         return None
-    return float(vals["traffic_bytes_per_launch"]), vals.get("tiling", "")
+    if tiling is not None and vals.get("tiling") != tiling:
+        return None
+    return float(vals[key]), vals.get("tiling", "")
 
 
 def batched_vs_plain(window=200):
@@ -694,7 +698,8 @@ def large_window(args):
     kern = kernel_records(stats, gmax, nx, ny, nz, w.npml, nf, tsize, accsize, kb, "KAHAN"
                           if acc == "kahan" else acc.upper())
     dom = max(kern, key=lambda k: kern[k]["ms_per_step"])
-    mt = measured_traffic(kern[dom]["kernel"], "pmc_large_e_update.md")
+    mt = measured_traffic(kern[dom]["kernel"], "pmc_large_step_kernels.md",
+                          ",".join(str(tuned[k.lower()]) for k in TILING_KEYS))
     desc = (f"c5_large gradient window: 400x400x200 stretched grid (100 m core, ratio 1.05), "
             f"random log-normal sediment (corr. 500 m) with a 100 ohm-m 2x2 km reservoir, "
             f"8 freqs 0.1-2 Hz, {w.ns} x-dipoles in {len(groups)} groups of <= {gmax} "
