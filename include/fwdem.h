@@ -317,8 +317,14 @@ enum {
                                 1: one fused launch per step -- each block owns a block_x x
                                 block_y column tile and a chunk of FWD_OPT_ZCHUNK planes, stages
                                 E and H planes with their halo in LDS and marches up in z,
-                                recomputing the H halo of its tile.  Same arithmetic per edge:
-                                results equal those of schedule 0 bit for bit */
+                                recomputing the H halo of its tile;
+                                2: persistent -- one cooperative launch runs up to 4096 steps,
+                                every block looping over the tiles of schedule 0 (one node per
+                                thread) through the H update, the E update and the block
+                                transform, with a grid-wide barrier between phases (order 2,
+                                transform block 8 or 16, vector widths forced to 1).
+                                Same arithmetic per edge: results equal those of schedule 0 bit
+                                for bit */
   FWD_OPT_ZCHUNK = 9,        /* planes per block of the fused schedule: 1 .. 64 (default 8) */
   FWD_OPT_TILE_ORDER = 10,   /* 0 (default): tiles numbered x fastest; 1: z fastest, so the
                                 blocks of neighbouring planes run side by side */
@@ -334,11 +340,15 @@ enum {
                                 and the basis (call fwd_set_model again); order 4 runs the
                                 two-kernel schedule with vector widths 1 and rejects other
                                 SCHEDULE / VECTOR / VECTOR_H values. */
-  FWD_OPT_LEAN = 14          /* 1 (default): blocks of the two-kernel schedule whose tile lies
+  FWD_OPT_LEAN = 14,         /* 1 (default): blocks of the two-kernel schedule whose tile lies
                                 inside the CPML layers' inner boundary take an update path with
                                 no CPML or wall logic; 0: every block takes the general path.
                                 The arithmetic per edge is the same: results are equal bit for
                                 bit. */
+  FWD_OPT_BARRIER_US = 15    /* persistent schedule: longest wait of a block at one grid barrier,
+                                microseconds (default 5e6).  A longer wait (or a block that
+                                gave up) ends the launch: every block returns and the call
+                                reports FWD_ERR_HIP.  The run's state is then undefined. */
 };
 fwd_status fwd_set_option(fwd_plan *plan, int key, double value);
 fwd_status fwd_get_option(const fwd_plan *plan, int key, double *value);

@@ -309,9 +309,13 @@ fwd_status fwd_set_option(fwd_plan *h, int key, double value) {
         p.vx = v;
         break;
       case FWD_OPT_SCHEDULE:
-        if (v != 0 && v != 1) fail(FWD_ERR_INVALID_ARG, "schedule option in {0, 1}");
+        if (v != 0 && v != 1 && v != 2) fail(FWD_ERR_INVALID_ARG, "schedule option in {0, 1, 2}");
         if (v != 0 && p.fd_order == 4) fail(FWD_ERR_INVALID_ARG, "order 4 runs with schedule 0");
         p.sched = v;
+        break;
+      case FWD_OPT_BARRIER_US:
+        if (!(value >= 0.0)) fail(FWD_ERR_INVALID_ARG, "barrier wait limit >= 0 microseconds");
+        p.barrier_us = value;
         break;
       case FWD_OPT_ZCHUNK:
         if (v < 1 || v > 64) fail(FWD_ERR_INVALID_ARG, "planes per block in [1, 64]");
@@ -374,6 +378,7 @@ fwd_status fwd_get_option(const fwd_plan *h, int key, double *value) {
       case FWD_OPT_VTI_GRADIENT: *value = p.vti_grad; break;
       case FWD_OPT_FD_ORDER: *value = p.fd_order; break;
       case FWD_OPT_LEAN: *value = p.lean; break;
+      case FWD_OPT_BARRIER_US: *value = p.barrier_us; break;
       default: fail(FWD_ERR_INVALID_ARG, "unknown option");
     }
   });

@@ -141,8 +141,8 @@ struct StepArgs {
 // consecutive planes of a column tile run side by side, so the plane
 // neighbours a stencil reads are still in L2).  Returns the tile index.
 template <typename T>
-__device__ __forceinline__ int tile_of(const StepArgs<T> &A, int &bx, int &by, int &bz, int &s) {
-  uint32_t b = blockIdx.x;
+__device__ __forceinline__ int tile_of_b(const StepArgs<T> &A, uint32_t b, int &bx, int &by,
+                                         int &bz, int &s) {
   if (A.xcd) {
     const uint32_t q = (uint32_t)A.nblocks >> 3, r = (uint32_t)A.nblocks & 7u;
     const uint32_t x = b & 7u, local = b >> 3;
@@ -162,6 +162,10 @@ __device__ __forceinline__ int tile_of(const StepArgs<T> &A, int &bx, int &by, i
     bz = (int)u;
   }
   return (int)tile;
+}
+template <typename T>
+__device__ __forceinline__ int tile_of(const StepArgs<T> &A, int &bx, int &by, int &bz, int &s) {
+  return tile_of_b(A, blockIdx.x, bx, by, bz, s);
 }
 
 // Index of the step a launch computes: one uniform scalar load of the
@@ -1305,25 +1309,25 @@ __global__ void __launch_bounds__(256) k_step(StepArgs<T> A) {
 // E component (grid z); threads off the component's lattice return.  A
 // thread holds only its KB samples; the block's twiddles (all frequencies)
 // are staged once in LDS and read as broadcasts.
-template <typename T, int ACC, bool ADJ, int KB, bool FLUSH>
-__global__ void __launch_bounds__(256) k_transform(StepArgs<T> A) {
-  extern __shared__ double2 s_tw[];          // [nf][KB] twiddles of the block
-  const int s = blockIdx.y, c = blockIdx.z;
-  const int m_last = A.step[0] + 1;          // the newest sample
-  const int r_end = m_last & (KB - 1);
-  const int cnt = FLUSH ? r_end : KB;
-  if (FLUSH ? cnt == 0 : r_end != 0) return; // uniform: the whole grid returns
-  const int nf = A.nf, nt = A.nt, first = m_last - cnt + 1;
-  {
-    const double2 *tw = ADJ ? A.Q : A.zE;
-    for (int e = threadIdx.x; e < nf * KB; e += blockDim.x) {
-      const int kf = e / KB, t = e - kf * KB;
-      s_tw[e] = t < cnt ? tw[(int64_t)(first - 1 + t) * nf + kf] : make_double2(0.0, 0.0);
-    }
+// The block's twiddles (all frequencies) in LDS: s_tw[kf * KB + t] for the
+// samples first .. first+cnt-1 (zero beyond cnt); the caller synchronises.
+template <typename T, bool ADJ, int KB>
+__device__ __forceinline__ void stage_twiddles(const StepArgs<T> &A, double2 *s_tw, int first,
+                                               int cnt, int tid, int nthr) {
+  const double2 *tw = ADJ ? A.Q : A.zE;
+  const int nf = A.nf;
+  for (int e = tid; e < nf * KB; e += nthr) {
+    const int kf = e / KB, t = e - kf * KB;
+    s_tw[e] = t < cnt ? tw[(int64_t)(first - 1 + t) * nf + kf] : make_double2(0.0, 0.0);
   }
-  __syncthreads();
-  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= A.F) return;
+}
+
+// The block transform of node q (padded layout), component c of source s:
+// the cnt samples ending at m_last, twiddles staged in s_tw.
+template <typename T, int ACC, bool ADJ, int KB, bool FLUSH>
+__device__ __forceinline__ void transform_node(const StepArgs<T> &A, int64_t q, int s, int c,
+                                               int m_last, int cnt, const double2 *s_tw) {
+  const int nf = A.nf, nt = A.nt, first = m_last - cnt + 1;
   const uint32_t qq = (uint32_t)q;
   const uint32_t k = fdiv(qq, A.dplane), rem = qq - k * (uint32_t)A.plane;
   const uint32_t j = fdiv(rem, A.dpx), i = rem - j * (uint32_t)A.PX;
@@ -1356,7 +1360,7 @@ __global__ void __launch_bounds__(256) k_transform(StepArgs<T> A) {
       double2 sum = make_double2(0.0, 0.0);
 #pragma unroll
       for (int t = 0; t < KB; ++t) {
-        if (t >= cnt) break;
+        if (FLUSH && t >= cnt) break;
         const double2 zt = z[t];
         sum.x = fma((double)val[t], zt.x, sum.x);
         sum.y = fma((double)val[t], zt.y, sum.y);
@@ -1385,7 +1389,7 @@ __global__ void __launch_bounds__(256) k_transform(StepArgs<T> A) {
       double sx = 0.0, sy = 0.0;
 #pragma unroll
       for (int t = 0; t < KB; ++t) {
-        if (t >= cnt) break;
+        if (FLUSH && t >= cnt) break;
         const double2 qt = Qt[t];
         sx = fma((double)val[t], qt.x, sx);
         sy = fma((double)val[t], qt.y, sy);
@@ -1394,6 +1398,135 @@ __global__ void __launch_bounds__(256) k_transform(StepArgs<T> A) {
     }
     double *g = A.gedge + ((int64_t)s * 3 + c) * F + q;
     *g = *g + re;
+  }
+}
+
+template <typename T, int ACC, bool ADJ, int KB, bool FLUSH>
+__global__ void __launch_bounds__(256) k_transform(StepArgs<T> A) {
+  extern __shared__ double2 s_tw[];          // [nf][KB] twiddles of the block
+  const int m_last = A.step[0] + 1;          // the newest sample
+  const int r_end = m_last & (KB - 1);
+  const int cnt = FLUSH ? r_end : KB;
+  if (FLUSH ? cnt == 0 : r_end != 0) return; // uniform: the whole grid returns
+  stage_twiddles<T, ADJ, KB>(A, s_tw, m_last - cnt + 1, cnt, threadIdx.x, blockDim.x);
+  __syncthreads();
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= A.F) return;
+  transform_node<T, ACC, ADJ, KB, FLUSH>(A, q, blockIdx.y, blockIdx.z, m_last, cnt, s_tw);
+}
+
+// ---------------------------------------------------------------------------
+// Persistent schedule (FWD_OPT_SCHEDULE = 2): one cooperative launch runs
+// nsteps leapfrog steps.  Every block loops over the tiles of a phase -- the
+// H update, the E update, and the block transform after a step that closes
+// a transform block -- with a grid-wide barrier between phases.  The tiles,
+// their entry lists and the per-node arithmetic are those of the two-kernel
+// schedule, so the results are the same bit for bit.
+//
+// The barrier: the first thread of each block reads the generation, then
+// arrives on the counter (device-scope atomics; a release fence first, so
+// the block's stores, complete at workgroup scope after __syncthreads, reach
+// the other XCDs); the last block to arrive resets the counter and moves the
+// generation on (release); the others poll the generation with acquire loads
+// and pass when it moves.  The launch is cooperative (the runtime refuses a
+// grid whose blocks cannot all be resident at once) and sized from the
+// occupancy of the instantiation launched.  A wait longer than `limit`
+// wall-clock ticks, or the abort flag set by another block, ends the wait:
+// the block sets the flag and returns, so every block exits and the host
+// reports the abandoned run.
+// ---------------------------------------------------------------------------
+struct Bar {
+  unsigned *count, *gen;
+  int *abort;
+  uint64_t limit;     // wall-clock ticks a block may wait at one barrier
+};
+
+__device__ __forceinline__ bool grid_sync(const Bar &B) {
+  __shared__ int s_ok;
+  __syncthreads();
+  if (threadIdx.x == 0 && threadIdx.y == 0) {
+    int ok = 1;
+    const unsigned g = __hip_atomic_load(B.gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    const unsigned a = __hip_atomic_fetch_add(B.count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (a == gridDim.x - 1) {
+      __hip_atomic_store(B.count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(B.gen, g + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      const uint64_t t0 = wall_clock64();
+      while (__hip_atomic_load(B.gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+        if (__hip_atomic_load(B.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
+            wall_clock64() - t0 > B.limit) {
+          __hip_atomic_store(B.abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          ok = 0;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    s_ok = ok;
+  }
+  __syncthreads();
+  return s_ok != 0;
+}
+
+// A: E-update arguments (tiles of the E update, its entry lists); Ah: the
+// H update's (its tiling and, with INJ, its table of magnetic sources).  The
+// host equalised the step counters; block 0 leaves both at the last step.
+template <typename T, bool HIST, int ACC, bool ADJ, int KB, bool INJ>
+__global__ void __launch_bounds__(256) k_persist(StepArgs<T> A, StepArgs<T> Ah, int nsteps, Bar B) {
+  extern __shared__ double2 s_tw[];          // twiddles of a closing block
+  const int tid = threadIdx.y * blockDim.x + threadIdx.x, nthr = blockDim.x * blockDim.y;
+  const int n0 = A.step[0] + 1;
+  const uint32_t nq = (uint32_t)((A.F + nthr - 1) / nthr);   // transform tiles per source, component
+  for (int t = 0; t < nsteps; ++t) {
+    const int n = n0 + t, par = n & 1;
+    for (uint32_t vb = blockIdx.x; vb < (uint32_t)Ah.nblocks; vb += gridDim.x) {
+      int bx, by, bz, s;
+      const int b = tile_of_b(Ah, vb, bx, by, bz, s);
+      const int i0 = bx * blockDim.x + threadIdx.x, j = by * blockDim.y + threadIdx.y, k = bz;
+      if (i0 > A.nx || j > A.ny || k > A.nz) continue;
+      int lo = 0, hi = 0;
+      if constexpr (INJ) entry_slice(Ah, b, n, lo, hi);
+      if (interior_tile(Ah, bx, by, k, blockDim.x))
+        h_vec<T, 1, INJ, true>(Ah, half_of(Ah, par, s), half_of(Ah, par ^ 1, s), i0, j,
+                               __builtin_amdgcn_readfirstlane(k), lo, hi, s, n);
+      else
+        h_vec<T, 1, INJ, false>(Ah, half_of(Ah, par, s), half_of(Ah, par ^ 1, s), i0, j, k, lo, hi,
+                                s, n);
+    }
+    if (!grid_sync(B)) return;
+    for (uint32_t vb = blockIdx.x; vb < (uint32_t)A.nblocks; vb += gridDim.x) {
+      int bx, by, bz, s;
+      const int b = tile_of_b(A, vb, bx, by, bz, s);
+      const int i0 = bx * blockDim.x + threadIdx.x, j = by * blockDim.y + threadIdx.y, k = bz;
+      if (i0 > A.nx || j > A.ny || k > A.nz) continue;
+      if (interior_tile(A, bx, by, k, blockDim.x))
+        e_vec<T, HIST, 1, true>(A, s, b, half_of(A, par, s), half_of(A, par ^ 1, s),
+                                half_of(A, 0, s), i0, j, __builtin_amdgcn_readfirstlane(k), n);
+      else
+        e_vec<T, HIST, 1, false>(A, s, b, half_of(A, par, s), half_of(A, par ^ 1, s),
+                                 half_of(A, 0, s), i0, j, k, n);
+    }
+    if (!grid_sync(B)) return;
+    if (HIST && (n + 1) % KB == 0) {
+      const int m = n + 1;
+      stage_twiddles<T, ADJ, KB>(A, s_tw, m - KB + 1, KB, tid, nthr);
+      __syncthreads();
+      const uint32_t total = nq * (uint32_t)A.ns * 3u;
+      for (uint32_t vb = blockIdx.x; vb < total; vb += gridDim.x) {
+        const uint32_t qc = vb % nq, rest = vb / nq;
+        const int s = (int)(rest % (uint32_t)A.ns), c = (int)(rest / (uint32_t)A.ns);
+        const int64_t q = (int64_t)qc * nthr + tid;
+        if (q < A.F) transform_node<T, ACC, ADJ, KB, false>(A, q, s, c, m, KB, s_tw);
+      }
+      if (!grid_sync(B)) return;
+    }
+  }
+  if (blockIdx.x == 0 && tid == 0) {          // counters r = 0 and 1 of the workspace
+    const_cast<int *>(A.step)[0] = n0 + nsteps - 1;
+    A.step_w[0] = n0 + nsteps - 1;
   }
 }
 
@@ -2099,6 +2232,8 @@ struct WS {
   double2 *racc;
   int *step;            // [2] step counters (last completed step)
   int *flushed;         // last sample already added by a flush
+  unsigned *bar;        // persistent schedule: barrier counter and generation
+  int *abort;           // persistent schedule: a barrier wait was abandoned
   void *hist;
   double *gedge;
 };
@@ -2116,6 +2251,8 @@ static WS carve(const Plan &p, void *ws) {
   b += a256((size_t)p.ns * p.rn_c.size() * p.nf() * 16);
   w.step = reinterpret_cast<int *>(b);
   w.flushed = w.step + 2;
+  w.bar = reinterpret_cast<unsigned *>(w.step + 4);
+  w.abort = w.step + 6;
   b += 256;
   w.hist = b;
   b += a256((size_t)p.ns * p.hist_elems_per_source() * p.tsize());
@@ -2144,7 +2281,9 @@ static Tiling tiling(const Plan &p, bool h_update = false) {
     t.nbz = (p.nz + p.kz - 1) / p.kz;
     t.lds = 3 * ((size_t)(p.bx + 2) * (p.by + 2) + (size_t)(p.bx + 1) * (p.by + 1)) * p.tsize();
   } else {
-    const int v = h_update ? p.vxh : p.vx;   // the H update has its own vector width
+    // the H update has its own vector width; the persistent schedule runs
+    // one node per thread
+    const int v = p.sched == 2 ? 1 : (h_update ? p.vxh : p.vx);
     t.vx = v == 1 ? 1 : (int)(16 / p.tsize());
     t.nbx = (p.NX + p.bx * t.vx - 1) / (p.bx * t.vx);
     t.nby = (p.NY + p.by - 1) / p.by;
@@ -2516,6 +2655,90 @@ static void flush_any(Plan &p, Dev &d, const WS &w, void *vol, bool adj, hipStre
     flush_t<float>(p, d, w, vol, adj, st);
 }
 
+// The persistent schedule: cooperative launches of up to 4096 steps each,
+// the grid sized from the occupancy of the instantiation (at most one block
+// per tile of the largest phase).
+template <typename T, bool HIST, int ACC, bool ADJ, int KB, bool INJ>
+static void launch_persist(const StepArgs<T> &A, const StepArgs<T> &Ah, int nsteps, const Bar &B,
+                           dim3 block, size_t lds, hipStream_t st) {
+  const void *fn = reinterpret_cast<const void *>(&k_persist<T, HIST, ACC, ADJ, KB, INJ>);
+  int dev = 0, per_cu = 0, cus = 0;
+  HIP_CHECK(hipGetDevice(&dev));
+  HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, (int)(block.x * block.y), lds));
+  if (per_cu < 1) fail(FWD_ERR_UNSUPPORTED, "persistent schedule: no block fits on a compute unit");
+  const int64_t tiles = std::max<int64_t>(A.nblocks, Ah.nblocks);
+  const unsigned grid = (unsigned)std::min<int64_t>((int64_t)per_cu * cus, tiles);
+  StepArgs<T> a = A, ah = Ah;
+  Bar b = B;
+  for (int done = 0; done < nsteps;) {
+    int m = std::min(4096, nsteps - done);
+    void *args[] = {&a, &ah, &m, &b};
+    HIP_CHECK(hipLaunchCooperativeKernel(fn, dim3(grid), block, args, (unsigned)lds, st));
+    done += m;
+  }
+}
+
+template <typename T, bool HIST, int ACC, bool ADJ, bool INJ>
+static void launch_persist_kb(const StepArgs<T> &A, const StepArgs<T> &Ah, int nsteps,
+                              const Bar &B, dim3 block, size_t lds, hipStream_t st, int kb) {
+  if (kb == 8) launch_persist<T, HIST, ACC, ADJ, 8, INJ>(A, Ah, nsteps, B, block, lds, st);
+  else if (kb == 16) launch_persist<T, HIST, ACC, ADJ, 16, INJ>(A, Ah, nsteps, B, block, lds, st);
+  else fail(FWD_ERR_UNSUPPORTED, "persistent schedule: transform block 8 or 16");
+}
+
+template <typename T>
+static void run_persistent(Plan &p, Dev &d, const WS &w, void *vol, bool adj, int nsteps,
+                           hipStream_t st) {
+  if (nsteps <= 0) return;
+  if (p.fd_order != 2) fail(FWD_ERR_UNSUPPORTED, "persistent schedule: order 2 only");
+  StepArgs<T> A = make_args<T>(p, d, w, vol, adj, 0);
+  StepArgs<T> Ah = A;
+  const Tiling th = tiling(p, true);
+  set_grid(Ah, th.nbx, th.nby, th.nbz);
+  const bool inj = adj && d.nh > 0;
+  Ah.tile_tab = inj ? d.tile_tab[2] : nullptr;
+  Ah.tl_off = inj ? d.tl_off[2] : nullptr;
+  Ah.tl_ent = inj ? d.tl_ent[2] : nullptr;
+  A.xcd = Ah.xcd = 0;                      // virtual blocks: no dispatch-order remap
+  int dev = 0, khz = 0;
+  HIP_CHECK(hipGetDevice(&dev));
+  HIP_CHECK(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+  const Bar B{w.bar, w.bar + 1, w.abort, (uint64_t)(p.barrier_us * (double)khz / 1000.0)};
+  const dim3 block(p.bx, p.by);
+  const bool hist = vol != nullptr;
+  const size_t lds = hist ? (size_t)p.nf() * p.kb * sizeof(double2) : 0;
+  if (!hist) {
+    launch_persist<T, false, ACC_F64, false, 8, false>(A, Ah, nsteps, B, block, lds, st);
+  } else {
+#define FWD_PERSIST(ACCV)                                                                   \
+  do {                                                                                      \
+    if (!adj) launch_persist_kb<T, true, ACCV, false, false>(A, Ah, nsteps, B, block, lds, st, p.kb); \
+    else if (!inj) launch_persist_kb<T, true, ACCV, true, false>(A, Ah, nsteps, B, block, lds, st, p.kb); \
+    else launch_persist_kb<T, true, ACCV, true, true>(A, Ah, nsteps, B, block, lds, st, p.kb); \
+  } while (0)
+    switch (p.acc) {
+      case FWD_ACC_F64: FWD_PERSIST(ACC_F64); break;
+      case FWD_ACC_KAHAN: FWD_PERSIST(ACC_KAHAN); break;
+      default: FWD_PERSIST(ACC_F32);
+    }
+#undef FWD_PERSIST
+  }
+  p.host_step += nsteps;
+}
+
+// A persistent run abandoned at a barrier (its wait exceeded the limit) is an
+// error of the call that ran it.
+static void check_abort(Plan &p, const WS &w, hipStream_t st) {
+  if (p.sched != 2) return;
+  int bad = 0;
+  HIP_CHECK(hipMemcpyAsync(&bad, w.abort, sizeof bad, hipMemcpyDeviceToHost, st));
+  HIP_CHECK(hipStreamSynchronize(st));
+  if (bad)
+    fail(FWD_ERR_HIP, "persistent schedule: a grid barrier wait exceeded " +
+                          std::to_string(p.barrier_us) + " us; the run was abandoned");
+}
+
 // Run nsteps steps from the current position.  The device counters hold the
 // step index for the kernels; the host keeps the same count (p.host_step)
 // to know which steps close a transform block.
@@ -2528,6 +2751,10 @@ static void run_steps_t(Plan &p, Dev &d, const WS &w, void *vol, bool adj, int n
   // both counters hold the last completed step; the steps then alternate
   // (r = counter read by the next step)
   hipLaunchKernelGGL(k_equalize, dim3(1), dim3(64), 0, st, w.step);
+  if (p.sched == 2) {
+    run_persistent<T>(p, d, w, vol, adj, nsteps, st);
+    return;
+  }
   int r = 0;
   // graphs hold an even number of steps (they start and end at r = 0) and a
   // whole number of transform blocks (every replay starts at the same phase)
@@ -2674,6 +2901,7 @@ void dev_run_steps(Plan &p, void *ws, void *vol, int nsteps, void *stream) {
   if (nsteps < 0 || nsteps > p.nt) fail(FWD_ERR_INVALID_ARG, "nsteps outside [0, nt]");
   Dev &d = D(p);
   run_steps_any(p, d, carve(p, ws), vol, false, nsteps, st);
+  check_abort(p, carve(p, ws), st);
 }
 
 void dev_run_receivers(Plan &p, void *ws, double *E_rec, void *stream) {
@@ -2716,6 +2944,7 @@ void dev_forward(Plan &p, void *ws, size_t ws_bytes, void *vol, size_t vol_bytes
   p.last_ms = ms;
   p.last_steps = p.nt;
   collect_kernel_stats(d);
+  check_abort(p, carve(p, ws), st);
   check_finite(reinterpret_cast<double2 *>(E_rec), (size_t)p.ns * p.nr * p.ncomp * p.nf(), st);
 }
 
@@ -2882,6 +3111,7 @@ void dev_adjoint(Plan &p, void *ws, size_t ws_bytes, const void *vol, const doub
   p.last_ms = ms;
   p.last_steps = p.nt;
   collect_kernel_stats(d);
+  check_abort(p, w, st);
   check_finite(dst, (size_t)n, st);
 }
 
@@ -3189,6 +3419,19 @@ double dev_autotune(Plan &p, void *ws, size_t ws_bytes, void *vol, size_t vol_by
         c.kz = kz;
         consider(c);
       }
+  }
+  // the persistent schedule (transform blocks of 8 or 16 only)
+  if (!o4 && (!vol || p.kb == 8 || p.kb == 16)) {
+    const TuneCand base = best;
+    const int pers[][2] = {{64, 4}, {32, 8}};
+    for (auto &sh : pers) {
+      TuneCand c = base;
+      c.sched = 2;
+      c.bx = sh[0];
+      c.by = sh[1];
+      c.vx = c.vxh = 1;
+      consider(c);
+    }
   }
   // stage 5: the transform block
   {

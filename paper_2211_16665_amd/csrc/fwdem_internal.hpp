@@ -118,6 +118,7 @@ struct Plan {
   int order = 0;                         // tile numbering: 0 x fastest, 1 z fastest
   int vti_grad = 0;                      // 1: gradients as [d/d ln rho_h, d/d ln rho_v]
   int lean = 1;                          // interior tiles take the lean update paths
+  double barrier_us = 5.0e6;             // persistent schedule: longest wait at a grid barrier
   int fd_order = 2;                      // order of the staggered differences: 2 or 4
 
   // ---- device side (managed in device.hip) ----

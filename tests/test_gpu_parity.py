@@ -365,6 +365,9 @@ TILINGS = [
     dict(schedule=0, block_y=4, block_x=16, xcd_remap=1, vector=1, vector_h=4),
     dict(schedule=0, block_y=8, block_x=32, xcd_remap=0, vector=4, vector_h=4, tile_order=1),
     dict(schedule=1, block_y=8, block_x=16, xcd_remap=1, zchunk=3, tile_order=1),
+    # persistent schedule: one cooperative launch for many steps
+    dict(schedule=2, block_y=4, block_x=64, xcd_remap=1),
+    dict(schedule=2, block_y=8, block_x=32, xcd_remap=0, tile_order=1),
 ]
 
 
@@ -436,6 +439,46 @@ def test_lean_interior_path_on_the_marine_grid(dtype):
                 assert rel(a, b) < 1e-12
             else:
                 assert same(a, b)
+
+
+@pytest.mark.parametrize("steps,volume", [(96, True), (200, False), (200, True)])
+def test_persistent_schedule_on_the_marine_grid(steps, volume):
+    """The persistent schedule (one cooperative launch, grid barriers between
+    the H, E and transform phases) against the two-kernel schedule on a
+    window of the full marine grid: receivers, and with the volume transform
+    also the volume, gradient and adjoint receiver transform, bit for bit."""
+    w = with_window(c2_marine1d(), steps)
+    say(f"persistent schedule on the marine grid, {steps} steps, volume {volume}")
+    if not volume:
+        E0 = gpu_forward(w, "f32", "f64")[1]
+        _, E2, _ = gpu_forward(w, "f32", "f64", schedule=2, block_x=64, block_y=4)
+        assert same(E0, E2)
+        return
+    p = fw.Plan.from_workload(w, field_dtype="f64")
+    p.set_model(w.rho)
+    d = p.forward().cpu().numpy() * 1.01
+    ref = _run_all(w, d, dict(schedule=0), True, "f32", "kahan")
+    out = _run_all(w, d, dict(schedule=2, block_x=32, block_y=8), True, "f32", "kahan")
+    for a, b in zip(ref, out):
+        assert same(a, b)
+
+
+def test_persistent_barrier_limit_abandons_the_run():
+    """A barrier wait limit of zero, set from the host, makes the persistent
+    launch give up at its first barrier: every block returns, the call
+    reports FWD_ERR_HIP, and the plan runs normally again afterwards."""
+    w = tiny(seed=9, npml=3, ns=2)
+    say("persistent schedule: a zero barrier limit abandons the run")
+    p = fw.Plan.from_workload(w, field_dtype="f32", acc_mode="f64")
+    p.set_option(fw.FWD_OPT_SCHEDULE, 2)
+    p.set_model(w.rho)
+    p.set_option(fw.FWD_OPT_BARRIER_US, 0)
+    with pytest.raises(fw.FwdError) as e:
+        p.forward()
+    assert e.value.status == 3 and "barrier" in str(e.value)
+    p.set_option(fw.FWD_OPT_BARRIER_US, 5e6)
+    E = p.forward().cpu().numpy()
+    assert same(E, gpu_forward(w, "f32", "f64")[1])
 
 
 def test_fused_graph_odd_chunks_and_schedule_switch():
