@@ -523,6 +523,51 @@ def order4_study(w_true, rho0, order2_s, tsize, accsize):
     return out
 
 
+def schedules_study(tuned, window=2000):
+    """The three schedules on a window of the marine workload (its first
+    ``window`` steps, FP32 fields, receiver and volume transforms): time per
+    step of the tuned two-kernel schedule, the fused schedule (one launch per
+    step) and the persistent schedule (one cooperative launch; at the
+    occupancy-sized grid and at one block per compute unit), each checked
+    bit for bit against the two-kernel receivers."""
+    import numpy as np
+    import torch
+    from paper_2211_16665_amd import fwdem as fw
+    from workloads import c2_marine1d, with_window
+    w = with_window(c2_marine1d(), window)
+    kb = tuned["dft_block"] if tuned["dft_block"] in (8, 16) else 8
+
+    def per_step(opts):
+        p = fw.Plan.from_workload(w, field_dtype="f32", acc_mode="f64")
+        for k, v in opts.items():
+            p.set_option(getattr(fw, "FWD_OPT_" + k), v)
+        p.set_model(w.rho)
+        vol = p.volume_buffer()
+        p.forward(vol=vol, want_volume=True)            # warm-up (graphs, lists)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        E, _ = p.forward(vol=vol, want_volume=True)
+        torch.cuda.synchronize()
+        us = (time.perf_counter() - t0) / window * 1e6
+        return us, E.cpu().numpy()
+
+    base = {k.upper(): tuned[k.lower()] for k in TILING_KEYS}
+    base["DFT_BLOCK"] = kb
+    us0, E0 = per_step(base)
+    out = {"window": window, "dft_block": kb, "two_kernel_tuned_us_per_step": us0}
+    runs = (("fused_64x4", dict(SCHEDULE=1, BLOCK_X=64, BLOCK_Y=4, ZCHUNK=4)),
+            ("fused_32x8", dict(SCHEDULE=1, BLOCK_X=32, BLOCK_Y=8, ZCHUNK=4)),
+            ("persistent_64x4", dict(SCHEDULE=2, BLOCK_X=64, BLOCK_Y=4)),
+            ("persistent_64x4_1_block_per_cu", dict(SCHEDULE=2, BLOCK_X=64, BLOCK_Y=4,
+                                                    PERSIST_BLOCKS=1)))
+    for name, opts in runs:
+        opts = dict(opts, VECTOR=1, VECTOR_H=1, XCD_REMAP=0, DFT_BLOCK=kb)
+        us, E = per_step(opts)
+        out[name] = {"us_per_step": us, "receivers_bitwise_equal": bool(np.array_equal(E, E0))}
+        log(f"schedules: {name} {out[name]}")
+    return out
+
+
 def adjoint_td_study(plan, resid, grad_basis, basis_s, npml, segment=500):
     """The time-domain adjoint (Appendix) on the bench workload: gradient time
     (forward with checkpoints, replay, reverse sweep) against the
@@ -760,7 +805,6 @@ def marine_gradient(args):
     tuned = {k.lower(): int(plan.get_option(getattr(fw, "FWD_OPT_" + k)))
              for k in TILING_KEYS + ("DFT_BLOCK",)}
     tuned["ms_per_forward_step"] = tune_ms
-    plan.set_option(fw.FWD_OPT_SAMPLE_EVERY, args.sample_every)
     grad = torch.zeros(plan.shape, dtype=torch.float64, device="cuda")
     stats = []
     resid_last = []
@@ -774,14 +818,21 @@ def marine_gradient(args):
         resid_last[:] = [resid]
         plan.adjoint(vol, resid, grad=grad)
 
+    # timed with no kernel sampling (each sampled step runs eagerly with
+    # events, ~0.6 ms extra on this small grid); one sampled step afterwards
+    # gives the kernel times
+    plan.set_option(fw.FWD_OPT_SAMPLE_EVERY, 0)
     step()
-    stats.clear()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.marine_steps):
         step()
     torch.cuda.synchronize()
     elapsed = (time.perf_counter() - t0) / args.marine_steps
+    plan.set_option(fw.FWD_OPT_SAMPLE_EVERY, args.sample_every)
+    stats.clear()
+    step()
+    plan.set_option(fw.FWD_OPT_SAMPLE_EVERY, 0)
     nz, ny, nx = plan.shape
     nt = plan.info.nt
     tsize = 4 if args.field_dtype == "f32" else 8
@@ -868,6 +919,8 @@ def main():
                     help="skip the marine workload's full gradient and the studies built on it")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched-vs-plain gradient-time comparison")
+    ap.add_argument("--no-schedules", action="store_true",
+                    help="skip the fused and persistent schedules' timing on the marine step")
     ap.add_argument("--no-td", action="store_true",
                     help="skip the time-domain adjoint study")
     ap.add_argument("--no-vti", action="store_true",
@@ -919,6 +972,8 @@ def main():
         out["marine1d"] = marine
         base_s = marine["gradient_s"]
         tsize = 4 if args.field_dtype == "f32" else 8
+        if not args.no_schedules:
+            out["schedules"] = schedules_study(tuned)
         if not args.no_td:
             out["adjoint_td"] = adjoint_td_study(plan, resid, grad, base_s, w_true.npml)
         if not args.no_vti:             # changes the plan's model: after the studies above

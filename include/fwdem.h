@@ -87,6 +87,11 @@ typedef struct {
   double cfl;                     /* fraction of the CFL bound used for dt (<= 0: 0.95) */
   double dt;                      /* > 0 fixes dt (s) instead of deriving it from the model */
   int nt;                         /* > 0 fixes the number of steps */
+  int src_kind;                   /* 0: electric dipoles, J = p delta(x - x_s), moments in A m;
+                                     1: magnetic dipoles, M = m delta(x - x_s) in the Faraday row
+                                     of eq. freq (M' = M, eq. mittet), moments in V m, injected
+                                     into the H update.  Every output is the field of the unit
+                                     source of that kind. */
 } fwd_plan_desc;
 
 typedef struct {
@@ -105,7 +110,10 @@ typedef struct {
 /* Tables readable by fwd_get_table (host copies; for tests and tools). */
 enum {
   FWD_TAB_WAVELET = 0,   /* [nt] w((n+1/2) dt) */
-  FWD_TAB_NORM = 1,      /* complex [nfreq]: sqrt(-i w / 2 w0) / W_k (E rows; H rows: 1 / W_k) */
+  FWD_TAB_NORM = 1,      /* complex [nfreq]: factor of the E rows; electric sources
+                            sqrt(-i w / 2 w0) / W_k with W_k = sum_n w_n z_k^{n+1/2}, magnetic
+                            1 / W^M_k with W^M_k = sum_n w_n z_k^n (H rows: either divided by
+                            sqrt(-i w / 2 w0)) */
   FWD_TAB_OMEGA = 2,     /* complex [nfreq]: Omega_k = (2/dt) sin(w'_k dt/2) */
   FWD_TAB_CPML_X = 3,    /* [6][nx+1]: kappa, b, a at integer nodes, then at half nodes (last unused) */
   FWD_TAB_CPML_Y = 4,
@@ -345,10 +353,14 @@ enum {
                                 no CPML or wall logic; 0: every block takes the general path.
                                 The arithmetic per edge is the same: results are equal bit for
                                 bit. */
-  FWD_OPT_BARRIER_US = 15    /* persistent schedule: longest wait of a block at one grid barrier,
+  FWD_OPT_BARRIER_US = 15,   /* persistent schedule: longest wait of a block at one grid barrier,
                                 microseconds (default 5e6).  A longer wait (or a block that
                                 gave up) ends the launch: every block returns and the call
                                 reports FWD_ERR_HIP.  The run's state is then undefined. */
+  FWD_OPT_PERSIST_BLOCKS = 16, /* persistent schedule: blocks per compute unit, 1 .. 32, or 0
+                                (default) for as many as the occupancy of the kernel allows */
+  FWD_OPT_BARRIER_SLEEP = 17 /* persistent schedule: pause between two polls of a waiting block,
+                                in units of 64 clock cycles, 1 (default) .. 64 */
 };
 fwd_status fwd_set_option(fwd_plan *plan, int key, double value);
 fwd_status fwd_get_option(const fwd_plan *plan, int key, double *value);

@@ -35,7 +35,7 @@ import numpy as np
 
 from .discretization import MU0, Setup, cell_gradient, edge_sigma_transpose, make_setup
 from .stencil import diff_e, diff_e_t, diff_h, diff_h_t
-from .stepping import receiver_nodes, source_injection
+from .stepping import receiver_nodes, source_injection, source_norms
 
 FIELDS = ("Ex", "Ey", "Ez", "Hx", "Hy", "Hz")
 # CPML memory variables: key -> (field it belongs to, axis of the derivative)
@@ -165,16 +165,22 @@ def adj_step(o, ad: dict) -> None:
 
 
 def forward_states(s: Setup, inj: list, tfun: np.ndarray, nt: int):
-    """E^0 .. E^nt of a driven run (fwd_step plus the injection
-    E -= ce w tfun[row, n] of oracle.stepping): list of (Ex, Ey, Ez)."""
+    """E^0 .. E^nt of a driven run (fwd_step plus the injections of
+    oracle.stepping: H += dt/mu w tfun[row, n] before the step for magnetic
+    entries, E -= ce w tfun[row, n] after it for electric ones): list of
+    (Ex, Ey, Ez)."""
     o = ops(s)
     st = zero_state(o)
     out = [tuple(np.zeros(o.shapes[c]) for c in ("Ex", "Ey", "Ez"))]
-    names = ("Ex", "Ey", "Ez")
+    names = FIELDS
     for n in range(nt):
+        for (c, k, j, i, w, row) in inj:
+            if c >= 3:
+                st[names[c]][k, j, i] += o.dtmu * w * tfun[row, n]
         fwd_step(o, st)
         for (c, k, j, i, w, row) in inj:
-            st[names[c]][k, j, i] -= s.ce[c][k, j, i] * w * tfun[row, n]
+            if c < 3:
+                st[names[c]][k, j, i] -= s.ce[c][k, j, i] * w * tfun[row, n]
         out.append(tuple(st[c].copy() for c in names))
     return out
 
@@ -189,21 +195,16 @@ def adjoint_gradient_td(p, resid: np.ndarray, setup: Setup | None = None,
     nt = s.nt if nt is None else nt
     o = ops(s)
     nodes, interp = receiver_nodes(s, np.asarray(p.rec_pos), p.rec_comp)
-    if nt != s.nt:
-        th = (np.arange(nt) + 0.5) * s.dt
-        What = s.wavelet[:nt] @ np.exp(1j * np.outer(th, s.wprime))
-        norm = np.sqrt(-1j * s.omega / (2.0 * s.omega0)) / What
-    else:
-        norm = s.norm
+    kind = getattr(p, "src_kind", 0)
     # magnetic rows (components 3-5): H = norm_h sum_n H^{n+1/2} z^{n+1/2}
-    norm_h = norm / np.sqrt(-1j * s.omega / (2.0 * s.omega0))
+    norm, norm_h = source_norms(s, nt, kind)
     zm = np.exp(1j * np.outer(np.arange(nt + 1) * s.dt, s.wprime))   # z^m, m = 0..nt
     zh = np.exp(1j * np.outer((np.arange(nt) + 0.5) * s.dt, s.wprime))   # z^{n+1/2}
     names = ("Ex", "Ey", "Ez", "Hx", "Hy", "Hz")
     mag = np.array([c >= 3 for (c, _, _, _) in nodes], dtype=bool)
     ge = [np.zeros(s.sig_e[c].shape) for c in range(3)]
     for si in range(len(p.src_pos)):
-        inj = source_injection(s, p.src_pos[si], p.src_mom[si])
+        inj = source_injection(s, p.src_pos[si], p.src_mom[si], kind=kind)
         E = forward_states(s, inj, s.wavelet[None, :], nt)
         # E_rec = norm sum_nodes w sum_m E^m z^m, so d phi / d E^m(node) =
         # -Re sum_k c_node,k z_k^m with c_node,k = sum w conj(resid) norm_k

@@ -22,16 +22,25 @@ Follows Section 2 of the paper:
     the magnetic field of the same source is H(omega_k) = u_H(omega_k)/W_k,
     u_H = sum_n H^{n+1/2} z_k^{n+1/2} (eq. dtft lists H' among the
     transformed fields; magnetic data enter the misfit eq. phid);
-  * a magnetic current M' (the adjoint source of magnetic data) enters the
-    H update at n dt, the time of the curl E it sits beside.
+  * a magnetic current M' (the adjoint source of magnetic data, or a
+    magnetic dipole source) enters the H update at n dt, the time of the
+    curl E it sits beside;
+  * magnetic dipole sources (M = m delta(x - x_s) in the Faraday row of
+    eq. freq; M' = M by the correspondence below eq. mittet): the wavelet
+    sample w_n is injected as M'^n = m w_n at n dt (reading: the paper fixes
+    no forward time function; each source is normalised by the transform of
+    what it injects, at the times it injects it), so
+    E(omega_k) = u(omega_k) / W^M_k with W^M_k = sum_n w_n z_k^n, and
+    H(omega_k) = u_H(omega_k) / (sqrt(-i omega_k / 2 omega0) W^M_k).
 Receiver components: 0, 1, 2 = E_x, E_y, E_z; 3, 4, 5 = H_x, H_y, H_z.
+Source kinds: 0 = electric dipoles (J), 1 = magnetic dipoles (M).
 """
 from __future__ import annotations
 
 import numpy as np
 
-from .discretization import (MU0, Setup, dual_volumes, h_lattices, lattices, make_setup,
-                             trilinear)
+from .discretization import (MU0, Setup, dual_volumes, h_lattices, h_volumes, lattices,
+                             make_setup, trilinear)
 from .stencil import diff_e, diff_h
 
 
@@ -50,7 +59,7 @@ def point_entries(s: Setup, comp: int, point) -> list:
 
 
 def run_stepping(s: Setup, inj: list, tfun: np.ndarray, rec_nodes: list,
-                 want_volume: bool, nt: int | None = None):
+                 want_volume: bool, nt: int | None = None, decimate: int = 1):
     """Run the leapfrog for ``nt`` steps (default s.nt).
 
     inj       list of (comp, k, j, i, weight, row): at step n an E edge
@@ -58,6 +67,10 @@ def run_stepping(s: Setup, inj: list, tfun: np.ndarray, rec_nodes: list,
               node (comp 3-5) M'^n = weight * tfun[row, n] (weights already
               divided by the dual volume of the edge or node).
     rec_nodes list of (comp, k, j, i) whose raw transforms are returned.
+    decimate  D >= 1: the volume transform takes only the samples E^m with
+              m a multiple of D, each weighted by D (the decimated transform;
+              D = 1 is eq. dft).  Receiver transforms always take every
+              sample.
     Returns (rec_acc [len(rec_nodes), nf], volume [3][nf, ...] or None) with
     the raw sums sum_n E^n z^n (E nodes) and sum_n H^{n+1/2} z^{n+1/2}
     (H nodes)."""
@@ -153,25 +166,49 @@ def run_stepping(s: Setup, inj: list, tfun: np.ndarray, rec_nodes: list,
         for r, (c, k, j, i) in enumerate(rec_nodes):
             if c < 3:
                 rec_acc[r] += E[c][k, j, i] * zn
-        if vol is not None:
+        if vol is not None and (n + 1) % decimate == 0:
             for c in range(3):
-                vol[c] += zn[:, None, None, None] * E[c][None]
+                vol[c] += decimate * zn[:, None, None, None] * E[c][None]
     return rec_acc, vol
 
 
-def source_injection(s: Setup, pos, mom, row: int = 0) -> list:
-    """Injection entries of a point electric dipole of moment ``mom`` at
-    ``pos`` (J = p delta(x - x_s), eq. freq): each component is spread over
-    its E lattice with trilinear weights, divided by the dual volume of the
-    edge it lands on."""
-    vols = dual_volumes(s)
+def source_injection(s: Setup, pos, mom, row: int = 0, kind: int = 0) -> list:
+    """Injection entries of a point dipole of moment ``mom`` at ``pos``.
+    kind 0, electric (J = p delta(x - x_s), eq. freq): each component is
+    spread over its E lattice with trilinear weights, divided by the dual
+    volume of the edge it lands on.  kind 1, magnetic (M = m delta(x - x_s)):
+    the same over the H lattices and the volumes of the H nodes (under which
+    the Faraday and Ampere rows form a symmetric pair); entries carry
+    components 3-5."""
+    vols = dual_volumes(s) if kind == 0 else h_volumes(s)
     inj = []
     for c in range(3):
         if mom[c] == 0.0:
             continue
-        for (k, j, i, w) in point_entries(s, c, pos):
-            inj.append((c, k, j, i, mom[c] * w / vols[c][k, j, i], row))
+        cc = c + 3 * kind
+        for (k, j, i, w) in point_entries(s, cc, pos):
+            inj.append((cc, k, j, i, mom[c] * w / vols[c][k, j, i], row))
     return inj
+
+
+def source_norms(s: Setup, nt: int, kind: int = 0):
+    """(norm_e, norm_h) [nf]: the factors that turn the raw transforms of a
+    run of ``nt`` steps into the fields of a unit dipole, for E rows and H
+    rows.  Electric sources inject w^{n+1/2} as J' (transform W_k over
+    (n+1/2) dt) with J' = sqrt(-i omega / 2 omega0) J; magnetic sources
+    inject w_n as M' = M at n dt (transform W^M_k over n dt).  In both,
+    H = H' / sqrt(-i omega / 2 omega0)."""
+    fac = np.sqrt(-1j * s.omega / (2.0 * s.omega0))
+    if kind == 0:
+        if nt != s.nt:
+            th = (np.arange(nt) + 0.5) * s.dt
+            norm = fac / (s.wavelet[:nt] @ np.exp(1j * np.outer(th, s.wprime)))
+        else:
+            norm = s.norm
+    else:
+        tn = np.arange(nt) * s.dt
+        norm = 1.0 / (s.wavelet[:nt] @ np.exp(1j * np.outer(tn, s.wprime)))
+    return norm, norm / fac
 
 
 def receiver_nodes(s: Setup, rec_pos, rec_comp):
@@ -194,13 +231,14 @@ def receiver_nodes(s: Setup, rec_pos, rec_comp):
 
 
 def forward(p, want_volume: bool = False, setup: Setup | None = None,
-            nt: int | None = None):
+            nt: int | None = None, decimate: int | None = None):
     """Frequency-domain fields at the receivers (and optionally E in the
     volume) for every source of problem ``p``: one leapfrog run per source.
 
     Returns dict with
       setup  the Setup used
-      E_rec  complex [ns][nr][ncomp][nf]  (eq. freq field of the dipole;
+      E_rec  complex [ns][nr][ncomp][nf]  (eq. freq field of the dipole,
+             electric or magnetic as p.src_kind says (default electric);
              the components p.rec_comp, E or H)
       vol    per source, [3][nf, ...] normalised volume fields (if asked)."""
     s = setup if setup is not None else make_setup(p)
@@ -209,20 +247,15 @@ def forward(p, want_volume: bool = False, setup: Setup | None = None,
     ns = len(p.src_pos)
     ncomp = len(p.rec_comp)
     nf = len(s.freqs)
-    if nt != s.nt:
-        # the normalisation uses the wavelet transform over the steps run
-        th = (np.arange(nt) + 0.5) * s.dt
-        What = s.wavelet[:nt] @ np.exp(1j * np.outer(th, s.wprime))
-        norm = np.sqrt(-1j * s.omega / (2.0 * s.omega0)) / What
-    else:
-        norm = s.norm
-    # H = H' / sqrt(-i omega / 2 omega0): the magnetic field needs 1 / W_k
-    norm_h = norm / np.sqrt(-1j * s.omega / (2.0 * s.omega0))
+    kind = getattr(p, "src_kind", 0)
+    dec = int(decimate or getattr(p, "dft_decimate", 1))
+    # the normalisation uses the wavelet transform over the steps run
+    norm, norm_h = source_norms(s, nt, kind)
     E_rec = np.zeros((ns, len(p.rec_pos), ncomp, nf), dtype=np.complex128)
     vols = []
     for si in range(ns):
-        inj = source_injection(s, p.src_pos[si], p.src_mom[si])
-        acc, vol = run_stepping(s, inj, s.wavelet[None, :], nodes, want_volume, nt)
+        inj = source_injection(s, p.src_pos[si], p.src_mom[si], kind=kind)
+        acc, vol = run_stepping(s, inj, s.wavelet[None, :], nodes, want_volume, nt, dec)
         for r in range(len(p.rec_pos)):
             for ci in range(ncomp):
                 val = sum(w * acc[ni] for ni, w in interp[r][ci])
@@ -230,4 +263,4 @@ def forward(p, want_volume: bool = False, setup: Setup | None = None,
         if vol is not None:
             vols.append([v * norm[:, None, None, None] for v in vol])
     return {"setup": s, "E_rec": E_rec, "vol": vols if want_volume else None,
-            "norm": norm}
+            "norm": norm, "decimate": dec}

@@ -317,6 +317,14 @@ fwd_status fwd_set_option(fwd_plan *h, int key, double value) {
         if (!(value >= 0.0)) fail(FWD_ERR_INVALID_ARG, "barrier wait limit >= 0 microseconds");
         p.barrier_us = value;
         break;
+      case FWD_OPT_PERSIST_BLOCKS:
+        if (v < 0 || v > 32) fail(FWD_ERR_INVALID_ARG, "blocks per compute unit in [0, 32]");
+        p.persist_blocks = v;
+        break;
+      case FWD_OPT_BARRIER_SLEEP:
+        if (v < 1 || v > 64) fail(FWD_ERR_INVALID_ARG, "barrier pause in [1, 64]");
+        p.barrier_sleep = v;
+        break;
       case FWD_OPT_ZCHUNK:
         if (v < 1 || v > 64) fail(FWD_ERR_INVALID_ARG, "planes per block in [1, 64]");
         p.kz = v;
@@ -379,6 +387,8 @@ fwd_status fwd_get_option(const fwd_plan *h, int key, double *value) {
       case FWD_OPT_FD_ORDER: *value = p.fd_order; break;
       case FWD_OPT_LEAN: *value = p.lean; break;
       case FWD_OPT_BARRIER_US: *value = p.barrier_us; break;
+      case FWD_OPT_PERSIST_BLOCKS: *value = p.persist_blocks; break;
+      case FWD_OPT_BARRIER_SLEEP: *value = p.barrier_sleep; break;
       default: fail(FWD_ERR_INVALID_ARG, "unknown option");
     }
   });

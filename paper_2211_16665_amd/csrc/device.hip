@@ -1439,6 +1439,7 @@ struct Bar {
   unsigned *count, *gen;
   int *abort;
   uint64_t limit;     // wall-clock ticks a block may wait at one barrier
+  int naps;           // s_sleep(1) pauses (64 cycles each) between two polls
 };
 
 __device__ __forceinline__ bool grid_sync(const Bar &B) {
@@ -1461,7 +1462,7 @@ __device__ __forceinline__ bool grid_sync(const Bar &B) {
           ok = 0;
           break;
         }
-        __builtin_amdgcn_s_sleep(1);
+        for (int z = 0; z < B.naps; ++z) __builtin_amdgcn_s_sleep(1);
       }
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
@@ -1856,6 +1857,24 @@ __global__ void k_hinj(StepArgs<T> A, const int *hn, int nh, const int *rn_c,
   f[q] = (T)((double)f[q] + dtmu * v);
 }
 
+// Forward magnetic dipole sources under the fused schedule, one thread per
+// injection target, before the fused step n: H^{n-1/2} += (dt/mu) M'^n with
+// M'^n = coef * w_n (the arithmetic of inject_h, so every schedule gives the
+// same bits).  Targets of the electric kind (c < 3) are skipped.
+template <typename T>
+__global__ void k_hsrc(StepArgs<T> A, const int *tg_s, const int *tg_c, const int64_t *tg_idx,
+                       int ntg, double dtmu) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ntg) return;
+  const int n = A.step[0] + 1;
+  if (n >= A.nt || tg_c[t] < 3) return;
+  const double v = fma(A.coef[t], A.Ftab[n], 0.0);
+  if (v == 0.0) return;                      // as inject_h: a zero leaves the node alone
+  T *f = h_comp(half_of(A, n & 1, tg_s[t]), tg_c[t]);
+  const int64_t q = tg_idx[t];
+  f[q] = (T)((double)f[q] + dtmu * v);
+}
+
 // dst [ns][3][F] <- E of every source in half `half` of the double buffer
 template <typename T>
 __global__ void k_copy_e(T *dst, const T *fields, int64_t fbuf, int half, int ns, int64_t F) {
@@ -2004,10 +2023,13 @@ struct Dev {
   // adjoint injection coefficients (rebuilt per call)
   double *at_coef = nullptr;
   // per-thread entry tables for the current tiling: the E update's forward
-  // (index 0) and adjoint (index 1) tables, and the H update's adjoint table
-  // of magnetic sources (index 2, two-kernel schedule); see build_lists
-  int *tile_tab[3] = {nullptr, nullptr, nullptr}, *tl_off[3] = {nullptr, nullptr, nullptr};
-  int2 *tl_ent[3] = {nullptr, nullptr, nullptr};
+  // (index 0) and adjoint (index 1) tables, and the H update's tables of
+  // magnetic sources, adjoint (index 2) and forward (index 3; two-kernel and
+  // persistent schedules); see build_lists
+  int *tile_tab[4] = {nullptr, nullptr, nullptr, nullptr};
+  int *tl_off[4] = {nullptr, nullptr, nullptr, nullptr};
+  int2 *tl_ent[4] = {nullptr, nullptr, nullptr, nullptr};
+  int ntg = 0;                  // forward injection targets (src_s .. src_coef)
   std::string list_key;
   std::vector<DevBuf> list_bufs;
   double *cellfac = nullptr, *cellfac_v = nullptr;   // sigma_h V / 4, sigma_v V / 4
@@ -2056,7 +2078,7 @@ static void free_lists(Dev &d) {
   for (auto &b : d.list_bufs) (void)hipFree(b.p);
   d.list_bufs.clear();
   d.list_key.clear();
-  for (int m = 0; m < 3; ++m) {
+  for (int m = 0; m < 4; ++m) {
     d.tile_tab[m] = d.tl_off[m] = nullptr;
     d.tl_ent[m] = nullptr;
   }
@@ -2145,6 +2167,7 @@ static void ensure_tables(Plan &p, hipStream_t stream) {
     d.src_idx = upload(d, idx);
     d.src_toff = upload(d, toff);
     d.src_coef = upload(d, coef);
+    d.ntg = (int)p.src_tg.size();
   }
   d.rn_c = upload(d, p.rn_c);
   d.rn_idx = upload(d, p.rn_idx);
@@ -2313,8 +2336,8 @@ static void build_lists(Plan &p, Dev &d) {
   free_lists(d);
   const int nn = (int)p.rn_c.size(), nf = p.nf();
   const int slots = p.bx * p.by;
-  for (int mode = 0; mode < 3; ++mode) {
-    const Tiling t = tiling(p, mode == 2);   // mode 2 lives on the H update's grid
+  for (int mode = 0; mode < 4; ++mode) {
+    const Tiling t = tiling(p, mode >= 2);   // modes 2 and 3 live on the H update's grid
     struct E {
       int b, slot;
       int2 v;
@@ -2344,7 +2367,14 @@ static void build_lists(Plan &p, Dev &d) {
     };
     if (mode == 0) {
       for (size_t q = 0; q < p.src_tg.size(); ++q)
-        place(p.src_tg[q].c, 0, p.src_tg[q].s, p.src_tg[q].idx, (int)q);
+        if (p.src_tg[q].c < 3) place(p.src_tg[q].c, 0, p.src_tg[q].s, p.src_tg[q].idx, (int)q);
+    } else if (mode == 3) {
+      // forward magnetic sources M'^n, added by the H update; the fused
+      // schedule uses k_hsrc instead
+      if (p.sched != 1)
+        for (size_t q = 0; q < p.src_tg.size(); ++q)
+          if (p.src_tg[q].c >= 3)
+            place(p.src_tg[q].c - 3, 0, p.src_tg[q].s, p.src_tg[q].idx, (int)q);
     } else if (mode == 1) {
       for (int s = 0; s < p.ns; ++s)
         for (int node = 0; node < nn; ++node)
@@ -2597,6 +2627,9 @@ static void enqueue_step(Plan &p, Dev &d, const WS &w, void *vol, bool adj, hipS
   if (d.nh > 0 && adj && p.sched == 1)
     hipLaunchKernelGGL((k_hinj<T>), hgrid, hblock, 0, st, A, d.hn, d.nh, d.rn_c, d.rn_idx,
                        p.dt / kMu0);
+  if (!adj && p.src_kind == 1 && p.sched == 1)
+    hipLaunchKernelGGL((k_hsrc<T>), dim3((d.ntg + 63) / 64), dim3(64), 0, st, A, d.src_s, d.src_c,
+                       d.src_idx, d.ntg, p.dt / kMu0);
   if (p.sched == 1) {
     if (ev) {
       (void)hipEventRecord(ev[0], st);
@@ -2606,15 +2639,17 @@ static void enqueue_step(Plan &p, Dev &d, const WS &w, void *vol, bool adj, hipS
     if (d.nh > 0)
       hipLaunchKernelGGL((k_hrec<T>), hgrid, hblock, 0, st, A, d.hn, d.nh, d.rn_c, d.rn_idx, d.zH);
   } else {
-    // the E update records the H receiver nodes itself; in adjoint runs the
-    // H update adds the magnetic sources from its own entry table
+    // the E update records the H receiver nodes itself; the H update adds
+    // the magnetic sources (adjoint runs with magnetic data, forward runs of
+    // magnetic dipoles) from its own entry table
     StepArgs<T> Ah = A;
     const Tiling th = tiling(p, true);
     set_grid(Ah, th.nbx, th.nby, th.nbz);
-    const bool hinj = adj && d.nh > 0;
-    Ah.tile_tab = hinj ? d.tile_tab[2] : nullptr;
-    Ah.tl_off = hinj ? d.tl_off[2] : nullptr;
-    Ah.tl_ent = hinj ? d.tl_ent[2] : nullptr;
+    const bool hinj = adj ? d.nh > 0 : p.src_kind == 1;
+    const int hm = adj ? 2 : 3;
+    Ah.tile_tab = hinj ? d.tile_tab[hm] : nullptr;
+    Ah.tl_off = hinj ? d.tl_off[hm] : nullptr;
+    Ah.tl_ent = hinj ? d.tl_ent[hm] : nullptr;
     const bool o4 = p.fd_order == 4;
     launch_h<T>(Ah, p.vxh, dim3(Ah.nblocks), block, st, kh, o4, hinj);
     launch_e<T>(A, p.vx, vol != nullptr, grid, block, st, ke, o4);
@@ -2660,13 +2695,14 @@ static void flush_any(Plan &p, Dev &d, const WS &w, void *vol, bool adj, hipStre
 // per tile of the largest phase).
 template <typename T, bool HIST, int ACC, bool ADJ, int KB, bool INJ>
 static void launch_persist(const StepArgs<T> &A, const StepArgs<T> &Ah, int nsteps, const Bar &B,
-                           dim3 block, size_t lds, hipStream_t st) {
+                           dim3 block, size_t lds, hipStream_t st, int cap) {
   const void *fn = reinterpret_cast<const void *>(&k_persist<T, HIST, ACC, ADJ, KB, INJ>);
   int dev = 0, per_cu = 0, cus = 0;
   HIP_CHECK(hipGetDevice(&dev));
   HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
   HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, (int)(block.x * block.y), lds));
   if (per_cu < 1) fail(FWD_ERR_UNSUPPORTED, "persistent schedule: no block fits on a compute unit");
+  if (cap > 0) per_cu = std::min(per_cu, cap);
   const int64_t tiles = std::max<int64_t>(A.nblocks, Ah.nblocks);
   const unsigned grid = (unsigned)std::min<int64_t>((int64_t)per_cu * cus, tiles);
   StepArgs<T> a = A, ah = Ah;
@@ -2681,9 +2717,10 @@ static void launch_persist(const StepArgs<T> &A, const StepArgs<T> &Ah, int nste
 
 template <typename T, bool HIST, int ACC, bool ADJ, bool INJ>
 static void launch_persist_kb(const StepArgs<T> &A, const StepArgs<T> &Ah, int nsteps,
-                              const Bar &B, dim3 block, size_t lds, hipStream_t st, int kb) {
-  if (kb == 8) launch_persist<T, HIST, ACC, ADJ, 8, INJ>(A, Ah, nsteps, B, block, lds, st);
-  else if (kb == 16) launch_persist<T, HIST, ACC, ADJ, 16, INJ>(A, Ah, nsteps, B, block, lds, st);
+                              const Bar &B, dim3 block, size_t lds, hipStream_t st, int kb,
+                              int cap) {
+  if (kb == 8) launch_persist<T, HIST, ACC, ADJ, 8, INJ>(A, Ah, nsteps, B, block, lds, st, cap);
+  else if (kb == 16) launch_persist<T, HIST, ACC, ADJ, 16, INJ>(A, Ah, nsteps, B, block, lds, st, cap);
   else fail(FWD_ERR_UNSUPPORTED, "persistent schedule: transform block 8 or 16");
 }
 
@@ -2696,26 +2733,31 @@ static void run_persistent(Plan &p, Dev &d, const WS &w, void *vol, bool adj, in
   StepArgs<T> Ah = A;
   const Tiling th = tiling(p, true);
   set_grid(Ah, th.nbx, th.nby, th.nbz);
-  const bool inj = adj && d.nh > 0;
-  Ah.tile_tab = inj ? d.tile_tab[2] : nullptr;
-  Ah.tl_off = inj ? d.tl_off[2] : nullptr;
-  Ah.tl_ent = inj ? d.tl_ent[2] : nullptr;
+  const bool inj = adj ? d.nh > 0 : p.src_kind == 1;
+  const int hm = adj ? 2 : 3;
+  Ah.tile_tab = inj ? d.tile_tab[hm] : nullptr;
+  Ah.tl_off = inj ? d.tl_off[hm] : nullptr;
+  Ah.tl_ent = inj ? d.tl_ent[hm] : nullptr;
   A.xcd = Ah.xcd = 0;                      // virtual blocks: no dispatch-order remap
   int dev = 0, khz = 0;
   HIP_CHECK(hipGetDevice(&dev));
   HIP_CHECK(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
-  const Bar B{w.bar, w.bar + 1, w.abort, (uint64_t)(p.barrier_us * (double)khz / 1000.0)};
+  const Bar B{w.bar, w.bar + 1, w.abort, (uint64_t)(p.barrier_us * (double)khz / 1000.0),
+              p.barrier_sleep};
+  const int cap = p.persist_blocks;
   const dim3 block(p.bx, p.by);
   const bool hist = vol != nullptr;
   const size_t lds = hist ? (size_t)p.nf() * p.kb * sizeof(double2) : 0;
   if (!hist) {
-    launch_persist<T, false, ACC_F64, false, 8, false>(A, Ah, nsteps, B, block, lds, st);
+    if (inj) launch_persist<T, false, ACC_F64, false, 8, true>(A, Ah, nsteps, B, block, lds, st, cap);
+    else launch_persist<T, false, ACC_F64, false, 8, false>(A, Ah, nsteps, B, block, lds, st, cap);
   } else {
 #define FWD_PERSIST(ACCV)                                                                   \
   do {                                                                                      \
-    if (!adj) launch_persist_kb<T, true, ACCV, false, false>(A, Ah, nsteps, B, block, lds, st, p.kb); \
-    else if (!inj) launch_persist_kb<T, true, ACCV, true, false>(A, Ah, nsteps, B, block, lds, st, p.kb); \
-    else launch_persist_kb<T, true, ACCV, true, true>(A, Ah, nsteps, B, block, lds, st, p.kb); \
+    if (!adj && inj) launch_persist_kb<T, true, ACCV, false, true>(A, Ah, nsteps, B, block, lds, st, p.kb, cap); \
+    else if (!adj) launch_persist_kb<T, true, ACCV, false, false>(A, Ah, nsteps, B, block, lds, st, p.kb, cap); \
+    else if (!inj) launch_persist_kb<T, true, ACCV, true, false>(A, Ah, nsteps, B, block, lds, st, p.kb, cap); \
+    else launch_persist_kb<T, true, ACCV, true, true>(A, Ah, nsteps, B, block, lds, st, p.kb, cap); \
   } while (0)
     switch (p.acc) {
       case FWD_ACC_F64: FWD_PERSIST(ACC_F64); break;

@@ -46,8 +46,8 @@ struct Axis {
   std::vector<double> kinv_h, b_h, a_h;
 };
 
-// One injection target: E component c of source s at linear index idx of
-// the padded device layout; the per-step value is
+// One injection target: component c of source s (0..2: an E edge, 3..5: an H
+// node) at linear index idx of the padded device layout; the per-step value is
 // sum_r coef[toff + r] * F[r][n] with nrow rows of time functions F.
 struct Target {
   int s;
@@ -66,6 +66,7 @@ struct Plan {
   std::vector<double> freqs, omega, a;   // a = sqrt(omega omega0)
   std::vector<cplx> wprime;              // (1+i) a
   int ns = 0, nr = 0, ncomp = 0;
+  int src_kind = 0;                      // 0: electric dipoles (J), 1: magnetic dipoles (M)
   std::vector<double> src_pos, src_mom, rec_pos;
   std::vector<int> comp;
   int dtype = FWD_F32, acc = FWD_ACC_F64;
@@ -85,10 +86,10 @@ struct Plan {
   int nt = 0;
   std::vector<double> wavelet;           // [nt]
   double tau = 0, t0 = 0;
-  std::vector<cplx> What, norm, Omega;   // [nf]
+  std::vector<cplx> What, norm, Omega;   // [nf]; What: transform of the injected wavelet
   std::vector<cplx> zE;                  // [nt][nf] z^{n+1}
   std::vector<cplx> zH;                  // [nt][nf] z^{n+1/2} (H samples)
-  std::vector<cplx> norm_h;              // [nf] 1 / What: magnetic receivers
+  std::vector<cplx> norm_h;              // [nf] H rows (magnetic receivers)
   // forward injection (per source, merged duplicates)
   std::vector<Target> src_tg;
   std::vector<double> src_coef;          // one coefficient per target
@@ -119,6 +120,8 @@ struct Plan {
   int vti_grad = 0;                      // 1: gradients as [d/d ln rho_h, d/d ln rho_v]
   int lean = 1;                          // interior tiles take the lean update paths
   double barrier_us = 5.0e6;             // persistent schedule: longest wait at a grid barrier
+  int persist_blocks = 0;                // persistent schedule: blocks per CU (0: occupancy)
+  int barrier_sleep = 1;                 // persistent schedule: s_sleep units between polls
   int fd_order = 2;                      // order of the staggered differences: 2 or 4
 
   // ---- device side (managed in device.hip) ----

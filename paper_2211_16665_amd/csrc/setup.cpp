@@ -148,6 +148,7 @@ Plan *plan_create(const fwd_plan_desc *d) {
     fail(FWD_ERR_INVALID_ARG, "field_dtype");
   if (d->acc_mode < FWD_ACC_F64 || d->acc_mode > FWD_ACC_F32) fail(FWD_ERR_INVALID_ARG, "acc_mode");
   if (d->dt < 0 || d->nt < 0) fail(FWD_ERR_INVALID_ARG, "dt and nt must be >= 0");
+  if (d->src_kind != 0 && d->src_kind != 1) fail(FWD_ERR_INVALID_ARG, "src_kind in {0, 1}");
 
   Plan *p = new Plan();
   p->nx = d->nx;
@@ -194,6 +195,7 @@ Plan *plan_create(const fwd_plan_desc *d) {
   if (p->cfl > 1.0) { delete p; fail(FWD_ERR_INVALID_ARG, "cfl must be <= 1"); }
   p->dt_user = d->dt;
   p->nt_user = d->nt;
+  p->src_kind = d->src_kind;
   return p;
 }
 
@@ -444,14 +446,24 @@ void set_model(Plan &p, const double *rho, const double *rho_v) {
   p.norm_h.resize(nf);
   const cplx I(0.0, 1.0);
   for (int k = 0; k < nf; ++k) {
+    // electric sources inject J'^{n+1/2} = p w_n at (n+1/2) dt; magnetic
+    // ones M'^n = m w_n at n dt (beside the curl E of the H update): each is
+    // normalised by the transform of what it injects, when it injects it
+    const double shift = p.src_kind == 1 ? 0.0 : 0.5;
     cplx acc = 0;
-    for (int n = 0; n < nt; ++n) acc += p.wavelet[n] * std::exp(I * p.wprime[k] * ((n + 0.5) * p.dt));
+    for (int n = 0; n < nt; ++n) acc += p.wavelet[n] * std::exp(I * p.wprime[k] * ((n + shift) * p.dt));
     p.What[k] = acc;
-    // J' = sqrt(-i omega / 2 omega0) J (correspondence below eq. mittet)
-    p.norm[k] = std::sqrt(cplx(0.0, -p.omega[k] / (2.0 * p.omega0))) / acc;
-    // H' = sqrt(-i omega / 2 omega0) H: the magnetic field of the same source
-    // carries no sqrt factor
-    p.norm_h[k] = 1.0 / acc;
+    const cplx fac = std::sqrt(cplx(0.0, -p.omega[k] / (2.0 * p.omega0)));
+    if (p.src_kind == 1) {
+      // M' = M and E' = E: E = u / W^M; H' = sqrt(-i omega / 2 omega0) H
+      p.norm[k] = 1.0 / acc;
+      p.norm_h[k] = 1.0 / (fac * acc);
+    } else {
+      // J' = sqrt(-i omega / 2 omega0) J (correspondence below eq. mittet);
+      // the magnetic field of the same source carries no sqrt factor
+      p.norm[k] = fac / acc;
+      p.norm_h[k] = 1.0 / acc;
+    }
     p.Omega[k] = (2.0 / p.dt) * std::sin(p.wprime[k] * p.dt * 0.5);
     for (int n = 0; n < nt; ++n) {
       p.zE[(size_t)n * nf + k] = std::exp(I * p.wprime[k] * ((n + 1.0) * p.dt));
@@ -460,16 +472,19 @@ void set_model(Plan &p, const double *rho, const double *rho_v) {
   }
 
   // forward injection: J = p delta(x - x_s) spread with trilinear weights
-  // over each component's lattice, divided by the dual volume of the edge
+  // over each component's lattice, divided by the dual volume of the edge;
+  // magnetic sources M = m delta(x - x_s) likewise over the H lattices and
+  // the volumes of the H nodes (targets c = 3..5; every H node is updated)
   p.src_tg.clear();
   p.src_coef.clear();
   double cmax = 0;
   for (int s = 0; s < p.ns; ++s) {
-    for (int c = 0; c < 3; ++c) {
-      const double m = p.src_mom[3 * s + c];
+    for (int cm = 0; cm < 3; ++cm) {
+      const double m = p.src_mom[3 * s + cm];
       if (m == 0.0) continue;
+      const int c = cm + 3 * p.src_kind;
       for (const NodeW &nw : point_weights(p, c, &p.src_pos[3 * s])) {
-        if (!interior_edge(p, c, nw.k, nw.j, nw.i))
+        if (c < 3 && !interior_edge(p, c, nw.k, nw.j, nw.i))
           fail(FWD_ERR_INVALID_ARG, "source touches the outer boundary of the grid");
         const int64_t idx = p.lin(nw.k, nw.j, nw.i);
         const double coef = m * nw.w / dual_volume(p, c, nw.k, nw.j, nw.i);
@@ -486,8 +501,10 @@ void set_model(Plan &p, const double *rho, const double *rho_v) {
       }
     }
   }
-  for (size_t t = 0; t < p.src_tg.size(); ++t)
-    cmax = std::max(cmax, std::fabs(p.src_coef[t]) * p.ce[p.src_tg[t].c][p.src_tg[t].idx]);
+  for (size_t t = 0; t < p.src_tg.size(); ++t) {
+    const Target &tg = p.src_tg[t];
+    cmax = std::max(cmax, std::fabs(p.src_coef[t]) * (tg.c < 3 ? p.ce[tg.c][tg.idx] : p.dt / kMu0));
+  }
   double wmax = 0;
   for (double w : p.wavelet) wmax = std::max(wmax, std::fabs(w));
   if (p.src_tg.empty() || cmax == 0) fail(FWD_ERR_INVALID_ARG, "every source moment is zero");

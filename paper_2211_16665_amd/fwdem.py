@@ -34,7 +34,8 @@ FWD_MODE_FORWARD, FWD_MODE_ADJOINT = 0, 1
 (FWD_OPT_GRAPH_STEPS, FWD_OPT_BLOCK_X, FWD_OPT_BLOCK_Y, FWD_OPT_XCD_REMAP,
  FWD_OPT_SAMPLE_EVERY, FWD_OPT_STRICT_CFL, FWD_OPT_DFT_BLOCK, FWD_OPT_VECTOR,
  FWD_OPT_SCHEDULE, FWD_OPT_ZCHUNK, FWD_OPT_TILE_ORDER, FWD_OPT_VECTOR_H,
- FWD_OPT_VTI_GRADIENT, FWD_OPT_FD_ORDER, FWD_OPT_LEAN, FWD_OPT_BARRIER_US) = range(16)
+ FWD_OPT_VTI_GRADIENT, FWD_OPT_FD_ORDER, FWD_OPT_LEAN, FWD_OPT_BARRIER_US,
+ FWD_OPT_PERSIST_BLOCKS, FWD_OPT_BARRIER_SLEEP) = range(18)
 
 FWD_STATIC_SCRATCH_BYTES = 32 << 20       # the static workspace of fwd_forward_static
 
@@ -62,6 +63,7 @@ class fwd_plan_desc(Structure):
         ("ncomp", c_int), ("rec_comp", POINTER(c_int)),
         ("field_dtype", c_int), ("acc_mode", c_int),
         ("rho_air_cap", c_double), ("cfl", c_double), ("dt", c_double), ("nt", c_int),
+        ("src_kind", c_int),
     ]
 
 
@@ -165,7 +167,7 @@ class Plan:
     def __init__(self, x, y, z, freqs, src_pos, src_mom, rec_pos, rec_comp=(0, 1), npml=8,
                  f0=1.0, field_dtype="f32", acc_mode="f64", rho_air_cap=1e4, cfl=0.95,
                  dt=0.0, nt=0, cpml_order=0.0, cpml_R=0.0, cpml_kappa_max=0.0,
-                 cpml_alpha_max=0.0, cpml_vref=0.0, fd_order=2):
+                 cpml_alpha_max=0.0, cpml_vref=0.0, fd_order=2, src_kind=0):
         self.lib = load()
         self._keep = [np.ascontiguousarray(a, dtype=np.float64) for a in
                       (x, y, z, freqs, src_pos, src_mom, rec_pos)]
@@ -186,6 +188,7 @@ class Plan:
         d.field_dtype = DTYPES[field_dtype]
         d.acc_mode = ACC_MODES[acc_mode]
         d.rho_air_cap, d.cfl, d.dt, d.nt = float(rho_air_cap), float(cfl), float(dt), int(nt)
+        d.src_kind = int(src_kind)
         h = c_void_p()
         check(self.lib.fwd_plan_create(byref(d), byref(h)))
         self.handle = h
@@ -201,7 +204,8 @@ class Plan:
     def from_workload(cls, w, field_dtype=None, acc_mode=None, **kw):
         args = dict(npml=w.npml, f0=w.f0, rho_air_cap=w.rho_air_cap, cfl=w.cfl, dt=w.dt,
                     nt=w.nt, field_dtype=field_dtype or w.field_dtype,
-                    acc_mode=acc_mode or w.acc_mode, fd_order=getattr(w, "fd_order", 2))
+                    acc_mode=acc_mode or w.acc_mode, fd_order=getattr(w, "fd_order", 2),
+                    src_kind=getattr(w, "src_kind", 0))
         for k in ("cpml_order", "cpml_R", "cpml_kappa_max", "cpml_alpha_max", "cpml_vref"):
             if hasattr(w, k):
                 args[k] = getattr(w, k)

@@ -74,3 +74,39 @@ def magnetic_field_discrete_time(r_vec, p, sigma, omega0, Omega, mu=MU0):
     k = np.sqrt(Omega ** 2 * mu * sigma / (2.0 * omega0) + 0j)
     k = np.where(np.imag(k) < 0, -k, k)
     return magnetic_field(r_vec, p, k)
+
+
+def magnetic_dipole_e(r_vec, m, k):
+    """E at offsets ``r_vec`` [..., 3] from a magnetic dipole of moment ``m``
+    [3] (M = m delta(x) in the Faraday row of eq. freq).  Taking the curl of
+    that row, curl curl E - k^2 E = curl M; E is divergence-free, so
+    (lap + k^2) E = -curl M and E = curl (G m) = grad G x m =
+    (ik - 1/r) G (r_hat x m)."""
+    r_vec = np.asarray(r_vec, dtype=np.float64)
+    m = np.asarray(m, dtype=np.float64)
+    r = np.linalg.norm(r_vec, axis=-1)
+    G = np.exp(1j * k * r) / (4.0 * np.pi * r)
+    dG = (1j * k - 1.0 / r) * G
+    return (dG / r)[..., None] * np.cross(r_vec, m)
+
+
+def magnetic_dipole_h(r_vec, m, k, sigma, omega, mu=MU0):
+    """H of the same magnetic dipole away from it: from the Faraday row,
+    i omega mu H = curl E = curl curl (G m) = (k^2 + grad div) (G m), which is
+    sigma times the electric dipole's E of moment m (dipole_field)."""
+    return sigma / (1j * omega * mu) * dipole_field(r_vec, m, k, sigma)
+
+
+def magnetic_dipole_discrete_time(r_vec, m, sigma, omega, omega0, Omega, mu=MU0):
+    """(E, H) of a magnetic dipole in the stepped system at complex frequency
+    Omega.  Its transformed rows are curl E^ - i Omega mu H^ = M^ and
+    curl H^ + i Omega eps E^ = J^ (eps = sigma / 2 omega0); with M' = M and
+    J = 0, E^ solves curl curl E^ - (Omega^2 mu sigma / 2 omega0) E^ = curl M^,
+    the closed form above with k^2 = Omega^2 mu sigma / (2 omega0) and no
+    other factor.  H' = H^ = sigma dipole_field(m) / (i Omega mu) away from
+    the source, and H = H' / sqrt(-i omega / 2 omega0)."""
+    k = np.sqrt(Omega ** 2 * mu * sigma / (2.0 * omega0) + 0j)
+    k = np.where(np.imag(k) < 0, -k, k)
+    E = magnetic_dipole_e(r_vec, m, k)
+    Hp = sigma / (1j * Omega * mu) * dipole_field(r_vec, m, k, sigma)
+    return E, Hp / np.sqrt(-1j * omega / (2.0 * omega0))

@@ -146,12 +146,17 @@ def _metrics(nodes, order):
 
 def solve(x, y, z, rho, npml, f0, freq, dt, sources, receivers, rec_comp,
           vref, cpml_order=2.0, cpml_R=1e-6, kappa_max=1.0, alpha_max=0.0,
-          rho_cap=1e8, rho_v=None, order=2):
+          rho_cap=1e8, rho_v=None, order=2, src_kind=0, full=False):
     """Frequency-domain field at ``receivers`` for each dipole in ``sources``
     (list of (pos, moment)); returns complex [ns][nr][ncomp].  The field is
     that of J (not J'): the right-hand side is sqrt(-i w/2w0) p w_l / V_l.
     Components 0-2 are E, 3-5 are H, taken from the Faraday row
-    H' = curl E' / (i Omega mu) and H = H' / sqrt(-i w/2w0)."""
+    H' = (curl E' - M') / (i Omega mu) and H = H' / sqrt(-i w/2w0).
+    src_kind 1: magnetic dipoles, M' = M = m w_l / V_l on the H nodes (V_l
+    the node length along the component times the cell lengths across it);
+    eliminating H' puts curl_h M' / (i Omega mu) on the right-hand side.
+    full=True also returns, per source, E on every edge as the three arrays
+    of the E lattices (zero on the walls)."""
     g = Grid(x, y, z)
     nx, ny, nz = g.nx, g.ny, g.nz
     hx, hy, hz = np.diff(x), np.diff(y), np.diff(z)
@@ -289,7 +294,13 @@ def solve(x, y, z, rho, npml, f0, freq, dt, sources, receivers, rec_comp,
             return mx[i] * dy[j] * dz[k]
         if c == 1:
             return dx[i] * my[j] * dz[k]
-        return dx[i] * dy[j] * mz[k]
+        if c == 2:
+            return dx[i] * dy[j] * mz[k]
+        if c == 3:                               # H_x: x node, y and z cells
+            return dx[i] * my[j] * mz[k]
+        if c == 4:
+            return mx[i] * dy[j] * mz[k]
+        return mx[i] * my[j] * dz[k]
 
     def weights(c, p):
         out = []
@@ -307,17 +318,26 @@ def solve(x, y, z, rho, npml, f0, freq, dt, sources, receivers, rec_comp,
 
     src_fac = np.sqrt(-1j * om / (2 * w0))
     out = np.zeros((len(sources), len(receivers), len(rec_comp)), dtype=np.complex128)
+    fields = []
     for si, (pos, mom) in enumerate(sources):
         rhs = np.zeros(len(idx), dtype=np.complex128)
+        m_full = np.zeros(g.hoff[-1], dtype=np.complex128)
         for c in range(3):
             if mom[c] == 0:
                 continue
-            for (k, j, i, w) in weights(c, pos):
-                rhs[pos_of[int(g.e(c, k, j, i))]] += src_fac * mom[c] * w / dualvol(c, k, j, i)
+            if src_kind == 0:
+                for (k, j, i, w) in weights(c, pos):
+                    rhs[pos_of[int(g.e(c, k, j, i))]] += src_fac * mom[c] * w / dualvol(c, k, j, i)
+            else:
+                for (k, j, i, w) in weights(c + 3, pos):
+                    m_full[int(g.h(c, k, j, i))] += mom[c] * w / dualvol(c + 3, k, j, i)
+        if src_kind != 0:
+            rhs += (CH @ m_full)[idx] / (1j * Om * MU0)
         sol = lu.solve(rhs)
         e_full = np.zeros(g.eoff[-1], dtype=np.complex128)
         e_full[idx] = sol
-        h_full = (CE @ e_full) / (1j * Om * MU0) / src_fac
+        fields.append([e_full[g.eoff[c]:g.eoff[c + 1]].reshape(g.eshape[c]) for c in range(3)])
+        h_full = (CE @ e_full - m_full) / (1j * Om * MU0) / src_fac
         for ri, rp in enumerate(receivers):
             for ci, c in enumerate(rec_comp):
                 val = 0j
@@ -329,4 +349,4 @@ def solve(x, y, z, rho, npml, f0, freq, dt, sources, receivers, rec_comp,
                     if m is not None:
                         val += w * sol[m]
                 out[si, ri, ci] = val
-    return out
+    return (out, fields) if full else out

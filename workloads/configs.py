@@ -42,6 +42,7 @@ class Workload:
     extra: dict = field(default_factory=dict)
     rho_v: np.ndarray | None = None   # vertical resistivity (VTI); None: isotropic
     fd_order: int = 2             # order of the staggered differences (2 or 4)
+    src_kind: int = 0             # 0: electric dipoles (J, moments in A m); 1: magnetic (M, V m)
 
     @property
     def shape(self):
