@@ -80,9 +80,11 @@ def adjoint_gradient(p, fwd: dict, resid: np.ndarray, gamma_rel: float = 1e-12,
                      gamma_abs: float = 0.0, probe_nodes: list | None = None):
     """Gradient of phi_d with respect to ln(rho) for every cell.
 
-    fwd    output of ``stepping.forward(p, want_volume=True)`` (with a
-           decimated volume transform, the adjoint transform is decimated
-           alike and the gradient is that of the two decimated transforms)
+    fwd    output of ``stepping.forward(p, want_volume=True)``; its volume
+           transform may be decimated (stepping.run_stepping), the adjoint
+           transform never is: the adjoint sources built from the basis
+           functions start at full amplitude and fall within a few steps,
+           so a decimated adjoint transform would alias
     resid  weighted residual W^2 (d - E) [ns][nr][ncomp][nf]
     Returns dict(grad [nz][ny][nx], grad_edges (gx, gy, gz), basis, fit,
     probe [ns][len(probe_nodes)][nf] raw adjoint transforms at probe_nodes)."""
@@ -99,9 +101,7 @@ def adjoint_gradient(p, fwd: dict, resid: np.ndarray, gamma_rel: float = 1e-12,
     probes = []
     for si in range(len(p.src_pos)):
         inj, ts, _ = adjoint_sources(s, p.rec_pos, p.rec_comp, resid[si], b)
-        # the adjoint volume transform decimated as the forward one
-        acc, v = run_stepping(s, inj, ts, probe_nodes or [], True,
-                              decimate=fwd.get("decimate", 1))
+        acc, v = run_stepping(s, inj, ts, probe_nodes or [], True)
         probes.append(acc)
         E = fwd["vol"][si]
         for c, g in enumerate((gx, gy, gz)):

@@ -32,6 +32,11 @@ Follows Section 2 of the paper:
     what it injects, at the times it injects it), so
     E(omega_k) = u(omega_k) / W^M_k with W^M_k = sum_n w_n z_k^n, and
     H(omega_k) = u_H(omega_k) / (sqrt(-i omega_k / 2 omega0) W^M_k).
+  * an option that is not the paper's: the volume transform decimated by D,
+    D sum over m = D, 2D, ... of E^m z^m, a coarser Riemann sum of the
+    integral of eq. dtft (receivers keep every sample).  Its error is the
+    aliasing of the field's content above pi / (D dt); the forward field,
+    driven by a wavelet many steps wide, has little there.
 Receiver components: 0, 1, 2 = E_x, E_y, E_z; 3, 4, 5 = H_x, H_y, H_z.
 Source kinds: 0 = electric dipoles (J), 1 = magnetic dipoles (M).
 """
