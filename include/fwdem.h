@@ -359,8 +359,21 @@ enum {
                                 reports FWD_ERR_HIP.  The run's state is then undefined. */
   FWD_OPT_PERSIST_BLOCKS = 16, /* persistent schedule: blocks per compute unit, 1 .. 32, or 0
                                 (default) for as many as the occupancy of the kernel allows */
-  FWD_OPT_BARRIER_SLEEP = 17 /* persistent schedule: pause between two polls of a waiting block,
+  FWD_OPT_BARRIER_SLEEP = 17, /* persistent schedule: pause between two polls of a waiting block,
                                 in units of 64 clock cycles, 1 (default) .. 64 */
+  FWD_OPT_DFT_DECIMATE = 18  /* D = 1 (default), 2, 4, ..., 64: forward runs add to the volume
+                                transform only the samples E^m with m a multiple of D, each
+                                weighted by D -- a coarser Riemann sum of eq. dtft than eq.
+                                dft, an approximation that is not the paper's.  Its error is
+                                the aliasing of the field's content above pi / (D dt): small
+                                while D dt is well inside the source wavelet's width
+                                (fwd_info.tau).  Receiver transforms and the adjoint's gradient
+                                product take every sample (the adjoint sources of Section 3.3
+                                start at full amplitude and would alias).  The E update keeps
+                                history only on sampled steps and the block transform runs
+                                once per D * FWD_OPT_DFT_BLOCK steps.  Schedule 0 only (other
+                                schedules report FWD_ERR_UNSUPPORTED for forward runs with a
+                                volume transform). */
 };
 fwd_status fwd_set_option(fwd_plan *plan, int key, double value);
 fwd_status fwd_get_option(const fwd_plan *plan, int key, double *value);

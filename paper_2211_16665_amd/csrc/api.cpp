@@ -317,6 +317,14 @@ fwd_status fwd_set_option(fwd_plan *h, int key, double value) {
         if (!(value >= 0.0)) fail(FWD_ERR_INVALID_ARG, "barrier wait limit >= 0 microseconds");
         p.barrier_us = value;
         break;
+      case FWD_OPT_DFT_DECIMATE: {
+        int l = 0;
+        while (l <= 6 && (1 << l) != v) ++l;
+        if (l > 6) fail(FWD_ERR_INVALID_ARG, "decimation in {1, 2, 4, ..., 64}");
+        p.dec = v;
+        p.dec_log2 = l;
+        break;
+      }
       case FWD_OPT_PERSIST_BLOCKS:
         if (v < 0 || v > 32) fail(FWD_ERR_INVALID_ARG, "blocks per compute unit in [0, 32]");
         p.persist_blocks = v;
@@ -388,6 +396,7 @@ fwd_status fwd_get_option(const fwd_plan *h, int key, double *value) {
       case FWD_OPT_LEAN: *value = p.lean; break;
       case FWD_OPT_BARRIER_US: *value = p.barrier_us; break;
       case FWD_OPT_PERSIST_BLOCKS: *value = p.persist_blocks; break;
+      case FWD_OPT_DFT_DECIMATE: *value = p.dec; break;
       case FWD_OPT_BARRIER_SLEEP: *value = p.barrier_sleep; break;
       default: fail(FWD_ERR_INVALID_ARG, "unknown option");
     }

@@ -101,6 +101,7 @@ struct StepArgs {
   int nbx, nby, nbz, nblocks, xcd, kz;   // nblocks = tiles * ns (the grid)
   int lean;           // interior tiles take the lean paths (npml >= 1)
   int kb;             // samples per transform block
+  int dl;             // log2 of the volume transform's decimation (forward runs; 0: every sample)
   FDiv dplane, dpx;   // node decode of the block transform (q -> k, j, i)
   int order;          // tile numbering: 0 x fastest, 1 z fastest
   FDiv dns, dnbx, dnby, dnbz;             // dividers of the block decode (set_grid)
@@ -599,18 +600,20 @@ struct Acc<ACC_F32> {
 
 // After the E update of the three components at q .. q+VX-1 (new values e1
 // = sample m = n+1 of eq. dft): the samples of the current transform block
-// wait in the history buffer until the block closes (m % KB == 0); sample
-// m with m % KB = r (1 .. KB-1) goes to slot r-1.  The closing sample stays
-// in the field buffer, where the block transform k_transform reads it.
+// wait in the history buffer until the block closes; with decimation D =
+// 2^dl only samples m = jD enter, and sample j with j % KB = r (1 .. KB-1)
+// goes to slot r-1 (D = 1: j = m).  The closing sample (r = 0) stays in the
+// field buffer, where the block transform k_transform reads it.
 // Elements outside a component's lattice (ok bit clear) keep garbage that
 // k_transform never reads; steps past the run keep nothing.
 template <typename T, int VX>
 __device__ __forceinline__ void hist_store(const StepArgs<T> &A, int s, int64_t q,
                                            const Vec<T, VX> (&e1)[3], const unsigned (&ok)[3],
                                            int n) {
-  const int kb = A.kb;
+  const int kb = A.kb, m = n + 1;
   if (kb <= 1 || n >= A.nt || !(ok[0] | ok[1] | ok[2])) return;
-  const int r = (n + 1) & (kb - 1);
+  if (m & ((1 << A.dl) - 1)) return;
+  const int r = (m >> A.dl) & (kb - 1);
   if (r == 0) return;
   T *h = A.hist + (int64_t)s * A.hist_src + q + (int64_t)(r - 1) * 3 * A.F;
 #pragma unroll
@@ -1310,24 +1313,37 @@ __global__ void __launch_bounds__(256) k_step(StepArgs<T> A) {
 // thread holds only its KB samples; the block's twiddles (all frequencies)
 // are staged once in LDS and read as broadcasts.
 // The block's twiddles (all frequencies) in LDS: s_tw[kf * KB + t] for the
-// samples first .. first+cnt-1 (zero beyond cnt); the caller synchronises.
+// samples first, first + D, ..., first + (cnt-1) D (zero beyond cnt), each
+// times the weight D of a decimated sample (a power of two: exact); the
+// caller synchronises.
 template <typename T, bool ADJ, int KB>
 __device__ __forceinline__ void stage_twiddles(const StepArgs<T> &A, double2 *s_tw, int first,
-                                               int cnt, int tid, int nthr) {
+                                               int cnt, int dl, int tid, int nthr) {
   const double2 *tw = ADJ ? A.Q : A.zE;
   const int nf = A.nf;
+  const double wgt = (double)(1 << dl);
   for (int e = tid; e < nf * KB; e += nthr) {
     const int kf = e / KB, t = e - kf * KB;
-    s_tw[e] = t < cnt ? tw[(int64_t)(first - 1 + t) * nf + kf] : make_double2(0.0, 0.0);
+    double2 v = make_double2(0.0, 0.0);
+    if (t < cnt) {
+      v = tw[(int64_t)(first - 1 + (t << dl)) * nf + kf];
+      v.x *= wgt;
+      v.y *= wgt;
+    }
+    s_tw[e] = v;
   }
 }
 
 // The block transform of node q (padded layout), component c of source s:
-// the cnt samples ending at m_last, twiddles staged in s_tw.
+// the cnt samples first, first + D, ... (D = 2^A.dl), twiddles staged in
+// s_tw.  A closing block reads its newest sample from the field half
+// m_last % 2 (m_last: the step just completed); a flush reads every sample
+// from the history.
 template <typename T, int ACC, bool ADJ, int KB, bool FLUSH>
 __device__ __forceinline__ void transform_node(const StepArgs<T> &A, int64_t q, int s, int c,
-                                               int m_last, int cnt, const double2 *s_tw) {
-  const int nf = A.nf, nt = A.nt, first = m_last - cnt + 1;
+                                               int first, int cnt, int m_last,
+                                               const double2 *s_tw) {
+  const int nf = A.nf, nt = A.nt, dl = A.dl;
   const uint32_t qq = (uint32_t)q;
   const uint32_t k = fdiv(qq, A.dplane), rem = qq - k * (uint32_t)A.plane;
   const uint32_t j = fdiv(rem, A.dpx), i = rem - j * (uint32_t)A.PX;
@@ -1345,9 +1361,9 @@ __device__ __forceinline__ void transform_node(const StepArgs<T> &A, int64_t q, 
 #pragma unroll
   for (int t = 0; t < KB; ++t) {
     T v = T(0);
-    if (t < cnt - 1) v = h[(int64_t)t * F3];
+    if (t < cnt - 1 || (FLUSH && t < cnt)) v = h[(int64_t)t * F3];
     else if (t == cnt - 1) v = f[0];
-    const int idx = first + t;
+    const int idx = first + (t << dl);
     val[t] = idx <= fl || idx > nt ? T(0) : v;
   }
   const int64_t base = ((int64_t)s * nf * 3 + c) * F + q;    // + kf * 3 F
@@ -1404,15 +1420,18 @@ __device__ __forceinline__ void transform_node(const StepArgs<T> &A, int64_t q, 
 template <typename T, int ACC, bool ADJ, int KB, bool FLUSH>
 __global__ void __launch_bounds__(256) k_transform(StepArgs<T> A) {
   extern __shared__ double2 s_tw[];          // [nf][KB] twiddles of the block
-  const int m_last = A.step[0] + 1;          // the newest sample
-  const int r_end = m_last & (KB - 1);
+  const int m_last = A.step[0] + 1;          // the step just completed
+  const int j_last = m_last >> A.dl;         // the newest (decimated) sample
+  const int r_end = j_last & (KB - 1);
   const int cnt = FLUSH ? r_end : KB;
-  if (FLUSH ? cnt == 0 : r_end != 0) return; // uniform: the whole grid returns
-  stage_twiddles<T, ADJ, KB>(A, s_tw, m_last - cnt + 1, cnt, threadIdx.x, blockDim.x);
+  // uniform: the whole grid returns
+  if (FLUSH ? cnt == 0 : r_end != 0 || (m_last & ((1 << A.dl) - 1)) != 0) return;
+  const int first = (j_last - cnt + 1) << A.dl;
+  stage_twiddles<T, ADJ, KB>(A, s_tw, first, cnt, A.dl, threadIdx.x, blockDim.x);
   __syncthreads();
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= A.F) return;
-  transform_node<T, ACC, ADJ, KB, FLUSH>(A, q, blockIdx.y, blockIdx.z, m_last, cnt, s_tw);
+  transform_node<T, ACC, ADJ, KB, FLUSH>(A, q, blockIdx.y, blockIdx.z, first, cnt, m_last, s_tw);
 }
 
 // ---------------------------------------------------------------------------
@@ -1513,14 +1532,14 @@ __global__ void __launch_bounds__(256) k_persist(StepArgs<T> A, StepArgs<T> Ah, 
     if (!grid_sync(B)) return;
     if (HIST && (n + 1) % KB == 0) {
       const int m = n + 1;
-      stage_twiddles<T, ADJ, KB>(A, s_tw, m - KB + 1, KB, tid, nthr);
+      stage_twiddles<T, ADJ, KB>(A, s_tw, m - KB + 1, KB, 0, tid, nthr);
       __syncthreads();
       const uint32_t total = nq * (uint32_t)A.ns * 3u;
       for (uint32_t vb = blockIdx.x; vb < total; vb += gridDim.x) {
         const uint32_t qc = vb % nq, rest = vb / nq;
         const int s = (int)(rest % (uint32_t)A.ns), c = (int)(rest / (uint32_t)A.ns);
         const int64_t q = (int64_t)qc * nthr + tid;
-        if (q < A.F) transform_node<T, ACC, ADJ, KB, false>(A, q, s, c, m, KB, s_tw);
+        if (q < A.F) transform_node<T, ACC, ADJ, KB, false>(A, q, s, c, m - KB + 1, KB, m, s_tw);
       }
       if (!grid_sync(B)) return;
     }
@@ -2491,6 +2510,7 @@ static StepArgs<T> make_args(Plan &p, Dev &d, const WS &w, void *vol, bool adj, 
   A.order = p.order;
   A.lean = p.npml >= 1 && p.lean ? 1 : 0;
   A.kb = p.kb;
+  A.dl = adj ? 0 : p.dec_log2;   // the adjoint's gradient product takes every sample
   A.dplane = fdiv_make((uint32_t)A.plane);
   A.dpx = fdiv_make((uint32_t)p.PX);
   A.nf = p.nf();
@@ -2652,11 +2672,14 @@ static void enqueue_step(Plan &p, Dev &d, const WS &w, void *vol, bool adj, hipS
     Ah.tl_ent = hinj ? d.tl_ent[hm] : nullptr;
     const bool o4 = p.fd_order == 4;
     launch_h<T>(Ah, p.vxh, dim3(Ah.nblocks), block, st, kh, o4, hinj);
-    launch_e<T>(A, p.vx, vol != nullptr, grid, block, st, ke, o4);
+    // with a decimated volume transform only the steps whose sample enters
+    // it keep history
+    const int D = adj ? 1 : p.dec;
+    launch_e<T>(A, p.vx, vol != nullptr && (n + 1) % D == 0, grid, block, st, ke, o4);
   }
   // the block transform after the step whose sample closes a block; it reads
   // the counter the E update has just written (step n)
-  const bool close = vol != nullptr && (n + 1) % p.kb == 0;
+  const bool close = vol != nullptr && (n + 1) % (p.kb * (adj ? 1 : p.dec)) == 0;
   if (closed) *closed = close;
   if (close) {
     StepArgs<T> At = A;
@@ -2674,7 +2697,9 @@ static void enqueue_step(Plan &p, Dev &d, const WS &w, void *vol, bool adj, hipS
 // index from the equalised counters.
 template <typename T>
 static void flush_t(Plan &p, Dev &d, const WS &w, void *vol, bool adj, hipStream_t st) {
-  if (p.kb == 1 || !vol || p.host_step % p.kb == 0) return;
+  // decimated samples taken so far (every step's sample when D = 1)
+  const int taken = p.host_step / (adj ? 1 : p.dec);
+  if (p.kb == 1 || !vol || taken % p.kb == 0) return;
   build_lists(p, d);
   hipLaunchKernelGGL(k_equalize, dim3(1), dim3(64), 0, st, w.step);
   StepArgs<T> A = make_args<T>(p, d, w, vol, adj);
@@ -2792,6 +2817,9 @@ static void run_steps_t(Plan &p, Dev &d, const WS &w, void *vol, bool adj, int n
   build_lists(p, d);
   // both counters hold the last completed step; the steps then alternate
   // (r = counter read by the next step)
+  const int D = adj ? 1 : p.dec;
+  if (D > 1 && vol && p.sched != 0)
+    fail(FWD_ERR_UNSUPPORTED, "a decimated volume transform runs with schedule 0");
   hipLaunchKernelGGL(k_equalize, dim3(1), dim3(64), 0, st, w.step);
   if (p.sched == 2) {
     run_persistent<T>(p, d, w, vol, adj, nsteps, st);
@@ -2799,9 +2827,11 @@ static void run_steps_t(Plan &p, Dev &d, const WS &w, void *vol, bool adj, int n
   }
   int r = 0;
   // graphs hold an even number of steps (they start and end at r = 0) and a
-  // whole number of transform blocks (every replay starts at the same phase)
-  const int unit = std::max(2, p.kb);
-  const int K = plain ? 0 : (p.graph_steps & ~1) / unit * unit;
+  // whole number of transform blocks (every replay starts at the same phase);
+  // a block of D-decimated samples spans kb * D steps
+  const int unit = std::max(2, p.kb * D);
+  const int Kg = p.graph_steps & ~1;
+  const int K = plain || Kg < 2 ? 0 : std::max(unit, Kg / unit * unit);
   const int sample = plain ? 0 : d.sample_every;
   // eager launches of m steps, each bracketed by events if asked
   auto eager = [&](int m, bool timed) {
@@ -2833,10 +2863,10 @@ static void run_steps_t(Plan &p, Dev &d, const WS &w, void *vol, bool adj, int n
     return;
   }
   // graph of K steps, captured on a private stream and replayed on st
-  const int phase = p.host_step % p.kb;
+  const int phase = p.host_step % (p.kb * D);
   char key[256];
   snprintf(key, sizeof key, "%p/%p/%d/%d/%d/%d/%d/%d/%d/%d/%d/%d/%d/%d/%d/%llu/%llu", w.fields,
-           vol, (int)adj, K, phase, p.bx, p.by, p.xcd, p.kb, p.vx, p.vxh, p.sched, p.kz, p.order,
+           vol, (int)adj, K, phase, p.bx, p.by, p.xcd, p.kb * 64 + D, p.vx, p.vxh, p.sched, p.kz, p.order,
            p.lean, (unsigned long long)p.model_version, (unsigned long long)p.basis_version);
   if (!d.exec || d.exec_key != key) {
     if (d.exec) {
@@ -3353,6 +3383,8 @@ double dev_autotune(Plan &p, void *ws, size_t ws_bytes, void *vol, size_t vol_by
   ensure_tables(p, st);
   Dev &d = D(p);
   const bool o4 = p.fd_order == 4;      // order 4: two-kernel schedule, scalar threads
+  // a decimated forward volume transform runs on the two-kernel schedule only
+  const bool sched0_only = o4 || (vol && !adj && p.dec > 1);
   // transform blocks the caller's workspace can hold (the history grows with K)
   std::vector<int> kbs{p.kb};
   if (vol) {
@@ -3364,9 +3396,9 @@ double dev_autotune(Plan &p, void *ws, size_t ws_bytes, void *vol, size_t vol_by
     p.kb = keep;
   }
   char key[256];
-  snprintf(key, sizeof key, "%d/%d/%d/%d/%d/%d/%d/%d/%d/%d/%d/%d/%d/%d", p.nx, p.ny, p.nz, p.npml,
-           p.ns, p.nf(), p.dtype, p.acc, p.fd_order, mode, vol ? 1 : 0, (int)kbs.size(),
-           (int)p.rn_c.size(), steps);
+  snprintf(key, sizeof key, "%d/%d/%d/%d/%d/%d/%d/%d/%d/%d/%d/%d/%d/%d/%d", p.nx, p.ny, p.nz,
+           p.npml, p.ns, p.nf(), p.dtype, p.acc, p.fd_order, mode, vol ? 1 : 0, (int)kbs.size(),
+           (int)p.rn_c.size(), steps, adj ? 1 : p.dec);
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune_cache.find(key);
@@ -3448,7 +3480,7 @@ double dev_autotune(Plan &p, void *ws, size_t ws_bytes, void *vol, size_t vol_by
       }
   }
   // stage 4: the fused schedule
-  if (!o4) {
+  if (!sched0_only) {
     const TuneCand base = best;
     const int fused[][2] = {{64, 4}, {32, 8}, {16, 16}, {16, 8}};
     for (auto &sh : fused)
@@ -3463,7 +3495,7 @@ double dev_autotune(Plan &p, void *ws, size_t ws_bytes, void *vol, size_t vol_by
       }
   }
   // the persistent schedule (transform blocks of 8 or 16 only)
-  if (!o4 && (!vol || p.kb == 8 || p.kb == 16)) {
+  if (!sched0_only && (!vol || p.kb == 8 || p.kb == 16)) {
     const TuneCand base = best;
     const int pers[][2] = {{64, 4}, {32, 8}};
     for (auto &sh : pers) {
