@@ -690,11 +690,11 @@ def large_window(args):
     w = with_window(c5_large(), args.window)
     acc = args.acc or w.acc_mode
     rho0 = background_model(w)
-    # workspaces sized for the longer transform block (16 samples), so that
-    # the autotuner may choose either block
+    # workspaces sized for the longest transform block (32 samples), so that
+    # the autotuner may choose any block
     one = fw.Plan.from_workload(w.replace(src_pos=w.src_pos[:1], src_mom=w.src_mom[:1]),
                                 field_dtype=args.field_dtype, acc_mode=acc)
-    one.set_option(fw.FWD_OPT_DFT_BLOCK, 16)
+    one.set_option(fw.FWD_OPT_DFT_BLOCK, 32)
     one.set_model(w.rho)
     per_src = one.workspace_size(fw.FWD_MODE_ADJOINT) + one.volume_size()
     del one
@@ -705,7 +705,7 @@ def large_window(args):
     for a, b in groups:
         wg = w.replace(src_pos=w.src_pos[a:b], src_mom=w.src_mom[a:b])
         p = fw.Plan.from_workload(wg, field_dtype=args.field_dtype, acc_mode=acc)
-        p.set_option(fw.FWD_OPT_DFT_BLOCK, 16)
+        p.set_option(fw.FWD_OPT_DFT_BLOCK, 32)
         p.set_model(w.rho)
         plans.append(p)
     gmax = max(b - a for a, b in groups)

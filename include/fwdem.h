@@ -29,7 +29,10 @@
  *     named *_dev are device memory on the current HIP device.  Device
  *     buffers passed in (workspace, volume, outputs) are owned by the
  *     caller and must stay alive until the work enqueued on `stream` ends.
- *     The plan owns only tables proportional to one copy of the model.
+ *     Workspace, volume, scratch and snapshot buffers start on a 256-byte
+ *     boundary (as hipMalloc returns them); others are rejected with
+ *     FWD_ERR_INVALID_ARG.  The plan owns only tables proportional to one
+ *     copy of the model.
  *   * Work is enqueued on the caller's stream (a hipStream_t passed as
  *     void*, 0 for the null stream).  fwd_forward / fwd_adjoint wait for
  *     their own work before returning, so that a non-finite result can be
@@ -311,7 +314,7 @@ enum {
   FWD_OPT_STRICT_CFL = 5,    /* 1 (default): fwd_set_model rejects a fixed dt above the CFL
                                 bound with FWD_ERR_CFL; 0 lets it run (and typically end in
                                 FWD_ERR_NONFINITE) */
-  FWD_OPT_DFT_BLOCK = 6,     /* 1, 2, 4, 8 (default) or 16: samples per read-modify-write of the
+  FWD_OPT_DFT_BLOCK = 6,     /* 1, 2, 4, 8 (default), 16 or 32: samples per read-modify-write of the
                                 volume transform (and of the gradient product).  The E update
                                 keeps samples 1 .. K-1 of a block in a history buffer of the
                                 workspace; after the step whose sample closes the block, a
@@ -381,7 +384,7 @@ fwd_status fwd_get_option(const fwd_plan *plan, int key, double *value);
 /* Self-written tile/schedule autotuner.  A staged search on the given
  * buffers: block shape, then vector widths, then tile order and XCD remap,
  * then the fused schedule (shapes, planes per block), then the transform
- * block FWD_OPT_DFT_BLOCK in {8, 16} when vol_dev is given and ws_bytes holds
+ * block FWD_OPT_DFT_BLOCK in {8, 16, 32} when vol_dev is given and ws_bytes holds
  * the workspace of the longer block.  Each candidate runs `steps` steps of
  * the given mode untimed (graph capture) and then the same number timed; the
  * fastest is kept (as options of the plan) and its time per step (ms)

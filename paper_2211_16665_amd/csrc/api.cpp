@@ -41,6 +41,13 @@ static const Plan &P(const fwd_plan *h) {
   return *h->p;
 }
 
+// Device buffers the library carves (workspace, volume transform, scratch,
+// snapshots) start on a 256-byte boundary, as hipMalloc returns them.
+static void need_aligned(const void *ptr, const char *what) {
+  if (reinterpret_cast<uintptr_t>(ptr) & 255u)
+    fail(FWD_ERR_INVALID_ARG, std::string(what) + " must be 256-byte aligned");
+}
+
 extern "C" {
 
 const char *fwd_last_error(void) { return g_err.c_str(); }
@@ -140,6 +147,8 @@ fwd_status fwd_forward(fwd_plan *h, void *ws, size_t ws_bytes, void *vol, size_t
     Plan &p = P(h);
     if (!p.have_model) fail(FWD_ERR_STATE, "no model set");
     if (!ws || !E_rec) fail(FWD_ERR_INVALID_ARG, "workspace and E_rec are required");
+    need_aligned(ws, "workspace");
+    need_aligned(vol, "volume buffer");
     dev_forward(p, ws, ws_bytes, vol, vol_bytes, E_rec, stream);
   });
 }
@@ -150,6 +159,7 @@ fwd_status fwd_forward_static(fwd_plan *h, void *vol, size_t vol_bytes, double *
     Plan &p = P(h);
     if (!p.have_model) fail(FWD_ERR_STATE, "no model set");
     if (!E_rec) fail(FWD_ERR_INVALID_ARG, "E_rec is required");
+    need_aligned(vol, "volume buffer");
     dev_forward_static(p, vol, vol_bytes, E_rec, stream);
   });
 }
@@ -160,6 +170,8 @@ fwd_status fwd_run_begin(fwd_plan *h, void *ws, size_t ws_bytes, void *vol, size
     Plan &p = P(h);
     if (!p.have_model) fail(FWD_ERR_STATE, "no model set");
     if (!ws) fail(FWD_ERR_INVALID_ARG, "workspace is required");
+    need_aligned(ws, "workspace");
+    need_aligned(vol, "volume buffer");
     dev_run_begin(p, ws, ws_bytes, vol, vol_bytes, stream);
   });
 }
@@ -169,6 +181,8 @@ fwd_status fwd_run_steps(fwd_plan *h, void *ws, void *vol, int nsteps, void *str
     Plan &p = P(h);
     if (!p.have_model) fail(FWD_ERR_STATE, "no model set");
     if (!ws) fail(FWD_ERR_INVALID_ARG, "workspace is required");
+    need_aligned(ws, "workspace");
+    need_aligned(vol, "volume buffer");
     dev_run_steps(p, ws, vol, nsteps, stream);
   });
 }
@@ -206,6 +220,8 @@ fwd_status fwd_checkpoint_save(fwd_plan *h, const void *ws, const void *vol, voi
     Plan &p = P(h);
     if (!p.have_model) fail(FWD_ERR_STATE, "no model set");
     if (!ws || !snap) fail(FWD_ERR_INVALID_ARG, "workspace and snapshot are required");
+    need_aligned(ws, "workspace");
+    need_aligned(snap, "snapshot");
     dev_checkpoint(p, ws, vol, snap, 1, stream);
   });
 }
@@ -216,6 +232,8 @@ fwd_status fwd_checkpoint_restore(fwd_plan *h, void *ws, void *vol, const void *
     Plan &p = P(h);
     if (!p.have_model) fail(FWD_ERR_STATE, "no model set");
     if (!ws || !snap) fail(FWD_ERR_INVALID_ARG, "workspace and snapshot are required");
+    need_aligned(ws, "workspace");
+    need_aligned(snap, "snapshot");
     dev_checkpoint(p, ws, vol, const_cast<void *>(snap), 0, stream);
   });
 }
@@ -241,6 +259,8 @@ fwd_status fwd_adjoint(fwd_plan *h, void *ws, size_t ws_bytes, const void *vol,
     Plan &p = P(h);
     if (!p.have_model) fail(FWD_ERR_STATE, "no model set");
     if (!ws || !resid || !grad) fail(FWD_ERR_INVALID_ARG, "workspace, residual and gradient are required");
+    need_aligned(ws, "workspace");
+    need_aligned(vol, "volume buffer");
     dev_adjoint(p, ws, ws_bytes, vol, resid, grad, accumulate, E_adj, stream);
   });
 }
@@ -263,6 +283,8 @@ fwd_status fwd_adjoint_td(fwd_plan *h, void *ws, size_t ws_bytes, void *scratch,
     if (!p.have_model) fail(FWD_ERR_STATE, "no model set");
     if (!ws || !scratch || !resid || !grad)
       fail(FWD_ERR_INVALID_ARG, "workspace, scratch, residual and gradient are required");
+    need_aligned(ws, "workspace");
+    need_aligned(scratch, "scratch");
     dev_adjoint_td(p, ws, ws_bytes, scratch, scratch_bytes, segment, resid, grad, accumulate,
                    stream);
   });
@@ -298,8 +320,8 @@ fwd_status fwd_set_option(fwd_plan *h, int key, double value) {
         p.strict_cfl = v ? 1 : 0;
         break;
       case FWD_OPT_DFT_BLOCK:
-        if (v != 1 && v != 2 && v != 4 && v != 8 && v != 16)
-          fail(FWD_ERR_INVALID_ARG, "transform block in {1,2,4,8,16}");
+        if (v != 1 && v != 2 && v != 4 && v != 8 && v != 16 && v != 32)
+          fail(FWD_ERR_INVALID_ARG, "transform block in {1,2,4,8,16,32}");
         p.kb = v;
         break;
 
@@ -410,6 +432,8 @@ fwd_status fwd_autotune(fwd_plan *h, void *ws, size_t ws_bytes, void *vol, size_
     if (!p.have_model) fail(FWD_ERR_STATE, "no model set");
     if (!ws) fail(FWD_ERR_INVALID_ARG, "workspace is required");
     if (steps < 1) fail(FWD_ERR_INVALID_ARG, "steps >= 1");
+    need_aligned(ws, "workspace");
+    need_aligned(vol, "volume buffer");
     const double ms = dev_autotune(p, ws, ws_bytes, vol, vol_bytes, mode, steps, stream);
     if (best_ms) *best_ms = ms;
   });

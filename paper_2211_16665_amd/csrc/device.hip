@@ -2006,6 +2006,25 @@ __global__ void k_set_int(int *p, int v) {
   if (threadIdx.x == 0 && blockIdx.x == 0) p[0] = v;
 }
 
+// Zero n bytes at p (16-byte stores, then the remaining bytes): a kernel
+// rather than a memset node, so that a caller may capture the runs in a
+// graph and replay them.
+__global__ void k_zero(unsigned char *p, size_t n) {
+  const size_t n16 = n / 16, stride = (size_t)gridDim.x * blockDim.x;
+  uint4 *q = reinterpret_cast<uint4 *>(p);
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride)
+    q[i] = make_uint4(0u, 0u, 0u, 0u);
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n - n16 * 16) p[n16 * 16 + t] = 0;
+}
+
+static void zero_bytes(void *p, size_t n, hipStream_t st) {
+  if (n == 0) return;
+  const size_t blocks = std::min<size_t>((n / 16 + 255) / 256 + 1, 8192);
+  hipLaunchKernelGGL(k_zero, dim3((unsigned)blocks), dim3(256), 0, st,
+                     static_cast<unsigned char *>(p), n);
+}
+
 // ---------------------------------------------------------------------------
 // device tables owned by the plan
 // ---------------------------------------------------------------------------
@@ -2602,7 +2621,8 @@ static void launch_transform(const StepArgs<T> &A, int kb, int acc, bool adj, hi
     case 2: launch_transform_kb<T, 2, FLUSH>(A, acc, adj, st, kt); break;
     case 4: launch_transform_kb<T, 4, FLUSH>(A, acc, adj, st, kt); break;
     case 8: launch_transform_kb<T, 8, FLUSH>(A, acc, adj, st, kt); break;
-    default: launch_transform_kb<T, 16, FLUSH>(A, acc, adj, st, kt);
+    case 16: launch_transform_kb<T, 16, FLUSH>(A, acc, adj, st, kt); break;
+    default: launch_transform_kb<T, 32, FLUSH>(A, acc, adj, st, kt);
   }
 }
 
@@ -2934,10 +2954,17 @@ static void collect_kernel_stats(Dev &d) {
   d.kstat_ntr = ntr;
 }
 
+// A run starts from zero fields, CPML memory, receiver sums and counters
+// (and, in adjoint runs, zero gradient accumulators).  The transform-block
+// history is not cleared: every slot a block transform reads was written
+// earlier in the same run (slots of samples past the run are masked by a
+// select), and on the large grids it is the largest part of the workspace.
 static void zero_state(Plan &p, const WS &w, void *ws, void *vol, int mode, hipStream_t st) {
   p.host_step = 0;
-  HIP_CHECK(hipMemsetAsync(ws, 0, p.workspace_bytes(mode), st));
-  if (vol && mode == FWD_MODE_FORWARD) HIP_CHECK(hipMemsetAsync(vol, 0, p.volume_bytes(), st));
+  char *b = static_cast<char *>(ws);
+  zero_bytes(b, p.core_state_bytes(), st);
+  zero_bytes(b + p.state_bytes(), p.workspace_bytes(mode) - p.state_bytes(), st);
+  if (vol && mode == FWD_MODE_FORWARD) zero_bytes(vol, p.volume_bytes(), st);
   hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, st, w.step, -1);
   hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, st, w.step + 1, -1);
   HIP_CHECK(hipGetLastError());
@@ -3389,7 +3416,7 @@ double dev_autotune(Plan &p, void *ws, size_t ws_bytes, void *vol, size_t vol_by
   std::vector<int> kbs{p.kb};
   if (vol) {
     const int keep = p.kb;
-    for (int kb : {8, 16}) {
+    for (int kb : {8, 16, 32}) {
       p.kb = kb;
       if (kb != keep && p.workspace_bytes(mode) <= ws_bytes) kbs.push_back(kb);
     }
@@ -3417,7 +3444,7 @@ double dev_autotune(Plan &p, void *ws, size_t ws_bytes, void *vol, size_t vol_by
   // the flush marker are reset (stepping on from any state costs the same)
   HIP_CHECK(hipMemsetAsync(ws, 0, ws_bytes, st));
   if (vol && !adj) HIP_CHECK(hipMemsetAsync(vol, 0, p.volume_bytes(), st));
-  auto time_cand = [&](const TuneCand &c) {
+  auto time_cand = [&](const TuneCand &c, int nsteps) {
     apply_cand(p, c);
     const WS wc = carve(p, ws);
     for (int t = 0; t < 2; ++t) {
@@ -3426,20 +3453,20 @@ double dev_autotune(Plan &p, void *ws, size_t ws_bytes, void *vol, size_t vol_by
       hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, st, wc.flushed, 0);
       p.host_step = 0;
       if (t == 1) HIP_CHECK(hipEventRecord(e0, st));
-      run_steps_any(p, d, wc, vol, adj, steps, st);
+      run_steps_any(p, d, wc, vol, adj, nsteps, st);
     }
     HIP_CHECK(hipEventRecord(e1, st));
     HIP_CHECK(hipEventSynchronize(e1));
     float ms = 0;
     HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
-    return (double)ms / steps;
+    return (double)ms / nsteps;
   };
   TuneCand best = cand_of(p);
   best.sched = 0;
   best.vx = best.vxh = 1;
   double best_ms = 1e300;
   auto consider = [&](const TuneCand &c) {
-    const double ms = time_cand(c);
+    const double ms = time_cand(c, steps);
     if (ms < best_ms) {
       best_ms = ms;
       best = c;
@@ -3507,15 +3534,25 @@ double dev_autotune(Plan &p, void *ws, size_t ws_bytes, void *vol, size_t vol_by
       consider(c);
     }
   }
-  // stage 5: the transform block
-  {
+  // stage 5: the transform block, every candidate over the same whole
+  // number of the longest block (each closes its blocks inside the timing)
+  if (kbs.size() > 1) {
     const TuneCand base = best;
+    int kmax = 1;
+    for (int kb : kbs) kmax = std::max(kmax, kb);
+    const int ksteps = (std::max(steps, kmax) + kmax - 1) / kmax * kmax;
+    double kbest = 1e300;
     for (int kb : kbs) {
-      if (kb == base.kb) continue;
+      if (base.sched == 2 && kb != 8 && kb != 16) continue;   // the persistent kernel's blocks
       TuneCand c = base;
       c.kb = kb;
-      consider(c);
+      const double ms = time_cand(c, ksteps);
+      if (ms < kbest) {
+        kbest = ms;
+        best = c;
+      }
     }
+    best_ms = kbest;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);

@@ -111,7 +111,7 @@ struct Plan {
 
   // ---- options ----
   int graph_steps = 32, bx = 64, by = 4, xcd = 1, strict_cfl = 1;   // bx: threads along x
-  int kb = 8;                            // samples per volume-transform block (1, 2, 4, 8, 16)
+  int kb = 8;                            // samples per volume-transform block (1, 2, 4, 8, 16, 32)
   int dec = 1, dec_log2 = 0;             // forward volume transform: every dec-th sample (2^dec_log2)
   int vx = 1;                            // E update: 1 x node per thread; 4: a 16-byte vector
   int vxh = 1;                           // the same for the H update

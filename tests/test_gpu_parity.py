@@ -327,7 +327,7 @@ def test_autograd_two_models_through_one_plan(method, fixed_dt):
 # --------------------------------------------------------------------------
 # transform blocking (FWD_OPT_DFT_BLOCK): changes only the order of the sums
 # --------------------------------------------------------------------------
-@pytest.mark.parametrize("kb", [1, 2, 4, 8, 16])
+@pytest.mark.parametrize("kb", [1, 2, 4, 8, 16, 32])
 def test_transform_block_sizes_agree(kb):
     w0, d = _inverse_problem(seed=5, ns=2)
     w0 = w0.replace(nt=w0.nt + 3)            # not a multiple of the block: flush path
@@ -347,7 +347,7 @@ def test_transform_block_sizes_agree(kb):
     assert np.linalg.norm(g - go) / np.linalg.norm(go) < 1e-7
 
 
-@pytest.mark.parametrize("kb,sched", [(8, 0), (16, 0), (16, 1)])
+@pytest.mark.parametrize("kb,sched", [(8, 0), (16, 0), (32, 0), (16, 1)])
 def test_flush_midway_then_continue(kb, sched):
     w = tiny(seed=12, npml=3, ns=1)
     say(f"flush midway, transform block {kb}, schedule {sched}")

@@ -6,6 +6,8 @@ import json
 import os
 import re
 
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -135,6 +137,14 @@ def test_errors_before_any_device_call(lib):
     st = p.lib.fwd_forward(p.handle, None, 0, None, 0, None, None)
     assert st == 1
     assert b"required" in p.lib.fwd_last_error()
+    # a workspace off the 256-byte boundary: refused before any HIP call
+    # (the pointers are never dereferenced)
+    bogus = ctypes.c_void_p(0x10010)
+    out = ctypes.c_void_p(0x20000)
+    st = p.lib.fwd_forward(p.handle, bogus, 1 << 20, None, 0, out, None)
+    assert st == 1 and b"256-byte aligned" in p.lib.fwd_last_error()
+    st = p.lib.fwd_run_steps(p.handle, ctypes.c_void_p(0x30000), bogus, 1, None)
+    assert st == 1 and b"volume buffer must be 256-byte aligned" in p.lib.fwd_last_error()
 
 
 @pytest.mark.parametrize("make", [c1_wholespace, c2_marine1d, c3_blocks,
