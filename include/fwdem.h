@@ -208,36 +208,44 @@ fwd_status fwd_forward_static(fwd_plan *plan, void *vol_dev, size_t vol_bytes, d
  * (and vol, if given); fwd_run_steps advances it by nsteps (the step index
  * lives in the workspace, so runs may be split anywhere); fwd_run_receivers
  * writes the receiver output of the steps done so far, normalised as in
- * fwd_forward.  Only FWD_MODE_FORWARD runs can be split. */
+ * fwd_forward.  Only FWD_MODE_FORWARD runs can be split.  Every call takes
+ * the byte counts of its buffers: a workspace below
+ * fwd_workspace_size(FORWARD) or a volume buffer below fwd_volume_size is
+ * refused with FWD_ERR_INVALID_ARG before any device work. */
 fwd_status fwd_run_begin(fwd_plan *plan, void *ws_dev, size_t ws_bytes,
                          void *vol_dev, size_t vol_bytes, void *stream);
-fwd_status fwd_run_steps(fwd_plan *plan, void *ws_dev, void *vol_dev,
-                         int nsteps, void *stream);
-fwd_status fwd_run_receivers(fwd_plan *plan, void *ws_dev, double *E_rec_dev,
+fwd_status fwd_run_steps(fwd_plan *plan, void *ws_dev, size_t ws_bytes, void *vol_dev,
+                         size_t vol_bytes, int nsteps, void *stream);
+fwd_status fwd_run_receivers(fwd_plan *plan, void *ws_dev, size_t ws_bytes, double *E_rec_dev,
                              void *stream);
 
 /* Add the samples of an incomplete transform block (nsteps not a multiple of
  * FWD_OPT_DFT_BLOCK) to the volume transform, so that vol_dev holds the sum
  * over every step run so far.  Stepping may continue afterwards: samples
  * already added are not added again.  fwd_forward does this itself. */
-fwd_status fwd_run_flush(fwd_plan *plan, void *ws_dev, void *vol_dev, void *stream);
+fwd_status fwd_run_flush(fwd_plan *plan, void *ws_dev, size_t ws_bytes, void *vol_dev,
+                         size_t vol_bytes, void *stream);
 
 /* Snapshot of the forward state (both halves of the double-buffered fields
  * and CPML memory, receiver sums, step index, transform-block history; the
  * volume transform when vol_dev is given): fwd_checkpoint_size bytes of
- * caller memory (device) per snapshot. */
+ * caller memory (device) per snapshot.  Buffers below their sizes (ws_bytes,
+ * vol_bytes, snap_bytes) are refused with FWD_ERR_INVALID_ARG. */
 fwd_status fwd_checkpoint_size(const fwd_plan *plan, int with_volume, size_t *bytes);
-fwd_status fwd_checkpoint_save(fwd_plan *plan, const void *ws_dev, const void *vol_dev,
-                               void *snap_dev, void *stream);
-fwd_status fwd_checkpoint_restore(fwd_plan *plan, void *ws_dev, void *vol_dev,
-                                  const void *snap_dev, void *stream);
+fwd_status fwd_checkpoint_save(fwd_plan *plan, const void *ws_dev, size_t ws_bytes,
+                               const void *vol_dev, size_t vol_bytes, void *snap_dev,
+                               size_t snap_bytes, void *stream);
+fwd_status fwd_checkpoint_restore(fwd_plan *plan, void *ws_dev, size_t ws_bytes, void *vol_dev,
+                                  size_t vol_bytes, const void *snap_dev, size_t snap_bytes,
+                                  void *stream);
 
-/* Normalised volume field E(omega_k) from a forward volume transform:
- * out_dev complex [nsrc][nfreq][3][nz+1][ny+1][nx+1]; component c sits at
- * its staggered position (E_x at (x_{i+1/2}, y_j, z_k), ...), slots outside
- * a component's lattice are 0. */
-fwd_status fwd_volume_export(fwd_plan *plan, const void *vol_dev, double *out_dev,
-                             void *stream);
+/* Normalised volume field E(omega_k) from a forward volume transform
+ * (vol_bytes >= fwd_volume_size): out_dev complex
+ * [nsrc][nfreq][3][nz+1][ny+1][nx+1]; component c sits at its staggered
+ * position (E_x at (x_{i+1/2}, y_j, z_k), ...), slots outside a component's
+ * lattice are 0. */
+fwd_status fwd_volume_export(fwd_plan *plan, const void *vol_dev, size_t vol_bytes,
+                             double *out_dev, void *stream);
 
 /* Basis functions of the adjoint-source estimate (Section 3.3): the 2 nfreq
  * columns of B+ = (B^T B + gamma I)^-1 B^T, each obtained by a conjugate
@@ -252,7 +260,9 @@ fwd_status fwd_basis_build(fwd_plan *plan, double gamma_rel, double gamma_abs,
                            int max_iter, double tol, double *fit_err, int *iters);
 
 /* Adjoint run and gradient.
- *   vol_fwd_dev   forward volume transform of the same model and sources
+ *   ws_dev        fwd_workspace_size(FWD_MODE_ADJOINT) bytes (ws_bytes)
+ *   vol_fwd_dev   forward volume transform of the same model and sources,
+ *                 vol_bytes >= fwd_volume_size
  *   resid_dev     complex [nsrc][nrec][ncomp][nfreq] weighted residual
  *                 W^2 (d - E) (eq. phid); for a general loss L(E) pass
  *                 -dL/dE (real and imaginary partial derivatives as re, im)
@@ -271,7 +281,7 @@ fwd_status fwd_basis_build(fwd_plan *plan, double gamma_rel, double gamma_abs,
  * weights are w / (dual volume of the H node).  Errors: STATE (no model /
  * no basis), HIP, NONFINITE. */
 fwd_status fwd_adjoint(fwd_plan *plan, void *ws_dev, size_t ws_bytes,
-                       const void *vol_fwd_dev, const double *resid_dev,
+                       const void *vol_fwd_dev, size_t vol_bytes, const double *resid_dev,
                        double *grad_dev, int accumulate, double *E_adj_dev,
                        void *stream);
 

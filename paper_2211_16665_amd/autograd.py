@@ -8,9 +8,8 @@ backward returns d loss / d log_rho (Section 3.5 chain rule) by one of two
 adjoints:
   method="basis" (default)  one adjoint simulation driven by the
       basis-function adjoint sources (Section 3.3); the forward keeps the
-      volume transform of E as the frequency-domain checkpoint the gradient
-      needs and, with ``snapshot_every`` > 0, device snapshots of the full
-      time-domain state every that many steps;
+      volume transform of E, the frequency-domain checkpoint that is all the
+      gradient needs (``snapshot_every`` is not used);
   method="time"  the time-domain adjoint of the Appendix on the stepped
       system (exact, also inside the CPML): the backward reruns the forward
       with checkpoints every ``snapshot_every`` steps (200 if 0) and steps the
@@ -49,33 +48,13 @@ class FictitiousForward(torch.autograd.Function):
         ctx.in_device = log_rho.device
         if method == "time":
             ctx.vol = None
-            ctx.snapshots = []
             return plan.forward()
         if method != "basis":
             raise ValueError(f"unknown adjoint method {method!r}")
         if not plan.info.have_basis:
             plan.basis_build(gamma_rel=gamma_rel)
-        vol = plan.volume_buffer()
-        snaps = []
-        if snapshot_every and snapshot_every > 0:
-            nt = plan.info.nt
-            plan.run_begin(vol)
-            done = 0
-            while done < nt:
-                m = min(snapshot_every, nt - done)
-                plan.run_steps(m, vol)
-                done += m
-                if done < nt:
-                    snap = torch.empty(plan.checkpoint_size(False), dtype=torch.uint8,
-                                       device="cuda")
-                    plan.checkpoint_save(snap)
-                    snaps.append((done, snap))
-            plan.run_flush(vol)              # the incomplete last transform block
-            E = plan.run_receivers()
-        else:
-            E, vol = plan.forward(vol=vol, want_volume=True)
+        E, vol = plan.forward(vol=plan.volume_buffer(), want_volume=True)
         ctx.vol = vol
-        ctx.snapshots = snaps
         return E
 
     @staticmethod

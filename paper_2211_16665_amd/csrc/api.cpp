@@ -48,6 +48,14 @@ static void need_aligned(const void *ptr, const char *what) {
     fail(FWD_ERR_INVALID_ARG, std::string(what) + " must be 256-byte aligned");
 }
 
+// A buffer shorter than what the call reads or writes is refused before
+// any device work.
+static void need_bytes(size_t have, size_t need, const char *what) {
+  if (have < need)
+    fail(FWD_ERR_INVALID_ARG, std::string(what) + " of " + std::to_string(have) +
+                                  " bytes, the call needs " + std::to_string(need));
+}
+
 extern "C" {
 
 const char *fwd_last_error(void) { return g_err.c_str(); }
@@ -176,31 +184,42 @@ fwd_status fwd_run_begin(fwd_plan *h, void *ws, size_t ws_bytes, void *vol, size
   });
 }
 
-fwd_status fwd_run_steps(fwd_plan *h, void *ws, void *vol, int nsteps, void *stream) {
+fwd_status fwd_run_steps(fwd_plan *h, void *ws, size_t ws_bytes, void *vol, size_t vol_bytes,
+                         int nsteps, void *stream) {
   return guard([&] {
     Plan &p = P(h);
     if (!p.have_model) fail(FWD_ERR_STATE, "no model set");
     if (!ws) fail(FWD_ERR_INVALID_ARG, "workspace is required");
     need_aligned(ws, "workspace");
     need_aligned(vol, "volume buffer");
+    need_bytes(ws_bytes, p.workspace_bytes(FWD_MODE_FORWARD), "workspace");
+    if (vol) need_bytes(vol_bytes, p.volume_bytes(), "volume buffer");
     dev_run_steps(p, ws, vol, nsteps, stream);
   });
 }
 
-fwd_status fwd_run_receivers(fwd_plan *h, void *ws, double *E_rec, void *stream) {
+fwd_status fwd_run_receivers(fwd_plan *h, void *ws, size_t ws_bytes, double *E_rec,
+                             void *stream) {
   return guard([&] {
     Plan &p = P(h);
     if (!p.have_model) fail(FWD_ERR_STATE, "no model set");
     if (!ws || !E_rec) fail(FWD_ERR_INVALID_ARG, "workspace and E_rec are required");
+    need_aligned(ws, "workspace");
+    need_bytes(ws_bytes, p.workspace_bytes(FWD_MODE_FORWARD), "workspace");
     dev_run_receivers(p, ws, E_rec, stream);
   });
 }
 
-fwd_status fwd_run_flush(fwd_plan *h, void *ws, void *vol, void *stream) {
+fwd_status fwd_run_flush(fwd_plan *h, void *ws, size_t ws_bytes, void *vol, size_t vol_bytes,
+                         void *stream) {
   return guard([&] {
     Plan &p = P(h);
     if (!p.have_model) fail(FWD_ERR_STATE, "no model set");
     if (!ws) fail(FWD_ERR_INVALID_ARG, "workspace is required");
+    need_aligned(ws, "workspace");
+    need_aligned(vol, "volume buffer");
+    need_bytes(ws_bytes, p.workspace_bytes(FWD_MODE_FORWARD), "workspace");
+    if (vol) need_bytes(vol_bytes, p.volume_bytes(), "volume buffer");
     if (vol) dev_run_flush(p, ws, vol, stream);
   });
 }
@@ -214,35 +233,47 @@ fwd_status fwd_checkpoint_size(const fwd_plan *h, int with_volume, size_t *bytes
   });
 }
 
-fwd_status fwd_checkpoint_save(fwd_plan *h, const void *ws, const void *vol, void *snap,
-                               void *stream) {
+fwd_status fwd_checkpoint_save(fwd_plan *h, const void *ws, size_t ws_bytes, const void *vol,
+                               size_t vol_bytes, void *snap, size_t snap_bytes, void *stream) {
   return guard([&] {
     Plan &p = P(h);
     if (!p.have_model) fail(FWD_ERR_STATE, "no model set");
     if (!ws || !snap) fail(FWD_ERR_INVALID_ARG, "workspace and snapshot are required");
     need_aligned(ws, "workspace");
+    need_aligned(vol, "volume buffer");
     need_aligned(snap, "snapshot");
+    need_bytes(ws_bytes, p.state_bytes(), "workspace");
+    if (vol) need_bytes(vol_bytes, p.volume_bytes(), "volume buffer");
+    need_bytes(snap_bytes, p.state_bytes() + (vol ? p.volume_bytes() : 0), "snapshot");
     dev_checkpoint(p, ws, vol, snap, 1, stream);
   });
 }
 
-fwd_status fwd_checkpoint_restore(fwd_plan *h, void *ws, void *vol, const void *snap,
+fwd_status fwd_checkpoint_restore(fwd_plan *h, void *ws, size_t ws_bytes, void *vol,
+                                  size_t vol_bytes, const void *snap, size_t snap_bytes,
                                   void *stream) {
   return guard([&] {
     Plan &p = P(h);
     if (!p.have_model) fail(FWD_ERR_STATE, "no model set");
     if (!ws || !snap) fail(FWD_ERR_INVALID_ARG, "workspace and snapshot are required");
     need_aligned(ws, "workspace");
+    need_aligned(vol, "volume buffer");
     need_aligned(snap, "snapshot");
+    need_bytes(ws_bytes, p.state_bytes(), "workspace");
+    if (vol) need_bytes(vol_bytes, p.volume_bytes(), "volume buffer");
+    need_bytes(snap_bytes, p.state_bytes() + (vol ? p.volume_bytes() : 0), "snapshot");
     dev_checkpoint(p, ws, vol, const_cast<void *>(snap), 0, stream);
   });
 }
 
-fwd_status fwd_volume_export(fwd_plan *h, const void *vol, double *out, void *stream) {
+fwd_status fwd_volume_export(fwd_plan *h, const void *vol, size_t vol_bytes, double *out,
+                             void *stream) {
   return guard([&] {
     Plan &p = P(h);
     if (!p.have_model) fail(FWD_ERR_STATE, "no model set");
     if (!vol || !out) fail(FWD_ERR_INVALID_ARG, "volume and output are required");
+    need_aligned(vol, "volume buffer");
+    need_bytes(vol_bytes, p.volume_bytes(), "volume buffer");
     dev_volume_export(p, vol, out, stream);
   });
 }
@@ -253,14 +284,15 @@ fwd_status fwd_basis_build(fwd_plan *h, double gamma_rel, double gamma_abs, int 
 }
 
 fwd_status fwd_adjoint(fwd_plan *h, void *ws, size_t ws_bytes, const void *vol,
-                       const double *resid, double *grad, int accumulate, double *E_adj,
-                       void *stream) {
+                       size_t vol_bytes, const double *resid, double *grad, int accumulate,
+                       double *E_adj, void *stream) {
   return guard([&] {
     Plan &p = P(h);
     if (!p.have_model) fail(FWD_ERR_STATE, "no model set");
     if (!ws || !resid || !grad) fail(FWD_ERR_INVALID_ARG, "workspace, residual and gradient are required");
     need_aligned(ws, "workspace");
     need_aligned(vol, "volume buffer");
+    if (vol) need_bytes(vol_bytes, p.volume_bytes(), "volume buffer");
     dev_adjoint(p, ws, ws_bytes, vol, resid, grad, accumulate, E_adj, stream);
   });
 }

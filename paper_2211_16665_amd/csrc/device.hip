@@ -1397,12 +1397,14 @@ __device__ __forceinline__ void transform_node(const StepArgs<T> &A, int64_t q, 
     }
   } else {
     // per frequency Re(S V), S formed from the samples and Q while the
-    // forward transform V is loading
+    // forward transform V is loading; two frequencies at a time, both
+    // V loads issued before either sum (the same order of additions into
+    // re as one frequency at a time)
     double re = 0.0;
-    for (int kf = 0; kf < nf; ++kf) {
-      const double2 v = Ac::value(Ac::load(A.vol, base + (int64_t)kf * F3));
+    auto block_s = [&](int kf, double &sx, double &sy) {
       const double2 *Qt = s_tw + kf * KB;
-      double sx = 0.0, sy = 0.0;
+      sx = 0.0;
+      sy = 0.0;
 #pragma unroll
       for (int t = 0; t < KB; ++t) {
         if (FLUSH && t >= cnt) break;
@@ -1410,6 +1412,21 @@ __device__ __forceinline__ void transform_node(const StepArgs<T> &A, int64_t q, 
         sx = fma((double)val[t], qt.x, sx);
         sy = fma((double)val[t], qt.y, sy);
       }
+    };
+    int kf = 0;
+    for (; kf + 1 < nf; kf += 2) {
+      const double2 v0 = Ac::value(Ac::load(A.vol, base + (int64_t)kf * F3));
+      const double2 v1 = Ac::value(Ac::load(A.vol, base + (int64_t)(kf + 1) * F3));
+      double sx0, sy0, sx1, sy1;
+      block_s(kf, sx0, sy0);
+      block_s(kf + 1, sx1, sy1);
+      re = fma(sx0, v0.x, fma(-sy0, v0.y, re));
+      re = fma(sx1, v1.x, fma(-sy1, v1.y, re));
+    }
+    if (kf < nf) {
+      const double2 v = Ac::value(Ac::load(A.vol, base + (int64_t)kf * F3));
+      double sx, sy;
+      block_s(kf, sx, sy);
       re = fma(sx, v.x, fma(-sy, v.y, re));
     }
     double *g = A.gedge + ((int64_t)s * 3 + c) * F + q;

@@ -94,17 +94,19 @@ SIGNATURES = {
     "fwd_forward": (c_int, [c_void_p, c_void_p, c_size_t, c_void_p, c_size_t, c_void_p, c_void_p]),
     "fwd_forward_static": (c_int, [c_void_p, c_void_p, c_size_t, c_void_p, c_void_p]),
     "fwd_run_begin": (c_int, [c_void_p, c_void_p, c_size_t, c_void_p, c_size_t, c_void_p]),
-    "fwd_run_steps": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_void_p]),
-    "fwd_run_receivers": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
-    "fwd_run_flush": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
+    "fwd_run_steps": (c_int, [c_void_p, c_void_p, c_size_t, c_void_p, c_size_t, c_int, c_void_p]),
+    "fwd_run_receivers": (c_int, [c_void_p, c_void_p, c_size_t, c_void_p, c_void_p]),
+    "fwd_run_flush": (c_int, [c_void_p, c_void_p, c_size_t, c_void_p, c_size_t, c_void_p]),
     "fwd_checkpoint_size": (c_int, [c_void_p, c_int, POINTER(c_size_t)]),
-    "fwd_checkpoint_save": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
-    "fwd_checkpoint_restore": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
-    "fwd_volume_export": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
+    "fwd_checkpoint_save": (c_int, [c_void_p, c_void_p, c_size_t, c_void_p, c_size_t, c_void_p,
+                                    c_size_t, c_void_p]),
+    "fwd_checkpoint_restore": (c_int, [c_void_p, c_void_p, c_size_t, c_void_p, c_size_t,
+                                       c_void_p, c_size_t, c_void_p]),
+    "fwd_volume_export": (c_int, [c_void_p, c_void_p, c_size_t, c_void_p, c_void_p]),
     "fwd_basis_build": (c_int, [c_void_p, c_double, c_double, c_int, c_double,
                                 POINTER(c_double), POINTER(c_int)]),
-    "fwd_adjoint": (c_int, [c_void_p, c_void_p, c_size_t, c_void_p, c_void_p, c_void_p, c_int,
-                            c_void_p, c_void_p]),
+    "fwd_adjoint": (c_int, [c_void_p, c_void_p, c_size_t, c_void_p, c_size_t, c_void_p, c_void_p,
+                            c_int, c_void_p, c_void_p]),
     "fwd_adjoint_td_size": (c_int, [c_void_p, c_int, POINTER(c_size_t)]),
     "fwd_adjoint_td": (c_int, [c_void_p, c_void_p, c_size_t, c_void_p, c_size_t, c_int, c_void_p,
                                c_void_p, c_int, c_void_p]),
@@ -150,6 +152,11 @@ def _dptr(a: np.ndarray):
 def _ptr(t):
     """Device pointer of a torch tensor (None -> NULL)."""
     return None if t is None else c_void_p(t.data_ptr())
+
+
+def _nbytes(t):
+    """Byte count of a torch tensor's storage view (0 for None)."""
+    return 0 if t is None else t.numel() * t.element_size()
 
 
 def _stream(stream=None):
@@ -348,18 +355,20 @@ class Plan:
 
     def run_steps(self, nsteps, vol=None, stream=None):
         ws = self.workspace(FWD_MODE_FORWARD)
-        check(self.lib.fwd_run_steps(self.handle, _ptr(ws), _ptr(vol), int(nsteps),
-                                     _stream(stream)))
+        check(self.lib.fwd_run_steps(self.handle, _ptr(ws), ws.numel(), _ptr(vol), _nbytes(vol),
+                                     int(nsteps), _stream(stream)))
 
     def run_receivers(self, stream=None):
         ws = self.workspace(FWD_MODE_FORWARD)
         E = self.rec_buffer()
-        check(self.lib.fwd_run_receivers(self.handle, _ptr(ws), _ptr(E), _stream(stream)))
+        check(self.lib.fwd_run_receivers(self.handle, _ptr(ws), ws.numel(), _ptr(E),
+                                         _stream(stream)))
         return E
 
     def run_flush(self, vol, stream=None):
         ws = self.workspace(FWD_MODE_FORWARD)
-        check(self.lib.fwd_run_flush(self.handle, _ptr(ws), _ptr(vol), _stream(stream)))
+        check(self.lib.fwd_run_flush(self.handle, _ptr(ws), ws.numel(), _ptr(vol), _nbytes(vol),
+                                     _stream(stream)))
 
     def checkpoint_size(self, with_volume=False) -> int:
         n = c_size_t()
@@ -368,12 +377,14 @@ class Plan:
 
     def checkpoint_save(self, snap, vol=None, stream=None):
         ws = self.workspace(FWD_MODE_FORWARD)
-        check(self.lib.fwd_checkpoint_save(self.handle, _ptr(ws), _ptr(vol), _ptr(snap),
+        check(self.lib.fwd_checkpoint_save(self.handle, _ptr(ws), ws.numel(), _ptr(vol),
+                                           _nbytes(vol), _ptr(snap), _nbytes(snap),
                                            _stream(stream)))
 
     def checkpoint_restore(self, snap, vol=None, stream=None):
         ws = self.workspace(FWD_MODE_FORWARD)
-        check(self.lib.fwd_checkpoint_restore(self.handle, _ptr(ws), _ptr(vol), _ptr(snap),
+        check(self.lib.fwd_checkpoint_restore(self.handle, _ptr(ws), ws.numel(), _ptr(vol),
+                                              _nbytes(vol), _ptr(snap), _nbytes(snap),
                                               _stream(stream)))
 
     def volume_export(self, vol, stream=None):
@@ -381,7 +392,8 @@ class Plan:
         nz, ny, nx = self.shape
         out = torch.empty((self.ns, self.nf, 3, nz + 1, ny + 1, nx + 1), dtype=torch.complex128,
                           device="cuda")
-        check(self.lib.fwd_volume_export(self.handle, _ptr(vol), _ptr(out), _stream(stream)))
+        check(self.lib.fwd_volume_export(self.handle, _ptr(vol), _nbytes(vol), _ptr(out),
+                                         _stream(stream)))
         return out
 
     def adjoint(self, vol, resid, grad=None, accumulate=False, want_adjoint_rec=False,
@@ -396,8 +408,9 @@ class Plan:
         elif tuple(grad.shape) != tuple(self.grad_shape) or grad.dtype != torch.float64:
             raise ValueError(f"grad must be float64 of shape {self.grad_shape}")
         Ea = self.rec_buffer() if want_adjoint_rec else None
-        check(self.lib.fwd_adjoint(self.handle, _ptr(ws), ws.numel(), _ptr(vol), _ptr(resid),
-                                   _ptr(grad), int(accumulate), _ptr(Ea), _stream(stream)))
+        check(self.lib.fwd_adjoint(self.handle, _ptr(ws), ws.numel(), _ptr(vol), _nbytes(vol),
+                                   _ptr(resid), _ptr(grad), int(accumulate), _ptr(Ea),
+                                   _stream(stream)))
         return (grad, Ea) if want_adjoint_rec else grad
 
     def adjoint_td_size(self, segment=200):

@@ -8,10 +8,11 @@ transform, so accumulator checks compare exported volumes.
     every receiver and frequency; over the whole run, the volume transform
     with compensated-FP32 and FP32 accumulators against FP64 accumulators
     (same FP32 fields);
-  * three blocks (128x128x96): the FP64 gradient from FictitiousForward
-    (with forward snapshots every 200 steps) against central finite
-    differences on 10 random interior cells, and the FP32 gradient against
-    the FP64 one;
+  * three blocks (128x128x96): the FP64 basis-function gradient from
+    FictitiousForward (its checkpoint is the forward volume transform)
+    against central finite differences on 10 random interior cells, and the
+    FP32 gradient against the FP64 one; the time-domain gradient (forward
+    checkpoints every 200 steps) against central differences too;
   * batched (200x200x100, 16 sources): FP32 against FP64 per frequency on a
     window, batch against a single-source run;
   * large (400x400x200, ~32M cells, 8 frequencies): the volume transform with
@@ -115,11 +116,11 @@ def _blocks_problem():
 def test_blocks_gradient_finite_differences():
     from paper_2211_16665_amd.autograd import FictitiousForward, misfit
     w0, d = _blocks_problem()
-    say(f"three blocks: fp64 gradient with snapshots every 200 steps, nt={w0.nt}")
+    say(f"three blocks: fp64 basis-function gradient, nt={w0.nt}")
     p = fw.Plan.from_workload(w0, field_dtype="f64")
     m0 = np.log(w0.rho)
     m = torch.tensor(m0, dtype=torch.float64, device="cuda", requires_grad=True)
-    L = misfit(FictitiousForward.apply(m, p, 200), d)
+    L = misfit(FictitiousForward.apply(m, p), d)
     L.backward()
     g = m.grad.cpu().numpy()
     rng = np.random.default_rng(1)

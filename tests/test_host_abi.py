@@ -143,8 +143,33 @@ def test_errors_before_any_device_call(lib):
     out = ctypes.c_void_p(0x20000)
     st = p.lib.fwd_forward(p.handle, bogus, 1 << 20, None, 0, out, None)
     assert st == 1 and b"256-byte aligned" in p.lib.fwd_last_error()
-    st = p.lib.fwd_run_steps(p.handle, ctypes.c_void_p(0x30000), bogus, 1, None)
+    st = p.lib.fwd_run_steps(p.handle, ctypes.c_void_p(0x30000), 1 << 40, bogus, 1 << 40, 1, None)
     assert st == 1 and b"volume buffer must be 256-byte aligned" in p.lib.fwd_last_error()
+
+
+def test_short_buffers_are_refused_on_the_host(lib):
+    """Every call that takes device buffers checks their byte counts before
+    any device work (the pointers are aligned and never dereferenced)."""
+    w = tiny(seed=2)
+    p = _plan(w)
+    p.set_model(w.rho)
+    ws_f, ws_a, vb = p.workspace_size(fw.FWD_MODE_FORWARD), p.workspace_size(fw.FWD_MODE_ADJOINT), p.volume_size()
+    snap = p.checkpoint_size(True)
+    a, b, c = (ctypes.c_void_p(x) for x in (0x100000, 0x200000, 0x300000))
+    L = p.lib
+    calls = [
+        lambda: L.fwd_run_steps(p.handle, a, ws_f - 1, None, 0, 1, None),
+        lambda: L.fwd_run_steps(p.handle, a, ws_f, b, vb - 256, 1, None),
+        lambda: L.fwd_run_receivers(p.handle, a, ws_f - 1, c, None),
+        lambda: L.fwd_run_flush(p.handle, a, ws_f, b, vb - 1, None),
+        lambda: L.fwd_checkpoint_save(p.handle, a, ws_f, b, vb, c, snap - 1, None),
+        lambda: L.fwd_checkpoint_restore(p.handle, a, ws_f - ws_f // 2, b, vb, c, snap, None),
+        lambda: L.fwd_volume_export(p.handle, b, vb - 8, c, None),
+        lambda: L.fwd_adjoint(p.handle, a, ws_a, b, vb - 1, c, c, 0, None, None),
+    ]
+    for call in calls:
+        assert call() == 1
+        assert b"bytes, the call needs" in L.fwd_last_error(), L.fwd_last_error()
 
 
 @pytest.mark.parametrize("make", [c1_wholespace, c2_marine1d, c3_blocks,
