@@ -922,9 +922,11 @@ def marine_gradient(args):
 def profile_mode(args):
     """A short run for hardware-counter collection: one elementwise kernel of
     a known size (1 GiB read + 1 GiB written, the calibration of the byte
-    counters; larger than the 256 MB Infinity Cache), then a forward and an adjoint run of ``profile_steps`` steps
-    on the full grid of the workload (for the large workload: one group of
-    ``--group`` sources), with eager launches."""
+    counters; larger than the 256 MB Infinity Cache), two more calibration
+    points (a 256 MiB elementwise kernel, a 1 GiB reduction), then a forward
+    and an adjoint run of ``profile_steps`` steps on the full grid of the
+    workload (for the large workload: one group of ``--group`` sources), with
+    eager launches."""
     import torch
     from paper_2211_16665_amd import fwdem as fw
     from workloads import c2_marine1d, c4_batched, c5_large
@@ -934,7 +936,14 @@ def profile_mode(args):
     torch.cuda.synchronize()
     torch.mul(a, 2.0, out=b)          # one elementwise kernel: 1 GiB read, 1 GiB written
     torch.cuda.synchronize()
-    del a, b
+    # two more calibration points: a 256 MiB elementwise kernel, and a
+    # reduction that reads 1 GiB and writes almost nothing
+    q = n // 4
+    torch.mul(a[:q], 3.0, out=b[:q])
+    torch.cuda.synchronize()
+    r = torch.sum(a)
+    torch.cuda.synchronize()
+    del a, b, r
     if args.profile_workload == "large":
         w = c5_large()
         g = args.group or 8

@@ -2312,6 +2312,7 @@ struct WS {
   int *flushed;         // last sample already added by a flush
   unsigned *bar;        // persistent schedule: barrier counter and generation
   int *abort;           // persistent schedule: a barrier wait was abandoned
+  int *bad;             // a non-finite value in the final fields or the gradient
   void *hist;
   double *gedge;
 };
@@ -2331,6 +2332,7 @@ static WS carve(const Plan &p, void *ws) {
   w.flushed = w.step + 2;
   w.bar = reinterpret_cast<unsigned *>(w.step + 4);
   w.abort = w.step + 6;
+  w.bad = w.step + 7;
   b += 256;
   w.hist = b;
   b += a256((size_t)p.ns * p.hist_elems_per_source() * p.tsize());
@@ -2992,13 +2994,54 @@ static void check_sizes(Plan &p, size_t ws_bytes, int mode, void *vol, size_t vo
   if (vol && vol_bytes < p.volume_bytes()) fail(FWD_ERR_INVALID_ARG, "volume buffer too small");
 }
 
-static void check_finite(const double2 *dptr, size_t n, hipStream_t st) {
+// Sets *flag when any of n values at v (16-byte aligned) is Inf or NaN:
+// 16-byte loads, then the last n % W values one by one.
+template <typename T>
+__global__ void k_nonfinite_v(const T *v, size_t n, int *flag) {
+  using V = Vec<T, 16 / sizeof(T)>;
+  constexpr int W = 16 / sizeof(T);
+  const size_t nv = n / W, stride = (size_t)gridDim.x * blockDim.x;
+  const size_t t0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool bad = false;
+  for (size_t i = t0; i < nv; i += stride) {
+    const V x = *reinterpret_cast<const V *>(v + i * W);
+#pragma unroll
+    for (int e = 0; e < W; ++e) bad |= !isfinite(x.v[e]);
+  }
+  if (t0 < n - nv * W) bad |= !isfinite(v[nv * W + t0]);
+  if (bad) flag[0] = 1;
+}
+
+template <typename T>
+static void flag_nonfinite(const T *v, size_t n, int *flag, hipStream_t st) {
+  constexpr int W = 16 / sizeof(T);
+  const size_t blocks = std::min<size_t>((n / W + 255) / 256 + 1, 4096);
+  if (n == 0) return;
+  hipLaunchKernelGGL((k_nonfinite_v<T>), dim3((unsigned)blocks), dim3(256), 0, st, v, n, flag);
+}
+
+// The fields of the last completed step (the half step n wrote, n = host
+// step count - 1) to the workspace's flag: a blow-up anywhere in the grid
+// (inside a CPML layer, far from every receiver) shows up there.
+static void flag_final_fields(Plan &p, const WS &w, hipStream_t st) {
+  const size_t half = (size_t)p.ns * 6 * p.field_elems();
+  const int h = p.host_step & 1;
+  if (p.dtype == FWD_F64)
+    flag_nonfinite(static_cast<const double *>(w.fields) + h * half, half, w.bad, st);
+  else
+    flag_nonfinite(static_cast<const float *>(w.fields) + h * half, half, w.bad, st);
+}
+
+// Receiver output (host copy) and the device flag, one synchronisation.
+static void check_finite(const double2 *dptr, size_t n, const int *flag_dev, hipStream_t st) {
   std::vector<double2> h(n);
+  int bad = 0;
   HIP_CHECK(hipMemcpyAsync(h.data(), dptr, n * sizeof(double2), hipMemcpyDeviceToHost, st));
+  if (flag_dev) HIP_CHECK(hipMemcpyAsync(&bad, flag_dev, sizeof bad, hipMemcpyDeviceToHost, st));
   HIP_CHECK(hipStreamSynchronize(st));
   for (auto &v : h)
-    if (!std::isfinite(v.x) || !std::isfinite(v.y))
-      fail(FWD_ERR_NONFINITE, "non-finite field: unstable run (dt above the CFL bound?)");
+    if (!std::isfinite(v.x) || !std::isfinite(v.y)) bad = 1;
+  if (bad) fail(FWD_ERR_NONFINITE, "non-finite field: unstable run (dt above the CFL bound?)");
 }
 
 // ---------------------------------------------------------------------------
@@ -3061,7 +3104,10 @@ void dev_forward(Plan &p, void *ws, size_t ws_bytes, void *vol, size_t vol_bytes
   p.last_steps = p.nt;
   collect_kernel_stats(d);
   check_abort(p, carve(p, ws), st);
-  check_finite(reinterpret_cast<double2 *>(E_rec), (size_t)p.ns * p.nr * p.ncomp * p.nf(), st);
+  const WS w = carve(p, ws);
+  flag_final_fields(p, w, st);
+  check_finite(reinterpret_cast<double2 *>(E_rec), (size_t)p.ns * p.nr * p.ncomp * p.nf(), w.bad,
+               st);
 }
 
 // ---------------------------------------------------------------------------
@@ -3088,6 +3134,10 @@ static void *static_scratch(int dev) {
     g_scratch_ptr[dev] = ptr;
   }
   return g_scratch_ptr[dev];
+}
+
+__global__ void k_or_flag(int *flag, const int *other) {
+  if (threadIdx.x == 0 && blockIdx.x == 0 && other[0]) flag[0] = 1;
 }
 
 __global__ void k_nonfinite(const double *v, size_t n, int *flag) {
@@ -3125,6 +3175,8 @@ void dev_forward_static(Plan &p, void *vol, size_t vol_bytes, double *E_rec, voi
   const size_t n = 2 * (size_t)p.ns * p.nr * p.ncomp * p.nf();
   hipLaunchKernelGGL(k_nonfinite, dim3((unsigned)std::min<size_t>((n + 255) / 256, 1024)),
                      dim3(256), 0, st, E_rec, n, flag);
+  flag_final_fields(p, w, st);                 // into w.bad, cleared by zero_state
+  hipLaunchKernelGGL(k_or_flag, dim3(1), dim3(64), 0, st, flag, (const int *)w.bad);
   HIP_CHECK(hipGetLastError());
   int bad = 0;
   HIP_CHECK(hipMemcpyAsync(&bad, flag, sizeof bad, hipMemcpyDeviceToHost, st));
@@ -3228,7 +3280,9 @@ void dev_adjoint(Plan &p, void *ws, size_t ws_bytes, const void *vol, const doub
   p.last_steps = p.nt;
   collect_kernel_stats(d);
   check_abort(p, w, st);
-  check_finite(dst, (size_t)n, st);
+  flag_final_fields(p, w, st);
+  flag_nonfinite(grad, (size_t)p.nx * p.ny * p.nz * (p.vti_grad ? 2 : 1), w.bad, st);
+  check_finite(dst, (size_t)n, w.bad, st);
 }
 
 // ---------------------------------------------------------------------------
