@@ -204,8 +204,11 @@ fwd_status fwd_forward(fwd_plan *plan, void *ws_dev, size_t ws_bytes,
 fwd_status fwd_forward_static(fwd_plan *plan, void *vol_dev, size_t vol_bytes, double *E_rec_dev,
                               void *stream);
 
-/* Partial runs for checkpointing.  fwd_run_begin zeroes the state in ws
- * (and vol, if given); fwd_run_steps advances it by nsteps (the step index
+/* Partial runs for checkpointing.  fwd_run_begin zeroes the state in ws;
+ * vol is not cleared: the run's first transform block writes all of it (a
+ * run flushed before its first sample clears it at the flush), so its
+ * contents are defined once a block has closed or fwd_run_flush has
+ * returned.  fwd_run_steps advances the state by nsteps (the step index
  * lives in the workspace, so runs may be split anywhere); fwd_run_receivers
  * writes the receiver output of the steps done so far, normalised as in
  * fwd_forward.  Only FWD_MODE_FORWARD runs can be split.  Every call takes

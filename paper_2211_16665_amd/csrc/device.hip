@@ -543,6 +543,7 @@ struct Acc;
 template <>
 struct Acc<ACC_F64> {
   using S = double2;
+  static __device__ __forceinline__ S zero() { return make_double2(0.0, 0.0); }
   static __device__ __forceinline__ S load(const void *b, int64_t i) {
     return reinterpret_cast<const double2 *>(b)[i];
   }
@@ -559,6 +560,7 @@ struct Acc<ACC_F64> {
 template <>
 struct Acc<ACC_KAHAN> {
   using S = float4;
+  static __device__ __forceinline__ S zero() { return make_float4(0.f, 0.f, 0.f, 0.f); }
   static __device__ __forceinline__ S load(const void *b, int64_t i) {
     return reinterpret_cast<const float4 *>(b)[i];
   }
@@ -582,6 +584,7 @@ struct Acc<ACC_KAHAN> {
 template <>
 struct Acc<ACC_F32> {
   using S = float2;
+  static __device__ __forceinline__ S zero() { return make_float2(0.f, 0.f); }
   static __device__ __forceinline__ S load(const void *b, int64_t i) {
     return reinterpret_cast<const float2 *>(b)[i];
   }
@@ -1350,9 +1353,21 @@ __device__ __forceinline__ void transform_node(const StepArgs<T> &A, int64_t q, 
   const bool iin = i < (uint32_t)A.nx, jin = j < (uint32_t)A.ny, kin = k < (uint32_t)A.nz;
   const bool ii = i >= 1 && iin, ji = j >= 1 && jin, ki = k >= 1 && kin;
   const bool on = c == 0 ? iin && ji && ki : (c == 1 ? ii && jin && ki : ii && ji && kin);
-  if (!on) return;
   const int fl = A.flushed[0];
   const int64_t F = A.F, F3 = 3 * A.F;
+  const int64_t base = ((int64_t)s * nf * 3 + c) * F + q;    // + kf * 3 F
+  using Ac = Acc<ACC>;
+  // The run's first block with nothing flushed before it: the forward
+  // accumulators are written, not updated (a run does not clear the volume
+  // buffer first), and nodes off the component's lattice receive zeros.
+  // Adding to zero gives the same bits, so this is the cleared buffer's
+  // result without the clearing pass or the first block's loads.
+  const bool fresh = !ADJ && first == (1 << dl) && fl == 0;
+  if (!on) {
+    if (fresh)
+      for (int kf = 0; kf < nf; ++kf) Ac::store(A.vol, base + (int64_t)kf * F3, Ac::zero());
+    return;
+  }
   const T *h = A.hist + (int64_t)s * A.hist_src + (int64_t)c * F + q;
   const T *f = A.fields + ((m_last & 1) ? A.fbuf : 0) + (int64_t)s * A.F6 + (int64_t)c * F + q;
   // the samples in the field type; those outside (fl, nt] are zeroed with a
@@ -1366,8 +1381,6 @@ __device__ __forceinline__ void transform_node(const StepArgs<T> &A, int64_t q, 
     const int idx = first + (t << dl);
     val[t] = idx <= fl || idx > nt ? T(0) : v;
   }
-  const int64_t base = ((int64_t)s * nf * 3 + c) * F + q;    // + kf * 3 F
-  using Ac = Acc<ACC>;
   if constexpr (!ADJ) {
     // two frequencies at a time: both accumulators are loaded before either
     // store (loads and stores share one in-order completion counter)
@@ -1385,14 +1398,15 @@ __device__ __forceinline__ void transform_node(const StepArgs<T> &A, int64_t q, 
     };
     int kf = 0;
     for (; kf + 1 < nf; kf += 2) {
-      const typename Ac::S a0 = Ac::load(A.vol, base + (int64_t)kf * F3);
-      const typename Ac::S a1 = Ac::load(A.vol, base + (int64_t)(kf + 1) * F3);
+      const typename Ac::S a0 = fresh ? Ac::zero() : Ac::load(A.vol, base + (int64_t)kf * F3);
+      const typename Ac::S a1 =
+          fresh ? Ac::zero() : Ac::load(A.vol, base + (int64_t)(kf + 1) * F3);
       const double2 s0 = block_sum(kf), s1 = block_sum(kf + 1);
       Ac::store(A.vol, base + (int64_t)kf * F3, Ac::add(a0, s0));
       Ac::store(A.vol, base + (int64_t)(kf + 1) * F3, Ac::add(a1, s1));
     }
     if (kf < nf) {
-      const typename Ac::S a = Ac::load(A.vol, base + (int64_t)kf * F3);
+      const typename Ac::S a = fresh ? Ac::zero() : Ac::load(A.vol, base + (int64_t)kf * F3);
       Ac::store(A.vol, base + (int64_t)kf * F3, Ac::add(a, block_sum(kf)));
     }
   } else {
@@ -2738,6 +2752,8 @@ template <typename T>
 static void flush_t(Plan &p, Dev &d, const WS &w, void *vol, bool adj, hipStream_t st) {
   // decimated samples taken so far (every step's sample when D = 1)
   const int taken = p.host_step / (adj ? 1 : p.dec);
+  // no sample, so no block transform has written the volume buffer yet
+  if (!adj && vol && taken == 0) zero_bytes(vol, p.volume_bytes(), st);
   if (p.kb == 1 || !vol || taken % p.kb == 0) return;
   build_lists(p, d);
   hipLaunchKernelGGL(k_equalize, dim3(1), dim3(64), 0, st, w.step);
@@ -2978,12 +2994,14 @@ static void collect_kernel_stats(Dev &d) {
 // history is not cleared: every slot a block transform reads was written
 // earlier in the same run (slots of samples past the run are masked by a
 // select), and on the large grids it is the largest part of the workspace.
-static void zero_state(Plan &p, const WS &w, void *ws, void *vol, int mode, hipStream_t st) {
+// Neither is the volume buffer: the run's first block transform writes all
+// of it (and a run that ends before its first sample clears it at the
+// flush).
+static void zero_state(Plan &p, const WS &w, void *ws, int mode, hipStream_t st) {
   p.host_step = 0;
   char *b = static_cast<char *>(ws);
   zero_bytes(b, p.core_state_bytes(), st);
   zero_bytes(b + p.state_bytes(), p.workspace_bytes(mode) - p.state_bytes(), st);
-  if (vol && mode == FWD_MODE_FORWARD) zero_bytes(vol, p.volume_bytes(), st);
   hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, st, w.step, -1);
   hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, st, w.step + 1, -1);
   HIP_CHECK(hipGetLastError());
@@ -3051,7 +3069,7 @@ void dev_run_begin(Plan &p, void *ws, size_t ws_bytes, void *vol, size_t vol_byt
   hipStream_t st = static_cast<hipStream_t>(stream);
   check_sizes(p, ws_bytes, FWD_MODE_FORWARD, vol, vol_bytes);
   ensure_tables(p, st);
-  zero_state(p, carve(p, ws), ws, vol, FWD_MODE_FORWARD, st);
+  zero_state(p, carve(p, ws), ws, FWD_MODE_FORWARD, st);
 }
 
 void dev_run_steps(Plan &p, void *ws, void *vol, int nsteps, void *stream) {
@@ -3166,7 +3184,7 @@ void dev_forward_static(Plan &p, void *vol, size_t vol_bytes, double *E_rec, voi
                         "tiling: run fwd_forward once first");
   Dev &d = *dp;
   const WS w = carve(p, ws);
-  zero_state(p, w, ws, vol, FWD_MODE_FORWARD, st);
+  zero_state(p, w, ws, FWD_MODE_FORWARD, st);
   run_steps_any(p, d, w, vol, false, p.nt, st, true);
   flush_any(p, d, w, vol, false, st);
   dev_run_receivers(p, ws, E_rec, stream);
@@ -3250,7 +3268,7 @@ void dev_adjoint(Plan &p, void *ws, size_t ws_bytes, const void *vol, const doub
   std::vector<double2> as(p.nf(), make_double2(1.0 / adj_scale, 0.0));
   HIP_CHECK(hipMemcpyAsync(d.adj_scale_v, as.data(), as.size() * sizeof(double2),
                            hipMemcpyHostToDevice, st));
-  zero_state(p, w, ws, nullptr, FWD_MODE_ADJOINT, st);
+  zero_state(p, w, ws, FWD_MODE_ADJOINT, st);
   d.kstat_n = 0;
   hipEvent_t e0, e1;
   HIP_CHECK(hipEventCreate(&e0));
@@ -3317,7 +3335,7 @@ static void adjoint_td_t(Plan &p, Dev &d, const WS &w, void *ws, char *scratch, 
   HIP_CHECK(hipMemcpyAsync(coef, C.data(), C.size() * sizeof(double), hipMemcpyHostToDevice, st));
   HIP_CHECK(hipMemcpyAsync(tdw, Wt.data(), Wt.size() * sizeof(double), hipMemcpyHostToDevice, st));
   // forward run, checkpointing the core state at the start of every segment
-  zero_state(p, w, ws, nullptr, FWD_MODE_FORWARD, st);
+  zero_state(p, w, ws, FWD_MODE_FORWARD, st);
   for (int sg = 0; sg < nseg; ++sg) {
     HIP_CHECK(hipMemcpyAsync(ckpt + (size_t)sg * ckb, ws, core, hipMemcpyDeviceToDevice, st));
     run_steps_t<T>(p, d, w, nullptr, false, std::min(L, nt - sg * L), st);
