@@ -68,14 +68,21 @@ def algorithmic_bytes_e(nx, ny, nz, npml, tsize=4, kb=8, hist=True):
     return int(edges * (4 * tsize + keep) + psi * 2 * tsize), edges
 
 
-def algorithmic_bytes_transform(edges, nf, tsize=4, accsize=16, kb=8, adjoint=False):
+def algorithmic_bytes_transform(edges, nf, tsize=4, accsize=16, kb=8, adjoint=False, blocks=None):
     """Algorithmic HBM bytes of one launch of the block transform (once per
     kb steps): per updated edge the block's kb samples (kb-1 from the
     history, the newest from the fields) and the accumulators -- forward,
     read + write of nf complex values (2 nf accsize); adjoint, a read of the
     forward transform (nf accsize) and the FP64 gradient accumulator's read
-    + write (16)."""
-    acc = nf * accsize + 16 if adjoint else 2 * nf * accsize
+    + write (16).  The first forward block of a run only writes its
+    accumulators (nf accsize): with ``blocks`` (the blocks of a run) the
+    forward figure is the average over the run's launches."""
+    if adjoint:
+        acc = nf * accsize + 16
+    elif blocks:
+        acc = (2 * nf * accsize * (blocks - 1) + nf * accsize) / blocks
+    else:
+        acc = 2 * nf * accsize
     return int(edges * (kb * tsize + acc))
 
 
@@ -329,8 +336,9 @@ def batched_vs_plain(window=200):
     t_tuned = time.perf_counter() - t0
     p.set_option(fw.FWD_OPT_SAMPLE_EVERY, 64)
     p.forward(vol=vol, want_volume=True)
+    kb = int(p.get_option(fw.FWD_OPT_DFT_BLOCK))
     kern = kernel_records([p.kernel_stats()], w.ns, nx, ny, nz, w.npml, len(w.freqs), 4, 16,
-                          int(p.get_option(fw.FWD_OPT_DFT_BLOCK)), "F64")
+                          kb, "F64", max(1, window // kb))
     del vol
     return {"workload": f"c4_batched window: {nx}x{ny}x{nz}, {w.ns} sources, {len(w.freqs)} freqs, "
                         f"{window} forward + {window} adjoint steps",
@@ -511,7 +519,7 @@ def order4_study(w_true, rho0, order2_s, tsize, accsize):
     nz, ny, nx = plan.shape
     kb = int(plan.get_option(fw.FWD_OPT_DFT_BLOCK))
     kern = kernel_records(ks[:1], 1, nx, ny, nz, w_true.npml, len(w_true.freqs), tsize, accsize,
-                          kb, "F64")
+                          kb, "F64", max(1, plan.info.nt // kb))
     nt = plan.info.nt
     out = {"gradient_s": t, "order2_gradient_s": order2_s, "nt": nt, "dt": plan.info.dt,
            "mcell_per_s": 2.0 * nx * ny * nz * nt / t / 1e6,
@@ -629,12 +637,13 @@ def background_model(w):
     return rho0
 
 
-def kernel_records(stats, ns, nx, ny, nz, npml, nf, tsize, accsize, kb, acc_tag):
+def kernel_records(stats, ns, nx, ny, nz, npml, nf, tsize, accsize, kb, acc_tag, blocks):
     """Per kernel of a forward step (H update, E update, block transform):
     the average launch time over the sampled steps of the forward runs in
     ``stats`` (kernel_stats() results), its algorithmic bytes per launch for
-    ``ns`` sources (dt/eps read once for all of them) and the time per step
-    (the block transform runs once in kb steps)."""
+    ``ns`` sources (dt/eps read once for all of them; the transform's
+    averaged over the ``blocks`` blocks of a run) and the time per step (the
+    block transform runs once in kb steps)."""
     ok = [s_ for s_ in stats if s_[1] > 0]
     ms = [float(np.mean([s_[0][k] for s_ in ok])) if ok else float("nan") for k in range(3)]
     samples = sum(s_[1] for s_ in stats)
@@ -649,7 +658,8 @@ def kernel_records(stats, ns, nx, ny, nz, npml, nf, tsize, accsize, kb, acc_tag)
                      "avg_launch_ms": ms[1], "ms_per_step": ms[1]},
         "transform": {"kernel": f"k_transform<{t},{acc_tag},fwd,{kb}>",
                       "bytes_per_launch": ns * algorithmic_bytes_transform(edges, nf, tsize,
-                                                                           accsize, kb),
+                                                                           accsize, kb,
+                                                                           blocks=blocks),
                       "avg_launch_ms": ms[2], "ms_per_step": ms[2] / kb},
     }
     for v in out.values():
@@ -797,8 +807,8 @@ def large_window(args):
     accsize = 8 if acc == "f32" else 16
     kb = tuned["dft_block"]
     nf = len(w.freqs)
-    kern = kernel_records(headline_stats, gmax, nx, ny, nz, w.npml, nf, tsize, accsize, kb, "KAHAN"
-                          if acc == "kahan" else acc.upper())
+    kern = kernel_records(headline_stats, gmax, nx, ny, nz, w.npml, nf, tsize, accsize, kb,
+                          "KAHAN" if acc == "kahan" else acc.upper(), max(1, args.window // kb))
     dom = max(kern, key=lambda k: kern[k]["ms_per_step"])
     mt = measured_traffic(kern[dom]["kernel"], "pmc_large_step_kernels.md",
                           ",".join(str(tuned[k.lower()]) for k in TILING_KEYS))
@@ -899,7 +909,7 @@ def marine_gradient(args):
     accsize = 8 if args.acc == "f32" else 16
     kb = tuned["dft_block"]
     kern = kernel_records(stats, 1, nx, ny, nz, w_true.npml, len(w_true.freqs), tsize, accsize,
-                          kb, "F64")
+                          kb, "F64", max(1, nt // kb))
     dom = max(kern, key=lambda k: kern[k]["ms_per_step"])
     mt = measured_traffic(kern[dom]["kernel"], "pmc_marine1d_e_update.md")
     out = {"workload": "c2_marine1d gradient: 101x101x61 stretched grid, 3 freqs, 1 x-dipole, "

@@ -387,6 +387,10 @@ fwd_status fwd_set_option(fwd_plan *h, int key, double value) {
         if (v < 1 || v > 64) fail(FWD_ERR_INVALID_ARG, "barrier pause in [1, 64]");
         p.barrier_sleep = v;
         break;
+      case FWD_OPT_STREAM_STORES:
+        if (v < -1 || v > 1) fail(FWD_ERR_INVALID_ARG, "stream stores in {-1, 0, 1}");
+        p.stream_stores = v;
+        break;
       case FWD_OPT_ZCHUNK:
         if (v < 1 || v > 64) fail(FWD_ERR_INVALID_ARG, "planes per block in [1, 64]");
         p.kz = v;
@@ -452,6 +456,7 @@ fwd_status fwd_get_option(const fwd_plan *h, int key, double *value) {
       case FWD_OPT_PERSIST_BLOCKS: *value = p.persist_blocks; break;
       case FWD_OPT_DFT_DECIMATE: *value = p.dec; break;
       case FWD_OPT_BARRIER_SLEEP: *value = p.barrier_sleep; break;
+      case FWD_OPT_STREAM_STORES: *value = p.stream_stores; break;
       default: fail(FWD_ERR_INVALID_ARG, "unknown option");
     }
   });

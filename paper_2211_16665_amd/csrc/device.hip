@@ -102,6 +102,7 @@ struct StepArgs {
   int lean;           // interior tiles take the lean paths (npml >= 1)
   int kb;             // samples per transform block
   int dl;             // log2 of the volume transform's decimation (forward runs; 0: every sample)
+  int nts;            // 1: non-temporal stores for the field halves and the history
   FDiv dplane, dpx;   // node decode of the block transform (q -> k, j, i)
   int order;          // tile numbering: 0 x fastest, 1 z fastest
   FDiv dns, dnbx, dnby, dnbz;             // dividers of the block decode (set_grid)
@@ -271,6 +272,39 @@ __device__ __forceinline__ void vstore(T *p, const Vec<T, N> &r) {
   }
 }
 
+// Non-temporal store of a vector: for data that the next touch reads from
+// HBM anyway (a field half read one step later, a history sample read at
+// the block's close).  On the large grids the streaming hint took the H
+// update from 2.22 to 2.10 ms and the E update from 3.12 to 3.00 ms per
+// launch (8 sources, 32 M cells); the same hint on loads made them slower,
+// and on the accumulators of the block transform it gained under 1 %.
+// Where the whole working set stays in the Infinity Cache (the marine grid)
+// it costs 15-20 %, so the update kernels take it as a template parameter
+// chosen per run (StepArgs::nts); a run-time branch between the two store
+// forms is merged by the compiler into one plain store.
+template <typename T, int N>
+__device__ __forceinline__ void vstore_nt(T *p, const Vec<T, N> &r) {
+  if constexpr (N == 1) {
+    __builtin_nontemporal_store(r.v[0], p);
+  } else if constexpr (sizeof(T) == 4) {
+    typedef float f4v __attribute__((ext_vector_type(4)));
+    const f4v x = {r.v[0], r.v[1], r.v[2], r.v[3]};
+    __builtin_nontemporal_store(x, reinterpret_cast<f4v *>(p));
+  } else {
+    typedef double d2v __attribute__((ext_vector_type(2)));
+    const d2v x = {r.v[0], r.v[1]};
+    __builtin_nontemporal_store(x, reinterpret_cast<d2v *>(p));
+  }
+}
+
+template <bool NT, typename T, int N>
+__device__ __forceinline__ void vstore_h(T *p, const Vec<T, N> &r) {
+  if constexpr (NT)
+    vstore_nt(p, r);
+  else
+    vstore(p, r);
+}
+
 template <typename T, int N>
 __device__ __forceinline__ Vec<T, N> vzero() {
   Vec<T, N> r;
@@ -428,7 +462,7 @@ __device__ __forceinline__ bool interior_tile(const StepArgs<T> &A, int bx, int 
 // LEAN: the block's tile is interior (see interior_tile): every lattice mask
 // and bounds test is true and no node is inside a CPML layer, as compile-time
 // constants; the per-node arithmetic is the same helpers' (same bits).
-template <typename T, int VX, bool INJ, bool LEAN>
+template <typename T, int VX, bool INJ, bool LEAN, bool NT = false>
 __device__ __forceinline__ void h_vec(const StepArgs<T> &A, const Half<T> &I, const Half<T> &O,
                                       int i0, int j, int k, int lo, int hi, int s, int n) {
   using V = Vec<T, VX>;
@@ -485,9 +519,9 @@ __device__ __forceinline__ void h_vec(const StepArgs<T> &A, const Half<T> &I, co
     }
   }
   // ---- stores (slots outside a component's lattice keep their zero) ----
-  vstore(O.hx + q, hxv);
-  vstore(O.hy + q, hyv);
-  vstore(O.hz + q, hzv);
+  vstore_h<NT>(O.hx + q, hxv);
+  vstore_h<NT>(O.hy + q, hyv);
+  vstore_h<NT>(O.hz + q, hzv);
   if (pyv && k_in) vstore(O.psY + 0 * sY + iY, ps_hx_y);
   if (pyv) vstore(O.psY + 1 * sY + iY, ps_hz_y);
   if (pzv && j_in) vstore(O.psZ + 0 * sZ + iZ, ps_hx_z);
@@ -495,8 +529,8 @@ __device__ __forceinline__ void h_vec(const StepArgs<T> &A, const Half<T> &I, co
 }
 
 // INJ: adjoint runs with magnetic receivers (the H update adds the magnetic
-// sources of its nodes); otherwise the plain update
-template <typename T, int VX, bool INJ>
+// sources of its nodes); otherwise the plain update.  NT: streaming stores.
+template <typename T, int VX, bool INJ, bool NT>
 __global__ void __launch_bounds__(256) k_update_h(StepArgs<T> A) {
   int bx, by, bz, s;
   const int b = tile_of(A, bx, by, bz, s);
@@ -509,10 +543,11 @@ __global__ void __launch_bounds__(256) k_update_h(StepArgs<T> A) {
   int lo = 0, hi = 0;
   if constexpr (INJ) entry_slice(A, b, n, lo, hi);
   if (interior_tile(A, bx, by, k, blockDim.x * VX))
-    h_vec<T, VX, INJ, true>(A, half_of(A, par, s), half_of(A, par ^ 1, s), i0, j,
-                            __builtin_amdgcn_readfirstlane(k), lo, hi, s, n);
+    h_vec<T, VX, INJ, true, NT>(A, half_of(A, par, s), half_of(A, par ^ 1, s), i0, j,
+                                __builtin_amdgcn_readfirstlane(k), lo, hi, s, n);
   else
-    h_vec<T, VX, INJ, false>(A, half_of(A, par, s), half_of(A, par ^ 1, s), i0, j, k, lo, hi, s, n);
+    h_vec<T, VX, INJ, false, NT>(A, half_of(A, par, s), half_of(A, par ^ 1, s), i0, j, k, lo, hi,
+                                 s, n);
 }
 
 // ---------------------------------------------------------------------------
@@ -548,7 +583,7 @@ struct Acc<ACC_F64> {
     return reinterpret_cast<const double2 *>(b)[i];
   }
   static __device__ __forceinline__ void store(void *b, int64_t i, S v) {
-    reinterpret_cast<double2 *>(b)[i] = v;
+    reinterpret_cast<S *>(b)[i] = v;
   }
   static __device__ __forceinline__ S add(S v, double2 x) {
     v.x += x.x;
@@ -565,7 +600,7 @@ struct Acc<ACC_KAHAN> {
     return reinterpret_cast<const float4 *>(b)[i];
   }
   static __device__ __forceinline__ void store(void *b, int64_t i, S v) {
-    reinterpret_cast<float4 *>(b)[i] = v;
+    reinterpret_cast<S *>(b)[i] = v;
   }
   static __device__ __forceinline__ S add(S v, double2 x) {
     const float xr = (float)x.x, xi = (float)x.y;
@@ -589,7 +624,7 @@ struct Acc<ACC_F32> {
     return reinterpret_cast<const float2 *>(b)[i];
   }
   static __device__ __forceinline__ void store(void *b, int64_t i, S v) {
-    reinterpret_cast<float2 *>(b)[i] = v;
+    reinterpret_cast<S *>(b)[i] = v;
   }
   static __device__ __forceinline__ S add(S v, double2 x) {
     v.x += (float)x.x;
@@ -609,7 +644,7 @@ struct Acc<ACC_F32> {
 // field buffer, where the block transform k_transform reads it.
 // Elements outside a component's lattice (ok bit clear) keep garbage that
 // k_transform never reads; steps past the run keep nothing.
-template <typename T, int VX>
+template <typename T, int VX, bool NT = false>
 __device__ __forceinline__ void hist_store(const StepArgs<T> &A, int s, int64_t q,
                                            const Vec<T, VX> (&e1)[3], const unsigned (&ok)[3],
                                            int n) {
@@ -621,7 +656,7 @@ __device__ __forceinline__ void hist_store(const StepArgs<T> &A, int s, int64_t 
   T *h = A.hist + (int64_t)s * A.hist_src + q + (int64_t)(r - 1) * 3 * A.F;
 #pragma unroll
   for (int c = 0; c < 3; ++c)
-    if (ok[c]) vstore(h + c * A.F, e1[c]);
+    if (ok[c]) vstore_h<NT>(h + c * A.F, e1[c]);
 }
 
 // per-thread list walk.  Entry x = c | kind << 2 | sub << 3 | s << 9, where
@@ -720,7 +755,7 @@ __device__ __forceinline__ void record(const StepArgs<T> &A, int lo, int hi, int
 // VX consecutive x nodes; the x neighbour before the vector is one extra
 // element load; all stencil loads precede the stores.
 // ---------------------------------------------------------------------------
-template <typename T, bool HIST, int VX, bool LEAN>
+template <typename T, bool HIST, int VX, bool LEAN, bool NT = false>
 __device__ __forceinline__ void e_vec(const StepArgs<T> &A, int s, int b, const Half<T> &I,
                                       const Half<T> &O, const Half<T> &P, int i0, int j, int k,
                                       int n) {
@@ -803,9 +838,9 @@ __device__ __forceinline__ void e_vec(const StepArgs<T> &A, int s, int b, const 
     }
   }
   // ---- stores ----
-  if (okx) vstore(O.ex + q, e1x);
-  if (oky) vstore(O.ey + q, e1y);
-  if (okz) vstore(O.ez + q, e1z);
+  if (okx) vstore_h<NT>(O.ex + q, e1x);
+  if (oky) vstore_h<NT>(O.ey + q, e1y);
+  if (okz) vstore_h<NT>(O.ez + q, e1z);
   if (py && okx) vstore(P.psY + 2 * sY + iY, ps_ex_y);
   if (py && okz) vstore(P.psY + 3 * sY + iY, ps_ez_y);
   if (pz && okx) vstore(P.psZ + 2 * sZ + iZ, ps_ex_z);
@@ -819,13 +854,14 @@ __device__ __forceinline__ void e_vec(const StepArgs<T> &A, int s, int b, const 
   if constexpr (HIST) {
     const Vec<T, VX> e1[3] = {e1x, e1y, e1z};
     const unsigned ok[3] = {okx, oky, okz};
-    hist_store<T, VX>(A, s, q, e1, ok, n);
+    hist_store<T, VX, NT>(A, s, q, e1, ok, n);
   }
 }
 
 // HIST: the run takes the volume transform (forward) or the gradient
-// product (adjoint): each sample is kept for the block transform
-template <typename T, bool HIST, int VX>
+// product (adjoint): each sample is kept for the block transform.  NT:
+// streaming stores.
+template <typename T, bool HIST, int VX, bool NT>
 __global__ void __launch_bounds__(256) k_update_e(StepArgs<T> A) {
   int bx, by, bz, s;
   const int b = tile_of(A, bx, by, bz, s);
@@ -836,11 +872,11 @@ __global__ void __launch_bounds__(256) k_update_e(StepArgs<T> A) {
   if (i0 <= A.nx && j <= A.ny && k <= A.nz) {
     const int par = n & 1;
     if (interior_tile(A, bx, by, k, blockDim.x * VX))
-      e_vec<T, HIST, VX, true>(A, s, b, half_of(A, par, s), half_of(A, par ^ 1, s),
-                               half_of(A, 0, s), i0, j, __builtin_amdgcn_readfirstlane(k), n);
+      e_vec<T, HIST, VX, true, NT>(A, s, b, half_of(A, par, s), half_of(A, par ^ 1, s),
+                                   half_of(A, 0, s), i0, j, __builtin_amdgcn_readfirstlane(k), n);
     else
-      e_vec<T, HIST, VX, false>(A, s, b, half_of(A, par, s), half_of(A, par ^ 1, s),
-                                half_of(A, 0, s), i0, j, k, n);
+      e_vec<T, HIST, VX, false, NT>(A, s, b, half_of(A, par, s), half_of(A, par ^ 1, s),
+                                    half_of(A, 0, s), i0, j, k, n);
   }
 }
 
@@ -2563,6 +2599,7 @@ static StepArgs<T> make_args(Plan &p, Dev &d, const WS &w, void *vol, bool adj, 
   A.lean = p.npml >= 1 && p.lean ? 1 : 0;
   A.kb = p.kb;
   A.dl = adj ? 0 : p.dec_log2;   // the adjoint's gradient product takes every sample
+  A.nts = p.streaming(vol != nullptr) ? 1 : 0;
   A.dplane = fdiv_make((uint32_t)A.plane);
   A.dpx = fdiv_make((uint32_t)p.PX);
   A.nf = p.nf();
@@ -2620,11 +2657,21 @@ static void launch_e(const StepArgs<T> &A, int vx, bool hist, dim3 grid, dim3 bl
     if (hist) go(k_update_e4<T, true>, grid, block, 0, st, kt, A);
     else go(k_update_e4<T, false>, grid, block, 0, st, kt, A);
   } else if (vx == 1) {
-    if (hist) go(k_update_e<T, true, 1>, grid, block, 0, st, kt, A);
-    else go(k_update_e<T, false, 1>, grid, block, 0, st, kt, A);
+    if (A.nts) {
+      if (hist) go(k_update_e<T, true, 1, true>, grid, block, 0, st, kt, A);
+      else go(k_update_e<T, false, 1, true>, grid, block, 0, st, kt, A);
+    } else {
+      if (hist) go(k_update_e<T, true, 1, false>, grid, block, 0, st, kt, A);
+      else go(k_update_e<T, false, 1, false>, grid, block, 0, st, kt, A);
+    }
   } else {
-    if (hist) go(k_update_e<T, true, VV>, grid, block, 0, st, kt, A);
-    else go(k_update_e<T, false, VV>, grid, block, 0, st, kt, A);
+    if (A.nts) {
+      if (hist) go(k_update_e<T, true, VV, true>, grid, block, 0, st, kt, A);
+      else go(k_update_e<T, false, VV, true>, grid, block, 0, st, kt, A);
+    } else {
+      if (hist) go(k_update_e<T, true, VV, false>, grid, block, 0, st, kt, A);
+      else go(k_update_e<T, false, VV, false>, grid, block, 0, st, kt, A);
+    }
   }
 }
 
@@ -2670,15 +2717,24 @@ template <typename T>
 static void launch_h(const StepArgs<T> &A, int vx, dim3 grid, dim3 block, hipStream_t st,
                      const KTime *kt = nullptr, bool o4 = false, bool inj = false) {
   constexpr int VV = (int)(16 / sizeof(T));
-  if (inj) {
-    if (o4) go(k_update_h4<T, true>, grid, block, 0, st, kt, A);
-    else if (vx == 1) go(k_update_h<T, 1, true>, grid, block, 0, st, kt, A);
-    else go(k_update_h<T, VV, true>, grid, block, 0, st, kt, A);
+  if (o4) {
+    if (inj) go(k_update_h4<T, true>, grid, block, 0, st, kt, A);
+    else go(k_update_h4<T, false>, grid, block, 0, st, kt, A);
     return;
   }
-  if (o4) go(k_update_h4<T, false>, grid, block, 0, st, kt, A);
-  else if (vx == 1) go(k_update_h<T, 1, false>, grid, block, 0, st, kt, A);
-  else go(k_update_h<T, VV, false>, grid, block, 0, st, kt, A);
+#define FWD_H(VXV, INJV)                                                   \
+  do {                                                                     \
+    if (A.nts) go(k_update_h<T, VXV, INJV, true>, grid, block, 0, st, kt, A); \
+    else go(k_update_h<T, VXV, INJV, false>, grid, block, 0, st, kt, A);   \
+  } while (0)
+  if (inj) {
+    if (vx == 1) FWD_H(1, true);
+    else FWD_H(VV, true);
+  } else {
+    if (vx == 1) FWD_H(1, false);
+    else FWD_H(VV, false);
+  }
+#undef FWD_H
 }
 
 // enqueue step n (H update, E update; or the fused step), followed by the
@@ -3512,9 +3568,9 @@ double dev_autotune(Plan &p, void *ws, size_t ws_bytes, void *vol, size_t vol_by
     p.kb = keep;
   }
   char key[256];
-  snprintf(key, sizeof key, "%d/%d/%d/%d/%d/%d/%d/%d/%d/%d/%d/%d/%d/%d/%d", p.nx, p.ny, p.nz,
-           p.npml, p.ns, p.nf(), p.dtype, p.acc, p.fd_order, mode, vol ? 1 : 0, (int)kbs.size(),
-           (int)p.rn_c.size(), steps, adj ? 1 : p.dec);
+  snprintf(key, sizeof key, "%d/%d/%d/%d/%d/%d/%d/%d/%d/%d/%d/%d/%d/%d/%d/%d", p.nx, p.ny,
+           p.nz, p.npml, p.ns, p.nf(), p.dtype, p.acc, p.fd_order, mode, vol ? 1 : 0,
+           (int)kbs.size(), (int)p.rn_c.size(), steps, adj ? 1 : p.dec, p.stream_stores);
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune_cache.find(key);

@@ -123,6 +123,8 @@ struct Plan {
   double barrier_us = 5.0e6;             // persistent schedule: longest wait at a grid barrier
   int persist_blocks = 0;                // persistent schedule: blocks per CU (0: occupancy)
   int barrier_sleep = 1;                 // persistent schedule: s_sleep units between polls
+  int stream_stores = -1;                // non-temporal stores: 1 on, 0 off, -1 by working set
+  bool streaming(bool with_vol) const;   // stream_stores resolved for a run
   int fd_order = 2;                      // order of the staggered differences: 2 or 4
 
   // ---- device side (managed in device.hip) ----

@@ -64,6 +64,17 @@ size_t Plan::volume_bytes() const {
   return (size_t)ns * nf() * 3 * field_elems() * acc_bytes();
 }
 
+// Streaming stores pay when the data a step streams cannot stay in the
+// 256 MB Infinity Cache until its next use: both field halves, and with a
+// volume transform the history slots and the accumulators.
+bool Plan::streaming(bool with_vol) const {
+  if (stream_stores >= 0) return stream_stores == 1;
+  const size_t tsize = dtype == FWD_F64 ? 8 : 4;
+  size_t bytes = (size_t)ns * 12 * field_elems() * tsize;
+  if (with_vol) bytes += (size_t)ns * 3 * field_elems() * tsize * (kb - 1) + volume_bytes();
+  return bytes > ((size_t)256 << 20);
+}
+
 // ---------------------------------------------------------------------------
 // plan creation
 // ---------------------------------------------------------------------------

@@ -35,7 +35,8 @@ FWD_MODE_FORWARD, FWD_MODE_ADJOINT = 0, 1
  FWD_OPT_SAMPLE_EVERY, FWD_OPT_STRICT_CFL, FWD_OPT_DFT_BLOCK, FWD_OPT_VECTOR,
  FWD_OPT_SCHEDULE, FWD_OPT_ZCHUNK, FWD_OPT_TILE_ORDER, FWD_OPT_VECTOR_H,
  FWD_OPT_VTI_GRADIENT, FWD_OPT_FD_ORDER, FWD_OPT_LEAN, FWD_OPT_BARRIER_US,
- FWD_OPT_PERSIST_BLOCKS, FWD_OPT_BARRIER_SLEEP, FWD_OPT_DFT_DECIMATE) = range(19)
+ FWD_OPT_PERSIST_BLOCKS, FWD_OPT_BARRIER_SLEEP, FWD_OPT_DFT_DECIMATE,
+ FWD_OPT_STREAM_STORES) = range(20)
 
 FWD_STATIC_SCRATCH_BYTES = 32 << 20       # the static workspace of fwd_forward_static
 

@@ -52,6 +52,12 @@ def test_e_update_byte_model(nx, ny, nz, npml):
         edges * (kb * tsize + 2 * nf * accsize)
     assert bench.algorithmic_bytes_transform(edges, nf, tsize, accsize, kb, adjoint=True) == \
         edges * (kb * tsize + nf * accsize + 16)
+    # the first block of a run only writes its accumulators: over a run of
+    # 2 blocks the launches average 1.5 accumulator passes
+    assert bench.algorithmic_bytes_transform(edges, nf, tsize, accsize, kb, blocks=2) == \
+        int(edges * (kb * tsize + 1.5 * nf * accsize))
+    assert bench.algorithmic_bytes_transform(edges, nf, tsize, accsize, kb, blocks=1) == \
+        edges * (kb * tsize + nf * accsize)
 
 
 @pytest.mark.parametrize("nx,ny,nz,npml", [(12, 10, 9, 3), (9, 11, 8, 0)])

@@ -292,3 +292,21 @@ def test_static_scratch_size_matches_header():
     hdr = open(os.path.join(ROOT, "include", "fwdem.h")).read()
     m = re.search(r"#define FWD_STATIC_SCRATCH_BYTES \((\d+)u << (\d+)\)", hdr)
     assert m and int(m.group(1)) << int(m.group(2)) == fw.FWD_STATIC_SCRATCH_BYTES
+
+
+def test_option_ranges(lib):
+    """Host-only: the value ranges of the run options, and their defaults."""
+    p = _plan(tiny(seed=1))
+    assert p.get_option(fw.FWD_OPT_STREAM_STORES) == -1
+    assert p.get_option(fw.FWD_OPT_DFT_DECIMATE) == 1
+    for key, good, bad in ((fw.FWD_OPT_STREAM_STORES, (-1, 0, 1), (-2, 2)),
+                           (fw.FWD_OPT_DFT_DECIMATE, (1, 2, 64), (0, 3, 128)),
+                           (fw.FWD_OPT_PERSIST_BLOCKS, (0, 1, 32), (-1, 33)),
+                           (fw.FWD_OPT_BARRIER_SLEEP, (1, 64), (0, 65))):
+        for v in good:
+            p.set_option(key, v)
+            assert p.get_option(key) == v
+        for v in bad:
+            with pytest.raises(fw.FwdError) as e:
+                p.set_option(key, v)
+            assert e.value.status == 1
