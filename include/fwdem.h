@@ -281,8 +281,10 @@ fwd_status fwd_basis_build(fwd_plan *plan, double gamma_rel, double gamma_abs,
  * magnetic current in the M' slot (M' = M), added to H at n dt before the
  * H update: its spectrum is s_k = conj(resid) z_k^{1/2}, because the basis
  * functions reproduce spectra at the J' times (n+1/2) dt, and its node
- * weights are w / (dual volume of the H node).  Errors: STATE (no model /
- * no basis), HIP, NONFINITE. */
+ * weights are w / (dual volume of the H node).  The coefficients are formed
+ * from resid_dev on the device (no host copy of the residual); the call's
+ * one synchronisation is the final non-finite check.  Errors: STATE (no
+ * model / no basis), HIP, NONFINITE. */
 fwd_status fwd_adjoint(fwd_plan *plan, void *ws_dev, size_t ws_bytes,
                        const void *vol_fwd_dev, size_t vol_bytes, const double *resid_dev,
                        double *grad_dev, int accumulate, double *E_adj_dev,

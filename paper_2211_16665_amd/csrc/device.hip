@@ -1972,6 +1972,75 @@ __global__ void k_copy_e(T *dst, const T *fields, int64_t fbuf, int half, int ns
   }
 }
 
+// Coefficients of the adjoint injection (eq. adj2, reading: the electric
+// residual is an electric current source carrying sqrt(-i w / 2 w0)), one
+// thread per (source, receiver node): the spectrum s_k = fac_k conj(r_k)
+// summed over the residual rows touching the node with their trilinear
+// weights, as the real vector [Re s_1..Re s_nf, Im s_1..Im s_nf] of eq.
+// basis; a magnetic node (H lattice) takes fac_h = z_k^{1/2}, since the
+// basis functions reproduce spectra at the injection times (n+1/2) dt of J'
+// while M' enters H at n dt.  inc bounds the node's largest injected
+// increment: sum_r |t_r| max_n |b_r(n)| times its update factor (dt/eps or
+// dt/mu).
+__global__ void k_adj_coef(int ns, int nn, int nf, int rows, const double *resid,
+                           const int *at_ptr, const int *at_row, const double *at_w,
+                           const int *rn_c, const double2 *fac, const double2 *fac_h,
+                           const double *bmax, const double *nodefac, double *T, double *inc) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ns * nn) return;
+  const int s = t / nn, node = t - s * nn, m = 2 * nf;
+  double *c = T + (int64_t)t * m;
+  for (int r = 0; r < m; ++r) c[r] = 0.0;
+  const double2 *f = rn_c[node] >= 3 ? fac_h : fac;
+  for (int e = at_ptr[node]; e < at_ptr[node + 1]; ++e) {
+    const int row = at_row[e];
+    const double w = at_w[e];
+    for (int k = 0; k < nf; ++k) {
+      const double *rr = resid + 2 * (((int64_t)s * rows + row) * nf + k);
+      const double a = f[k].x, b = f[k].y, cr = rr[0], ci = -rr[1];
+      const double re = a * cr - b * ci, im = a * ci + b * cr;
+      c[k] += w * re;
+      c[nf + k] += w * im;
+    }
+  }
+  double sum = 0.0;
+  for (int r = 0; r < m; ++r) sum += fabs(c[r]) * bmax[r];
+  inc[t] = sum * nodefac[node];
+}
+
+// The power of two nearest (in log2) to 1 / max inc, so that the injected
+// increments stay near 1 (exact scaling); scale_v[k] = 1 / scale for the
+// adjoint receiver output.  One block.
+__global__ void k_adj_scale(const double *inc, int n, int nf, double *scale, double2 *scale_v) {
+  __shared__ double s_big[256];
+  double big = 0.0;
+  for (int t = threadIdx.x; t < n; t += blockDim.x) big = fmax(big, inc[t]);
+  s_big[threadIdx.x] = big;
+  __syncthreads();
+  for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+    if (threadIdx.x < h) s_big[threadIdx.x] = fmax(s_big[threadIdx.x], s_big[threadIdx.x + h]);
+    __syncthreads();
+  }
+  big = s_big[0];
+  double sc = 1.0;
+  if (big > 0.0) {
+    // round(log2(1 / big)) from the exponent and mantissa: 1 / big = m 2^e
+    // with m in [1/2, 1), log2 m in [-1, 0) rounds to 0 from m >= 2^-1/2
+    int e = 0;
+    const double m = frexp(1.0 / big, &e);
+    sc = ldexp(1.0, m >= 0.70710678118654752440 ? e : e - 1);
+  }
+  if (threadIdx.x == 0) scale[0] = sc;
+  for (int k = threadIdx.x; k < nf; k += blockDim.x) scale_v[k] = make_double2(1.0 / sc, 0.0);
+}
+
+__global__ void k_adj_apply(double *T, int64_t n, const double *scale) {
+  const double sc = scale[0];
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
+       t += (int64_t)gridDim.x * blockDim.x)
+    T[t] *= sc;
+}
+
 // receiver output: interpolate node transforms and scale per frequency; a
 // row (receiver r, component position ci = row % ncomp) takes scale_h when
 // its component is magnetic (rcomp >= 3), scale otherwise
@@ -2004,8 +2073,10 @@ __global__ void k_rec_out(int ns, int nrows, int nn, int nf, const int *ptr, con
 // stride LA, and each edge term is scaled by the product of its three.
 __global__ void k_grad_cells(int nx, int ny, int nz, int ns, int PX, int NY, int64_t F,
                              const double *gedge, const double *cellfac, const double *cellfac_v,
-                             double gscale, double *grad, int accumulate, int split,
-                             const double *vr, int LA) {
+                             double gscale, const double *gdiv, double *grad, int accumulate,
+                             int split, const double *vr, int LA) {
+  // gdiv (device, may be null): the scale is 1 / (gscale gdiv[0])
+  if (gdiv) gscale = 1.0 / (gscale * gdiv[0]);
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y;
   const int k = blockIdx.z;
@@ -2125,8 +2196,15 @@ struct Dev {
   int nh = 0;
   double2 *zH = nullptr, *fwd_scale_h = nullptr;
   int *rcomp = nullptr;
-  // adjoint injection coefficients (rebuilt per call)
+  // adjoint injection coefficients (rebuilt per call from the residual on
+  // the device): the node -> residual-row table, the spectral factors of E
+  // and H nodes, the basis functions' largest values, each node's update
+  // factor, per-(source, node) increment bounds and the power-of-two scale
   double *at_coef = nullptr;
+  int *at_ptr = nullptr, *at_row = nullptr;
+  double *at_w = nullptr, *adj_bmax = nullptr, *adj_nodefac = nullptr, *adj_inc = nullptr;
+  double *adj_scale = nullptr;
+  double2 *adj_fac = nullptr, *adj_fac_h = nullptr;
   // per-thread entry tables for the current tiling: the E update's forward
   // (index 0) and adjoint (index 1) tables, and the H update's tables of
   // magnetic sources, adjoint (index 2) and forward (index 3; two-kernel and
@@ -2301,10 +2379,34 @@ static void ensure_tables(Plan &p, hipStream_t stream) {
   d.vol_scale = d.fwd_scale;
   d.adj_scale_v = static_cast<double2 *>(dalloc(d, nf * sizeof(double2)));
   // adjoint injection coefficients [ns][node][2nf] (filled per adjoint call)
+  // and the tables their synthesis reads
   {
     const int nn = (int)p.rn_c.size();
     d.at_coef = static_cast<double *>(dalloc(d, (size_t)p.ns * nn * 2 * nf * sizeof(double)));
     d.eadj = static_cast<double2 *>(dalloc(d, (size_t)p.ns * p.nr * p.ncomp * nf * sizeof(double2)));
+    d.at_ptr = upload(d, p.at_ptr);
+    d.at_row = upload(d, p.at_row);
+    d.at_w = upload(d, p.at_w);
+    std::vector<double2> fac(nf), fac_h(nf);
+    for (int k = 0; k < nf; ++k) {
+      const cplx f = std::sqrt(cplx(0.0, -p.omega[k] / (2.0 * p.omega0)));
+      const cplx fh = std::exp(cplx(0.0, 1.0) * p.wprime[k] * (0.5 * p.dt));
+      fac[k] = make_double2(f.real(), f.imag());
+      fac_h[k] = make_double2(fh.real(), fh.imag());
+    }
+    d.adj_fac = upload(d, fac);
+    d.adj_fac_h = upload(d, fac_h);
+    std::vector<double> bmax(2 * nf, 0.0), nodefac(nn);
+    if (p.have_basis)
+      for (int r = 0; r < 2 * nf; ++r)
+        for (int n = 0; n < p.nt; ++n)
+          bmax[r] = std::max(bmax[r], std::fabs(p.basis[(size_t)r * p.nt + n]));
+    for (int node = 0; node < nn; ++node)
+      nodefac[node] = p.rn_c[node] >= 3 ? p.dt / kMu0 : p.ce[p.rn_c[node]][p.rn_idx[node]];
+    d.adj_bmax = upload(d, bmax);
+    d.adj_nodefac = upload(d, nodefac);
+    d.adj_inc = static_cast<double *>(dalloc(d, (size_t)std::max(1, p.ns * nn) * sizeof(double)));
+    d.adj_scale = static_cast<double *>(dalloc(d, sizeof(double)));
   }
   // per-cell factors sigma_h V / 4 and sigma_v V / 4 (zero for cells above
   // the resistivity cap)
@@ -2976,9 +3078,10 @@ static void run_steps_t(Plan &p, Dev &d, const WS &w, void *vol, bool adj, int n
   // graph of K steps, captured on a private stream and replayed on st
   const int phase = p.host_step % (p.kb * D);
   char key[256];
-  snprintf(key, sizeof key, "%p/%p/%d/%d/%d/%d/%d/%d/%d/%d/%d/%d/%d/%d/%d/%llu/%llu", w.fields,
+  snprintf(key, sizeof key, "%p/%p/%d/%d/%d/%d/%d/%d/%d/%d/%d/%d/%d/%d/%d/%d/%llu/%llu", w.fields,
            vol, (int)adj, K, phase, p.bx, p.by, p.xcd, p.kb * 64 + D, p.vx, p.vxh, p.sched, p.kz, p.order,
-           p.lean, (unsigned long long)p.model_version, (unsigned long long)p.basis_version);
+           p.lean, p.streaming(vol != nullptr) ? 1 : 0, (unsigned long long)p.model_version,
+           (unsigned long long)p.basis_version);
   if (!d.exec || d.exec_key != key) {
     if (d.exec) {
       HIP_CHECK(hipGraphExecDestroy(d.exec));
@@ -3312,18 +3415,23 @@ void dev_adjoint(Plan &p, void *ws, size_t ws_bytes, const void *vol, const doub
   ensure_tables(p, st);
   Dev &d = D(p);
   WS w = carve(p, ws);
-  // adjoint coefficients on the host (small): residual -> spectrum -> nodes
-  const size_t nres = (size_t)p.ns * p.nr * p.ncomp * p.nf();
-  std::vector<double> rh(2 * nres);
-  HIP_CHECK(hipMemcpyAsync(rh.data(), resid, rh.size() * sizeof(double), hipMemcpyDeviceToHost, st));
-  HIP_CHECK(hipStreamSynchronize(st));
-  std::vector<double> T;
-  double adj_scale = 1.0;
-  adjoint_coefficients(p, rh.data(), T, adj_scale);
-  HIP_CHECK(hipMemcpyAsync(d.at_coef, T.data(), T.size() * sizeof(double), hipMemcpyHostToDevice, st));
-  std::vector<double2> as(p.nf(), make_double2(1.0 / adj_scale, 0.0));
-  HIP_CHECK(hipMemcpyAsync(d.adj_scale_v, as.data(), as.size() * sizeof(double2),
-                           hipMemcpyHostToDevice, st));
+  // adjoint coefficients from the residual, on the device: spectrum ->
+  // nodes, the power-of-two scale, then the scaled coefficients
+  const int nn = (int)p.rn_c.size(), nsn = p.ns * nn;
+  if (nsn > 0) {
+    hipLaunchKernelGGL(k_adj_coef, dim3((nsn + 127) / 128), dim3(128), 0, st, p.ns, nn, p.nf(),
+                       p.nr * p.ncomp, resid, d.at_ptr, d.at_row, d.at_w, d.rn_c, d.adj_fac,
+                       d.adj_fac_h, d.adj_bmax, d.adj_nodefac, d.at_coef, d.adj_inc);
+  }
+  hipLaunchKernelGGL(k_adj_scale, dim3(1), dim3(256), 0, st, d.adj_inc, nsn, p.nf(), d.adj_scale,
+                     d.adj_scale_v);
+  {
+    const int64_t nc = (int64_t)nsn * 2 * p.nf();
+    if (nc > 0)
+      hipLaunchKernelGGL(k_adj_apply, dim3((unsigned)std::min<int64_t>((nc + 255) / 256, 1024)),
+                         dim3(256), 0, st, d.at_coef, nc, (const double *)d.adj_scale);
+  }
+  HIP_CHECK(hipGetLastError());
   zero_state(p, w, ws, FWD_MODE_ADJOINT, st);
   d.kstat_n = 0;
   hipEvent_t e0, e1;
@@ -3333,13 +3441,13 @@ void dev_adjoint(Plan &p, void *ws, size_t ws_bytes, const void *vol, const doub
   run_steps_any(p, d, w, const_cast<void *>(vol), true, p.nt, st);
   flush_any(p, d, w, const_cast<void *>(vol), true, st);
   HIP_CHECK(hipEventRecord(e1, st));
-  // gradient on cells
-  const double gscale = 1.0 / (p.src_scale * adj_scale);
+  // gradient on cells, scaled by 1 / (src_scale adj_scale)
   hipLaunchKernelGGL(k_grad_cells, dim3((p.nx + 127) / 128, p.ny, p.nz), dim3(128), 0, st, p.nx,
                      p.ny, p.nz, p.ns, p.PX, p.NY, p.field_elems(), w.gedge, d.cellfac,
-                     d.cellfac_v, gscale, grad, accumulate, p.vti_grad, d.vratio, d.LA);
+                     d.cellfac_v, p.src_scale, (const double *)d.adj_scale, grad, accumulate,
+                     p.vti_grad, d.vratio, d.LA);
   HIP_CHECK(hipGetLastError());
-  const int nrows = p.nr * p.ncomp, nn = (int)p.rn_c.size(), n = p.ns * nrows * p.nf();
+  const int nrows = p.nr * p.ncomp, n = p.ns * nrows * p.nf();
   double2 *dst = E_adj ? reinterpret_cast<double2 *>(E_adj) : d.eadj;
   hipLaunchKernelGGL(k_rec_out, dim3((n + 127) / 128), dim3(128), 0, st, p.ns, nrows, nn, p.nf(),
                      d.ri_ptr, d.ri_node, d.ri_w, w.racc, d.adj_scale_v, d.adj_scale_v, d.rcomp,
@@ -3463,7 +3571,8 @@ static void adjoint_td_t(Plan &p, Dev &d, const WS &w, void *ws, char *scratch, 
   }
   hipLaunchKernelGGL(k_grad_cells, dim3((p.nx + 127) / 128, p.ny, p.nz), dim3(128), 0, st, p.nx,
                      p.ny, p.nz, p.ns, p.PX, p.NY, p.field_elems(), gedge, d.cellfac, d.cellfac_v,
-                     gscale, grad, accumulate, p.vti_grad, d.vratio, d.LA);
+                     gscale, (const double *)nullptr, grad, accumulate, p.vti_grad, d.vratio,
+                     d.LA);
   HIP_CHECK(hipGetLastError());
 }
 

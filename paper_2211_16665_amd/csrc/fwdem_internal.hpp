@@ -156,8 +156,6 @@ Plan *plan_create(const fwd_plan_desc *d);
 void set_model(Plan &p, const double *rho, const double *rho_v = nullptr);
 void basis_build(Plan &p, double gamma_rel, double gamma_abs, int max_iter, double tol,
                  double *fit_err, int *iters);
-void adjoint_coefficients(const Plan &p, const double *resid_host, std::vector<double> &T,
-                          double &scale);
 void get_table(const Plan &p, int which, double *out, size_t n);
 // time-domain adjoint: receiver-node sensitivity coefficients [ns][nn][nf]
 // (complex, scaled by a power of two) and 1/(sigma_e dV_e) per updated edge

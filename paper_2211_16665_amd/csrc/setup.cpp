@@ -675,50 +675,6 @@ void basis_build(Plan &p, double gamma_rel, double gamma_abs, int max_iter, doub
   if (iters) *iters = worst;
 }
 
-// Coefficients of the adjoint injection (eq. adj2, reading: the electric
-// residual is an electric current source carrying sqrt(-i w / 2 w0)):
-// spectrum s = sqrt(-i w_k / 2 w0) conj(resid), real coefficient vector
-// C = [Re s_1..Re s_nf, Im s_1..Im s_nf] (eq. basis), spread onto the
-// receiver nodes with the trilinear weights over the dual volume.  A
-// magnetic residual (H nodes) is a magnetic current M' = M, injected into H
-// at n dt: its spectrum is conj(resid) z_k^{1/2}, since the basis functions
-// reproduce spectra at the injection times (n+1/2) dt of J'.
-// T[s][node][2nf]; scale keeps the injected increments near 1.
-void adjoint_coefficients(const Plan &p, const double *resid, std::vector<double> &T,
-                          double &scale) {
-  const int nf = p.nf(), m = 2 * nf, nn = (int)p.rn_c.size();
-  T.assign((size_t)p.ns * nn * m, 0.0);
-  std::vector<cplx> fac(nf), fac_h(nf);
-  for (int k = 0; k < nf; ++k) {
-    fac[k] = std::sqrt(cplx(0.0, -p.omega[k] / (2.0 * p.omega0)));
-    fac_h[k] = std::exp(cplx(0.0, 1.0) * p.wprime[k] * (0.5 * p.dt));
-  }
-  std::vector<double> bmax(m, 0.0);
-  for (int r = 0; r < m; ++r)
-    for (int n = 0; n < p.nt; ++n) bmax[r] = std::max(bmax[r], std::fabs(p.basis[(size_t)r * p.nt + n]));
-  double big = 0;
-  for (int s = 0; s < p.ns; ++s)
-    for (int node = 0; node < nn; ++node) {
-      double *t = &T[((size_t)s * nn + node) * m];
-      const bool mag = p.rn_c[node] >= 3;
-      for (int e = p.at_ptr[node]; e < p.at_ptr[node + 1]; ++e) {
-        const int row = p.at_row[e];
-        const double w = p.at_w[e];
-        for (int k = 0; k < nf; ++k) {
-          const double *rr = &resid[2 * (((size_t)s * p.nr * p.ncomp + row) * nf + k)];
-          const cplx sp = (mag ? fac_h[k] : fac[k]) * std::conj(cplx(rr[0], rr[1]));
-          t[k] += w * sp.real();
-          t[nf + k] += w * sp.imag();
-        }
-      }
-      double inc = 0;
-      for (int r = 0; r < m; ++r) inc += std::fabs(t[r]) * bmax[r];
-      big = std::max(big, inc * (mag ? p.dt / kMu0 : p.ce[p.rn_c[node]][p.rn_idx[node]]));
-    }
-  scale = big > 0 ? std::exp2(std::round(std::log2(1.0 / big))) : 1.0;  // power of two: exact
-  for (double &v : T) v *= scale;
-}
-
 void td_coefficients(const Plan &p, const double *resid, std::vector<double> &C,
                      double &scale) {
   // E_rec[s][r][c][k] = norm_k sum_nodes w sum_m E^m z_k^m, so the misfit's
