@@ -972,6 +972,10 @@ def profile_mode(args):
     plan.basis_build(gamma_rel=1e-12)
     E, vol = plan.forward(want_volume=True)
     plan.adjoint(vol, -E)
+    if args.profile_td > 0:
+        # the time-domain adjoint of the same run, checkpoints every
+        # profile_td steps
+        plan.adjoint_td(-E, segment=args.profile_td)
     torch.cuda.synchronize()
     print(json.dumps({"profile_steps": args.profile_steps, "copy_bytes": 4 * n,
                       "workload": w.name, "sources": w.ns}), flush=True)
@@ -1023,6 +1027,9 @@ def main():
                     help="fixed tiling instead of autotuning: " + ",".join(TILING_KEYS).lower())
     ap.add_argument("--profile-workload", default="large", choices=("large", "marine", "batched"),
                     help="workload of the counter-collection mode")
+    ap.add_argument("--profile-td", type=int, default=0,
+                    help="counter-collection mode: also the time-domain adjoint, with "
+                         "checkpoints every this many steps")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="counter-collection mode: a 1 GiB device copy (calibration of the "
                          "byte counters) then this many forward and adjoint steps of the "
