@@ -8,7 +8,8 @@ and accumulators, so the bar is rounding):
     grid nodes;
   * runs of one to five steps, where the first transform block is also the
     flushed last one (with and without decimation, blocks of 1, 2 and 8);
-  * the gradient on a minimal grid.
+  * the gradient on a minimal grid;
+  * adjoints of a zero residual and of residuals scaled by powers of two.
 """
 import numpy as np
 import pytest
@@ -111,3 +112,27 @@ def test_gradient_on_a_minimal_grid():
     err = np.linalg.norm(g - go) / np.linalg.norm(go)
     say(f"  relative L2 {err:.2e}")
     assert err < 1e-7
+
+
+def test_adjoint_of_zero_and_scaled_residuals():
+    """The adjoint sources are formed on the device with a power-of-two
+    scale: a zero residual gives an exactly zero gradient (no 0/0), and a
+    residual scaled by 2^k (k = -60, 90) gives the gradient scaled by 2^k
+    bit for bit, with FP32 fields as with FP64."""
+    w_true = tiny(seed=35, n=(8, 8, 8), npml=2, ns=2, nr=4)
+    w0 = w_true.replace(rho=w_true.rho * 1.3)
+    d = torch.from_numpy(oracle.forward(w_true)["E_rec"]).cuda()
+    for dtype in ("f64", "f32"):
+        say(f"zero and scaled residuals, {dtype}")
+        p = fw.Plan.from_workload(w0, field_dtype=dtype, acc_mode="f64")
+        p.set_model(w0.rho)
+        p.basis_build(gamma_rel=1e-12)
+        E, vol = p.forward(want_volume=True)
+        g0 = p.adjoint(vol, torch.zeros_like(E))
+        assert not torch.any(g0)
+        r = d - E
+        g = p.adjoint(vol, r)
+        assert torch.isfinite(g).all() and torch.any(g)
+        for k in (-60, 90):
+            gk = p.adjoint(vol, r * 2.0 ** k)
+            assert torch.equal(gk, g * 2.0 ** k), k
