@@ -224,8 +224,9 @@ fwd_status fwd_run_receivers(fwd_plan *plan, void *ws_dev, size_t ws_bytes, doub
 
 /* Add the samples of an incomplete transform block (nsteps not a multiple of
  * FWD_OPT_DFT_BLOCK) to the volume transform, so that vol_dev holds the sum
- * over every step run so far.  Stepping may continue afterwards: samples
- * already added are not added again.  fwd_forward does this itself. */
+ * over every step run so far (all zeros when the run has taken no sample
+ * yet).  Stepping may continue afterwards: samples already added are not
+ * added again.  fwd_forward does this itself. */
 fwd_status fwd_run_flush(fwd_plan *plan, void *ws_dev, size_t ws_bytes, void *vol_dev,
                          size_t vol_bytes, void *stream);
 
